@@ -1,0 +1,346 @@
+"""Seeded synthetic inputs for the hybrid depth-of-field pass.
+
+This module produces *data only*: scene triangles, albedos, lights, camera
+paths, lens settings and parameter values.  It holds none of the method's
+arithmetic (no circle of confusion, no filtering, no ray tracing), so both the
+GPU library and the CPU oracle can consume the same inputs without sharing any
+of the code under test.
+
+Randomness is SplitMix64 (Steele, Lea & Flood 2014): a 64-bit counter stepped by
+the golden-ratio increment and finalised by two xor-shift-multiply rounds.
+Uniform floats take the top 24 bits times 2^-24.
+
+The scenes stand in for the paper's test scenes (The Modern Living Room, Sun
+Temple, Bistro Exterior; section 4.2), which are not available: a far field of
+simple opaque objects and a foreground layer of thin geometry whose blurred
+silhouettes are what the ray-traced branch exists for.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+BASE_SEED = 2210061580
+
+
+class SplitMix64:
+    """Counter-form SplitMix64; `uniform(n)` draws n floats in [0, 1)."""
+
+    def __init__(self, seed: int):
+        self.state = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+        self.count = 0
+
+    def next_u64(self, n: int) -> np.ndarray:
+        with np.errstate(over="ignore"):
+            idx = np.arange(self.count + 1, self.count + n + 1, dtype=np.uint64)
+            z = self.state + idx * _GOLDEN
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            z = z ^ (z >> np.uint64(31))
+        self.count += n
+        return z
+
+    def uniform(self, n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+        u = (self.next_u64(n) >> np.uint64(40)).astype(np.float64) * (2.0 ** -24)
+        return lo + (hi - lo) * u
+
+
+# ----------------------------------------------------------------------------
+# Plain input records (mirrors of the C structs on both sides)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Camera:
+    pos: tuple
+    right: tuple
+    up: tuple
+    fwd: tuple
+    width: int
+    height: int
+    frame: int = 0
+    seed: int = 1
+
+
+@dataclass
+class Lens:
+    focal: float = 0.050        # metres ("f = 50 mm")
+    fnum: float = 1.4           # N; aperture diameter a = f / N
+    focus: float = 15.0         # d, distance to the focus plane
+    sensor: float = 0.036       # w_s, 36 mm full-frame sensor width
+    blades: int = 0             # 0 = circular aperture, 6 = hexagon
+    blade_rot: float = 0.0      # radians
+
+
+MASK_ADAPTIVE, MASK_FIXED, MASK_ALL = 0, 1, 2
+
+
+@dataclass
+class Params:
+    m: int = 4                  # ray budget per pixel (section 3.2.1)
+    s: float = 0.8              # eq. (2) scale (section 4.2)
+    var_mask_w: float = 1.0e5   # eq. (4) variance weight
+    alpha: float = 0.95         # history weight of the moving average (3.2.3)
+    alpha_motion: float = 0.8   # reduced history weight during motion
+    var_recon_w: float = 2000.0 # eq. (5)
+    b_max: float = 0.9          # eq. (5)
+    h_edge: float = 0.3         # eq. (7)
+    lod_scale: float = 0.05     # eq. (8)
+    lod_max: float = 3.0        # eq. (8)
+    depth_range: float = 0.1    # main-filter depth range, 10 cm (4.2)
+    r_max: float = 32.0         # largest gather radius in half-res pixels
+    tile: int = 16              # tile side for the neighbourhood max CoC
+    l_spec: float = 1.0         # luma threshold of a "high specular" tap
+    mask_mode: int = MASK_ADAPTIVE
+
+
+@dataclass
+class Scene:
+    verts: np.ndarray           # (n, 9) float32: v0 xyz, v1 xyz, v2 xyz
+    albedo: np.ndarray          # (n, 3) float32
+    light_dir: tuple = (0.0, -1.0, 0.0)   # direction the light travels
+    light_rad: tuple = (1.0, 1.0, 1.0)
+    ambient: tuple = (0.15, 0.15, 0.15)
+    sky: tuple = (0.55, 0.70, 0.95)
+
+    @property
+    def ntri(self) -> int:
+        return int(self.verts.shape[0])
+
+
+def _normalize(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v)
+
+
+def f32tuple(v):
+    return tuple(float(np.float32(x)) for x in v)
+
+
+def look_camera(pos, yaw: float, pitch: float, width: int, height: int,
+                frame: int = 0, seed: int = 1) -> Camera:
+    """Orthonormal camera basis: +y up, forward +z at zero yaw/pitch
+    (left-handed, right = +x)."""
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    cp, sp = math.cos(pitch), math.sin(pitch)
+    fwd = np.array([sy * cp, sp, cy * cp])
+    right = np.array([cy, 0.0, -sy])
+    up = np.cross(fwd, right)
+    return Camera(f32tuple(pos), f32tuple(right), f32tuple(up), f32tuple(fwd),
+                  int(width), int(height), int(frame), int(seed))
+
+
+def half_fov_tan(lens: Lens) -> float:
+    """Horizontal half-field tangent of the sensor at the focused image
+    distance; used only to place objects inside the frame."""
+    f, d, ws = lens.focal, lens.focus, lens.sensor
+    return ws * (d - f) / (2.0 * f * d)
+
+
+# ----------------------------------------------------------------------------
+# Geometry builders
+# ----------------------------------------------------------------------------
+
+_BOX_FACES = np.array([
+    [0, 2, 1], [0, 3, 2],   # -z
+    [4, 5, 6], [4, 6, 7],   # +z
+    [0, 1, 5], [0, 5, 4],   # -y
+    [3, 7, 6], [3, 6, 2],   # +y
+    [0, 4, 7], [0, 7, 3],   # -x
+    [1, 2, 6], [1, 6, 5],   # +x
+], dtype=np.int64)
+
+
+def boxes(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Axis-aligned boxes -> (12 * nbox, 9) triangles."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    n = lo.shape[0]
+    corners = np.empty((n, 8, 3))
+    for c in range(8):
+        x = hi[:, 0] if c in (1, 2, 5, 6) else lo[:, 0]
+        y = hi[:, 1] if c in (2, 3, 6, 7) else lo[:, 1]
+        z = hi[:, 2] if c >= 4 else lo[:, 2]
+        corners[:, c] = np.stack([x, y, z], axis=1)
+    tris = corners[:, _BOX_FACES]            # (n, 12, 3, 3)
+    return tris.reshape(n * 12, 9).astype(np.float32)
+
+
+def quad(p0, p1, p2, p3) -> np.ndarray:
+    """Two triangles of the quad p0 p1 p2 p3 (in order around the rim)."""
+    p = [np.asarray(x, np.float64) for x in (p0, p1, p2, p3)]
+    return np.stack([np.concatenate([p[0], p[1], p[2]]),
+                     np.concatenate([p[0], p[2], p[3]])]).astype(np.float32)
+
+
+def uv_spheres(centres: np.ndarray, radii: np.ndarray,
+               slices: int = 12, bands: int = 11) -> np.ndarray:
+    """UV spheres with `slices` x `bands` cells: 2 * slices * (bands - 1)
+    triangles each (240 for 12 x 11)."""
+    th = np.linspace(0.0, math.pi, bands + 1)          # polar
+    ph = np.linspace(0.0, 2.0 * math.pi, slices + 1)[:-1]
+    unit = []
+    for b in range(bands):
+        t0, t1 = th[b], th[b + 1]
+        for s in range(slices):
+            p0, p1 = ph[s], ph[(s + 1) % slices]
+            a = (math.sin(t0) * math.cos(p0), math.cos(t0), math.sin(t0) * math.sin(p0))
+            bb = (math.sin(t0) * math.cos(p1), math.cos(t0), math.sin(t0) * math.sin(p1))
+            c = (math.sin(t1) * math.cos(p0), math.cos(t1), math.sin(t1) * math.sin(p0))
+            d = (math.sin(t1) * math.cos(p1), math.cos(t1), math.sin(t1) * math.sin(p1))
+            if b == 0:
+                unit.append((a, d, c))
+            elif b == bands - 1:
+                unit.append((a, bb, c))
+            else:
+                unit.append((a, bb, d))
+                unit.append((a, d, c))
+    unit = np.array(unit, dtype=np.float64)            # (k, 3, 3)
+    k = unit.shape[0]
+    out = unit[None] * radii[:, None, None, None] + centres[:, None, None, :]
+    return out.reshape(-1, 9).astype(np.float32), k
+
+
+# ----------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------
+
+def scene_small(seed: int = BASE_SEED + 1000) -> tuple:
+    """256x256 workload: ground quad (2 tris), 64 boxes at depth 10-30 with
+    uniform albedo (768 tris), 8 thin bars at depth 1.5-2.5 (96 tris);
+    Lambert shading with one directional light.  Returns (scene, camera,
+    lens, params)."""
+    rng = SplitMix64(seed)
+    lens = Lens(focal=0.050, fnum=1.4, focus=15.0, sensor=0.036)
+    tx = half_fov_tan(lens)
+    ground = quad((-60, 0, -1), (-60, 0, 80), (60, 0, 80), (60, 0, -1))
+    gal = np.array([[0.45, 0.42, 0.38]] * 2, np.float32)
+
+    nb = 64
+    z = rng.uniform(nb, 10.0, 30.0)
+    x = rng.uniform(nb, -0.9, 0.9) * z * tx
+    fw = rng.uniform(nb, 0.6, 2.4)
+    fd = rng.uniform(nb, 0.6, 2.4)
+    h = rng.uniform(nb, 0.6, 3.0)
+    alb = rng.uniform(nb * 3).reshape(nb, 3)
+    lo = np.stack([x - fw / 2, np.zeros(nb), z - fd / 2], 1)
+    hi = np.stack([x + fw / 2, h, z + fd / 2], 1)
+    bt = boxes(lo, hi)
+    bal = np.repeat(alb, 12, axis=0).astype(np.float32)
+
+    nbar = 8
+    zb = rng.uniform(nbar, 1.5, 2.5)
+    wb = rng.uniform(nbar, 0.01, 0.04)
+    xb = (-0.8 + 1.6 * (np.arange(nbar) + rng.uniform(nbar)) / nbar) * zb * tx
+    albb = rng.uniform(nbar * 3, 0.2, 0.9).reshape(nbar, 3)
+    lo = np.stack([xb - wb / 2, np.zeros(nbar), zb - wb / 2], 1)
+    hi = np.stack([xb + wb / 2, np.full(nbar, 3.0), zb + wb / 2], 1)
+    bart = boxes(lo, hi)
+    baral = np.repeat(albb, 12, axis=0).astype(np.float32)
+
+    verts = np.concatenate([ground, bt, bart]).astype(np.float32)
+    albedo = np.concatenate([gal, bal, baral]).astype(np.float32)
+    scene = Scene(verts, albedo, light_dir=f32tuple(_normalize((-0.4, -1.0, 0.6))))
+    cam = look_camera((0.0, 1.2, 0.0), 0.0, 0.0, 256, 256, frame=0, seed=seed & 0xFFFFFFFF)
+    return scene, cam, lens, Params(m=4)
+
+
+def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
+                n_blades: int = 50000) -> tuple:
+    """1920x1080 workload: ground quad, 4096 UV spheres of 240 triangles over
+    depth 5-80 and a foreground grass band of 50k 4-triangle blades at depth
+    0.5-3 (about 1.18M triangles).  Returns (scene, camera_path(60), lens,
+    params)."""
+    rng = SplitMix64(seed)
+    lens = Lens(focal=0.050, fnum=1.4, focus=15.0, sensor=0.036)
+    tx = half_fov_tan(lens)
+    ground = quad((-200, 0, -2), (-200, 0, 200), (200, 0, 200), (200, 0, -2))
+    gal = np.array([[0.40, 0.45, 0.30]] * 2, np.float32)
+
+    ns = n_spheres
+    zc = rng.uniform(ns, 5.0, 80.0)
+    r = rng.uniform(ns, 0.3, 1.5)
+    xc = rng.uniform(ns, -1.0, 1.0) * (zc * tx * 1.1 + 1.0)
+    cen = np.stack([xc, r, zc], 1)
+    st, per = uv_spheres(cen, r)
+    salb = np.repeat(rng.uniform(ns * 3, 0.05, 0.95).reshape(ns, 3), per, axis=0)
+
+    nbld = n_blades
+    zg = rng.uniform(nbld, 0.5, 3.0)
+    xg = rng.uniform(nbld, -1.0, 1.0) * (zg * tx + 0.5)
+    hg = rng.uniform(nbld, 0.1, 0.5)
+    wg = rng.uniform(nbld, 0.005, 0.02)
+    yaw = rng.uniform(nbld, -0.6, 0.6)
+    lean_x = rng.uniform(nbld, -0.25, 0.25)
+    lean_z = rng.uniform(nbld, -0.25, 0.25)
+    gshade = rng.uniform(nbld, 0.6, 1.0)
+    ux, uz = np.cos(yaw), -np.sin(yaw)
+    pts = []
+    for level, (yf, wf) in enumerate(((0.0, 1.0), (0.5, 0.7), (1.0, 0.15))):
+        y = hg * yf
+        cx = xg + lean_x * hg * yf * yf
+        cz = zg + lean_z * hg * yf * yf
+        hw = 0.5 * wg * wf
+        pts.append((np.stack([cx - hw * ux, y, cz - hw * uz], 1),
+                    np.stack([cx + hw * ux, y, cz + hw * uz], 1)))
+    gl = []
+    for lv in range(2):
+        (a0, a1), (b0, b1) = pts[lv], pts[lv + 1]
+        gl.append(np.concatenate([a0, a1, b1], 1))
+        gl.append(np.concatenate([a0, b1, b0], 1))
+    gt = np.stack(gl, 1).reshape(-1, 9).astype(np.float32)
+    galb = np.stack([0.25 * gshade, 0.55 * gshade, 0.12 * gshade], 1)
+    galb = np.repeat(galb, 4, axis=0)
+
+    verts = np.concatenate([ground, st, gt]).astype(np.float32)
+    albedo = np.concatenate([gal, salb, galb]).astype(np.float32)
+    scene = Scene(verts, albedo, light_dir=f32tuple(_normalize((-0.3, -1.0, 0.5))))
+    cams = camera_spline(rng, 60, 1920, 1080, seed & 0xFFFFFFFF)
+    return scene, cams, lens, Params(m=8)
+
+
+def camera_spline(rng: SplitMix64, nframes: int, width: int, height: int,
+                  seed: int) -> list:
+    """Catmull-Rom path through 8 seeded control points at eye height
+    0.3-0.6 with yaw within +-10 degrees and a slight downward pitch."""
+    k = 8
+    px = rng.uniform(k, -0.3, 0.3)
+    py = rng.uniform(k, 0.3, 0.6)
+    pz = rng.uniform(k, -0.3, 0.3)
+    yaw = rng.uniform(k, -math.radians(10), math.radians(10))
+    ctrl = np.stack([px, py, pz, yaw], 1)
+    cams = []
+    for fi in range(nframes):
+        s = 1.0 + (k - 3) * fi / max(1, nframes - 1)
+        i = min(int(math.floor(s)), k - 3)
+        t = s - i
+        p0, p1, p2, p3 = ctrl[i - 1], ctrl[i], ctrl[i + 1], ctrl[i + 2]
+        t2, t3 = t * t, t * t * t
+        v = 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t2
+                   + (-p0 + 3 * p1 - 3 * p2 + p3) * t3)
+        cams.append(look_camera(v[:3], float(v[3]), math.radians(-4.0), width, height,
+                                frame=fi, seed=seed))
+    return cams
+
+
+def pan_camera(cam: Camera, dx: float) -> Camera:
+    """The same camera translated by dx along its right axis."""
+    p = np.asarray(cam.pos, np.float64) + dx * np.asarray(cam.right, np.float64)
+    return dataclasses.replace(cam, pos=f32tuple(p), frame=cam.frame + 1)
+
+
+def random_triangles(n: int, seed: int, spread: float = 4.0, size: float = 0.6):
+    """Small random triangle soups for closest-hit checks."""
+    rng = SplitMix64(seed)
+    c = rng.uniform(n * 3, -spread, spread).reshape(n, 1, 3)
+    off = rng.uniform(n * 9, -size, size).reshape(n, 3, 3)
+    v = (c + off).reshape(n, 9).astype(np.float32)
+    alb = rng.uniform(n * 3).reshape(n, 3).astype(np.float32)
+    return v, alb

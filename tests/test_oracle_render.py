@@ -1,0 +1,368 @@
+"""Oracle pins for the per-frame pass: mask (3.2.1, eqs. 2-4), post-process
+filters (3.1), resolve and temporal accumulation (3.2.2-3.2.3), reconstruction
+(3.2.4, eq. 5) and composite (3.3)."""
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+from paper_2210_06158_amd import synth
+
+
+def plane_scene(z0, albedo=(0.6, 0.5, 0.4), extent=400.0):
+    v = synth.quad((-extent, -extent, z0), (-extent, extent, z0), (extent, extent, z0), (extent, -extent, z0))
+    return synth.Scene(v, np.array([albedo, albedo], np.float32),
+                       light_dir=synth.f32tuple(synth._normalize((0.2, -0.3, 1.0))))
+
+
+def gb_from_half(orc, depth_half, normal=(0.0, 0.0, -1.0), colour=(0.5, 0.5, 0.5)):
+    hh, hw = depth_half.shape
+    d = np.repeat(np.repeat(depth_half.astype(np.float32), 2, 0), 2, 1)
+    H, W = d.shape
+    n = np.zeros((H, W, 4), np.float32)
+    n[..., :3] = normal
+    c = np.ones((H, W, 4), np.float32)
+    c[..., :3] = colour
+    return orc.GBuffer(c, d, n)
+
+
+@pytest.fixture(scope="module")
+def small(orc):
+    scene, cam, lens, params = synth.scene_small()
+    sc = orc.OracleScene(scene)
+    sc.build_bvh()
+    gb = orc.gbuffer(sc, cam, lens)
+    out = orc.render_frame(sc, cam, lens, params, gb)
+    return dict(scene=scene, sc=sc, cam=cam, lens=lens, params=params, gb=gb, out=out)
+
+
+# ---------------------------------------------------------------- composite
+
+def test_pinhole_reduction_is_the_gbuffer(orc, small):
+    """a = 0 (N = infinity): every CoC is 0, so every pixel is in the zone of
+    focus and the output equals the sharp raster colour bit for bit."""
+    lens = dataclasses.replace(small["lens"], fnum=math.inf)
+    gb = orc.gbuffer(small["sc"], small["cam"], lens)
+    out = orc.render_frame(small["sc"], small["cam"], lens, small["params"], gb)
+    assert np.array_equal(out["colour"][..., :3].view(np.uint32), gb.colour[..., :3].view(np.uint32))
+
+
+def test_in_focus_pixels_copy_raster_colour(orc, small):
+    out, gb, lens = small["out"], small["gb"], small["lens"]
+    H, W = gb.depth.shape
+    valid = out["temporal"][0][..., 3] > 0
+    hv = np.pad(valid, 1, mode="edge")
+    # a full-res pixel blends the 4 half-res texels around (x/2 - 1/4, y/2 - 1/4)
+    yy, xx = np.mgrid[0:H, 0:W]
+    y0, x0 = (yy + 1) // 2 - 1, (xx + 1) // 2 - 1
+    any_valid = np.zeros((H, W), bool)
+    for dy in (0, 1):
+        for dx in (0, 1):
+            any_valid |= hv[np.clip(y0 + dy, 0, H // 2 - 1) + 1, np.clip(x0 + dx, 0, W // 2 - 1) + 1]
+    coc = np.array([[orc.coc(lens, W, float(z)) for z in row] for row in gb.depth[:, ::1]])
+    sel = (coc <= math.sqrt(2.0)) & ~any_valid
+    assert sel.sum() > 1000
+    assert np.array_equal(out["colour"][sel][:, :3].view(np.uint32), gb.colour[sel][:, :3].view(np.uint32))
+
+
+# ---------------------------------------------------------------- ray mask
+
+@pytest.mark.parametrize("z0,expect", [(40.0, 0), (15.0, 0), (3.0, 1)])
+def test_mask_flat_plane(orc, z0, expect):
+    """Constant depth and normal: no gradient, so x_n = 0; only an
+    out-of-focus near-field pixel gets its single ray (3.2.1)."""
+    lens = synth.Lens()
+    sc = orc.OracleScene(plane_scene(z0))
+    cam = synth.look_camera((0, 0, 0), 0, 0, 256, 64)
+    gb = gb_from_half(orc, np.full((32, 128), z0))
+    out = orc.render_frame(sc, cam, lens, synth.Params(m=6), gb)
+    assert (out["mask"] == expect).all()
+
+
+@pytest.mark.parametrize("alpha,count", [(0.25, 2), (1.0, 5), (4.0, 9)])
+def test_mask_depth_ramp(orc, alpha, count):
+    """d/z rising by alpha per half-res pixel: the unit-gain Sobel gives
+    delta_d = alpha, so x = 0.8 alpha, x_n = 1 - 1/(x + 1) (eqs. 2, 3) and the
+    ray count is round(x_n * m) (eq. 4 with zero variance)."""
+    lens = synth.Lens(fnum=64.0)
+    d = lens.focus
+    qx = np.arange(128, dtype=np.float64)
+    depth = np.tile(d / (alpha * qx + 1.0), (32, 1))
+    sc = orc.OracleScene(plane_scene(20.0))
+    cam = synth.look_camera((0, 0, 0), 0, 0, 256, 64)
+    out = orc.render_frame(sc, cam, lens, synth.Params(m=12), gb_from_half(orc, depth))
+    x = 0.8 * alpha
+    want = math.floor((1.0 - 1.0 / (x + 1.0)) * 12 + 0.5)
+    assert want == count
+    assert (out["mask"][:, 4:124] == count).all()
+
+
+@pytest.mark.parametrize("var,m,count", [(2e-6, 10, 2), (5e-6, 10, 5), (1e-5, 10, 10), (1e-3, 7, 7)])
+def test_mask_variance_term(orc, var, m, count):
+    """Eq. (4): x_f = saturate(x_n + var * 1e5) * m with the previous frame's
+    blurred variance at the reprojected texel (static camera)."""
+    lens = synth.Lens()
+    sc = orc.OracleScene(plane_scene(40.0))
+    cam = synth.look_camera((0, 0, 0), 0, 0, 128, 64)
+    gb = gb_from_half(orc, np.full((32, 64), 40.0))
+    npx = 32 * 64
+    hist = orc.history_zeros(128, 64)
+    hist[4 * npx + 3:8 * npx:4] = 1.0            # age
+    hist[12 * npx:] = var                         # blurred variance
+    out = orc.render_frame(sc, cam, lens, synth.Params(m=m), gb, hist_in=hist, prev_cam=cam, prev_lens=lens)
+    assert (out["prev_idx"].ravel() == np.arange(npx)).all()
+    assert (out["mask"] == count).all()
+
+
+# ---------------------------------------------------------------- post-process
+
+def test_tile_max_and_dilation(small):
+    out, p = small["out"], small["params"]
+    r = np.abs(out["colr"][..., 3])
+    T = p.tile
+    th, tw = out["tile_max"].shape
+    pad = np.zeros((th * T, tw * T), np.float32)
+    pad[:r.shape[0], :r.shape[1]] = r
+    tmax = pad.reshape(th, T, tw, T).max(axis=(1, 3))
+    assert np.array_equal(out["tile_max"], tmax)
+    D = math.ceil(p.r_max / T)
+    dil = ndi.maximum_filter(tmax, size=2 * D + 1, mode="constant", cval=0.0)
+    assert np.array_equal(out["tile_dil"], dil)
+
+
+def test_half_res_reduce(orc, small):
+    out, gb, lens = small["out"], small["gb"], small["lens"]
+    z = gb.depth
+    quads = np.stack([z[0::2, 0::2], z[0::2, 1::2], z[1::2, 0::2], z[1::2, 1::2]])
+    assert np.array_equal(out["zn"][..., 0], quads.min(0))
+    r = out["colr"][..., 3]
+    coc = np.array([[orc.coc(lens, 256, float(v)) for v in row] for row in quads.min(0)])
+    np.testing.assert_allclose(np.abs(r), np.minimum(coc / 4, 32.0), rtol=1e-6)
+    assert ((r < 0) == (quads.min(0) < lens.focus)).all() | (r == 0).all()
+
+
+def test_median_postfilter_is_median(small):
+    g = small["out"]["gather"][..., :3]
+    pad = np.pad(g, ((1, 1), (1, 1), (0, 0)), mode="edge")
+    stack = np.stack([pad[dy:dy + g.shape[0], dx:dx + g.shape[1]] for dy in range(3) for dx in range(3)])
+    assert np.array_equal(small["out"]["ppmed"][..., :3], np.median(stack, axis=0).astype(np.float32))
+
+
+def test_constant_image_is_preserved(orc):
+    """Normalised filters leave a constant image constant (3.1.1-3.1.3)."""
+    lens = synth.Lens()
+    sc = orc.OracleScene(plane_scene(3.0))
+    cam = synth.look_camera((0, 0, 0), 0, 0, 128, 64)
+    col = (0.3, 0.6, 0.9)
+    out = orc.render_frame(sc, cam, lens, synth.Params(), gb_from_half(orc, np.full((32, 64), 3.0), colour=col))
+    for k in ("pre", "gather", "ppmed"):
+        np.testing.assert_allclose(out[k][..., :3], np.broadcast_to(col, out[k][..., :3].shape), rtol=2e-5)
+
+
+def test_all_in_focus_gather_is_identity(orc):
+    lens = synth.Lens(fnum=math.inf)
+    scene, cam, _, params = synth.scene_small()
+    sc = orc.OracleScene(scene)
+    gb = orc.gbuffer(sc, cam, lens)
+    out = orc.render_frame(sc, cam, lens, params, gb)
+    assert np.array_equal(out["gather"][..., :3], out["pre"][..., :3])
+
+
+# ---------------------------------------------------------------- rays
+
+def test_compaction_order(small):
+    out = small["out"]
+    m = out["mask"].ravel().astype(np.int64)
+    q = np.flatnonzero(m)
+    assert np.array_equal(out["queue"], q)
+    base = np.concatenate([[0], np.cumsum(m[q])[:-1]])
+    assert np.array_equal(out["ray_base"], base)
+    assert out["n_rays"] == m.sum()
+
+
+def test_thin_lens_at_zero_aperture_is_pinhole(orc):
+    """a = 0: every lens point is the lens centre, so the ray towards the focus
+    point is the pinhole ray; its hits match a half-resolution pinhole
+    G-buffer away from depth discontinuities."""
+    scene, cam, _, params = synth.scene_small()
+    lens = synth.Lens(fnum=math.inf)
+    sc = orc.OracleScene(scene)
+    gb = orc.gbuffer(sc, cam, lens)
+    out = orc.render_frame(sc, cam, lens, dataclasses.replace(params, mask_mode=synth.MASK_ALL, m=1), gb)
+    half = dataclasses.replace(cam, width=128, height=128)
+    ghalf = orc.gbuffer(sc, half, lens)
+    z_ray = out["ray_col"][:, 3].reshape(128, 128)
+    same = np.isclose(z_ray, ghalf.depth, rtol=1e-5) | (np.isinf(z_ray) & np.isinf(ghalf.depth))
+    assert same.mean() > 0.995
+
+
+def test_resolve_lerp_equals_sample_mean(small):
+    """With both fields populated, lerp(far, near, h) is the plain mean of the
+    pixel's ray colours (3.2.2)."""
+    out = small["out"]
+    R0, R1, R2 = (out["resolve"][i].reshape(-1, 4) for i in range(3))
+    checked = 0
+    for j, q in enumerate(out["queue"]):
+        n = int(R2[q, 2])
+        N = R0[q, 3]
+        if not (0 < N < n):
+            continue
+        b = out["ray_base"][j]
+        mean = out["ray_col"][b:b + n, :3].astype(np.float64).mean(0)
+        h = R1[q, 3]
+        lerp = R1[q, :3] + (R0[q, :3] - R1[q, :3]) * h
+        np.testing.assert_allclose(lerp, mean, atol=2e-6)
+        checked += 1
+    assert checked > 50
+
+
+def test_half_plane_occluder_hit_ratio(orc):
+    """Near-field half-plane x < 0 at depth z1 in front of a far wall: the
+    rays of a pixel cross depth z1 inside a disc of radius rho = (a/2)(d -
+    z1)/d around the pixel's line of sight, so the hit ratio is the
+    circular-segment fraction F(s) = (arccos s - s sqrt(1 - s^2)) / pi of that
+    disc lying beyond the edge, s = signed distance / rho (3.2.2)."""
+    lens = synth.Lens(fnum=1.4, focus=15.0)
+    z1 = 0.5
+    occ = synth.quad((-50, -50, z1), (-50, 50, z1), (0, 50, z1), (0, -50, z1))
+    wall = synth.quad((-500, -500, 60), (-500, 500, 60), (500, 500, 60), (500, -500, 60))
+    scene = synth.Scene(np.concatenate([occ, wall]), np.ones((4, 3), np.float32))
+    sc = orc.OracleScene(scene)
+    cam = synth.look_camera((0, 0, 0), 0, 0, 1024, 8)
+    gb = orc.gbuffer(sc, cam, lens)
+    out = orc.render_frame(sc, cam, lens, synth.Params(m=255, mask_mode=synth.MASK_ALL), gb)
+    h = out["resolve"][1][..., 3]                                   # hit ratio per pixel
+    a = lens.focal / lens.fnum
+    rho = 0.5 * a * (lens.focus - z1) / lens.focus
+    tx = synth.half_fov_tan(lens)
+    qx = np.arange(512)
+    u = (2 * (qx + 0.5) / 512 - 1) * tx                             # line of sight at z1: x = u * z1
+    s = u * z1 / rho
+    sc_ = np.clip(s, -1, 1)
+    # part of the disc beyond x = 0 on the side away from its centre
+    seg = (np.arccos(np.abs(sc_)) - np.abs(sc_) * np.sqrt(1 - sc_ ** 2)) / math.pi
+    want = np.where(s > 0, seg, 1.0 - seg)                          # fraction at x < 0 (occluder side)
+    got = h.mean(0)
+    band = np.abs(s) < 1.2
+    assert band.sum() > 20
+    err = np.abs(got[band] - want[band])
+    assert err.max() < 0.09 and err.mean() < 0.03
+
+
+# ---------------------------------------------------------------- temporal
+
+def test_moving_average_closed_form(orc):
+    """Static camera, constant far-field input c0, history H: after n frames
+    the accumulated colour is c0 + 0.95^n (H - c0) (3.2.3)."""
+    lens = synth.Lens()
+    scene = plane_scene(40.0, albedo=(0.7, 0.2, 0.4))
+    sc = orc.OracleScene(scene)
+    cam = synth.look_camera((0, 0, 0), 0, 0, 64, 32)
+    gb = orc.gbuffer(sc, cam, lens)
+    params = synth.Params(m=1, mask_mode=synth.MASK_ALL)
+    npx = 16 * 32
+    Hc = np.array([0.1, 0.9, 0.5], np.float32)
+    hist = orc.history_zeros(64, 32)
+    hist[4 * npx:8 * npx] = np.tile(np.concatenate([Hc, [1.0]]), npx)
+    out0 = orc.render_frame(sc, cam, lens, params, gb)
+    c0 = out0["resolve"][1][..., :3].reshape(-1, 3)[0].astype(np.float64)
+    for n in range(1, 6):
+        out = orc.render_frame(sc, dataclasses.replace(cam, frame=n), lens, params, gb, hist_in=hist,
+                               prev_cam=cam, prev_lens=lens)
+        want = c0 + 0.95 ** n * (Hc - c0)
+        np.testing.assert_allclose(out["temporal"][0][..., :3].reshape(-1, 3), np.tile(want, (npx, 1)), atol=2e-6)
+        hist = out["hist_out"]
+
+
+def test_reset_equals_first_frame(orc, small):
+    c = small
+    cam1 = synth.pan_camera(c["cam"], 0.02)
+    gb1 = orc.gbuffer(c["sc"], cam1, c["lens"])
+    garbage = np.full_like(c["out"]["hist_out"], 7.0)
+    a = orc.render_frame(c["sc"], cam1, c["lens"], c["params"], gb1, hist_in=garbage, prev_cam=c["cam"],
+                         prev_lens=c["lens"], reset=True)
+    b = orc.render_frame(c["sc"], cam1, c["lens"], c["params"], gb1)
+    assert np.array_equal(a["colour"], b["colour"]) and np.array_equal(a["hist_out"], b["hist_out"])
+
+
+def test_history_reprojection_static_and_pan(orc, small):
+    c = small
+    out1 = orc.render_frame(c["sc"], dataclasses.replace(c["cam"], frame=1), c["lens"], c["params"], c["gb"],
+                            hist_in=c["out"]["hist_out"], prev_cam=c["cam"], prev_lens=c["lens"])
+    hw = 128
+    valid = c["out"]["mask"].ravel() > 0
+    idx = out1["prev_idx"].ravel()
+    assert np.array_equal(idx[valid], np.flatnonzero(valid))
+    # temporal variance stays non-negative and the blur is the 3x3 binomial
+    var = out1["temporal"][1][..., 2]
+    assert (var >= 0).all()
+    k = np.outer([1, 2, 1], [1, 2, 1]) / 16.0
+    blur = ndi.correlate(var.astype(np.float64), k, mode="nearest")
+    np.testing.assert_allclose(out1["var_blur"], blur, rtol=1e-5, atol=1e-12)
+
+
+# ---------------------------------------------------------------- reconstruction
+
+def test_zero_variance_weight_keeps_median(orc, small):
+    """Eq. (5) with b = 0: the reconstruction returns the median-filtered
+    ray-traced colour unchanged (3.2.4)."""
+    c = small
+    p = dataclasses.replace(c["params"], var_recon_w=0.0)
+    out = orc.render_frame(c["sc"], c["cam"], c["lens"], p, c["gb"])
+    valid = out["temporal"][0][..., 3] > 0
+    assert np.array_equal(out["recon"][valid][:, :3], out["rtmed"][valid][:, :3])
+
+
+def test_rt_median_is_median_over_valid(small):
+    T0 = small["out"]["temporal"][0]
+    valid = T0[..., 3] > 0
+    hh, hw = valid.shape
+    for y, x in list(zip(*np.nonzero(valid)))[::97]:
+        for c in range(3):
+            vals = []
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    yy, xx = min(max(y + dy, 0), hh - 1), min(max(x + dx, 0), hw - 1)
+                    vals.append(T0[yy, xx, c] if valid[yy, xx] else T0[y, x, c])
+            assert small["out"]["rtmed"][y, x, c] == np.float32(np.median(vals))
+
+
+def test_mip_chain_box_average(small):
+    out = small["out"]
+    from oracle import mip_dims
+    dims = mip_dims(128, 128)
+    off = 0
+    levels = []
+    for w, h in dims:
+        levels.append(out["mips"][off:off + w * h * 4].reshape(h, w, 4))
+        off += w * h * 4
+    m0 = levels[0]
+    np.testing.assert_array_equal(m0[..., 3], (out["temporal"][0][..., 3] > 0).astype(np.float32))
+    for L in range(1, 4):
+        src = levels[L - 1].astype(np.float64)
+        want = 0.25 * (src[0::2, 0::2] + src[0::2, 1::2] + src[1::2, 0::2] + src[1::2, 1::2])
+        np.testing.assert_allclose(levels[L], want, rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- estimator
+
+def test_ray_traced_dof_converges_to_lens_integral(orc, small):
+    """Cook's distributed ray tracing (3.2.2) is a Monte Carlo estimate of the
+    lens integral: against a 64 x 64 stratified quadrature of the aperture the
+    RMS error falls roughly as spp^-1/2."""
+    c = small
+    T0 = c["out"]["resolve"][1][..., 3]
+    # silhouette pixels of the foreground bars: partial hit ratio
+    cand = np.flatnonzero((T0.ravel() > 0.05) & (T0.ravel() < 0.95))[:48]
+    assert cand.size >= 24
+    ref = orc.lens_integral(c["sc"], c["cam"], c["lens"], cand, grid=64).astype(np.float64)
+    errs = []
+    for spp in (1, 4, 16, 64, 256):
+        est = orc.pixel_estimate(c["sc"], c["cam"], c["lens"], cand, spp).astype(np.float64)
+        errs.append(math.sqrt(((est - ref) ** 2).mean()))
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < errs[1] / 4.0
+    assert errs[-1] < 0.03
