@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Hybrid depth-of-field pass: throughput on one MI355X.
+
+Workload: 1920x1080, 60-frame seeded camera path through a procedural scene
+of 1,183,042 triangles (4096 UV spheres of 240 triangles at depth 5-80, a
+foreground band of 50k four-triangle grass blades at depth 0.5-3, a ground
+quad), FP16 colour/normal + FP32 depth G-buffer, thin lens f = 50 mm,
+N = 1.4, focus 15, up to 8 rays per masked half-res pixel, temporal and
+spatial reconstruction.  A step is one dof_render_frame (every stage of the
+pass); the G-buffers are rendered beforehand and stay resident in HBM.
+
+Prints one JSON line: frames/s (value), masked Grays/s, p50/p99 frame ms,
+per-stage device ms, the roofline of the dominant kernel (live HIP-event
+timing) and the CPU oracle's frames/s on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--m", type=int, default=8)
+    ap.add_argument("--stage-frames", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def stage_bytes(stage, W, H, P, R):
+    """Compulsory HBM bytes of one launch of a stage: every input element it
+    depends on read once and every output written once, in the formats the
+    pass uses (FP16 colour/normal G-buffer, FP32 planes, FP16 output)."""
+    F = W * H            # full-res pixels
+    h = F // 4           # half-res pixels
+    table = {
+        # colour 8 B + depth 4 B per full-res px, one normal (8 B) per quad; out colr 16 + zn 16 + z 4
+        "reduce": F * 12 + h * 8 + h * 36,
+        "dilate": 0,
+        "prefilter": h * 16 + h * 16,
+        "gather": h * 16 + h * 4 + h * 16,          # colour+CoC and depth in, v_p + bokeh out
+        "median": h * 16 + h * 16,
+        "mask": h * 16 + h * 52 + h * 4 + h * 1,    # zn, history in, prev index + mask out
+        "compact": 2 * h + P * 8 + R * 4,
+        "trace": R * (12 + 40),                     # queue/base/pixel of each ray in; hit, t, colour, position out
+        "resolve": R * 40 + P * 64,
+        "temporal": h * (1 + 4 + 64 + 52) + h * (32 + 48),
+        "blur_median_mips": h * (16 + 4) + h * (4 + 4 + 16 + 16) + h * 16 // 3,
+        "recon": h * (16 + 16 + 16 + 4) + h * 16,
+        "composite": F * (8 + 4) + h * (16 + 16 + 16 + 16) + F * 8,
+    }
+    return table[stage]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a "
+                                   "design note, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2210_06158_amd import dof, synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
+
+    scene, cams, lens, params = synth.scene_1080p()
+    params.m = args.m
+    W, H = cams[0].width, cams[0].height
+    nfr = len(cams)
+    log(f"scene: {scene.ntri} triangles, {W}x{H}, m={params.m}")
+
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        gs.build_bvh()
+    e1.record()
+    torch.cuda.synchronize()
+    bvh_ms = e0.elapsed_time(e1) / 3
+    log(f"bvh build {bvh_ms:.3f} ms")
+
+    gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in cams]
+    torch.cuda.synchronize()
+    hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
+    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F)
+
+    def step(i, frame):
+        f = i % nfr
+        prev = cams[f - 1] if f > 0 else None
+        frame.render(gs, cams[f], lens, gbs[f], hist[(i + 1) % 2] if prev is not None else None, hist[i % 2],
+                     prev_cam=prev, prev_lens=lens)
+
+    for i in range(args.warmup):
+        step(i, fr)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    stats = torch.zeros((K, 8), dtype=torch.int32, device=dev)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for k in range(K):
+        starts[k].record()
+        step(args.warmup + k, fr)
+        ends[k].record()
+        stats[k].copy_(fr.stats, non_blocking=True)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    frame_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    st = stats.cpu().numpy().astype(np.int64)
+    rays = int(st[:, 1].sum())
+    masked = int(st[:, 0].sum())
+    fps = K / (total_ms / 1e3)
+    log(f"timed {K} frames: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
+
+    # live per-stage timing (same workload, HIP events around every stage)
+    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True)
+    sums = {s: 0.0 for s in dof.STAGES}
+    t_rays = 0
+    t_masked = 0
+    nst = min(args.stage_frames, K)
+    for k in range(nst):
+        step(args.warmup + k, frt)
+        ts = gs.stage_times()
+        for s, v in ts.items():
+            sums[s] += v
+        sv = frt.stats.cpu().numpy()
+        t_masked += int(sv[0])
+        t_rays += int(sv[1])
+    stage_ms = {s: v / nst for s, v in sums.items()}
+    dom = max(stage_ms, key=stage_ms.get)
+    P_avg, R_avg = t_masked / nst, t_rays / nst
+    dom_bytes = stage_bytes(dom, W, H, P_avg, R_avg)
+    achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "bytes_per_launch": int(dom_bytes), "ms_per_launch": round(stage_ms[dom], 5)}
+    trace_grays = (t_rays / (sums["trace"] * 1e-3) / 1e9) if sums["trace"] > 0 else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cams, lens, params, args.cpu_seconds, log)
+
+    out = {
+        "metric": "hybrid DoF frames/s at 1080p (1 MI355X)",
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1920x1080 hybrid DoF, 60-frame camera path, 1,183,042-triangle procedural scene "
+                               "(4096 spheres + 50k grass blades), m=8, FP16 G-buffer, FP16 output",
+                   "resolution": [W, H], "triangles": scene.ntri, "m": params.m, "frames_in_path": nfr},
+        "masked_grays_per_s": round(rays / (total_ms * 1e-3) / 1e9, 4),
+        "trace_kernel_grays_per_s": round(trace_grays, 4) if trace_grays else None,
+        "rays_per_frame": round(rays / K, 1),
+        "masked_px_per_frame": round(masked / K, 1),
+        "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),
+        "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 4),
+        "bvh_build_ms": round(bvh_ms, 3),
+        "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
+        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, cams, lens, params, budget_s, log):
+    """The CPU oracle timed on this host on a bounded sample of the same
+    workload (whole frames of the 1080p path; G-buffer rendered untimed)."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    oracle.set_threads(cores)
+    osc = oracle.OracleScene(scene)
+    t = time.perf_counter()
+    osc.build_bvh()
+    bvh_s = time.perf_counter() - t
+    done, spent = 0, 0.0
+    hist, prev = None, None
+    for f in range(len(cams)):
+        gb = oracle.gbuffer(osc, cams[f], lens)
+        t = time.perf_counter()
+        out = oracle.render_frame(osc, cams[f], lens, params, gb, hist_in=hist, prev_cam=prev, prev_lens=lens,
+                                  debug=False)
+        spent += time.perf_counter() - t
+        done += 1
+        hist, prev = out["hist_out"], cams[f]
+        log(f"cpu oracle frame {f}: {spent:.2f} s total")
+        if spent >= budget_s or done >= 3:
+            break
+    return {"value": round(done / spent, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} consecutive 1080p frames of the same camera path (G-buffer rendered untimed), "
+                      f"oracle BVH build {bvh_s:.2f} s untimed"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * libdof -- hybrid depth-of-field pass for AMD Instinct MI355X (gfx950).
+ *
+ * Implements the per-frame pass of Tan, Chua, Biette & Bhojan, "A Hybrid
+ * System for Real-Time Rendering of Depth of Field Effect in Games":
+ * a post-process gather blur (section 3.1), thin-lens rays traced only where
+ * a ray mask asks for them (3.2.1-3.2.2), temporal and spatial reconstruction
+ * of those sparse samples (3.2.3-3.2.4) and the adaptive composite of both
+ * (3.3).  Every stage is a HIP kernel; this header is the whole interface.
+ *
+ * Conventions
+ *  - Plain C.  Every call returns a dof_status; 0 is success.  On failure
+ *    dof_last_error() returns a message for the calling thread.  No C++
+ *    exception crosses this boundary.
+ *  - "device pointer" means memory on the current HIP device; "host pointer"
+ *    means ordinary host memory.  The library never allocates device memory:
+ *    the caller owns every device buffer (scene arena, history, outputs,
+ *    scratch) and sizes it with the *_bytes() queries.  Host structs are
+ *    read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work is enqueued on it; no call synchronises the device
+ *    except where stated.  Asynchronous device faults surface as
+ *    DOF_E_DEVICE on a later call.
+ *  - Images are row-major, row 0 at the top; pixel (x, y) is at y * W + x.
+ *    Full-resolution W and H must be even; half resolution is W/2 x H/2.
+ *  - Camera: orthonormal right/up/forward, view depth z = (P - pos) . fwd;
+ *    pixel (x, y) looks along fwd + u right + v up with
+ *    u = (2 (x + 1/2) / W - 1) tan_x, v = (1 - 2 (y + 1/2) / H) tan_y,
+ *    tan_x = w_s (d - f) / (2 f d) (sensor at the focused image distance),
+ *    tan_y = tan_x H / W.
+ *  - A dof_scene must not be used from two threads at once; distinct scenes
+ *    may be.
+ */
+#ifndef DOF_H
+#define DOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOF_ABI_VERSION 1
+
+typedef int32_t dof_status;
+#define DOF_OK 0
+#define DOF_E_INVALID 1     /* bad argument: null pointer, size, format, range */
+#define DOF_E_NOMEM 2       /* a caller-provided buffer is too small */
+#define DOF_E_DEVICE 3      /* a HIP call failed (message in dof_last_error) */
+#define DOF_E_STATE 4       /* call out of order, e.g. render before build */
+#define DOF_E_UNSUPPORTED 5 /* valid but not implemented (e.g. tile != 16) */
+
+#define DOF_RGBA32F 0       /* 4 x float per pixel, 16 B */
+#define DOF_RGBA16F 1       /* 4 x IEEE half per pixel, 8 B */
+
+#define DOF_MASK_ADAPTIVE 0 /* ray count from eqs. (2)-(4) */
+#define DOF_MASK_FIXED 1    /* m rays wherever the adaptive count is > 0 */
+#define DOF_MASK_ALL 2      /* m rays at every half-res pixel */
+
+typedef struct {
+    float pos[3], right[3], up[3], fwd[3];
+    int32_t width, height;  /* full resolution */
+    uint32_t frame, seed;   /* counters of the lens-sample hash */
+} dof_camera;
+
+/* Thin lens (sections 1.1, 3.3): focal length f, f-number N (aperture
+ * diameter a = f / N; N = +inf gives a pinhole), focus distance d, sensor
+ * width w_s, all in scene units.  blades = 0 for a circular aperture, else a
+ * regular polygon with 3..16 blades rotated by blade_rot radians. */
+typedef struct {
+    float focal, fnum, focus, sensor;
+    int32_t blades;
+    float blade_rot;
+} dof_lens;
+
+/* Every tunable of the pass, with the paper's values as defaults
+ * (dof_default_params).  m: ray budget per pixel (3.2.1), 1..255.
+ * s: eq. (2) scale (4.2).  var_mask_w: eq. (4) weight (1e5).  alpha: history
+ * weight of the moving average (0.95, 3.2.3); alpha_motion: reduced weight
+ * when the camera moved.  var_recon_w, b_max: eq. (5).  h_edge: eq. (7).
+ * lod_scale, lod_max: eq. (8).  depth_range: main-filter depth range (0.1 =
+ * 10 cm, 4.2).  r_max: largest gather radius in half-res pixels.  tile:
+ * neighbourhood-max tile side (16 only).  l_spec: luma of a "high specular"
+ * tap (3.1.2).  trace_blocks: blocks of the persistent traversal kernel (0 =
+ * 5 per compute unit).  timing: see dof_stage_times. */
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(dof_params) */
+    int32_t m;
+    float s, var_mask_w, alpha, alpha_motion, var_recon_w, b_max, h_edge;
+    float lod_scale, lod_max, depth_range, r_max;
+    int32_t tile;
+    float l_spec;
+    int32_t mask_mode;
+    int32_t trace_blocks;
+    int32_t timing;         /* nonzero: record a HIP event pair per stage */
+    int32_t reserved[3];
+} dof_params;
+
+/* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view
+ * depth (+inf for the sky), world normal xyz (w ignored).  Device pointers. */
+typedef struct {
+    const void *colour;
+    int32_t colour_format;  /* DOF_RGBA32F or DOF_RGBA16F */
+    const float *depth;
+    const void *normal;
+    int32_t normal_format;
+} dof_gbuffer;
+
+/* Temporal history (3.2.3): dof_history_bytes() per buffer.  `in` is last
+ * frame's `out` (ignored when reset != 0); `out` is written completely.
+ * in and out must not overlap.  prev_camera / prev_lens: the view of `in`.
+ * Record layout (per half-res pixel, four planes back to back): float4
+ * (near rgb, hit ratio), float4 (far rgb, age), float4 (near CoC, far CoC,
+ * luma mean, luma second moment), float (blurred luma variance). */
+typedef struct {
+    const void *in;
+    void *out;
+    dof_camera prev_camera;
+    dof_lens prev_lens;
+    int32_t reset;
+} dof_history_io;
+
+/* Device-side counters of one frame. */
+typedef struct {
+    uint32_t masked_px;     /* half-res pixels with at least one ray */
+    uint32_t rays;          /* thin-lens rays traced */
+    uint32_t reserved[6];
+} dof_stats;
+
+typedef struct {
+    void *colour;           /* device, W x H, colour_format */
+    int32_t colour_format;
+    uint8_t *mask;          /* device, W/2 x H/2 ray counts (the ray mask) */
+    dof_stats *stats;       /* device, may be NULL */
+} dof_frame_out;
+
+typedef struct {
+    int32_t ntri;
+    const float *verts;     /* host, 9 floats per triangle (v0 v1 v2 xyz) */
+    const float *albedo;    /* host, 3 floats per triangle */
+    float light_dir[3];     /* direction the light travels (unit) */
+    float light_rad[3], ambient[3], sky[3];
+} dof_scene_desc;
+
+typedef struct dof_scene dof_scene;
+
+/* Device views of the acceleration structure (for inspection and tests).
+ * keys: sorted 30-bit Morton codes; ids: triangle ids in the same order;
+ * nodes: ntri-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
+ * float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z, R.lo.z,
+ * R.hi.z), uint4 (left, right, 0, 0)}, child bit 31 = leaf (sorted index);
+ * parent: 2 ntri - 1 entries (internal nodes, then leaves), root = ~0u;
+ * tris: 3 float4 per leaf in sorted order (w of the first = id bits). */
+typedef struct {
+    int32_t ntri;
+    const uint32_t *keys, *ids, *parent;
+    const void *nodes, *tris;
+} dof_bvh_view;
+
+/* Device pointers into a frame's scratch (valid after dof_render_frame). */
+typedef struct {
+    void *colr, *zn, *tile_max, *tile_dil, *pre, *gather, *ppmed, *prev_idx;
+    void *queue, *ray_base, *ray_hit, *ray_t, *ray_col, *ray_pos;
+    void *resolve, *temporal, *var_blur, *rtmed, *mips, *recon, *counters;
+} dof_debug_view;
+
+int32_t dof_abi_version(void);
+const char *dof_last_error(void);
+void dof_default_params(dof_params *p);
+
+/* Scene arena size for ntri triangles (triangles, BVH and build scratch). */
+dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);
+
+/* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes) on
+ * `stream` and returns a host handle; the arena must outlive the scene.
+ * Synchronises `stream` once (the host arrays may be freed on return). */
+dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t arena_bytes,
+                            void *stream, dof_scene **out);
+
+/* LBVH build on the device (Morton codes, radix sort, binary radix tree,
+ * bottom-up bounds) -- the acceleration structure the paper builds with DXR
+ * inside its Ray Trace timing (5.2). */
+dof_status dof_build_bvh(dof_scene *scene, void *stream);
+dof_status dof_bvh_view_get(const dof_scene *scene, dof_bvh_view *out);
+void dof_destroy_scene(dof_scene *scene);
+
+/* Closest hit of n rays (device arrays org[3n], dir[3n]; dir need not be
+ * unit) -> hit[n] original triangle id or -1, t[n] distance or +inf. */
+dof_status dof_trace_rays(const dof_scene *scene, int64_t n, const float *org, const float *dir,
+                          int32_t *hit, float *t, void *stream);
+
+/* All-in-focus G-buffer through the lens centre, one ray per full-res pixel
+ * (the sharp raster image of section 3, produced here by ray casting). */
+dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
+                              void *colour, int32_t colour_format, float *depth, void *normal,
+                              int32_t normal_format, void *stream);
+
+dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes);
+dof_status dof_history_reset(void *hist, int32_t width, int32_t height, void *stream);
+dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_params *p, size_t *bytes);
+
+/* The pass (sections 3.1-3.3) for one frame: CoC and half-res reduce, tile
+ * max, prefilter, 81-tap gather, median, ray mask, compaction, thin-lens
+ * traversal, resolve, temporal accumulation, variance blur, median + mips,
+ * reconstruction, composite.  Enqueued on `stream`, no host sync. */
+dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
+                            const dof_gbuffer *gb, const dof_history_io *hist, const dof_params *p,
+                            const dof_frame_out *out, void *scratch, size_t scratch_bytes,
+                            void *stream);
+
+/* Stages timed when params.timing is set, in launch order. */
+#define DOF_NUM_STAGES 13
+/* Per-stage device time (ms) of the scene's most recent frame rendered with
+ * params.timing != 0: reduce, dilate, prefilter, gather, median, mask,
+ * compaction, trace, resolve, temporal, blur+median+mips, reconstruction,
+ * composite.  Waits for that frame's last event (host sync on it only).
+ * Writes min(cap, DOF_NUM_STAGES) values to ms (host) and the count to *n. */
+dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n);
+
+dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, const dof_params *p,
+                              dof_debug_view *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,567 @@
+// C ABI of libdof (include/dof.h): argument checks, buffer layouts, the
+// lens-derived constants of a frame and the launch sequence.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "dof_internal.h"
+
+struct dof_scene {
+    dof::SceneDev dev;
+    dof::SceneShade shade;
+    char *arena;
+    size_t arena_bytes;
+    bool built;
+    bool events_ready;   // ev[] created (host-side timing objects)
+    bool timed_frame;    // ev[] hold the last timed frame
+    hipEvent_t ev[DOF_NUM_STAGES + 1];
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+dof_status fail(dof_status code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define DOF_HIP(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(DOF_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct SceneLayout {
+    size_t verts_in, albedo_in, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp, flags, hist, bounds, total;
+    int sort_blocks, bound_blocks;
+};
+
+SceneLayout scene_layout(int64_t n)
+{
+    SceneLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const int64_t ni = n > 1 ? n - 1 : 1;
+    L.sort_blocks = (int)((n + 4095) / 4096);
+    L.bound_blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    L.verts_in = take(sizeof(float) * 9 * n);
+    L.albedo_in = take(sizeof(float) * 3 * n);
+    L.tris = take(sizeof(float4) * 3 * n);
+    L.albedo = take(sizeof(float4) * n);
+    L.nodes = take(sizeof(dof::BvhNode) * ni);
+    L.parent = take(sizeof(uint32_t) * (2 * n - 1));
+    L.keys = take(sizeof(uint32_t) * n);
+    L.keys_tmp = take(sizeof(uint32_t) * n);
+    L.ids = take(sizeof(uint32_t) * n);
+    L.ids_tmp = take(sizeof(uint32_t) * n);
+    L.flags = take(sizeof(uint32_t) * ni);
+    L.hist = take(sizeof(uint32_t) * 256 * (size_t)L.sort_blocks);
+    L.bounds = take(sizeof(float) * (6 * (size_t)L.bound_blocks + 8));
+    L.total = off;
+    return L;
+}
+
+dof::ScratchLayout frame_layout(int W, int H, int m)
+{
+    dof::ScratchLayout L{};
+    const size_t np = (size_t)(W / 2) * (H / 2);
+    const int T = dof::kTile;
+    const size_t ntiles = (size_t)((W / 2 + T - 1) / T) * ((H / 2 + T - 1) / T);
+    const size_t nr = np * (size_t)m;
+    L.nchunks = (int64_t)((np + dof::kChunk - 1) / dof::kChunk);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return o;
+    };
+    L.colr = take(16 * np);
+    L.zn = take(16 * np);
+    L.zh = take(4 * np);
+    L.tile_max = take(4 * ntiles);
+    L.tile_dil = take(4 * ntiles);
+    L.pre = take(16 * np);
+    L.gather = take(16 * np);
+    L.ppmed = take(16 * np);
+    L.prev_idx = take(4 * np);
+    L.chunk_cnt = take(8 * (size_t)L.nchunks);
+    L.chunk_off = take(8 * (size_t)L.nchunks);
+    L.counters = take(64);
+    L.queue = take(4 * np);
+    L.ray_base = take(4 * np);
+    L.ray_pix = take(4 * nr);
+    L.ray_hit = take(4 * nr);
+    L.ray_t = take(4 * nr);
+    L.ray_col = take(16 * nr);
+    L.ray_pos = take(16 * nr);
+    L.resolve = take(64 * np);
+    L.temporal = take(32 * np);
+    L.var_blur = take(4 * np);
+    L.rtmed = take(16 * np);
+    size_t mt = 0;
+    int w = W / 2, h = H / 2;
+    for (int l = 0; l < 4; ++l) {
+        mt += (size_t)w * h;
+        w = (w + 1) >> 1;
+        h = (h + 1) >> 1;
+    }
+    L.mips = take(16 * mt);
+    L.recon = take(16 * np);
+    L.spill = 0;
+    L.spill_threads = 0;
+    L.total = off;
+    return L;
+}
+
+struct LensDerived {
+    float a, tanx, tany, cock, znb, ramp, half_a;
+};
+
+// Thin-lens constants (sections 1.1, 3.3): sensor at the focused image
+// distance v = f d / (d - f); CoC(z) = (a f / (d - f)) (W / w_s) |1 - d / z|
+// in pixels; eq. (6)'s near bound z_nb with w_i = W.
+LensDerived lens_derived(const dof_lens &l, int W, int H)
+{
+    LensDerived q;
+    const float f = l.focal, d = l.focus, ws = l.sensor;
+    q.a = f / l.fnum;
+    q.tanx = (ws * (d - f)) / ((2.0f * f) * d);
+    q.tany = q.tanx * ((float)H / (float)W);
+    q.cock = ((q.a * f) / (d - f)) * ((float)W / ws);
+    const float g = (dof::kSqrt2 * (d - f)) * (ws / (float)W);
+    const float af = q.a * f;
+    q.znb = (af * d) / (af + g);
+    q.ramp = 2.0f * (d - q.znb);
+    q.half_a = q.a * 0.5f;
+    return q;
+}
+
+void view_of(const dof_camera &c, const LensDerived &q, dof::ViewConst &v)
+{
+    memcpy(v.pos, c.pos, sizeof(v.pos));
+    memcpy(v.right, c.right, sizeof(v.right));
+    memcpy(v.up, c.up, sizeof(v.up));
+    memcpy(v.fwd, c.fwd, sizeof(v.fwd));
+    v.tanx = q.tanx;
+    v.tany = q.tany;
+}
+
+// 81 taps: centre + rings k = 1..4 of 8k taps at radius k/4, angle 2 pi j / 8k
+// (section 3.1.1), evaluated in binary64 then rounded.
+dof::Rings make_rings()
+{
+    dof::Rings r;
+    r.ox[0] = 0.0f;
+    r.oy[0] = 0.0f;
+    r.frac[0] = 0.0f;
+    int i = 1;
+    const double pi = 3.14159265358979323846;
+    for (int k = 1; k <= 4; ++k) {
+        const int taps = 8 * k;
+        for (int j = 0; j < taps; ++j, ++i) {
+            const double ang = 2.0 * pi * (double)j / (double)taps;
+            r.ox[i] = (float)(k / 4.0 * cos(ang));
+            r.oy[i] = (float)(k / 4.0 * sin(ang));
+            r.frac[i] = (float)k * 0.25f;
+        }
+    }
+    return r;
+}
+
+// Regular-polygon aperture: inward edge normals at blade_rot + pi/n + 2 pi i/n,
+// apothem cos(pi / n) for a unit circumradius.
+void make_aperture(const dof_lens &l, dof::Aperture &ap)
+{
+    memset(&ap, 0, sizeof(ap));
+    ap.blades = l.blades;
+    ap.apothem = 1.0f;
+    if (l.blades >= 3) {
+        const double pi = 3.14159265358979323846;
+        const int n = l.blades;
+        ap.apothem = (float)cos(pi / n);
+        for (int i = 0; i < n; ++i) {
+            const double th = (double)l.blade_rot + pi / n + 2.0 * pi * i / n;
+            ap.nx[i] = (float)cos(th);
+            ap.ny[i] = (float)sin(th);
+        }
+    }
+}
+
+bool lens_ok(const dof_lens *l)
+{
+    if (!l) return false;
+    if (!(l->focal > 0.0f) || !(l->fnum > 0.0f) || !(l->sensor > 0.0f) || !(l->focus > l->focal)) return false;
+    if (!(l->focal < INFINITY) || !(l->focus < INFINITY) || !(l->sensor < INFINITY)) return false;
+    return l->blades == 0 || (l->blades >= 3 && l->blades <= dof::kMaxBlades);
+}
+
+bool camera_ok(const dof_camera *c)
+{
+    if (!c || c->width <= 0 || c->height <= 0 || (c->width & 1) || (c->height & 1)) return false;
+    if ((int64_t)c->width * c->height > (int64_t)1 << 30) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(c->pos[a]) || !isfinite(c->right[a]) || !isfinite(c->up[a]) || !isfinite(c->fwd[a])) return false;
+    return true;
+}
+
+dof_status params_check(const dof_params *p)
+{
+    if (!p) return fail(DOF_E_INVALID, "params is NULL");
+    if (p->struct_size != sizeof(dof_params)) return fail(DOF_E_INVALID, "params.struct_size mismatch");
+    if (p->m < 1 || p->m > 255) return fail(DOF_E_INVALID, "m must be in 1..255");
+    if (p->tile != dof::kTile) return fail(DOF_E_UNSUPPORTED, "tile must be 16");
+    if (p->mask_mode < 0 || p->mask_mode > 2) return fail(DOF_E_INVALID, "bad mask_mode");
+    if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
+    if (!(p->lod_max >= 0.0f)) return fail(DOF_E_INVALID, "bad lod_max");
+    if (p->trace_blocks < 0) return fail(DOF_E_INVALID, "bad trace_blocks");
+    return DOF_OK;
+}
+
+void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens &lens, const dof_params &p,
+                      bool have_hist, bool motion, const dof_camera &pcam, const dof_lens &plens,
+                      dof::FrameConst &fc)
+{
+    memset(&fc, 0, sizeof(fc));
+    const int W = cam.width, H = cam.height;
+    fc.W = W;
+    fc.H = H;
+    fc.hw = W / 2;
+    fc.hh = H / 2;
+    fc.T = p.tile;
+    fc.tw = (fc.hw + fc.T - 1) / fc.T;
+    fc.th = (fc.hh + fc.T - 1) / fc.T;
+    fc.D = (int)ceilf(p.r_max / (float)fc.T);
+    fc.m = p.m;
+    fc.mask_mode = p.mask_mode;
+    fc.have_hist = have_hist;
+    fc.motion = motion;
+    fc.seed = cam.seed;
+    fc.frame = cam.frame;
+    const LensDerived q = lens_derived(lens, W, H);
+    fc.d = lens.focus;
+    fc.half_a = q.half_a;
+    fc.cock = q.cock;
+    fc.znb = q.znb;
+    fc.ramp = q.ramp;
+    fc.s = p.s;
+    fc.var_mask_w = p.var_mask_w;
+    fc.alpha_h = motion ? p.alpha_motion : p.alpha;
+    fc.var_recon_w = p.var_recon_w;
+    fc.b_max = p.b_max;
+    fc.h_edge = p.h_edge;
+    fc.lod_scale = p.lod_scale;
+    fc.lod_max = p.lod_max;
+    fc.lod_levels = p.lod_max >= 3.0f ? 3 : (int)p.lod_max;
+    fc.depth_range = p.depth_range;
+    fc.r_max = p.r_max;
+    fc.l_spec = p.l_spec;
+    view_of(cam, q, fc.cur);
+    view_of(have_hist ? pcam : cam, have_hist ? lens_derived(plens, W, H) : q, fc.prev);
+    make_aperture(lens, fc.ap);
+    if (s) memcpy(&fc.shade, &s->shade, sizeof(fc.shade));
+    int w = fc.hw, h = fc.hh;
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+        fc.mw[l] = w;
+        fc.mh[l] = h;
+        fc.moff[l] = off;
+        off += (int64_t)w * h;
+        w = (w + 1) >> 1;
+        h = (h + 1) >> 1;
+    }
+}
+
+bool same_view(const dof_camera &a, const dof_camera &b, const dof_lens &la, const dof_lens &lb)
+{
+    return memcmp(a.pos, b.pos, sizeof(a.pos)) == 0 && memcmp(a.right, b.right, sizeof(a.right)) == 0 &&
+           memcmp(a.up, b.up, sizeof(a.up)) == 0 && memcmp(a.fwd, b.fwd, sizeof(a.fwd)) == 0 &&
+           memcmp(&la, &lb, sizeof(la)) == 0;
+}
+
+int default_trace_blocks()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
+    return cus * 5;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dof_abi_version(void) { return DOF_ABI_VERSION; }
+
+const char *dof_last_error(void) { return g_err; }
+
+void dof_default_params(dof_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(dof_params);
+    p->m = 8;
+    p->s = 0.8f;
+    p->var_mask_w = 1.0e5f;
+    p->alpha = 0.95f;
+    p->alpha_motion = 0.8f;
+    p->var_recon_w = 2000.0f;
+    p->b_max = 0.9f;
+    p->h_edge = 0.3f;
+    p->lod_scale = 0.05f;
+    p->lod_max = 3.0f;
+    p->depth_range = 0.1f;
+    p->r_max = 32.0f;
+    p->tile = dof::kTile;
+    p->l_spec = 1.0f;
+    p->mask_mode = DOF_MASK_ADAPTIVE;
+    p->trace_blocks = 0;
+}
+
+dof_status dof_scene_bytes(int32_t ntri, size_t *bytes)
+{
+    if (ntri <= 0 || !bytes) return fail(DOF_E_INVALID, "ntri must be > 0 and bytes non-NULL");
+    *bytes = scene_layout(ntri).total;
+    return DOF_OK;
+}
+
+dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t arena_bytes, void *stream,
+                            dof_scene **out)
+{
+    if (!desc || !out || !arena || !desc->verts || !desc->albedo || desc->ntri <= 0)
+        return fail(DOF_E_INVALID, "dof_create_scene: NULL argument or ntri <= 0");
+    *out = nullptr;
+    const SceneLayout L = scene_layout(desc->ntri);
+    if (arena_bytes < L.total) return fail(DOF_E_NOMEM, "scene arena needs %zu bytes, got %zu", L.total, arena_bytes);
+    dof_scene *s = new (std::nothrow) dof_scene;
+    if (!s) return fail(DOF_E_NOMEM, "host allocation failed");
+    memset(s, 0, sizeof(*s));
+    char *a = static_cast<char *>(arena);
+    s->arena = a;
+    s->arena_bytes = arena_bytes;
+    dof::SceneDev &d = s->dev;
+    d.ntri = desc->ntri;
+    d.verts_in = reinterpret_cast<float *>(a + L.verts_in);
+    d.albedo_in = reinterpret_cast<float *>(a + L.albedo_in);
+    d.tris = reinterpret_cast<float4 *>(a + L.tris);
+    d.albedo = reinterpret_cast<float4 *>(a + L.albedo);
+    d.nodes = reinterpret_cast<dof::BvhNode *>(a + L.nodes);
+    d.parent = reinterpret_cast<uint32_t *>(a + L.parent);
+    d.keys = reinterpret_cast<uint32_t *>(a + L.keys);
+    d.keys_tmp = reinterpret_cast<uint32_t *>(a + L.keys_tmp);
+    d.ids = reinterpret_cast<uint32_t *>(a + L.ids);
+    d.ids_tmp = reinterpret_cast<uint32_t *>(a + L.ids_tmp);
+    d.flags = reinterpret_cast<uint32_t *>(a + L.flags);
+    d.hist = reinterpret_cast<uint32_t *>(a + L.hist);
+    d.bounds = reinterpret_cast<float *>(a + L.bounds);
+    d.sort_blocks = L.sort_blocks;
+    d.bound_blocks = L.bound_blocks;
+    memcpy(s->shade.light_dir, desc->light_dir, sizeof(desc->light_dir));
+    memcpy(s->shade.light_rad, desc->light_rad, sizeof(desc->light_rad));
+    memcpy(s->shade.ambient, desc->ambient, sizeof(desc->ambient));
+    memcpy(s->shade.sky, desc->sky, sizeof(desc->sky));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(a + L.verts_in, desc->verts, sizeof(float) * 9 * (size_t)desc->ntri,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a + L.albedo_in, desc->albedo, sizeof(float) * 3 * (size_t)desc->ntri,
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(DOF_E_DEVICE, "scene upload: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return DOF_OK;
+}
+
+dof_status dof_build_bvh(dof_scene *scene, void *stream)
+{
+    if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
+    DOF_HIP(dof::launch_build_bvh(scene->dev, static_cast<hipStream_t>(stream)));
+    scene->built = true;
+    return DOF_OK;
+}
+
+dof_status dof_bvh_view_get(const dof_scene *scene, dof_bvh_view *out)
+{
+    if (!scene || !out) return fail(DOF_E_INVALID, "NULL argument");
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    out->ntri = scene->dev.ntri;
+    out->keys = scene->dev.keys;
+    out->ids = scene->dev.ids;
+    out->parent = scene->dev.parent;
+    out->nodes = scene->dev.nodes;
+    out->tris = scene->dev.tris;
+    return DOF_OK;
+}
+
+void dof_destroy_scene(dof_scene *scene)
+{
+    if (!scene) return;
+    if (scene->events_ready)
+        for (int i = 0; i <= DOF_NUM_STAGES; ++i) (void)hipEventDestroy(scene->ev[i]);
+    delete scene;
+}
+
+dof_status dof_trace_rays(const dof_scene *scene, int64_t n, const float *org, const float *dir, int32_t *hit,
+                          float *t, void *stream)
+{
+    if (!scene || n < 0 || (n > 0 && (!org || !dir || !hit || !t))) return fail(DOF_E_INVALID, "bad arguments");
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    if (n > ((int64_t)1 << 31)) return fail(DOF_E_INVALID, "too many rays");
+    DOF_HIP(dof::launch_trace_rays(scene->dev, n, org, dir, hit, t, static_cast<hipStream_t>(stream)));
+    return DOF_OK;
+}
+
+dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, const dof_lens *lens, void *colour,
+                              int32_t colour_format, float *depth, void *normal, int32_t normal_format, void *stream)
+{
+    if (!scene || !camera_ok(cam) || !lens_ok(lens) || !colour || !depth || !normal)
+        return fail(DOF_E_INVALID, "dof_render_gbuffer: bad arguments");
+    if ((colour_format != DOF_RGBA32F && colour_format != DOF_RGBA16F) ||
+        (normal_format != DOF_RGBA32F && normal_format != DOF_RGBA16F))
+        return fail(DOF_E_INVALID, "bad format");
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    dof_params p;
+    dof_default_params(&p);
+    dof::FrameConst fc;
+    fill_frame_const(scene, *cam, *lens, p, false, false, *cam, *lens, fc);
+    DOF_HIP(dof::launch_gbuffer(scene->dev, fc, colour, colour_format, depth, normal, normal_format,
+                                static_cast<hipStream_t>(stream)));
+    return DOF_OK;
+}
+
+dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes)
+{
+    if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
+        return fail(DOF_E_INVALID, "width/height must be even and positive");
+    *bytes = (size_t)(width / 2) * (height / 2) * 52;
+    return DOF_OK;
+}
+
+dof_status dof_history_reset(void *hist, int32_t width, int32_t height, void *stream)
+{
+    size_t b = 0;
+    dof_status st = dof_history_bytes(width, height, &b);
+    if (st != DOF_OK) return st;
+    if (!hist) return fail(DOF_E_INVALID, "hist is NULL");
+    DOF_HIP(dof::launch_history_reset(static_cast<float *>(hist), (int64_t)(b / 4), static_cast<hipStream_t>(stream)));
+    return DOF_OK;
+}
+
+dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_params *p, size_t *bytes)
+{
+    if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
+        return fail(DOF_E_INVALID, "width/height must be even and positive");
+    dof_status st = params_check(p);
+    if (st != DOF_OK) return st;
+    *bytes = frame_layout(width, height, p->m).total;
+    return DOF_OK;
+}
+
+dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *lens, const dof_gbuffer *gb,
+                            const dof_history_io *hist, const dof_params *p, const dof_frame_out *out, void *scratch,
+                            size_t scratch_bytes, void *stream)
+{
+    if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
+    if (!camera_ok(cam)) return fail(DOF_E_INVALID, "bad camera (size must be even and positive)");
+    if (!lens_ok(lens)) return fail(DOF_E_INVALID, "bad lens");
+    dof_status st = params_check(p);
+    if (st != DOF_OK) return st;
+    if (!gb || !gb->colour || !gb->depth || !gb->normal) return fail(DOF_E_INVALID, "bad G-buffer");
+    if ((gb->colour_format != DOF_RGBA32F && gb->colour_format != DOF_RGBA16F) ||
+        (gb->normal_format != DOF_RGBA32F && gb->normal_format != DOF_RGBA16F))
+        return fail(DOF_E_INVALID, "bad G-buffer format");
+    if (!hist || !hist->out) return fail(DOF_E_INVALID, "history output is NULL");
+    if (hist->in && hist->in == hist->out) return fail(DOF_E_INVALID, "history in and out must differ");
+    if (!out || !out->colour || !out->mask) return fail(DOF_E_INVALID, "bad frame output");
+    if (out->colour_format != DOF_RGBA32F && out->colour_format != DOF_RGBA16F)
+        return fail(DOF_E_INVALID, "bad output format");
+    if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    const dof::ScratchLayout L = frame_layout(cam->width, cam->height, p->m);
+    if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
+    const bool have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
+                           hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
+    const bool motion = have_hist && !same_view(*cam, hist->prev_camera, *lens, hist->prev_lens);
+    dof::FrameConst fc;
+    fill_frame_const(scene, *cam, *lens, *p, have_hist, motion, hist->prev_camera, hist->prev_lens, fc);
+    static const dof::Rings rings = make_rings();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *scr = static_cast<char *>(scratch);
+    const void *hin = have_hist ? hist->in : nullptr;
+    hipEvent_t *ev = nullptr;
+    if (p->timing) {
+        if (!scene->events_ready) {
+            for (int i = 0; i <= DOF_NUM_STAGES; ++i) DOF_HIP(hipEventCreate(&scene->ev[i]));
+            scene->events_ready = true;
+        }
+        ev = scene->ev;
+    }
+    DOF_HIP(dof::launch_frame_pre(fc, rings, L, scr, *gb, hin, out->mask, ev, s));
+    const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
+    DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
+    DOF_HIP(dof::launch_frame_post(fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
+    scene->timed_frame = ev != nullptr;
+    return DOF_OK;
+}
+
+dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n)
+{
+    if (!scene || !ms || cap < 0 || !n) return fail(DOF_E_INVALID, "bad arguments");
+    if (!scene->timed_frame) return fail(DOF_E_STATE, "no frame rendered with params.timing set");
+    DOF_HIP(hipEventSynchronize(scene->ev[DOF_NUM_STAGES]));
+    const int k = cap < DOF_NUM_STAGES ? cap : DOF_NUM_STAGES;
+    for (int i = 0; i < k; ++i) DOF_HIP(hipEventElapsedTime(&ms[i], scene->ev[i], scene->ev[i + 1]));
+    *n = k;
+    return DOF_OK;
+}
+
+dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, const dof_params *p, dof_debug_view *out)
+{
+    if (!scratch || !out || width <= 0 || height <= 0 || (width & 1) || (height & 1))
+        return fail(DOF_E_INVALID, "bad arguments");
+    dof_status st = params_check(p);
+    if (st != DOF_OK) return st;
+    const dof::ScratchLayout L = frame_layout(width, height, p->m);
+    char *s = static_cast<char *>(scratch);
+    out->colr = s + L.colr;
+    out->zn = s + L.zn;
+    out->tile_max = s + L.tile_max;
+    out->tile_dil = s + L.tile_dil;
+    out->pre = s + L.pre;
+    out->gather = s + L.gather;
+    out->ppmed = s + L.ppmed;
+    out->prev_idx = s + L.prev_idx;
+    out->queue = s + L.queue;
+    out->ray_base = s + L.ray_base;
+    out->ray_hit = s + L.ray_hit;
+    out->ray_t = s + L.ray_t;
+    out->ray_col = s + L.ray_col;
+    out->ray_pos = s + L.ray_pos;
+    out->resolve = s + L.resolve;
+    out->temporal = s + L.temporal;
+    out->var_blur = s + L.var_blur;
+    out->rtmed = s + L.rtmed;
+    out->mips = s + L.mips;
+    out->recon = s + L.recon;
+    out->counters = s + L.counters;
+    return DOF_OK;
+}
+
+}  // extern "C"

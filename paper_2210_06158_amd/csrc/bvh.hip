@@ -1,0 +1,360 @@
+// LBVH build on the device: the acceleration structure that replaces the
+// DXR build the paper times inside its Ray Trace pass (section 5.2).
+//
+//   centroid bounds -> 30-bit Morton keys -> stable LSD radix sort of
+//   (key, id) -> binary radix tree over the 62-bit keys (key << 32 | id)
+//   (Karras 2012) -> triangles reordered to leaf order -> bottom-up refit of
+//   the child boxes stored in each node.
+//
+// All results are bit-reproducible: min/max are compare-selects and the
+// sort is stable, so the tree depends only on the input triangles.
+#include "dof_internal.h"
+
+namespace dof {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kThreads * kSortItems;   // keys per sort block
+
+__device__ inline void tri_box3(const float *v, float lo[3], float hi[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float x = v[a], y = v[3 + a], z = v[6 + a];
+        float m = x;
+        m = y < m ? y : m;
+        m = z < m ? z : m;
+        lo[a] = m;
+        float M = x;
+        M = y > M ? y : M;
+        M = z > M ? z : M;
+        hi[a] = M;
+    }
+}
+
+__device__ inline float wave_min(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmin_cs(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline float wave_max(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmax_cs(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Per-block min/max of triangle-box centroids (grid-stride).
+__global__ __launch_bounds__(kThreads) void k_centroid_bounds(const float *__restrict__ verts, int n,
+                                                              float *__restrict__ partial)
+{
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        float v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = verts[9 * (size_t)i + k];
+        float bl[3], bh[3];
+        tri_box3(v, bl, bh);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float c = (bl[a] + bh[a]) * 0.5f;
+            lo[a] = fmin_cs(lo[a], c);
+            hi[a] = fmax_cs(hi[a], c);
+        }
+    }
+    __shared__ float red[6][kThreads / 64];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float m = wave_min(lo[a]), M = wave_max(hi[a]);
+        if (lane == 0) { red[a][w] = m; red[3 + a][w] = M; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int a = threadIdx.x;
+        float r = red[a][0];
+        for (int k = 1; k < kThreads / 64; ++k) r = a < 3 ? fmin_cs(r, red[a][k]) : fmax_cs(r, red[a][k]);
+        partial[6 * blockIdx.x + a] = r;
+    }
+}
+
+// Reduce the partial bounds; final slot = lo[3], inv[3] with inv = 1024 / extent.
+__global__ void k_bounds_final(float *__restrict__ partial, int nblocks)
+{
+    if (threadIdx.x != 0) return;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nblocks; ++b)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin_cs(lo[a], partial[6 * b + a]);
+            hi[a] = fmax_cs(hi[a], partial[6 * b + 3 + a]);
+        }
+    float *out = partial + 6 * (size_t)nblocks;
+    for (int a = 0; a < 3; ++a) {
+        float ext = hi[a] - lo[a];
+        out[a] = lo[a];
+        out[3 + a] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    }
+}
+
+__device__ inline uint32_t spread_bits10(uint32_t x)
+{
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ verts, int n,
+                                                     const float *__restrict__ fin, uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ ids)
+{
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = verts[9 * (size_t)i + k];
+    float bl[3], bh[3];
+    tri_box3(v, bl, bh);
+    uint32_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float c = (bl[a] + bh[a]) * 0.5f;
+        float t = floorf((c - fin[a]) * fin[3 + a]);
+        int qi = (int)t;
+        q[a] = (uint32_t)(qi > 1023 ? 1023 : qi);
+    }
+    keys[i] = (spread_bits10(q[0]) << 2) | (spread_bits10(q[1]) << 1) | spread_bits10(q[2]);
+    ids[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+// Per pass: digit histogram per tile (digit-major), one-block exclusive scan,
+// stable scatter.  Ranks inside a tile come from 8 wave ballots per round
+// (lanes sharing a digit), so equal digits keep their input order.
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int n, int shift,
+                                                         uint32_t *__restrict__ hist, int nblocks)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        size_t i = base + (size_t)r * kThreads + threadIdx.x;
+        if (i < (size_t)n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of `total` counters with one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *__restrict__ data, int total)
+{
+    __shared__ uint32_t part[1024];
+    int per = (total + 1023) / 1024;
+    int b = threadIdx.x * per, e = min(total, b + per);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        uint32_t v = data[i];
+        data[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                            const uint32_t *__restrict__ vin,
+                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                            int n, int shift, const uint32_t *__restrict__ offs,
+                                                            int nblocks)
+{
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kThreads / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    running[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kThreads / 64; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    size_t base = (size_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        size_t i = base + (size_t)r * kThreads + tid;
+        bool valid = i < (size_t)n;
+        uint32_t key = valid ? kin[i] : 0u;
+        uint32_t val = valid ? vin[i] : 0u;
+        uint32_t dg = (key >> shift) & 0xffu;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bb = __ballot((dg >> bit) & 1u);
+            match &= ((dg >> bit) & 1u) ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(match & lt);
+        if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = running[dg] + rank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][dg];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int k = 0; k < kThreads / 64; ++k) {
+            add += wcnt[k][tid];
+            wcnt[k][tid] = 0;
+        }
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- hierarchy
+
+__global__ __launch_bounds__(kThreads) void k_reorder(const float *__restrict__ verts, const float *__restrict__ alb,
+                                                      const uint32_t *__restrict__ ids, int n,
+                                                      float4 *__restrict__ tris, float4 *__restrict__ albedo)
+{
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    uint32_t id = ids[i];
+    const float *v = verts + 9 * (size_t)id;
+    tris[3 * (size_t)i + 0] = make_float4(v[0], v[1], v[2], __uint_as_float(id));
+    tris[3 * (size_t)i + 1] = make_float4(v[3], v[4], v[5], 0.0f);
+    tris[3 * (size_t)i + 2] = make_float4(v[6], v[7], v[8], 0.0f);
+    const float *a = alb + 3 * (size_t)id;
+    albedo[i] = make_float4(a[0], a[1], a[2], 0.0f);
+}
+
+__device__ inline int delta64(const uint32_t *keys, const uint32_t *ids, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = ((uint64_t)keys[i] << 32) | ids[i];
+    uint64_t b = ((uint64_t)keys[j] << 32) | ids[j];
+    return __clzll(a ^ b);
+}
+
+__global__ __launch_bounds__(kThreads) void k_karras(const uint32_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ ids, int n,
+                                                     BvhNode *__restrict__ nodes, uint32_t *__restrict__ parent,
+                                                     uint32_t *__restrict__ flags)
+{
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n - 1) return;
+    int dn = delta64(keys, ids, n, i, i + 1), dp = delta64(keys, ids, n, i, i - 1);
+    int d = dn > dp ? 1 : -1;
+    int dmin = d > 0 ? dp : dn;
+    int lmax = 2;
+    while (delta64(keys, ids, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta64(keys, ids, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = delta64(keys, ids, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta64(keys, ids, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int gamma = i + s * d + (d < 0 ? -1 : 0);
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    uint32_t left = (lo == gamma) ? ((uint32_t)gamma | kLeaf) : (uint32_t)gamma;
+    uint32_t right = (hi == gamma + 1) ? ((uint32_t)(gamma + 1) | kLeaf) : (uint32_t)(gamma + 1);
+    nodes[i].d = make_uint4(left, right, 0u, 0u);
+    parent[(left & kLeaf) ? (size_t)(n - 1) + (left & ~kLeaf) : left] = (uint32_t)i;
+    parent[(right & kLeaf) ? (size_t)(n - 1) + (right & ~kLeaf) : right] = (uint32_t)i;
+    flags[i] = 0u;
+    if (i == 0) parent[0] = ~0u;
+}
+
+__device__ inline void store_child_box(BvhNode *nd, bool left, const float lo[3], const float hi[3])
+{
+    if (left) {
+        nd->a = make_float4(lo[0], hi[0], lo[1], hi[1]);
+        nd->c.x = lo[2];
+        nd->c.y = hi[2];
+    } else {
+        nd->b = make_float4(lo[0], hi[0], lo[1], hi[1]);
+        nd->c.z = lo[2];
+        nd->c.w = hi[2];
+    }
+}
+
+// One thread per leaf climbs towards the root; the second thread to reach a
+// node (counted by an acq_rel atomic) merges both child boxes and continues.
+__global__ __launch_bounds__(kThreads) void k_refit(const float4 *__restrict__ tris, int n, BvhNode *nodes,
+                                                    const uint32_t *__restrict__ parent, uint32_t *flags)
+{
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    float v[9];
+    float4 t0 = tris[3 * (size_t)i], t1 = tris[3 * (size_t)i + 1], t2 = tris[3 * (size_t)i + 2];
+    v[0] = t0.x; v[1] = t0.y; v[2] = t0.z;
+    v[3] = t1.x; v[4] = t1.y; v[5] = t1.z;
+    v[6] = t2.x; v[7] = t2.y; v[8] = t2.z;
+    float lo[3], hi[3];
+    tri_box3(v, lo, hi);
+    uint32_t child = (uint32_t)i | kLeaf;
+    uint32_t p = parent[(size_t)(n - 1) + i];
+    while (p != ~0u) {
+        BvhNode *nd = nodes + p;
+        bool is_left = nd->d.x == child;
+        store_child_box(nd, is_left, lo, hi);
+        uint32_t old = __hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0u) return;
+        float4 a = nd->a, b = nd->b, c = nd->c;
+        // union(left, right) as compare-selects, left first
+        lo[0] = b.x < a.x ? b.x : a.x;
+        hi[0] = b.y > a.y ? b.y : a.y;
+        lo[1] = b.z < a.z ? b.z : a.z;
+        hi[1] = b.w > a.w ? b.w : a.w;
+        lo[2] = c.z < c.x ? c.z : c.x;
+        hi[2] = c.w > c.y ? c.w : c.y;
+        child = p;
+        p = parent[p];
+    }
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
+{
+    const int n = s.ntri;
+    const int nb = s.bound_blocks;
+    k_centroid_bounds<<<nb, kThreads, 0, st>>>(s.verts_in, n, s.bounds);
+    k_bounds_final<<<1, 64, 0, st>>>(s.bounds, nb);
+    const float *fin = s.bounds + 6 * (size_t)nb;
+    k_morton<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, n, fin, s.keys, s.ids);
+    const int sb = s.sort_blocks;
+    uint32_t *ka = s.keys, *kb = s.keys_tmp, *va = s.ids, *vb = s.ids_tmp;
+    for (int shift = 0; shift < 32; shift += 8) {
+        k_radix_hist<<<sb, kThreads, 0, st>>>(ka, n, shift, s.hist, sb);
+        k_scan_u32<<<1, 1024, 0, st>>>(s.hist, 256 * sb);
+        k_radix_scatter<<<sb, kThreads, 0, st>>>(ka, va, kb, vb, n, shift, s.hist, sb);
+        uint32_t *t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    k_reorder<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, s.albedo_in, s.ids, n, s.tris, s.albedo);
+    if (n >= 2) {
+        k_karras<<<ceil_div(n - 1, kThreads), kThreads, 0, st>>>(s.keys, s.ids, n, s.nodes, s.parent, s.flags);
+        k_refit<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.tris, n, s.nodes, s.parent, s.flags);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dof

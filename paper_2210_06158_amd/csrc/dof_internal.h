@@ -1,0 +1,138 @@
+// Internal declarations shared by the libdof translation units (not part of
+// the ABI).  Device helpers here are compiled with contraction off and
+// correctly rounded division/sqrt, so every kernel computes in plain
+// IEEE binary32 in the order written.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dof.h"
+
+namespace dof {
+
+constexpr uint32_t kLeaf = 0x80000000u;
+constexpr float kSqrt2 = 1.41421356237f;  // one pixel diagonal (3.1.1, 3.3)
+constexpr int kTile = 16;                 // neighbourhood-max tile side
+constexpr int kRingTaps = 81;             // 1 + 8 + 16 + 24 + 32 (3.1.1)
+constexpr int kMaxBlades = 16;
+constexpr int kStackLds = 32;             // traversal stack entries kept in LDS
+constexpr int kStackMax = 64;             // total depth; a 62-bit key tree never exceeds it
+constexpr int kTraceThreads = 256;
+
+// ---------------------------------------------------------------- scene
+
+struct BvhNode {      // 64 B, both children's boxes with the parent
+    float4 a;         // L.lo.x, L.hi.x, L.lo.y, L.hi.y
+    float4 b;         // R.lo.x, R.hi.x, R.lo.y, R.hi.y
+    float4 c;         // L.lo.z, L.hi.z, R.lo.z, R.hi.z
+    uint4 d;          // left, right, 0, 0
+};
+
+struct SceneShade {
+    float light_dir[3], light_rad[3], ambient[3], sky[3];
+};
+
+struct SceneDev {
+    int32_t ntri;
+    const float *verts_in;   // 9 per triangle, original order
+    const float *albedo_in;  // 3 per triangle, original order
+    float4 *tris;            // 3 per leaf, sorted order; tris[3i].w = id bits
+    float4 *albedo;          // 1 per leaf, sorted order
+    BvhNode *nodes;          // ntri - 1
+    uint32_t *parent;        // 2 ntri - 1
+    uint32_t *keys, *keys_tmp, *ids, *ids_tmp;
+    uint32_t *flags;         // ntri - 1 refit visit counters
+    uint32_t *hist;          // radix histograms
+    float *bounds;           // 6 partial-bound slots per reduce block + 8 final
+    int32_t sort_blocks;
+    int32_t bound_blocks;
+};
+
+// ---------------------------------------------------------------- frame
+
+struct Aperture {
+    int32_t blades;
+    float apothem;
+    float nx[kMaxBlades], ny[kMaxBlades];
+};
+
+struct Rings {
+    float ox[kRingTaps], oy[kRingTaps], frac[kRingTaps];
+};
+
+struct ViewConst {    // a camera with its lens-derived projection
+    float pos[3], right[3], up[3], fwd[3];
+    float tanx, tany;
+};
+
+struct FrameConst {
+    int32_t W, H, hw, hh, tw, th, T, D;
+    int32_t m, mask_mode, have_hist, motion;
+    uint32_t seed, frame;
+    float d, half_a, cock, znb, ramp;
+    float s, var_mask_w, alpha_h, var_recon_w, b_max, h_edge, lod_scale, lod_max, depth_range;
+    float r_max, l_spec;
+    int32_t lod_levels;       // highest mip level used (<= 3)
+    ViewConst cur, prev;
+    Aperture ap;
+    SceneShade shade;
+    int32_t mw[4], mh[4];     // mip level sizes
+    int64_t moff[4];          // mip level offsets in float4 units
+};
+
+// Byte offsets of every plane in a frame's scratch buffer.
+struct ScratchLayout {
+    size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx;
+    size_t chunk_cnt, chunk_off, counters;
+    size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
+    size_t resolve, temporal, var_blur, rtmed, mips, recon;
+    size_t spill;
+    size_t total;
+    int64_t nchunks;
+    int64_t spill_threads;
+};
+
+constexpr int kChunk = 1024;   // pixels per compaction chunk (256 threads x 4)
+
+// counters[] slots in scratch
+enum : int { kCntMasked = 0, kCntRays = 1, kCntWork = 2, kCntSpill = 3 };
+
+// ---------------------------------------------------------------- helpers
+
+__host__ __device__ inline float fmin_cs(float a, float b) { return b < a ? b : a; }
+__host__ __device__ inline float fmax_cs(float a, float b) { return b > a ? b : a; }
+__host__ __device__ inline float sat(float x) { return x > 0.0f ? (x < 1.0f ? x : 1.0f) : 0.0f; }
+__host__ __device__ inline float lerp1(float a, float b, float t) { return a + (b - a) * t; }
+__host__ __device__ inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+__host__ __device__ inline float clampf(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
+__device__ inline float luma709(float r, float g, float b) { return (0.2126f * r + 0.7152f * g) + 0.0722f * b; }
+
+// Full-res CoC diameter in pixels: cock * |1 - d / z| (eq. 6 solved for z).
+__device__ inline float coc_px(float cock, float d, float z) { return cock * fabsf(1.0f - d / z); }
+
+// ---------------------------------------------------------------- launchers
+
+// bvh.hip
+hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
+
+// trace.hip
+hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
+                        int blocks, hipStream_t st);
+hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
+                          void *normal, int nfmt, hipStream_t st);
+hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,
+                             float *t, hipStream_t st);
+
+// frame.hip
+// ev (nullable): DOF_NUM_STAGES + 1 events; pre records ev[0..7], post ev[8..13]
+hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+                            const dof_gbuffer &gb, const void *hist_in, uint8_t *mask, hipEvent_t *ev,
+                            hipStream_t st);
+hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+                             const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
+                             const dof_frame_out &out, hipEvent_t *ev, hipStream_t st);
+hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
+
+}  // namespace dof

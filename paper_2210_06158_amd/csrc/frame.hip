@@ -1,0 +1,938 @@
+// Per-frame kernels of the hybrid depth-of-field pass, except the ray
+// traversal (trace.hip).  Stage names follow section 3 of the paper:
+//   A1  CoC + half-res reduce (+ per-tile max CoC)          3.1, 3.3 eq. 6
+//   A2  tile-neighbourhood max CoC                          3.1.1
+//   A3  9-tap bilateral prefilter                           3.1.1
+//   A4  81-tap near/far gather, eq. (1)                     3.1.2
+//   A5  3x3 median postfilter                               3.1.3
+//   A6  ray mask, eqs. (2)-(4)                              3.2.1
+//   A7  ordered compaction of masked pixels into a queue    (GPU dispatch)
+//   A11 near/far resolve and hit ratio                      3.2.2
+//   A12 temporal accumulation, reprojection, variance       3.2.3
+//   A13 median, mip chain, spatial reconstruction, eq. (5)(8)  3.2.4
+//   A14 composite, eqs. (6)(7)                              3.3
+// Every floating-point expression is evaluated in the order written, in
+// binary32 without contraction, so that index decisions (nearest texels,
+// ray counts) are reproducible.
+#include "dof_internal.h"
+
+namespace dof {
+namespace {
+
+constexpr int kBX = 64, kBY = 4;   // pixel-kernel block: one wave per row
+
+__device__ inline float4 ld_rgba(const void *p, int fmt, size_t i)
+{
+    if (fmt == DOF_RGBA32F) return reinterpret_cast<const float4 *>(p)[i];
+    const __half *h = reinterpret_cast<const __half *>(p) + 4 * i;
+    return make_float4(__half2float(h[0]), __half2float(h[1]), __half2float(h[2]), __half2float(h[3]));
+}
+
+__device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
+{
+    if (fmt == DOF_RGBA32F) {
+        reinterpret_cast<float4 *>(p)[i] = v;
+    } else {
+        __half2 *h = reinterpret_cast<__half2 *>(p) + 2 * i;
+        h[0] = __halves2half2(__float2half(v.x), __float2half(v.y));
+        h[1] = __halves2half2(__float2half(v.z), __float2half(v.w));
+    }
+}
+
+__device__ inline float4 bilinear4(const float4 *img, int w, int h, float x, float y)
+{
+    float x0f = floorf(x), y0f = floorf(y);
+    float fx = x - x0f, fy = y - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    int x1 = clampi(x0 + 1, 0, w - 1), y1 = clampi(y0 + 1, 0, h - 1);
+    x0 = clampi(x0, 0, w - 1);
+    y0 = clampi(y0, 0, h - 1);
+    float4 a = img[(size_t)y0 * w + x0], b = img[(size_t)y0 * w + x1];
+    float4 c = img[(size_t)y1 * w + x0], d = img[(size_t)y1 * w + x1];
+    float4 top, bot, o;
+    top.x = a.x + (b.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
+    top.y = a.y + (b.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
+    top.z = a.z + (b.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
+    top.w = a.w + (b.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
+    return o;
+}
+
+__device__ inline int nearest_idx(float s, int n) { return clampi((int)floorf(s + 0.5f), 0, n - 1); }
+
+// Median of 9 by a max-min exchange network (19 compare-exchanges).
+__device__ inline float median9(float p0, float p1, float p2, float p3, float p4, float p5, float p6, float p7,
+                                float p8)
+{
+#define DOF_CX(a, b)                  \
+    {                                 \
+        float lo_ = fmin_cs(a, b);    \
+        float hi_ = fmax_cs(a, b);    \
+        a = lo_;                      \
+        b = hi_;                      \
+    }
+    DOF_CX(p1, p2); DOF_CX(p4, p5); DOF_CX(p7, p8);
+    DOF_CX(p0, p1); DOF_CX(p3, p4); DOF_CX(p6, p7);
+    DOF_CX(p1, p2); DOF_CX(p4, p5); DOF_CX(p7, p8);
+    DOF_CX(p0, p3); DOF_CX(p5, p8); DOF_CX(p4, p7);
+    DOF_CX(p3, p6); DOF_CX(p1, p4); DOF_CX(p2, p5);
+    DOF_CX(p4, p7); DOF_CX(p4, p2); DOF_CX(p6, p4);
+    DOF_CX(p4, p2);
+#undef DOF_CX
+    return p4;
+}
+
+// View direction through the centre of pixel (x, y) of a w x h grid.
+__device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h, float fv[3])
+{
+    float u = ((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) * v.tanx;
+    float vv = (1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) * v.tany;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
+}
+
+// Half-res texel of the previous view that sees p (a direction when is_dir).
+__device__ inline int reproject(const ViewConst &pv, int hw, int hh, const float p[3], bool is_dir)
+{
+    float e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e[a] = is_dir ? p[a] : p[a] - pv.pos[a];
+    float ex = (e[0] * pv.right[0] + e[1] * pv.right[1]) + e[2] * pv.right[2];
+    float ey = (e[0] * pv.up[0] + e[1] * pv.up[1]) + e[2] * pv.up[2];
+    float ez = (e[0] * pv.fwd[0] + e[1] * pv.fwd[1]) + e[2] * pv.fwd[2];
+    if (!(ez > 0.0f)) return -1;
+    float pu = (ex / ez) / pv.tanx;
+    float pvv = (ey / ez) / pv.tany;
+    float px = ((pu + 1.0f) * 0.5f) * (float)hw - 0.5f;
+    float py = ((1.0f - pvv) * 0.5f) * (float)hh - 0.5f;
+    float sx = px + 0.5f, sy = py + 0.5f;
+    if (!(sx >= 0.0f && sx < (float)hw && sy >= 0.0f && sy < (float)hh)) return -1;
+    return (int)floorf(sy) * hw + (int)floorf(sx);
+}
+
+// History planes: A (near rgb, h) | B (far rgb, age) | C (cN, cF, mu1, mu2) | D var
+struct Hist {
+    const float4 *A, *B, *C;
+    const float *D;
+};
+struct HistW {
+    float4 *A, *B, *C;
+    float *D;
+};
+__device__ inline Hist hist_view(const void *h, size_t np)
+{
+    const float4 *p = reinterpret_cast<const float4 *>(h);
+    return Hist{p, p + np, p + 2 * np, reinterpret_cast<const float *>(p + 3 * np)};
+}
+__device__ inline HistW hist_wview(void *h, size_t np)
+{
+    float4 *p = reinterpret_cast<float4 *>(h);
+    return HistW{p, p + np, p + 2 * np, reinterpret_cast<float *>(p + 3 * np)};
+}
+
+struct Planes {
+    float4 *colr, *zn, *pre, *gather, *ppmed;
+    float *zh, *tile_max, *tile_dil;
+    int32_t *prev_idx;
+    uint2 *chunk_cnt, *chunk_off;
+    uint32_t *counters, *queue, *ray_base, *ray_pix;
+    const int32_t *ray_hit;
+    const float4 *ray_col, *ray_pos;
+    float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
+    float *var_blur;
+};
+
+Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
+{
+    size_t np = (size_t)fc.hw * fc.hh;
+    Planes p;
+    p.colr = reinterpret_cast<float4 *>(s + L.colr);
+    p.zn = reinterpret_cast<float4 *>(s + L.zn);
+    p.zh = reinterpret_cast<float *>(s + L.zh);
+    p.tile_max = reinterpret_cast<float *>(s + L.tile_max);
+    p.tile_dil = reinterpret_cast<float *>(s + L.tile_dil);
+    p.pre = reinterpret_cast<float4 *>(s + L.pre);
+    p.gather = reinterpret_cast<float4 *>(s + L.gather);
+    p.ppmed = reinterpret_cast<float4 *>(s + L.ppmed);
+    p.prev_idx = reinterpret_cast<int32_t *>(s + L.prev_idx);
+    p.chunk_cnt = reinterpret_cast<uint2 *>(s + L.chunk_cnt);
+    p.chunk_off = reinterpret_cast<uint2 *>(s + L.chunk_off);
+    p.counters = reinterpret_cast<uint32_t *>(s + L.counters);
+    p.queue = reinterpret_cast<uint32_t *>(s + L.queue);
+    p.ray_base = reinterpret_cast<uint32_t *>(s + L.ray_base);
+    p.ray_pix = reinterpret_cast<uint32_t *>(s + L.ray_pix);
+    p.ray_hit = reinterpret_cast<const int32_t *>(s + L.ray_hit);
+    p.ray_col = reinterpret_cast<const float4 *>(s + L.ray_col);
+    p.ray_pos = reinterpret_cast<const float4 *>(s + L.ray_pos);
+    float4 *res = reinterpret_cast<float4 *>(s + L.resolve);
+    p.R0 = res; p.R1 = res + np; p.R2 = res + 2 * np; p.R3 = res + 3 * np;
+    float4 *tmp = reinterpret_cast<float4 *>(s + L.temporal);
+    p.T0 = tmp; p.T1 = tmp + np;
+    p.var_blur = reinterpret_cast<float *>(s + L.var_blur);
+    p.rtmed = reinterpret_cast<float4 *>(s + L.rtmed);
+    p.mips = reinterpret_cast<float4 *>(s + L.mips);
+    p.recon = reinterpret_cast<float4 *>(s + L.recon);
+    return p;
+}
+
+// ---------------------------------------------------------------- A1
+
+__global__ __launch_bounds__(256) void k_reduce(FrameConst fc, dof_gbuffer gb, Planes P)
+{
+    const int x = blockIdx.x * kTile + threadIdx.x, y = blockIdx.y * kTile + threadIdx.y;
+    float ar = 0.0f;
+    if (x < fc.hw && y < fc.hh) {
+        const size_t W = (size_t)fc.W;
+        size_t t[4] = {(size_t)(2 * y) * W + 2 * x, (size_t)(2 * y) * W + 2 * x + 1,
+                       (size_t)(2 * y + 1) * W + 2 * x, (size_t)(2 * y + 1) * W + 2 * x + 1};
+        float zz[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zz[k] = gb.depth[t[k]];
+        int sel = 0;
+        float z = zz[0];
+        if (zz[1] < z) { z = zz[1]; sel = 1; }
+        if (zz[2] < z) { z = zz[2]; sel = 2; }
+        if (zz[3] < z) { z = zz[3]; sel = 3; }
+        float4 c0 = ld_rgba(gb.colour, gb.colour_format, t[0]), c1 = ld_rgba(gb.colour, gb.colour_format, t[1]);
+        float4 c2 = ld_rgba(gb.colour, gb.colour_format, t[2]), c3 = ld_rgba(gb.colour, gb.colour_format, t[3]);
+        size_t ts = sel == 0 ? t[0] : (sel == 1 ? t[1] : (sel == 2 ? t[2] : t[3]));
+        float4 nn = ld_rgba(gb.normal, gb.normal_format, ts);
+        float r = coc_px(fc.cock, fc.d, z) * 0.25f;
+        r = fmin_cs(r, fc.r_max);
+        r = z < fc.d ? -r : r;
+        size_t i = (size_t)y * fc.hw + x;
+        P.colr[i] = make_float4(((c0.x + c1.x) + (c2.x + c3.x)) * 0.25f, ((c0.y + c1.y) + (c2.y + c3.y)) * 0.25f,
+                                ((c0.z + c1.z) + (c2.z + c3.z)) * 0.25f, r);
+        P.zn[i] = make_float4(z, nn.x, nn.y, nn.z);
+        P.zh[i] = z;
+        ar = fabsf(r);
+    }
+    // per-tile maximum |r| (tile == block)
+    __shared__ float red[4];
+    const int tid = threadIdx.y * kTile + threadIdx.x;
+    for (int o = 32; o >= 1; o >>= 1) ar = fmax_cs(ar, __shfl_xor(ar, o));
+    if ((tid & 63) == 0) red[tid >> 6] = ar;
+    __syncthreads();
+    if (tid == 0) {
+        float m = 0.0f;
+        for (int k = 0; k < 4; ++k) m = fmax_cs(m, red[k]);
+        P.tile_max[(size_t)blockIdx.y * fc.tw + blockIdx.x] = m;
+    }
+}
+
+// ---------------------------------------------------------------- A2
+
+__global__ void k_dilate(FrameConst fc, Planes P)
+{
+    const int tx = blockIdx.x * blockDim.x + threadIdx.x, ty = blockIdx.y * blockDim.y + threadIdx.y;
+    if (tx >= fc.tw || ty >= fc.th) return;
+    float m = 0.0f;
+    for (int j = ty - fc.D; j <= ty + fc.D; ++j)
+        for (int i = tx - fc.D; i <= tx + fc.D; ++i)
+            if (i >= 0 && j >= 0 && i < fc.tw && j < fc.th) m = fmax_cs(m, P.tile_max[(size_t)j * fc.tw + i]);
+    P.tile_dil[(size_t)ty * fc.tw + tx] = m;
+}
+
+// ---------------------------------------------------------------- A3
+
+__global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    if (x >= fc.hw || y >= fc.hh) return;
+    const size_t i = (size_t)y * fc.hw + x;
+    float Rn = P.tile_dil[(size_t)(y / fc.T) * fc.tw + x / fc.T];
+    float dpre = Rn * 0.25f;
+    if (dpre < kSqrt2) dpre = kSqrt2;
+    float sp = dpre * 0.5f;
+    float rc = P.colr[i].w;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f, sw = 0.0f;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            float sx = (float)x + (float)dx * sp, sy = (float)y + (float)dy * sp;
+            float4 v = bilinear4(P.colr, fc.hw, fc.hh, sx, sy);
+            float w = 1.0f / (1.0f + fabsf(v.w - rc));
+            ax = ax + w * v.x;
+            ay = ay + w * v.y;
+            az = az + w * v.z;
+            sw = sw + w;
+        }
+    P.pre[i] = make_float4(ax / sw, ay / sw, az / sw, rc);
+}
+
+// ---------------------------------------------------------------- A4
+
+__global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings, Planes P)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    if (x >= fc.hw || y >= fc.hh) return;
+    const size_t i = (size_t)y * fc.hw + x;
+    const float Rn = P.tile_dil[(size_t)(y / fc.T) * fc.tw + x / fc.T];
+    const float4 c0 = P.pre[i];
+    const float rc = c0.w, zc = P.zh[i], arc = fabsf(rc);
+    float vf0 = 0.0f, vf1 = 0.0f, vf2 = 0.0f, vb0 = 0.0f, vb1 = 0.0f, vb2 = 0.0f, sw = 0.0f, ss = 0.0f;
+    for (int k = 0; k < kRingTaps; ++k) {
+        float dist = Rn * rings.frac[k];
+        float sx = (float)x + rings.ox[k] * Rn, sy = (float)y + rings.oy[k] * Rn;
+        int ix = nearest_idx(sx, fc.hw), iy = nearest_idx(sy, fc.hh);
+        size_t j = (size_t)iy * fc.hw + ix;
+        float4 ci = P.pre[j];
+        float ari = fabsf(ci.w);
+        float mr = fmax_cs(ari, 0.5f);
+        float alpha = 1.0f / (mr * mr);
+        float dfg = ari > dist ? 1.0f : 0.0f;
+        float dbg = fmin_cs(ari, arc) > dist ? 1.0f : 0.0f;
+        float wbg = sat((P.zh[j] - zc) / fc.depth_range);
+        float wf = alpha * ((1.0f - wbg) * dfg);
+        float wb = alpha * (wbg * dbg);
+        vf0 = vf0 + wf * ci.x; vb0 = vb0 + wb * ci.x;
+        vf1 = vf1 + wf * ci.y; vb1 = vb1 + wb * ci.y;
+        vf2 = vf2 + wf * ci.z; vb2 = vb2 + wb * ci.z;
+        float wi = wf + wb;
+        sw = sw + wi;
+        if (luma709(ci.x, ci.y, ci.z) > fc.l_spec) ss = ss + wi;
+    }
+    float4 o;
+    if (sw > 0.0f) o = make_float4((vf0 + vb0) / sw, (vf1 + vb1) / sw, (vf2 + vb2) / sw, ss / sw);
+    else o = make_float4(c0.x, c0.y, c0.z, 0.0f);
+    P.gather[i] = o;
+}
+
+// ---------------------------------------------------------------- A5
+
+__global__ __launch_bounds__(kBX *kBY) void k_median_pp(FrameConst fc, Planes P)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    if (x >= fc.hw || y >= fc.hh) return;
+    float4 v[9];
+    int n = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx)
+            v[n++] = P.gather[(size_t)clampi(y + dy, 0, fc.hh - 1) * fc.hw + clampi(x + dx, 0, fc.hw - 1)];
+    const size_t i = (size_t)y * fc.hw + x;
+    P.ppmed[i] = make_float4(median9(v[0].x, v[1].x, v[2].x, v[3].x, v[4].x, v[5].x, v[6].x, v[7].x, v[8].x),
+                             median9(v[0].y, v[1].y, v[2].y, v[3].y, v[4].y, v[5].y, v[6].y, v[7].y, v[8].y),
+                             median9(v[0].z, v[1].z, v[2].z, v[3].z, v[4].z, v[5].z, v[6].z, v[7].z, v[8].z),
+                             v[4].w);
+}
+
+// ---------------------------------------------------------------- A6
+
+constexpr int kMaskHalo = 4, kMaskL = kTile + 2 * kMaskHalo;   // 24 x 24 LDS cells
+
+__global__ __launch_bounds__(256) void k_mask(FrameConst fc, Planes P, const void *hist_in, uint8_t *mask)
+{
+    __shared__ float4 F[kMaskL][kMaskL];
+    __shared__ float4 Hh[kMaskL][kMaskL];
+    __shared__ float4 B[kMaskL][kMaskL];
+    const int hw = fc.hw, hh = fc.hh;
+    const int ox = blockIdx.x * kTile - kMaskHalo, oy = blockIdx.y * kTile - kMaskHalo;
+    const int tid = threadIdx.y * kTile + threadIdx.x;
+    // Cells hold values at clamped coordinates; a coordinate g maps to cell g - origin.
+    for (int c = tid; c < kMaskL * kMaskL; c += 256) {
+        int lx = c % kMaskL, ly = c / kMaskL;
+        int gx = clampi(ox + lx, 0, hw - 1), gy = clampi(oy + ly, 0, hh - 1);
+        float4 v = P.zn[(size_t)gy * hw + gx];
+        F[ly][lx] = make_float4(fc.d / v.x, v.y, v.z, v.w);
+    }
+    __syncthreads();
+    const float g5[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+    for (int c = tid; c < kMaskL * kMaskL; c += 256) {
+        int lx = c % kMaskL, ly = c / kMaskL;
+        if (lx < 2 || lx >= kMaskL - 2) continue;
+        int cx = clampi(ox + lx, 0, hw - 1);
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int j = 0; j < 5; ++j) {
+            float4 v = F[ly][clampi(cx + j - 2, 0, hw - 1) - ox];
+            acc.x = acc.x + g5[j] * v.x;
+            acc.y = acc.y + g5[j] * v.y;
+            acc.z = acc.z + g5[j] * v.z;
+            acc.w = acc.w + g5[j] * v.w;
+        }
+        Hh[ly][lx] = acc;
+    }
+    __syncthreads();
+    for (int c = tid; c < kMaskL * kMaskL; c += 256) {
+        int lx = c % kMaskL, ly = c / kMaskL;
+        if (lx < 2 || lx >= kMaskL - 2 || ly < 2 || ly >= kMaskL - 2) continue;
+        int cy = clampi(oy + ly, 0, hh - 1);
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int i = 0; i < 5; ++i) {
+            float4 v = Hh[clampi(cy + i - 2, 0, hh - 1) - oy][lx];
+            acc.x = acc.x + g5[i] * v.x;
+            acc.y = acc.y + g5[i] * v.y;
+            acc.z = acc.z + g5[i] * v.z;
+            acc.w = acc.w + g5[i] * v.w;
+        }
+        B[ly][lx] = acc;
+    }
+    __syncthreads();
+    const int x = blockIdx.x * kTile + threadIdx.x, y = blockIdx.y * kTile + threadIdx.y;
+    if (x >= hw || y >= hh) return;
+    const float sm[5] = {1.0f, 4.0f, 6.0f, 4.0f, 1.0f};
+    const float dv[5] = {-1.0f, -2.0f, 0.0f, 2.0f, 1.0f};
+    float gx[4], gy[4];
+    {
+        float axv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, ayv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int r = 0; r < 5; ++r) {
+            int ly = clampi(y + r - 2, 0, hh - 1) - oy;
+            float hx[4] = {0.0f, 0.0f, 0.0f, 0.0f}, hs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int k = 0; k < 5; ++k) {
+                float4 v = B[ly][clampi(x + k - 2, 0, hw - 1) - ox];
+                float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    hx[c] = hx[c] + dv[k] * vv[c];
+                    hs[c] = hs[c] + sm[k] * vv[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                axv[c] = axv[c] + sm[r] * hx[c];
+                ayv[c] = ayv[c] + dv[r] * hs[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            gx[c] = axv[c] * 0.0078125f;
+            gy[c] = ayv[c] * 0.0078125f;
+        }
+    }
+    float dd = sqrtf(gx[0] * gx[0] + gy[0] * gy[0]);
+    float an = 0.0f;
+    for (int c = 1; c < 4; ++c) an = an + (gx[c] * gx[c] + gy[c] * gy[c]);
+    float dn = sqrtf(an);
+    float xx = (dd + dn) * fc.s;
+    float xn = sat(1.0f - 1.0f / (xx + 1.0f));
+    const size_t i = (size_t)y * hw + x;
+    const float z = P.zh[i];
+    int pi = -1;
+    const size_t np = (size_t)hw * hh;
+    if (fc.have_hist) {
+        float fv[3], Pw[3];
+        pixel_dir(fc.cur, x, y, hw, hh, fv);
+        bool isdir = !(z < INFINITY);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Pw[a] = isdir ? fv[a] : fc.cur.pos[a] + z * fv[a];
+        pi = reproject(fc.prev, hw, hh, Pw, isdir);
+        if (pi >= 0 && !(hist_view(hist_in, np).B[pi].w > 0.0f)) pi = -1;
+    }
+    P.prev_idx[i] = pi;
+    float var_prev = pi >= 0 ? hist_view(hist_in, np).D[pi] : 0.0f;
+    float xf = sat(xn + var_prev * fc.var_mask_w) * (float)fc.m;
+    int cnt = (int)floorf(xf + 0.5f);
+    int near_oof = (z < fc.d) && (coc_px(fc.cock, fc.d, z) > kSqrt2);
+    int n = cnt > near_oof ? cnt : near_oof;
+    if (n > fc.m) n = fc.m;
+    if (fc.mask_mode == DOF_MASK_FIXED) n = n > 0 ? fc.m : 0;
+    if (fc.mask_mode == DOF_MASK_ALL) n = fc.m;
+    mask[i] = (uint8_t)n;
+}
+
+// ---------------------------------------------------------------- A7
+// Chunks of 1024 pixels in row-major order; ranks from wave ballots (masked
+// pixels) and wave prefix sums (rays), so the queue is ascending.
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    size_t base = (size_t)blockIdx.x * kChunk;
+    uint32_t cp = 0, cr = 0;
+    for (int r = 0; r < kChunk / 256; ++r) {
+        size_t i = base + (size_t)r * 256 + tid;
+        uint32_t n = i < (size_t)np ? mask[i] : 0u;
+        cp += n > 0u;
+        cr += n;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        cp += __shfl_xor(cp, o);
+        cr += __shfl_xor(cr, o);
+    }
+    __shared__ uint32_t sp[4], sr[4];
+    if (lane == 0) { sp[w] = cp; sr[w] = cr; }
+    __syncthreads();
+    if (tid == 0) P.chunk_cnt[blockIdx.x] = make_uint2(sp[0] + sp[1] + sp[2] + sp[3], sr[0] + sr[1] + sr[2] + sr[3]);
+}
+
+__global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P, dof_stats *stats)
+{
+    __shared__ uint32_t pp[1024], pr[1024];
+    const int per = (int)((nchunks + 1023) / 1024);
+    const int b = threadIdx.x * per, e = (int)min((int64_t)(b + per), nchunks);
+    uint32_t sp = 0, sr = 0;
+    for (int i = b; i < e; ++i) {
+        uint2 c = P.chunk_cnt[i];
+        sp += c.x;
+        sr += c.y;
+    }
+    pp[threadIdx.x] = sp;
+    pr[threadIdx.x] = sr;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t a = threadIdx.x >= (unsigned)off ? pp[threadIdx.x - off] : 0u;
+        uint32_t c = threadIdx.x >= (unsigned)off ? pr[threadIdx.x - off] : 0u;
+        __syncthreads();
+        pp[threadIdx.x] += a;
+        pr[threadIdx.x] += c;
+        __syncthreads();
+    }
+    uint32_t rp = pp[threadIdx.x] - sp, rr = pr[threadIdx.x] - sr;
+    for (int i = b; i < e; ++i) {
+        uint2 c = P.chunk_cnt[i];
+        P.chunk_off[i] = make_uint2(rp, rr);
+        rp += c.x;
+        rr += c.y;
+    }
+    if (threadIdx.x == 1023) {
+        P.counters[kCntMasked] = pp[1023];
+        P.counters[kCntRays] = pr[1023];
+        P.counters[kCntWork] = 0u;
+        P.counters[kCntSpill] = 0u;
+        if (stats) {
+            stats->masked_px = pp[1023];
+            stats->rays = pr[1023];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ uint32_t wp[4], wr[4];
+    __shared__ uint32_t runp, runr;
+    if (tid == 0) {
+        uint2 o = P.chunk_off[blockIdx.x];
+        runp = o.x;
+        runr = o.y;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    size_t base = (size_t)blockIdx.x * kChunk;
+    for (int r = 0; r < kChunk / 256; ++r) {
+        size_t i = base + (size_t)r * 256 + tid;
+        uint32_t n = i < (size_t)np ? mask[i] : 0u;
+        uint64_t bal = __ballot(n > 0u);
+        uint32_t rank = (uint32_t)__popcll(bal & lt);
+        uint32_t incl = wave_incl_scan(n, lane);
+        if (lane == 63) { wp[w] = (uint32_t)__popcll(bal); wr[w] = incl; }
+        __syncthreads();
+        uint32_t op = runp, orr = runr;
+        for (int k = 0; k < w; ++k) { op += wp[k]; orr += wr[k]; }
+        if (n > 0u) {
+            uint32_t pos = op + rank;
+            uint32_t rb = orr + incl - n;
+            P.queue[pos] = (uint32_t)i;
+            P.ray_base[pos] = rb;
+            for (uint32_t k = 0; k < n; ++k) P.ray_pix[rb + k] = pos;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            runp += wp[0] + wp[1] + wp[2] + wp[3];
+            runr += wr[0] + wr[1] + wr[2] + wr[3];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- A11
+
+__global__ __launch_bounds__(256) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= P.counters[kCntMasked]) return;
+    const uint32_t q = P.queue[j];
+    const int n = mask[q];
+    const uint32_t base = P.ray_base[j];
+    float N = 0.0f, sn0 = 0.0f, sn1 = 0.0f, sn2 = 0.0f, sf0 = 0.0f, sf1 = 0.0f, sf2 = 0.0f;
+    float scn = 0.0f, scf = 0.0f, fp0 = 0.0f, fp1 = 0.0f, fp2 = 0.0f, fw = 0.0f;
+    for (int k = 0; k < n; ++k) {
+        const uint32_t r = base + k;
+        float4 c = P.ray_col[r];
+        bool hit = P.ray_hit[r] >= 0;
+        float w = hit ? sat(0.5f + (fc.d - c.w) / fc.ramp) : 0.0f;
+        float om = 1.0f - w;
+        float cz = coc_px(fc.cock, fc.d, c.w);
+        N = N + w;
+        sn0 = sn0 + w * c.x; sf0 = sf0 + om * c.x;
+        sn1 = sn1 + w * c.y; sf1 = sf1 + om * c.y;
+        sn2 = sn2 + w * c.z; sf2 = sf2 + om * c.z;
+        scn = scn + w * cz;
+        scf = scf + om * cz;
+        if (hit) {
+            float4 p = P.ray_pos[r];
+            fp0 = fp0 + om * p.x;
+            fp1 = fp1 + om * p.y;
+            fp2 = fp2 + om * p.z;
+            fw = fw + om;
+        }
+    }
+    const float nf = (float)n - N;
+    const bool hn = N > 0.0f, hf = nf > 0.0f, hp = fw > 0.0f;
+    P.R0[q] = make_float4(hn ? sn0 / N : 0.0f, hn ? sn1 / N : 0.0f, hn ? sn2 / N : 0.0f, N);
+    P.R1[q] = make_float4(hf ? sf0 / nf : 0.0f, hf ? sf1 / nf : 0.0f, hf ? sf2 / nf : 0.0f, N / (float)n);
+    P.R2[q] = make_float4(hn ? scn / N : 0.0f, hf ? scf / nf : 0.0f, (float)n, 0.0f);
+    P.R3[q] = make_float4(hp ? fp0 / fw : 0.0f, hp ? fp1 / fw : 0.0f, hp ? fp2 / fw : 0.0f, hp ? 1.0f : 0.0f);
+}
+
+// ---------------------------------------------------------------- A12
+
+__global__ __launch_bounds__(kBX *kBY) void k_temporal(FrameConst fc, Planes P, const uint8_t *__restrict__ mask,
+                                                       const void *hist_in, void *hist_out)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int hw = fc.hw, hh = fc.hh;
+    if (x >= hw || y >= hh) return;
+    const size_t np = (size_t)hw * hh, i = (size_t)y * hw + x;
+    HistW ho = hist_wview(hist_out, np);
+    const int n = mask[i];
+    const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (n == 0) {
+        P.T0[i] = z4; P.T1[i] = z4;
+        ho.A[i] = z4; ho.B[i] = z4; ho.C[i] = z4;
+        return;
+    }
+    const float4 r0 = P.R0[i], r1 = P.R1[i], r2 = P.R2[i], r3 = P.R3[i];
+    const float N = r0.w, hcur = r1.w, nf = (float)n - N;
+    const int pn = P.prev_idx[i];
+    const bool vn = pn >= 0;
+    float fpos[3];
+    bool fvalid = r3.w > 0.0f;
+    if (fvalid) {
+        fpos[0] = r3.x; fpos[1] = r3.y; fpos[2] = r3.z;
+    } else {
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        int cnt = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int xx = x + dx, yy = y + dy;
+                if ((dx == 0 && dy == 0) || xx < 0 || yy < 0 || xx >= hw || yy >= hh) continue;
+                size_t k = (size_t)yy * hw + xx;
+                if (mask[k]) {
+                    float4 q3 = P.R3[k];
+                    if (q3.w > 0.0f) {
+                        a0 = a0 + q3.x; a1 = a1 + q3.y; a2 = a2 + q3.z;
+                        ++cnt;
+                    }
+                }
+            }
+        if (cnt > 0) {
+            fpos[0] = a0 / (float)cnt; fpos[1] = a1 / (float)cnt; fpos[2] = a2 / (float)cnt;
+            fvalid = true;
+        }
+    }
+    Hist hi = hist_view(hist_in, np);
+    int pf = -1;
+    if (fc.have_hist && fvalid) {
+        pf = reproject(fc.prev, hw, hh, fpos, false);
+        if (pf >= 0 && !(hi.B[pf].w > 0.0f)) pf = -1;
+    }
+    const bool vf = pf >= 0;
+    const float ah = fc.alpha_h;
+    float4 hNa = vn ? hi.A[pn] : z4, hNb = vn ? hi.B[pn] : z4, hNc = vn ? hi.C[pn] : z4;
+    float4 hFb = vf ? hi.B[pf] : z4, hFc = vf ? hi.C[pf] : z4;
+    const float cur_n[3] = {r0.x, r0.y, r0.z}, cur_f[3] = {r1.x, r1.y, r1.z};
+    const float hn_[3] = {hNa.x, hNa.y, hNa.z}, hf_[3] = {hFb.x, hFb.y, hFb.z};
+    float accN[3], accF[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        accN[c] = N > 0.0f ? (vn ? lerp1(cur_n[c], hn_[c], ah) : cur_n[c]) : (vn ? hn_[c] : 0.0f);
+        accF[c] = nf > 0.0f ? (vf ? lerp1(cur_f[c], hf_[c], ah) : cur_f[c]) : (vf ? hf_[c] : 0.0f);
+    }
+    float accCN = N > 0.0f ? (vn ? lerp1(r2.x, hNc.x, ah) : r2.x) : (vn ? hNc.x : 0.0f);
+    float accCF = nf > 0.0f ? (vf ? lerp1(r2.y, hFc.y, ah) : r2.y) : (vf ? hFc.y : 0.0f);
+    float accH = vn ? lerp1(hcur, hNa.w, ah) : hcur;
+    float huse = fc.motion ? hcur : accH;
+    float crt[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) crt[c] = lerp1(accF[c], accN[c], huse);
+    float ct = lerp1(accCF, accCN, huse);
+    float l = luma709(crt[0], crt[1], crt[2]);
+    float mu1 = vn ? lerp1(l, hNc.z, ah) : l;
+    float mu2 = vn ? lerp1(l * l, hNc.w, ah) : l * l;
+    float v = mu2 - mu1 * mu1;
+    v = v > 0.0f ? v : 0.0f;
+    float age = vn ? hNb.w + 1.0f : 1.0f;
+    P.T0[i] = make_float4(crt[0], crt[1], crt[2], 1.0f);
+    P.T1[i] = make_float4(ct, huse, v, 0.0f);
+    ho.A[i] = make_float4(accN[0], accN[1], accN[2], accH);
+    ho.B[i] = make_float4(accF[0], accF[1], accF[2], age);
+    ho.C[i] = make_float4(accCN, accCF, mu1, mu2);
+}
+
+// ---------------------------------------------------------------- A12 blur + A13 median, mips
+// One wave per 8 x 8 tile: variance blur (3x3 binomial), 3x3 median of the
+// ray-traced colour (invalid neighbours replaced by the centre), level 0 of
+// the validity-weighted mip chain, then levels 1..3 of the tile from LDS.
+
+__global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P, void *hist_out)
+{
+    const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;
+    const int x = blockIdx.x * 8 + tx, y = blockIdx.y * 8 + ty;
+    const int hw = fc.hw, hh = fc.hh;
+    const size_t np = (size_t)hw * hh;
+    __shared__ float4 m0[8][8];
+    __shared__ float4 m1[4][4];
+    __shared__ float4 m2[2][2];
+    if (x < hw && y < hh) {
+        const size_t i = (size_t)y * hw + x;
+        const float g3[3] = {0.25f, 0.5f, 0.25f};
+        float acc = 0.0f;
+        for (int r = 0; r < 3; ++r) {
+            size_t row = (size_t)clampi(y + r - 1, 0, hh - 1) * hw;
+            float hs = 0.0f;
+            for (int k = 0; k < 3; ++k) hs = hs + g3[k] * P.T1[row + clampi(x + k - 1, 0, hw - 1)].z;
+            acc = acc + g3[r] * hs;
+        }
+        P.var_blur[i] = acc;
+        hist_wview(hist_out, np).D[i] = acc;
+        float4 c = P.T0[i];
+        float4 med = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (c.w > 0.0f) {
+            float4 v[9];
+            int n = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    float4 t = P.T0[(size_t)clampi(y + dy, 0, hh - 1) * hw + clampi(x + dx, 0, hw - 1)];
+                    v[n++] = t.w > 0.0f ? t : c;
+                }
+            med = make_float4(median9(v[0].x, v[1].x, v[2].x, v[3].x, v[4].x, v[5].x, v[6].x, v[7].x, v[8].x),
+                              median9(v[0].y, v[1].y, v[2].y, v[3].y, v[4].y, v[5].y, v[6].y, v[7].y, v[8].y),
+                              median9(v[0].z, v[1].z, v[2].z, v[3].z, v[4].z, v[5].z, v[6].z, v[7].z, v[8].z),
+                              1.0f);
+        }
+        P.rtmed[i] = med;
+        float4 pm = make_float4(med.x * med.w, med.y * med.w, med.z * med.w, med.w);
+        P.mips[fc.moff[0] + i] = pm;
+        m0[ty][tx] = pm;
+    }
+    __syncthreads();
+    // level 1 (4 x 4 of this tile)
+    if (threadIdx.x < 16) {
+        const int lx = threadIdx.x & 3, ly = threadIdx.x >> 2;
+        const int gx = blockIdx.x * 4 + lx, gy = blockIdx.y * 4 + ly;
+        if (gx < fc.mw[1] && gy < fc.mh[1]) {
+            int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[0] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[0] - 1);
+            float4 a = m0[y0 - blockIdx.y * 8][x0 - blockIdx.x * 8], b = m0[y0 - blockIdx.y * 8][x1 - blockIdx.x * 8];
+            float4 c = m0[y1 - blockIdx.y * 8][x0 - blockIdx.x * 8], d = m0[y1 - blockIdx.y * 8][x1 - blockIdx.x * 8];
+            float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                                   ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
+            P.mips[fc.moff[1] + (size_t)gy * fc.mw[1] + gx] = o;
+            m1[ly][lx] = o;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int lx = threadIdx.x & 1, ly = threadIdx.x >> 1;
+        const int gx = blockIdx.x * 2 + lx, gy = blockIdx.y * 2 + ly;
+        if (gx < fc.mw[2] && gy < fc.mh[2]) {
+            int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[1] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[1] - 1);
+            float4 a = m1[y0 - blockIdx.y * 4][x0 - blockIdx.x * 4], b = m1[y0 - blockIdx.y * 4][x1 - blockIdx.x * 4];
+            float4 c = m1[y1 - blockIdx.y * 4][x0 - blockIdx.x * 4], d = m1[y1 - blockIdx.y * 4][x1 - blockIdx.x * 4];
+            float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                                   ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
+            P.mips[fc.moff[2] + (size_t)gy * fc.mw[2] + gx] = o;
+            m2[ly][lx] = o;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int gx = blockIdx.x, gy = blockIdx.y;
+        if (gx < fc.mw[3] && gy < fc.mh[3]) {
+            int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[2] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[2] - 1);
+            float4 a = m2[y0 - blockIdx.y * 2][x0 - blockIdx.x * 2], b = m2[y0 - blockIdx.y * 2][x1 - blockIdx.x * 2];
+            float4 c = m2[y1 - blockIdx.y * 2][x0 - blockIdx.x * 2], d = m2[y1 - blockIdx.y * 2][x1 - blockIdx.x * 2];
+            float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
+                                   ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
+            P.mips[fc.moff[3] + (size_t)gy * fc.mw[3] + gx] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- A13
+
+__global__ __launch_bounds__(kBX *kBY) void k_recon(FrameConst fc, Rings rings, Planes P)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int hw = fc.hw, hh = fc.hh;
+    if (x >= hw || y >= hh) return;
+    const size_t i = (size_t)y * hw + x;
+    if (!(P.T0[i].w > 0.0f)) {
+        P.recon[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const float4 t1 = P.T1[i];
+    const float ct = t1.x, hu = t1.y;
+    const float Rr = fmin_cs(ct * 0.25f, fc.r_max);
+    const float lod = clampf(ct * fc.lod_scale, 0.0f, fc.lod_max);
+    int L0 = (int)floorf(lod);
+    const int Lmax = fc.lod_levels;
+    if (L0 > Lmax) L0 = Lmax;
+    const int L1 = L0 < Lmax ? L0 + 1 : Lmax;
+    const float fl = lod - (float)L0;
+    float sc0 = 1.0f, sc1 = 1.0f;
+    for (int L = 0; L < L0; ++L) sc0 = sc0 * 0.5f;
+    for (int L = 0; L < L1; ++L) sc1 = sc1 * 0.5f;
+    const float4 *mip0 = P.mips + fc.moff[L0], *mip1 = P.mips + fc.moff[L1];
+    const int w0 = fc.mw[L0], h0 = fc.mh[L0], w1 = fc.mw[L1], h1 = fc.mh[L1];
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, sh = 0.0f;
+    int na = 0;
+    for (int k = 0; k < kRingTaps; ++k) {
+        float dist = Rr * rings.frac[k];
+        float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
+        int ix = nearest_idx(sx, hw), iy = nearest_idx(sy, hh);
+        size_t j = (size_t)iy * hw + ix;
+        if (!(P.T0[j].w > 0.0f)) continue;
+        float4 tj = P.T1[j];
+        if (tj.x * 0.25f < dist) continue;
+        float4 s0 = bilinear4(mip0, w0, h0, (sx + 0.5f) * sc0 - 0.5f, (sy + 0.5f) * sc0 - 0.5f);
+        float4 s1 = bilinear4(mip1, w1, h1, (sx + 0.5f) * sc1 - 0.5f, (sy + 0.5f) * sc1 - 0.5f);
+        a0 = a0 + lerp1(s0.x, s1.x, fl);
+        a1 = a1 + lerp1(s0.y, s1.y, fl);
+        a2 = a2 + lerp1(s0.z, s1.z, fl);
+        a3 = a3 + lerp1(s0.w, s1.w, fl);
+        sh = sh + tj.y;
+        ++na;
+    }
+    const float4 med = P.rtmed[i];
+    float nb0 = a3 > 0.0f ? a0 / a3 : med.x, nb1 = a3 > 0.0f ? a1 / a3 : med.y, nb2 = a3 > 0.0f ? a2 / a3 : med.z;
+    float hnb = na > 0 ? sh / (float)na : hu;
+    float bb = clampf(P.var_blur[i] * fc.var_recon_w, 0.0f, fc.b_max);
+    P.recon[i] = make_float4(lerp1(med.x, nb0, bb), lerp1(med.y, nb1, bb), lerp1(med.z, nb2, bb), lerp1(hu, hnb, bb));
+}
+
+// ---------------------------------------------------------------- A14
+
+__global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    if (x >= fc.W || y >= fc.H) return;
+    const int hw = fc.hw, hh = fc.hh;
+    const size_t p = (size_t)y * fc.W + x;
+    const float z = gb.depth[p];
+    const float c = coc_px(fc.cock, fc.d, z);
+    const float hx = (float)x * 0.5f - 0.25f, hy = (float)y * 0.5f - 0.25f;
+    const float4 pp = bilinear4(P.ppmed, hw, hh, hx, hy);
+    const float x0f = floorf(hx), y0f = floorf(hy);
+    const float fx = hx - x0f, fy = hy - y0f;
+    const int x0 = (int)x0f, y0 = (int)y0f;
+    const int xs[2] = {clampi(x0, 0, hw - 1), clampi(x0 + 1, 0, hw - 1)};
+    const int ys[2] = {clampi(y0, 0, hh - 1), clampi(y0 + 1, 0, hh - 1)};
+    const float wts[4] = {(1.0f - fx) * (1.0f - fy), fx * (1.0f - fy), (1.0f - fx) * fy, fx * fy};
+    float sw = 0.0f, rc0 = 0.0f, rc1 = 0.0f, rc2 = 0.0f, rh = 0.0f, rct = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        size_t j = (size_t)ys[k >> 1] * hw + xs[k & 1];
+        float wv = wts[k] * P.T0[j].w;
+        float4 rj = P.recon[j];
+        sw = sw + wv;
+        rc0 = rc0 + wv * rj.x;
+        rc1 = rc1 + wv * rj.y;
+        rc2 = rc2 + wv * rj.z;
+        rh = rh + wv * rj.w;
+        rct = rct + wv * P.T1[j].x;
+    }
+    const bool rtv = sw > 0.0f;
+    if (rtv) {
+        rc0 = rc0 / sw; rc1 = rc1 / sw; rc2 = rc2 / sw;
+        rh = rh / sw;
+        rct = rct / sw;
+    }
+    float4 o;
+    if (c <= kSqrt2 && (!rtv || rct < kSqrt2)) {
+        float4 g = ld_rgba(gb.colour, gb.colour_format, p);
+        o = make_float4(g.x, g.y, g.z, 1.0f);
+    } else if (!rtv) {
+        o = make_float4(pp.x, pp.y, pp.z, 1.0f);
+    } else if (z < fc.d) {
+        o = make_float4(lerp1(rc0, pp.x, pp.w), lerp1(rc1, pp.y, pp.w), lerp1(rc2, pp.z, pp.w), 1.0f);
+    } else {
+        float t = sat(rh / fc.h_edge);
+        float w = (t * t) * (3.0f - 2.0f * t);
+        o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
+    }
+    st_rgba(out.colour, out.colour_format, p, o);
+}
+
+__global__ void k_fill_zero(float *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+inline dim3 grid2(int w, int h, int bx, int by) { return dim3((w + bx - 1) / bx, (h + by - 1) / by); }
+
+}  // namespace
+
+#define DOF_REC(k)                                          \
+    do {                                                    \
+        if (ev) {                                           \
+            hipError_t e_ = hipEventRecord(ev[(k)], st);    \
+            if (e_ != hipSuccess) return e_;                \
+        }                                                   \
+    } while (0)
+
+hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+                            const dof_gbuffer &gb, const void *hist_in, uint8_t *mask, hipEvent_t *ev,
+                            hipStream_t st)
+{
+    Planes P = planes(fc, L, scratch);
+    const int64_t np = (int64_t)fc.hw * fc.hh;
+    DOF_REC(0);
+    k_reduce<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, gb, P);
+    DOF_REC(1);
+    k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
+    DOF_REC(2);
+    k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
+    DOF_REC(3);
+    k_gather<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
+    DOF_REC(4);
+    k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
+    DOF_REC(5);
+    k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, mask);
+    DOF_REC(6);
+    k_compact_count<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
+    k_compact_scan<<<1, 1024, 0, st>>>(L.nchunks, P, nullptr);
+    k_compact_scatter<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
+    DOF_REC(7);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+                             const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
+                             const dof_frame_out &out, hipEvent_t *ev, hipStream_t st)
+{
+    Planes P = planes(fc, L, scratch);
+    const int64_t np = (int64_t)fc.hw * fc.hh;
+    DOF_REC(8);
+    k_resolve<<<(unsigned)((np + 255) / 256), 256, 0, st>>>(fc, P, mask);
+    DOF_REC(9);
+    k_temporal<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, mask, hist_in, hist_out);
+    DOF_REC(10);
+    k_blur_median_mips<<<grid2(fc.hw, fc.hh, 8, 8), 64, 0, st>>>(fc, P, hist_out);
+    DOF_REC(11);
+    k_recon<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
+    DOF_REC(12);
+    k_composite<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, out);
+    DOF_REC(13);
+    if (out.stats) {
+        // copy the frame counters to the caller's stats record
+        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 2 * sizeof(uint32_t),
+                                      hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
+{
+    k_fill_zero<<<1024, 256, 0, st>>>(hist, nfloats);
+    return hipGetLastError();
+}
+
+}  // namespace dof

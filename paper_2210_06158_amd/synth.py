@@ -256,7 +256,7 @@ def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
                 n_blades: int = 50000) -> tuple:
     """1920x1080 workload: ground quad, 4096 UV spheres of 240 triangles over
     depth 5-80 and a foreground grass band of 50k 4-triangle blades at depth
-    0.5-3 (about 1.18M triangles).  Returns (scene, camera_path(60), lens,
+    0.5-3 (1,183,042 triangles).  Returns (scene, camera_path(60), lens,
     params)."""
     rng = SplitMix64(seed)
     lens = Lens(focal=0.050, fnum=1.4, focus=15.0, sensor=0.036)
@@ -267,7 +267,9 @@ def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
     ns = n_spheres
     zc = rng.uniform(ns, 5.0, 80.0)
     r = rng.uniform(ns, 0.3, 1.5)
-    xc = rng.uniform(ns, -1.0, 1.0) * (zc * tx * 1.1 + 1.0)
+    # scattered over a wide field: the frame sees a slice of it (a few near
+    # spheres, many distant ones, sky above the horizon)
+    xc = rng.uniform(ns, -400.0, 400.0)
     cen = np.stack([xc, r, zc], 1)
     st, per = uv_spheres(cen, r)
     salb = np.repeat(rng.uniform(ns * 3, 0.05, 0.95).reshape(ns, 3), per, axis=0)
@@ -309,10 +311,11 @@ def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
 def camera_spline(rng: SplitMix64, nframes: int, width: int, height: int,
                   seed: int) -> list:
     """Catmull-Rom path through 8 seeded control points at eye height
-    0.3-0.6 with yaw within +-10 degrees and a slight downward pitch."""
+    0.8-1.1 with yaw within +-10 degrees and a 5-degree downward pitch, so the
+    grass is a foreground band in the lower part of the frame."""
     k = 8
     px = rng.uniform(k, -0.3, 0.3)
-    py = rng.uniform(k, 0.3, 0.6)
+    py = rng.uniform(k, 0.8, 1.1)
     pz = rng.uniform(k, -0.3, 0.3)
     yaw = rng.uniform(k, -math.radians(10), math.radians(10))
     ctrl = np.stack([px, py, pz, yaw], 1)
@@ -325,7 +328,7 @@ def camera_spline(rng: SplitMix64, nframes: int, width: int, height: int,
         t2, t3 = t * t, t * t * t
         v = 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t2
                    + (-p0 + 3 * p1 - 3 * p2 + p3) * t3)
-        cams.append(look_camera(v[:3], float(v[3]), math.radians(-4.0), width, height,
+        cams.append(look_camera(v[:3], float(v[3]), math.radians(-5.0), width, height,
                                 frame=fi, seed=seed))
     return cams
 

@@ -1,0 +1,244 @@
+"""GPU parity: libdof (through its C ABI) against the CPU oracle on the same
+seeded inputs, stage by stage, on the 256x256 workload (866 triangles, 4 rays
+per masked pixel).  Index work is compared bit for bit; intermediate floats
+to 1e-5; the final colour to 1e-3 per linear-RGB channel."""
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from paper_2210_06158_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+LEAF = 0x80000000
+COLOUR_TOL = 1e-3
+STAGE_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def env(orc):
+    import torch
+    from paper_2210_06158_amd import dof
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    scene, cam, lens, params = synth.scene_small()
+    osc = orc.OracleScene(scene)
+    osc.build_bvh()
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    torch.cuda.synchronize()
+    return dict(torch=torch, dof=dof, scene=scene, cam=cam, lens=lens, params=params, osc=osc, gs=gs)
+
+
+def to_gpu(torch, gb):
+    return (torch.from_numpy(gb.colour).cuda(), torch.from_numpy(gb.depth).cuda(), torch.from_numpy(gb.normal).cuda())
+
+
+def run_pair(env, orc, cam, lens, params, gb, hist_in=None, prev_cam=None, prev_lens=None, fmt16=False):
+    torch, dof = env["torch"], env["dof"]
+    o = orc.render_frame(env["osc"], cam, lens, params, gb, hist_in=hist_in, prev_cam=prev_cam, prev_lens=prev_lens)
+    fr = dof.Frame(cam.width, cam.height, params)
+    g = to_gpu(torch, gb)
+    if fmt16:
+        g = (g[0].half(), g[1], g[2].half())
+    hin = torch.from_numpy(hist_in).cuda() if hist_in is not None else None
+    hout = dof.history_alloc(cam.width, cam.height)
+    fr.render(env["gs"], cam, lens, g, hin, hout, prev_cam=prev_cam, prev_lens=prev_lens)
+    torch.cuda.synchronize()
+    d = fr.debug()
+    d["colour"] = fr.colour.float().cpu().numpy()
+    d["mask"] = fr.mask.cpu().numpy()
+    d["hist_out"] = hout.cpu().numpy()
+    d["stats"] = fr.stats.cpu().numpy()
+    return o, d
+
+
+def compare_frame(o, d, label):
+    m = o["mask"] > 0
+    assert np.array_equal(d["colr"], o["colr"]), label
+    assert np.array_equal(d["zn"], o["zn"]), label
+    assert np.array_equal(d["tile_max"], o["tile_max"]) and np.array_equal(d["tile_dil"], o["tile_dil"]), label
+    np.testing.assert_allclose(d["pre"], o["pre"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["gather"], o["gather"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["ppmed"], o["ppmed"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    assert np.array_equal(d["prev_idx"], o["prev_idx"]), label
+    assert np.array_equal(d["mask"], o["mask"]), label
+    assert d["n_masked"] == o["n_masked"] and d["n_rays"] == o["n_rays"], label
+    assert int(d["stats"][0]) == o["n_masked"] and int(d["stats"][1]) == o["n_rays"], label
+    assert np.array_equal(d["queue"], o["queue"]) and np.array_equal(d["ray_base"], o["ray_base"]), label
+    assert np.array_equal(d["ray_hit"], o["ray_hit"]), label
+    assert np.array_equal(d["ray_t"].view(np.uint32), o["ray_t"].view(np.uint32)), label
+    np.testing.assert_allclose(d["ray_col"], o["ray_col"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["ray_pos"], o["ray_pos"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["resolve"][:, m], o["resolve"][:, m], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["temporal"], o["temporal"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["var_blur"], o["var_blur"], rtol=STAGE_TOL, atol=1e-9, err_msg=label)
+    np.testing.assert_allclose(d["rtmed"], o["rtmed"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["mips"], o["mips"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["recon"], o["recon"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    np.testing.assert_allclose(d["hist_out"], o["hist_out"], rtol=STAGE_TOL, atol=STAGE_TOL, err_msg=label)
+    err = np.abs(d["colour"][..., :3] - o["colour"][..., :3]).max()
+    assert err <= COLOUR_TOL, (label, err)
+
+
+# ---------------------------------------------------------------- BVH
+
+def test_bvh_bit_exact(env, orc):
+    torch = env["torch"]
+    v = env["gs"].bvh_view()
+    ob = env["osc"].bvh
+    n = env["osc"].ntri
+    keys = v["keys"].cpu().numpy().view(np.uint32)
+    ids = v["ids"].cpu().numpy().view(np.uint32)
+    assert np.array_equal(keys, (ob["keys"] >> np.uint64(32)).astype(np.uint32))
+    assert np.array_equal(ids, (ob["keys"] & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+    nodes = v["nodes"].cpu().numpy().reshape(n - 1, 16)
+    nu = nodes.view(np.uint32)
+    assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
+    assert np.array_equal(v["parent"].cpu().numpy().view(np.uint32), ob["parent"])
+
+    def child_box(c):
+        return ob["leaf_bounds"][c & ~LEAF] if c & LEAF else ob["bounds"][c]
+    for i in range(n - 1):
+        a, b, c = nodes[i, 0:4], nodes[i, 4:8], nodes[i, 8:12]
+        lb = np.array([a[0], a[2], c[0], a[1], a[3], c[1]], np.float32)
+        rb = np.array([b[0], b[2], c[2], b[1], b[3], c[3]], np.float32)
+        assert np.array_equal(lb.view(np.uint32), child_box(int(ob["left"][i])).view(np.uint32))
+        assert np.array_equal(rb.view(np.uint32), child_box(int(ob["right"][i])).view(np.uint32))
+    tris = v["tris"].cpu().numpy().reshape(n, 12)
+    want = env["scene"].verts[ids]
+    assert np.array_equal(tris[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]], want)
+    assert np.array_equal(tris[:, 3].view(np.uint32), ids)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 3), (2, 4), (3, 5), (257, 6), (5000, 7)])
+def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
+    torch, dof = env["torch"], env["dof"]
+    v, a = synth.random_triangles(n, seed=seed, spread=4.0, size=0.8)
+    sc = synth.Scene(v, a)
+    osc = orc.OracleScene(sc)
+    ob = osc.build_bvh()
+    gs = dof.Scene(sc)
+    gs.build_bvh()
+    torch.cuda.synchronize()
+    view = gs.bvh_view()
+    keys = view["keys"].cpu().numpy().view(np.uint32)
+    ids = view["ids"].cpu().numpy().view(np.uint32)
+    assert np.array_equal((keys.astype(np.uint64) << np.uint64(32)) | ids.astype(np.uint64), ob["keys"])
+    if n > 1:
+        nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
+        assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
+    rng = synth.SplitMix64(seed * 31)
+    nr = 20000
+    o = rng.uniform(3 * nr, -5, 5).reshape(nr, 3).astype(np.float32)
+    t = rng.uniform(3 * nr, -3, 3).reshape(nr, 3)
+    d = (t - o).astype(np.float32)
+    hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
+    assert np.array_equal(hg.cpu().numpy(), ho)
+    assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
+
+
+def test_watertight_on_gpu(env, orc):
+    torch, dof = env["torch"], env["dof"]
+    mesh, _ = synth.uv_spheres(np.array([[0.3, -0.2, 0.1]]), np.array([1.7]))
+    sc = synth.Scene(mesh, np.ones((mesh.shape[0], 3), np.float32))
+    gs = dof.Scene(sc)
+    gs.build_bvh()
+    tv = mesh.reshape(-1, 3, 3)
+    targets = np.concatenate([tv.reshape(-1, 3), 0.5 * (tv[:, 0] + tv[:, 1])]).astype(np.float32)
+    o = np.tile(np.array([0.3, -0.2, 0.1], np.float32), (targets.shape[0], 1))
+    hg, _ = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(targets - o).cuda())
+    assert (hg.cpu().numpy() >= 0).all()
+
+
+# ---------------------------------------------------------------- G-buffer
+
+def test_gbuffer_matches_oracle(env, orc):
+    torch = env["torch"]
+    og = orc.gbuffer(env["osc"], env["cam"], env["lens"])
+    c, dpt, nrm = env["gs"].render_gbuffer(env["cam"], env["lens"])
+    torch.cuda.synchronize()
+    assert np.array_equal(dpt.cpu().numpy().view(np.uint32), og.depth.view(np.uint32))
+    assert np.array_equal(c.cpu().numpy(), og.colour)
+    assert np.array_equal(nrm.cpu().numpy(), og.normal)
+
+
+# ---------------------------------------------------------------- frames
+
+@pytest.fixture(scope="module")
+def frame0(env, orc):
+    gb = orc.gbuffer(env["osc"], env["cam"], env["lens"])
+    o, d = run_pair(env, orc, env["cam"], env["lens"], env["params"], gb)
+    return gb, o, d
+
+
+def test_frame0_parity(frame0):
+    _, o, d = frame0
+    compare_frame(o, d, "frame 0")
+    assert o["n_rays"] > 1000
+
+
+def test_frame1_pan_parity(env, orc, frame0):
+    """Second frame after a 0.02-unit pan, both sides fed the oracle's
+    history of frame 0 (motion: reduced blend, latest hit ratio)."""
+    _, o0, _ = frame0
+    cam1 = synth.pan_camera(env["cam"], 0.02)
+    gb1 = orc.gbuffer(env["osc"], cam1, env["lens"])
+    o, d = run_pair(env, orc, cam1, env["lens"], env["params"], gb1, hist_in=o0["hist_out"],
+                    prev_cam=env["cam"], prev_lens=env["lens"])
+    assert (o["prev_idx"] >= 0).mean() > 0.5
+    compare_frame(o, d, "frame 1 pan")
+
+
+def test_frame1_static_parity(env, orc, frame0):
+    gb, o0, _ = frame0
+    cam1 = dataclasses.replace(env["cam"], frame=1)
+    o, d = run_pair(env, orc, cam1, env["lens"], env["params"], gb, hist_in=o0["hist_out"],
+                    prev_cam=env["cam"], prev_lens=env["lens"])
+    compare_frame(o, d, "frame 1 static")
+
+
+def test_fp16_gbuffer_parity(env, orc):
+    """FP16 colour/normal G-buffer: the oracle reads the same values widened
+    to binary32 (exact), so parity holds at the same tolerances."""
+    gb = orc.gbuffer(env["osc"], env["cam"], env["lens"])
+    gb16 = orc.GBuffer(gb.colour.astype(np.float16).astype(np.float32), gb.depth,
+                       gb.normal.astype(np.float16).astype(np.float32))
+    o, d = run_pair(env, orc, env["cam"], env["lens"], env["params"], gb16, fmt16=True)
+    compare_frame(o, d, "fp16 G-buffer")
+
+
+@pytest.mark.parametrize("mode,m", [(synth.MASK_ALL, 3), (synth.MASK_FIXED, 5)])
+def test_mask_modes_parity(env, orc, frame0, mode, m):
+    gb, _, _ = frame0
+    p = dataclasses.replace(env["params"], mask_mode=mode, m=m)
+    o, d = run_pair(env, orc, env["cam"], env["lens"], p, gb)
+    compare_frame(o, d, f"mask mode {mode}")
+
+
+def test_hexagon_aperture_and_ragged_size(env, orc):
+    """6-blade aperture at a size that is not a multiple of any tile
+    (ragged tails in every kernel)."""
+    lens = dataclasses.replace(env["lens"], fnum=2.0, blades=6, blade_rot=0.2)
+    cam = dataclasses.replace(env["cam"], width=202, height=118)
+    gb = orc.gbuffer(env["osc"], cam, lens)
+    o, d = run_pair(env, orc, cam, lens, dataclasses.replace(env["params"], m=6), gb)
+    compare_frame(o, d, "hexagon 202x118")
+
+
+def test_pinhole_reduction_on_gpu(env, orc):
+    lens = dataclasses.replace(env["lens"], fnum=math.inf)
+    gb = orc.gbuffer(env["osc"], env["cam"], lens)
+    o, d = run_pair(env, orc, env["cam"], lens, env["params"], gb)
+    assert np.array_equal(d["colour"][..., :3].view(np.uint32), gb.colour[..., :3].view(np.uint32))
+
+
+def test_determinism_run_twice(env, orc, frame0):
+    gb, _, d0 = frame0
+    _, d1 = run_pair(env, orc, env["cam"], env["lens"], env["params"], gb)
+    for k in ("colour", "mask", "queue", "ray_hit", "ray_col", "recon", "hist_out"):
+        assert np.array_equal(d0[k], d1[k]), k
