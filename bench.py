@@ -133,9 +133,11 @@ def main():
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
     frame_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    st = stats.cpu().numpy().astype(np.int64)
-    rays = int(st[:, 1].sum())
-    masked = int(st[:, 0].sum())
+    st = stats.cpu().numpy()
+    rays = int(st[:, 1].astype(np.int64).sum())
+    masked = int(st[:, 0].astype(np.int64).sum())
+    st64 = st.view(np.int64)
+    visits, tests = int(st64[:, 1].sum()), int(st64[:, 2].sum())
     fps = K / (total_ms / 1e3)
     log(f"timed {K} frames: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
 
@@ -186,6 +188,8 @@ def main():
         "masked_grays_per_s": round(rays / (total_ms * 1e-3) / 1e9, 4),
         "trace_kernel_grays_per_s": round(trace_grays, 4) if trace_grays else None,
         "rays_per_frame": round(rays / K, 1),
+        "node_visits_per_ray": round(visits / max(rays, 1), 2),
+        "tri_tests_per_ray": round(tests / max(rays, 1), 2),
         "masked_px_per_frame": round(masked / K, 1),
         "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),
         "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 4),

@@ -125,7 +125,9 @@ typedef struct {
 typedef struct {
     uint32_t masked_px;     /* half-res pixels with at least one ray */
     uint32_t rays;          /* thin-lens rays traced */
-    uint32_t reserved[6];
+    uint64_t node_visits;   /* BVH nodes fetched by the traversal */
+    uint64_t tri_tests;     /* ray/triangle tests */
+    uint32_t reserved[2];
 } dof_stats;
 
 typedef struct {
@@ -146,7 +148,9 @@ typedef struct {
 typedef struct dof_scene dof_scene;
 
 /* Device views of the acceleration structure (for inspection and tests).
- * keys: sorted 30-bit Morton codes; ids: triangle ids in the same order;
+ * keys: sorted 63-bit Morton codes (21 bits per axis of the triangle box
+ * centre over the centre bounds, x at bit 3i+2, y 3i+1, z 3i), ties in id
+ * order; ids: triangle ids in the same order;
  * nodes: ntri-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
  * float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z, R.lo.z,
  * R.hi.z), uint4 (left, right, 0, 0)}, child bit 31 = leaf (sorted index);
@@ -154,7 +158,8 @@ typedef struct dof_scene dof_scene;
  * tris: 3 float4 per leaf in sorted order (w of the first = id bits). */
 typedef struct {
     int32_t ntri;
-    const uint32_t *keys, *ids, *parent;
+    const uint64_t *keys;
+    const uint32_t *ids, *parent;
     const void *nodes, *tris;
 } dof_bvh_view;
 
@@ -169,7 +174,8 @@ int32_t dof_abi_version(void);
 const char *dof_last_error(void);
 void dof_default_params(dof_params *p);
 
-/* Scene arena size for ntri triangles (triangles, BVH and build scratch). */
+/* Scene arena size for ntri triangles (triangles, BVH, build scratch and a
+ * traversal stack spill area of about 40 MB). */
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);
 
 /* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes) on

@@ -45,7 +45,7 @@ class OrcScene(C.Structure):
 
 
 class OrcBvh(C.Structure):
-    _fields_ = [("ntri", C.c_int32), ("keys", C.c_void_p), ("left", C.c_void_p),
+    _fields_ = [("ntri", C.c_int32), ("keys", C.c_void_p), ("ids", C.c_void_p), ("left", C.c_void_p),
                 ("right", C.c_void_p), ("parent", C.c_void_p), ("bounds", C.c_void_p),
                 ("leaf_bounds", C.c_void_p)]
 
@@ -130,11 +130,11 @@ class OracleScene:
 
     def build_bvh(self):
         n = self.ntri
-        b = dict(keys=np.zeros(n, np.uint64), left=np.zeros(max(n - 1, 1), np.uint32),
+        b = dict(keys=np.zeros(n, np.uint64), ids=np.zeros(n, np.uint32), left=np.zeros(max(n - 1, 1), np.uint32),
                  right=np.zeros(max(n - 1, 1), np.uint32), parent=np.zeros(2 * n - 1, np.uint32),
                  bounds=np.zeros((max(n - 1, 1), 6), np.float32),
                  leaf_bounds=np.zeros((n, 6), np.float32))
-        st = OrcBvh(n, *(_ptr(b[k]) for k in ("keys", "left", "right", "parent", "bounds", "leaf_bounds")))
+        st = OrcBvh(n, *(_ptr(b[k]) for k in ("keys", "ids", "left", "right", "parent", "bounds", "leaf_bounds")))
         rc = lib().orc_build_bvh(C.byref(self.s), C.byref(st))
         if rc != 0:
             raise RuntimeError(f"orc_build_bvh failed: {rc}")
@@ -151,7 +151,7 @@ class OracleScene:
 
 
 def morton(scene: OracleScene) -> np.ndarray:
-    out = np.zeros(scene.ntri, np.uint32)
+    out = np.zeros(scene.ntri, np.uint64)
     rc = lib().orc_morton(C.byref(scene.s), _ptr(out))
     if rc != 0:
         raise RuntimeError("orc_morton failed")

@@ -181,15 +181,17 @@ static void tri_box(const float *v, float lo[3], float hi[3])
     }
 }
 
-static uint32_t spread10(uint32_t x)
+static uint64_t spread21(uint32_t x)
 {
     /* place bit i of x at bit 3i, bit by bit */
-    uint32_t r = 0;
-    for (int i = 0; i < 10; i++) r |= ((x >> i) & 1u) << (3 * i);
+    uint64_t r = 0;
+    for (int i = 0; i < 21; i++) r |= (uint64_t)((x >> i) & 1u) << (3 * i);
     return r;
 }
 
-int orc_morton(const orc_scene *s, uint32_t *codes)
+/* 63-bit Morton code (21 bits per axis, x at bit 3i+2, y at 3i+1, z at 3i)
+ * of each triangle's box centre, quantised over the bounds of all centres. */
+int orc_morton(const orc_scene *s, uint64_t *codes)
 {
     if (!s || s->ntri <= 0 || !codes) return -1;
     int n = s->ntri;
@@ -209,25 +211,31 @@ int orc_morton(const orc_scene *s, uint32_t *codes)
     float inv[3];
     for (int a = 0; a < 3; a++) {
         float ext = hi[a] - lo[a];
-        inv[a] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+        inv[a] = ext > 0.0f ? 2097152.0f / ext : 0.0f;
     }
     for (int i = 0; i < n; i++) {
         uint32_t qv[3];
         for (int a = 0; a < 3; a++) {
             float t = floorf((cen[3 * (size_t)i + a] - lo[a]) * inv[a]);
             int qi = (int)t;
-            qv[a] = (uint32_t)(qi > 1023 ? 1023 : qi);
+            qv[a] = (uint32_t)(qi > 2097151 ? 2097151 : qi);
         }
-        codes[i] = (spread10(qv[0]) << 2) | (spread10(qv[1]) << 1) | spread10(qv[2]);
+        codes[i] = (spread21(qv[0]) << 2) | (spread21(qv[1]) << 1) | spread21(qv[2]);
     }
     free(cen);
     return 0;
 }
 
-static int cmp_u64(const void *a, const void *b)
+typedef struct {
+    uint64_t code;
+    uint32_t id;
+} keyed;
+
+static int cmp_keyed(const void *a, const void *b)
 {
-    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
-    return x < y ? -1 : (x > y ? 1 : 0);
+    const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
 }
 
 static void box_union(const float *a, const float *b, float *o)
@@ -238,16 +246,24 @@ static void box_union(const float *a, const float *b, float *o)
     }
 }
 
+/* Bit b (0 = most significant) of the 96-bit key (code << 32 | id) of leaf i:
+ * the code occupies key bits 0..63, the id bits 64..95. */
+static int key_bit(const orc_bvh *b, uint32_t i, int bit)
+{
+    if (bit < 64) return (int)((b->keys[i] >> (63 - bit)) & 1u);
+    return (int)((b->ids[i] >> (95 - bit)) & 1u);
+}
+
 /* Top-down: the node covering sorted leaves [first, last] splits where the
- * highest bit in which its first and last keys differ turns from 0 to 1.
- * The left child is numbered by its last leaf, the right child by its first
- * leaf, the root is 0 (Karras 2012 numbering). */
+ * most significant key bit in which its first and last keys differ turns from
+ * 0 to 1.  The left child is numbered by its last leaf, the right child by
+ * its first leaf, the root is 0 (Karras 2012 numbering). */
 static void build_rec(orc_bvh *b, uint32_t first, uint32_t last, uint32_t index)
 {
-    uint64_t x = b->keys[first] ^ b->keys[last];
-    int bit = 63 - __builtin_clzll(x);
+    int bit = 0;
+    while (key_bit(b, first, bit) == key_bit(b, last, bit)) bit++;
     uint32_t split = first;
-    while (split + 1 <= last && ((b->keys[split + 1] >> bit) & 1u) == 0) split++;
+    while (split + 1 <= last && key_bit(b, split + 1, bit) == 0) split++;
     uint32_t l, r;
     if (split == first) {
         l = split | LEAF_BIT;
@@ -276,14 +292,17 @@ int orc_build_bvh(const orc_scene *s, orc_bvh *b)
 {
     if (!s || !b || s->ntri <= 0 || b->ntri != s->ntri) return -1;
     int n = s->ntri;
-    uint32_t *codes = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
-    if (!codes) return -2;
+    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    keyed *kv = (keyed *)malloc(sizeof(keyed) * (size_t)n);
+    if (!codes || !kv) { free(codes); free(kv); return -2; }
     orc_morton(s, codes);
-    for (int i = 0; i < n; i++) b->keys[i] = ((uint64_t)codes[i] << 32) | (uint32_t)i;
+    for (int i = 0; i < n; i++) { kv[i].code = codes[i]; kv[i].id = (uint32_t)i; }
     free(codes);
-    qsort(b->keys, (size_t)n, sizeof(uint64_t), cmp_u64);
+    qsort(kv, (size_t)n, sizeof(keyed), cmp_keyed);
+    for (int i = 0; i < n; i++) { b->keys[i] = kv[i].code; b->ids[i] = kv[i].id; }
+    free(kv);
     for (int i = 0; i < n; i++) {
-        uint32_t id = (uint32_t)(b->keys[i] & 0xffffffffu);
+        uint32_t id = b->ids[i];
         float lo[3], hi[3];
         tri_box(s->verts + 9 * (size_t)id, lo, hi);
         for (int a = 0; a < 3; a++) {
@@ -291,11 +310,8 @@ int orc_build_bvh(const orc_scene *s, orc_bvh *b)
             b->leaf_bounds[6 * (size_t)i + 3 + a] = hi[a];
         }
     }
-    if (n == 1) {
-        b->parent[0] = ~0u;
-        return 0;
-    }
     b->parent[0] = ~0u;
+    if (n == 1) return 0;
     build_rec(b, 0, (uint32_t)n - 1, 0);
     return 0;
 }
@@ -411,8 +427,7 @@ static void trace_rec(const orc_scene *s, const orc_bvh *b, const wray *r,
                                          : b->bounds + 6 * (size_t)x;
         if (!box_hit(bx, o, inv, zero, (double)*tb)) continue;
         if (x & LEAF_BIT) {
-            uint32_t id = (uint32_t)(b->keys[x & ~LEAF_BIT] & 0xffffffffu);
-            consider(s, r, id, tb, ib);
+            consider(s, r, b->ids[x & ~LEAF_BIT], tb, ib);
         } else {
             trace_rec(s, b, r, o, inv, zero, x, tb, ib);
         }

@@ -54,11 +54,12 @@ typedef struct {
     float light_dir[3], light_rad[3], ambient[3], sky[3];
 } orc_scene;
 
-/* Binary radix tree over (Morton << 32 | id) keys, Karras numbering.
- * All arrays are caller-allocated. */
+/* Binary radix tree over 96-bit keys (63-bit Morton code, then triangle
+ * id), Karras numbering.  All arrays are caller-allocated. */
 typedef struct {
     int32_t ntri;
-    uint64_t *keys;         /* ntri, ascending */
+    uint64_t *keys;         /* ntri Morton codes, ascending with ids */
+    uint32_t *ids;          /* ntri triangle ids in leaf order */
     uint32_t *left, *right; /* ntri-1 each; bit 31 set = leaf (sorted index) */
     uint32_t *parent;       /* 2*ntri-1: internal nodes then leaves; root = ~0u */
     float *bounds;          /* 6 per internal node: lo xyz, hi xyz */
@@ -95,7 +96,7 @@ int orc_threads(void);
 float orc_coc(const orc_lens *lens, int32_t width, float z);
 int orc_zone(const orc_lens *lens, int32_t width, float *z_near, float *z_far);
 
-int orc_morton(const orc_scene *s, uint32_t *codes);
+int orc_morton(const orc_scene *s, uint64_t *codes);
 int orc_build_bvh(const orc_scene *s, orc_bvh *b);
 
 /* Closest hit per ray; bvh == NULL means brute force over all triangles. */

@@ -43,9 +43,12 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct SceneLayout {
-    size_t verts_in, albedo_in, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp, flags, hist, bounds, total;
+    size_t verts_in, albedo_in, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp, flags, hist, bounds;
+    size_t aux, spill, total;
     int sort_blocks, bound_blocks;
 };
+
+constexpr size_t kSpillBytes = sizeof(uint32_t) * dof::kSpillPerThread * dof::kTB * (size_t)dof::kMaxTraceBlocks;
 
 SceneLayout scene_layout(int64_t n)
 {
@@ -65,13 +68,15 @@ SceneLayout scene_layout(int64_t n)
     L.albedo = take(sizeof(float4) * n);
     L.nodes = take(sizeof(dof::BvhNode) * ni);
     L.parent = take(sizeof(uint32_t) * (2 * n - 1));
-    L.keys = take(sizeof(uint32_t) * n);
-    L.keys_tmp = take(sizeof(uint32_t) * n);
+    L.keys = take(sizeof(uint64_t) * n);
+    L.keys_tmp = take(sizeof(uint64_t) * n);
     L.ids = take(sizeof(uint32_t) * n);
     L.ids_tmp = take(sizeof(uint32_t) * n);
     L.flags = take(sizeof(uint32_t) * ni);
-    L.hist = take(sizeof(uint32_t) * 256 * (size_t)L.sort_blocks);
+    L.hist = take(sizeof(uint32_t) * 256 * ((size_t)L.sort_blocks + 1));
     L.bounds = take(sizeof(float) * (6 * (size_t)L.bound_blocks + 8));
+    L.aux = take(64);
+    L.spill = take(kSpillBytes);
     L.total = off;
     return L;
 }
@@ -122,8 +127,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m)
     }
     L.mips = take(16 * mt);
     L.recon = take(16 * np);
-    L.spill = 0;
-    L.spill_threads = 0;
+    L.spill = take(kSpillBytes);
     L.total = off;
     return L;
 }
@@ -228,7 +232,7 @@ dof_status params_check(const dof_params *p)
     if (p->mask_mode < 0 || p->mask_mode > 2) return fail(DOF_E_INVALID, "bad mask_mode");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
     if (!(p->lod_max >= 0.0f)) return fail(DOF_E_INVALID, "bad lod_max");
-    if (p->trace_blocks < 0) return fail(DOF_E_INVALID, "bad trace_blocks");
+    if (p->trace_blocks < 0 || p->trace_blocks > dof::kMaxTraceBlocks) return fail(DOF_E_INVALID, "bad trace_blocks");
     return DOF_OK;
 }
 
@@ -298,7 +302,8 @@ int default_trace_blocks()
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
-    return cus * 5;
+    const int b = cus * 5;
+    return b > dof::kMaxTraceBlocks ? dof::kMaxTraceBlocks : b;
 }
 
 }  // namespace
@@ -361,13 +366,15 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
     d.albedo = reinterpret_cast<float4 *>(a + L.albedo);
     d.nodes = reinterpret_cast<dof::BvhNode *>(a + L.nodes);
     d.parent = reinterpret_cast<uint32_t *>(a + L.parent);
-    d.keys = reinterpret_cast<uint32_t *>(a + L.keys);
-    d.keys_tmp = reinterpret_cast<uint32_t *>(a + L.keys_tmp);
+    d.keys = reinterpret_cast<uint64_t *>(a + L.keys);
+    d.keys_tmp = reinterpret_cast<uint64_t *>(a + L.keys_tmp);
     d.ids = reinterpret_cast<uint32_t *>(a + L.ids);
     d.ids_tmp = reinterpret_cast<uint32_t *>(a + L.ids_tmp);
     d.flags = reinterpret_cast<uint32_t *>(a + L.flags);
     d.hist = reinterpret_cast<uint32_t *>(a + L.hist);
     d.bounds = reinterpret_cast<float *>(a + L.bounds);
+    d.aux = reinterpret_cast<uint32_t *>(a + L.aux);
+    d.spill = reinterpret_cast<uint32_t *>(a + L.spill);
     d.sort_blocks = L.sort_blocks;
     d.bound_blocks = L.bound_blocks;
     memcpy(s->shade.light_dir, desc->light_dir, sizeof(desc->light_dir));
@@ -424,7 +431,8 @@ dof_status dof_trace_rays(const dof_scene *scene, int64_t n, const float *org, c
     if (!scene || n < 0 || (n > 0 && (!org || !dir || !hit || !t))) return fail(DOF_E_INVALID, "bad arguments");
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
     if (n > ((int64_t)1 << 31)) return fail(DOF_E_INVALID, "too many rays");
-    DOF_HIP(dof::launch_trace_rays(scene->dev, n, org, dir, hit, t, static_cast<hipStream_t>(stream)));
+    DOF_HIP(dof::launch_trace_rays(scene->dev, n, org, dir, hit, t, default_trace_blocks(),
+                                   static_cast<hipStream_t>(stream)));
     return DOF_OK;
 }
 
@@ -442,7 +450,7 @@ dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, con
     dof::FrameConst fc;
     fill_frame_const(scene, *cam, *lens, p, false, false, *cam, *lens, fc);
     DOF_HIP(dof::launch_gbuffer(scene->dev, fc, colour, colour_format, depth, normal, normal_format,
-                                static_cast<hipStream_t>(stream)));
+                                default_trace_blocks(), static_cast<hipStream_t>(stream)));
     return DOF_OK;
 }
 

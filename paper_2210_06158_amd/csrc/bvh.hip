@@ -1,10 +1,10 @@
 // LBVH build on the device: the acceleration structure that replaces the
 // DXR build the paper times inside its Ray Trace pass (section 5.2).
 //
-//   centroid bounds -> 30-bit Morton keys -> stable LSD radix sort of
-//   (key, id) -> binary radix tree over the 62-bit keys (key << 32 | id)
-//   (Karras 2012) -> triangles reordered to leaf order -> bottom-up refit of
-//   the child boxes stored in each node.
+//   centroid bounds -> 63-bit Morton keys (21 bits per axis) -> stable LSD
+//   radix sort of (key, id) -> binary radix tree over the 96-bit keys
+//   key << 32 | id (Karras 2012) -> triangles reordered to leaf order ->
+//   bottom-up refit of the child boxes stored in each node.
 //
 // All results are bit-reproducible: min/max are compare-selects and the
 // sort is stable, so the tree depends only on the input triangles.
@@ -79,36 +79,46 @@ __global__ __launch_bounds__(kThreads) void k_centroid_bounds(const float *__res
     }
 }
 
-// Reduce the partial bounds; final slot = lo[3], inv[3] with inv = 1024 / extent.
-__global__ void k_bounds_final(float *__restrict__ partial, int nblocks)
+// Reduce the partial bounds; final slot = lo[3], inv[3] with inv = 2^21 / extent.
+__global__ __launch_bounds__(256) void k_bounds_final(float *__restrict__ partial, int nblocks)
 {
-    if (threadIdx.x != 0) return;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nblocks; ++b)
+    for (int b = threadIdx.x; b < nblocks; b += 256)
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin_cs(lo[a], partial[6 * b + a]);
             hi[a] = fmax_cs(hi[a], partial[6 * b + 3 + a]);
         }
-    float *out = partial + 6 * (size_t)nblocks;
+    __shared__ float red[6][4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int a = 0; a < 3; ++a) {
-        float ext = hi[a] - lo[a];
-        out[a] = lo[a];
-        out[3 + a] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+        float m = wave_min(lo[a]), M = wave_max(hi[a]);
+        if (lane == 0) { red[a][w] = m; red[3 + a][w] = M; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        float l = red[a][0], h = red[3 + a][0];
+        for (int k = 1; k < 4; ++k) { l = fmin_cs(l, red[a][k]); h = fmax_cs(h, red[3 + a][k]); }
+        float *out = partial + 6 * (size_t)nblocks;
+        float ext = h - l;
+        out[a] = l;
+        out[3 + a] = ext > 0.0f ? 2097152.0f / ext : 0.0f;
     }
 }
 
-__device__ inline uint32_t spread_bits10(uint32_t x)
+__device__ inline uint64_t spread_bits21(uint32_t v)
 {
-    x &= 0x3ffu;
-    x = (x | (x << 16)) & 0x030000ffu;
-    x = (x | (x << 8)) & 0x0300f00fu;
-    x = (x | (x << 4)) & 0x030c30c3u;
-    x = (x | (x << 2)) & 0x09249249u;
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
     return x;
 }
 
 __global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ verts, int n,
-                                                     const float *__restrict__ fin, uint32_t *__restrict__ keys,
+                                                     const float *__restrict__ fin, uint64_t *__restrict__ keys,
                                                      uint32_t *__restrict__ ids)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
@@ -124,18 +134,19 @@ __global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ v
         float c = (bl[a] + bh[a]) * 0.5f;
         float t = floorf((c - fin[a]) * fin[3 + a]);
         int qi = (int)t;
-        q[a] = (uint32_t)(qi > 1023 ? 1023 : qi);
+        q[a] = (uint32_t)(qi > 2097151 ? 2097151 : qi);
     }
-    keys[i] = (spread_bits10(q[0]) << 2) | (spread_bits10(q[1]) << 1) | spread_bits10(q[2]);
+    keys[i] = (spread_bits21(q[0]) << 2) | (spread_bits21(q[1]) << 1) | spread_bits21(q[2]);
     ids[i] = (uint32_t)i;
 }
 
 // ---------------------------------------------------------------- radix sort
-// Per pass: digit histogram per tile (digit-major), one-block exclusive scan,
+// Per 8-bit pass: digit histogram per tile (digit-major), per-digit scans
+// across tiles (one block per digit), a scan of the 256 digit totals, then a
 // stable scatter.  Ranks inside a tile come from 8 wave ballots per round
 // (lanes sharing a digit), so equal digits keep their input order.
 
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int n, int shift,
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int n, int shift,
                                                          uint32_t *__restrict__ hist, int nblocks)
 {
     __shared__ uint32_t cnt[256];
@@ -144,46 +155,64 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     size_t base = (size_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; ++r) {
         size_t i = base + (size_t)r * kThreads + threadIdx.x;
-        if (i < (size_t)n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1u);
+        if (i < (size_t)n) atomicAdd(&cnt[(uint32_t)(keys[i] >> shift) & 0xffu], 1u);
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of `total` counters with one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *__restrict__ data, int total)
+// Block d: exclusive scan of digit d's counts over all tiles (in place); the
+// digit total goes to tot[d].
+__global__ __launch_bounds__(256) void k_scan_digit(uint32_t *__restrict__ hist, int nblocks,
+                                                    uint32_t *__restrict__ tot)
 {
-    __shared__ uint32_t part[1024];
-    int per = (total + 1023) / 1024;
-    int b = threadIdx.x * per, e = min(total, b + per);
-    uint32_t s = 0;
-    for (int i = b; i < e; ++i) s += data[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __shared__ uint32_t part[256];
+    uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nblocks; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < nblocks ? row[i] : 0u;
+        part[threadIdx.x] = v;
         __syncthreads();
-        part[threadIdx.x] += v;
+        for (int off = 1; off < 256; off <<= 1) {
+            uint32_t u = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (i < nblocks) row[i] = carry + part[threadIdx.x] - v;
+        carry += part[255];
         __syncthreads();
     }
-    uint32_t run = part[threadIdx.x] - s;
-    for (int i = b; i < e; ++i) {
-        uint32_t v = data[i];
-        data[i] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+// Exclusive scan of the 256 digit totals in place.
+__global__ __launch_bounds__(256) void k_scan_totals(uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t part[256];
+    const uint32_t v = tot[threadIdx.x];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t u = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += u;
+        __syncthreads();
+    }
+    tot[threadIdx.x] = part[threadIdx.x] - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                             const uint32_t *__restrict__ vin,
-                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             int n, int shift, const uint32_t *__restrict__ offs,
-                                                            int nblocks)
+                                                            const uint32_t *__restrict__ doff, int nblocks)
 {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[kThreads / 64][256];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    running[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    running[tid] = doff[tid] + offs[(size_t)tid * nblocks + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kThreads / 64; ++k) wcnt[k][tid] = 0;
     __syncthreads();
@@ -192,9 +221,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
     for (int r = 0; r < kSortItems; ++r) {
         size_t i = base + (size_t)r * kThreads + tid;
         bool valid = i < (size_t)n;
-        uint32_t key = valid ? kin[i] : 0u;
+        uint64_t key = valid ? kin[i] : 0ull;
         uint32_t val = valid ? vin[i] : 0u;
-        uint32_t dg = (key >> shift) & 0xffu;
+        uint32_t dg = (uint32_t)(key >> shift) & 0xffu;
         uint64_t match = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -239,35 +268,37 @@ __global__ __launch_bounds__(kThreads) void k_reorder(const float *__restrict__ 
     albedo[i] = make_float4(a[0], a[1], a[2], 0.0f);
 }
 
-__device__ inline int delta64(const uint32_t *keys, const uint32_t *ids, int n, int i, int j)
+// Length of the common prefix of the 96-bit keys (code << 32 | id) of leaves
+// i and j; -1 outside the array.
+__device__ inline int delta96(const uint64_t *keys, const uint32_t *ids, int n, int i, int j)
 {
     if (j < 0 || j >= n) return -1;
-    uint64_t a = ((uint64_t)keys[i] << 32) | ids[i];
-    uint64_t b = ((uint64_t)keys[j] << 32) | ids[j];
-    return __clzll(a ^ b);
+    uint64_t x = keys[i] ^ keys[j];
+    if (x != 0ull) return __clzll(x);
+    return 64 + __clz(ids[i] ^ ids[j]);
 }
 
-__global__ __launch_bounds__(kThreads) void k_karras(const uint32_t *__restrict__ keys,
+__global__ __launch_bounds__(kThreads) void k_karras(const uint64_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ ids, int n,
                                                      BvhNode *__restrict__ nodes, uint32_t *__restrict__ parent,
                                                      uint32_t *__restrict__ flags)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n - 1) return;
-    int dn = delta64(keys, ids, n, i, i + 1), dp = delta64(keys, ids, n, i, i - 1);
+    int dn = delta96(keys, ids, n, i, i + 1), dp = delta96(keys, ids, n, i, i - 1);
     int d = dn > dp ? 1 : -1;
     int dmin = d > 0 ? dp : dn;
     int lmax = 2;
-    while (delta64(keys, ids, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    while (delta96(keys, ids, n, i, i + lmax * d) > dmin) lmax <<= 1;
     int l = 0;
     for (int t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta64(keys, ids, n, i, i + (l + t) * d) > dmin) l += t;
+        if (delta96(keys, ids, n, i, i + (l + t) * d) > dmin) l += t;
     int j = i + l * d;
-    int dnode = delta64(keys, ids, n, i, j);
+    int dnode = delta96(keys, ids, n, i, j);
     int s = 0, t = l;
     do {
         t = (t + 1) >> 1;
-        if (delta64(keys, ids, n, i, i + (s + t) * d) > dnode) s += t;
+        if (delta96(keys, ids, n, i, i + (s + t) * d) > dnode) s += t;
     } while (t > 1);
     int gamma = i + s * d + (d < 0 ? -1 : 0);
     int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -337,17 +368,20 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
     const int n = s.ntri;
     const int nb = s.bound_blocks;
     k_centroid_bounds<<<nb, kThreads, 0, st>>>(s.verts_in, n, s.bounds);
-    k_bounds_final<<<1, 64, 0, st>>>(s.bounds, nb);
+    k_bounds_final<<<1, 256, 0, st>>>(s.bounds, nb);
     const float *fin = s.bounds + 6 * (size_t)nb;
     k_morton<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, n, fin, s.keys, s.ids);
     const int sb = s.sort_blocks;
-    uint32_t *ka = s.keys, *kb = s.keys_tmp, *va = s.ids, *vb = s.ids_tmp;
-    for (int shift = 0; shift < 32; shift += 8) {
+    uint32_t *doff = s.hist + 256 * (size_t)sb;
+    uint64_t *ka = s.keys, *kb = s.keys_tmp;
+    uint32_t *va = s.ids, *vb = s.ids_tmp;
+    for (int shift = 0; shift < 64; shift += 8) {
         k_radix_hist<<<sb, kThreads, 0, st>>>(ka, n, shift, s.hist, sb);
-        k_scan_u32<<<1, 1024, 0, st>>>(s.hist, 256 * sb);
-        k_radix_scatter<<<sb, kThreads, 0, st>>>(ka, va, kb, vb, n, shift, s.hist, sb);
-        uint32_t *t = ka; ka = kb; kb = t;
-        t = va; va = vb; vb = t;
+        k_scan_digit<<<256, 256, 0, st>>>(s.hist, sb, doff);
+        k_scan_totals<<<1, 256, 0, st>>>(doff);
+        k_radix_scatter<<<sb, kThreads, 0, st>>>(ka, va, kb, vb, n, shift, s.hist, doff, sb);
+        uint64_t *t = ka; ka = kb; kb = t;
+        uint32_t *u = va; va = vb; vb = u;
     }
     k_reorder<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, s.albedo_in, s.ids, n, s.tris, s.albedo);
     if (n >= 2) {

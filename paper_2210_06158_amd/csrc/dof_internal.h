@@ -18,8 +18,10 @@ constexpr int kTile = 16;                 // neighbourhood-max tile side
 constexpr int kRingTaps = 81;             // 1 + 8 + 16 + 24 + 32 (3.1.1)
 constexpr int kMaxBlades = 16;
 constexpr int kStackLds = 32;             // traversal stack entries kept in LDS
-constexpr int kStackMax = 64;             // total depth; a 62-bit key tree never exceeds it
-constexpr int kTraceThreads = 256;
+constexpr int kStackMax = 96;             // a tree over 95 significant key bits is at most 95 deep
+constexpr int kSpillPerThread = kStackMax - kStackLds;   // entries beyond LDS live in global memory
+constexpr int kTB = 128;                  // threads per traversal block
+constexpr int kMaxTraceBlocks = 1280;     // persistent traversal grid limit (spill buffers sized for it)
 
 // ---------------------------------------------------------------- scene
 
@@ -42,10 +44,13 @@ struct SceneDev {
     float4 *albedo;          // 1 per leaf, sorted order
     BvhNode *nodes;          // ntri - 1
     uint32_t *parent;        // 2 ntri - 1
-    uint32_t *keys, *keys_tmp, *ids, *ids_tmp;
+    uint64_t *keys, *keys_tmp;   // 63-bit Morton codes
+    uint32_t *ids, *ids_tmp;
     uint32_t *flags;         // ntri - 1 refit visit counters
-    uint32_t *hist;          // radix histograms
+    uint32_t *hist;          // radix histograms (digit-major) + 256 digit offsets
     float *bounds;           // 6 partial-bound slots per reduce block + 8 final
+    uint32_t *aux;           // 64 B: work counter of the scene-level traversal kernels
+    uint32_t *spill;         // traversal stack spill of the scene-level kernels
     int32_t sort_blocks;
     int32_t bound_blocks;
 };
@@ -91,13 +96,13 @@ struct ScratchLayout {
     size_t spill;
     size_t total;
     int64_t nchunks;
-    int64_t spill_threads;
 };
 
 constexpr int kChunk = 1024;   // pixels per compaction chunk (256 threads x 4)
 
-// counters[] slots in scratch
-enum : int { kCntMasked = 0, kCntRays = 1, kCntWork = 2, kCntSpill = 3 };
+// counters[] slots (u32) in scratch: [0] masked px, [1] rays, [2..3] u64 node
+// visits, [4..5] u64 triangle tests, [8] traversal work counter
+enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntWork = 8 };
 
 // ---------------------------------------------------------------- helpers
 
@@ -121,9 +126,9 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
-                          void *normal, int nfmt, hipStream_t st);
+                          void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,
-                             float *t, hipStream_t st);
+                             float *t, int blocks, hipStream_t st);
 
 // frame.hip
 // ev (nullable): DOF_NUM_STAGES + 1 events; pre records ev[0..7], post ev[8..13]

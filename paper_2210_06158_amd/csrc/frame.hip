@@ -493,8 +493,8 @@ __global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P
     if (threadIdx.x == 1023) {
         P.counters[kCntMasked] = pp[1023];
         P.counters[kCntRays] = pr[1023];
+        for (int k = kCntVisits; k < kCntVisits + 4; ++k) P.counters[k] = 0u;
         P.counters[kCntWork] = 0u;
-        P.counters[kCntSpill] = 0u;
         if (stats) {
             stats->masked_px = pp[1023];
             stats->rays = pr[1023];
@@ -922,8 +922,8 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
     DOF_REC(13);
     if (out.stats) {
         // copy the frame counters to the caller's stats record
-        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 2 * sizeof(uint32_t),
-                                      hipMemcpyDeviceToDevice, st);
+        // masked px, rays, node visits, triangle tests
+        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 24, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();

@@ -1,26 +1,30 @@
 // Ray traversal kernels.
 //
-//  k_trace     thin-lens rays for the masked pixels (3.2.2, after Cook's
-//              distributed ray tracing): persistent; each wave takes 64 ray
-//              indices at a time from a device counter until the frame's ray
-//              total (written by the compaction) is used up.
-//  k_gbuffer   all-in-focus pinhole rays, one per full-res pixel (the sharp
-//              raster image of section 3, produced by ray casting).
-//  k_trace_raw closest hit of arbitrary rays.
+// One persistent kernel template serves three ray sources:
+//  LensRays   thin-lens rays for the masked pixels (3.2.2, after Cook's
+//             distributed ray tracing), count read from the compaction;
+//  PinholeRays  all-in-focus rays, one per full-res pixel (the sharp raster
+//             image of section 3, produced by ray casting);
+//  RawRays    closest hit of caller-given rays.
 //
-// Closest hit: stack-based traversal of the binary radix tree (both child
-// boxes live in the parent node, so one 64-byte fetch tests two boxes),
-// watertight ray/triangle test of Woop, Benthin & Wald (JCGT 2013),
-// two-sided, t > 0; equal distances resolve to the smaller triangle id, so
-// the result is the same as brute force over all triangles.  The box test
-// is loosened by a relative margin so that rounding can never cull a box
-// holding the winning triangle.
+// Scheduling: each lane owns one ray at a time and advances it one BVH node
+// per loop iteration; when 16 or more lanes of a wave are idle (or all are),
+// the wave takes that many new ray indices from a device counter with one
+// atomic and hands them to its idle lanes, so long rays do not hold a whole
+// wave hostage (persistent threads with dynamic fetch).
+//
+// Closest hit: binary radix tree whose nodes carry both children's boxes
+// (one 64-byte fetch tests two boxes), near child first, far child pushed on
+// a per-lane stack (32 entries in LDS, the rest spilled to global memory, so
+// any depth is exact); watertight ray/triangle test of Woop, Benthin & Wald
+// (JCGT 2013), two-sided, t > 0, equal distances resolved to the smaller
+// triangle id -- the same answer as brute force over all triangles.  Box
+// tests are loosened by a relative margin so rounding never culls a box that
+// holds the winning triangle.
 #include "dof_internal.h"
 
 namespace dof {
 namespace {
-
-constexpr int kTB = 128;   // threads per traversal block; LDS stack = kTB * 64 * 4 B = 32 KB
 
 struct SceneArgs {
     int32_t ntri;
@@ -91,7 +95,7 @@ __device__ inline bool tri_hit(const WRay &r, float4 v0, float4 v1, float4 v2, f
     return true;
 }
 
-// Conservative slab test against [0, limit]; returns entry distance.
+// Conservative slab test against [0, limit]; returns the entry distance.
 __device__ inline bool box_hit(const WRay &r, float lx, float hx, float ly, float hy, float lz, float hz, float limit,
                                float &tenter)
 {
@@ -123,44 +127,6 @@ __device__ inline void consider_leaf(const SceneArgs &S, const WRay &r, uint32_t
             h.leaf = leaf;
         }
     }
-}
-
-// stack: this lane's column of the block's LDS stack (entry s at stack[s * kTB])
-__device__ inline Hit closest_hit(const SceneArgs &S, const WRay &r, uint32_t *stack)
-{
-    Hit h{INFINITY, ~0u, 0u};
-    if (S.ntri == 1) {
-        consider_leaf(S, r, 0u, h);
-        return h;
-    }
-    uint32_t node = 0;
-    int sp = 0;
-    while (true) {
-        const BvhNode nd = S.nodes[node];
-        // prune against the best hit so far, loosened by 2^-10 relative
-        float limit = h.t * 1.0009765625f;
-        float tl, tr;
-        bool hl = box_hit(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, limit, tl);
-        bool hr = box_hit(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, limit, tr);
-        const uint32_t L = nd.d.x, R = nd.d.y;
-        if (hl && (L & kLeaf)) { consider_leaf(S, r, L & ~kLeaf, h); hl = false; }
-        if (hr && (R & kLeaf)) { consider_leaf(S, r, R & ~kLeaf, h); hr = false; }
-        if (hl && hr) {
-            uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
-            stack[sp * kTB] = farc;
-            ++sp;
-            node = nearc;
-        } else if (hl) {
-            node = L;
-        } else if (hr) {
-            node = R;
-        } else {
-            if (sp == 0) break;
-            --sp;
-            node = stack[sp * kTB];
-        }
-    }
-    return h;
 }
 
 struct Shaded {
@@ -234,64 +200,6 @@ __device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h,
     for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
 }
 
-struct TraceOut {
-    const uint32_t *counters, *queue, *ray_base, *ray_pix;
-    const uint8_t *mask;
-    int32_t *ray_hit;
-    float *ray_t;
-    float4 *ray_col, *ray_pos;
-    uint32_t *work;
-};
-
-__global__ __launch_bounds__(kTB) void k_trace(SceneArgs S, FrameConst fc, TraceOut T)
-{
-    __shared__ uint32_t stack[kStackMax * kTB];
-    const int lane = threadIdx.x & 63;
-    const uint32_t R = T.counters[kCntRays];
-    while (true) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(T.work, 64u);
-        base = __shfl(base, 0);
-        if (base >= R) break;
-        const uint32_t r = base + lane;
-        if (r >= R) continue;
-        const uint32_t j = T.ray_pix[r];
-        const uint32_t q = T.queue[j];
-        const uint32_t k = r - T.ray_base[j];
-        const int x = (int)(q % (uint32_t)fc.hw), y = (int)(q / (uint32_t)fc.hw);
-        float fv[3], pf[3], o[3], dir[3];
-        pixel_dir(fc.cur, x, y, fc.hw, fc.hh, fv);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
-        float lx, ly;
-        lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) o[a] = fc.cur.pos[a] + fc.half_a * (lx * fc.cur.right[a] + ly * fc.cur.up[a]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dir[a] = pf[a] - o[a];
-        float len = sqrtf((dir[0] * dir[0] + dir[1] * dir[1]) + dir[2] * dir[2]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dir[a] = dir[a] / len;
-        WRay wr = make_wray(o, dir);
-        Hit h = closest_hit(S, wr, stack + threadIdx.x);
-        if (h.id != ~0u) {
-            float P0 = o[0] + h.t * dir[0], P1 = o[1] + h.t * dir[1], P2 = o[2] + h.t * dir[2];
-            float z = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
-                      (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
-            Shaded s = shade(S, fc.shade, h.leaf, dir);
-            T.ray_hit[r] = (int32_t)h.id;
-            T.ray_t[r] = h.t;
-            T.ray_col[r] = make_float4(s.r, s.g, s.b, z);
-            T.ray_pos[r] = make_float4(P0, P1, P2, 0.0f);
-        } else {
-            T.ray_hit[r] = -1;
-            T.ray_t[r] = INFINITY;
-            T.ray_col[r] = make_float4(fc.shade.sky[0], fc.shade.sky[1], fc.shade.sky[2], INFINITY);
-            T.ray_pos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
-    }
-}
-
 __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
 {
     if (fmt == DOF_RGBA32F) {
@@ -303,81 +211,268 @@ __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
     }
 }
 
-__global__ __launch_bounds__(kTB) void k_gbuffer(SceneArgs S, FrameConst fc, void *colour, int cfmt, float *depth,
-                                                 void *normal, int nfmt)
-{
-    __shared__ uint32_t stack[kStackMax * kTB];
-    const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
-    if (p >= (int64_t)fc.W * fc.H) return;
-    const int x = (int)(p % fc.W), y = (int)(p / fc.W);
-    float fv[3], d[3];
-    pixel_dir(fc.cur, x, y, fc.W, fc.H, fv);
-    float len = sqrtf((fv[0] * fv[0] + fv[1] * fv[1]) + fv[2] * fv[2]);
+// ---------------------------------------------------------------- ray sources
+
+struct LensRays {
+    FrameConst fc;
+    SceneShade shade;
+    const uint32_t *queue, *ray_base, *ray_pix;
+    int32_t *ray_hit;
+    float *ray_t;
+    float4 *ray_col, *ray_pos;
+
+    __device__ void setup(uint32_t r, float o[3], float d[3]) const
+    {
+        const uint32_t j = ray_pix[r];
+        const uint32_t q = queue[j];
+        const uint32_t k = r - ray_base[j];
+        const int x = (int)(q % (uint32_t)fc.hw), y = (int)(q / (uint32_t)fc.hw);
+        float fv[3], pf[3];
+        pixel_dir(fc.cur, x, y, fc.hw, fc.hh, fv);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] = fv[a] / len;
-    WRay wr = make_wray(fc.cur.pos, d);
-    Hit h = closest_hit(S, wr, stack + threadIdx.x);
-    if (h.id != ~0u) {
-        float P0 = fc.cur.pos[0] + h.t * d[0], P1 = fc.cur.pos[1] + h.t * d[1], P2 = fc.cur.pos[2] + h.t * d[2];
-        Shaded s = shade(S, fc.shade, h.leaf, d);
-        st_rgba(colour, cfmt, p, make_float4(s.r, s.g, s.b, 1.0f));
-        depth[p] = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
-                   (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
-        st_rgba(normal, nfmt, p, make_float4(s.n0, s.n1, s.n2, 0.0f));
-    } else {
-        st_rgba(colour, cfmt, p, make_float4(fc.shade.sky[0], fc.shade.sky[1], fc.shade.sky[2], 1.0f));
-        depth[p] = INFINITY;
-        st_rgba(normal, nfmt, p, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
+        float lx, ly;
+        lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[a] = fc.cur.pos[a] + fc.half_a * (lx * fc.cur.right[a] + ly * fc.cur.up[a]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = pf[a] - o[a];
+        float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = d[a] / len;
+    }
+
+    __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
+    {
+        if (h.id != ~0u) {
+            float P0 = o[0] + h.t * d[0], P1 = o[1] + h.t * d[1], P2 = o[2] + h.t * d[2];
+            float z = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
+                      (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
+            Shaded s = dof::shade(S, shade, h.leaf, d);
+            ray_hit[r] = (int32_t)h.id;
+            ray_t[r] = h.t;
+            ray_col[r] = make_float4(s.r, s.g, s.b, z);
+            ray_pos[r] = make_float4(P0, P1, P2, 0.0f);
+        } else {
+            ray_hit[r] = -1;
+            ray_t[r] = INFINITY;
+            ray_col[r] = make_float4(shade.sky[0], shade.sky[1], shade.sky[2], INFINITY);
+            ray_pos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+};
+
+struct PinholeRays {
+    FrameConst fc;
+    SceneShade shade;
+    void *colour;
+    int cfmt;
+    float *depth;
+    void *normal;
+    int nfmt;
+
+    __device__ void setup(uint32_t p, float o[3], float d[3]) const
+    {
+        const int x = (int)(p % (uint32_t)fc.W), y = (int)(p / (uint32_t)fc.W);
+        float fv[3];
+        pixel_dir(fc.cur, x, y, fc.W, fc.H, fv);
+        float len = sqrtf((fv[0] * fv[0] + fv[1] * fv[1]) + fv[2] * fv[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            d[a] = fv[a] / len;
+            o[a] = fc.cur.pos[a];
+        }
+    }
+
+    __device__ void finish(const SceneArgs &S, uint32_t p, const float o[3], const float d[3], const Hit &h) const
+    {
+        if (h.id != ~0u) {
+            float P0 = o[0] + h.t * d[0], P1 = o[1] + h.t * d[1], P2 = o[2] + h.t * d[2];
+            Shaded s = dof::shade(S, shade, h.leaf, d);
+            st_rgba(colour, cfmt, p, make_float4(s.r, s.g, s.b, 1.0f));
+            depth[p] = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
+                       (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
+            st_rgba(normal, nfmt, p, make_float4(s.n0, s.n1, s.n2, 0.0f));
+        } else {
+            st_rgba(colour, cfmt, p, make_float4(shade.sky[0], shade.sky[1], shade.sky[2], 1.0f));
+            depth[p] = INFINITY;
+            st_rgba(normal, nfmt, p, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+        }
+    }
+};
+
+struct RawRays {
+    const float *org, *dir;
+    int32_t *hit;
+    float *t;
+
+    __device__ void setup(uint32_t i, float o[3], float d[3]) const
+    {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = org[3 * (size_t)i + a];
+            d[a] = dir[3 * (size_t)i + a];
+        }
+    }
+
+    __device__ void finish(const SceneArgs &, uint32_t i, const float *, const float *, const Hit &h) const
+    {
+        hit[i] = h.id == ~0u ? -1 : (int32_t)h.id;
+        t[i] = h.t;
+    }
+};
+
+// ---------------------------------------------------------------- persistent traversal
+
+constexpr int kRefill = 16;   // refill when at least this many lanes are idle
+
+template <class Src>
+__global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
+                                                  uint32_t *work, uint32_t *spill, unsigned long long *stats)
+{
+    __shared__ uint32_t lds_stack[kStackLds * kTB];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t nthreads = gridDim.x * kTB;
+    const uint32_t gtid = blockIdx.x * kTB + tid;
+    const uint32_t N = count_ptr ? *count_ptr : count;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *stk = lds_stack + tid;
+
+    bool active = false, exhausted = false;
+    uint32_t item = 0, node = 0;
+    int sp = 0;
+    float o[3], d[3];
+    WRay wr;
+    Hit h;
+    uint32_t visits = 0, tests = 0;
+
+    while (true) {
+        const uint64_t idle = __ballot(!active && !exhausted);
+        const uint64_t live = __ballot(active);
+        if (idle != 0ull && (__popcll(idle) >= kRefill || live == 0ull)) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(work, (uint32_t)__popcll(idle));
+            base = __shfl(base, 0);
+            if (!active && !exhausted) {
+                item = base + (uint32_t)__popcll(idle & lt);
+                if (item < N) {
+                    src.setup(item, o, d);
+                    wr = make_wray(o, d);
+                    h = Hit{INFINITY, ~0u, 0u};
+                    node = 0;
+                    sp = 0;
+                    if (S.ntri == 1) {
+                        ++tests;
+                        consider_leaf(S, wr, 0u, h);
+                        src.finish(S, item, o, d, h);
+                    } else {
+                        active = true;
+                    }
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) {
+            if (__ballot(!exhausted) == 0ull) break;
+            continue;
+        }
+        if (active) {
+            const BvhNode nd = S.nodes[node];
+            ++visits;
+            const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
+            float tl, tr;
+            bool hl = box_hit(wr, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, limit, tl);
+            bool hr = box_hit(wr, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, limit, tr);
+            const uint32_t L = nd.d.x, R = nd.d.y;
+            if (hl && (L & kLeaf)) { ++tests; consider_leaf(S, wr, L & ~kLeaf, h); hl = false; }
+            if (hr && (R & kLeaf)) { ++tests; consider_leaf(S, wr, R & ~kLeaf, h); hr = false; }
+            if (hl && hr) {
+                const uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
+                if (sp < kStackLds) stk[sp * kTB] = farc;
+                else spill[(size_t)(sp - kStackLds) * nthreads + gtid] = farc;
+                ++sp;
+                node = nearc;
+            } else if (hl) {
+                node = L;
+            } else if (hr) {
+                node = R;
+            } else if (sp > 0) {
+                --sp;
+                node = sp < kStackLds ? stk[sp * kTB] : spill[(size_t)(sp - kStackLds) * nthreads + gtid];
+            } else {
+                src.finish(S, item, o, d, h);
+                active = false;
+            }
+        }
+    }
+    if (stats) {
+        unsigned long long v = visits, t = tests;
+        for (int off = 32; off >= 1; off >>= 1) {
+            v += __shfl_xor(v, off);
+            t += __shfl_xor(t, off);
+        }
+        if (lane == 0) {
+            atomicAdd(stats, v);
+            atomicAdd(stats + 1, t);
+        }
     }
 }
 
-__global__ __launch_bounds__(kTB) void k_trace_raw(SceneArgs S, int64_t n, const float *org, const float *dir,
-                                                   int32_t *hit, float *tout)
+__global__ void k_zero_u32(uint32_t *p, int n)
 {
-    __shared__ uint32_t stack[kStackMax * kTB];
-    const int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x;
-    if (i >= n) return;
-    float o[3] = {org[3 * i], org[3 * i + 1], org[3 * i + 2]};
-    float d[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
-    WRay wr = make_wray(o, d);
-    Hit h = closest_hit(S, wr, stack + threadIdx.x);
-    hit[i] = h.id == ~0u ? -1 : (int32_t)h.id;
-    tout[i] = h.t;
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
+
+int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks ? kMaxTraceBlocks : blocks); }
 
 }  // namespace
 
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, int blocks,
                         hipStream_t st)
 {
-    TraceOut T;
-    T.counters = reinterpret_cast<const uint32_t *>(scratch + L.counters);
-    T.work = reinterpret_cast<uint32_t *>(scratch + L.counters) + kCntWork;
-    T.queue = reinterpret_cast<const uint32_t *>(scratch + L.queue);
-    T.ray_base = reinterpret_cast<const uint32_t *>(scratch + L.ray_base);
-    T.ray_pix = reinterpret_cast<const uint32_t *>(scratch + L.ray_pix);
-    T.mask = nullptr;
-    T.ray_hit = reinterpret_cast<int32_t *>(scratch + L.ray_hit);
-    T.ray_t = reinterpret_cast<float *>(scratch + L.ray_t);
-    T.ray_col = reinterpret_cast<float4 *>(scratch + L.ray_col);
-    T.ray_pos = reinterpret_cast<float4 *>(scratch + L.ray_pos);
-    k_trace<<<blocks, kTB, 0, st>>>(scene_args(s), fc, T);
+    LensRays src;
+    src.fc = fc;
+    src.shade = fc.shade;
+    src.queue = reinterpret_cast<const uint32_t *>(scratch + L.queue);
+    src.ray_base = reinterpret_cast<const uint32_t *>(scratch + L.ray_base);
+    src.ray_pix = reinterpret_cast<const uint32_t *>(scratch + L.ray_pix);
+    src.ray_hit = reinterpret_cast<int32_t *>(scratch + L.ray_hit);
+    src.ray_t = reinterpret_cast<float *>(scratch + L.ray_t);
+    src.ray_col = reinterpret_cast<float4 *>(scratch + L.ray_col);
+    src.ray_pos = reinterpret_cast<float4 *>(scratch + L.ray_pos);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
+    k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(
+        scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork, reinterpret_cast<uint32_t *>(scratch + L.spill),
+        reinterpret_cast<unsigned long long *>(cnt + kCntVisits));
     return hipGetLastError();
 }
 
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth, void *normal,
-                          int nfmt, hipStream_t st)
+                          int nfmt, int blocks, hipStream_t st)
 {
-    int64_t n = (int64_t)fc.W * fc.H;
-    k_gbuffer<<<(unsigned)((n + kTB - 1) / kTB), kTB, 0, st>>>(scene_args(s), fc, colour, cfmt, depth, normal, nfmt);
+    PinholeRays src;
+    src.fc = fc;
+    src.shade = fc.shade;
+    src.colour = colour;
+    src.cfmt = cfmt;
+    src.depth = depth;
+    src.normal = normal;
+    src.nfmt = nfmt;
+    k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+    k_traverse<PinholeRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H),
+                                                                  nullptr, s.aux, s.spill, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit, float *t,
-                             hipStream_t st)
+                             int blocks, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    k_trace_raw<<<(unsigned)((n + kTB - 1) / kTB), kTB, 0, st>>>(scene_args(s), n, org, dir, hit, t);
+    RawRays src{org, dir, hit, t};
+    k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+    k_traverse<RawRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux, s.spill,
+                                                              nullptr);
     return hipGetLastError();
 }
 

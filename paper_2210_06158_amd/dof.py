@@ -53,7 +53,8 @@ class DofHistoryIO(C.Structure):
 
 
 class DofStats(C.Structure):
-    _fields_ = [("masked_px", C.c_uint32), ("rays", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+    _fields_ = [("masked_px", C.c_uint32), ("rays", C.c_uint32), ("node_visits", C.c_uint64),
+                ("tri_tests", C.c_uint64), ("reserved", C.c_uint32 * 2)]
 
 
 class DofFrameOut(C.Structure):
@@ -189,7 +190,7 @@ class Scene:
         v = DofBvhView()
         check(lib().dof_bvh_view_get(self.handle, C.byref(v)))
         n = self.ntri
-        return dict(keys=self._slice(v.keys, 4 * n, torch.int32), ids=self._slice(v.ids, 4 * n, torch.int32),
+        return dict(keys=self._slice(v.keys, 8 * n, torch.int64), ids=self._slice(v.ids, 4 * n, torch.int32),
                     parent=self._slice(v.parent, 4 * (2 * n - 1), torch.int32),
                     nodes=self._slice(v.nodes, 64 * max(n - 1, 1), torch.float32),
                     tris=self._slice(v.tris, 48 * n, torch.float32))

@@ -91,10 +91,10 @@ def test_bvh_bit_exact(env, orc):
     v = env["gs"].bvh_view()
     ob = env["osc"].bvh
     n = env["osc"].ntri
-    keys = v["keys"].cpu().numpy().view(np.uint32)
+    keys = v["keys"].cpu().numpy().view(np.uint64)
     ids = v["ids"].cpu().numpy().view(np.uint32)
-    assert np.array_equal(keys, (ob["keys"] >> np.uint64(32)).astype(np.uint32))
-    assert np.array_equal(ids, (ob["keys"] & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+    assert np.array_equal(keys, ob["keys"])
+    assert np.array_equal(ids, ob["ids"])
     nodes = v["nodes"].cpu().numpy().reshape(n - 1, 16)
     nu = nodes.view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
@@ -125,9 +125,9 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
     gs.build_bvh()
     torch.cuda.synchronize()
     view = gs.bvh_view()
-    keys = view["keys"].cpu().numpy().view(np.uint32)
+    keys = view["keys"].cpu().numpy().view(np.uint64)
     ids = view["ids"].cpu().numpy().view(np.uint32)
-    assert np.array_equal((keys.astype(np.uint64) << np.uint64(32)) | ids.astype(np.uint64), ob["keys"])
+    assert np.array_equal(keys, ob["keys"]) and np.array_equal(ids, ob["ids"])
     if n > 1:
         nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
         assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
@@ -138,6 +138,58 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
     d = (t - o).astype(np.float32)
     hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
     ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
+    assert np.array_equal(hg.cpu().numpy(), ho)
+    assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
+
+
+def caterpillar_scene():
+    """Triangles whose Morton codes are 0, 2^k (k = 0..62) and 2^63 - 1: the
+    radix tree is a chain about 63 deep.  Every triangle is huge and they all
+    overlap, so a ray enters both children at every level and the traversal
+    stack grows past its 32 LDS entries into the global spill area."""
+    S = float(2 ** 23)
+    cents = [(0.0, 0.0, 0.0), (2.0 ** 21, 2.0 ** 21, 2.0 ** 21)]
+    for k in range(63):
+        axis = 2 - (k % 3)                      # bit 3i+2 is x, 3i+1 y, 3i z
+        c = [0.0, 0.0, 0.0]
+        c[axis] = float(2 ** (k // 3))
+        cents.append(tuple(c))
+    tris = []
+    for cx, cy, cz in cents:
+        tris.append([cx - S, cy - S, cz - S, cx + S, cy - S, cz + S, cx, cy + S, cz])
+    v = np.array(tris, np.float32)
+    return synth.Scene(v, np.ones((v.shape[0], 3), np.float32))
+
+
+def test_deep_tree_stack_spill(env, orc):
+    torch, dof = env["torch"], env["dof"]
+    sc = caterpillar_scene()
+    osc = orc.OracleScene(sc)
+    ob = osc.build_bvh()
+    gs = dof.Scene(sc)
+    gs.build_bvh()
+    torch.cuda.synchronize()
+    view = gs.bvh_view()
+    assert np.array_equal(view["keys"].cpu().numpy().view(np.uint64), ob["keys"])
+    n = sc.ntri
+    nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
+    assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
+    # depth of the tree (> 32 LDS stack entries are needed)
+    depth, stack = 0, [(0, 0)]
+    while stack:
+        node, dd = stack.pop()
+        depth = max(depth, dd)
+        for c in (int(ob["left"][node]), int(ob["right"][node])):
+            if not c & LEAF:
+                stack.append((c, dd + 1))
+    assert depth > 40
+    rng = synth.SplitMix64(99)
+    nr = 4096
+    o = np.stack([rng.uniform(nr, -1e5, 1e5), rng.uniform(nr, -1e5, 1e5), np.full(nr, -3e7)], 1).astype(np.float32)
+    d = np.stack([rng.uniform(nr, -0.01, 0.01), rng.uniform(nr, -0.01, 0.01), np.ones(nr)], 1).astype(np.float32)
+    hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
+    assert (ho >= 0).mean() > 0.9
     assert np.array_equal(hg.cpu().numpy(), ho)
     assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
 

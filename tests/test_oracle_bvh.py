@@ -26,10 +26,12 @@ def test_morton_golden(orc):
     assert orc.morton(sc).tolist() == g["codes"]
 
 
-def _tree_checks(keys, left, right, parent, bounds, leaf_bounds, verts):
-    n = keys.size
-    ids = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    assert np.all(keys[1:] > keys[:-1])
+def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
+    """Checks of a binary radix tree over the 96-bit keys code << 32 | id."""
+    n = codes.size
+    keys = [(int(c) << 32) | int(i) for c, i in zip(codes, ids)]
+    ids = ids.astype(np.int64)
+    assert all(a < b for a, b in zip(keys, keys[1:]))
     assert sorted(ids.tolist()) == list(range(n))
     if n == 1:
         return
@@ -48,14 +50,14 @@ def _tree_checks(keys, left, right, parent, bounds, leaf_bounds, verts):
     while stack:
         node, f, l = stack.pop()
         assert node in (f, l)                        # one end carries the index
-        diff = int(keys[f]) ^ int(keys[l])
+        diff = keys[f] ^ keys[l]
         b = diff.bit_length() - 1
         lc, rc = int(left[node]), int(right[node])
         split = (lc & 0x7FFFFFFF) if lc & 0x80000000 else lc
-        ks = keys[f:l + 1].astype(object)
-        assert all(((int(k) >> b) & 1) == 0 for k in ks[:split - f + 1])
-        assert all(((int(k) >> b) & 1) == 1 for k in ks[split - f + 1:])
-        assert all((int(k) >> (b + 1)) == (int(keys[f]) >> (b + 1)) for k in ks)
+        ks = keys[f:l + 1]
+        assert all(((k >> b) & 1) == 0 for k in ks[:split - f + 1])
+        assert all(((k >> b) & 1) == 1 for k in ks[split - f + 1:])
+        assert all((k >> (b + 1)) == (keys[f] >> (b + 1)) for k in ks)
         if rc & 0x80000000:
             assert (rc & 0x7FFFFFFF) == split + 1 == l
         else:
@@ -86,9 +88,8 @@ def test_radix_tree_properties(orc, n):
     sc = orc.OracleScene(synth.Scene(v, a))
     b = sc.build_bvh()
     codes = orc.morton(sc)
-    ids = (b["keys"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    assert np.array_equal((b["keys"] >> np.uint64(32)).astype(np.uint32), codes[ids])
-    _tree_checks(b["keys"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
+    assert np.array_equal(b["keys"], codes[b["ids"]])
+    _tree_checks(b["keys"], b["ids"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
                  b["leaf_bounds"], v)
 
 
@@ -100,7 +101,7 @@ def test_radix_tree_duplicate_codes(orc):
     sc = orc.OracleScene(synth.Scene(v, a))
     b = sc.build_bvh()
     n = v.shape[0]
-    _tree_checks(b["keys"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
+    _tree_checks(b["keys"], b["ids"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
                  b["leaf_bounds"], v)
 
 
