@@ -27,6 +27,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
+# Floating-point operations of the traversal, counted from the kernel source:
+# one node visit = two slab tests (6 sub, 6 mul, 12 min/max/compare-class ops
+# and 2 for the 2^-20 exit margin each) plus the prune limit; one
+# triangle test = the watertight test (edge functions, determinant, distance).
+FLOP_PER_VISIT = 53
+FLOP_PER_TRI_TEST = 55
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_1080p.txt")
+TRACE_SOURCE = os.path.join(ROOT, "paper_2210_06158_amd", "csrc", "trace.hip")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -37,6 +46,10 @@ def parse():
     ap.add_argument("--stage-frames", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--trace-blocks", type=int, default=0, help="persistent traversal blocks (0 = library default)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
+                         "known traffic for hardware byte counters)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -64,6 +77,23 @@ def stage_bytes(stage, W, H, P, R):
         "composite": F * (8 + 4) + h * (16 + 16 + 16 + 16) + F * 8,
     }
     return table[stage]
+
+
+def measured_traffic():
+    """HBM bytes per traversal launch from the committed rocprofv3 counter
+    summary, scaled by its copy-kernel calibration; None when the traversal
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split("=", 1) for l in open(TRAFFIC_FILE).read().split("\n") if "=" in l and not l.startswith("#"))
+        sha = hashlib.sha256(open(TRACE_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("trace_source_sha256", "").strip() != sha:
+        return None
+    fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
+    write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
+    return int(fetch + write)
 
 
 def main():
@@ -103,7 +133,7 @@ def main():
     gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in cams]
     torch.cuda.synchronize()
     hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
-    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F)
+    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=args.trace_blocks)
 
     def step(i, frame):
         f = i % nfr
@@ -142,10 +172,12 @@ def main():
     log(f"timed {K} frames: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
 
     # live per-stage timing (same workload, HIP events around every stage)
-    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True)
+    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True, trace_blocks=args.trace_blocks)
     sums = {s: 0.0 for s in dof.STAGES}
     t_rays = 0
     t_masked = 0
+    t_visits = 0
+    t_tests = 0
     nst = min(args.stage_frames, K)
     for k in range(nst):
         step(args.warmup + k, frt)
@@ -155,15 +187,37 @@ def main():
         sv = frt.stats.cpu().numpy()
         t_masked += int(sv[0])
         t_rays += int(sv[1])
+        t_visits += int(sv.view(np.int64)[1])
+        t_tests += int(sv.view(np.int64)[2])
     stage_ms = {s: v / nst for s, v in sums.items()}
     dom = max(stage_ms, key=stage_ms.get)
     P_avg, R_avg = t_masked / nst, t_rays / nst
-    dom_bytes = stage_bytes(dom, W, H, P_avg, R_avg)
-    achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "bytes_per_launch": int(dom_bytes), "ms_per_launch": round(stage_ms[dom], 5)}
+    if dom == "trace":
+        # pointer chasing that executes on the vector ALUs: its roofline is
+        # the FP32 vector peak, with FLOPs from the measured visit/test counts
+        flops = (FLOP_PER_VISIT * t_visits + FLOP_PER_TRI_TEST * t_tests) / nst
+        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+        roofline = {"kernel": "trace (k_traverse<LensRays>)", "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5),
+                    "traffic": measured_traffic(), "flop_per_launch": int(flops),
+                    "ms_per_launch": round(stage_ms[dom], 5),
+                    "compulsory_bytes_per_launch": int(stage_bytes(dom, W, H, P_avg, R_avg))}
+    else:
+        dom_bytes = stage_bytes(dom, W, H, P_avg, R_avg)
+        achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                    "bytes_per_launch": int(dom_bytes), "ms_per_launch": round(stage_ms[dom], 5)}
     trace_grays = (t_rays / (sums["trace"] * 1e-3) / 1e9) if sums["trace"] > 0 else None
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -82,8 +82,9 @@ typedef struct {
  * lod_scale, lod_max: eq. (8).  depth_range: main-filter depth range (0.1 =
  * 10 cm, 4.2).  r_max: largest gather radius in half-res pixels.  tile:
  * neighbourhood-max tile side (16 only).  l_spec: luma of a "high specular"
- * tap (3.1.2).  trace_blocks: blocks of the persistent traversal kernel (0 =
- * 5 per compute unit).  timing: see dof_stage_times. */
+ * tap (3.1.2).  trace_blocks: blocks of 128 threads of the persistent
+ * traversal kernel, at most 2560 (0 = 5 per compute unit).  timing: see
+ * dof_stage_times. */
 typedef struct {
     uint32_t struct_size;   /* = sizeof(dof_params) */
     int32_t m;
@@ -175,7 +176,7 @@ const char *dof_last_error(void);
 void dof_default_params(dof_params *p);
 
 /* Scene arena size for ntri triangles (triangles, BVH, build scratch and a
- * traversal stack spill area of about 40 MB). */
+ * traversal stack spill area of 84 MB). */
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);
 
 /* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes) on

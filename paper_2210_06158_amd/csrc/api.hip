@@ -48,7 +48,7 @@ struct SceneLayout {
     int sort_blocks, bound_blocks;
 };
 
-constexpr size_t kSpillBytes = sizeof(uint32_t) * dof::kSpillPerThread * dof::kTB * (size_t)dof::kMaxTraceBlocks;
+constexpr size_t kSpillBytes = sizeof(uint32_t) * (size_t)dof::kSpillPerThread * dof::kTB * (size_t)dof::kMaxTraceBlocks;
 
 SceneLayout scene_layout(int64_t n)
 {
@@ -299,10 +299,14 @@ bool same_view(const dof_camera &a, const dof_camera &b, const dof_lens &la, con
 
 int default_trace_blocks()
 {
-    int dev = 0, cus = 0;
+    // as many 128-thread blocks as fit on the device at once (registers and
+    // the LDS stack decide), capped by the spill-buffer size
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
-    const int b = cus * 5;
+    per_cu = dof::trace_blocks_per_cu();
+    if (per_cu <= 0) per_cu = 5;
+    const int b = cus * per_cu;
     return b > dof::kMaxTraceBlocks ? dof::kMaxTraceBlocks : b;
 }
 

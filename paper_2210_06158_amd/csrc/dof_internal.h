@@ -17,11 +17,13 @@ constexpr float kSqrt2 = 1.41421356237f;  // one pixel diagonal (3.1.1, 3.3)
 constexpr int kTile = 16;                 // neighbourhood-max tile side
 constexpr int kRingTaps = 81;             // 1 + 8 + 16 + 24 + 32 (3.1.1)
 constexpr int kMaxBlades = 16;
+// The binary tree over 95 significant key bits is at most 95 deep, and the
+// traversal pushes at most one entry (node, entry distance) per level.
 constexpr int kStackLds = 32;             // traversal stack entries kept in LDS
-constexpr int kStackMax = 96;             // a tree over 95 significant key bits is at most 95 deep
+constexpr int kStackMax = 96;
 constexpr int kSpillPerThread = kStackMax - kStackLds;   // entries beyond LDS live in global memory
 constexpr int kTB = 128;                  // threads per traversal block
-constexpr int kMaxTraceBlocks = 1280;     // persistent traversal grid limit (spill buffers sized for it)
+constexpr int kMaxTraceBlocks = 4096;     // persistent traversal grid limit (spill buffers sized for it)
 
 // ---------------------------------------------------------------- scene
 
@@ -123,6 +125,7 @@ __device__ inline float coc_px(float cock, float d, float z) { return cock * fab
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 
 // trace.hip
+int trace_blocks_per_cu();   // resident blocks of the lens-ray traversal per CU
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,

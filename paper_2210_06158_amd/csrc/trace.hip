@@ -16,7 +16,10 @@
 // Closest hit: binary radix tree whose nodes carry both children's boxes
 // (one 64-byte fetch tests two boxes), near child first, far child pushed on
 // a per-lane stack (32 entries in LDS, the rest spilled to global memory, so
-// any depth is exact); watertight ray/triangle test of Woop, Benthin & Wald
+// any depth is exact); leaf hits wait in a 4-entry per-lane queue and the
+// triangle test runs when at least 32 lanes of the wave have one (or a queue
+// is nearly full, or a lane has finished its traversal), so it executes with
+// most lanes active instead of once per node visit for a few lanes; watertight ray/triangle test of Woop, Benthin & Wald
 // (JCGT 2013), two-sided, t > 0, equal distances resolved to the smaller
 // triangle id -- the same answer as brute force over all triangles.  Box
 // tests are loosened by a relative margin so rounding never culls a box that
@@ -96,17 +99,20 @@ __device__ inline bool tri_hit(const WRay &r, float4 v0, float4 v1, float4 v2, f
 }
 
 // Conservative slab test against [0, limit]; returns the entry distance.
+// It only culls, so it may use the hardware min/max (no NaN can arise: the
+// reciprocals are finite); the exit distance is enlarged by 2^-20 relative
+// to cover rounding.
 __device__ inline bool box_hit(const WRay &r, float lx, float hx, float ly, float hy, float lz, float hz, float limit,
                                float &tenter)
 {
     float t0x = (lx - r.o0) * r.ix, t1x = (hx - r.o0) * r.ix;
     float t0y = (ly - r.o1) * r.iy, t1y = (hy - r.o1) * r.iy;
     float t0z = (lz - r.o2) * r.iz, t1z = (hz - r.o2) * r.iz;
-    float tn = fmax_cs(fmax_cs(fmin_cs(t0x, t1x), fmin_cs(t0y, t1y)), fmin_cs(t0z, t1z));
-    float tf = fmin_cs(fmin_cs(fmax_cs(t0x, t1x), fmax_cs(t0y, t1y)), fmax_cs(t0z, t1z));
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.00000095367431640625f;
     tenter = tn;
-    float slack = (fabsf(tn) + fabsf(tf)) * 9.5367431640625e-7f;   // 2^-20
-    return tn <= tf + slack && tf >= -slack && tn <= limit;
+    // tn <= tf, tf >= 0 and tn <= limit (limit >= 0) in one comparison
+    return fmaxf(tn, 0.0f) <= fminf(tf, limit);
 }
 
 struct Hit {
@@ -325,6 +331,7 @@ struct RawRays {
 // ---------------------------------------------------------------- persistent traversal
 
 constexpr int kRefill = 16;   // refill when at least this many lanes are idle
+constexpr int kLeafBatch = 32;   // run triangle tests when at least this many lanes have one pending
 
 template <class Src>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
@@ -345,6 +352,10 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     WRay wr;
     Hit h;
     uint32_t visits = 0, tests = 0;
+    // pending leaf hits of this lane (tested when enough lanes have some)
+    uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+    int nq = 0;
+    bool trav = false;   // the lane still has an inner node to visit
 
     while (true) {
         const uint64_t idle = __ballot(!active && !exhausted);
@@ -361,12 +372,14 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     h = Hit{INFINITY, ~0u, 0u};
                     node = 0;
                     sp = 0;
+                    nq = 0;
+                    active = true;
                     if (S.ntri == 1) {
-                        ++tests;
-                        consider_leaf(S, wr, 0u, h);
-                        src.finish(S, item, o, d, h);
+                        trav = false;
+                        q0 = 0u;
+                        nq = 1;
                     } else {
-                        active = true;
+                        trav = true;
                     }
                 } else {
                     exhausted = true;
@@ -377,7 +390,18 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             if (__ballot(!exhausted) == 0ull) break;
             continue;
         }
-        if (active) {
+        // triangle tests, batched across the wave
+        const bool want = active && nq > 0;
+        const bool must = want && (nq >= 3 || !trav);
+        if (__ballot(must) != 0ull || __popcll(__ballot(want)) >= kLeafBatch) {
+            if (want) {
+                ++tests;
+                consider_leaf(S, wr, q0, h);
+                q0 = q1; q1 = q2; q2 = q3;
+                --nq;
+            }
+        }
+        if (active && trav && nq <= 2) {
             const BvhNode nd = S.nodes[node];
             ++visits;
             const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
@@ -385,8 +409,18 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             bool hl = box_hit(wr, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, limit, tl);
             bool hr = box_hit(wr, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, limit, tr);
             const uint32_t L = nd.d.x, R = nd.d.y;
-            if (hl && (L & kLeaf)) { ++tests; consider_leaf(S, wr, L & ~kLeaf, h); hl = false; }
-            if (hr && (R & kLeaf)) { ++tests; consider_leaf(S, wr, R & ~kLeaf, h); hr = false; }
+            if (hl && (L & kLeaf)) {
+                const uint32_t v = L & ~kLeaf;
+                if (nq == 0) q0 = v; else if (nq == 1) q1 = v; else if (nq == 2) q2 = v; else q3 = v;
+                ++nq;
+                hl = false;
+            }
+            if (hr && (R & kLeaf)) {
+                const uint32_t v = R & ~kLeaf;
+                if (nq == 0) q0 = v; else if (nq == 1) q1 = v; else if (nq == 2) q2 = v; else q3 = v;
+                ++nq;
+                hr = false;
+            }
             if (hl && hr) {
                 const uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
                 if (sp < kStackLds) stk[sp * kTB] = farc;
@@ -401,9 +435,12 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                 --sp;
                 node = sp < kStackLds ? stk[sp * kTB] : spill[(size_t)(sp - kStackLds) * nthreads + gtid];
             } else {
-                src.finish(S, item, o, d, h);
-                active = false;
+                trav = false;
             }
+        }
+        if (active && !trav && nq == 0) {
+            src.finish(S, item, o, d, h);
+            active = false;
         }
     }
     if (stats) {
@@ -427,6 +464,13 @@ __global__ void k_zero_u32(uint32_t *p, int n)
 int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks ? kMaxTraceBlocks : blocks); }
 
 }  // namespace
+
+int trace_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<LensRays>, kTB, 0) != hipSuccess) return 0;
+    return n;
+}
 
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, int blocks,
                         hipStream_t st)
