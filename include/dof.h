@@ -81,10 +81,10 @@ typedef struct {
  * when the camera moved.  var_recon_w, b_max: eq. (5).  h_edge: eq. (7).
  * lod_scale, lod_max: eq. (8).  depth_range: main-filter depth range (0.1 =
  * 10 cm, 4.2).  r_max: largest gather radius in half-res pixels.  tile:
- * neighbourhood-max tile side (16 only).  l_spec: luma of a "high specular"
- * tap (3.1.2).  trace_blocks: blocks of 128 threads of the persistent
- * traversal kernel, at most 2560 (0 = 5 per compute unit).  timing: see
- * dof_stage_times. */
+ * neighbourhood-max tile side (16 only).  l_spec: luma above which a gather
+ * tap counts as a bright, specular sample (3.1.2).  trace_blocks: blocks of
+ * 128 threads of the persistent traversal kernel, at most 4096 (0 = as many
+ * as are resident at once).  timing: see dof_stage_times. */
 typedef struct {
     uint32_t struct_size;   /* = sizeof(dof_params) */
     int32_t m;

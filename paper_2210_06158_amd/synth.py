@@ -97,7 +97,7 @@ class Params:
     depth_range: float = 0.1    # main-filter depth range, 10 cm (4.2)
     r_max: float = 32.0         # largest gather radius in half-res pixels
     tile: int = 16              # tile side for the neighbourhood max CoC
-    l_spec: float = 1.0         # luma threshold of a "high specular" tap
+    l_spec: float = 1.0         # luma above which a tap counts as a bright (specular) sample
     mask_mode: int = MASK_ADAPTIVE
 
 
