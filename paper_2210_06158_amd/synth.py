@@ -308,6 +308,64 @@ def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
     return scene, cams, lens, Params(m=8)
 
 
+def scene_4k(seed: int = BASE_SEED + 3000, n_boxes: int = 130000, n_links: int = 200000) -> tuple:
+    """3840x2160 workload: a random-height box city (130k boxes, 1.56M
+    triangles, heights 2-40, footprints 2-6) on both sides of a 20 m wide
+    street, seen through a chain-link fence of 200k thin quads (400k
+    triangles; 5 cm diamonds, 3 mm wire) at depth 1-2; static camera,
+    6-blade aperture, N = 2, f = 50 mm, focus pulled linearly from 3 to 40
+    over 60 frames; 16 rays per masked pixel.  Returns (scene, cameras(60),
+    lenses(60), params)."""
+    rng = SplitMix64(seed)
+    base = Lens(focal=0.050, fnum=2.0, focus=3.0, sensor=0.036, blades=6, blade_rot=0.0)
+    nb = n_boxes
+    z = rng.uniform(nb, 5.0, 800.0)
+    side = np.where(rng.uniform(nb) < 0.5, -1.0, 1.0)
+    x = side * rng.uniform(nb, 10.0, 800.0)
+    fw = rng.uniform(nb, 2.0, 6.0)
+    fd = rng.uniform(nb, 2.0, 6.0)
+    h = rng.uniform(nb, 2.0, 40.0)
+    lo = np.stack([x - fw / 2, np.zeros(nb), z - fd / 2], 1)
+    hi = np.stack([x + fw / 2, h, z + fd / 2], 1)
+    city = boxes(lo, hi)
+    calb = np.repeat(rng.uniform(nb * 3, 0.2, 0.9).reshape(nb, 3), 12, axis=0)
+    ground = quad((-900, 0, -10), (-900, 0, 900), (900, 0, 900), (900, 0, -10))
+    galb = np.array([[0.35, 0.35, 0.38]] * 2)
+    # fence: each diamond cell contributes one wire per diagonal, each wire a
+    # quad 3 mm wide; gently wavy in depth between 1 and 2
+    nl = n_links
+    cols = 500
+    k = np.arange(nl)
+    diag = k % 2
+    cell = k // 2
+    ci = cell % cols
+    cj = cell // cols
+    pitch = 0.05
+    cx = -12.5 + (ci + 0.5) * pitch
+    cy = (cj + 0.5) * pitch
+    cz = 1.5 + 0.45 * np.sin(cx * 0.9) + rng.uniform(nl, -0.005, 0.005)
+    dx = 0.5 * pitch * np.where(diag == 0, 1.0, -1.0)
+    dy = 0.5 * pitch
+    p0 = np.stack([cx - dx, cy - dy, cz], 1)
+    p1 = np.stack([cx + dx, cy + dy, cz], 1)
+    nrm = np.stack([-dy * np.ones(nl), dx, np.zeros(nl)], 1)
+    nrm = nrm / np.linalg.norm(nrm, axis=1, keepdims=True) * 0.0015
+    a0, a1, b1, b0 = p0 - nrm, p1 - nrm, p1 + nrm, p0 + nrm
+    t1 = np.concatenate([a0, a1, b1], 1)
+    t2 = np.concatenate([a0, b1, b0], 1)
+    fence = np.stack([t1, t2], 1).reshape(-1, 9).astype(np.float32)
+    falb = np.tile(np.array([[0.75, 0.75, 0.72]]), (2 * nl, 1))
+    verts = np.concatenate([ground, city, fence]).astype(np.float32)
+    albedo = np.concatenate([galb, calb, falb]).astype(np.float32)
+    scene = Scene(verts, albedo, light_dir=f32tuple(_normalize((0.4, -1.0, 0.3))))
+    cam = look_camera((0.0, 1.6, 0.0), 0.0, math.radians(3.0), 3840, 2160, frame=0, seed=seed & 0xFFFFFFFF)
+    cams, lenses = [], []
+    for fi in range(60):
+        cams.append(dataclasses.replace(cam, frame=fi))
+        lenses.append(dataclasses.replace(base, focus=float(np.float32(3.0 + 37.0 * fi / 59.0))))
+    return scene, cams, lenses, Params(m=16)
+
+
 def camera_spline(rng: SplitMix64, nframes: int, width: int, height: int,
                   seed: int) -> list:
     """Catmull-Rom path through 8 seeded control points at eye height
