@@ -34,7 +34,10 @@ FP32_PEAK_TFLOPS = 157.3
 FLOP_PER_VISIT = 53
 FLOP_PER_TRI_TEST = 55
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_1080p.txt")
-TRACE_SOURCE = os.path.join(ROOT, "paper_2210_06158_amd", "csrc", "trace.hip")
+# what the traversal's memory traffic depends on: its kernel, the tree the
+# build produces, and the scene generator
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2210_06158_amd", *p) for p in
+                   (("csrc", "trace.hip"), ("csrc", "bvh.hip"), ("synth.py",))]
 
 
 def parse():
@@ -81,15 +84,19 @@ def stage_bytes(stage, W, H, P, R):
 
 def measured_traffic():
     """HBM bytes per traversal launch from the committed rocprofv3 counter
-    summary, scaled by its copy-kernel calibration; None when the traversal
-    source has changed since the counters were taken."""
+    summary, scaled by its copy-kernel calibration; None when the traversal,
+    the BVH build or the scene generator has changed since the counters were
+    taken."""
     import hashlib
     try:
         kv = dict(l.split("=", 1) for l in open(TRAFFIC_FILE).read().split("\n") if "=" in l and not l.startswith("#"))
-        sha = hashlib.sha256(open(TRACE_SOURCE, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for path in TRAFFIC_SOURCES:
+            h.update(open(path, "rb").read())
+        sha = h.hexdigest()
     except OSError:
         return None
-    if kv.get("trace_source_sha256", "").strip() != sha:
+    if kv.get("source_sha256", "").strip() != sha:
         return None
     fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
     write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024

@@ -149,9 +149,11 @@ typedef struct {
 typedef struct dof_scene dof_scene;
 
 /* Device views of the acceleration structure (for inspection and tests).
- * keys: sorted 63-bit Morton codes (21 bits per axis of the triangle box
- * centre over the centre bounds, x at bit 3i+2, y 3i+1, z 3i), ties in id
- * order; ids: triangle ids in the same order;
+ * keys: sorted 64-bit keys, ties in id order: bits 0-62 are the Morton code
+ * of the triangle box centre on cubic cells (one scale, 2^21 over the
+ * largest extent of the centre bounds; 21 bits per axis, x at bit 3i+2,
+ * y 3i+1, z 3i), bit 63 is set for a triangle whose box diagonal exceeds a
+ * quarter of the centre bounds' diagonal; ids: triangle ids in that order;
  * nodes: ntri-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
  * float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z, R.lo.z,
  * R.hi.z), uint4 (left, right, 0, 0)}, child bit 31 = leaf (sorted index);

@@ -189,14 +189,24 @@ static uint64_t spread21(uint32_t x)
     return r;
 }
 
-/* 63-bit Morton code (21 bits per axis, x at bit 3i+2, y at 3i+1, z at 3i)
- * of each triangle's box centre, quantised over the bounds of all centres. */
+/* LBVH key of each triangle: a 63-bit Morton code (21 bits per axis, x at
+ * bit 3i+2, y at 3i+1, z at 3i) of its box centre, quantised on cubic cells
+ * (one scale 2^21 / largest extent of the centre bounds, for all axes), and
+ * bit 63 set for a large triangle: one whose box diagonal exceeds a quarter
+ * of the diagonal of the centre bounds (compared squared).  The flag puts
+ * the few scene-sized triangles (ground planes) under one child of the root
+ * instead of inflating every box on their path. */
 int orc_morton(const orc_scene *s, uint64_t *codes)
 {
     if (!s || s->ntri <= 0 || !codes) return -1;
     int n = s->ntri;
     float *cen = (float *)malloc(sizeof(float) * 3 * (size_t)n);
-    if (!cen) return -2;
+    float *diag2 = (float *)malloc(sizeof(float) * (size_t)n);
+    if (!cen || !diag2) {
+        free(cen);
+        free(diag2);
+        return -2;
+    }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < n; i++) {
         float bl[3], bh[3];
@@ -207,22 +217,27 @@ int orc_morton(const orc_scene *s, uint64_t *codes)
             lo[a] = c < lo[a] ? c : lo[a];
             hi[a] = c > hi[a] ? c : hi[a];
         }
+        float dx = bh[0] - bl[0], dy = bh[1] - bl[1], dz = bh[2] - bl[2];
+        diag2[i] = (dx * dx + dy * dy) + dz * dz;
     }
-    float inv[3];
-    for (int a = 0; a < 3; a++) {
-        float ext = hi[a] - lo[a];
-        inv[a] = ext > 0.0f ? 2097152.0f / ext : 0.0f;
-    }
+    float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+    float e = ext[0];
+    e = ext[1] > e ? ext[1] : e;
+    e = ext[2] > e ? ext[2] : e;
+    float inv = e > 0.0f ? 2097152.0f / e : 0.0f;
+    float large = ((ext[0] * ext[0] + ext[1] * ext[1]) + ext[2] * ext[2]) * 0.0625f;
     for (int i = 0; i < n; i++) {
         uint32_t qv[3];
         for (int a = 0; a < 3; a++) {
-            float t = floorf((cen[3 * (size_t)i + a] - lo[a]) * inv[a]);
+            float t = floorf((cen[3 * (size_t)i + a] - lo[a]) * inv);
             int qi = (int)t;
             qv[a] = (uint32_t)(qi > 2097151 ? 2097151 : qi);
         }
-        codes[i] = (spread21(qv[0]) << 2) | (spread21(qv[1]) << 1) | spread21(qv[2]);
+        uint64_t flag = diag2[i] > large ? 1u : 0u;
+        codes[i] = (flag << 63) | (spread21(qv[0]) << 2) | (spread21(qv[1]) << 1) | spread21(qv[2]);
     }
     free(cen);
+    free(diag2);
     return 0;
 }
 

@@ -54,11 +54,12 @@ typedef struct {
     float light_dir[3], light_rad[3], ambient[3], sky[3];
 } orc_scene;
 
-/* Binary radix tree over 96-bit keys (63-bit Morton code, then triangle
- * id), Karras numbering.  All arrays are caller-allocated. */
+/* Binary radix tree over 96-bit keys (the 64-bit key of orc_morton -- a
+ * large-triangle flag over a 63-bit Morton code -- then the triangle id),
+ * Karras numbering.  All arrays are caller-allocated. */
 typedef struct {
     int32_t ntri;
-    uint64_t *keys;         /* ntri Morton codes, ascending with ids */
+    uint64_t *keys;         /* ntri 64-bit keys, ascending with ids */
     uint32_t *ids;          /* ntri triangle ids in leaf order */
     uint32_t *left, *right; /* ntri-1 each; bit 31 set = leaf (sorted index) */
     uint32_t *parent;       /* 2*ntri-1: internal nodes then leaves; root = ~0u */

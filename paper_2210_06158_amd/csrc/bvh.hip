@@ -1,7 +1,8 @@
 // LBVH build on the device: the acceleration structure that replaces the
 // DXR build the paper times inside its Ray Trace pass (section 5.2).
 //
-//   centroid bounds -> 63-bit Morton keys (21 bits per axis) -> stable LSD
+//   centroid bounds -> 64-bit keys (a large-triangle flag in bit 63 over a
+//   63-bit Morton code, 21 bits per axis, of cubic cells) -> stable LSD
 //   radix sort of (key, id) -> binary radix tree over the 96-bit keys
 //   key << 32 | id (Karras 2012) -> triangles reordered to leaf order ->
 //   bottom-up refit of the child boxes stored in each node.
@@ -79,7 +80,10 @@ __global__ __launch_bounds__(kThreads) void k_centroid_bounds(const float *__res
     }
 }
 
-// Reduce the partial bounds; final slot = lo[3], inv[3] with inv = 2^21 / extent.
+// Reduce the partial bounds.  Final slot: lo[3], then one scale for all three
+// axes, inv = 2^21 / (largest extent), so Morton cells are cubes, then the
+// squared-diagonal threshold above which a triangle counts as large
+// (a quarter of the centre bounds' diagonal, squared).
 __global__ __launch_bounds__(256) void k_bounds_final(float *__restrict__ partial, int nblocks)
 {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -95,14 +99,23 @@ __global__ __launch_bounds__(256) void k_bounds_final(float *__restrict__ partia
         if (lane == 0) { red[a][w] = m; red[3 + a][w] = M; }
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-        const int a = threadIdx.x;
-        float l = red[a][0], h = red[3 + a][0];
-        for (int k = 1; k < 4; ++k) { l = fmin_cs(l, red[a][k]); h = fmax_cs(h, red[3 + a][k]); }
+    if (threadIdx.x == 0) {
+        float l[3], ext[3];
+        for (int a = 0; a < 3; ++a) {
+            float lv = red[a][0], hv = red[3 + a][0];
+            for (int k = 1; k < 4; ++k) { lv = fmin_cs(lv, red[a][k]); hv = fmax_cs(hv, red[3 + a][k]); }
+            l[a] = lv;
+            ext[a] = hv - lv;
+        }
+        const float e = fmax_cs(fmax_cs(ext[0], ext[1]), ext[2]);
+        const float s2 = (ext[0] * ext[0] + ext[1] * ext[1]) + ext[2] * ext[2];
         float *out = partial + 6 * (size_t)nblocks;
-        float ext = h - l;
-        out[a] = l;
-        out[3 + a] = ext > 0.0f ? 2097152.0f / ext : 0.0f;
+        out[0] = l[0];
+        out[1] = l[1];
+        out[2] = l[2];
+        out[3] = e > 0.0f ? 2097152.0f / e : 0.0f;
+        out[4] = s2 * 0.0625f;
+        out[5] = 0.0f;
     }
 }
 
@@ -132,11 +145,13 @@ __global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ v
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float c = (bl[a] + bh[a]) * 0.5f;
-        float t = floorf((c - fin[a]) * fin[3 + a]);
+        float t = floorf((c - fin[a]) * fin[3]);
         int qi = (int)t;
         q[a] = (uint32_t)(qi > 2097151 ? 2097151 : qi);
     }
-    keys[i] = (spread_bits21(q[0]) << 2) | (spread_bits21(q[1]) << 1) | spread_bits21(q[2]);
+    const float dx = bh[0] - bl[0], dy = bh[1] - bl[1], dz = bh[2] - bl[2];
+    const uint64_t large = ((dx * dx + dy * dy) + dz * dz) > fin[4] ? 1ull : 0ull;
+    keys[i] = (large << 63) | (spread_bits21(q[0]) << 2) | (spread_bits21(q[1]) << 1) | spread_bits21(q[2]);
     ids[i] = (uint32_t)i;
 }
 

@@ -24,6 +24,10 @@ def test_morton_golden(orc):
     verts = np.tile(pts, (1, 3))
     sc = orc.OracleScene(synth.Scene(verts, np.ones((len(pts), 3), np.float32)))
     assert orc.morton(sc).tolist() == g["codes"]
+    # cubic cells and the large-triangle flag
+    tv = np.array(g["triangles"], np.float32)
+    sc = orc.OracleScene(synth.Scene(tv, np.ones((len(tv), 3), np.float32)))
+    assert orc.morton(sc).tolist() == g["triangle_codes"]
 
 
 def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
