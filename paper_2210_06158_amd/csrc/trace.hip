@@ -15,15 +15,19 @@
 //
 // Closest hit: binary radix tree whose nodes carry both children's boxes
 // (one 64-byte fetch tests two boxes), near child first, far child pushed on
-// a per-lane stack (32 entries in LDS, the rest spilled to global memory, so
-// any depth is exact); leaf hits wait in a 4-entry per-lane queue and the
-// triangle test runs when at least 32 lanes of the wave have one (or a queue
-// is nearly full, or a lane has finished its traversal), so it executes with
-// most lanes active instead of once per node visit for a few lanes; watertight ray/triangle test of Woop, Benthin & Wald
-// (JCGT 2013), two-sided, t > 0, equal distances resolved to the smaller
-// triangle id -- the same answer as brute force over all triangles.  Box
-// tests are loosened by a relative margin so rounding never culls a box that
-// holds the winning triangle.
+// a per-lane stack: 32 entries in LDS; when they are full the older 16 move
+// to a global spill area and come back when the LDS part runs empty, so any
+// depth the 96-bit keys allow is exact and a pop is always an LDS read.
+// Each outer iteration advances a lane by up to two nodes, which halves the
+// per-iteration cost of the wave-wide refill and batching decisions.  Leaf
+// hits wait in a 4-entry per-lane queue and the triangle test runs when at
+// least 32 lanes of the wave have one (or a queue is nearly full, or a lane
+// has finished its traversal), so it executes with most lanes active
+// instead of once per node visit for a few lanes; watertight ray/triangle
+// test of Woop, Benthin & Wald (JCGT 2013), two-sided, t > 0, equal
+// distances resolved to the smaller triangle id -- the same answer as brute
+// force over all triangles.  Box tests are loosened by a relative margin so
+// rounding never culls a box that holds the winning triangle.
 #include "dof_internal.h"
 
 namespace dof {
@@ -330,6 +334,7 @@ struct RawRays {
 
 // ---------------------------------------------------------------- persistent traversal
 
+constexpr int kSpillChunk = 16;   // stack entries moved per spill or refill
 constexpr int kRefill = 16;   // refill when at least this many lanes are idle
 constexpr int kLeafBatch = 32;   // run triangle tests when at least this many lanes have one pending
 
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
 
     bool active = false, exhausted = false;
     uint32_t item = 0, node = 0;
-    int sp = 0;
+    int sp = 0, ns = 0;   // entries in LDS, entries spilled to global memory
     float o[3], d[3];
     WRay wr;
     Hit h;
@@ -372,6 +377,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     h = Hit{INFINITY, ~0u, 0u};
                     node = 0;
                     sp = 0;
+                    ns = 0;
                     nq = 0;
                     active = true;
                     if (S.ntri == 1) {
@@ -401,7 +407,9 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                 --nq;
             }
         }
-        if (active && trav && nq <= 2) {
+#pragma unroll
+        for (int step = 0; step < 2; ++step) {
+            if (!(active && trav && nq <= 2)) continue;
             const BvhNode nd = S.nodes[node];
             ++visits;
             const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
@@ -409,33 +417,42 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             bool hl = box_hit(wr, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, limit, tl);
             bool hr = box_hit(wr, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, limit, tr);
             const uint32_t L = nd.d.x, R = nd.d.y;
-            if (hl && (L & kLeaf)) {
-                const uint32_t v = L & ~kLeaf;
-                if (nq == 0) q0 = v; else if (nq == 1) q1 = v; else if (nq == 2) q2 = v; else q3 = v;
-                ++nq;
-                hl = false;
-            }
-            if (hr && (R & kLeaf)) {
-                const uint32_t v = R & ~kLeaf;
-                if (nq == 0) q0 = v; else if (nq == 1) q1 = v; else if (nq == 2) q2 = v; else q3 = v;
-                ++nq;
-                hr = false;
-            }
+            // leaf children go to the front of the pending queue (shift in)
+            const bool pl = hl && (L & kLeaf) != 0u, pr = hr && (R & kLeaf) != 0u;
+            q3 = pl ? q2 : q3; q2 = pl ? q1 : q2; q1 = pl ? q0 : q1; q0 = pl ? (L & ~kLeaf) : q0;
+            q3 = pr ? q2 : q3; q2 = pr ? q1 : q2; q1 = pr ? q0 : q1; q0 = pr ? (R & ~kLeaf) : q0;
+            nq += (int)pl + (int)pr;
+            hl = hl && !pl;
+            hr = hr && !pr;
             if (hl && hr) {
                 const uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
-                if (sp < kStackLds) stk[sp * kTB] = farc;
-                else spill[(size_t)(sp - kStackLds) * nthreads + gtid] = farc;
+                if (sp == kStackLds) {
+                    // LDS part full: its older half moves to the global spill area
+                    for (int i = 0; i < kSpillChunk; ++i) spill[(size_t)(ns + i) * nthreads + gtid] = stk[i * kTB];
+                    for (int i = 0; i < kStackLds - kSpillChunk; ++i) stk[i * kTB] = stk[(i + kSpillChunk) * kTB];
+                    ns += kSpillChunk;
+                    sp -= kSpillChunk;
+                }
+                stk[sp * kTB] = farc;
                 ++sp;
                 node = nearc;
             } else if (hl) {
                 node = L;
             } else if (hr) {
                 node = R;
-            } else if (sp > 0) {
-                --sp;
-                node = sp < kStackLds ? stk[sp * kTB] : spill[(size_t)(sp - kStackLds) * nthreads + gtid];
             } else {
-                trav = false;
+                if (sp == 0 && ns > 0) {
+                    // LDS part empty: the most recently spilled chunk comes back
+                    ns -= kSpillChunk;
+                    for (int i = 0; i < kSpillChunk; ++i) stk[i * kTB] = spill[(size_t)(ns + i) * nthreads + gtid];
+                    sp = kSpillChunk;
+                }
+                if (sp > 0) {
+                    --sp;
+                    node = stk[sp * kTB];
+                } else {
+                    trav = false;
+                }
             }
         }
         if (active && !trav && nq == 0) {
