@@ -230,6 +230,57 @@ dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n)
 dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, const dof_params *p,
                               dof_debug_view *out);
 
+/* ---- Batches: frames of several sessions in one launch per stage --------
+ * Not a passage of the paper (it renders one view per frame): a throughput
+ * path for serving many sessions at once.  Each item is one frame with the
+ * same arguments as dof_render_frame (its own scene, size, G-buffer,
+ * history, outputs and scratch); all items share one dof_params.  Every
+ * stage runs as one launch over all items' pixels and one persistent
+ * traversal runs over all items' rays, and each item's colour, mask,
+ * history and scratch planes are bit-identical to what dof_render_frame
+ * gives for it alone.  Items of one batch must not share a scratch,
+ * history output or colour buffer.  params.timing is ignored. */
+#define DOF_MAX_BATCH 128
+
+typedef struct dof_batch dof_batch;
+
+typedef struct {
+    dof_scene *scene;
+    dof_camera camera;
+    dof_lens lens;
+    dof_gbuffer gbuffer;
+    dof_history_io history;
+    dof_frame_out out;          /* out.stats: masked_px and rays of this item, visits/tests 0 */
+    void *scratch;              /* dof_frame_scratch_bytes(width, height, params) bytes */
+    size_t scratch_bytes;
+} dof_batch_item;
+
+/* Device-written totals of one batch run. */
+typedef struct {
+    int32_t frames;
+    uint32_t rays;
+    uint64_t node_visits;
+    uint64_t tri_tests;
+} dof_batch_stats;
+
+/* Size of the device table of a batch of up to max_items (<= DOF_MAX_BATCH). */
+dof_status dof_batch_bytes(int32_t max_items, size_t *bytes);
+/* Host handle over a caller-owned device table (256-byte aligned, at least
+ * dof_batch_bytes(max_items) bytes, kept alive until dof_batch_destroy). */
+dof_status dof_batch_create(void *table, size_t table_bytes, int32_t max_items, dof_batch **out);
+/* Checks every item as dof_render_frame would (an error names the item) and
+ * uploads the item table on `stream` (host memory is not retained). */
+dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, const dof_params *p,
+                         void *stream);
+/* Renders the items of the last dof_batch_set on `stream`: launches only
+ * (no host sync, no allocation), so it may be captured in a HIP graph.  A
+ * captured run may be replayed after later dof_batch_set calls whose items
+ * have the same count, sizes and order and the same first-item scratch
+ * buffer (grid sizes and the traversal's spill area are captured).
+ * stats (device pointer, nullable) receives the batch totals. */
+dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream);
+void dof_batch_destroy(dof_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

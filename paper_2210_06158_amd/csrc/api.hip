@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "dof_internal.h"
 
@@ -297,20 +298,68 @@ bool same_view(const dof_camera &a, const dof_camera &b, const dof_lens &la, con
            memcmp(&la, &lb, sizeof(la)) == 0;
 }
 
-int default_trace_blocks()
+int default_trace_blocks(bool batch = false)
 {
     // as many 128-thread blocks as fit on the device at once (registers and
     // the LDS stack decide), capped by the spill-buffer size
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
-    per_cu = dof::trace_blocks_per_cu();
+    per_cu = dof::trace_blocks_per_cu(batch);
     if (per_cu <= 0) per_cu = 5;
     const int b = cus * per_cu;
     return b > dof::kMaxTraceBlocks ? dof::kMaxTraceBlocks : b;
 }
 
+// Checks of one frame's arguments (shared by single frames and batches);
+// on success L is the frame's scratch layout and fc its constants.
+dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *lens, const dof_gbuffer *gb,
+                       const dof_history_io *hist, const dof_params *p, const dof_frame_out *out, void *scratch,
+                       size_t scratch_bytes, dof::ScratchLayout &L, dof::FrameConst &fc, bool &have_hist)
+{
+    if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
+    if (!camera_ok(cam)) return fail(DOF_E_INVALID, "bad camera (size must be even and positive)");
+    if (!lens_ok(lens)) return fail(DOF_E_INVALID, "bad lens");
+    dof_status st = params_check(p);
+    if (st != DOF_OK) return st;
+    if (!gb || !gb->colour || !gb->depth || !gb->normal) return fail(DOF_E_INVALID, "bad G-buffer");
+    if ((gb->colour_format != DOF_RGBA32F && gb->colour_format != DOF_RGBA16F) ||
+        (gb->normal_format != DOF_RGBA32F && gb->normal_format != DOF_RGBA16F))
+        return fail(DOF_E_INVALID, "bad G-buffer format");
+    if (!hist || !hist->out) return fail(DOF_E_INVALID, "history output is NULL");
+    if (hist->in && hist->in == hist->out) return fail(DOF_E_INVALID, "history in and out must differ");
+    if (!out || !out->colour || !out->mask) return fail(DOF_E_INVALID, "bad frame output");
+    if (out->colour_format != DOF_RGBA32F && out->colour_format != DOF_RGBA16F)
+        return fail(DOF_E_INVALID, "bad output format");
+    if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    L = frame_layout(cam->width, cam->height, p->m);
+    if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
+    have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
+                hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
+    const bool motion = have_hist && !same_view(*cam, hist->prev_camera, *lens, hist->prev_lens);
+    fill_frame_const(scene, *cam, *lens, *p, have_hist, motion, hist->prev_camera, hist->prev_lens, fc);
+    return DOF_OK;
+}
+
+const dof::Rings &ring_table()
+{
+    static const dof::Rings rings = make_rings();
+    return rings;
+}
+
 }  // namespace
+
+struct dof_batch {
+    char *table;                       // device: BatchHead, then the jobs
+    size_t table_bytes;
+    int32_t max_items;
+    int32_t n;                         // jobs of the current set (0 = none)
+    uint32_t nblk[dof::kNumGrids];     // total blocks of each grid shape
+    uint32_t *spill;                   // traversal spill (first frame's scratch)
+    int32_t trace_blocks;
+    std::vector<char> host;            // staging copy of the table
+};
 
 extern "C" {
 
@@ -490,30 +539,12 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
                             const dof_history_io *hist, const dof_params *p, const dof_frame_out *out, void *scratch,
                             size_t scratch_bytes, void *stream)
 {
-    if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
-    if (!camera_ok(cam)) return fail(DOF_E_INVALID, "bad camera (size must be even and positive)");
-    if (!lens_ok(lens)) return fail(DOF_E_INVALID, "bad lens");
-    dof_status st = params_check(p);
-    if (st != DOF_OK) return st;
-    if (!gb || !gb->colour || !gb->depth || !gb->normal) return fail(DOF_E_INVALID, "bad G-buffer");
-    if ((gb->colour_format != DOF_RGBA32F && gb->colour_format != DOF_RGBA16F) ||
-        (gb->normal_format != DOF_RGBA32F && gb->normal_format != DOF_RGBA16F))
-        return fail(DOF_E_INVALID, "bad G-buffer format");
-    if (!hist || !hist->out) return fail(DOF_E_INVALID, "history output is NULL");
-    if (hist->in && hist->in == hist->out) return fail(DOF_E_INVALID, "history in and out must differ");
-    if (!out || !out->colour || !out->mask) return fail(DOF_E_INVALID, "bad frame output");
-    if (out->colour_format != DOF_RGBA32F && out->colour_format != DOF_RGBA16F)
-        return fail(DOF_E_INVALID, "bad output format");
-    if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
-    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
-    const dof::ScratchLayout L = frame_layout(cam->width, cam->height, p->m);
-    if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
-    const bool have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
-                           hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
-    const bool motion = have_hist && !same_view(*cam, hist->prev_camera, *lens, hist->prev_lens);
+    dof::ScratchLayout L;
     dof::FrameConst fc;
-    fill_frame_const(scene, *cam, *lens, *p, have_hist, motion, hist->prev_camera, hist->prev_lens, fc);
-    static const dof::Rings rings = make_rings();
+    bool have_hist = false;
+    dof_status st = check_frame(scene, cam, lens, gb, hist, p, out, scratch, scratch_bytes, L, fc, have_hist);
+    if (st != DOF_OK) return st;
+    const dof::Rings &rings = ring_table();
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *scr = static_cast<char *>(scratch);
     const void *hin = have_hist ? hist->in : nullptr;
@@ -532,6 +563,105 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
     scene->timed_frame = ev != nullptr;
     return DOF_OK;
 }
+
+dof_status dof_batch_bytes(int32_t max_items, size_t *bytes)
+{
+    if (max_items < 1 || max_items > DOF_MAX_BATCH || !bytes) return fail(DOF_E_INVALID, "bad arguments");
+    *bytes = dof::batch_table_bytes(max_items);
+    return DOF_OK;
+}
+
+dof_status dof_batch_create(void *table, size_t table_bytes, int32_t max_items, dof_batch **out)
+{
+    if (!table || !out || max_items < 1 || max_items > DOF_MAX_BATCH) return fail(DOF_E_INVALID, "bad arguments");
+    if ((reinterpret_cast<uintptr_t>(table) & 255u) != 0) return fail(DOF_E_INVALID, "table must be 256-byte aligned");
+    if (table_bytes < dof::batch_table_bytes(max_items))
+        return fail(DOF_E_NOMEM, "batch table needs %zu bytes, got %zu", dof::batch_table_bytes(max_items), table_bytes);
+    dof_batch *b = new (std::nothrow) dof_batch();
+    if (!b) return fail(DOF_E_NOMEM, "host allocation failed");
+    b->table = static_cast<char *>(table);
+    b->table_bytes = table_bytes;
+    b->max_items = max_items;
+    b->n = 0;
+    *out = b;
+    return DOF_OK;
+}
+
+dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, const dof_params *p, void *stream)
+{
+    if (!b || !items || n < 1) return fail(DOF_E_INVALID, "bad arguments");
+    if (n > b->max_items) return fail(DOF_E_NOMEM, "batch holds at most %d items, got %d", b->max_items, n);
+    b->n = 0;
+    const size_t jobs_at = dof::batch_table_bytes(0);
+    b->host.assign(dof::batch_table_bytes(n), 0);
+    dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->host.data());
+    dof::Job *jobs = reinterpret_cast<dof::Job *>(b->host.data() + jobs_at);
+    head->njobs = n;
+    uint32_t tot[dof::kNumGrids] = {};
+    for (int i = 0; i < n; ++i) {
+        const dof_batch_item &it = items[i];
+        dof::ScratchLayout L;
+        dof::Job &J = jobs[i];
+        bool have_hist = false;
+        dof_status st = check_frame(it.scene, &it.camera, &it.lens, &it.gbuffer, &it.history, p, &it.out, it.scratch,
+                                    it.scratch_bytes, L, J.fc, have_hist);
+        if (st != DOF_OK) {
+            char msg[sizeof(g_err)];
+            snprintf(msg, sizeof(msg), "%s", g_err);
+            return fail(st, "item %d: %s", i, msg);
+        }
+        for (int k = 0; k < i; ++k)
+            if (items[k].scratch == it.scratch || items[k].history.out == it.history.out ||
+                items[k].out.colour == it.out.colour)
+                return fail(DOF_E_INVALID, "items %d and %d share a scratch, history output or colour buffer", k, i);
+        char *scr = static_cast<char *>(it.scratch);
+        J.P = dof::planes(J.fc, L, scr);
+        J.gb = it.gbuffer;
+        J.hist_in = have_hist ? it.history.in : nullptr;
+        J.hist_out = it.history.out;
+        J.mask = it.out.mask;
+        J.out = it.out;
+        J.scene = dof::SceneArgs{it.scene->dev.ntri, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes};
+        const dof::FrameConst &fc = J.fc;
+        const int64_t np = (int64_t)fc.hw * fc.hh;
+        auto cdiv = [](int64_t a, int64_t c) { return (uint32_t)((a + c - 1) / c); };
+        const uint32_t bxs[dof::kNumGrids] = {(uint32_t)fc.tw, cdiv(fc.tw, 16), cdiv(fc.hw, 64), (uint32_t)L.nchunks,
+                                              cdiv(np, 256), cdiv(fc.hw, 8), cdiv(fc.W, 64)};
+        const uint32_t bys[dof::kNumGrids] = {(uint32_t)fc.th, cdiv(fc.th, 16), cdiv(fc.hh, 4), 1u, 1u,
+                                              cdiv(fc.hh, 8), cdiv(fc.H, 4)};
+        for (int g = 0; g < dof::kNumGrids; ++g) {
+            J.bstart[g] = tot[g];
+            J.bx[g] = bxs[g];
+            const uint64_t t = (uint64_t)tot[g] + (uint64_t)bxs[g] * bys[g];
+            if (t > 0x7fffffffu) return fail(DOF_E_INVALID, "batch too large for one launch");
+            tot[g] = (uint32_t)t;
+        }
+        if (i == 0) b->spill = reinterpret_cast<uint32_t *>(scr + L.spill);
+    }
+    DOF_HIP(hipMemcpyAsync(b->table, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
+                           static_cast<hipStream_t>(stream)));
+    for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
+    b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
+    b->n = n;
+    return DOF_OK;
+}
+
+dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
+{
+    if (!b) return fail(DOF_E_INVALID, "batch is NULL");
+    if (b->n < 1) return fail(DOF_E_STATE, "no items set");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->table);
+    const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
+    const dof::Rings &rings = ring_table();
+    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, s));
+    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, s));
+    DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, s));
+    if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
+    return DOF_OK;
+}
+
+void dof_batch_destroy(dof_batch *b) { delete b; }
 
 dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n)
 {

@@ -6,6 +6,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/dof.h"
@@ -102,6 +103,77 @@ struct ScratchLayout {
 
 constexpr int kChunk = 1024;   // pixels per compaction chunk (256 threads x 4)
 
+// Device pointers of every plane of one frame (from its scratch layout).
+struct Planes {
+    float4 *colr, *zn, *pre, *gather, *ppmed;
+    float *zh, *tile_max, *tile_dil;
+    int32_t *prev_idx;
+    uint2 *chunk_cnt, *chunk_off;
+    uint32_t *counters, *queue, *ray_base, *ray_pix;
+    int32_t *ray_hit;
+    float *ray_t;
+    float4 *ray_col, *ray_pos;
+    float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
+    float *var_blur;
+};
+Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
+
+// What the traversal reads of a scene.
+struct SceneArgs {
+    int32_t ntri;
+    const float4 *__restrict__ tris;
+    const float4 *__restrict__ albedo;
+    const BvhNode *__restrict__ nodes;
+};
+
+// ---------------------------------------------------------------- batches
+// A batch renders several frames (any scenes and sizes) with one launch per
+// stage: every stage kernel runs over the concatenation of the frames'
+// block grids, and one persistent traversal runs over the concatenation of
+// their ray queues.  The device table holds a BatchHead and one Job per frame.
+
+constexpr int kMaxBatch = 128;
+
+// block-grid shapes of the stage kernels
+enum : int {
+    kGridTiles = 0,   // (tw, th) blocks of 16 x 16: reduce, mask
+    kGridDilate,      // tiles in blocks of 16 x 16: dilate
+    kGridHalf,        // half-res pixels in blocks of 64 x 4
+    kGridChunk,       // compaction chunks
+    kGridResolve,     // half-res pixels in blocks of 256
+    kGridMip,         // half-res pixels in 8 x 8 tiles
+    kGridFull,        // full-res pixels in blocks of 64 x 4
+    kNumGrids
+};
+
+struct Job {
+    FrameConst fc;
+    Planes P;
+    dof_gbuffer gb;
+    const void *hist_in;     // nullptr when the frame has no usable history
+    void *hist_out;
+    uint8_t *mask;
+    dof_frame_out out;
+    SceneArgs scene;
+    uint32_t bstart[kNumGrids];   // first block of this job in each grid
+    uint32_t bx[kNumGrids];       // blocks per row of this job in each grid
+};
+
+struct BatchHead {      // the first 24 bytes are the batch's dof_batch_stats
+    int32_t njobs;
+    uint32_t rays;                       // total rays of the batch
+    unsigned long long visits, tests;    // traversal statistics of the batch
+    uint32_t work;                       // traversal work counter
+    uint32_t pad;
+    uint32_t ray_off[kMaxBatch + 1];     // first ray of each job in the batch
+};
+static_assert(offsetof(BatchHead, visits) == 8 && offsetof(BatchHead, tests) == 16, "stats prefix");
+
+inline size_t batch_table_bytes(int n)
+{
+    return (sizeof(BatchHead) + 255) / 256 * 256 + sizeof(Job) * (size_t)n;
+}
+
 // counters[] slots (u32) in scratch: [0] masked px, [1] rays, [2..3] u64 node
 // visits, [4..5] u64 triangle tests, [8] traversal work counter
 enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntWork = 8 };
@@ -125,7 +197,7 @@ __device__ inline float coc_px(float cock, float d, float z) { return cock * fab
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 
 // trace.hip
-int trace_blocks_per_cu();   // resident blocks of the lens-ray traversal per CU
+int trace_blocks_per_cu(bool batch);   // resident blocks of the lens-ray traversal per CU
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
@@ -142,5 +214,13 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
                              const dof_frame_out &out, hipEvent_t *ev, hipStream_t st);
 hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
+// batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
+// total blocks of grid g over the jobs
+hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
+                            const Rings &rings, hipStream_t st);
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
+                              hipStream_t st);
+hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
+                             const Rings &rings, hipStream_t st);
 
 }  // namespace dof

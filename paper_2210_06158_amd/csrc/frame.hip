@@ -129,17 +129,7 @@ __device__ inline HistW hist_wview(void *h, size_t np)
     return HistW{p, p + np, p + 2 * np, reinterpret_cast<float *>(p + 3 * np)};
 }
 
-struct Planes {
-    float4 *colr, *zn, *pre, *gather, *ppmed;
-    float *zh, *tile_max, *tile_dil;
-    int32_t *prev_idx;
-    uint2 *chunk_cnt, *chunk_off;
-    uint32_t *counters, *queue, *ray_base, *ray_pix;
-    const int32_t *ray_hit;
-    const float4 *ray_col, *ray_pos;
-    float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
-    float *var_blur;
-};
+}  // namespace
 
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
 {
@@ -160,9 +150,10 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.queue = reinterpret_cast<uint32_t *>(s + L.queue);
     p.ray_base = reinterpret_cast<uint32_t *>(s + L.ray_base);
     p.ray_pix = reinterpret_cast<uint32_t *>(s + L.ray_pix);
-    p.ray_hit = reinterpret_cast<const int32_t *>(s + L.ray_hit);
-    p.ray_col = reinterpret_cast<const float4 *>(s + L.ray_col);
-    p.ray_pos = reinterpret_cast<const float4 *>(s + L.ray_pos);
+    p.ray_hit = reinterpret_cast<int32_t *>(s + L.ray_hit);
+    p.ray_t = reinterpret_cast<float *>(s + L.ray_t);
+    p.ray_col = reinterpret_cast<float4 *>(s + L.ray_col);
+    p.ray_pos = reinterpret_cast<float4 *>(s + L.ray_pos);
     float4 *res = reinterpret_cast<float4 *>(s + L.resolve);
     p.R0 = res; p.R1 = res + np; p.R2 = res + 2 * np; p.R3 = res + 3 * np;
     float4 *tmp = reinterpret_cast<float4 *>(s + L.temporal);
@@ -174,11 +165,30 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     return p;
 }
 
+namespace {
+
+// Job of a block of a batched launch: the last job whose first block in grid
+// g is at or before b; (bx, by) is the block within that job's own grid.
+__device__ inline int job_of_block(const Job *__restrict__ jobs, int njobs, int g, uint32_t b, uint32_t &bx,
+                                   uint32_t &by)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].bstart[g] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t lb = b - jobs[lo].bstart[g], w = jobs[lo].bx[g];
+    bx = lb % w;
+    by = lb / w;
+    return lo;
+}
+
 // ---------------------------------------------------------------- A1
 
-__global__ __launch_bounds__(256) void k_reduce(FrameConst fc, dof_gbuffer gb, Planes P)
+__device__ inline void b_reduce(const FrameConst &fc, const dof_gbuffer &gb, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kTile + threadIdx.x, y = blockIdx.y * kTile + threadIdx.y;
+    const int x = bx * kTile + threadIdx.x, y = by * kTile + threadIdx.y;
     float ar = 0.0f;
     if (x < fc.hw && y < fc.hh) {
         const size_t W = (size_t)fc.W;
@@ -215,15 +225,27 @@ __global__ __launch_bounds__(256) void k_reduce(FrameConst fc, dof_gbuffer gb, P
     if (tid == 0) {
         float m = 0.0f;
         for (int k = 0; k < 4; ++k) m = fmax_cs(m, red[k]);
-        P.tile_max[(size_t)blockIdx.y * fc.tw + blockIdx.x] = m;
+        P.tile_max[(size_t)by * fc.tw + bx] = m;
     }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(FrameConst fc, dof_gbuffer gb, Planes P)
+{
+    b_reduce(fc, gb, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_reduce(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridTiles, blockIdx.x, bx, by)];
+    b_reduce(J.fc, J.gb, J.P, bx, by);
 }
 
 // ---------------------------------------------------------------- A2
 
-__global__ void k_dilate(FrameConst fc, Planes P)
+__device__ inline void b_dilate(const FrameConst &fc, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int tx = blockIdx.x * blockDim.x + threadIdx.x, ty = blockIdx.y * blockDim.y + threadIdx.y;
+    const int tx = bx * blockDim.x + threadIdx.x, ty = by * blockDim.y + threadIdx.y;
     if (tx >= fc.tw || ty >= fc.th) return;
     float m = 0.0f;
     for (int j = ty - fc.D; j <= ty + fc.D; ++j)
@@ -232,11 +254,23 @@ __global__ void k_dilate(FrameConst fc, Planes P)
     P.tile_dil[(size_t)ty * fc.tw + tx] = m;
 }
 
+__global__ void k_dilate(FrameConst fc, Planes P)
+{
+    b_dilate(fc, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ void kb_dilate(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridDilate, blockIdx.x, bx, by)];
+    b_dilate(J.fc, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A3
 
-__global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
+__device__ inline void b_prefilter(const FrameConst &fc, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     if (x >= fc.hw || y >= fc.hh) return;
     const size_t i = (size_t)y * fc.hw + x;
     float Rn = P.tile_dil[(size_t)(y / fc.T) * fc.tw + x / fc.T];
@@ -258,11 +292,23 @@ __global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
     P.pre[i] = make_float4(ax / sw, ay / sw, az / sw, rc);
 }
 
+__global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
+{
+    b_prefilter(fc, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_prefilter(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_prefilter(J.fc, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A4
 
-__global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings, Planes P)
+__device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     if (x >= fc.hw || y >= fc.hh) return;
     const size_t i = (size_t)y * fc.hw + x;
     const float Rn = P.tile_dil[(size_t)(y / fc.T) * fc.tw + x / fc.T];
@@ -296,11 +342,23 @@ __global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings,
     P.gather[i] = o;
 }
 
+__global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings, Planes P)
+{
+    b_gather(fc, rings, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_gather(const Job *__restrict__ jobs, int njobs, Rings rings)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_gather(J.fc, rings, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A5
 
-__global__ __launch_bounds__(kBX *kBY) void k_median_pp(FrameConst fc, Planes P)
+__device__ inline void b_median_pp(const FrameConst &fc, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     if (x >= fc.hw || y >= fc.hh) return;
     float4 v[9];
     int n = 0;
@@ -314,17 +372,29 @@ __global__ __launch_bounds__(kBX *kBY) void k_median_pp(FrameConst fc, Planes P)
                              v[4].w);
 }
 
+__global__ __launch_bounds__(kBX *kBY) void k_median_pp(FrameConst fc, Planes P)
+{
+    b_median_pp(fc, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_median_pp(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_median_pp(J.fc, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A6
 
 constexpr int kMaskHalo = 4, kMaskL = kTile + 2 * kMaskHalo;   // 24 x 24 LDS cells
 
-__global__ __launch_bounds__(256) void k_mask(FrameConst fc, Planes P, const void *hist_in, uint8_t *mask)
+__device__ inline void b_mask(const FrameConst &fc, const Planes &P, const void *hist_in, uint8_t *mask, const uint32_t bx, const uint32_t by)
 {
     __shared__ float4 F[kMaskL][kMaskL];
     __shared__ float4 Hh[kMaskL][kMaskL];
     __shared__ float4 B[kMaskL][kMaskL];
     const int hw = fc.hw, hh = fc.hh;
-    const int ox = blockIdx.x * kTile - kMaskHalo, oy = blockIdx.y * kTile - kMaskHalo;
+    const int ox = bx * kTile - kMaskHalo, oy = by * kTile - kMaskHalo;
     const int tid = threadIdx.y * kTile + threadIdx.x;
     // Cells hold values at clamped coordinates; a coordinate g maps to cell g - origin.
     for (int c = tid; c < kMaskL * kMaskL; c += 256) {
@@ -365,7 +435,7 @@ __global__ __launch_bounds__(256) void k_mask(FrameConst fc, Planes P, const voi
         B[ly][lx] = acc;
     }
     __syncthreads();
-    const int x = blockIdx.x * kTile + threadIdx.x, y = blockIdx.y * kTile + threadIdx.y;
+    const int x = bx * kTile + threadIdx.x, y = by * kTile + threadIdx.y;
     if (x >= hw || y >= hh) return;
     const float sm[5] = {1.0f, 4.0f, 6.0f, 4.0f, 1.0f};
     const float dv[5] = {-1.0f, -2.0f, 0.0f, 2.0f, 1.0f};
@@ -427,6 +497,18 @@ __global__ __launch_bounds__(256) void k_mask(FrameConst fc, Planes P, const voi
     mask[i] = (uint8_t)n;
 }
 
+__global__ __launch_bounds__(256) void k_mask(FrameConst fc, Planes P, const void *hist_in, uint8_t *mask)
+{
+    b_mask(fc, P, hist_in, mask, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_mask(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridTiles, blockIdx.x, bx, by)];
+    b_mask(J.fc, J.P, J.hist_in, J.mask, bx, by);
+}
+
 // ---------------------------------------------------------------- A7
 // Chunks of 1024 pixels in row-major order; ranks from wave ballots (masked
 // pixels) and wave prefix sums (rays), so the queue is ascending.
@@ -440,10 +522,10 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v, int lane)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+__device__ inline void b_compact_count(int64_t np, const uint8_t *__restrict__ mask, const Planes &P, const uint32_t bx, const uint32_t by)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    size_t base = (size_t)blockIdx.x * kChunk;
+    size_t base = (size_t)bx * kChunk;
     uint32_t cp = 0, cr = 0;
     for (int r = 0; r < kChunk / 256; ++r) {
         size_t i = base + (size_t)r * 256 + tid;
@@ -458,10 +540,22 @@ __global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t
     __shared__ uint32_t sp[4], sr[4];
     if (lane == 0) { sp[w] = cp; sr[w] = cr; }
     __syncthreads();
-    if (tid == 0) P.chunk_cnt[blockIdx.x] = make_uint2(sp[0] + sp[1] + sp[2] + sp[3], sr[0] + sr[1] + sr[2] + sr[3]);
+    if (tid == 0) P.chunk_cnt[bx] = make_uint2(sp[0] + sp[1] + sp[2] + sp[3], sr[0] + sr[1] + sr[2] + sr[3]);
 }
 
-__global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P, dof_stats *stats)
+__global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+{
+    b_compact_count(np, mask, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_compact_count(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridChunk, blockIdx.x, bx, by)];
+    b_compact_count((int64_t)J.fc.hw * J.fc.hh, J.mask, J.P, bx, by);
+}
+
+__device__ inline void b_compact_scan(int64_t nchunks, const Planes &P, dof_stats *stats)
 {
     __shared__ uint32_t pp[1024], pr[1024];
     const int per = (int)((nchunks + 1023) / 1024);
@@ -502,18 +596,30 @@ __global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P
     }
 }
 
-__global__ __launch_bounds__(256) void k_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+__global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P, dof_stats *stats)
+{
+    b_compact_scan(nchunks, P, stats);
+}
+
+__global__ __launch_bounds__(1024) void kb_compact_scan(const Job *__restrict__ jobs)
+{
+    const Job &J = jobs[blockIdx.x];
+    const int64_t np = (int64_t)J.fc.hw * J.fc.hh;
+    b_compact_scan((np + kChunk - 1) / kChunk, J.P, nullptr);
+}
+
+__device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, const Planes &P, const uint32_t bx, const uint32_t by)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     __shared__ uint32_t wp[4], wr[4];
     __shared__ uint32_t runp, runr;
     if (tid == 0) {
-        uint2 o = P.chunk_off[blockIdx.x];
+        uint2 o = P.chunk_off[bx];
         runp = o.x;
         runr = o.y;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    size_t base = (size_t)blockIdx.x * kChunk;
+    size_t base = (size_t)bx * kChunk;
     for (int r = 0; r < kChunk / 256; ++r) {
         size_t i = base + (size_t)r * 256 + tid;
         uint32_t n = i < (size_t)np ? mask[i] : 0u;
@@ -540,11 +646,23 @@ __global__ __launch_bounds__(256) void k_compact_scatter(int64_t np, const uint8
     }
 }
 
+__global__ __launch_bounds__(256) void k_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, Planes P)
+{
+    b_compact_scatter(np, mask, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridChunk, blockIdx.x, bx, by)];
+    b_compact_scatter((int64_t)J.fc.hw * J.fc.hh, J.mask, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A11
 
-__global__ __launch_bounds__(256) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
+__device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask, const uint32_t bx, const uint32_t by)
 {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t j = bx * 256 + threadIdx.x;
     if (j >= P.counters[kCntMasked]) return;
     const uint32_t q = P.queue[j];
     const int n = mask[q];
@@ -580,12 +698,24 @@ __global__ __launch_bounds__(256) void k_resolve(FrameConst fc, Planes P, const 
     P.R3[q] = make_float4(hp ? fp0 / fw : 0.0f, hp ? fp1 / fw : 0.0f, hp ? fp2 / fw : 0.0f, hp ? 1.0f : 0.0f);
 }
 
+__global__ __launch_bounds__(256) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
+{
+    b_resolve(fc, P, mask, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_resolve(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridResolve, blockIdx.x, bx, by)];
+    b_resolve(J.fc, J.P, J.mask, bx, by);
+}
+
 // ---------------------------------------------------------------- A12
 
-__global__ __launch_bounds__(kBX *kBY) void k_temporal(FrameConst fc, Planes P, const uint8_t *__restrict__ mask,
-                                                       const void *hist_in, void *hist_out)
+__device__ inline void b_temporal(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
+                                                       const void *hist_in, void *hist_out, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     const int hw = fc.hw, hh = fc.hh;
     if (x >= hw || y >= hh) return;
     const size_t np = (size_t)hw * hh, i = (size_t)y * hw + x;
@@ -665,15 +795,28 @@ __global__ __launch_bounds__(kBX *kBY) void k_temporal(FrameConst fc, Planes P, 
     ho.C[i] = make_float4(accCN, accCF, mu1, mu2);
 }
 
+__global__ __launch_bounds__(kBX *kBY) void k_temporal(FrameConst fc, Planes P, const uint8_t *__restrict__ mask,
+                                                       const void *hist_in, void *hist_out)
+{
+    b_temporal(fc, P, mask, hist_in, hist_out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_temporal(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_temporal(J.fc, J.P, J.mask, J.hist_in, J.hist_out, bx, by);
+}
+
 // ---------------------------------------------------------------- A12 blur + A13 median, mips
 // One wave per 8 x 8 tile: variance blur (3x3 binomial), 3x3 median of the
 // ray-traced colour (invalid neighbours replaced by the centre), level 0 of
 // the validity-weighted mip chain, then levels 1..3 of the tile from LDS.
 
-__global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P, void *hist_out)
+__device__ inline void b_blur_median_mips(const FrameConst &fc, const Planes &P, void *hist_out, const uint32_t bx, const uint32_t by)
 {
     const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;
-    const int x = blockIdx.x * 8 + tx, y = blockIdx.y * 8 + ty;
+    const int x = bx * 8 + tx, y = by * 8 + ty;
     const int hw = fc.hw, hh = fc.hh;
     const size_t np = (size_t)hw * hh;
     __shared__ float4 m0[8][8];
@@ -715,11 +858,11 @@ __global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P
     // level 1 (4 x 4 of this tile)
     if (threadIdx.x < 16) {
         const int lx = threadIdx.x & 3, ly = threadIdx.x >> 2;
-        const int gx = blockIdx.x * 4 + lx, gy = blockIdx.y * 4 + ly;
+        const int gx = bx * 4 + lx, gy = by * 4 + ly;
         if (gx < fc.mw[1] && gy < fc.mh[1]) {
             int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[0] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[0] - 1);
-            float4 a = m0[y0 - blockIdx.y * 8][x0 - blockIdx.x * 8], b = m0[y0 - blockIdx.y * 8][x1 - blockIdx.x * 8];
-            float4 c = m0[y1 - blockIdx.y * 8][x0 - blockIdx.x * 8], d = m0[y1 - blockIdx.y * 8][x1 - blockIdx.x * 8];
+            float4 a = m0[y0 - by * 8][x0 - bx * 8], b = m0[y0 - by * 8][x1 - bx * 8];
+            float4 c = m0[y1 - by * 8][x0 - bx * 8], d = m0[y1 - by * 8][x1 - bx * 8];
             float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
                                    ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
             P.mips[fc.moff[1] + (size_t)gy * fc.mw[1] + gx] = o;
@@ -729,11 +872,11 @@ __global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P
     __syncthreads();
     if (threadIdx.x < 4) {
         const int lx = threadIdx.x & 1, ly = threadIdx.x >> 1;
-        const int gx = blockIdx.x * 2 + lx, gy = blockIdx.y * 2 + ly;
+        const int gx = bx * 2 + lx, gy = by * 2 + ly;
         if (gx < fc.mw[2] && gy < fc.mh[2]) {
             int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[1] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[1] - 1);
-            float4 a = m1[y0 - blockIdx.y * 4][x0 - blockIdx.x * 4], b = m1[y0 - blockIdx.y * 4][x1 - blockIdx.x * 4];
-            float4 c = m1[y1 - blockIdx.y * 4][x0 - blockIdx.x * 4], d = m1[y1 - blockIdx.y * 4][x1 - blockIdx.x * 4];
+            float4 a = m1[y0 - by * 4][x0 - bx * 4], b = m1[y0 - by * 4][x1 - bx * 4];
+            float4 c = m1[y1 - by * 4][x0 - bx * 4], d = m1[y1 - by * 4][x1 - bx * 4];
             float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
                                    ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
             P.mips[fc.moff[2] + (size_t)gy * fc.mw[2] + gx] = o;
@@ -742,11 +885,11 @@ __global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int gx = blockIdx.x, gy = blockIdx.y;
+        const int gx = bx, gy = by;
         if (gx < fc.mw[3] && gy < fc.mh[3]) {
             int x0 = 2 * gx, y0 = 2 * gy, x1 = clampi(2 * gx + 1, 0, fc.mw[2] - 1), y1 = clampi(2 * gy + 1, 0, fc.mh[2] - 1);
-            float4 a = m2[y0 - blockIdx.y * 2][x0 - blockIdx.x * 2], b = m2[y0 - blockIdx.y * 2][x1 - blockIdx.x * 2];
-            float4 c = m2[y1 - blockIdx.y * 2][x0 - blockIdx.x * 2], d = m2[y1 - blockIdx.y * 2][x1 - blockIdx.x * 2];
+            float4 a = m2[y0 - by * 2][x0 - bx * 2], b = m2[y0 - by * 2][x1 - bx * 2];
+            float4 c = m2[y1 - by * 2][x0 - bx * 2], d = m2[y1 - by * 2][x1 - bx * 2];
             float4 o = make_float4(((a.x + b.x) + (c.x + d.x)) * 0.25f, ((a.y + b.y) + (c.y + d.y)) * 0.25f,
                                    ((a.z + b.z) + (c.z + d.z)) * 0.25f, ((a.w + b.w) + (c.w + d.w)) * 0.25f);
             P.mips[fc.moff[3] + (size_t)gy * fc.mw[3] + gx] = o;
@@ -754,11 +897,23 @@ __global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P
     }
 }
 
+__global__ __launch_bounds__(64) void k_blur_median_mips(FrameConst fc, Planes P, void *hist_out)
+{
+    b_blur_median_mips(fc, P, hist_out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(64) void kb_blur_median_mips(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridMip, blockIdx.x, bx, by)];
+    b_blur_median_mips(J.fc, J.P, J.hist_out, bx, by);
+}
+
 // ---------------------------------------------------------------- A13
 
-__global__ __launch_bounds__(kBX *kBY) void k_recon(FrameConst fc, Rings rings, Planes P)
+__device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     const int hw = fc.hw, hh = fc.hh;
     if (x >= hw || y >= hh) return;
     const size_t i = (size_t)y * hw + x;
@@ -806,11 +961,23 @@ __global__ __launch_bounds__(kBX *kBY) void k_recon(FrameConst fc, Rings rings, 
     P.recon[i] = make_float4(lerp1(med.x, nb0, bb), lerp1(med.y, nb1, bb), lerp1(med.z, nb2, bb), lerp1(hu, hnb, bb));
 }
 
+__global__ __launch_bounds__(kBX *kBY) void k_recon(FrameConst fc, Rings rings, Planes P)
+{
+    b_recon(fc, rings, P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_recon(const Job *__restrict__ jobs, int njobs, Rings rings)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_recon(J.fc, rings, J.P, bx, by);
+}
+
 // ---------------------------------------------------------------- A14
 
-__global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
+__device__ inline void b_composite(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb, const dof_frame_out &out, const uint32_t bx, const uint32_t by)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     if (x >= fc.W || y >= fc.H) return;
     const int hw = fc.hw, hh = fc.hh;
     const size_t p = (size_t)y * fc.W + x;
@@ -857,6 +1024,32 @@ __global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P,
         o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
     }
     st_rgba(out.colour, out.colour_format, p, o);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
+{
+    b_composite(fc, P, gb, out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_composite(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridFull, blockIdx.x, bx, by)];
+    b_composite(J.fc, J.P, J.gb, J.out, bx, by);
+}
+
+// Per-job stats records of a batch: masked pixels and rays of the job; the
+// traversal statistics of a batch are kept once, in its head.
+__global__ void kb_stats(const Job *__restrict__ jobs, int njobs)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs || !jobs[j].out.stats) return;
+    const uint32_t *c = jobs[j].P.counters;
+    dof_stats *o = jobs[j].out.stats;
+    o->masked_px = c[kCntMasked];
+    o->rays = c[kCntRays];
+    o->node_visits = 0;
+    o->tri_tests = 0;
 }
 
 __global__ void k_fill_zero(float *p, int64_t n)
@@ -932,6 +1125,33 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
 hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
 {
     k_fill_zero<<<1024, 256, 0, st>>>(hist, nfloats);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
+                            hipStream_t st)
+{
+    kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
+    kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
+    kb_prefilter<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
+    kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
+    kb_compact_count<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);
+    kb_compact_scan<<<njobs, 1024, 0, st>>>(jobs);
+    kb_compact_scatter<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
+                             hipStream_t st)
+{
+    kb_resolve<<<nblk[kGridResolve], 256, 0, st>>>(jobs, njobs);
+    kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
+    kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
+    kb_composite<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

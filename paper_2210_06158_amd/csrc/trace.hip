@@ -33,13 +33,6 @@
 namespace dof {
 namespace {
 
-struct SceneArgs {
-    int32_t ntri;
-    const float4 *__restrict__ tris;
-    const float4 *__restrict__ albedo;
-    const BvhNode *__restrict__ nodes;
-};
-
 SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.ntri, s.tris, s.albedo, s.nodes}; }
 
 __device__ inline float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
@@ -223,56 +216,107 @@ __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
 
 // ---------------------------------------------------------------- ray sources
 
+// Thin-lens ray r of a frame: its pixel from the ray -> pixel map, the
+// pixel's point on the focus plane, a lens point, normalised direction.
+__device__ inline void lens_ray(const FrameConst &fc, const uint32_t *queue, const uint32_t *ray_base,
+                                const uint32_t *ray_pix, uint32_t r, float o[3], float d[3])
+{
+    const uint32_t j = ray_pix[r];
+    const uint32_t q = queue[j];
+    const uint32_t k = r - ray_base[j];
+    const int x = (int)(q % (uint32_t)fc.hw), y = (int)(q / (uint32_t)fc.hw);
+    float fv[3], pf[3];
+    pixel_dir(fc.cur, x, y, fc.hw, fc.hh, fv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
+    float lx, ly;
+    lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[a] = fc.cur.pos[a] + fc.half_a * (lx * fc.cur.right[a] + ly * fc.cur.up[a]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = pf[a] - o[a];
+    float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = d[a] / len;
+}
+
+// Per-ray record of a lens ray: hit id, distance, shaded colour with view
+// depth, hit position (sky colour and +inf depth on a miss).
+__device__ inline void lens_finish(const SceneArgs &S, const FrameConst &fc, int32_t *ray_hit, float *ray_t,
+                                   float4 *ray_col, float4 *ray_pos, uint32_t r, const float o[3], const float d[3],
+                                   const Hit &h)
+{
+    if (h.id != ~0u) {
+        float P0 = o[0] + h.t * d[0], P1 = o[1] + h.t * d[1], P2 = o[2] + h.t * d[2];
+        float z = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
+                  (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
+        Shaded s = dof::shade(S, fc.shade, h.leaf, d);
+        ray_hit[r] = (int32_t)h.id;
+        ray_t[r] = h.t;
+        ray_col[r] = make_float4(s.r, s.g, s.b, z);
+        ray_pos[r] = make_float4(P0, P1, P2, 0.0f);
+    } else {
+        ray_hit[r] = -1;
+        ray_t[r] = INFINITY;
+        ray_col[r] = make_float4(fc.shade.sky[0], fc.shade.sky[1], fc.shade.sky[2], INFINITY);
+        ray_pos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
 struct LensRays {
+    static constexpr bool kPerLaneScene = false;
     FrameConst fc;
-    SceneShade shade;
     const uint32_t *queue, *ray_base, *ray_pix;
     int32_t *ray_hit;
     float *ray_t;
     float4 *ray_col, *ray_pos;
 
+    __device__ void setup(uint32_t r, float o[3], float d[3]) const { lens_ray(fc, queue, ray_base, ray_pix, r, o, d); }
+
+    __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
+    {
+        lens_finish(S, fc, ray_hit, ray_t, ray_col, ray_pos, r, o, d, h);
+    }
+};
+
+// Lens rays of all frames of a batch: ray r belongs to the last job whose
+// first ray is at or before r; each lane traces against its own job's scene.
+struct BatchRays {
+    static constexpr bool kPerLaneScene = true;
+    const Job *jobs;
+    const BatchHead *head;
+    int njobs;
+
+    __device__ int job_of(uint32_t r) const
+    {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (head->ray_off[mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+
+    __device__ SceneArgs scene(uint32_t r) const { return jobs[job_of(r)].scene; }
+
     __device__ void setup(uint32_t r, float o[3], float d[3]) const
     {
-        const uint32_t j = ray_pix[r];
-        const uint32_t q = queue[j];
-        const uint32_t k = r - ray_base[j];
-        const int x = (int)(q % (uint32_t)fc.hw), y = (int)(q / (uint32_t)fc.hw);
-        float fv[3], pf[3];
-        pixel_dir(fc.cur, x, y, fc.hw, fc.hh, fv);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
-        float lx, ly;
-        lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) o[a] = fc.cur.pos[a] + fc.half_a * (lx * fc.cur.right[a] + ly * fc.cur.up[a]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) d[a] = pf[a] - o[a];
-        float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) d[a] = d[a] / len;
+        const int j = job_of(r);
+        const Job &J = jobs[j];
+        lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, r - head->ray_off[j], o, d);
     }
 
     __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
     {
-        if (h.id != ~0u) {
-            float P0 = o[0] + h.t * d[0], P1 = o[1] + h.t * d[1], P2 = o[2] + h.t * d[2];
-            float z = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
-                      (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
-            Shaded s = dof::shade(S, shade, h.leaf, d);
-            ray_hit[r] = (int32_t)h.id;
-            ray_t[r] = h.t;
-            ray_col[r] = make_float4(s.r, s.g, s.b, z);
-            ray_pos[r] = make_float4(P0, P1, P2, 0.0f);
-        } else {
-            ray_hit[r] = -1;
-            ray_t[r] = INFINITY;
-            ray_col[r] = make_float4(shade.sky[0], shade.sky[1], shade.sky[2], INFINITY);
-            ray_pos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
+        const int j = job_of(r);
+        const Job &J = jobs[j];
+        lens_finish(S, J.fc, J.P.ray_hit, J.P.ray_t, J.P.ray_col, J.P.ray_pos, r - head->ray_off[j], o, d, h);
     }
 };
 
 struct PinholeRays {
+    static constexpr bool kPerLaneScene = false;
     FrameConst fc;
     SceneShade shade;
     void *colour;
@@ -312,6 +356,7 @@ struct PinholeRays {
 };
 
 struct RawRays {
+    static constexpr bool kPerLaneScene = false;
     const float *org, *dir;
     int32_t *hit;
     float *t;
@@ -361,6 +406,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
     int nq = 0;
     bool trav = false;   // the lane still has an inner node to visit
+    SceneArgs Sl = S;    // scene of the lane's ray (differs per lane in a batch)
 
     while (true) {
         const uint64_t idle = __ballot(!active && !exhausted);
@@ -372,6 +418,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             if (!active && !exhausted) {
                 item = base + (uint32_t)__popcll(idle & lt);
                 if (item < N) {
+                    if constexpr (Src::kPerLaneScene) Sl = src.scene(item);
                     src.setup(item, o, d);
                     wr = make_wray(o, d);
                     h = Hit{INFINITY, ~0u, 0u};
@@ -380,7 +427,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     ns = 0;
                     nq = 0;
                     active = true;
-                    if (S.ntri == 1) {
+                    if (Sl.ntri == 1) {
                         trav = false;
                         q0 = 0u;
                         nq = 1;
@@ -402,7 +449,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
         if (__ballot(must) != 0ull || __popcll(__ballot(want)) >= kLeafBatch) {
             if (want) {
                 ++tests;
-                consider_leaf(S, wr, q0, h);
+                consider_leaf(Sl, wr, q0, h);
                 q0 = q1; q1 = q2; q2 = q3;
                 --nq;
             }
@@ -410,7 +457,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
 #pragma unroll
         for (int step = 0; step < 2; ++step) {
             if (!(active && trav && nq <= 2)) continue;
-            const BvhNode nd = S.nodes[node];
+            const BvhNode nd = Sl.nodes[node];
             ++visits;
             const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
             float tl, tr;
@@ -456,7 +503,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             }
         }
         if (active && !trav && nq == 0) {
-            src.finish(S, item, o, d, h);
+            src.finish(Sl, item, o, d, h);
             active = false;
         }
     }
@@ -478,15 +525,33 @@ __global__ void k_zero_u32(uint32_t *p, int n)
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
+// First ray of every job of a batch (exclusive prefix of the jobs' ray
+// counts), the batch total, and cleared traversal counters.
+__global__ void kb_ray_offsets(BatchHead *head, const Job *__restrict__ jobs, int njobs)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int j = 0; j < njobs; ++j) {
+        head->ray_off[j] = acc;
+        acc += jobs[j].P.counters[kCntRays];
+    }
+    head->ray_off[njobs] = acc;
+    head->rays = acc;
+    head->work = 0u;
+    head->visits = 0ull;
+    head->tests = 0ull;
+}
+
 int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks ? kMaxTraceBlocks : blocks); }
 
 }  // namespace
 
-int trace_blocks_per_cu()
+int trace_blocks_per_cu(bool batch)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<LensRays>, kTB, 0) != hipSuccess) return 0;
-    return n;
+    const hipError_t e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<BatchRays>, kTB, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<LensRays>, kTB, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, int blocks,
@@ -494,7 +559,6 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
 {
     LensRays src;
     src.fc = fc;
-    src.shade = fc.shade;
     src.queue = reinterpret_cast<const uint32_t *>(scratch + L.queue);
     src.ray_base = reinterpret_cast<const uint32_t *>(scratch + L.ray_base);
     src.ray_pix = reinterpret_cast<const uint32_t *>(scratch + L.ray_pix);
@@ -534,6 +598,16 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
     k_traverse<RawRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux, s.spill,
                                                               nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
+                              hipStream_t st)
+{
+    kb_ray_offsets<<<1, 64, 0, st>>>(head, jobs, njobs);
+    BatchRays src{jobs, head, njobs};
+    k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
+                                                                &head->visits);
     return hipGetLastError();
 }
 

@@ -61,6 +61,11 @@ class DofFrameOut(C.Structure):
     _fields_ = [("colour", C.c_void_p), ("colour_format", C.c_int32), ("mask", C.c_void_p), ("stats", C.c_void_p)]
 
 
+class DofBatchItem(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("camera", DofCamera), ("lens", DofLens), ("gbuffer", DofGBuffer),
+                ("history", DofHistoryIO), ("out", DofFrameOut), ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+
+
 class DofSceneDesc(C.Structure):
     _fields_ = [("ntri", C.c_int32), ("verts", C.c_void_p), ("albedo", C.c_void_p), ("light_dir", _f3),
                 ("light_rad", _f3), ("ambient", _f3), ("sky", _f3)]
@@ -83,7 +88,8 @@ class DofDebugView(C.Structure):
 EXPORTS = ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_scene_bytes", "dof_create_scene",
            "dof_build_bvh", "dof_bvh_view_get", "dof_destroy_scene", "dof_trace_rays", "dof_render_gbuffer",
            "dof_history_bytes", "dof_history_reset", "dof_frame_scratch_bytes", "dof_render_frame",
-           "dof_debug_view_get", "dof_stage_times")
+           "dof_debug_view_get", "dof_stage_times", "dof_batch_bytes", "dof_batch_create", "dof_batch_set",
+           "dof_batch_run", "dof_batch_destroy")
 
 STAGES = ("reduce", "dilate", "prefilter", "gather", "median", "mask", "compact", "trace", "resolve", "temporal",
           "blur_median_mips", "recon", "composite")
@@ -124,8 +130,15 @@ def lib():
                                        P(DofParams), P(DofFrameOut), vp, C.c_size_t, vp]
         L.dof_debug_view_get.argtypes = [vp, C.c_int32, C.c_int32, P(DofParams), P(DofDebugView)]
         L.dof_stage_times.argtypes = [vp, P(C.c_float), C.c_int32, P(C.c_int32)]
+        L.dof_batch_bytes.argtypes = [C.c_int32, P(C.c_size_t)]
+        L.dof_batch_create.argtypes = [vp, C.c_size_t, C.c_int32, P(vp)]
+        L.dof_batch_set.argtypes = [vp, P(DofBatchItem), C.c_int32, P(DofParams), vp]
+        L.dof_batch_run.argtypes = [vp, vp, vp]
+        L.dof_batch_destroy.argtypes = [vp]
+        L.dof_batch_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene"):
+            if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
+                            "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
         if L.dof_abi_version() != 1:
             raise ImportError("libdof ABI version mismatch")
@@ -265,7 +278,8 @@ class Frame:
         self.mask = torch.empty((H // 2, W // 2), dtype=torch.uint8, device=device)
         self.stats = torch.zeros(8, dtype=torch.int32, device=device)
 
-    def render(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False):
+    def item(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False):
+        """The frame's arguments as one batch item (see Batch)."""
         colour, depth, normal = gb
         cf = RGBA32F if colour.dtype == torch.float32 else RGBA16F
         nf = RGBA32F if normal.dtype == torch.float32 else RGBA16F
@@ -275,9 +289,14 @@ class Frame:
                            lens_struct(prev_lens if prev_lens is not None else lens),
                            1 if (reset or hist_in is None or prev_cam is None) else 0)
         out = DofFrameOut(_ptr(self.colour), self.out_format, _ptr(self.mask), _ptr(self.stats))
-        c, l = camera_struct(cam), lens_struct(lens)
-        check(lib().dof_render_frame(scene.handle, C.byref(c), C.byref(l), C.byref(g), C.byref(hio),
-                                     C.byref(self.ps), C.byref(out), _ptr(self.scratch), self.nbytes, _stream()))
+        return DofBatchItem(scene.handle, camera_struct(cam), lens_struct(lens), g, hio, out, _ptr(self.scratch),
+                            self.nbytes)
+
+    def render(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False):
+        it = self.item(scene, cam, lens, gb, hist_in, hist_out, prev_cam, prev_lens, reset)
+        check(lib().dof_render_frame(it.scene, C.byref(it.camera), C.byref(it.lens), C.byref(it.gbuffer),
+                                     C.byref(it.history), C.byref(self.ps), C.byref(it.out), it.scratch,
+                                     it.scratch_bytes, _stream()))
 
     def debug(self):
         """Host copies of every intermediate plane (synchronises)."""
@@ -321,3 +340,45 @@ class Frame:
 
     def _view(self, off, nbytes, dtype):
         return self.scratch[off:off + nbytes].view(dtype)
+
+
+class Batch:
+    """Frames of several sessions rendered with one launch per stage.
+
+    set() takes Frame.item(...) records (each frame keeps its own scratch and
+    outputs) and uploads the item table; run() launches the pass for all of
+    them on the current stream and can be captured in a graph.  Totals of
+    the last run (frames, rays, node visits, triangle tests) are in stats.
+    """
+
+    def __init__(self, max_items, params, device="cuda", trace_blocks=0):
+        nb = C.c_size_t()
+        check(lib().dof_batch_bytes(max_items, C.byref(nb)))
+        self.table = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(lib().dof_batch_create(_ptr(self.table), nb.value, max_items, C.byref(h)))
+        self.handle = h
+        self.max_items = max_items
+        self.ps = params_struct(params, trace_blocks, False)
+        self.stats = torch.zeros(6, dtype=torch.int32, device=device)
+        self._lib = lib()
+
+    def set(self, items):
+        arr = (DofBatchItem * len(items))(*items)
+        check(lib().dof_batch_set(self.handle, arr, len(items), C.byref(self.ps), _stream()))
+
+    def run(self):
+        check(lib().dof_batch_run(self.handle, _ptr(self.stats), _stream()))
+
+    def totals(self):
+        """(frames, rays, node visits, triangle tests) of the last run (synchronises)."""
+        s = self.stats.cpu().numpy()
+        s64 = s.view(np.int64)
+        return int(s[0]), int(s[1]), int(s64[1]), int(s64[2])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self._lib.dof_batch_destroy(h)
+            self.handle = None
+

@@ -253,11 +253,11 @@ def scene_small(seed: int = BASE_SEED + 1000) -> tuple:
 
 
 def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
-                n_blades: int = 50000) -> tuple:
+                n_blades: int = 50000, width: int = 1920, height: int = 1080) -> tuple:
     """1920x1080 workload: ground quad, 4096 UV spheres of 240 triangles over
     depth 5-80 and a foreground grass band of 50k 4-triangle blades at depth
     0.5-3 (1,183,042 triangles).  Returns (scene, camera_path(60), lens,
-    params)."""
+    params).  Other sizes and counts give the same kind of scene."""
     rng = SplitMix64(seed)
     lens = Lens(focal=0.050, fnum=1.4, focus=15.0, sensor=0.036)
     tx = half_fov_tan(lens)
@@ -304,8 +304,33 @@ def scene_1080p(seed: int = BASE_SEED + 2000, n_spheres: int = 4096,
     verts = np.concatenate([ground, st, gt]).astype(np.float32)
     albedo = np.concatenate([gal, salb, galb]).astype(np.float32)
     scene = Scene(verts, albedo, light_dir=f32tuple(_normalize((-0.3, -1.0, 0.5))))
-    cams = camera_spline(rng, 60, 1920, 1080, seed & 0xFFFFFFFF)
+    cams = camera_spline(rng, 60, width, height, seed & 0xFFFFFFFF)
     return scene, cams, lens, Params(m=8)
+
+
+SESSION_SIZES = ((1280, 720), (1920, 1080), (2560, 1440))
+
+
+def session_specs(n: int, seed: int = BASE_SEED + 4000) -> list:
+    """n sessions of the batched workload: resolution uniform over 720p /
+    1080p / 1440p, triangle budget uniform in [0.2M, 1M] split between
+    spheres and grass in the 1080p scene's proportion.  Returns
+    (seed, width, height, n_spheres, n_blades) per session."""
+    rng = SplitMix64(seed)
+    cls = rng.uniform(n)
+    tri = rng.uniform(n, 0.2e6, 1.0e6)
+    out = []
+    for i in range(n):
+        w, h = SESSION_SIZES[min(int(cls[i] * 3), 2)]
+        scale = tri[i] / 1183042.0
+        out.append((seed + 1 + i, w, h, max(1, int(round(4096 * scale))), max(1, int(round(50000 * scale)))))
+    return out
+
+
+def scene_session(spec: tuple) -> tuple:
+    """One session of the batched workload (see session_specs)."""
+    sd, w, h, ns, nb = spec
+    return scene_1080p(seed=sd, n_spheres=ns, n_blades=nb, width=w, height=h)
 
 
 def scene_4k(seed: int = BASE_SEED + 3000, n_boxes: int = 130000, n_links: int = 200000) -> tuple:

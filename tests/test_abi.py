@@ -97,3 +97,28 @@ def test_render_rejects_bad_arguments_before_device_work(dof):
     offs = [getattr(v, f) - base for f in dof.DEBUG_FIELDS]
     assert all(0 <= o < b.value for o in offs) and len(set(offs)) == len(offs)
     assert all(o % 256 == 0 for o in offs)
+
+
+def test_batch_entry_points_check_arguments_on_the_host(dof):
+    L = dof.lib()
+    b = C.c_size_t()
+    assert L.dof_batch_bytes(0, C.byref(b)) == dof.DOF_E_INVALID
+    assert L.dof_batch_bytes(129, C.byref(b)) == dof.DOF_E_INVALID
+    assert L.dof_batch_bytes(1, C.byref(b)) == 0
+    one = b.value
+    assert L.dof_batch_bytes(32, C.byref(b)) == 0 and b.value > one and b.value % 256 == 0
+    need = b.value
+    h = C.c_void_p()
+    base = 1 << 40      # never dereferenced on the host
+    assert L.dof_batch_create(C.c_void_p(base + 8), need, 32, C.byref(h)) == dof.DOF_E_INVALID   # misaligned
+    assert L.dof_batch_create(C.c_void_p(base), need - 1, 32, C.byref(h)) == dof.DOF_E_NOMEM
+    assert L.dof_batch_create(C.c_void_p(base), need, 32, C.byref(h)) == 0 and h.value
+    p = dof.DofParams()
+    L.dof_default_params(C.byref(p))
+    items = (dof.DofBatchItem * 2)()
+    assert L.dof_batch_run(h, None, None) == dof.DOF_E_STATE          # nothing set yet
+    assert L.dof_batch_set(h, items, 0, C.byref(p), None) == dof.DOF_E_INVALID
+    assert L.dof_batch_set(h, items, 2, C.byref(p), None) == dof.DOF_E_INVALID   # null scene
+    assert b"item 0" in L.dof_last_error()
+    assert L.dof_batch_run(h, None, None) == dof.DOF_E_STATE
+    L.dof_batch_destroy(h)
