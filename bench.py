@@ -12,6 +12,14 @@ pass); the G-buffers are rendered beforehand and stay resident in HBM.
 Prints one JSON line: frames/s (value), masked Grays/s, p50/p99 frame ms,
 per-stage device ms, the roofline of the dominant kernel (live HIP-event
 timing) and the CPU oracle's frames/s on a bounded sample.
+
+A second measurement ("batched") renders 32 sessions at once -- each its own
+seeded scene of 0.2M-1M triangles at 720p, 1080p or 1440p with its own
+history -- as per-session launches, as one batched launch per stage, and as
+that batched run replayed from a HIP graph.  A third ("serving") serves 64
+sessions (720p to 4K) whose frame requests arrive as Poisson processes at
+60 Hz each, with continuous batching and, for comparison, one frame at a
+time: frames/s and p50/p99 request latency.
 """
 
 import argparse
@@ -53,6 +61,10 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
+    ap.add_argument("--batched-sessions", type=int, default=32, help="sessions of the batched measurement (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--serving-sessions", type=int, default=64, help="sessions of the serving measurement (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -226,6 +238,15 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy} MiB")
 
+    batched = None
+    if args.batched_sessions > 0:
+        del fr, frt, gbs, hist
+        batched = batched_leg(args.batched_sessions, args.batched_steps, 2, log)
+
+    serving = None
+    if args.serving_sessions > 0:
+        serving = serving_leg(args.serving_sessions, args.serving_seconds, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, cams, lens, params, args.cpu_seconds, log)
@@ -259,8 +280,155 @@ def main():
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(n_sessions, steps, warmup, log):
+    """Frames/s of n sessions rendered per step as per-session launches, as
+    one batched launch per stage, and as a graph replay of the batched run.
+    G-buffers are rendered before each step, outside the timed region."""
+    import numpy as np
+    import torch
+
+    from paper_2210_06158_amd import dof, sessions, synth
+
+    specs = synth.session_specs(n_sessions)
+    ss = [sessions.Session.from_spec(sp, m=8) for sp in specs]
+    torch.cuda.synchronize()
+    px = sum(s.W * s.H for s in ss)
+    tris = sum(s.ntri for s in ss)
+    log(f"batched: {n_sessions} sessions, {px / 1e6:.1f} Mpx and {tris / 1e6:.1f} Mtri per step, "
+        f"{sum(s.bytes for s in ss) / 2**30:.1f} GiB resident")
+    batch = dof.Batch(n_sessions, ss[0].params)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(mode, graph=None):
+        for s in ss:
+            s.done = 0
+        times, rays = [], 0
+        for k in range(warmup + steps):
+            for s in ss:
+                s.prepare(k)
+            torch.cuda.synchronize()
+            e0.record()
+            if mode == "single":
+                for s in ss:
+                    s.render()
+            else:
+                batch.set([s.item() for s in ss])
+                if graph is None:
+                    batch.run()
+                else:
+                    graph.replay()
+                for s in ss:
+                    s.advance()
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                times.append(e0.elapsed_time(e1))
+                if mode == "single":
+                    rays += sum(int(s.frame.stats[1].item()) for s in ss)
+                else:
+                    rays += batch.totals()[1]
+        finals = [s.frame.colour.clone() for s in ss]
+        return np.array(times), rays, finals
+
+    t_single, r_single, c_single = run("single")
+    t_batch, r_batch, c_batch = run("batch")
+    # capture the batched run (table of step 0 set, one eager run as warm-up)
+    for s in ss:
+        s.done = 0
+        s.prepare(0)
+    batch.set([s.item() for s in ss])
+    batch.run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            batch.run()
+    torch.cuda.synchronize()
+    t_graph, r_graph, c_graph = run("graph", g)
+    same = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in zip(c_single, c_batch, c_graph))
+    fps = {m: n_sessions * steps / (t.sum() * 1e-3) for m, t in (("single", t_single), ("batch", t_batch),
+                                                                  ("graph", t_graph))}
+    res = {}
+    for s in ss:
+        res[f"{s.W}x{s.H}"] = res.get(f"{s.W}x{s.H}", 0) + 1
+    out = {
+        "workload": f"{n_sessions} sessions, each its own seeded scene (0.2M-1M triangles) and history, "
+                    "resolutions uniform over 720p/1080p/1440p, m=8, FP16 G-buffer and output",
+        "sessions": n_sessions,
+        "resolutions": res,
+        "megapixels_per_step": round(px / 1e6, 2),
+        "triangles": tris,
+        "steps": steps,
+        "rays_per_step": round(r_batch / steps, 1),
+        "per_session_launches_frames_per_s": round(fps["single"], 2),
+        "batched_frames_per_s": round(fps["batch"], 2),
+        "batched_graph_frames_per_s": round(fps["graph"], 2),
+        "speedup_batched_vs_per_session": round(fps["batch"] / fps["single"], 3),
+        "step_ms": {m: {"p50": round(float(np.percentile(t, 50)), 3), "p99": round(float(np.percentile(t, 99)), 3)}
+                    for m, t in (("per_session", t_single), ("batched", t_batch), ("graph", t_graph))},
+        "masked_grays_per_s_batched": round(r_batch / (t_batch.sum() * 1e-3) / 1e9, 4),
+        "outputs_identical_across_modes": bool(same),
+        "rays_identical_across_modes": r_single == r_batch == r_graph,
+    }
+    log(f"batched: {out}")
+    del ss, batch, g
+    torch.cuda.synchronize()
+    return out
+
+
+def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
+    """Continuous batching vs one frame at a time on the same Poisson request
+    stream (sessions admitted under an HBM budget)."""
+    import torch
+
+    from paper_2210_06158_amd import serve, synth
+
+    params = synth.Params(m=8)
+    srv = serve.Server(budget_gib << 30, params, max_batch=32, max_inflight=2, ring=4)
+    specs = serve.serving_specs(n_sessions)
+    admitted = sum(srv.admit(sp) for sp in specs)
+    torch.cuda.synchronize()
+    log(f"serving: {admitted}/{n_sessions} sessions admitted, {srv.used / 2**30:.1f} GiB resident")
+    arrivals = serve.poisson_arrivals(n_sessions, rate_hz, seconds, seed=synth.BASE_SEED + 6100)
+    warm = serve.poisson_arrivals(n_sessions, rate_hz, 0.3, seed=synth.BASE_SEED + 6200)
+
+    def run(mode, mb, mi):
+        srv.run(warm, 0.3, mode=mode, max_batch=mb, max_inflight=mi)
+        return srv.run(arrivals, seconds, mode=mode, max_batch=mb, max_inflight=mi)
+
+    single = run("single", 1, 1)
+    single2 = run("single", 1, 2)
+    batched = {mb: run("batched", mb, 2) for mb in (8, 16, 32)}
+    res = {}
+    for s in srv.sessions:
+        key = f"{s.W}x{s.H}"
+        res[key] = res.get(key, 0) + 1
+    out = {
+        "workload": f"{n_sessions} sessions, resolutions uniform over 720p/1080p/1440p/4K, 0.2M-1M triangles each, "
+                    f"Poisson requests at {rate_hz:g} Hz per session for {seconds:g} s, m=8, newest request of a "
+                    "session supersedes a waiting one",
+        "sessions_admitted": admitted,
+        "resident_gib": round(srv.used / 2**30, 2),
+        "budget_gib": budget_gib,
+        "resolutions": res,
+        "offered_frames_per_s": round(len(arrivals) / seconds, 1),
+        "one_frame_at_a_time": single,
+        "single_frames_two_streams": single2,
+        "batched": {f"max_batch_{k}": v for k, v in batched.items()},
+        "speedup_frames_per_s_batched32_vs_one_at_a_time": round(batched[32]["frames_per_s"] /
+                                                                 max(single["frames_per_s"], 1e-9), 3),
+    }
+    log(f"serving: {out}")
+    del srv
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(scene, cams, lens, params, budget_s, log):

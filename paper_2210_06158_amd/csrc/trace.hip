@@ -280,38 +280,52 @@ struct LensRays {
 };
 
 // Lens rays of all frames of a batch: ray r belongs to the last job whose
-// first ray is at or before r; each lane traces against its own job's scene.
+// first ray is at or before r (found in an LDS copy of the jobs' first rays);
+// each lane remembers its ray's job and traces against that job's scene.
 struct BatchRays {
     static constexpr bool kPerLaneScene = true;
     const Job *jobs;
     const BatchHead *head;
     int njobs;
 
+    __device__ static uint32_t *offsets()
+    {
+        __shared__ uint32_t off[kMaxBatch + 1];
+        return off;
+    }
+
+    __device__ void init() const
+    {
+        uint32_t *off = offsets();
+        for (int j = threadIdx.x; j <= njobs; j += blockDim.x) off[j] = head->ray_off[j];
+        __syncthreads();
+    }
+
     __device__ int job_of(uint32_t r) const
     {
+        const uint32_t *off = offsets();
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (head->ray_off[mid] <= r) lo = mid;
+            if (off[mid] <= r) lo = mid;
             else hi = mid - 1;
         }
         return lo;
     }
 
-    __device__ SceneArgs scene(uint32_t r) const { return jobs[job_of(r)].scene; }
+    __device__ SceneArgs scene(int j) const { return jobs[j].scene; }
 
-    __device__ void setup(uint32_t r, float o[3], float d[3]) const
+    __device__ void setup(uint32_t r, int j, float o[3], float d[3]) const
     {
-        const int j = job_of(r);
         const Job &J = jobs[j];
-        lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, r - head->ray_off[j], o, d);
+        lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, r - offsets()[j], o, d);
     }
 
-    __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
+    __device__ void finish(const SceneArgs &S, uint32_t r, int j, const float o[3], const float d[3],
+                           const Hit &h) const
     {
-        const int j = job_of(r);
         const Job &J = jobs[j];
-        lens_finish(S, J.fc, J.P.ray_hit, J.P.ray_t, J.P.ray_col, J.P.ray_pos, r - head->ray_off[j], o, d, h);
+        lens_finish(S, J.fc, J.P.ray_hit, J.P.ray_t, J.P.ray_col, J.P.ray_pos, r - offsets()[j], o, d, h);
     }
 };
 
@@ -407,6 +421,8 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     int nq = 0;
     bool trav = false;   // the lane still has an inner node to visit
     SceneArgs Sl = S;    // scene of the lane's ray (differs per lane in a batch)
+    int job = 0;         // job of the lane's ray (batches)
+    if constexpr (Src::kPerLaneScene) src.init();
 
     while (true) {
         const uint64_t idle = __ballot(!active && !exhausted);
@@ -418,8 +434,13 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             if (!active && !exhausted) {
                 item = base + (uint32_t)__popcll(idle & lt);
                 if (item < N) {
-                    if constexpr (Src::kPerLaneScene) Sl = src.scene(item);
-                    src.setup(item, o, d);
+                    if constexpr (Src::kPerLaneScene) {
+                        job = src.job_of(item);
+                        Sl = src.scene(job);
+                        src.setup(item, job, o, d);
+                    } else {
+                        src.setup(item, o, d);
+                    }
                     wr = make_wray(o, d);
                     h = Hit{INFINITY, ~0u, 0u};
                     node = 0;
@@ -503,7 +524,8 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             }
         }
         if (active && !trav && nq == 0) {
-            src.finish(Sl, item, o, d, h);
+            if constexpr (Src::kPerLaneScene) src.finish(Sl, item, job, o, d, h);
+            else src.finish(Sl, item, o, d, h);
             active = false;
         }
     }
@@ -608,6 +630,23 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint3
     BatchRays src{jobs, head, njobs};
     k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
                                                                 &head->visits);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_job(const Job &J, uint32_t *spill, int blocks, hipStream_t st)
+{
+    LensRays src;
+    src.fc = J.fc;
+    src.queue = J.P.queue;
+    src.ray_base = J.P.ray_base;
+    src.ray_pix = J.P.ray_pix;
+    src.ray_hit = J.P.ray_hit;
+    src.ray_t = J.P.ray_t;
+    src.ray_col = J.P.ray_col;
+    src.ray_pos = J.P.ray_pos;
+    uint32_t *cnt = J.P.counters;
+    k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(J.scene, src, 0u, cnt + kCntRays, cnt + kCntWork, spill,
+                                                               reinterpret_cast<unsigned long long *>(cnt + kCntVisits));
     return hipGetLastError();
 }
 

@@ -226,9 +226,17 @@ class Scene:
         colour = torch.empty((H, W, 4), dtype=dt, device=device)
         normal = torch.empty((H, W, 4), dtype=dt, device=device)
         depth = torch.empty((H, W), dtype=torch.float32, device=device)
+        return self.render_gbuffer_into(cam, lens, colour, depth, normal)
+
+    def render_gbuffer_into(self, cam, lens, colour, depth, normal):
+        """Pinhole G-buffer into caller tensors (colour/normal FP32 or FP16)."""
+        assert colour.shape == (cam.height, cam.width, 4) and normal.shape == colour.shape
+        assert depth.shape == (cam.height, cam.width) and depth.dtype == torch.float32
+        cf = RGBA32F if colour.dtype == torch.float32 else RGBA16F
+        nf = RGBA32F if normal.dtype == torch.float32 else RGBA16F
         c, l = camera_struct(cam), lens_struct(lens)
-        check(lib().dof_render_gbuffer(self.handle, C.byref(c), C.byref(l), _ptr(colour), fmt, _ptr(depth),
-                                       _ptr(normal), fmt, _stream()))
+        check(lib().dof_render_gbuffer(self.handle, C.byref(c), C.byref(l), _ptr(colour), cf, _ptr(depth),
+                                       _ptr(normal), nf, _stream()))
         return colour, depth, normal
 
     def stage_times(self):
@@ -244,6 +252,12 @@ class Scene:
                 _lib.dof_destroy_scene(self.handle)
         except Exception:
             pass
+
+
+def scene_bytes(ntri) -> int:
+    b = C.c_size_t()
+    check(lib().dof_scene_bytes(ntri, C.byref(b)))
+    return b.value
 
 
 def history_bytes(W, H) -> int:
