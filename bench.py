@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
+    ap.add_argument("--uhd-steps", type=int, default=60, help="frames of the 3840x2160 measurement (0 = skip)")
     ap.add_argument("--batched-sessions", type=int, default=32, help="sessions of the batched measurement (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--serving-sessions", type=int, default=64, help="sessions of the serving measurement (0 = skip)")
@@ -87,8 +88,8 @@ def stage_bytes(stage, W, H, P, R):
         "trace": R * (12 + 40),                     # queue/base/pixel of each ray in; hit, t, colour, position out
         "resolve": R * 40 + P * 64,
         "temporal": h * (1 + 4 + 64 + 52) + h * (32 + 48),
-        "blur_median_mips": h * (16 + 4) + h * (4 + 4 + 16 + 16) + h * 16 // 3,
-        "recon": h * (16 + 16 + 16 + 4) + h * 16,
+        "blur_median_mips": h * (16 + 4) + h * (4 + 4 + 8 + 16 + 16) + h * 16 // 3,
+        "recon": h * (16 + 16 + 8 + 16 + 4) + h * 16,
         "composite": F * (8 + 4) + h * (16 + 16 + 16 + 16) + F * 8,
     }
     return table[stage]
@@ -113,6 +114,97 @@ def measured_traffic():
     fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
     write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
     return int(fetch + write)
+
+
+def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_blocks, log):
+    """Render steps frames of a camera path (after warmup frames) with one
+    dof_render_frame each, history ping-pong, then stage_frames more with
+    per-stage HIP events.  Returns timing and counter totals."""
+    import numpy as np
+    import torch
+
+    from paper_2210_06158_amd import dof
+
+    W, H = cams[0].width, cams[0].height
+    nfr = len(cams)
+    hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
+    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=trace_blocks)
+
+    def step(i, frame):
+        f = i % nfr
+        prev = cams[f - 1] if f > 0 else None
+        frame.render(gs, cams[f], lenses[f], gbs[f], hist[(i + 1) % 2] if prev is not None else None, hist[i % 2],
+                     prev_cam=prev, prev_lens=lenses[f - 1] if f > 0 else None)
+
+    for i in range(warmup):
+        step(i, fr)
+    torch.cuda.synchronize()
+    K = steps
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    stats = torch.zeros((K, 8), dtype=torch.int32, device="cuda")
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for k in range(K):
+        starts[k].record()
+        step(warmup + k, fr)
+        ends[k].record()
+        stats[k].copy_(fr.stats, non_blocking=True)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    frame_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    st = stats.cpu().numpy()
+    st64 = st.view(np.int64)
+    log(f"timed {K} frames of {W}x{H}: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
+
+    # live per-stage timing (same workload, HIP events around every stage)
+    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True, trace_blocks=trace_blocks)
+    sums = {s: 0.0 for s in dof.STAGES}
+    t_rays = t_masked = t_visits = t_tests = 0
+    nst = min(stage_frames, K)
+    for k in range(nst):
+        step(warmup + k, frt)
+        for s, v in gs.stage_times().items():
+            sums[s] += v
+        sv = frt.stats.cpu().numpy()
+        t_masked += int(sv[0])
+        t_rays += int(sv[1])
+        t_visits += int(sv.view(np.int64)[1])
+        t_tests += int(sv.view(np.int64)[2])
+    return dict(W=W, H=H, K=K, total_ms=total_ms, frame_ms=frame_ms, rays=int(st[:, 1].astype(np.int64).sum()),
+                masked=int(st[:, 0].astype(np.int64).sum()), visits=int(st64[:, 1].sum()),
+                tests=int(st64[:, 2].sum()), stage_ms={s: v / nst for s, v in sums.items()},
+                stage_frames=nst, t_rays=t_rays, t_masked=t_masked, t_visits=t_visits, t_tests=t_tests)
+
+
+def stage_roofline(r):
+    """Per-stage compulsory HBM bytes and achieved fraction of 8 TB/s."""
+    W, H, nst = r["W"], r["H"], r["stage_frames"]
+    P, R = r["t_masked"] / nst, r["t_rays"] / nst
+    out = {}
+    for s, ms in r["stage_ms"].items():
+        b = stage_bytes(s, W, H, P, R)
+        gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out[s] = {"ms": round(ms, 5), "bytes": int(b), "GB_per_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def trace_roofline(r):
+    """Roofline of the traversal: FP32 vector ALU peak, FLOPs from the
+    measured visit and test counts."""
+    nst = r["stage_frames"]
+    flops = (FLOP_PER_VISIT * r["t_visits"] + FLOP_PER_TRI_TEST * r["t_tests"]) / nst
+    ms = r["stage_ms"]["trace"]
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"kernel": "trace (k_traverse<LensRays>)", "bound": "alu", "achieved": round(achieved, 3),
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5),
+            "flop_per_launch": int(flops), "ms_per_launch": round(ms, 5),
+            "compulsory_bytes_per_launch": int(stage_bytes("trace", r["W"], r["H"], r["t_masked"] / nst,
+                                                           r["t_rays"] / nst))}
 
 
 def main():
@@ -151,83 +243,26 @@ def main():
 
     gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in cams]
     torch.cuda.synchronize()
-    hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
-    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=args.trace_blocks)
-
-    def step(i, frame):
-        f = i % nfr
-        prev = cams[f - 1] if f > 0 else None
-        frame.render(gs, cams[f], lens, gbs[f], hist[(i + 1) % 2] if prev is not None else None, hist[i % 2],
-                     prev_cam=prev, prev_lens=lens)
-
-    for i in range(args.warmup):
-        step(i, fr)
-    torch.cuda.synchronize()
-
-    K = args.steps
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    stats = torch.zeros((K, 8), dtype=torch.int32, device=dev)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t0.record()
-    for k in range(K):
-        starts[k].record()
-        step(args.warmup + k, fr)
-        ends[k].record()
-        stats[k].copy_(fr.stats, non_blocking=True)
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t0.elapsed_time(t1)
-    frame_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    st = stats.cpu().numpy()
-    rays = int(st[:, 1].astype(np.int64).sum())
-    masked = int(st[:, 0].astype(np.int64).sum())
-    st64 = st.view(np.int64)
-    visits, tests = int(st64[:, 1].sum()), int(st64[:, 2].sum())
+    r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, args.trace_blocks,
+                 log)
+    K, total_ms, frame_ms = r["K"], r["total_ms"], r["frame_ms"]
+    rays, masked, visits, tests = r["rays"], r["masked"], r["visits"], r["tests"]
     fps = K / (total_ms / 1e3)
-    log(f"timed {K} frames: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
-
-    # live per-stage timing (same workload, HIP events around every stage)
-    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True, trace_blocks=args.trace_blocks)
-    sums = {s: 0.0 for s in dof.STAGES}
-    t_rays = 0
-    t_masked = 0
-    t_visits = 0
-    t_tests = 0
-    nst = min(args.stage_frames, K)
-    for k in range(nst):
-        step(args.warmup + k, frt)
-        ts = gs.stage_times()
-        for s, v in ts.items():
-            sums[s] += v
-        sv = frt.stats.cpu().numpy()
-        t_masked += int(sv[0])
-        t_rays += int(sv[1])
-        t_visits += int(sv.view(np.int64)[1])
-        t_tests += int(sv.view(np.int64)[2])
-    stage_ms = {s: v / nst for s, v in sums.items()}
+    stage_ms = r["stage_ms"]
     dom = max(stage_ms, key=stage_ms.get)
-    P_avg, R_avg = t_masked / nst, t_rays / nst
+    P_avg, R_avg = r["t_masked"] / r["stage_frames"], r["t_rays"] / r["stage_frames"]
     if dom == "trace":
         # pointer chasing that executes on the vector ALUs: its roofline is
         # the FP32 vector peak, with FLOPs from the measured visit/test counts
-        flops = (FLOP_PER_VISIT * t_visits + FLOP_PER_TRI_TEST * t_tests) / nst
-        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
-        roofline = {"kernel": "trace (k_traverse<LensRays>)", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5),
-                    "traffic": measured_traffic(), "flop_per_launch": int(flops),
-                    "ms_per_launch": round(stage_ms[dom], 5),
-                    "compulsory_bytes_per_launch": int(stage_bytes(dom, W, H, P_avg, R_avg))}
+        roofline = trace_roofline(r)
+        roofline["traffic"] = measured_traffic()
     else:
         dom_bytes = stage_bytes(dom, W, H, P_avg, R_avg)
         achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                     "bytes_per_launch": int(dom_bytes), "ms_per_launch": round(stage_ms[dom], 5)}
-    trace_grays = (t_rays / (sums["trace"] * 1e-3) / 1e9) if sums["trace"] > 0 else None
+    trace_grays = (r["t_rays"] / (stage_ms["trace"] * r["stage_frames"] * 1e-3) / 1e9) if stage_ms["trace"] > 0 else None
 
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
@@ -237,10 +272,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy} MiB")
+    del gbs
+
+    w4k = None
+    if args.uhd_steps > 0:
+        w4k = uhd_leg(args, log)
 
     batched = None
     if args.batched_sessions > 0:
-        del fr, frt, gbs, hist
         batched = batched_leg(args.batched_sessions, args.batched_steps, 2, log)
 
     serving = None
@@ -278,12 +317,48 @@ def main():
         "bvh_build_ms": round(bvh_ms, 3),
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stage_roofline": stage_roofline(r),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "workload_4k": w4k,
         "batched": batched,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def uhd_leg(args, log):
+    """The 3840x2160 workload: box city behind a chain-link fence, 6-blade
+    aperture, focus pulled 3 -> 40 over 60 frames, m = 16."""
+    import numpy as np
+    import torch
+
+    from paper_2210_06158_amd import dof, synth
+
+    scene, cams, lenses, params = synth.scene_4k()
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams, lenses)]
+    torch.cuda.synchronize()
+    r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), args.trace_blocks, log)
+    out = {
+        "workload": "3840x2160, box city (130k boxes) behind a chain-link fence of 200k wire quads at depth 1-2, "
+                    "1,960,002 triangles, 6-blade aperture N=2, focus pulled 3 -> 40 over 60 frames, m=16",
+        "frames": r["K"],
+        "frames_per_s": round(r["K"] / (r["total_ms"] / 1e3), 2),
+        "p50_frame_ms": round(float(np.percentile(r["frame_ms"], 50)), 3),
+        "p99_frame_ms": round(float(np.percentile(r["frame_ms"], 99)), 3),
+        "rays_per_frame": round(r["rays"] / r["K"], 1),
+        "masked_grays_per_s": round(r["rays"] / (r["total_ms"] * 1e-3) / 1e9, 4),
+        "node_visits_per_ray": round(r["visits"] / max(r["rays"], 1), 2),
+        "tri_tests_per_ray": round(r["tests"] / max(r["rays"], 1), 2),
+        "stage_roofline": stage_roofline(r),
+        "trace_roofline": trace_roofline(r),
+    }
+    log(f"4k: {out['frames_per_s']} frames/s")
+    del gbs, gs
+    torch.cuda.synchronize()
+    return out
 
 
 def batched_leg(n_sessions, steps, warmup, log):

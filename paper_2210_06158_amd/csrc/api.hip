@@ -127,6 +127,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m)
         h = (h + 1) >> 1;
     }
     L.mips = take(16 * mt);
+    L.tap = take(8 * np);
     L.recon = take(16 * np);
     L.spill = take(kSpillBytes);
     L.total = off;
@@ -626,7 +627,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         const int64_t np = (int64_t)fc.hw * fc.hh;
         auto cdiv = [](int64_t a, int64_t c) { return (uint32_t)((a + c - 1) / c); };
         const uint32_t bxs[dof::kNumGrids] = {(uint32_t)fc.tw, cdiv(fc.tw, 16), cdiv(fc.hw, 64), (uint32_t)L.nchunks,
-                                              cdiv(np, 256), cdiv(fc.hw, 8), cdiv(fc.W, 64)};
+                                              cdiv(np, 64), cdiv(fc.hw, 8), cdiv(fc.W, 64)};
         const uint32_t bys[dof::kNumGrids] = {(uint32_t)fc.th, cdiv(fc.th, 16), cdiv(fc.hh, 4), 1u, 1u,
                                               cdiv(fc.hh, 8), cdiv(fc.H, 4)};
         for (int g = 0; g < dof::kNumGrids; ++g) {

@@ -95,7 +95,7 @@ struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
-    size_t resolve, temporal, var_blur, rtmed, mips, recon;
+    size_t resolve, temporal, var_blur, rtmed, mips, tap, recon;
     size_t spill;
     size_t total;
     int64_t nchunks;
@@ -115,6 +115,7 @@ struct Planes {
     float4 *ray_col, *ray_pos;
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;
+    float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
 };
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
 
@@ -140,7 +141,7 @@ enum : int {
     kGridDilate,      // tiles in blocks of 16 x 16: dilate
     kGridHalf,        // half-res pixels in blocks of 64 x 4
     kGridChunk,       // compaction chunks
-    kGridResolve,     // half-res pixels in blocks of 256
+    kGridResolve,     // queue entries (at most the half-res pixels) in blocks of 64
     kGridMip,         // half-res pixels in 8 x 8 tiles
     kGridFull,        // full-res pixels in blocks of 64 x 4
     kNumGrids

@@ -161,6 +161,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.var_blur = reinterpret_cast<float *>(s + L.var_blur);
     p.rtmed = reinterpret_cast<float4 *>(s + L.rtmed);
     p.mips = reinterpret_cast<float4 *>(s + L.mips);
+    p.tap = reinterpret_cast<float2 *>(s + L.tap);
     p.recon = reinterpret_cast<float4 *>(s + L.recon);
     return p;
 }
@@ -660,36 +661,65 @@ __global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict_
 
 // ---------------------------------------------------------------- A11
 
-__device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask, const uint32_t bx, const uint32_t by)
+// One wave per 64 consecutive queue entries.  Their rays are one contiguous
+// range (a pixel's rays follow each other in queue order), which the wave
+// stages into LDS in chunks with coalesced loads; each lane then sums its
+// pixel's rays from LDS in ray order, as the single-thread loop would.
+constexpr int kResolveChunk = 512;
+
+__device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
+                                 const uint32_t bx, const uint32_t by)
 {
-    const uint32_t j = bx * 256 + threadIdx.x;
-    if (j >= P.counters[kCntMasked]) return;
-    const uint32_t q = P.queue[j];
-    const int n = mask[q];
-    const uint32_t base = P.ray_base[j];
+    __shared__ float4 s_col[kResolveChunk], s_pos[kResolveChunk];
+    __shared__ int32_t s_hit[kResolveChunk];
+    const uint32_t masked = P.counters[kCntMasked];
+    const uint32_t j0 = bx * 64;
+    if (j0 >= masked) return;
+    const uint32_t j = j0 + threadIdx.x;
+    const bool have = j < masked;
+    uint32_t q = 0, base = 0;
+    int n = 0;
+    if (have) {
+        q = P.queue[j];
+        n = mask[q];
+        base = P.ray_base[j];
+    }
+    const uint32_t jl = min(j0 + 63u, masked - 1u);
+    const uint32_t r0 = P.ray_base[j0], r1 = P.ray_base[jl] + mask[P.queue[jl]];
     float N = 0.0f, sn0 = 0.0f, sn1 = 0.0f, sn2 = 0.0f, sf0 = 0.0f, sf1 = 0.0f, sf2 = 0.0f;
     float scn = 0.0f, scf = 0.0f, fp0 = 0.0f, fp1 = 0.0f, fp2 = 0.0f, fw = 0.0f;
-    for (int k = 0; k < n; ++k) {
-        const uint32_t r = base + k;
-        float4 c = P.ray_col[r];
-        bool hit = P.ray_hit[r] >= 0;
-        float w = hit ? sat(0.5f + (fc.d - c.w) / fc.ramp) : 0.0f;
-        float om = 1.0f - w;
-        float cz = coc_px(fc.cock, fc.d, c.w);
-        N = N + w;
-        sn0 = sn0 + w * c.x; sf0 = sf0 + om * c.x;
-        sn1 = sn1 + w * c.y; sf1 = sf1 + om * c.y;
-        sn2 = sn2 + w * c.z; sf2 = sf2 + om * c.z;
-        scn = scn + w * cz;
-        scf = scf + om * cz;
-        if (hit) {
-            float4 p = P.ray_pos[r];
-            fp0 = fp0 + om * p.x;
-            fp1 = fp1 + om * p.y;
-            fp2 = fp2 + om * p.z;
-            fw = fw + om;
+    for (uint32_t c0 = r0; c0 < r1; c0 += kResolveChunk) {
+        const uint32_t c1 = min(c0 + (uint32_t)kResolveChunk, r1);
+        for (uint32_t r = c0 + threadIdx.x; r < c1; r += 64) {
+            s_col[r - c0] = P.ray_col[r];
+            s_pos[r - c0] = P.ray_pos[r];
+            s_hit[r - c0] = P.ray_hit[r];
         }
+        __syncthreads();
+        const uint32_t kb = max(base, c0), ke = min(base + (uint32_t)n, c1);
+        for (uint32_t r = kb; r < ke; ++r) {
+            const float4 c = s_col[r - c0];
+            const bool hit = s_hit[r - c0] >= 0;
+            float w = hit ? sat(0.5f + (fc.d - c.w) / fc.ramp) : 0.0f;
+            float om = 1.0f - w;
+            float cz = coc_px(fc.cock, fc.d, c.w);
+            N = N + w;
+            sn0 = sn0 + w * c.x; sf0 = sf0 + om * c.x;
+            sn1 = sn1 + w * c.y; sf1 = sf1 + om * c.y;
+            sn2 = sn2 + w * c.z; sf2 = sf2 + om * c.z;
+            scn = scn + w * cz;
+            scf = scf + om * cz;
+            if (hit) {
+                const float4 p = s_pos[r - c0];
+                fp0 = fp0 + om * p.x;
+                fp1 = fp1 + om * p.y;
+                fp2 = fp2 + om * p.z;
+                fw = fw + om;
+            }
+        }
+        __syncthreads();
     }
+    if (!have) return;
     const float nf = (float)n - N;
     const bool hn = N > 0.0f, hf = nf > 0.0f, hp = fw > 0.0f;
     P.R0[q] = make_float4(hn ? sn0 / N : 0.0f, hn ? sn1 / N : 0.0f, hn ? sn2 / N : 0.0f, N);
@@ -698,12 +728,12 @@ __device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const ui
     P.R3[q] = make_float4(hp ? fp0 / fw : 0.0f, hp ? fp1 / fw : 0.0f, hp ? fp2 / fw : 0.0f, hp ? 1.0f : 0.0f);
 }
 
-__global__ __launch_bounds__(256) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
+__global__ __launch_bounds__(64) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
 {
     b_resolve(fc, P, mask, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void kb_resolve(const Job *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(64) void kb_resolve(const Job *__restrict__ jobs, int njobs)
 {
     uint32_t bx, by;
     const Job &J = jobs[job_of_block(jobs, njobs, kGridResolve, blockIdx.x, bx, by)];
@@ -811,7 +841,9 @@ __global__ __launch_bounds__(kBX *kBY) void kb_temporal(const Job *__restrict__ 
 // ---------------------------------------------------------------- A12 blur + A13 median, mips
 // One wave per 8 x 8 tile: variance blur (3x3 binomial), 3x3 median of the
 // ray-traced colour (invalid neighbours replaced by the centre), level 0 of
-// the validity-weighted mip chain, then levels 1..3 of the tile from LDS.
+// the validity-weighted mip chain, then levels 1..3 of the tile from LDS;
+// also the 8-byte record (CoC or -inf, hit ratio) that the reconstruction
+// reads for each of its taps.
 
 __device__ inline void b_blur_median_mips(const FrameConst &fc, const Planes &P, void *hist_out, const uint32_t bx, const uint32_t by)
 {
@@ -835,6 +867,8 @@ __device__ inline void b_blur_median_mips(const FrameConst &fc, const Planes &P,
         P.var_blur[i] = acc;
         hist_wview(hist_out, np).D[i] = acc;
         float4 c = P.T0[i];
+        const float4 t1 = P.T1[i];
+        P.tap[i] = make_float2(c.w > 0.0f ? t1.x : -INFINITY, t1.y);
         float4 med = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (c.w > 0.0f) {
             float4 v[9];
@@ -942,9 +976,10 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
         float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
         int ix = nearest_idx(sx, hw), iy = nearest_idx(sy, hh);
         size_t j = (size_t)iy * hw + ix;
-        if (!(P.T0[j].w > 0.0f)) continue;
-        float4 tj = P.T1[j];
-        if (tj.x * 0.25f < dist) continue;
+        // a tap counts when its pixel is ray traced and its CoC radius
+        // reaches the tap (invalid pixels carry -inf)
+        const float2 tj = P.tap[j];
+        if (!(tj.x * 0.25f >= dist)) continue;
         float4 s0 = bilinear4(mip0, w0, h0, (sx + 0.5f) * sc0 - 0.5f, (sy + 0.5f) * sc0 - 0.5f);
         float4 s1 = bilinear4(mip1, w1, h1, (sx + 0.5f) * sc1 - 0.5f, (sy + 0.5f) * sc1 - 0.5f);
         a0 = a0 + lerp1(s0.x, s1.x, fl);
@@ -1103,7 +1138,7 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
     Planes P = planes(fc, L, scratch);
     const int64_t np = (int64_t)fc.hw * fc.hh;
     DOF_REC(8);
-    k_resolve<<<(unsigned)((np + 255) / 256), 256, 0, st>>>(fc, P, mask);
+    k_resolve<<<(unsigned)((np + 63) / 64), 64, 0, st>>>(fc, P, mask);
     DOF_REC(9);
     k_temporal<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, mask, hist_in, hist_out);
     DOF_REC(10);
@@ -1146,7 +1181,7 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
 hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
                              hipStream_t st)
 {
-    kb_resolve<<<nblk[kGridResolve], 256, 0, st>>>(jobs, njobs);
+    kb_resolve<<<nblk[kGridResolve], 64, 0, st>>>(jobs, njobs);
     kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
