@@ -80,8 +80,8 @@ def stage_bytes(stage, W, H, P, R):
         # colour 8 B + depth 4 B per full-res px, one normal (8 B) per quad; out colr 16 + zn 16 + z 4
         "reduce": F * 12 + h * 8 + h * 36,
         "dilate": 0,
-        "prefilter": h * 16 + h * 16,
-        "gather": h * 16 + h * 4 + h * 16,          # colour+CoC and depth in, v_p + bokeh out
+        "prefilter": h * 16 + h * 4 + h * 16 + h * 8,
+        "gather": h * 16 + h * 8 + h * 16,          # colour+CoC, depth+weight in, v_p + bokeh out
         "median": h * 16 + h * 16,
         "mask": h * 16 + h * 52 + h * 4 + h * 1,    # zn, history in, prev index + mask out
         "compact": 2 * h + P * 8 + R * 4,

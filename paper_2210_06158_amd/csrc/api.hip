@@ -104,6 +104,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m)
     L.pre = take(16 * np);
     L.gather = take(16 * np);
     L.ppmed = take(16 * np);
+    L.za = take(8 * np);
     L.prev_idx = take(4 * np);
     L.chunk_cnt = take(8 * (size_t)L.nchunks);
     L.chunk_off = take(8 * (size_t)L.nchunks);

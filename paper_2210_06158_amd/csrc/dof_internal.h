@@ -20,7 +20,7 @@ constexpr int kRingTaps = 81;             // 1 + 8 + 16 + 24 + 32 (3.1.1)
 constexpr int kMaxBlades = 16;
 // The binary tree over 95 significant key bits is at most 95 deep, and the
 // traversal pushes at most one entry (node, entry distance) per level.
-constexpr int kStackLds = 32;             // traversal stack entries kept in LDS
+constexpr int kStackLds = 24;             // traversal stack entries kept in LDS
 constexpr int kStackMax = 96;
 constexpr int kSpillPerThread = kStackMax - kStackLds;   // entries beyond LDS live in global memory
 constexpr int kTB = 128;                  // threads per traversal block
@@ -95,7 +95,7 @@ struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
-    size_t resolve, temporal, var_blur, rtmed, mips, tap, recon;
+    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon;
     size_t spill;
     size_t total;
     int64_t nchunks;
@@ -116,6 +116,7 @@ struct Planes {
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
+    float2 *za;              // per half-res pixel: (depth, gather weight 1 / max(|r|, 1/2)^2)
 };
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
 

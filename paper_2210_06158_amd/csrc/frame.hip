@@ -162,6 +162,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.rtmed = reinterpret_cast<float4 *>(s + L.rtmed);
     p.mips = reinterpret_cast<float4 *>(s + L.mips);
     p.tap = reinterpret_cast<float2 *>(s + L.tap);
+    p.za = reinterpret_cast<float2 *>(s + L.za);
     p.recon = reinterpret_cast<float4 *>(s + L.recon);
     return p;
 }
@@ -291,6 +292,11 @@ __device__ inline void b_prefilter(const FrameConst &fc, const Planes &P, const 
             sw = sw + w;
         }
     P.pre[i] = make_float4(ax / sw, ay / sw, az / sw, rc);
+    // depth and the gather's per-tap weight of this pixel (sampleAlpha of
+    // eq. 1 read as 1 / max(|r|, 1/2)^2), computed once here instead of at
+    // each of the 81 taps that read this pixel
+    const float mr = fmax_cs(fabsf(rc), 0.5f);
+    P.za[i] = make_float2(P.zh[i], 1.0f / (mr * mr));
 }
 
 __global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
@@ -323,11 +329,11 @@ __device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const 
         size_t j = (size_t)iy * fc.hw + ix;
         float4 ci = P.pre[j];
         float ari = fabsf(ci.w);
-        float mr = fmax_cs(ari, 0.5f);
-        float alpha = 1.0f / (mr * mr);
+        const float2 za = P.za[j];
+        float alpha = za.y;
         float dfg = ari > dist ? 1.0f : 0.0f;
         float dbg = fmin_cs(ari, arc) > dist ? 1.0f : 0.0f;
-        float wbg = sat((P.zh[j] - zc) / fc.depth_range);
+        float wbg = sat((za.x - zc) / fc.depth_range);
         float wf = alpha * ((1.0f - wbg) * dfg);
         float wb = alpha * (wbg * dbg);
         vf0 = vf0 + wf * ci.x; vb0 = vb0 + wb * ci.x;

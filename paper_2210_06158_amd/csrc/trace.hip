@@ -15,9 +15,10 @@
 //
 // Closest hit: binary radix tree whose nodes carry both children's boxes
 // (one 64-byte fetch tests two boxes), near child first, far child pushed on
-// a per-lane stack: 32 entries in LDS; when they are full the older 16 move
+// a per-lane stack: 24 entries in LDS; when they are full the oldest 8 move
 // to a global spill area and come back when the LDS part runs empty, so any
-// depth the 96-bit keys allow is exact and a pop is always an LDS read.
+// depth the 96-bit keys allow is exact (at most 96 - 24 entries are ever
+// spilled, the size of the spill area) and a pop is always an LDS read.
 // Each outer iteration advances a lane by up to two nodes, which halves the
 // per-iteration cost of the wave-wide refill and batching decisions.  Leaf
 // hits wait in a 4-entry per-lane queue and the triangle test runs when at
@@ -393,7 +394,8 @@ struct RawRays {
 
 // ---------------------------------------------------------------- persistent traversal
 
-constexpr int kSpillChunk = 16;   // stack entries moved per spill or refill
+constexpr int kSpillChunk = 8;    // stack entries moved per spill or refill (divides kStackLds and kStackMax)
+static_assert(kStackLds % kSpillChunk == 0 && kStackMax % kSpillChunk == 0, "spill chunks must tile the stack");
 constexpr int kRefill = 16;   // refill when at least this many lanes are idle
 constexpr int kLeafBatch = 32;   // run triangle tests when at least this many lanes have one pending
 
