@@ -377,7 +377,29 @@ def batched_leg(n_sessions, steps, warmup, log):
     tris = sum(s.ntri for s in ss)
     log(f"batched: {n_sessions} sessions, {px / 1e6:.1f} Mpx and {tris / 1e6:.1f} Mtri per step, "
         f"{sum(s.bytes for s in ss) / 2**30:.1f} GiB resident")
-    batch = dof.Batch(n_sessions, ss[0].params)
+    # autotune the persistent traversal grid of the batched run on step 2
+    # (frames 0 and 1 rendered first, so the step has history like the rest;
+    # repeating it reads the same history and rewrites the same outputs)
+    from paper_2210_06158_amd import tune
+    for s in ss:
+        s.done = 0
+    for k in range(2):
+        for s in ss:
+            s.prepare(k)
+            s.render()
+    for s in ss:
+        s.prepare(2)
+    tuners = {}
+
+    def trial(tb):
+        if tb not in tuners:
+            tuners[tb] = dof.Batch(n_sessions, ss[0].params, trace_blocks=tb)
+        tuners[tb].set([s.item() for s in ss])
+        tuners[tb].run()
+    best_tb, tune_ms = tune.tune(trial, tune.candidate_blocks(), reps=2)
+    del tuners
+    log(f"batched: traversal grid {best_tb} ({tune_ms})")
+    batch = dof.Batch(n_sessions, ss[0].params, trace_blocks=best_tb)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def run(mode, graph=None):
@@ -450,6 +472,8 @@ def batched_leg(n_sessions, steps, warmup, log):
                     for m, t in (("per_session", t_single), ("batched", t_batch), ("graph", t_graph))},
         "masked_grays_per_s_batched": round(r_batch / (t_batch.sum() * 1e-3) / 1e9, 4),
         "outputs_identical_across_modes": bool(same),
+        "autotuned_trace_blocks": best_tb if best_tb else "library default",
+        "autotune_ms": {str(k if k else "default"): round(v, 3) for k, v in tune_ms.items()},
         "rays_identical_across_modes": r_single == r_batch == r_graph,
     }
     log(f"batched: {out}")

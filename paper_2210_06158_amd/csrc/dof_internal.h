@@ -222,8 +222,6 @@ hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, c
                             const Rings &rings, hipStream_t st);
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
                               hipStream_t st);
-// lens rays of one job (host copy of the job; counts read on the device)
-hipError_t launch_trace_job(const Job &J, uint32_t *spill, int blocks, hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
                              const Rings &rings, hipStream_t st);
 

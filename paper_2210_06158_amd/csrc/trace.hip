@@ -635,21 +635,4 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_trace_job(const Job &J, uint32_t *spill, int blocks, hipStream_t st)
-{
-    LensRays src;
-    src.fc = J.fc;
-    src.queue = J.P.queue;
-    src.ray_base = J.P.ray_base;
-    src.ray_pix = J.P.ray_pix;
-    src.ray_hit = J.P.ray_hit;
-    src.ray_t = J.P.ray_t;
-    src.ray_col = J.P.ray_col;
-    src.ray_pos = J.P.ray_pos;
-    uint32_t *cnt = J.P.counters;
-    k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(J.scene, src, 0u, cnt + kCntRays, cnt + kCntWork, spill,
-                                                               reinterpret_cast<unsigned long long *>(cnt + kCntVisits));
-    return hipGetLastError();
-}
-
 }  // namespace dof
