@@ -80,17 +80,24 @@ def stage_bytes(stage, W, H, P, R):
         # colour 8 B + depth 4 B per full-res px, one normal (8 B) per quad; out colr 16 + zn 16 + z 4
         "reduce": F * 12 + h * 8 + h * 36,
         "dilate": 0,
+        # colr + depth in; prefiltered colour, (depth, gather weight) out
         "prefilter": h * 16 + h * 4 + h * 16 + h * 8,
         "gather": h * 16 + h * 8 + h * 16,          # colour+CoC, depth+weight in, v_p + bokeh out
         "median": h * 16 + h * 16,
-        "mask": h * 16 + h * 52 + h * 4 + h * 1,    # zn, history in, prev index + mask out
+        # depth+normal in, history validity + variance (8 B) at the reprojected texel; prev index + count out
+        "mask": h * 16 + h * 8 + h * 4 + h * 1,
         "compact": 2 * h + P * 8 + R * 4,
         "trace": R * (12 + 40),                     # queue/base/pixel of each ray in; hit, t, colour, position out
-        "resolve": R * 40 + P * 64,
-        "temporal": h * (1 + 4 + 64 + 52) + h * (32 + 48),
-        "blur_median_mips": h * (16 + 4) + h * (4 + 4 + 8 + 16 + 16) + h * 16 // 3,
-        "recon": h * (16 + 16 + 8 + 16 + 4) + h * 16,
-        "composite": F * (8 + 4) + h * (16 + 16 + 16 + 16) + F * 8,
+        # hit, colour, position of each ray; queue entry, ray offset, count in and 4 planes out per masked px
+        "resolve": R * 36 + P * (4 + 4 + 1 + 64),
+        # count, prev index, resolve planes, history A B C in; T0 T1 and history A B C out
+        "temporal": h * (1 + 4 + 64 + 48) + h * (32 + 48),
+        # T0 T1 in; variance, history variance, tap record, median, mip level 0 (+ levels 1-3) out
+        "blur_median_mips": h * (16 + 16) + h * (4 + 4 + 8 + 16 + 16) + h * 16 // 3,
+        # T0 T1 tap median variance and the mip chain in, reconstruction out
+        "recon": h * (16 + 16 + 8 + 16 + 4) + h * 16 * 4 // 3 + h * 16,
+        # depth (+ colour) per full-res px; median, reconstruction and tap record per half-res px; colour out
+        "composite": F * (8 + 4) + h * (16 + 16 + 8) + F * 8,
     }
     return table[stage]
 

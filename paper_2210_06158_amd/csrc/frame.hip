@@ -517,6 +517,8 @@ __global__ __launch_bounds__(256) void kb_mask(const Job *__restrict__ jobs, int
 }
 
 // ---------------------------------------------------------------- A7
+
+constexpr int kPixLds = 4096;   // staged ray->pixel entries per 256-pixel round (16 rays per pixel)
 // Chunks of 1024 pixels in row-major order; ranks from wave ballots (masked
 // pixels) and wave prefix sums (rays), so the queue is ascending.
 
@@ -620,6 +622,7 @@ __device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     __shared__ uint32_t wp[4], wr[4];
     __shared__ uint32_t runp, runr;
+    __shared__ uint32_t s_pix[kPixLds];   // ray -> queue position of one round's rays
     if (tid == 0) {
         uint2 o = P.chunk_off[bx];
         runp = o.x;
@@ -636,15 +639,25 @@ __device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__
         if (lane == 63) { wp[w] = (uint32_t)__popcll(bal); wr[w] = incl; }
         __syncthreads();
         uint32_t op = runp, orr = runr;
+        const uint32_t rbase = runr, round_rays = wr[0] + wr[1] + wr[2] + wr[3];
+        // the round's rays are one contiguous range: stage their pixel map in
+        // LDS and store it coalesced (rounds with more rays store directly)
+        const bool staged = round_rays <= (uint32_t)kPixLds;
         for (int k = 0; k < w; ++k) { op += wp[k]; orr += wr[k]; }
         if (n > 0u) {
             uint32_t pos = op + rank;
             uint32_t rb = orr + incl - n;
             P.queue[pos] = (uint32_t)i;
             P.ray_base[pos] = rb;
-            for (uint32_t k = 0; k < n; ++k) P.ray_pix[rb + k] = pos;
+            if (staged) {
+                for (uint32_t k = 0; k < n; ++k) s_pix[rb - rbase + k] = pos;
+            } else {
+                for (uint32_t k = 0; k < n; ++k) P.ray_pix[rb + k] = pos;
+            }
         }
         __syncthreads();
+        if (staged)
+            for (uint32_t t = tid; t < round_rays; t += 256) P.ray_pix[rbase + t] = s_pix[t];
         if (tid == 0) {
             runp += wp[0] + wp[1] + wp[2] + wp[3];
             runr += wr[0] + wr[1] + wr[2] + wr[3];
@@ -1036,14 +1049,17 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         size_t j = (size_t)ys[k >> 1] * hw + xs[k & 1];
-        float wv = wts[k] * P.T0[j].w;
+        // validity (exactly 0 or 1) and CoC (0 where invalid) from the tap record
+        const float2 tp = P.tap[j];
+        const bool valid = tp.x != -INFINITY;
+        float wv = valid ? wts[k] : 0.0f;
         float4 rj = P.recon[j];
         sw = sw + wv;
         rc0 = rc0 + wv * rj.x;
         rc1 = rc1 + wv * rj.y;
         rc2 = rc2 + wv * rj.z;
         rh = rh + wv * rj.w;
-        rct = rct + wv * P.T1[j].x;
+        rct = rct + wv * (valid ? tp.x : 0.0f);
     }
     const bool rtv = sw > 0.0f;
     if (rtv) {
