@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
+    ap.add_argument("--no-m-sweep", dest="m_sweep", action="store_false")
     ap.add_argument("--uhd-steps", type=int, default=60, help="frames of the 3840x2160 measurement (0 = skip)")
     ap.add_argument("--batched-sessions", type=int, default=32, help="sessions of the batched measurement (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -248,8 +249,11 @@ def main():
     bvh_ms = e0.elapsed_time(e1) / 3
     log(f"bvh build {bvh_ms:.3f} ms")
 
+    e0.record()
     gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in cams]
+    e1.record()
     torch.cuda.synchronize()
+    gbuffer_ms = e0.elapsed_time(e1) / nfr
     r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, args.trace_blocks,
                  log)
     K, total_ms, frame_ms = r["K"], r["total_ms"], r["frame_ms"]
@@ -279,6 +283,20 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy} MiB")
+    # ray budget sweep (Table 2 reports m = 1, 30, 50): traversal and frame
+    # time per m on the same path, and the traversal's cost per unit of m
+    m_sweep = None
+    if args.m_sweep:
+        import dataclasses
+        m_sweep = {}
+        for mm in (1, 8, 30, 50):
+            pm = dataclasses.replace(params, m=mm)
+            rm = run_path(gs, cams, [lens] * nfr, pm, gbs, 20, 5, 20, args.trace_blocks, log)
+            m_sweep[str(mm)] = {"frame_ms": round(rm["total_ms"] / rm["K"], 4),
+                                "trace_ms": round(rm["stage_ms"]["trace"], 4),
+                                "rays_per_frame": round(rm["rays"] / rm["K"], 1)}
+        t1, t50 = m_sweep["1"]["trace_ms"], m_sweep["50"]["trace_ms"]
+        m_sweep["trace_ms_per_unit_m"] = round((t50 - t1) / 49.0, 5)
     del gbs
 
     w4k = None
@@ -321,6 +339,9 @@ def main():
         "masked_px_per_frame": round(masked / K, 1),
         "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),
         "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 4),
+        "gbuffer_ms_per_frame": round(gbuffer_ms, 4),
+        "frames_per_s_with_gbuffer": round(K / ((total_ms + K * gbuffer_ms) / 1e3), 2),
+        "m_sweep": m_sweep,
         "bvh_build_ms": round(bvh_ms, 3),
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
