@@ -154,6 +154,24 @@ def test_full_frame_4k_hexagon(big, orc):
     d = gpu_frame(big, cam, gb, lens=lens, params=params, gs=gs)
     check(o, d, "4k frame 0")
     assert o["n_rays"] > 1000000
+    # frame 1: the focus has moved (lens changed -> motion weights), both
+    # sides fed the oracle's history of frame 0
+    cam1, lens1 = cams[1], lenses[1]
+    assert lens1.focus != lens.focus
+    gb1 = half_gb(orc, orc.gbuffer(osc, cam1, lens1))
+    o1 = orc.render_frame(osc, cam1, lens1, params, gb1, hist_in=o["hist_out"], prev_cam=cam, prev_lens=lens)
+    fr = big["dof"].Frame(cam1.width, cam1.height, params, out_format=big["dof"].RGBA16F)
+    g = (torch.from_numpy(gb1.colour).cuda().half(), torch.from_numpy(gb1.depth).cuda(),
+         torch.from_numpy(gb1.normal).cuda().half())
+    hin = torch.from_numpy(o["hist_out"]).cuda()
+    hout = big["dof"].history_alloc(cam1.width, cam1.height)
+    fr.render(gs, cam1, lens1, g, hin, hout, prev_cam=cam, prev_lens=lens)
+    torch.cuda.synchronize()
+    d1 = fr.debug()
+    d1["colour"] = fr.colour.float().cpu().numpy()
+    d1["mask"] = fr.mask.cpu().numpy()
+    d1["hist_out"] = hout.cpu().numpy()
+    check(o1, d1, "4k frame 1")
 
 
 # ---------------------------------------------------------------- edge cases
