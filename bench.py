@@ -297,6 +297,12 @@ def main():
                                 "rays_per_frame": round(rm["rays"] / rm["K"], 1)}
         t1, t50 = m_sweep["1"]["trace_ms"], m_sweep["50"]["trace_ms"]
         m_sweep["trace_ms_per_unit_m"] = round((t50 - t1) / 49.0, 5)
+        # the mask grown by the neighbourhood max CoC (remedy proposed in 5.3)
+        pd = dataclasses.replace(params, mask_mode=synth.MASK_DILATE)
+        rd = run_path(gs, cams, [lens] * nfr, pd, gbs, 20, 5, 20, args.trace_blocks, log)
+        m_sweep["mask_dilated_m8"] = {"frame_ms": round(rd["total_ms"] / rd["K"], 4),
+                                      "trace_ms": round(rd["stage_ms"]["trace"], 4),
+                                      "rays_per_frame": round(rd["rays"] / rd["K"], 1)}
     del gbs
 
     w4k = None

@@ -57,6 +57,11 @@ typedef int32_t dof_status;
 #define DOF_MASK_ADAPTIVE 0 /* ray count from eqs. (2)-(4) */
 #define DOF_MASK_FIXED 1    /* m rays wherever the adaptive count is > 0 */
 #define DOF_MASK_ALL 2      /* m rays at every half-res pixel */
+/* the adaptive counts grown by the neighbourhood's maximum CoC (the remedy
+ * section 5.3 proposes for tiling near the camera): each pixel takes the
+ * largest count within a square window whose radius is its tile's dilated
+ * maximum CoC radius, rounded up (r_max must be <= 32 in this mode) */
+#define DOF_MASK_DILATE 3
 
 typedef struct {
     float pos[3], right[3], up[3], fwd[3];

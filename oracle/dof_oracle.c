@@ -936,6 +936,37 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             }
     }
 
+    /* Mask mode 3, the remedy 5.3 proposes for tiling near the camera: the
+     * ray mask grown by the maximum CoC of the neighbourhood.  Each pixel
+     * takes the largest adaptive count within a square window whose radius
+     * is its tile's dilated maximum CoC radius (A2), rounded up, clipped to
+     * the image. */
+    if (p->mask_mode == 3) {
+        uint8_t *raw = (uint8_t *)malloc(np ? np : 1);
+        if (!raw) {
+            free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
+            free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
+            free(hblur); free(gblur); free(mips);
+            return -2;
+        }
+        memcpy(raw, out_mask, np);
+        for (int y = 0; y < hh; y++)
+            for (int x = 0; x < hw; x++) {
+                int R = (int)ceilf(tdil[(size_t)(y / T) * tw + x / T]);
+                uint8_t best = 0;
+                for (int yy = y - R; yy <= y + R; yy++) {
+                    if (yy < 0 || yy >= hh) continue;
+                    for (int xx = x - R; xx <= x + R; xx++) {
+                        if (xx < 0 || xx >= hw) continue;
+                        uint8_t v = raw[(size_t)yy * hw + xx];
+                        best = v > best ? v : best;
+                    }
+                }
+                out_mask[(size_t)y * hw + x] = best;
+            }
+        free(raw);
+    }
+
     /* A7 -- ordered list of masked pixels and their first ray (the GPU
      * dispatches rays only for these pixels). */
     size_t P = 0, R = 0;

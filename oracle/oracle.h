@@ -44,7 +44,7 @@ typedef struct {
     float lod_scale, lod_max, depth_range, r_max;
     int32_t tile;
     float l_spec;
-    int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all */
+    int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all, 3 adaptive dilated by the neighbourhood max CoC */
 } orc_params;
 
 typedef struct {

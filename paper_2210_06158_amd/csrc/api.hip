@@ -106,6 +106,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m)
     L.ppmed = take(16 * np);
     L.za = take(8 * np);
     L.prev_idx = take(4 * np);
+    L.mask_raw = take(np);
     L.chunk_cnt = take(8 * (size_t)L.nchunks);
     L.chunk_off = take(8 * (size_t)L.nchunks);
     L.counters = take(64);
@@ -232,7 +233,9 @@ dof_status params_check(const dof_params *p)
     if (p->struct_size != sizeof(dof_params)) return fail(DOF_E_INVALID, "params.struct_size mismatch");
     if (p->m < 1 || p->m > 255) return fail(DOF_E_INVALID, "m must be in 1..255");
     if (p->tile != dof::kTile) return fail(DOF_E_UNSUPPORTED, "tile must be 16");
-    if (p->mask_mode < 0 || p->mask_mode > 2) return fail(DOF_E_INVALID, "bad mask_mode");
+    if (p->mask_mode < 0 || p->mask_mode > 3) return fail(DOF_E_INVALID, "bad mask_mode");
+    if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
+        return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
     if (!(p->lod_max >= 0.0f)) return fail(DOF_E_INVALID, "bad lod_max");
     if (p->trace_blocks < 0 || p->trace_blocks > dof::kMaxTraceBlocks) return fail(DOF_E_INVALID, "bad trace_blocks");
@@ -360,6 +363,7 @@ struct dof_batch {
     uint32_t nblk[dof::kNumGrids];     // total blocks of each grid shape
     uint32_t *spill;                   // traversal spill (first frame's scratch)
     int32_t trace_blocks;
+    bool dilate;                       // params.mask_mode == DOF_MASK_DILATE
     std::vector<char> host;            // staging copy of the table
 };
 
@@ -644,6 +648,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
                            static_cast<hipStream_t>(stream)));
     for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
     b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
+    b->dilate = p->mask_mode == DOF_MASK_DILATE;
     b->n = n;
     return DOF_OK;
 }
@@ -656,7 +661,7 @@ dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
     dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->table);
     const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
     const dof::Rings &rings = ring_table();
-    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, s));
+    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, s));
     DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, s));
     DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));

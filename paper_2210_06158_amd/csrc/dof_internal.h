@@ -92,7 +92,7 @@ struct FrameConst {
 
 // Byte offsets of every plane in a frame's scratch buffer.
 struct ScratchLayout {
-    size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx;
+    size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
     size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon;
@@ -117,6 +117,7 @@ struct Planes {
     float *var_blur;
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
     float2 *za;              // per half-res pixel: (depth, gather weight 1 / max(|r|, 1/2)^2)
+    uint8_t *mask_raw;       // adaptive ray counts before dilation (mask mode DOF_MASK_DILATE)
 };
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
 
@@ -219,7 +220,7 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
 // total blocks of grid g over the jobs
 hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                            const Rings &rings, hipStream_t st);
+                            const Rings &rings, bool dilate, hipStream_t st);
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
                               hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,

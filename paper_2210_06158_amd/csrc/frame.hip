@@ -163,6 +163,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.mips = reinterpret_cast<float4 *>(s + L.mips);
     p.tap = reinterpret_cast<float2 *>(s + L.tap);
     p.za = reinterpret_cast<float2 *>(s + L.za);
+    p.mask_raw = reinterpret_cast<uint8_t *>(s + L.mask_raw);
     p.recon = reinterpret_cast<float4 *>(s + L.recon);
     return p;
 }
@@ -513,7 +514,55 @@ __global__ __launch_bounds__(256) void kb_mask(const Job *__restrict__ jobs, int
 {
     uint32_t bx, by;
     const Job &J = jobs[job_of_block(jobs, njobs, kGridTiles, blockIdx.x, bx, by)];
-    b_mask(J.fc, J.P, J.hist_in, J.mask, bx, by);
+    b_mask(J.fc, J.P, J.hist_in, J.fc.mask_mode == DOF_MASK_DILATE ? J.P.mask_raw : J.mask, bx, by);
+}
+
+// ---------------------------------------------------------------- A6, dilated (5.3)
+// One block per 16 x 16 tile: the tile's window of raw counts (radius R =
+// its dilated max CoC radius, rounded up) goes to LDS, then a horizontal and
+// a vertical running maximum give each pixel the largest count within R.
+
+constexpr int kDilMax = 32;
+constexpr int kDilSide = kTile + 2 * kDilMax;
+
+__device__ inline void b_mask_dilate(const FrameConst &fc, const Planes &P, uint8_t *mask, const uint32_t bx,
+                                     const uint32_t by)
+{
+    __shared__ uint8_t win[kDilSide * kDilSide];
+    __shared__ uint8_t hor[kDilSide * kTile];
+    const int hw = fc.hw, hh = fc.hh, tid = threadIdx.y * kTile + threadIdx.x;
+    const int R = min((int)ceilf(P.tile_dil[(size_t)by * fc.tw + bx]), kDilMax);
+    const int S = kTile + 2 * R;
+    const int ox = (int)bx * kTile - R, oy = (int)by * kTile - R;
+    for (int c = tid; c < S * S; c += kTile * kTile) {
+        const int gx = ox + c % S, gy = oy + c / S;
+        win[c] = (gx >= 0 && gy >= 0 && gx < hw && gy < hh) ? P.mask_raw[(size_t)gy * hw + gx] : (uint8_t)0;
+    }
+    __syncthreads();
+    for (int c = tid; c < S * kTile; c += kTile * kTile) {
+        const int row = c / kTile, col = c % kTile;
+        uint8_t m = 0;
+        for (int k = 0; k <= 2 * R; ++k) m = max(m, win[row * S + col + k]);
+        hor[row * kTile + col] = m;
+    }
+    __syncthreads();
+    const int x = (int)bx * kTile + threadIdx.x, y = (int)by * kTile + threadIdx.y;
+    if (x >= hw || y >= hh) return;
+    uint8_t m = 0;
+    for (int k = 0; k <= 2 * R; ++k) m = max(m, hor[(threadIdx.y + k) * kTile + threadIdx.x]);
+    mask[(size_t)y * hw + x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_mask_dilate(FrameConst fc, Planes P, uint8_t *mask)
+{
+    b_mask_dilate(fc, P, mask, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_mask_dilate(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridTiles, blockIdx.x, bx, by)];
+    b_mask_dilate(J.fc, J.P, J.mask, bx, by);
 }
 
 // ---------------------------------------------------------------- A7
@@ -1144,7 +1193,12 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     DOF_REC(4);
     k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
     DOF_REC(5);
-    k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, mask);
+    if (fc.mask_mode == DOF_MASK_DILATE) {
+        k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, P.mask_raw);
+        k_mask_dilate<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, mask);
+    } else {
+        k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, mask);
+    }
     DOF_REC(6);
     k_compact_count<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
     k_compact_scan<<<1, 1024, 0, st>>>(L.nchunks, P, nullptr);
@@ -1186,7 +1240,7 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
 }
 
 hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                            hipStream_t st)
+                            bool dilate, hipStream_t st)
 {
     kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
@@ -1194,6 +1248,7 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
     kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
     kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
+    if (dilate) kb_mask_dilate<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_compact_count<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);
     kb_compact_scan<<<njobs, 1024, 0, st>>>(jobs);
     kb_compact_scatter<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);

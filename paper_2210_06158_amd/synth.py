@@ -79,7 +79,7 @@ class Lens:
     blade_rot: float = 0.0      # radians
 
 
-MASK_ADAPTIVE, MASK_FIXED, MASK_ALL = 0, 1, 2
+MASK_ADAPTIVE, MASK_FIXED, MASK_ALL, MASK_DILATE = 0, 1, 2, 3
 
 
 @dataclass

@@ -122,3 +122,17 @@ def test_batch_entry_points_check_arguments_on_the_host(dof):
     assert b"item 0" in L.dof_last_error()
     assert L.dof_batch_run(h, None, None) == dof.DOF_E_STATE
     L.dof_batch_destroy(h)
+
+
+def test_mask_dilation_mode_limits(dof):
+    L = dof.lib()
+    p = dof.DofParams()
+    L.dof_default_params(C.byref(p))
+    b = C.c_size_t()
+    p.mask_mode = 3
+    assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == 0
+    p.r_max = 40.0
+    assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_UNSUPPORTED
+    p.r_max = 32.0
+    p.mask_mode = 4
+    assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID

@@ -125,6 +125,26 @@ def test_batch_equals_single_frames(sess):
     assert rays > 0
 
 
+def test_batch_with_dilated_mask_equals_single_frames(sess):
+    """Mask mode DOF_MASK_DILATE (an extra kernel between mask and
+    compaction), batched vs alone."""
+    torch, dof = sess["torch"], sess["dof"]
+    params = sess["params"]
+    try:
+        sess["params"] = dataclasses.replace(params, mask_mode=synth.MASK_DILATE)
+        alone = render_alone(sess)
+        frs, houts = make_frames(sess)
+        b = dof.Batch(4, sess["params"])
+        b.set(batch_items(sess, frs, houts))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone[k], f"dilated item {k}")
+        base = render_alone(dict(sess, params=params))
+        assert sum(a["n_rays"] for a in alone) > sum(a["n_rays"] for a in base)
+    finally:
+        sess["params"] = params
+
+
 def test_batch_second_frame_with_history(sess):
     """Frame 1 of every session on frame 0's history (camera panned), batched
     vs alone."""

@@ -264,7 +264,7 @@ def test_fp16_gbuffer_parity(env, orc):
     compare_frame(o, d, "fp16 G-buffer")
 
 
-@pytest.mark.parametrize("mode,m", [(synth.MASK_ALL, 3), (synth.MASK_FIXED, 5)])
+@pytest.mark.parametrize("mode,m", [(synth.MASK_ALL, 3), (synth.MASK_FIXED, 5), (synth.MASK_DILATE, 4)])
 def test_mask_modes_parity(env, orc, frame0, mode, m):
     gb, _, _ = frame0
     p = dataclasses.replace(env["params"], mask_mode=mode, m=m)

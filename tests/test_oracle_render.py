@@ -366,3 +366,46 @@ def test_ray_traced_dof_converges_to_lens_integral(orc, small):
     assert all(a > b for a, b in zip(errs, errs[1:]))
     assert errs[-1] < errs[1] / 4.0
     assert errs[-1] < 0.03
+
+
+# ---------------------------------------------------------------- mask dilation (5.3)
+
+def _dilate_pair(orc, small, W, H, lens, m=4):
+    cam = dataclasses.replace(small["cam"], width=W, height=H)
+    gb = orc.gbuffer(small["sc"], cam, lens)
+    p = synth.Params(m=m)
+    raw = orc.render_frame(small["sc"], cam, lens, p, gb)
+    dil = orc.render_frame(small["sc"], cam, lens, dataclasses.replace(p, mask_mode=synth.MASK_DILATE), gb)
+    return raw, dil
+
+
+def test_mask_dilation_reduces_to_a_max_filter_when_the_radius_is_uniform(orc, small):
+    """With at most 3 x 3 tiles every tile's neighbourhood (+-2 tiles) is the
+    whole image, so all tiles share one radius R and the dilation is the
+    library maximum filter of side 2R + 1 with zeros outside the image."""
+    raw, dil = _dilate_pair(orc, small, 96, 64, dataclasses.replace(small["lens"], fnum=0.5))
+    td = dil["tile_dil"]
+    assert td.shape == (2, 3) and np.all(td == td.flat[0]) and td.flat[0] > 1.0
+    R = int(math.ceil(float(td.flat[0])))
+    want = ndi.maximum_filter(raw["mask"], size=2 * R + 1, mode="constant", cval=0)
+    assert np.array_equal(dil["mask"], want)
+    assert (dil["mask"] >= raw["mask"]).all() and dil["n_rays"] > raw["n_rays"]
+
+
+def test_mask_dilation_only_grows_the_mask(orc, small):
+    """Dilation is extensive: every count is at least the adaptive count and
+    the ray total only grows (full 256 x 256 workload, radii vary by tile)."""
+    raw, dil = _dilate_pair(orc, small, 256, 256, small["lens"])
+    assert len(np.unique(dil["tile_dil"])) > 1
+    assert (dil["mask"] >= raw["mask"]).all() and dil["n_rays"] >= raw["n_rays"]
+    # every pixel dilated from zero has a masked pixel within its tile's radius
+    grown = (raw["mask"] == 0) & (dil["mask"] > 0)
+    assert grown.any()
+
+
+def test_mask_dilation_is_identity_without_blur(orc, small):
+    """a = 0: every CoC radius is 0, so R = 0 and the mask is unchanged."""
+    lens = dataclasses.replace(small["lens"], fnum=math.inf)
+    raw, dil = _dilate_pair(orc, small, 64, 48, lens)
+    assert np.all(dil["tile_dil"] == 0.0)
+    assert np.array_equal(dil["mask"], raw["mask"])
