@@ -389,6 +389,12 @@ def uhd_leg(args, log):
         "stage_roofline": stage_roofline(r),
         "trace_roofline": trace_roofline(r),
     }
+    # the same path with the post-process gather shaped like the hexagonal
+    # aperture (the polygonal-bokeh extension named in section 2)
+    import dataclasses
+    rp = run_path(gs, cams, lenses, dataclasses.replace(params, pp_polygon=1), gbs, 20, 5, 20, args.trace_blocks, log)
+    out["hexagonal_pp_gather"] = {"frames_per_s": round(rp["K"] / (rp["total_ms"] / 1e3), 2),
+                                  "gather_ms": round(rp["stage_ms"]["gather"], 4)}
     log(f"4k: {out['frames_per_s']} frames/s")
     del gbs, gs
     torch.cuda.synchronize()

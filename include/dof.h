@@ -100,7 +100,11 @@ typedef struct {
     int32_t mask_mode;
     int32_t trace_blocks;
     int32_t timing;         /* nonzero: record a HIP event pair per stage */
-    int32_t reserved[3];
+    /* 1: with a bladed lens, the post-process gather samples the aperture
+     * polygon instead of circles (section 2 names polygonal bokeh as a
+     * change of the sampling kernel's shape); 0 (default): circles */
+    int32_t pp_polygon;
+    int32_t reserved[2];
 } dof_params;
 
 /* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view

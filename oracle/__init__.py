@@ -36,7 +36,7 @@ class OrcParams(C.Structure):
                 ("var_recon_w", C.c_float), ("b_max", C.c_float), ("h_edge", C.c_float),
                 ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32),
-                ("l_spec", C.c_float), ("mask_mode", C.c_int32)]
+                ("l_spec", C.c_float), ("mask_mode", C.c_int32), ("pp_polygon", C.c_int32)]
 
 
 class OrcScene(C.Structure):
@@ -110,10 +110,21 @@ def lens_struct(lens) -> OrcLens:
     return OrcLens(lens.focal, lens.fnum, lens.focus, lens.sensor, lens.blades, lens.blade_rot)
 
 
+def gather_rings(lens, params):
+    """The post-process gather's taps: (ox, oy, frac) arrays of 81."""
+    ox, oy, fr = (np.zeros(81, np.float32) for _ in range(3))
+    L = lib()
+    L.orc_gather_rings.argtypes = [C.POINTER(OrcLens), C.POINTER(OrcParams), C.c_void_p, C.c_void_p, C.c_void_p]
+    rc = L.orc_gather_rings(C.byref(lens_struct(lens)), C.byref(params_struct(params)), _ptr(ox), _ptr(oy), _ptr(fr))
+    if rc != 0:
+        raise RuntimeError("orc_gather_rings failed")
+    return ox, oy, fr
+
+
 def params_struct(p) -> OrcParams:
     return OrcParams(p.m, p.s, p.var_mask_w, p.alpha, p.alpha_motion, p.var_recon_w, p.b_max,
                      p.h_edge, p.lod_scale, p.lod_max, p.depth_range, p.r_max, p.tile,
-                     p.l_spec, p.mask_mode)
+                     p.l_spec, p.mask_mode, getattr(p, "pp_polygon", 0))
 
 
 class OracleScene:

@@ -621,6 +621,51 @@ static ring_table make_rings(void)
     return t;
 }
 
+/* The gather kernel shaped like the aperture (section 2 names polygonal
+ * bokeh as an extension obtained by changing the shape of the sampling
+ * kernel): ring k holds 8k taps at equal arc length on the aperture polygon
+ * of circumradius k/4 (vertices at rot + 2 pi i / B, the corners between
+ * the blade normals), the first half a step past vertex 0; a tap's distance
+ * is k/4, its radius in the polygon's own norm.  Offsets take the far-field
+ * image of the aperture on screen (lens up is screen -y), reflected for
+ * gathering, i.e. lens point (x, y) becomes tap offset (-x, y). */
+static ring_table make_polygon_rings(int blades, float rot)
+{
+    ring_table t;
+    const double pi = 3.14159265358979323846;
+    const double side = 2.0 * sin(pi / blades);
+    t.ox[0] = 0.0f; t.oy[0] = 0.0f; t.frac[0] = 0.0f;
+    int i = 1;
+    for (int k = 1; k <= 4; k++) {
+        const int n = 8 * k;
+        for (int j = 0; j < n; j++, i++) {
+            double s = ((double)j + 0.5) * ((double)blades * side) / (double)n;
+            int e = (int)floor(s / side);
+            if (e >= blades) e = blades - 1;
+            double u = s / side - (double)e;
+            double a0 = (double)rot + 2.0 * pi * e / blades, a1 = (double)rot + 2.0 * pi * (e + 1) / blades;
+            double px = (1.0 - u) * cos(a0) + u * cos(a1), py = (1.0 - u) * sin(a0) + u * sin(a1);
+            t.ox[i] = (float)(k / 4.0 * -px);
+            t.oy[i] = (float)(k / 4.0 * py);
+            t.frac[i] = (float)k * 0.25f;
+        }
+    }
+    return t;
+}
+
+/* The 81 taps of the post-process gather for a lens and parameters (for
+ * tests): offsets in units of the kernel radius and ring distances. */
+int orc_gather_rings(const orc_lens *lens, const orc_params *p, float *ox, float *oy, float *frac)
+{
+    if (!lens || !p || !ox || !oy || !frac) return -1;
+    ring_table t = (p->pp_polygon && lens->blades >= 3) ? make_polygon_rings(lens->blades, lens->blade_rot)
+                                                       : make_rings();
+    memcpy(ox, t.ox, sizeof(t.ox));
+    memcpy(oy, t.oy, sizeof(t.oy));
+    memcpy(frac, t.frac, sizeof(t.frac));
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Reprojection into the previous camera (3.2.3)                            */
 /* ------------------------------------------------------------------------ */
@@ -691,6 +736,9 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     int motion = have_hist ? !same_view(cam, prev_cam, lens, prev_lens) : 0;
     lensq pq = have_hist ? lens_quantities(prev_lens, W, H) : q;
     const ring_table rings = make_rings();
+    /* the post-process gather's kernel: circles, or the aperture polygon */
+    const ring_table grings = (p->pp_polygon && lens->blades >= 3) ? make_polygon_rings(lens->blades, lens->blade_rot)
+                                                                   : rings;
     const aperture ap = make_aperture(lens->blades, lens->blade_rot);
 
     float *colr = (float *)calloc(np * 4, sizeof(float));
@@ -808,8 +856,8 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             float arc = fabsf(rc);
             float vf[3] = {0, 0, 0}, vb[3] = {0, 0, 0}, sw = 0.0f, ss = 0.0f;
             for (int k = 0; k < 81; k++) {
-                float dist = Rn * rings.frac[k];
-                float sx = (float)x + rings.ox[k] * Rn, sy = (float)y + rings.oy[k] * Rn;
+                float dist = Rn * grings.frac[k];
+                float sx = (float)x + grings.ox[k] * Rn, sy = (float)y + grings.oy[k] * Rn;
                 int ix = nearest_index(sx, hw), iy = nearest_index(sy, hh);
                 size_t j = (size_t)iy * hw + ix;
                 const float *ci = pre + 4 * j;

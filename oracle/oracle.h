@@ -45,6 +45,7 @@ typedef struct {
     int32_t tile;
     float l_spec;
     int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all, 3 adaptive dilated by the neighbourhood max CoC */
+    int32_t pp_polygon;                     /* 1: post-process gather taps on the aperture polygon (bladed lenses) */
 } orc_params;
 
 typedef struct {
@@ -109,6 +110,10 @@ int orc_lens_sample(uint32_t seed, uint32_t frame, uint32_t q, uint32_t k,
 
 int orc_gbuffer(const orc_scene *s, const orc_bvh *b, const orc_camera *cam,
                 const orc_lens *lens, float *colour, float *depth, float *normal);
+
+/* The post-process gather's 81 taps (offsets in kernel radii, ring
+ * distances): circles, or the aperture polygon with params->pp_polygon. */
+int orc_gather_rings(const orc_lens *lens, const orc_params *p, float *ox, float *oy, float *frac);
 
 int orc_render_frame(const orc_scene *s, const orc_bvh *b,
                      const orc_camera *cam, const orc_lens *lens,

@@ -171,6 +171,38 @@ void view_of(const dof_camera &c, const LensDerived &q, dof::ViewConst &v)
 
 // 81 taps: centre + rings k = 1..4 of 8k taps at radius k/4, angle 2 pi j / 8k
 // (section 3.1.1), evaluated in binary64 then rounded.
+// The gather's taps on the aperture polygon (pp_polygon): ring k holds 8k
+// taps at equal arc length on the polygon of circumradius k/4 whose corners
+// sit at rot + 2 pi i / B (between the blade normals), the first half a step
+// past corner 0; ring distance k/4.  Offsets are the far-field image of the
+// aperture on screen (lens up = screen -y) reflected for gathering: lens
+// point (x, y) -> offset (-x, y).  Binary64 on the host, rounded once.
+dof::Rings make_polygon_rings(int blades, float rot)
+{
+    dof::Rings r;
+    r.ox[0] = 0.0f;
+    r.oy[0] = 0.0f;
+    r.frac[0] = 0.0f;
+    const double pi = 3.14159265358979323846;
+    const double side = 2.0 * sin(pi / blades);
+    int i = 1;
+    for (int k = 1; k <= 4; ++k) {
+        const int taps = 8 * k;
+        for (int j = 0; j < taps; ++j, ++i) {
+            const double s = ((double)j + 0.5) * ((double)blades * side) / (double)taps;
+            int e = (int)floor(s / side);
+            if (e >= blades) e = blades - 1;
+            const double u = s / side - (double)e;
+            const double a0 = (double)rot + 2.0 * pi * e / blades, a1 = (double)rot + 2.0 * pi * (e + 1) / blades;
+            const double px = (1.0 - u) * cos(a0) + u * cos(a1), py = (1.0 - u) * sin(a0) + u * sin(a1);
+            r.ox[i] = (float)(k / 4.0 * -px);
+            r.oy[i] = (float)(k / 4.0 * py);
+            r.frac[i] = (float)k * 0.25f;
+        }
+    }
+    return r;
+}
+
 dof::Rings make_rings()
 {
     dof::Rings r;
@@ -234,6 +266,7 @@ dof_status params_check(const dof_params *p)
     if (p->m < 1 || p->m > 255) return fail(DOF_E_INVALID, "m must be in 1..255");
     if (p->tile != dof::kTile) return fail(DOF_E_UNSUPPORTED, "tile must be 16");
     if (p->mask_mode < 0 || p->mask_mode > 3) return fail(DOF_E_INVALID, "bad mask_mode");
+    if (p->pp_polygon != 0 && p->pp_polygon != 1) return fail(DOF_E_INVALID, "bad pp_polygon");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
@@ -351,6 +384,12 @@ const dof::Rings &ring_table()
 {
     static const dof::Rings rings = make_rings();
     return rings;
+}
+
+// the post-process gather's kernel for a lens and parameters
+dof::Rings gather_rings(const dof_lens &lens, const dof_params &p)
+{
+    return (p.pp_polygon && lens.blades >= 3) ? make_polygon_rings(lens.blades, lens.blade_rot) : ring_table();
 }
 
 }  // namespace
@@ -562,7 +601,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
         }
         ev = scene->ev;
     }
-    DOF_HIP(dof::launch_frame_pre(fc, rings, L, scr, *gb, hin, out->mask, ev, s));
+    DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, out->mask, ev, s));
     const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
     DOF_HIP(dof::launch_frame_post(fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
@@ -628,6 +667,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         J.mask = it.out.mask;
         J.out = it.out;
         J.scene = dof::SceneArgs{it.scene->dev.ntri, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes};
+        J.grings = gather_rings(it.lens, *p);
         const dof::FrameConst &fc = J.fc;
         const int64_t np = (int64_t)fc.hw * fc.hh;
         auto cdiv = [](int64_t a, int64_t c) { return (uint32_t)((a + c - 1) / c); };

@@ -158,6 +158,7 @@ struct Job {
     uint8_t *mask;
     dof_frame_out out;
     SceneArgs scene;
+    Rings grings;                 // the post-process gather's taps (lens-shaped or circular)
     uint32_t bstart[kNumGrids];   // first block of this job in each grid
     uint32_t bx[kNumGrids];       // blocks per row of this job in each grid
 };

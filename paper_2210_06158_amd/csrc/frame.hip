@@ -355,11 +355,11 @@ __global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings,
     b_gather(fc, rings, P, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(kBX *kBY) void kb_gather(const Job *__restrict__ jobs, int njobs, Rings rings)
+__global__ __launch_bounds__(kBX *kBY) void kb_gather(const Job *__restrict__ jobs, int njobs)
 {
     uint32_t bx, by;
     const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
-    b_gather(J.fc, rings, J.P, bx, by);
+    b_gather(J.fc, J.grings, J.P, bx, by);
 }
 
 // ---------------------------------------------------------------- A5
@@ -1245,7 +1245,7 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
     kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
     kb_prefilter<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
-    kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
+    kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     if (dilate) kb_mask_dilate<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);

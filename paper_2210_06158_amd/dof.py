@@ -39,7 +39,7 @@ class DofParams(C.Structure):
                 ("b_max", C.c_float), ("h_edge", C.c_float), ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32), ("l_spec", C.c_float),
                 ("mask_mode", C.c_int32), ("trace_blocks", C.c_int32), ("timing", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("pp_polygon", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class DofGBuffer(C.Structure):
@@ -170,6 +170,7 @@ def params_struct(p, trace_blocks: int = 0, timing: bool = False) -> DofParams:
     for k in ("m", "s", "var_mask_w", "alpha", "alpha_motion", "var_recon_w", "b_max", "h_edge", "lod_scale",
               "lod_max", "depth_range", "r_max", "tile", "l_spec", "mask_mode"):
         setattr(s, k, getattr(p, k))
+    s.pp_polygon = int(getattr(p, "pp_polygon", 0))
     s.trace_blocks = trace_blocks
     s.timing = 1 if timing else 0
     return s

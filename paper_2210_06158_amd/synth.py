@@ -99,6 +99,7 @@ class Params:
     tile: int = 16              # tile side for the neighbourhood max CoC
     l_spec: float = 1.0         # luma above which a tap counts as a bright (specular) sample
     mask_mode: int = MASK_ADAPTIVE
+    pp_polygon: int = 0         # 1: post-process gather kernel shaped like a bladed aperture
 
 
 @dataclass

@@ -145,6 +145,27 @@ def test_batch_with_dilated_mask_equals_single_frames(sess):
         sess["params"] = params
 
 
+def test_batch_with_polygonal_gather_equals_single_frames(sess):
+    """pp_polygon = 1: each item's gather kernel follows its own lens (the
+    hexagonal item samples a hexagon, the others circles), batched vs alone."""
+    torch, dof = sess["torch"], sess["dof"]
+    params = sess["params"]
+    try:
+        sess["params"] = dataclasses.replace(params, pp_polygon=1)
+        alone = render_alone(sess)
+        frs, houts = make_frames(sess)
+        b = dof.Batch(4, sess["params"])
+        b.set(batch_items(sess, frs, houts))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone[k], f"polygon item {k}")
+        base = render_alone(dict(sess, params=params))
+        assert not np.array_equal(alone[1]["gather"], base[1]["gather"])     # hexagonal lens: kernel changed
+        assert np.array_equal(alone[0]["gather"], base[0]["gather"])         # circular lens: unchanged
+    finally:
+        sess["params"] = params
+
+
 def test_batch_second_frame_with_history(sess):
     """Frame 1 of every session on frame 0's history (camera panned), batched
     vs alone."""

@@ -272,14 +272,16 @@ def test_mask_modes_parity(env, orc, frame0, mode, m):
     compare_frame(o, d, f"mask mode {mode}")
 
 
-def test_hexagon_aperture_and_ragged_size(env, orc):
+@pytest.mark.parametrize("polygon", [0, 1])
+def test_hexagon_aperture_and_ragged_size(env, orc, polygon):
     """6-blade aperture at a size that is not a multiple of any tile
-    (ragged tails in every kernel)."""
+    (ragged tails in every kernel); with polygon = 1 the post-process gather
+    samples the hexagon too."""
     lens = dataclasses.replace(env["lens"], fnum=2.0, blades=6, blade_rot=0.2)
     cam = dataclasses.replace(env["cam"], width=202, height=118)
     gb = orc.gbuffer(env["osc"], cam, lens)
-    o, d = run_pair(env, orc, cam, lens, dataclasses.replace(env["params"], m=6), gb)
-    compare_frame(o, d, "hexagon 202x118")
+    o, d = run_pair(env, orc, cam, lens, dataclasses.replace(env["params"], m=6, pp_polygon=polygon), gb)
+    compare_frame(o, d, f"hexagon 202x118 polygon={polygon}")
 
 
 def test_pinhole_reduction_on_gpu(env, orc):

@@ -151,15 +151,57 @@ def test_median_postfilter_is_median(small):
     assert np.array_equal(small["out"]["ppmed"][..., :3], np.median(stack, axis=0).astype(np.float32))
 
 
-def test_constant_image_is_preserved(orc):
-    """Normalised filters leave a constant image constant (3.1.1-3.1.3)."""
-    lens = synth.Lens()
+@pytest.mark.parametrize("blades,polygon", [(0, 0), (6, 1), (5, 1)])
+def test_constant_image_is_preserved(orc, blades, polygon):
+    """Normalised filters leave a constant image constant (3.1.1-3.1.3),
+    with the circular gather kernel and with the polygonal one."""
+    lens = synth.Lens(blades=blades, blade_rot=0.4)
     sc = orc.OracleScene(plane_scene(3.0))
     cam = synth.look_camera((0, 0, 0), 0, 0, 128, 64)
     col = (0.3, 0.6, 0.9)
-    out = orc.render_frame(sc, cam, lens, synth.Params(), gb_from_half(orc, np.full((32, 64), 3.0), colour=col))
+    out = orc.render_frame(sc, cam, lens, synth.Params(pp_polygon=polygon),
+                           gb_from_half(orc, np.full((32, 64), 3.0), colour=col))
     for k in ("pre", "gather", "ppmed"):
         np.testing.assert_allclose(out[k][..., :3], np.broadcast_to(col, out[k][..., :3].shape), rtol=2e-5)
+
+
+def _aperture_norm(x, y, lens):
+    """Norm of the lens aperture (blade normals at rot + pi/B + 2 pi i/B,
+    apothem cos(pi/B)) of the lens points behind gather offsets (x, y):
+    the offsets are the aperture's far-field image reflected, (-px, py)."""
+    B, rot = lens.blades, lens.blade_rot
+    th = rot + math.pi / B + 2.0 * math.pi * np.arange(B) / B
+    px, py = -np.asarray(x, np.float64), np.asarray(y, np.float64)
+    return np.max(np.outer(px, np.cos(th)) + np.outer(py, np.sin(th)), axis=1) / math.cos(math.pi / B)
+
+
+@pytest.mark.parametrize("blades,rot", [(6, 0.3), (5, 0.0), (8, 1.1)])
+def test_polygon_gather_taps_lie_on_the_aperture(orc, blades, rot):
+    """Section 2: polygonal bokeh by changing the shape of the sampling
+    kernel.  Ring k's 8k taps lie on the aperture polygon scaled to k/4 (its
+    own norm), one tap every 1/(8k) of the perimeter (chords between
+    neighbours equal the step unless a corner lies between them)."""
+    lens = synth.Lens(blades=blades, blade_rot=rot)
+    ox, oy, fr = orc.gather_rings(lens, synth.Params(pp_polygon=1))
+    assert ox[0] == 0.0 and oy[0] == 0.0 and fr[0] == 0.0
+    side = 2.0 * math.sin(math.pi / blades)
+    i = 1
+    for k in range(1, 5):
+        n = 8 * k
+        sl = slice(i, i + n)
+        assert np.all(fr[sl] == np.float32(0.25 * k))
+        np.testing.assert_allclose(_aperture_norm(ox[sl], oy[sl], lens), k / 4.0, rtol=2e-6)
+        step = (k / 4.0) * blades * side / n
+        x, y = ox[sl].astype(np.float64), oy[sl].astype(np.float64)
+        chords = np.hypot(np.diff(np.append(x, x[0])), np.diff(np.append(y, y[0])))
+        assert np.all(chords <= step * (1 + 1e-5))
+        if n > blades:      # some neighbours share an edge
+            assert chords.max() == pytest.approx(step, rel=1e-5)
+        i += n
+    # without the flag (or without blades) the kernel stays circular
+    for lz, pz in ((lens, synth.Params(pp_polygon=0)), (synth.Lens(blades=0), synth.Params(pp_polygon=1))):
+        cx, cy, cf = orc.gather_rings(lz, pz)
+        np.testing.assert_allclose(np.hypot(cx, cy), cf, atol=1e-6)
 
 
 def test_all_in_focus_gather_is_identity(orc):
