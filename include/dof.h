@@ -104,7 +104,13 @@ typedef struct {
      * polygon instead of circles (section 2 names polygonal bokeh as a
      * change of the sampling kernel's shape); 0 (default): circles */
     int32_t pp_polygon;
-    int32_t reserved[2];
+    /* 1: final temporal anti-aliasing after the composite (section 3.4, after
+     * Karis 2014): the composite colour blended with the previous output at
+     * the reprojected position, that history clamped to the current 3 x 3
+     * colour range, history weight 0.9.  The previous output lives in the
+     * history buffer; turning it on mid-sequence needs history.reset. */
+    int32_t taa;
+    int32_t reserved[1];
 } dof_params;
 
 /* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view
@@ -118,11 +124,14 @@ typedef struct {
 } dof_gbuffer;
 
 /* Temporal history (3.2.3): dof_history_bytes() per buffer.  `in` is last
- * frame's `out` (ignored when reset != 0); `out` is written completely.
- * in and out must not overlap.  prev_camera / prev_lens: the view of `in`.
- * Record layout (per half-res pixel, four planes back to back): float4
- * (near rgb, hit ratio), float4 (far rgb, age), float4 (near CoC, far CoC,
- * luma mean, luma second moment), float (blurred luma variance). */
+ * frame's `out` (ignored when reset != 0); `out` is written completely
+ * (its TAA plane only when params.taa is set).  in and out must not
+ * overlap.  prev_camera / prev_lens: the view of `in`.  Layout: the
+ * half-res record, four planes back to back -- float4 (near rgb, hit
+ * ratio), float4 (far rgb, age), float4 (near CoC, far CoC, luma mean, luma
+ * second moment), float (blurred luma variance) -- then, from the record's
+ * size rounded up to 16 bytes, the previous output colour for the final TAA
+ * (float4 per full-res pixel). */
 typedef struct {
     const void *in;
     void *out;

@@ -36,7 +36,7 @@ class OrcParams(C.Structure):
                 ("var_recon_w", C.c_float), ("b_max", C.c_float), ("h_edge", C.c_float),
                 ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32),
-                ("l_spec", C.c_float), ("mask_mode", C.c_int32), ("pp_polygon", C.c_int32)]
+                ("l_spec", C.c_float), ("mask_mode", C.c_int32), ("pp_polygon", C.c_int32), ("taa", C.c_int32)]
 
 
 class OrcScene(C.Structure):
@@ -124,7 +124,7 @@ def gather_rings(lens, params):
 def params_struct(p) -> OrcParams:
     return OrcParams(p.m, p.s, p.var_mask_w, p.alpha, p.alpha_motion, p.var_recon_w, p.b_max,
                      p.h_edge, p.lod_scale, p.lod_max, p.depth_range, p.r_max, p.tile,
-                     p.l_spec, p.mask_mode, getattr(p, "pp_polygon", 0))
+                     p.l_spec, p.mask_mode, getattr(p, "pp_polygon", 0), getattr(p, "taa", 0))
 
 
 class OracleScene:
@@ -223,11 +223,18 @@ def gbuffer(scene: OracleScene, cam, lens, use_bvh=True) -> GBuffer:
     return g
 
 
-HIST_FLOATS_PER_PX = 13
+def taa_offset(width: int, height: int) -> int:
+    """Float offset of the full-res TAA colour plane in a history buffer:
+    after the half-res record (13 floats per half-res pixel), 16-byte aligned."""
+    return (13 * (width // 2) * (height // 2) + 3) & ~3
+
+
+def history_floats(width: int, height: int) -> int:
+    return taa_offset(width, height) + 4 * width * height
 
 
 def history_zeros(width: int, height: int) -> np.ndarray:
-    return np.zeros((width // 2) * (height // 2) * HIST_FLOATS_PER_PX, np.float32)
+    return np.zeros(history_floats(width, height), np.float32)
 
 
 def mip_dims(hw: int, hh: int):
@@ -248,7 +255,7 @@ def render_frame(scene: OracleScene, cam, lens, params, gb: GBuffer, hist_in=Non
     T = params.tile
     tw, th = (hw + T - 1) // T, (hh + T - 1) // T
     out = dict(colour=np.zeros((H, W, 4), np.float32), mask=np.zeros((hh, hw), np.uint8),
-               hist_out=np.zeros(npx * HIST_FLOATS_PER_PX, np.float32))
+               hist_out=history_zeros(cam.width, cam.height))
     dbg = None
     if debug:
         rmax = npx * params.m

@@ -1359,6 +1359,75 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             o[3] = 1.0f;
         }
 
+    /* A15 -- final temporal anti-aliasing (3.4, after Karis 2014), with
+     * params->taa: each full-res pixel's composite colour is blended with the
+     * previous output at the pixel's reprojected position (its G-buffer
+     * point, or its direction for the sky, seen by the previous camera;
+     * bilinear), that history clamped per channel to the range of the
+     * current colour over the 3 x 3 neighbourhood, history weight 0.9.  The
+     * result is the output and the next frame's TAA history (the full-res
+     * plane after the half-res record, from its size rounded up to 16 bytes). */
+    if (p->taa) {
+        float *comp = (float *)malloc(sizeof(float) * 4 * (size_t)W * H);
+        if (comp) {
+            memcpy(comp, out_colour, sizeof(float) * 4 * (size_t)W * H);
+            const size_t taa_off = (13 * np + 3) & ~(size_t)3;   /* 16-byte aligned */
+            const float *taa_in = hist_in ? hist_in + taa_off : NULL;
+            float *taa_out = hist_out + taa_off;
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < W; x++) {
+                    size_t pidx = (size_t)y * W + x;
+                    float mn[3], mx[3];
+                    for (int cc = 0; cc < 3; cc++) { mn[cc] = INFINITY; mx[cc] = -INFINITY; }
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            const float *v = comp + 4 * ((size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1));
+                            for (int cc = 0; cc < 3; cc++) {
+                                mn[cc] = v[cc] < mn[cc] ? v[cc] : mn[cc];
+                                mx[cc] = v[cc] > mx[cc] ? v[cc] : mx[cc];
+                            }
+                        }
+                    const float *c = comp + 4 * pidx;
+                    float *o = out_colour + 4 * pidx;
+                    int valid = 0;
+                    float hcol[4];
+                    if (have_hist && taa_in) {
+                        float fv[3], P[3], e[3];
+                        pixel_dir(cam, &q, x, y, W, H, fv);
+                        float z = gb_depth[pidx];
+                        int isdir = !(z < INFINITY);
+                        for (int a = 0; a < 3; a++) P[a] = isdir ? fv[a] : cam->pos[a] + z * fv[a];
+                        for (int a = 0; a < 3; a++) e[a] = isdir ? P[a] : P[a] - prev_cam->pos[a];
+                        float ex = (e[0] * prev_cam->right[0] + e[1] * prev_cam->right[1]) + e[2] * prev_cam->right[2];
+                        float ey = (e[0] * prev_cam->up[0] + e[1] * prev_cam->up[1]) + e[2] * prev_cam->up[2];
+                        float ez = (e[0] * prev_cam->fwd[0] + e[1] * prev_cam->fwd[1]) + e[2] * prev_cam->fwd[2];
+                        if (ez > 0.0f) {
+                            float pu = (ex / ez) / pq.tanx, pv = (ey / ez) / pq.tany;
+                            float px = ((pu + 1.0f) * 0.5f) * (float)W - 0.5f;
+                            float py = ((1.0f - pv) * 0.5f) * (float)H - 0.5f;
+                            if (px + 0.5f >= 0.0f && px + 0.5f < (float)W && py + 0.5f >= 0.0f && py + 0.5f < (float)H) {
+                                bilinear4(taa_in, W, H, px, py, hcol);
+                                valid = 1;
+                            }
+                        }
+                    }
+                    for (int cc = 0; cc < 3; cc++) {
+                        float v = c[cc];
+                        if (valid) {
+                            float h = hcol[cc];
+                            h = h > mn[cc] ? h : mn[cc];
+                            h = h < mx[cc] ? h : mx[cc];
+                            v = lerpf(c[cc], h, 0.9f);
+                        }
+                        o[cc] = v;
+                    }
+                    o[3] = 1.0f;
+                    for (int cc = 0; cc < 4; cc++) taa_out[4 * pidx + cc] = o[cc];
+                }
+            free(comp);
+        }
+    }
+
     if (dbg) {
         if (dbg->colr) memcpy(dbg->colr, colr, np * 16);
         if (dbg->zn) memcpy(dbg->zn, zn, np * 16);

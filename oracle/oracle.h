@@ -46,6 +46,7 @@ typedef struct {
     float l_spec;
     int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all, 3 adaptive dilated by the neighbourhood max CoC */
     int32_t pp_polygon;                     /* 1: post-process gather taps on the aperture polygon (bladed lenses) */
+    int32_t taa;                            /* 1: final temporal anti-aliasing (history: full-res plane after the record) */
 } orc_params;
 
 typedef struct {

@@ -82,7 +82,7 @@ SceneLayout scene_layout(int64_t n)
     return L;
 }
 
-dof::ScratchLayout frame_layout(int W, int H, int m)
+dof::ScratchLayout frame_layout(int W, int H, int m, bool taa)
 {
     dof::ScratchLayout L{};
     const size_t np = (size_t)(W / 2) * (H / 2);
@@ -131,6 +131,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m)
     L.mips = take(16 * mt);
     L.tap = take(8 * np);
     L.recon = take(16 * np);
+    L.comp = taa ? take(16 * (size_t)W * H) : 0;   // composite colour before the final TAA
     L.spill = take(kSpillBytes);
     L.total = off;
     return L;
@@ -267,6 +268,7 @@ dof_status params_check(const dof_params *p)
     if (p->tile != dof::kTile) return fail(DOF_E_UNSUPPORTED, "tile must be 16");
     if (p->mask_mode < 0 || p->mask_mode > 3) return fail(DOF_E_INVALID, "bad mask_mode");
     if (p->pp_polygon != 0 && p->pp_polygon != 1) return fail(DOF_E_INVALID, "bad pp_polygon");
+    if (p->taa != 0 && p->taa != 1) return fail(DOF_E_INVALID, "bad taa");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
@@ -291,6 +293,7 @@ void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens 
     fc.D = (int)ceilf(p.r_max / (float)fc.T);
     fc.m = p.m;
     fc.mask_mode = p.mask_mode;
+    fc.taa = p.taa;
     fc.have_hist = have_hist;
     fc.motion = motion;
     fc.seed = cam.seed;
@@ -371,7 +374,7 @@ dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *
         return fail(DOF_E_INVALID, "bad output format");
     if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
-    L = frame_layout(cam->width, cam->height, p->m);
+    L = frame_layout(cam->width, cam->height, p->m, p->taa != 0);
     if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
     have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
                 hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
@@ -403,6 +406,7 @@ struct dof_batch {
     uint32_t *spill;                   // traversal spill (first frame's scratch)
     int32_t trace_blocks;
     bool dilate;                       // params.mask_mode == DOF_MASK_DILATE
+    bool taa;                          // params.taa
     std::vector<char> host;            // staging copy of the table
 };
 
@@ -556,7 +560,8 @@ dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes)
 {
     if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
         return fail(DOF_E_INVALID, "width/height must be even and positive");
-    *bytes = (size_t)(width / 2) * (height / 2) * 52;
+    const size_t record = ((size_t)(width / 2) * (height / 2) * 52 + 15) & ~(size_t)15;
+    *bytes = record + (size_t)width * height * 16;   // half-res record, then the full-res TAA colour
     return DOF_OK;
 }
 
@@ -576,7 +581,7 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
         return fail(DOF_E_INVALID, "width/height must be even and positive");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
-    *bytes = frame_layout(width, height, p->m).total;
+    *bytes = frame_layout(width, height, p->m, p->taa != 0).total;
     return DOF_OK;
 }
 
@@ -689,6 +694,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
     for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
     b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
     b->dilate = p->mask_mode == DOF_MASK_DILATE;
+    b->taa = p->taa != 0;
     b->n = n;
     return DOF_OK;
 }
@@ -703,7 +709,7 @@ dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
     const dof::Rings &rings = ring_table();
     DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, s));
     DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, s));
-    DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, s));
+    DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
     return DOF_OK;
 }
@@ -727,7 +733,7 @@ dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, cons
         return fail(DOF_E_INVALID, "bad arguments");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
-    const dof::ScratchLayout L = frame_layout(width, height, p->m);
+    const dof::ScratchLayout L = frame_layout(width, height, p->m, p->taa != 0);
     char *s = static_cast<char *>(scratch);
     out->colr = s + L.colr;
     out->zn = s + L.zn;

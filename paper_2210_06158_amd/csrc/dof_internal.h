@@ -77,7 +77,7 @@ struct ViewConst {    // a camera with its lens-derived projection
 
 struct FrameConst {
     int32_t W, H, hw, hh, tw, th, T, D;
-    int32_t m, mask_mode, have_hist, motion;
+    int32_t m, mask_mode, have_hist, motion, taa;
     uint32_t seed, frame;
     float d, half_a, cock, znb, ramp;
     float s, var_mask_w, alpha_h, var_recon_w, b_max, h_edge, lod_scale, lod_max, depth_range;
@@ -95,7 +95,7 @@ struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
-    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon;
+    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp;
     size_t spill;
     size_t total;
     int64_t nchunks;
@@ -118,6 +118,7 @@ struct Planes {
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
     float2 *za;              // per half-res pixel: (depth, gather weight 1 / max(|r|, 1/2)^2)
     uint8_t *mask_raw;       // adaptive ray counts before dilation (mask mode DOF_MASK_DILATE)
+    float4 *comp;            // full-res composite colour before the final TAA (params.taa)
 };
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
 
@@ -225,6 +226,6 @@ hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, c
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
                               hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                             const Rings &rings, hipStream_t st);
+                             const Rings &rings, bool taa, hipStream_t st);
 
 }  // namespace dof

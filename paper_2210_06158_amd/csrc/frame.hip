@@ -164,6 +164,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.tap = reinterpret_cast<float2 *>(s + L.tap);
     p.za = reinterpret_cast<float2 *>(s + L.za);
     p.mask_raw = reinterpret_cast<uint8_t *>(s + L.mask_raw);
+    p.comp = fc.taa ? reinterpret_cast<float4 *>(s + L.comp) : nullptr;
     p.recon = reinterpret_cast<float4 *>(s + L.recon);
     return p;
 }
@@ -1129,7 +1130,8 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
         float w = (t * t) * (3.0f - 2.0f * t);
         o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
     }
-    st_rgba(out.colour, out.colour_format, p, o);
+    if (fc.taa) P.comp[p] = o;
+    else st_rgba(out.colour, out.colour_format, p, o);
 }
 
 __global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
@@ -1156,6 +1158,89 @@ __global__ void kb_stats(const Job *__restrict__ jobs, int njobs)
     o->rays = c[kCntRays];
     o->node_visits = 0;
     o->tri_tests = 0;
+}
+
+// ---------------------------------------------------------------- A15
+// Final temporal anti-aliasing (3.4, after Karis 2014): the composite colour
+// blended with the previous output at the pixel's reprojected position (its
+// G-buffer point, or direction for the sky, in the previous camera;
+// bilinear), that history clamped per channel to the current 3 x 3 range,
+// history weight 0.9.  Writes the output and the next frame's TAA history.
+
+__device__ inline void b_taa(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb, const void *hist_in,
+                             void *hist_out, const dof_frame_out &out, const uint32_t bx, const uint32_t by)
+{
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+    const int W = fc.W, H = fc.H;
+    if (x >= W || y >= H) return;
+    const size_t p = (size_t)y * W + x;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const float4 v = P.comp[(size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            const float vv[3] = {v.x, v.y, v.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                mn[c] = vv[c] < mn[c] ? vv[c] : mn[c];
+                mx[c] = vv[c] > mx[c] ? vv[c] : mx[c];
+            }
+        }
+    const float4 cur = P.comp[p];
+    const size_t taa_off = ((size_t)fc.hw * fc.hh * 13 + 3) & ~(size_t)3;   // floats; 16-byte aligned
+    bool valid = false;
+    float4 hc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (fc.have_hist && hist_in) {
+        float fv[3], Pw[3], e[3];
+        pixel_dir(fc.cur, x, y, W, H, fv);
+        const float z = gb.depth[p];
+        const bool isdir = !(z < INFINITY);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Pw[a] = isdir ? fv[a] : fc.cur.pos[a] + z * fv[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) e[a] = isdir ? Pw[a] : Pw[a] - fc.prev.pos[a];
+        const float ex = (e[0] * fc.prev.right[0] + e[1] * fc.prev.right[1]) + e[2] * fc.prev.right[2];
+        const float ey = (e[0] * fc.prev.up[0] + e[1] * fc.prev.up[1]) + e[2] * fc.prev.up[2];
+        const float ez = (e[0] * fc.prev.fwd[0] + e[1] * fc.prev.fwd[1]) + e[2] * fc.prev.fwd[2];
+        if (ez > 0.0f) {
+            const float pu = (ex / ez) / fc.prev.tanx, pv = (ey / ez) / fc.prev.tany;
+            const float px = ((pu + 1.0f) * 0.5f) * (float)W - 0.5f;
+            const float py = ((1.0f - pv) * 0.5f) * (float)H - 0.5f;
+            if (px + 0.5f >= 0.0f && px + 0.5f < (float)W && py + 0.5f >= 0.0f && py + 0.5f < (float)H) {
+                hc = bilinear4(reinterpret_cast<const float4 *>(static_cast<const float *>(hist_in) + taa_off), W, H,
+                               px, py);
+                valid = true;
+            }
+        }
+    }
+    const float cv[3] = {cur.x, cur.y, cur.z}, hv[3] = {hc.x, hc.y, hc.z};
+    float o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float v = cv[c];
+        if (valid) {
+            float h = hv[c];
+            h = h > mn[c] ? h : mn[c];
+            h = h < mx[c] ? h : mx[c];
+            v = lerp1(cv[c], h, 0.9f);
+        }
+        o[c] = v;
+    }
+    const float4 r = make_float4(o[0], o[1], o[2], 1.0f);
+    st_rgba(out.colour, out.colour_format, p, r);
+    reinterpret_cast<float4 *>(static_cast<float *>(hist_out) + taa_off)[p] = r;
+}
+
+__global__ __launch_bounds__(kBX *kBY) void k_taa(FrameConst fc, Planes P, dof_gbuffer gb, const void *hist_in,
+                                                  void *hist_out, dof_frame_out out)
+{
+    b_taa(fc, P, gb, hist_in, hist_out, out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_taa(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridFull, blockIdx.x, bx, by)];
+    b_taa(J.fc, J.P, J.gb, J.hist_in, J.hist_out, J.out, bx, by);
 }
 
 __global__ void k_fill_zero(float *p, int64_t n)
@@ -1223,6 +1308,7 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
     k_recon<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
     DOF_REC(12);
     k_composite<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, out);
+    if (fc.taa) k_taa<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);
     DOF_REC(13);
     if (out.stats) {
         // copy the frame counters to the caller's stats record
@@ -1256,13 +1342,14 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
 }
 
 hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                             hipStream_t st)
+                             bool taa, hipStream_t st)
 {
     kb_resolve<<<nblk[kGridResolve], 64, 0, st>>>(jobs, njobs);
     kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
     kb_composite<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    if (taa) kb_taa<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }

@@ -39,7 +39,7 @@ class DofParams(C.Structure):
                 ("b_max", C.c_float), ("h_edge", C.c_float), ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32), ("l_spec", C.c_float),
                 ("mask_mode", C.c_int32), ("trace_blocks", C.c_int32), ("timing", C.c_int32),
-                ("pp_polygon", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("pp_polygon", C.c_int32), ("taa", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class DofGBuffer(C.Structure):
@@ -171,6 +171,7 @@ def params_struct(p, trace_blocks: int = 0, timing: bool = False) -> DofParams:
               "lod_max", "depth_range", "r_max", "tile", "l_spec", "mask_mode"):
         setattr(s, k, getattr(p, k))
     s.pp_polygon = int(getattr(p, "pp_polygon", 0))
+    s.taa = int(getattr(p, "taa", 0))
     s.trace_blocks = trace_blocks
     s.timing = 1 if timing else 0
     return s

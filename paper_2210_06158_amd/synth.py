@@ -100,6 +100,7 @@ class Params:
     l_spec: float = 1.0         # luma above which a tap counts as a bright (specular) sample
     mask_mode: int = MASK_ADAPTIVE
     pp_polygon: int = 0         # 1: post-process gather kernel shaped like a bladed aperture
+    taa: int = 0                # 1: final temporal anti-aliasing (3.4)
 
 
 @dataclass

@@ -53,7 +53,9 @@ def test_abi_version_and_defaults(dof):
 def test_size_queries(dof):
     L = dof.lib()
     b = C.c_size_t()
-    assert L.dof_history_bytes(1920, 1080, C.byref(b)) == 0 and b.value == 960 * 540 * 52
+    # half-res record (52 B per half-res pixel, rounded up to 16 B), then the full-res TAA colour
+    assert L.dof_history_bytes(1920, 1080, C.byref(b)) == 0 and b.value == 960 * 540 * 52 + 1920 * 1080 * 16
+    assert L.dof_history_bytes(202, 118, C.byref(b)) == 0 and b.value == (101 * 59 * 52 + 15) // 16 * 16 + 202 * 118 * 16
     assert L.dof_history_bytes(1921, 1080, C.byref(b)) == dof.DOF_E_INVALID
     assert L.dof_scene_bytes(0, C.byref(b)) == dof.DOF_E_INVALID
     assert L.dof_scene_bytes(1000, C.byref(b)) == 0 and b.value > 1000 * 200

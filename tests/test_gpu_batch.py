@@ -193,6 +193,37 @@ def test_batch_second_frame_with_history(sess):
             it["cam"] = c0
 
 
+def test_batch_with_taa_equals_single_frames(sess):
+    """taa = 1 (one more full-resolution kernel after the composite): frame 0
+    and then frame 1 on that TAA history, batched vs alone."""
+    torch, dof = sess["torch"], sess["dof"]
+    params = sess["params"]
+    saved = [it["cam"] for it in sess["items"]]
+    try:
+        sess["params"] = dataclasses.replace(params, taa=1)
+        alone0 = render_alone(sess)
+        frs, houts = make_frames(sess)
+        b = dof.Batch(4, sess["params"])
+        b.set(batch_items(sess, frs, houts))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone0[k], f"TAA frame 0 item {k}")
+        hist = [torch.from_numpy(a["hist_out"]).cuda() for a in alone0]
+        prev = list(saved)
+        for it in sess["items"]:
+            it["cam"] = dataclasses.replace(synth.pan_camera(it["cam"], 0.02), frame=1)
+        alone1 = render_alone(sess, hist_in=hist, prev=prev)
+        frs, houts = make_frames(sess)
+        b.set(batch_items(sess, frs, houts, hist_in=hist, prev=prev))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone1[k], f"TAA frame 1 item {k}")
+    finally:
+        sess["params"] = params
+        for it, c0 in zip(sess["items"], saved):
+            it["cam"] = c0
+
+
 def test_batch_item_matches_oracle(sess, orc):
     """The hexagonal-aperture item of a batch against the CPU oracle."""
     torch, dof = sess["torch"], sess["dof"]

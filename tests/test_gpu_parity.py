@@ -296,3 +296,41 @@ def test_determinism_run_twice(env, orc, frame0):
     _, d1 = run_pair(env, orc, env["cam"], env["lens"], env["params"], gb)
     for k in ("colour", "mask", "queue", "ray_hit", "ray_col", "recon", "hist_out"):
         assert np.array_equal(d0[k], d1[k]), k
+
+
+# ---------------------------------------------------------------- final TAA
+
+@pytest.fixture(scope="module")
+def taa0(env, orc, frame0):
+    gb, _, _ = frame0
+    p = dataclasses.replace(env["params"], taa=1)
+    o, d = run_pair(env, orc, env["cam"], env["lens"], p, gb)
+    return p, o, d
+
+
+def test_taa_frame0_is_the_composite(taa0, frame0):
+    """Without history the final TAA passes the composite through: same
+    stages and colour as the frame without TAA, and the TAA history plane
+    holds that colour."""
+    _, o, d = taa0
+    _, o_plain, d_plain = frame0
+    compare_frame(o, d, "TAA frame 0")
+    assert np.array_equal(d["colour"][..., :3], d_plain["colour"][..., :3])
+    W, H = o["colour"].shape[1], o["colour"].shape[0]
+    from oracle import taa_offset
+    plane = d["hist_out"][taa_offset(W, H):].reshape(H, W, 4)
+    assert np.array_equal(plane[..., :3], d["colour"][..., :3])
+
+
+def test_taa_frame1_pan_parity(env, orc, taa0):
+    """Second frame after a pan, both sides fed the oracle's TAA history of
+    frame 0: reprojected, clamped history blended at weight 0.9."""
+    p, o0, _ = taa0
+    cam1 = synth.pan_camera(env["cam"], 0.02)
+    gb1 = orc.gbuffer(env["osc"], cam1, env["lens"])
+    o, d = run_pair(env, orc, cam1, env["lens"], p, gb1, hist_in=o0["hist_out"], prev_cam=env["cam"],
+                    prev_lens=env["lens"])
+    compare_frame(o, d, "TAA frame 1 pan")
+    plain = orc.render_frame(env["osc"], cam1, env["lens"], dataclasses.replace(p, taa=0), gb1,
+                             hist_in=o0["hist_out"], prev_cam=env["cam"], prev_lens=env["lens"])
+    assert np.abs(plain["colour"][..., :3] - o["colour"][..., :3]).max() > 1e-3   # the history took part

@@ -451,3 +451,89 @@ def test_mask_dilation_is_identity_without_blur(orc, small):
     raw, dil = _dilate_pair(orc, small, 64, 48, lens)
     assert np.all(dil["tile_dil"] == 0.0)
     assert np.array_equal(dil["mask"], raw["mask"])
+
+
+# ---------------------------------------------------------------- final TAA (3.4)
+
+def _taa_plane(hist, W, H):
+    import oracle
+    return hist[oracle.taa_offset(W, H):].reshape(H, W, 4)
+
+
+def test_taa_without_history_is_the_composite(orc, small):
+    cam, lens, gb = small["cam"], small["lens"], small["gb"]
+    off = orc.render_frame(small["sc"], cam, lens, small["params"], gb)
+    on = orc.render_frame(small["sc"], cam, lens, dataclasses.replace(small["params"], taa=1), gb)
+    assert np.array_equal(on["colour"], off["colour"])
+    assert np.array_equal(_taa_plane(on["hist_out"], cam.width, cam.height), on["colour"])
+
+
+def test_taa_keeps_a_constant_image_whatever_the_history(orc):
+    """The history is clamped to the current 3 x 3 range, which is a single
+    value on a constant image, so any history leaves the image unchanged."""
+    lens = synth.Lens()
+    sc = orc.OracleScene(plane_scene(lens.focus))
+    cam = synth.look_camera((0, 0, 0), 0, 0, 64, 48)
+    p = synth.Params(taa=1)
+    gb = orc.gbuffer(sc, cam, lens)
+    f0 = orc.render_frame(sc, cam, lens, p, gb)
+    assert np.all(f0["colour"] == f0["colour"][0, 0])
+    hist = f0["hist_out"].copy()
+    rng = np.random.default_rng(5)
+    _taa_plane(hist, 64, 48)[...] = rng.uniform(-3.0, 5.0, (48, 64, 4)).astype(np.float32)
+    f1 = orc.render_frame(sc, dataclasses.replace(cam, frame=1), lens, p, gb, hist_in=hist, prev_cam=cam,
+                          prev_lens=lens)
+    assert np.array_equal(f1["colour"], f0["colour"])
+
+
+def test_taa_onto_its_own_composite_is_identity(orc, small):
+    """Static camera, history = the current composite: every pixel reprojects
+    onto itself, so the blend returns the composite (up to the bilinear
+    weights of a self-reprojection computed in binary32)."""
+    cam, lens, gb, p = small["cam"], small["lens"], small["gb"], small["params"]
+    f0 = orc.render_frame(small["sc"], cam, lens, p, gb)
+    cam1 = dataclasses.replace(cam, frame=1)
+    comp1 = orc.render_frame(small["sc"], cam1, lens, p, gb, hist_in=f0["hist_out"], prev_cam=cam, prev_lens=lens)
+    hist = f0["hist_out"].copy()
+    _taa_plane(hist, cam.width, cam.height)[...] = comp1["colour"]
+    t1 = orc.render_frame(small["sc"], cam1, lens, dataclasses.replace(p, taa=1), gb, hist_in=hist, prev_cam=cam,
+                          prev_lens=lens)
+    np.testing.assert_allclose(t1["colour"], comp1["colour"], atol=1e-4)
+    assert not np.array_equal(f0["colour"], comp1["colour"])      # the composite itself changed between frames
+
+
+def test_taa_weight_window_and_reprojection_closed_form(orc):
+    """Pinhole lens, so the composite is the G-buffer colour: a seeded random
+    field over a plane at depth z0 facing the camera.  The camera pans right
+    by exactly s pixel pitches at that depth, so pixel x of the new frame sees
+    what pixel x + s saw.  The history plane holds the 3 x 3 minimum of the
+    new colour field (scipy, clamp to edge) moved s pixels right.  Expected
+    result: c + 0.9 (min - c) where x + s is on screen, c elsewhere."""
+    from scipy.ndimage import minimum_filter
+    W, H, s, z0 = 64, 48, 3, 10.0
+    lens = synth.Lens(fnum=math.inf)
+    tanx = (lens.sensor * (lens.focus - lens.focal)) / (2.0 * lens.focal * lens.focus)   # half field of view
+    cam0 = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    cam1 = synth.pan_camera(cam0, s * z0 * 2.0 * tanx / W)
+    rng = np.random.default_rng(9)
+    col = np.ones((H, W, 4), np.float32)
+    col[..., :3] = rng.uniform(0.0, 1.0, (H, W, 3))
+    nrm = np.zeros((H, W, 4), np.float32)
+    nrm[..., 2] = -1.0
+    gb = orc.GBuffer(col, np.full((H, W), z0, np.float32), nrm)
+    sc = orc.OracleScene(plane_scene(z0))
+    sc.build_bvh()
+    p = synth.Params(taa=1)
+    f0 = orc.render_frame(sc, cam0, lens, p, gb)
+    plain = orc.render_frame(sc, cam1, lens, dataclasses.replace(p, taa=0), gb, hist_in=f0["hist_out"],
+                             prev_cam=cam0, prev_lens=lens)
+    assert np.array_equal(plain["colour"][..., :3], col[..., :3])          # pinhole: composite = G-buffer
+    mn = minimum_filter(col[..., :3], size=(3, 3, 1), mode="nearest")
+    hist = f0["hist_out"].copy()
+    plane = _taa_plane(hist, W, H)
+    plane[:, s:, :3] = mn[:, :W - s]
+    plane[:, :s, :3] = 7.0                                                  # never fetched
+    t1 = orc.render_frame(sc, cam1, lens, p, gb, hist_in=hist, prev_cam=cam0, prev_lens=lens)
+    exp = col[..., :3].copy()
+    exp[:, :W - s] = col[:, :W - s, :3] + 0.9 * (mn[:, :W - s] - col[:, :W - s, :3])
+    np.testing.assert_allclose(t1["colour"][..., :3], exp, rtol=0, atol=2e-4)
