@@ -303,6 +303,25 @@ def main():
         m_sweep["mask_dilated_m8"] = {"frame_ms": round(rd["total_ms"] / rd["K"], 4),
                                       "trace_ms": round(rd["stage_ms"]["trace"], 4),
                                       "rays_per_frame": round(rd["rays"] / rd["K"], 1)}
+        # with the final TAA (3.4) after the composite; its kernel is timed
+        # inside the composite stage
+        pt = dataclasses.replace(params, taa=1)
+        rt = run_path(gs, cams, [lens] * nfr, pt, gbs, 20, 5, 20, args.trace_blocks, log)
+        m_sweep["final_taa_m8"] = {"frame_ms": round(rt["total_ms"] / rt["K"], 4),
+                                   "composite_and_taa_ms": round(rt["stage_ms"]["composite"], 4),
+                                   "composite_ms_without": round(stage_ms["composite"], 4)}
+        # all three TAA stages (raster, post-filter, final) on the camera path
+        # with seeded sub-pixel jitter (3.1.2), G-buffers rendered jittered
+        jc = synth.jittered(cams, seed=synth.BASE_SEED + 77)
+        jg = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in jc]
+        pa = dataclasses.replace(params, taa=synth.TAA_ALL)
+        ra = run_path(gs, jc, [lens] * nfr, pa, jg, 20, 5, 20, args.trace_blocks, log)
+        m_sweep["all_taa_jittered_m8"] = {"frame_ms": round(ra["total_ms"] / ra["K"], 4),
+                                          "reduce_ms": round(ra["stage_ms"]["reduce"], 4),
+                                          "median_ms": round(ra["stage_ms"]["median"], 4),
+                                          "composite_ms": round(ra["stage_ms"]["composite"], 4),
+                                          "rays_per_frame": round(ra["rays"] / ra["K"], 1)}
+        del jg
     del gbs
 
     w4k = None

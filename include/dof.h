@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define DOF_ABI_VERSION 1
+#define DOF_ABI_VERSION 2
 
 typedef int32_t dof_status;
 #define DOF_OK 0
@@ -63,10 +63,25 @@ typedef int32_t dof_status;
  * maximum CoC radius, rounded up (r_max must be <= 32 in this mode) */
 #define DOF_MASK_DILATE 3
 
+/* Bits of dof_params.taa: temporal anti-aliasing stages (section 3.4, after
+ * Karis 2014).  Each blends an image with its previous version at the
+ * reprojected position, that history clamped per RGB channel to the current
+ * 3 x 3 range, history weight 0.9; each keeps its previous version in its
+ * own plane of the history buffer. */
+#define DOF_TAA_FINAL 1     /* the output, after the composite */
+#define DOF_TAA_RASTER 2    /* the G-buffer colour, before any filtering; every later stage reads the result */
+#define DOF_TAA_POST 4      /* the half-res post-filter output, before the composite reads it */
+
 typedef struct {
     float pos[3], right[3], up[3], fwd[3];
     int32_t width, height;  /* full resolution */
     uint32_t frame, seed;   /* counters of the lens-sample hash */
+    /* sub-pixel camera jitter (section 3.1.2): this frame's sample positions
+     * sit (jitter[0], jitter[1]) full-res pixels right of and below the pixel
+     * centres, for the G-buffer rays, the traced rays and the reconstruction
+     * of world points from depth; |jitter| <= 1.  Projections into the
+     * previous view ignore its jitter (histories are unjittered images). */
+    float jitter[2];
 } dof_camera;
 
 /* Thin lens (sections 1.1, 3.3): focal length f, f-number N (aperture
@@ -104,11 +119,9 @@ typedef struct {
      * polygon instead of circles (section 2 names polygonal bokeh as a
      * change of the sampling kernel's shape); 0 (default): circles */
     int32_t pp_polygon;
-    /* 1: final temporal anti-aliasing after the composite (section 3.4, after
-     * Karis 2014): the composite colour blended with the previous output at
-     * the reprojected position, that history clamped to the current 3 x 3
-     * colour range, history weight 0.9.  The previous output lives in the
-     * history buffer; turning it on mid-sequence needs history.reset. */
+    /* TAA stages, bits DOF_TAA_* (0 = none).  A stage's previous image lives
+     * in the history buffer; turning a stage on mid-sequence needs
+     * history.reset. */
     int32_t taa;
     int32_t reserved[1];
 } dof_params;
@@ -125,13 +138,13 @@ typedef struct {
 
 /* Temporal history (3.2.3): dof_history_bytes() per buffer.  `in` is last
  * frame's `out` (ignored when reset != 0); `out` is written completely
- * (its TAA plane only when params.taa is set).  in and out must not
- * overlap.  prev_camera / prev_lens: the view of `in`.  Layout: the
- * half-res record, four planes back to back -- float4 (near rgb, hit
- * ratio), float4 (far rgb, age), float4 (near CoC, far CoC, luma mean, luma
- * second moment), float (blurred luma variance) -- then, from the record's
- * size rounded up to 16 bytes, the previous output colour for the final TAA
- * (float4 per full-res pixel). */
+ * (a TAA plane only when its stage is on).  in and out must not overlap.
+ * prev_camera / prev_lens: the view of `in`.  Layout: the half-res record,
+ * four planes back to back -- float4 (near rgb, hit ratio), float4 (far rgb,
+ * age), float4 (near CoC, far CoC, luma mean, luma second moment), float
+ * (blurred luma variance) -- then, from the record's size rounded up to 16
+ * bytes, the TAA planes of float4 per pixel: the final output (full res),
+ * the raster colour (full res), the post-filter output (half res). */
 typedef struct {
     const void *in;
     void *out;

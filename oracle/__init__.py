@@ -22,7 +22,7 @@ _f3 = C.c_float * 3
 class OrcCamera(C.Structure):
     _fields_ = [("pos", _f3), ("right", _f3), ("up", _f3), ("fwd", _f3),
                 ("width", C.c_int32), ("height", C.c_int32),
-                ("frame", C.c_uint32), ("seed", C.c_uint32)]
+                ("frame", C.c_uint32), ("seed", C.c_uint32), ("jitter", C.c_float * 2)]
 
 
 class OrcLens(C.Structure):
@@ -103,7 +103,8 @@ def _ptr(a):
 
 def camera_struct(cam) -> OrcCamera:
     return OrcCamera(_f3(*cam.pos), _f3(*cam.right), _f3(*cam.up), _f3(*cam.fwd),
-                     cam.width, cam.height, cam.frame & 0xFFFFFFFF, cam.seed & 0xFFFFFFFF)
+                     cam.width, cam.height, cam.frame & 0xFFFFFFFF, cam.seed & 0xFFFFFFFF,
+                     (C.c_float * 2)(*getattr(cam, "jitter", (0.0, 0.0))))
 
 
 def lens_struct(lens) -> OrcLens:
@@ -224,13 +225,24 @@ def gbuffer(scene: OracleScene, cam, lens, use_bvh=True) -> GBuffer:
 
 
 def taa_offset(width: int, height: int) -> int:
-    """Float offset of the full-res TAA colour plane in a history buffer:
-    after the half-res record (13 floats per half-res pixel), 16-byte aligned."""
+    """Float offset of the final TAA's full-res colour plane in a history
+    buffer: after the half-res record (13 floats per half-res pixel), 16-byte
+    aligned."""
     return (13 * (width // 2) * (height // 2) + 3) & ~3
 
 
-def history_floats(width: int, height: int) -> int:
+def raster_taa_offset(width: int, height: int) -> int:
+    """Float offset of the raster TAA's full-res plane (after the final's)."""
     return taa_offset(width, height) + 4 * width * height
+
+
+def post_taa_offset(width: int, height: int) -> int:
+    """Float offset of the post-filter TAA's half-res plane (after the raster's)."""
+    return raster_taa_offset(width, height) + 4 * width * height
+
+
+def history_floats(width: int, height: int) -> int:
+    return post_taa_offset(width, height) + 4 * (width // 2) * (height // 2)
 
 
 def history_zeros(width: int, height: int) -> np.ndarray:

@@ -51,6 +51,7 @@ typedef struct {
     float znb, zfb; /* zone of focus, eq. (6) with w_i = image width */
     float ramp;     /* width of the near/far transition (3.2.2) */
     float half_a;
+    float ju, jv;   /* camera jitter as an offset of normalised image coordinates */
 } lensq;
 
 static lensq lens_quantities(const orc_lens *l, int W, int H)
@@ -72,6 +73,8 @@ static lensq lens_quantities(const orc_lens *l, int W, int H)
     q.zfb = (af > g) ? (af * d) / (af - g) : INFINITY;
     q.ramp = 2.0f * (d - q.znb);
     q.half_a = q.a * 0.5f;
+    q.ju = 0.0f;
+    q.jv = 0.0f;
     return q;
 }
 
@@ -504,11 +507,20 @@ static void shade(const orc_scene *s, uint32_t id, const float d[3], float rgb[3
     if (nrm) { nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2]; }
 }
 
-/* Direction through the centre of pixel (x, y) of a w x h grid. */
+/* Sub-pixel camera jitter (3.1.2): the frame's sample positions move by
+ * (jitter[0], jitter[1]) full-res pixels to the right and down.  As an offset
+ * of the normalised image coordinates it is the same on every grid. */
+static void set_jitter(lensq *q, const orc_camera *c)
+{
+    q->ju = (c->jitter[0] * 2.0f) / (float)c->width;
+    q->jv = (c->jitter[1] * 2.0f) / (float)c->height;
+}
+
+/* Direction through the (jittered) centre of pixel (x, y) of a w x h grid. */
 static void pixel_dir(const orc_camera *c, const lensq *q, int x, int y, int w, int h, float fv[3])
 {
-    float u = ((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) * q->tanx;
-    float v = (1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) * q->tany;
+    float u = (((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) + q->ju) * q->tanx;
+    float v = ((1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) - q->jv) * q->tany;
     for (int a = 0; a < 3; a++) fv[a] = (c->fwd[a] + u * c->right[a]) + v * c->up[a];
 }
 
@@ -525,6 +537,7 @@ int orc_gbuffer(const orc_scene *s, const orc_bvh *b, const orc_camera *cam,
     if (!s || !cam || !lens || cam->width <= 0 || cam->height <= 0) return -1;
     int W = cam->width, H = cam->height;
     lensq q = lens_quantities(lens, W, H);
+    set_jitter(&q, cam);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(g_threads)
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
@@ -712,6 +725,73 @@ static int same_view(const orc_camera *a, const orc_camera *b, const orc_lens *l
 /* The per-frame pass                                                        */
 /* ------------------------------------------------------------------------ */
 
+/* One TAA resolve (3.4, after Karis 2014) of the w x h float4 image `cur`,
+ * whose pixel i sees view depth depth[i * dstride] through the jittered
+ * camera: its colour is blended with the history image `hin` (the same grid;
+ * NULL: none) fetched bilinearly where the pixel's point -- its direction for
+ * the sky -- lands in the previous camera (none behind it or off the grid),
+ * that history clamped per RGB channel to cur's range over the 3 x 3
+ * neighbourhood (clamp to edge); history weight 0.9.  The result goes to out
+ * and hout, its 4th channel 1, or cur's with keep_w. */
+static void taa_resolve(const float *cur, const float *depth, int dstride, int w, int h, const orc_camera *cam,
+                        const lensq *q, const orc_camera *pc, const lensq *pq, const float *hin, float *out,
+                        float *hout, int keep_w)
+{
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            size_t pidx = (size_t)y * w + x;
+            float mn[3], mx[3];
+            for (int cc = 0; cc < 3; cc++) { mn[cc] = INFINITY; mx[cc] = -INFINITY; }
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    const float *v = cur + 4 * ((size_t)clampi(y + dy, 0, h - 1) * w + clampi(x + dx, 0, w - 1));
+                    for (int cc = 0; cc < 3; cc++) {
+                        mn[cc] = v[cc] < mn[cc] ? v[cc] : mn[cc];
+                        mx[cc] = v[cc] > mx[cc] ? v[cc] : mx[cc];
+                    }
+                }
+            const float *c = cur + 4 * pidx;
+            int valid = 0;
+            float hcol[4];
+            if (hin) {
+                float fv[3], P[3], e[3];
+                pixel_dir(cam, q, x, y, w, h, fv);
+                float z = depth[pidx * (size_t)dstride];
+                int isdir = !(z < INFINITY);
+                for (int a = 0; a < 3; a++) P[a] = isdir ? fv[a] : cam->pos[a] + z * fv[a];
+                for (int a = 0; a < 3; a++) e[a] = isdir ? P[a] : P[a] - pc->pos[a];
+                float ex = (e[0] * pc->right[0] + e[1] * pc->right[1]) + e[2] * pc->right[2];
+                float ey = (e[0] * pc->up[0] + e[1] * pc->up[1]) + e[2] * pc->up[2];
+                float ez = (e[0] * pc->fwd[0] + e[1] * pc->fwd[1]) + e[2] * pc->fwd[2];
+                if (ez > 0.0f) {
+                    float pu = (ex / ez) / pq->tanx, pv = (ey / ez) / pq->tany;
+                    float px = ((pu + 1.0f) * 0.5f) * (float)w - 0.5f;
+                    float py = ((1.0f - pv) * 0.5f) * (float)h - 0.5f;
+                    if (px + 0.5f >= 0.0f && px + 0.5f < (float)w && py + 0.5f >= 0.0f && py + 0.5f < (float)h) {
+                        bilinear4(hin, w, h, px, py, hcol);
+                        valid = 1;
+                    }
+                }
+            }
+            float o[4];
+            for (int cc = 0; cc < 3; cc++) {
+                float v = c[cc];
+                if (valid) {
+                    float hv = hcol[cc];
+                    hv = hv > mn[cc] ? hv : mn[cc];
+                    hv = hv < mx[cc] ? hv : mx[cc];
+                    v = lerpf(c[cc], hv, 0.9f);
+                }
+                o[cc] = v;
+            }
+            o[3] = keep_w ? c[3] : 1.0f;
+            for (int cc = 0; cc < 4; cc++) {
+                out[4 * pidx + cc] = o[cc];
+                hout[4 * pidx + cc] = o[cc];
+            }
+        }
+}
+
 int orc_render_frame(const orc_scene *s, const orc_bvh *b,
                      const orc_camera *cam, const orc_lens *lens,
                      const orc_camera *prev_cam, const orc_lens *prev_lens,
@@ -731,7 +811,8 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     const size_t np = (size_t)hw * hh;
     const int T = p->tile, tw = (hw + T - 1) / T, th = (hh + T - 1) / T;
     const float d = lens->focus;
-    const lensq q = lens_quantities(lens, W, H);
+    lensq q = lens_quantities(lens, W, H);
+    set_jitter(&q, cam);
     int have_hist = !reset && hist_in && prev_cam && prev_lens && prev_cam->width == W && prev_cam->height == H;
     int motion = have_hist ? !same_view(cam, prev_cam, lens, prev_lens) : 0;
     lensq pq = have_hist ? lens_quantities(prev_lens, W, H) : q;
@@ -765,12 +846,35 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     for (int L = 1; L < 4; L++) { mw[L] = (mw[L - 1] + 1) >> 1; mh[L] = (mh[L - 1] + 1) >> 1; }
     for (int L = 0; L < 4; L++) { moff[L] = mtot; mtot += (size_t)mw[L] * mh[L] * 4; }
     float *mips = (float *)calloc(mtot, sizeof(float));
+    const int taa_final = (p->taa & ORC_TAA_FINAL) != 0, taa_rast = (p->taa & ORC_TAA_RASTER) != 0,
+              taa_post = (p->taa & ORC_TAA_POST) != 0;
+    float *rast = taa_rast ? (float *)calloc((size_t)W * H * 4, sizeof(float)) : NULL;
+    float *ppt = taa_post ? (float *)calloc(np * 4, sizeof(float)) : NULL;
+    float *comp = taa_final ? (float *)calloc((size_t)W * H * 4, sizeof(float)) : NULL;
     if (!colr || !zn || !tmax || !tdil || !pre || !gat || !ppm || !prev || !queue || !rbase || !res || !tmp ||
-        !var || !vblur || !rtmed || !rec || !hblur || !gblur || !mips) {
+        !var || !vblur || !rtmed || !rec || !hblur || !gblur || !mips || (taa_rast && !rast) || (taa_post && !ppt) ||
+        (taa_final && !comp)) {
         free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
         free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-        free(hblur); free(gblur); free(mips);
+        free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp);
         return -2;
+    }
+
+    /* History layout: the half-res record (13 floats per half-res pixel),
+     * then from its size rounded up to 16 bytes three TAA planes of float4
+     * per pixel: the final image's (full res), the raster image's (full res)
+     * and the post-filter output's (half res). */
+    const size_t taa_off = (13 * np + 3) & ~(size_t)3;
+    const size_t rast_off = taa_off + 4 * (size_t)W * H, post_off = rast_off + 4 * (size_t)W * H;
+    const float *hist_ok = have_hist ? hist_in : NULL;
+
+    /* A0 -- TAA of the raster image before filtering (3.4), with
+     * ORC_TAA_RASTER: every later stage reads the resolved colour. */
+    const float *gbc = gb_colour;
+    if (taa_rast) {
+        taa_resolve(gb_colour, gb_depth, 1, W, H, cam, &q, prev_cam, &pq, hist_ok ? hist_ok + rast_off : NULL, rast,
+                    hist_out + rast_off, 0);
+        gbc = rast;
     }
 
     /* A1 -- CoC and half-resolution reduce (3.1: the image is downscaled to
@@ -788,8 +892,8 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
                 if (gb_depth[t[k]] < z) { z = gb_depth[t[k]]; sel = k; }
             size_t i = (size_t)y * hw + x;
             for (int c = 0; c < 3; c++)
-                colr[4 * i + c] = ((gb_colour[4 * t[0] + c] + gb_colour[4 * t[1] + c]) +
-                                   (gb_colour[4 * t[2] + c] + gb_colour[4 * t[3] + c])) * 0.25f;
+                colr[4 * i + c] = ((gbc[4 * t[0] + c] + gbc[4 * t[1] + c]) + (gbc[4 * t[2] + c] + gbc[4 * t[3] + c])) *
+                                  0.25f;
             float r = coc_of(&q, d, z) * 0.25f;
             r = fmin_cs(r, p->r_max);
             colr[4 * i + 3] = z < d ? -r : r;
@@ -902,6 +1006,16 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             ppm[4 * i + 3] = gat[4 * i + 3];
         }
 
+    /* A5b -- TAA of the post-filter output (3.4), with ORC_TAA_POST, at half
+     * resolution (the quad's nearest depth locates each pixel); the composite
+     * reads the resolved image.  Its 4th channel passes through. */
+    const float *ppc = ppm;
+    if (taa_post) {
+        taa_resolve(ppm, zn, 4, hw, hh, cam, &q, prev_cam, &pq, hist_ok ? hist_ok + post_off : NULL, ppt,
+                    hist_out + post_off, 1);
+        ppc = ppt;
+    }
+
     /* A6 -- ray mask, eqs. (2)-(4) (3.2.1).  Gaussian (binomial 5-tap) on the
      * half-res depth feature d / z and the normals, then a 5x5 Sobel whose
      * gain is 1 per unit slope; x = (dd + dn) s, x_n = saturate(1 - 1/(x+1)), x_f = saturate(x_n
@@ -994,7 +1108,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
         if (!raw) {
             free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
             free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-            free(hblur); free(gblur); free(mips);
+            free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp); free(rast); free(ppt); free(comp);
             return -2;
         }
         memcpy(raw, out_mask, np);
@@ -1322,7 +1436,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             float c = coc_of(&q, d, z);
             float hx = (float)x * 0.5f - 0.25f, hy = (float)y * 0.5f - 0.25f;
             float pp[4];
-            bilinear4(ppm, hw, hh, hx, hy, pp);
+            bilinear4(ppc, hw, hh, hx, hy, pp);
             float x0f = floorf(hx), y0f = floorf(hy);
             float fx = hx - x0f, fy = hy - y0f;
             int x0 = (int)x0f, y0 = (int)y0f;
@@ -1346,7 +1460,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             }
             float *o = out_colour + 4 * pidx;
             if (c <= OR_SQRT2 && (!rtv || rct < OR_SQRT2)) {
-                for (int cc = 0; cc < 3; cc++) o[cc] = gb_colour[4 * pidx + cc];
+                for (int cc = 0; cc < 3; cc++) o[cc] = gbc[4 * pidx + cc];
             } else if (!rtv) {
                 for (int cc = 0; cc < 3; cc++) o[cc] = pp[cc];
             } else if (z < d) {
@@ -1360,72 +1474,11 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
         }
 
     /* A15 -- final temporal anti-aliasing (3.4, after Karis 2014), with
-     * params->taa: each full-res pixel's composite colour is blended with the
-     * previous output at the pixel's reprojected position (its G-buffer
-     * point, or its direction for the sky, seen by the previous camera;
-     * bilinear), that history clamped per channel to the range of the
-     * current colour over the 3 x 3 neighbourhood, history weight 0.9.  The
-     * result is the output and the next frame's TAA history (the full-res
-     * plane after the half-res record, from its size rounded up to 16 bytes). */
-    if (p->taa) {
-        float *comp = (float *)malloc(sizeof(float) * 4 * (size_t)W * H);
-        if (comp) {
-            memcpy(comp, out_colour, sizeof(float) * 4 * (size_t)W * H);
-            const size_t taa_off = (13 * np + 3) & ~(size_t)3;   /* 16-byte aligned */
-            const float *taa_in = hist_in ? hist_in + taa_off : NULL;
-            float *taa_out = hist_out + taa_off;
-            for (int y = 0; y < H; y++)
-                for (int x = 0; x < W; x++) {
-                    size_t pidx = (size_t)y * W + x;
-                    float mn[3], mx[3];
-                    for (int cc = 0; cc < 3; cc++) { mn[cc] = INFINITY; mx[cc] = -INFINITY; }
-                    for (int dy = -1; dy <= 1; dy++)
-                        for (int dx = -1; dx <= 1; dx++) {
-                            const float *v = comp + 4 * ((size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1));
-                            for (int cc = 0; cc < 3; cc++) {
-                                mn[cc] = v[cc] < mn[cc] ? v[cc] : mn[cc];
-                                mx[cc] = v[cc] > mx[cc] ? v[cc] : mx[cc];
-                            }
-                        }
-                    const float *c = comp + 4 * pidx;
-                    float *o = out_colour + 4 * pidx;
-                    int valid = 0;
-                    float hcol[4];
-                    if (have_hist && taa_in) {
-                        float fv[3], P[3], e[3];
-                        pixel_dir(cam, &q, x, y, W, H, fv);
-                        float z = gb_depth[pidx];
-                        int isdir = !(z < INFINITY);
-                        for (int a = 0; a < 3; a++) P[a] = isdir ? fv[a] : cam->pos[a] + z * fv[a];
-                        for (int a = 0; a < 3; a++) e[a] = isdir ? P[a] : P[a] - prev_cam->pos[a];
-                        float ex = (e[0] * prev_cam->right[0] + e[1] * prev_cam->right[1]) + e[2] * prev_cam->right[2];
-                        float ey = (e[0] * prev_cam->up[0] + e[1] * prev_cam->up[1]) + e[2] * prev_cam->up[2];
-                        float ez = (e[0] * prev_cam->fwd[0] + e[1] * prev_cam->fwd[1]) + e[2] * prev_cam->fwd[2];
-                        if (ez > 0.0f) {
-                            float pu = (ex / ez) / pq.tanx, pv = (ey / ez) / pq.tany;
-                            float px = ((pu + 1.0f) * 0.5f) * (float)W - 0.5f;
-                            float py = ((1.0f - pv) * 0.5f) * (float)H - 0.5f;
-                            if (px + 0.5f >= 0.0f && px + 0.5f < (float)W && py + 0.5f >= 0.0f && py + 0.5f < (float)H) {
-                                bilinear4(taa_in, W, H, px, py, hcol);
-                                valid = 1;
-                            }
-                        }
-                    }
-                    for (int cc = 0; cc < 3; cc++) {
-                        float v = c[cc];
-                        if (valid) {
-                            float h = hcol[cc];
-                            h = h > mn[cc] ? h : mn[cc];
-                            h = h < mx[cc] ? h : mx[cc];
-                            v = lerpf(c[cc], h, 0.9f);
-                        }
-                        o[cc] = v;
-                    }
-                    o[3] = 1.0f;
-                    for (int cc = 0; cc < 4; cc++) taa_out[4 * pidx + cc] = o[cc];
-                }
-            free(comp);
-        }
+     * ORC_TAA_FINAL: the composite resolved against the previous output. */
+    if (taa_final) {
+        memcpy(comp, out_colour, sizeof(float) * 4 * (size_t)W * H);
+        taa_resolve(comp, gb_depth, 1, W, H, cam, &q, prev_cam, &pq, hist_ok ? hist_ok + taa_off : NULL, out_colour,
+                    hist_out + taa_off, 0);
     }
 
     if (dbg) {
@@ -1455,7 +1508,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     free(rhit); free(rt); free(rcol); free(rpos);
     free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
     free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-    free(hblur); free(gblur); free(mips);
+    free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp);
     return 0;
 }
 
@@ -1485,6 +1538,7 @@ int orc_pixel_estimate(const orc_scene *s, const orc_bvh *b, const orc_camera *c
     if (!s || !cam || !lens || spp < 1 || nq < 0) return -1;
     int W = cam->width, H = cam->height, hw = W / 2, hh = H / 2;
     lensq q = lens_quantities(lens, W, H);
+    set_jitter(&q, cam);
     aperture ap = make_aperture(lens->blades, lens->blade_rot);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(g_threads)
     for (int64_t j = 0; j < nq; j++) {
@@ -1511,6 +1565,7 @@ int orc_lens_integral(const orc_scene *s, const orc_bvh *b, const orc_camera *ca
     if (!s || !cam || !lens || grid < 1 || nq < 0) return -1;
     int W = cam->width, H = cam->height, hw = W / 2, hh = H / 2;
     lensq q = lens_quantities(lens, W, H);
+    set_jitter(&q, cam);
     aperture ap = make_aperture(lens->blades, lens->blade_rot);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int64_t j = 0; j < nq; j++) {

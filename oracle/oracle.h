@@ -30,7 +30,14 @@ typedef struct {
     float pos[3], right[3], up[3], fwd[3]; /* orthonormal camera basis */
     int32_t width, height;                  /* full-resolution image size */
     uint32_t frame, seed;                   /* lens-sample counters */
+    float jitter[2];                        /* sub-pixel sample offset, full-res pixels right/down (3.1.2) */
 } orc_camera;
+
+/* TAA stages (3.4): of the final image, of the raster image before
+ * filtering, of the post-filter output. */
+#define ORC_TAA_FINAL 1
+#define ORC_TAA_RASTER 2
+#define ORC_TAA_POST 4
 
 typedef struct {
     float focal, fnum, focus, sensor;       /* f, N, d, w_s (scene units) */
@@ -46,7 +53,7 @@ typedef struct {
     float l_spec;
     int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all, 3 adaptive dilated by the neighbourhood max CoC */
     int32_t pp_polygon;                     /* 1: post-process gather taps on the aperture polygon (bladed lenses) */
-    int32_t taa;                            /* 1: final temporal anti-aliasing (history: full-res plane after the record) */
+    int32_t taa;                            /* TAA stages (3.4), bits ORC_TAA_*; history planes after the record */
 } orc_params;
 
 typedef struct {

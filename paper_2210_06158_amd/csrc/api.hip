@@ -82,7 +82,7 @@ SceneLayout scene_layout(int64_t n)
     return L;
 }
 
-dof::ScratchLayout frame_layout(int W, int H, int m, bool taa)
+dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
 {
     dof::ScratchLayout L{};
     const size_t np = (size_t)(W / 2) * (H / 2);
@@ -131,7 +131,9 @@ dof::ScratchLayout frame_layout(int W, int H, int m, bool taa)
     L.mips = take(16 * mt);
     L.tap = take(8 * np);
     L.recon = take(16 * np);
-    L.comp = taa ? take(16 * (size_t)W * H) : 0;   // composite colour before the final TAA
+    L.comp = (taa & DOF_TAA_FINAL) ? take(16 * (size_t)W * H) : 0;   // composite colour before the final TAA
+    L.rast = (taa & DOF_TAA_RASTER) ? take(16 * (size_t)W * H) : 0;  // raster colour after its TAA
+    L.pptaa = (taa & DOF_TAA_POST) ? take(16 * np) : 0;              // post-filter output after its TAA
     L.spill = take(kSpillBytes);
     L.total = off;
     return L;
@@ -160,7 +162,9 @@ LensDerived lens_derived(const dof_lens &l, int W, int H)
     return q;
 }
 
-void view_of(const dof_camera &c, const LensDerived &q, dof::ViewConst &v)
+// jitter: apply the camera's sub-pixel jitter (the current view only; a
+// previous view is projected into unjittered)
+void view_of(const dof_camera &c, const LensDerived &q, dof::ViewConst &v, bool jitter)
 {
     memcpy(v.pos, c.pos, sizeof(v.pos));
     memcpy(v.right, c.right, sizeof(v.right));
@@ -168,6 +172,8 @@ void view_of(const dof_camera &c, const LensDerived &q, dof::ViewConst &v)
     memcpy(v.fwd, c.fwd, sizeof(v.fwd));
     v.tanx = q.tanx;
     v.tany = q.tany;
+    v.ju = jitter ? (c.jitter[0] * 2.0f) / (float)c.width : 0.0f;
+    v.jv = jitter ? (c.jitter[1] * 2.0f) / (float)c.height : 0.0f;
 }
 
 // 81 taps: centre + rings k = 1..4 of 8k taps at radius k/4, angle 2 pi j / 8k
@@ -257,6 +263,7 @@ bool camera_ok(const dof_camera *c)
     if ((int64_t)c->width * c->height > (int64_t)1 << 30) return false;
     for (int a = 0; a < 3; ++a)
         if (!isfinite(c->pos[a]) || !isfinite(c->right[a]) || !isfinite(c->up[a]) || !isfinite(c->fwd[a])) return false;
+    if (!(fabsf(c->jitter[0]) <= 1.0f) || !(fabsf(c->jitter[1]) <= 1.0f)) return false;
     return true;
 }
 
@@ -268,7 +275,7 @@ dof_status params_check(const dof_params *p)
     if (p->tile != dof::kTile) return fail(DOF_E_UNSUPPORTED, "tile must be 16");
     if (p->mask_mode < 0 || p->mask_mode > 3) return fail(DOF_E_INVALID, "bad mask_mode");
     if (p->pp_polygon != 0 && p->pp_polygon != 1) return fail(DOF_E_INVALID, "bad pp_polygon");
-    if (p->taa != 0 && p->taa != 1) return fail(DOF_E_INVALID, "bad taa");
+    if (p->taa < 0 || p->taa > (DOF_TAA_FINAL | DOF_TAA_RASTER | DOF_TAA_POST)) return fail(DOF_E_INVALID, "bad taa");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
@@ -316,8 +323,8 @@ void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens 
     fc.depth_range = p.depth_range;
     fc.r_max = p.r_max;
     fc.l_spec = p.l_spec;
-    view_of(cam, q, fc.cur);
-    view_of(have_hist ? pcam : cam, have_hist ? lens_derived(plens, W, H) : q, fc.prev);
+    view_of(cam, q, fc.cur, true);
+    view_of(have_hist ? pcam : cam, have_hist ? lens_derived(plens, W, H) : q, fc.prev, false);
     make_aperture(lens, fc.ap);
     if (s) memcpy(&fc.shade, &s->shade, sizeof(fc.shade));
     int w = fc.hw, h = fc.hh;
@@ -359,7 +366,7 @@ dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *
                        size_t scratch_bytes, dof::ScratchLayout &L, dof::FrameConst &fc, bool &have_hist)
 {
     if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
-    if (!camera_ok(cam)) return fail(DOF_E_INVALID, "bad camera (size must be even and positive)");
+    if (!camera_ok(cam)) return fail(DOF_E_INVALID, "bad camera (even positive size, finite basis, |jitter| <= 1)");
     if (!lens_ok(lens)) return fail(DOF_E_INVALID, "bad lens");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
@@ -374,7 +381,7 @@ dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *
         return fail(DOF_E_INVALID, "bad output format");
     if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
-    L = frame_layout(cam->width, cam->height, p->m, p->taa != 0);
+    L = frame_layout(cam->width, cam->height, p->m, p->taa);
     if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
     have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
                 hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
@@ -406,7 +413,7 @@ struct dof_batch {
     uint32_t *spill;                   // traversal spill (first frame's scratch)
     int32_t trace_blocks;
     bool dilate;                       // params.mask_mode == DOF_MASK_DILATE
-    bool taa;                          // params.taa
+    int taa;                           // params.taa (DOF_TAA_* bits)
     std::vector<char> host;            // staging copy of the table
 };
 
@@ -561,7 +568,8 @@ dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes)
     if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
         return fail(DOF_E_INVALID, "width/height must be even and positive");
     const size_t record = ((size_t)(width / 2) * (height / 2) * 52 + 15) & ~(size_t)15;
-    *bytes = record + (size_t)width * height * 16;   // half-res record, then the full-res TAA colour
+    // the half-res record, then the TAA planes: final and raster (full res), post-filter (half res)
+    *bytes = record + (size_t)width * height * 32 + (size_t)(width / 2) * (height / 2) * 16;
     return DOF_OK;
 }
 
@@ -581,7 +589,7 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
         return fail(DOF_E_INVALID, "width/height must be even and positive");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
-    *bytes = frame_layout(width, height, p->m, p->taa != 0).total;
+    *bytes = frame_layout(width, height, p->m, p->taa).total;
     return DOF_OK;
 }
 
@@ -606,7 +614,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
         }
         ev = scene->ev;
     }
-    DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, out->mask, ev, s));
+    DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, s));
     const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
     DOF_HIP(dof::launch_frame_post(fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
@@ -666,7 +674,8 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
                 return fail(DOF_E_INVALID, "items %d and %d share a scratch, history output or colour buffer", k, i);
         char *scr = static_cast<char *>(it.scratch);
         J.P = dof::planes(J.fc, L, scr);
-        J.gb = it.gbuffer;
+        J.gb_in = it.gbuffer;
+        J.gb = dof::resolved_gbuffer(J.fc, J.P, it.gbuffer);
         J.hist_in = have_hist ? it.history.in : nullptr;
         J.hist_out = it.history.out;
         J.mask = it.out.mask;
@@ -694,7 +703,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
     for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
     b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
     b->dilate = p->mask_mode == DOF_MASK_DILATE;
-    b->taa = p->taa != 0;
+    b->taa = p->taa;
     b->n = n;
     return DOF_OK;
 }
@@ -707,7 +716,7 @@ dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
     dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->table);
     const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
     const dof::Rings &rings = ring_table();
-    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, s));
+    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, s));
     DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, s));
     DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
@@ -733,7 +742,7 @@ dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, cons
         return fail(DOF_E_INVALID, "bad arguments");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
-    const dof::ScratchLayout L = frame_layout(width, height, p->m, p->taa != 0);
+    const dof::ScratchLayout L = frame_layout(width, height, p->m, p->taa);
     char *s = static_cast<char *>(scratch);
     out->colr = s + L.colr;
     out->zn = s + L.zn;

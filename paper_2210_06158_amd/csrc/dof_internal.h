@@ -73,7 +73,17 @@ struct Rings {
 struct ViewConst {    // a camera with its lens-derived projection
     float pos[3], right[3], up[3], fwd[3];
     float tanx, tany;
+    float ju, jv;     // camera jitter as an offset of normalised image coordinates (0 for a previous view)
 };
+
+// View direction through the (jittered) centre of pixel (x, y) of a w x h grid.
+__device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h, float fv[3])
+{
+    float u = (((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) + v.ju) * v.tanx;
+    float vv = ((1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) - v.jv) * v.tany;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
+}
 
 struct FrameConst {
     int32_t W, H, hw, hh, tw, th, T, D;
@@ -95,7 +105,7 @@ struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
-    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp;
+    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
     size_t spill;
     size_t total;
     int64_t nchunks;
@@ -118,9 +128,15 @@ struct Planes {
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
     float2 *za;              // per half-res pixel: (depth, gather weight 1 / max(|r|, 1/2)^2)
     uint8_t *mask_raw;       // adaptive ray counts before dilation (mask mode DOF_MASK_DILATE)
-    float4 *comp;            // full-res composite colour before the final TAA (params.taa)
+    float4 *comp;            // full-res composite colour before the final TAA (DOF_TAA_FINAL)
+    float4 *rast;            // full-res raster colour after its TAA (DOF_TAA_RASTER)
+    float4 *pptaa;           // half-res post-filter output after its TAA (DOF_TAA_POST)
+    float4 *ppout;           // what the composite reads: pptaa with DOF_TAA_POST, else ppmed
 };
 Planes planes(const FrameConst &fc, const ScratchLayout &L, char *scratch);
+// The G-buffer as the stages after the raster TAA read it: with
+// DOF_TAA_RASTER its colour is the resolved plane (RGBA32F), else gb itself.
+dof_gbuffer resolved_gbuffer(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb);
 
 // What the traversal reads of a scene.
 struct SceneArgs {
@@ -153,7 +169,8 @@ enum : int {
 struct Job {
     FrameConst fc;
     Planes P;
-    dof_gbuffer gb;
+    dof_gbuffer gb;          // as the stages read it (colour: the resolved raster plane with DOF_TAA_RASTER)
+    dof_gbuffer gb_in;       // as the caller passed it
     const void *hist_in;     // nullptr when the frame has no usable history
     void *hist_out;
     uint8_t *mask;
@@ -213,7 +230,7 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
 // frame.hip
 // ev (nullable): DOF_NUM_STAGES + 1 events; pre records ev[0..7], post ev[8..13]
 hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
-                            const dof_gbuffer &gb, const void *hist_in, uint8_t *mask, hipEvent_t *ev,
+                            const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask, hipEvent_t *ev,
                             hipStream_t st);
 hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
@@ -222,10 +239,10 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
 // total blocks of grid g over the jobs
 hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                            const Rings &rings, bool dilate, hipStream_t st);
+                            const Rings &rings, bool dilate, int taa, hipStream_t st);
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
                               hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                             const Rings &rings, bool taa, hipStream_t st);
+                             const Rings &rings, int taa, hipStream_t st);
 
 }  // namespace dof

@@ -81,15 +81,6 @@ __device__ inline float median9(float p0, float p1, float p2, float p3, float p4
     return p4;
 }
 
-// View direction through the centre of pixel (x, y) of a w x h grid.
-__device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h, float fv[3])
-{
-    float u = ((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) * v.tanx;
-    float vv = (1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) * v.tany;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
-}
-
 // Half-res texel of the previous view that sees p (a direction when is_dir).
 __device__ inline int reproject(const ViewConst &pv, int hw, int hh, const float p[3], bool is_dir)
 {
@@ -164,9 +155,22 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.tap = reinterpret_cast<float2 *>(s + L.tap);
     p.za = reinterpret_cast<float2 *>(s + L.za);
     p.mask_raw = reinterpret_cast<uint8_t *>(s + L.mask_raw);
-    p.comp = fc.taa ? reinterpret_cast<float4 *>(s + L.comp) : nullptr;
+    p.comp = (fc.taa & DOF_TAA_FINAL) ? reinterpret_cast<float4 *>(s + L.comp) : nullptr;
+    p.rast = (fc.taa & DOF_TAA_RASTER) ? reinterpret_cast<float4 *>(s + L.rast) : nullptr;
+    p.pptaa = (fc.taa & DOF_TAA_POST) ? reinterpret_cast<float4 *>(s + L.pptaa) : nullptr;
+    p.ppout = (fc.taa & DOF_TAA_POST) ? p.pptaa : p.ppmed;
     p.recon = reinterpret_cast<float4 *>(s + L.recon);
     return p;
+}
+
+dof_gbuffer resolved_gbuffer(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb)
+{
+    dof_gbuffer g = gb;
+    if (fc.taa & DOF_TAA_RASTER) {
+        g.colour = P.rast;
+        g.colour_format = DOF_RGBA32F;
+    }
+    return g;
 }
 
 namespace {
@@ -1088,7 +1092,7 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
     const float z = gb.depth[p];
     const float c = coc_px(fc.cock, fc.d, z);
     const float hx = (float)x * 0.5f - 0.25f, hy = (float)y * 0.5f - 0.25f;
-    const float4 pp = bilinear4(P.ppmed, hw, hh, hx, hy);
+    const float4 pp = bilinear4(P.ppout, hw, hh, hx, hy);
     const float x0f = floorf(hx), y0f = floorf(hy);
     const float fx = hx - x0f, fy = hy - y0f;
     const int x0 = (int)x0f, y0 = (int)y0f;
@@ -1130,7 +1134,7 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
         float w = (t * t) * (3.0f - 2.0f * t);
         o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
     }
-    if (fc.taa) P.comp[p] = o;
+    if (fc.taa & DOF_TAA_FINAL) P.comp[p] = o;
     else st_rgba(out.colour, out.colour_format, p, o);
 }
 
@@ -1160,24 +1164,30 @@ __global__ void kb_stats(const Job *__restrict__ jobs, int njobs)
     o->tri_tests = 0;
 }
 
-// ---------------------------------------------------------------- A15
-// Final temporal anti-aliasing (3.4, after Karis 2014): the composite colour
-// blended with the previous output at the pixel's reprojected position (its
-// G-buffer point, or direction for the sky, in the previous camera;
-// bilinear), that history clamped per channel to the current 3 x 3 range,
-// history weight 0.9.  Writes the output and the next frame's TAA history.
+// ---------------------------------------------------------------- TAA
+// Temporal anti-aliasing stages (3.4, after Karis 2014).  One resolve: the
+// current image's colour at (x, y) of a w x h grid is blended with the
+// history image of the same grid, fetched bilinearly where the pixel's point
+// (view depth z through the jittered camera; its direction for the sky)
+// lands in the previous camera -- none behind it or off the grid -- that
+// history clamped per RGB channel to the current 3 x 3 range (clamp to
+// edge), history weight 0.9.  cur(x, y) reads the current image.  The 4th
+// channel is 1, or the current one's with keep_w.
 
-__device__ inline void b_taa(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb, const void *hist_in,
-                             void *hist_out, const dof_frame_out &out, const uint32_t bx, const uint32_t by)
+__device__ inline size_t taa_plane_floats(const FrameConst &fc, int which)   // 0 final, 1 raster, 2 post-filter
 {
-    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
-    const int W = fc.W, H = fc.H;
-    if (x >= W || y >= H) return;
-    const size_t p = (size_t)y * W + x;
+    const size_t base = ((size_t)fc.hw * fc.hh * 13 + 3) & ~(size_t)3;   // the record, rounded up to 16 bytes
+    return base + (size_t)which * 4 * (size_t)fc.W * fc.H;
+}
+
+template <class Cur>
+__device__ inline float4 taa_resolve(const FrameConst &fc, const Cur &cur, float z, int x, int y, int w, int h,
+                                     const float4 *hin, bool keep_w)
+{
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
-            const float4 v = P.comp[(size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            const float4 v = cur(clampi(x + dx, 0, w - 1), clampi(y + dy, 0, h - 1));
             const float vv[3] = {v.x, v.y, v.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -1185,14 +1195,12 @@ __device__ inline void b_taa(const FrameConst &fc, const Planes &P, const dof_gb
                 mx[c] = vv[c] > mx[c] ? vv[c] : mx[c];
             }
         }
-    const float4 cur = P.comp[p];
-    const size_t taa_off = ((size_t)fc.hw * fc.hh * 13 + 3) & ~(size_t)3;   // floats; 16-byte aligned
+    const float4 c0 = cur(x, y);
     bool valid = false;
     float4 hc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (fc.have_hist && hist_in) {
+    if (hin) {
         float fv[3], Pw[3], e[3];
-        pixel_dir(fc.cur, x, y, W, H, fv);
-        const float z = gb.depth[p];
+        pixel_dir(fc.cur, x, y, w, h, fv);
         const bool isdir = !(z < INFINITY);
 #pragma unroll
         for (int a = 0; a < 3; ++a) Pw[a] = isdir ? fv[a] : fc.cur.pos[a] + z * fv[a];
@@ -1203,44 +1211,117 @@ __device__ inline void b_taa(const FrameConst &fc, const Planes &P, const dof_gb
         const float ez = (e[0] * fc.prev.fwd[0] + e[1] * fc.prev.fwd[1]) + e[2] * fc.prev.fwd[2];
         if (ez > 0.0f) {
             const float pu = (ex / ez) / fc.prev.tanx, pv = (ey / ez) / fc.prev.tany;
-            const float px = ((pu + 1.0f) * 0.5f) * (float)W - 0.5f;
-            const float py = ((1.0f - pv) * 0.5f) * (float)H - 0.5f;
-            if (px + 0.5f >= 0.0f && px + 0.5f < (float)W && py + 0.5f >= 0.0f && py + 0.5f < (float)H) {
-                hc = bilinear4(reinterpret_cast<const float4 *>(static_cast<const float *>(hist_in) + taa_off), W, H,
-                               px, py);
+            const float px = ((pu + 1.0f) * 0.5f) * (float)w - 0.5f;
+            const float py = ((1.0f - pv) * 0.5f) * (float)h - 0.5f;
+            if (px + 0.5f >= 0.0f && px + 0.5f < (float)w && py + 0.5f >= 0.0f && py + 0.5f < (float)h) {
+                hc = bilinear4(hin, w, h, px, py);
                 valid = true;
             }
         }
     }
-    const float cv[3] = {cur.x, cur.y, cur.z}, hv[3] = {hc.x, hc.y, hc.z};
+    const float cv[3] = {c0.x, c0.y, c0.z}, hv[3] = {hc.x, hc.y, hc.z};
     float o[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float v = cv[c];
         if (valid) {
-            float h = hv[c];
-            h = h > mn[c] ? h : mn[c];
-            h = h < mx[c] ? h : mx[c];
-            v = lerp1(cv[c], h, 0.9f);
+            float t = hv[c];
+            t = t > mn[c] ? t : mn[c];
+            t = t < mx[c] ? t : mx[c];
+            v = lerp1(cv[c], t, 0.9f);
         }
         o[c] = v;
     }
-    const float4 r = make_float4(o[0], o[1], o[2], 1.0f);
-    st_rgba(out.colour, out.colour_format, p, r);
-    reinterpret_cast<float4 *>(static_cast<float *>(hist_out) + taa_off)[p] = r;
+    return make_float4(o[0], o[1], o[2], keep_w ? c0.w : 1.0f);
 }
 
-__global__ __launch_bounds__(kBX *kBY) void k_taa(FrameConst fc, Planes P, dof_gbuffer gb, const void *hist_in,
-                                                  void *hist_out, dof_frame_out out)
+__device__ inline const float4 *taa_history(const FrameConst &fc, const void *hist_in, int which)
 {
-    b_taa(fc, P, gb, hist_in, hist_out, out, blockIdx.x, blockIdx.y);
+    return (fc.have_hist && hist_in) ? reinterpret_cast<const float4 *>(static_cast<const float *>(hist_in) +
+                                                                        taa_plane_floats(fc, which))
+                                     : nullptr;
 }
 
-__global__ __launch_bounds__(kBX *kBY) void kb_taa(const Job *__restrict__ jobs, int njobs)
+// The raster image before filtering (DOF_TAA_RASTER): G-buffer colour in,
+// the resolved plane out (every later stage reads it).
+__device__ inline void b_taa_raster(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb, const void *hist_in,
+                                    void *hist_out, const uint32_t bx, const uint32_t by)
+{
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+    const int W = fc.W, H = fc.H;
+    if (x >= W || y >= H) return;
+    const size_t p = (size_t)y * W + x;
+    auto cur = [&](int xx, int yy) { return ld_rgba(gb.colour, gb.colour_format, (size_t)yy * W + xx); };
+    const float4 r = taa_resolve(fc, cur, gb.depth[p], x, y, W, H, taa_history(fc, hist_in, 1), false);
+    P.rast[p] = r;
+    reinterpret_cast<float4 *>(static_cast<float *>(hist_out) + taa_plane_floats(fc, 1))[p] = r;
+}
+
+// The half-res post-filter output (DOF_TAA_POST); the quad's nearest depth
+// locates each pixel.
+__device__ inline void b_taa_post(const FrameConst &fc, const Planes &P, const void *hist_in, void *hist_out,
+                                  const uint32_t bx, const uint32_t by)
+{
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+    const int hw = fc.hw, hh = fc.hh;
+    if (x >= hw || y >= hh) return;
+    const size_t i = (size_t)y * hw + x;
+    auto cur = [&](int xx, int yy) { return P.ppmed[(size_t)yy * hw + xx]; };
+    const float4 r = taa_resolve(fc, cur, P.zn[i].x, x, y, hw, hh, taa_history(fc, hist_in, 2), true);
+    P.pptaa[i] = r;
+    reinterpret_cast<float4 *>(static_cast<float *>(hist_out) + taa_plane_floats(fc, 2))[i] = r;
+}
+
+// The output after the composite (DOF_TAA_FINAL).
+__device__ inline void b_taa_final(const FrameConst &fc, const Planes &P, const dof_gbuffer &gb, const void *hist_in,
+                                   void *hist_out, const dof_frame_out &out, const uint32_t bx, const uint32_t by)
+{
+    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+    const int W = fc.W, H = fc.H;
+    if (x >= W || y >= H) return;
+    const size_t p = (size_t)y * W + x;
+    auto cur = [&](int xx, int yy) { return P.comp[(size_t)yy * W + xx]; };
+    const float4 r = taa_resolve(fc, cur, gb.depth[p], x, y, W, H, taa_history(fc, hist_in, 0), false);
+    st_rgba(out.colour, out.colour_format, p, r);
+    reinterpret_cast<float4 *>(static_cast<float *>(hist_out) + taa_plane_floats(fc, 0))[p] = r;
+}
+
+__global__ __launch_bounds__(kBX *kBY) void k_taa_raster(FrameConst fc, Planes P, dof_gbuffer gb, const void *hist_in,
+                                                         void *hist_out)
+{
+    b_taa_raster(fc, P, gb, hist_in, hist_out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void k_taa_post(FrameConst fc, Planes P, const void *hist_in, void *hist_out)
+{
+    b_taa_post(fc, P, hist_in, hist_out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void k_taa_final(FrameConst fc, Planes P, dof_gbuffer gb, const void *hist_in,
+                                                        void *hist_out, dof_frame_out out)
+{
+    b_taa_final(fc, P, gb, hist_in, hist_out, out, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_taa_raster(const Job *__restrict__ jobs, int njobs)
 {
     uint32_t bx, by;
     const Job &J = jobs[job_of_block(jobs, njobs, kGridFull, blockIdx.x, bx, by)];
-    b_taa(J.fc, J.P, J.gb, J.hist_in, J.hist_out, J.out, bx, by);
+    b_taa_raster(J.fc, J.P, J.gb_in, J.hist_in, J.hist_out, bx, by);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_taa_post(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
+    b_taa_post(J.fc, J.P, J.hist_in, J.hist_out, bx, by);
+}
+
+__global__ __launch_bounds__(kBX *kBY) void kb_taa_final(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridFull, blockIdx.x, bx, by)];
+    b_taa_final(J.fc, J.P, J.gb, J.hist_in, J.hist_out, J.out, bx, by);
 }
 
 __global__ void k_fill_zero(float *p, int64_t n)
@@ -1262,13 +1343,15 @@ inline dim3 grid2(int w, int h, int bx, int by) { return dim3((w + bx - 1) / bx,
     } while (0)
 
 hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
-                            const dof_gbuffer &gb, const void *hist_in, uint8_t *mask, hipEvent_t *ev,
+                            const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask, hipEvent_t *ev,
                             hipStream_t st)
 {
     Planes P = planes(fc, L, scratch);
     const int64_t np = (int64_t)fc.hw * fc.hh;
     DOF_REC(0);
-    k_reduce<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, gb, P);
+    if (fc.taa & DOF_TAA_RASTER)
+        k_taa_raster<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out);
+    k_reduce<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, resolved_gbuffer(fc, P, gb), P);
     DOF_REC(1);
     k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
     DOF_REC(2);
@@ -1277,6 +1360,8 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     k_gather<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
     DOF_REC(4);
     k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
+    if (fc.taa & DOF_TAA_POST)
+        k_taa_post<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, hist_in, hist_out);
     DOF_REC(5);
     if (fc.mask_mode == DOF_MASK_DILATE) {
         k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, P.mask_raw);
@@ -1307,8 +1392,9 @@ hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const Scr
     DOF_REC(11);
     k_recon<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
     DOF_REC(12);
-    k_composite<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, out);
-    if (fc.taa) k_taa<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);
+    k_composite<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, resolved_gbuffer(fc, P, gb), out);
+    if (fc.taa & DOF_TAA_FINAL)
+        k_taa_final<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);
     DOF_REC(13);
     if (out.stats) {
         // copy the frame counters to the caller's stats record
@@ -1326,13 +1412,15 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
 }
 
 hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                            bool dilate, hipStream_t st)
+                            bool dilate, int taa, hipStream_t st)
 {
+    if (taa & DOF_TAA_RASTER) kb_taa_raster<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
     kb_prefilter<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    if (taa & DOF_TAA_POST) kb_taa_post<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     if (dilate) kb_mask_dilate<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_compact_count<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);
@@ -1342,14 +1430,14 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
 }
 
 hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                             bool taa, hipStream_t st)
+                             int taa, hipStream_t st)
 {
     kb_resolve<<<nblk[kGridResolve], 64, 0, st>>>(jobs, njobs);
     kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
     kb_composite<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
-    if (taa) kb_taa<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    if (taa & DOF_TAA_FINAL) kb_taa_final<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }

@@ -196,14 +196,6 @@ __device__ inline void lens_point(const Aperture &ap, uint32_t seed, uint32_t fr
     ly = 0.0f;
 }
 
-__device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h, float fv[3])
-{
-    float u = ((((float)x + 0.5f) * 2.0f) / (float)w - 1.0f) * v.tanx;
-    float vv = (1.0f - (((float)y + 0.5f) * 2.0f) / (float)h) * v.tany;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
-}
-
 __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
 {
     if (fmt == DOF_RGBA32F) {

@@ -25,7 +25,8 @@ MASK_ADAPTIVE, MASK_FIXED, MASK_ALL = 0, 1, 2
 
 class DofCamera(C.Structure):
     _fields_ = [("pos", _f3), ("right", _f3), ("up", _f3), ("fwd", _f3),
-                ("width", C.c_int32), ("height", C.c_int32), ("frame", C.c_uint32), ("seed", C.c_uint32)]
+                ("width", C.c_int32), ("height", C.c_int32), ("frame", C.c_uint32), ("seed", C.c_uint32),
+                ("jitter", C.c_float * 2)]
 
 
 class DofLens(C.Structure):
@@ -140,7 +141,7 @@ def lib():
             if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
                             "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
-        if L.dof_abi_version() != 1:
+        if L.dof_abi_version() != 2:
             raise ImportError("libdof ABI version mismatch")
         _lib = L
     return _lib
@@ -157,7 +158,7 @@ def _stream():
 
 def camera_struct(cam) -> DofCamera:
     return DofCamera(_f3(*cam.pos), _f3(*cam.right), _f3(*cam.up), _f3(*cam.fwd), cam.width, cam.height,
-                     cam.frame & 0xFFFFFFFF, cam.seed & 0xFFFFFFFF)
+                     cam.frame & 0xFFFFFFFF, cam.seed & 0xFFFFFFFF, (C.c_float * 2)(*getattr(cam, "jitter", (0.0, 0.0))))
 
 
 def lens_struct(lens) -> DofLens:

@@ -67,6 +67,7 @@ class Camera:
     height: int
     frame: int = 0
     seed: int = 1
+    jitter: tuple = (0.0, 0.0)  # sub-pixel sample offset in full-res pixels (right, down)
 
 
 @dataclass
@@ -80,6 +81,21 @@ class Lens:
 
 
 MASK_ADAPTIVE, MASK_FIXED, MASK_ALL, MASK_DILATE = 0, 1, 2, 3
+TAA_FINAL, TAA_RASTER, TAA_POST = 1, 2, 4     # bits of Params.taa
+TAA_ALL = TAA_FINAL | TAA_RASTER | TAA_POST
+
+
+def jitter_sequence(n: int, seed: int) -> list:
+    """n pseudorandom sub-pixel camera offsets in [-0.5, 0.5)^2 (full-res
+    pixels), one per frame, from a seeded SplitMix64 stream; binary32 values."""
+    u = SplitMix64(seed).uniform(2 * n, -0.5, 0.5).astype(np.float32).reshape(n, 2)
+    return [(float(a), float(b)) for a, b in u]
+
+
+def jittered(cams: list, seed: int) -> list:
+    """The camera path with per-frame jitter from jitter_sequence."""
+    js = jitter_sequence(len(cams), seed)
+    return [dataclasses.replace(c, jitter=j) for c, j in zip(cams, js)]
 
 
 @dataclass
@@ -100,7 +116,7 @@ class Params:
     l_spec: float = 1.0         # luma above which a tap counts as a bright (specular) sample
     mask_mode: int = MASK_ADAPTIVE
     pp_polygon: int = 0         # 1: post-process gather kernel shaped like a bladed aperture
-    taa: int = 0                # 1: final temporal anti-aliasing (3.4)
+    taa: int = 0                # TAA stages (3.4), bits TAA_FINAL / TAA_RASTER / TAA_POST
 
 
 @dataclass

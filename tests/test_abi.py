@@ -39,7 +39,8 @@ def test_library_exports_every_declared_symbol(dof):
 
 def test_abi_version_and_defaults(dof):
     L = dof.lib()
-    assert L.dof_abi_version() == 1
+    assert L.dof_abi_version() == 2
+    assert C.sizeof(dof.DofCamera) == 16 * 4 + 2 * 4   # basis, size, counters, jitter
     p = dof.DofParams()
     L.dof_default_params(C.byref(p))
     assert p.struct_size == C.sizeof(dof.DofParams)
@@ -53,9 +54,15 @@ def test_abi_version_and_defaults(dof):
 def test_size_queries(dof):
     L = dof.lib()
     b = C.c_size_t()
-    # half-res record (52 B per half-res pixel, rounded up to 16 B), then the full-res TAA colour
-    assert L.dof_history_bytes(1920, 1080, C.byref(b)) == 0 and b.value == 960 * 540 * 52 + 1920 * 1080 * 16
-    assert L.dof_history_bytes(202, 118, C.byref(b)) == 0 and b.value == (101 * 59 * 52 + 15) // 16 * 16 + 202 * 118 * 16
+    # half-res record (52 B per half-res pixel, rounded up to 16 B), then the TAA planes: final and
+    # raster (16 B per full-res pixel each), post-filter (16 B per half-res pixel)
+    assert L.dof_history_bytes(1920, 1080, C.byref(b)) == 0
+    assert b.value == 960 * 540 * 52 + 1920 * 1080 * 32 + 960 * 540 * 16
+    assert L.dof_history_bytes(202, 118, C.byref(b)) == 0
+    assert b.value == (101 * 59 * 52 + 15) // 16 * 16 + 202 * 118 * 32 + 101 * 59 * 16
+    import oracle
+    for w, h in ((1920, 1080), (202, 118), (2, 2)):
+        assert L.dof_history_bytes(w, h, C.byref(b)) == 0 and b.value == 4 * oracle.history_floats(w, h)
     assert L.dof_history_bytes(1921, 1080, C.byref(b)) == dof.DOF_E_INVALID
     assert L.dof_scene_bytes(0, C.byref(b)) == dof.DOF_E_INVALID
     assert L.dof_scene_bytes(1000, C.byref(b)) == 0 and b.value > 1000 * 200
@@ -138,3 +145,26 @@ def test_mask_dilation_mode_limits(dof):
     p.r_max = 32.0
     p.mask_mode = 4
     assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID
+
+
+def test_taa_bits_and_their_scratch(dof):
+    """Each TAA stage takes its own scratch plane: the final stage 16 B per
+    full-res pixel (the composite before it), the raster stage 16 B per
+    full-res pixel, the post-filter stage 16 B per half-res pixel (each
+    rounded to the 256 B plane alignment); bits beyond the three are rejected."""
+    L = dof.lib()
+    b = C.c_size_t()
+    p = dof.DofParams()
+    L.dof_default_params(C.byref(p))
+    sizes = {}
+    for t in range(8):
+        p.taa = t
+        assert L.dof_frame_scratch_bytes(640, 360, C.byref(p), C.byref(b)) == 0
+        sizes[t] = b.value
+    full, half = 640 * 360 * 16, 320 * 180 * 16
+    assert sizes[1] - sizes[0] == full and sizes[2] - sizes[0] == full and sizes[4] - sizes[0] == half
+    assert sizes[7] - sizes[0] == 2 * full + half
+    p.taa = 8
+    assert L.dof_frame_scratch_bytes(640, 360, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID
+    p.taa = -1
+    assert L.dof_frame_scratch_bytes(640, 360, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID

@@ -224,6 +224,41 @@ def test_batch_with_taa_equals_single_frames(sess):
             it["cam"] = c0
 
 
+def test_batch_with_all_taa_stages_and_jitter_equals_single_frames(sess):
+    """taa = raster | post-filter | final on jittered cameras: frame 0 and
+    then frame 1 on that history, batched vs alone (the raster stage hands
+    the reduce and the composite its resolved colour per job)."""
+    torch, dof = sess["torch"], sess["dof"]
+    params = sess["params"]
+    saved = [it["cam"] for it in sess["items"]]
+    try:
+        sess["params"] = dataclasses.replace(params, taa=synth.TAA_ALL)
+        for k, it in enumerate(sess["items"]):
+            it["cam"] = synth.jittered([it["cam"]], seed=synth.BASE_SEED + 40 + k)[0]
+        alone0 = render_alone(sess)
+        frs, houts = make_frames(sess)
+        b = dof.Batch(4, sess["params"])
+        b.set(batch_items(sess, frs, houts))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone0[k], f"TAA all frame 0 item {k}")
+        hist = [torch.from_numpy(a["hist_out"]).cuda() for a in alone0]
+        prev = [it["cam"] for it in sess["items"]]
+        for k, it in enumerate(sess["items"]):
+            c1 = dataclasses.replace(synth.pan_camera(it["cam"], 0.02), frame=1)
+            it["cam"] = synth.jittered([c1], seed=synth.BASE_SEED + 50 + k)[0]
+        alone1 = render_alone(sess, hist_in=hist, prev=prev)
+        frs, houts = make_frames(sess)
+        b.set(batch_items(sess, frs, houts, hist_in=hist, prev=prev))
+        b.run()
+        for k in range(len(frs)):
+            same(grab(torch, frs[k], houts[k]), alone1[k], f"TAA all frame 1 item {k}")
+    finally:
+        sess["params"] = params
+        for it, c0 in zip(sess["items"], saved):
+            it["cam"] = c0
+
+
 def test_batch_item_matches_oracle(sess, orc):
     """The hexagonal-aperture item of a batch against the CPU oracle."""
     torch, dof = sess["torch"], sess["dof"]

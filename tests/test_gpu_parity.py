@@ -209,10 +209,12 @@ def test_watertight_on_gpu(env, orc):
 
 # ---------------------------------------------------------------- G-buffer
 
-def test_gbuffer_matches_oracle(env, orc):
+@pytest.mark.parametrize("jitter", [(0.0, 0.0), (0.37, -0.21)])
+def test_gbuffer_matches_oracle(env, orc, jitter):
     torch = env["torch"]
-    og = orc.gbuffer(env["osc"], env["cam"], env["lens"])
-    c, dpt, nrm = env["gs"].render_gbuffer(env["cam"], env["lens"])
+    cam = dataclasses.replace(env["cam"], jitter=jitter)
+    og = orc.gbuffer(env["osc"], cam, env["lens"])
+    c, dpt, nrm = env["gs"].render_gbuffer(cam, env["lens"])
     torch.cuda.synchronize()
     assert np.array_equal(dpt.cpu().numpy().view(np.uint32), og.depth.view(np.uint32))
     assert np.array_equal(c.cpu().numpy(), og.colour)
@@ -318,7 +320,7 @@ def test_taa_frame0_is_the_composite(taa0, frame0):
     assert np.array_equal(d["colour"][..., :3], d_plain["colour"][..., :3])
     W, H = o["colour"].shape[1], o["colour"].shape[0]
     from oracle import taa_offset
-    plane = d["hist_out"][taa_offset(W, H):].reshape(H, W, 4)
+    plane = d["hist_out"][taa_offset(W, H):taa_offset(W, H) + 4 * W * H].reshape(H, W, 4)
     assert np.array_equal(plane[..., :3], d["colour"][..., :3])
 
 
@@ -334,3 +336,23 @@ def test_taa_frame1_pan_parity(env, orc, taa0):
     plain = orc.render_frame(env["osc"], cam1, env["lens"], dataclasses.replace(p, taa=0), gb1,
                              hist_in=o0["hist_out"], prev_cam=env["cam"], prev_lens=env["lens"])
     assert np.abs(plain["colour"][..., :3] - o["colour"][..., :3]).max() > 1e-3   # the history took part
+
+
+def test_taa_all_stages_on_jittered_frames_parity(env, orc):
+    """Raster, post-filter and final TAA on a jittered camera path (seeded
+    sub-pixel offsets per frame): frame 0, then frame 1 after a pan on the
+    oracle's history of frame 0.  Every stage, the history record with its
+    three TAA planes and the colour are compared as for plain frames."""
+    lens = env["lens"]
+    p = dataclasses.replace(env["params"], taa=synth.TAA_ALL)
+    cams = synth.jittered([env["cam"], synth.pan_camera(env["cam"], 0.02)], seed=synth.BASE_SEED + 31)
+    assert all(c.jitter != (0.0, 0.0) for c in cams)
+    gb0 = orc.gbuffer(env["osc"], cams[0], lens)
+    o0, d0 = run_pair(env, orc, cams[0], lens, p, gb0)
+    compare_frame(o0, d0, "TAA all, jittered frame 0")
+    gb1 = orc.gbuffer(env["osc"], cams[1], lens)
+    o1, d1 = run_pair(env, orc, cams[1], lens, p, gb1, hist_in=o0["hist_out"], prev_cam=cams[0], prev_lens=lens)
+    compare_frame(o1, d1, "TAA all, jittered frame 1")
+    plain = orc.render_frame(env["osc"], cams[1], lens, env["params"], gb1, hist_in=o0["hist_out"],
+                             prev_cam=cams[0], prev_lens=lens)
+    assert not np.array_equal(plain["colr"], o1["colr"])                  # the raster TAA took part

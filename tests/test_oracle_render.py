@@ -457,7 +457,20 @@ def test_mask_dilation_is_identity_without_blur(orc, small):
 
 def _taa_plane(hist, W, H):
     import oracle
-    return hist[oracle.taa_offset(W, H):].reshape(H, W, 4)
+    o = oracle.taa_offset(W, H)
+    return hist[o:o + 4 * W * H].reshape(H, W, 4)
+
+
+def _raster_plane(hist, W, H):
+    import oracle
+    o = oracle.raster_taa_offset(W, H)
+    return hist[o:o + 4 * W * H].reshape(H, W, 4)
+
+
+def _post_plane(hist, W, H):
+    import oracle
+    o = oracle.post_taa_offset(W, H)
+    return hist[o:o + W * H].reshape(H // 2, W // 2, 4)
 
 
 def test_taa_without_history_is_the_composite(orc, small):
@@ -502,20 +515,18 @@ def test_taa_onto_its_own_composite_is_identity(orc, small):
     assert not np.array_equal(f0["colour"], comp1["colour"])      # the composite itself changed between frames
 
 
-def test_taa_weight_window_and_reprojection_closed_form(orc):
-    """Pinhole lens, so the composite is the G-buffer colour: a seeded random
-    field over a plane at depth z0 facing the camera.  The camera pans right
-    by exactly s pixel pitches at that depth, so pixel x of the new frame sees
-    what pixel x + s saw.  The history plane holds the 3 x 3 minimum of the
-    new colour field (scipy, clamp to edge) moved s pixels right.  Expected
-    result: c + 0.9 (min - c) where x + s is on screen, c elsewhere."""
-    from scipy.ndimage import minimum_filter
-    W, H, s, z0 = 64, 48, 3, 10.0
+
+
+def _pan_setup(orc, s, grid_w, z0=10.0, W=64, H=48, seed=9):
+    """Pinhole lens (the composite is the G-buffer colour), a seeded random
+    colour field over a plane at depth z0 facing the camera, and a second
+    camera panned right by exactly s pixel pitches of a grid_w-wide grid at
+    that depth."""
     lens = synth.Lens(fnum=math.inf)
     tanx = (lens.sensor * (lens.focus - lens.focal)) / (2.0 * lens.focal * lens.focus)   # half field of view
     cam0 = synth.look_camera((0, 0, 0), 0, 0, W, H)
-    cam1 = synth.pan_camera(cam0, s * z0 * 2.0 * tanx / W)
-    rng = np.random.default_rng(9)
+    cam1 = synth.pan_camera(cam0, s * z0 * 2.0 * tanx / grid_w)
+    rng = np.random.default_rng(seed)
     col = np.ones((H, W, 4), np.float32)
     col[..., :3] = rng.uniform(0.0, 1.0, (H, W, 3))
     nrm = np.zeros((H, W, 4), np.float32)
@@ -523,17 +534,128 @@ def test_taa_weight_window_and_reprojection_closed_form(orc):
     gb = orc.GBuffer(col, np.full((H, W), z0, np.float32), nrm)
     sc = orc.OracleScene(plane_scene(z0))
     sc.build_bvh()
-    p = synth.Params(taa=1)
+    return lens, cam0, cam1, col, gb, sc
+
+
+def _closed_form(cur, s):
+    """(3 x 3 minimum, c + 0.9 (min - c) where x + s is on the grid, c
+    elsewhere), RGB; scipy's filter with clamp to edge."""
+    from scipy.ndimage import minimum_filter
+    mn = minimum_filter(cur[..., :3], size=(3, 3, 1), mode="nearest")
+    w = cur.shape[1]
+    exp = cur[..., :3].copy()
+    exp[:, :w - s] = cur[:, :w - s, :3] + 0.9 * (mn[:, :w - s] - cur[:, :w - s, :3])
+    return mn, exp
+
+
+@pytest.mark.parametrize("stage", [synth.TAA_FINAL, synth.TAA_RASTER])
+def test_taa_weight_window_and_reprojection_closed_form(orc, stage):
+    """Pixel x of the panned frame sees what pixel x + s saw; the stage's
+    history plane holds the 3 x 3 minimum of the new colour field moved s
+    pixels right.  Expected: c + 0.9 (min - c) where x + s is on screen, c
+    elsewhere.  With a pinhole lens the composite is the resolved raster
+    colour, so for the raster stage this also shows in the output."""
+    W, H, s = 64, 48, 3
+    lens, cam0, cam1, col, gb, sc = _pan_setup(orc, s, W)
+    p = synth.Params(taa=stage)
     f0 = orc.render_frame(sc, cam0, lens, p, gb)
     plain = orc.render_frame(sc, cam1, lens, dataclasses.replace(p, taa=0), gb, hist_in=f0["hist_out"],
                              prev_cam=cam0, prev_lens=lens)
     assert np.array_equal(plain["colour"][..., :3], col[..., :3])          # pinhole: composite = G-buffer
-    mn = minimum_filter(col[..., :3], size=(3, 3, 1), mode="nearest")
+    mn, exp = _closed_form(col, s)
+    plane_of = _taa_plane if stage == synth.TAA_FINAL else _raster_plane
     hist = f0["hist_out"].copy()
-    plane = _taa_plane(hist, W, H)
+    plane = plane_of(hist, W, H)
     plane[:, s:, :3] = mn[:, :W - s]
     plane[:, :s, :3] = 7.0                                                  # never fetched
     t1 = orc.render_frame(sc, cam1, lens, p, gb, hist_in=hist, prev_cam=cam0, prev_lens=lens)
-    exp = col[..., :3].copy()
-    exp[:, :W - s] = col[:, :W - s, :3] + 0.9 * (mn[:, :W - s] - col[:, :W - s, :3])
     np.testing.assert_allclose(t1["colour"][..., :3], exp, rtol=0, atol=2e-4)
+    out_plane = plane_of(t1["hist_out"], W, H)
+    np.testing.assert_allclose(out_plane[..., :3], exp, rtol=0, atol=2e-4)
+    assert np.all(out_plane[..., 3] == 1.0)
+
+
+def test_post_filter_taa_closed_form(orc):
+    """The same construction on the half-res grid of the post-filter output:
+    a pan of s half-res pitches, and the post-filter plane of the history set
+    to the 3 x 3 minimum of this frame's post-filter output moved s pixels
+    right.  The resolved plane is c + 0.9 (min - c) where x + s is on the
+    grid, c elsewhere, and keeps the output's 4th channel."""
+    W, H, s = 64, 48, 2
+    lens, cam0, cam1, col, gb, sc = _pan_setup(orc, s, W // 2)
+    p = synth.Params(taa=synth.TAA_POST)
+    f0 = orc.render_frame(sc, cam0, lens, p, gb)
+    probe = orc.render_frame(sc, cam1, lens, p, gb, hist_in=f0["hist_out"], prev_cam=cam0, prev_lens=lens)
+    ppm = probe["ppmed"]
+    assert ppm.shape == (H // 2, W // 2, 4) and np.ptp(ppm[..., :3]) > 0.1
+    mn, exp = _closed_form(ppm, s)
+    hist = f0["hist_out"].copy()
+    plane = _post_plane(hist, W, H)
+    plane[:, s:, :3] = mn[:, :W // 2 - s]
+    plane[:, :s, :3] = 7.0
+    t1 = orc.render_frame(sc, cam1, lens, p, gb, hist_in=hist, prev_cam=cam0, prev_lens=lens)
+    assert np.array_equal(t1["ppmed"], ppm)                                # the median is upstream of the TAA
+    out_plane = _post_plane(t1["hist_out"], W, H)
+    np.testing.assert_allclose(out_plane[..., :3], exp, rtol=0, atol=2e-4)
+    assert np.array_equal(out_plane[..., 3], ppm[..., 3])
+
+
+@pytest.mark.parametrize("stage", [synth.TAA_RASTER, synth.TAA_POST, synth.TAA_ALL])
+def test_taa_stages_without_history_pass_through(orc, small, stage):
+    """Frame 0 (no history): every TAA stage passes its image through, so the
+    frame equals the frame without TAA, and each enabled stage's history
+    plane holds its input (raster: the G-buffer colour; post-filter: the
+    median output)."""
+    cam, lens, gb, p = small["cam"], small["lens"], small["gb"], small["params"]
+    W, H = cam.width, cam.height
+    off = orc.render_frame(small["sc"], cam, lens, p, gb)
+    on = orc.render_frame(small["sc"], cam, lens, dataclasses.replace(p, taa=stage), gb)
+    for k in ("colour", "mask", "ppmed", "recon", "colr"):
+        assert np.array_equal(on[k], off[k]), k
+    if stage & synth.TAA_RASTER:
+        assert np.array_equal(_raster_plane(on["hist_out"], W, H)[..., :3], gb.colour[..., :3])
+    if stage & synth.TAA_POST:
+        assert np.array_equal(_post_plane(on["hist_out"], W, H), off["ppmed"])
+
+
+def test_later_stages_read_the_resolved_images(orc, small):
+    """With history, the reduce averages the resolved raster colour (2 x 2
+    box of the raster plane, not of the G-buffer), and the composite samples
+    the resolved post-filter image: a dark post-filter history darkens the
+    output while the median output stays the same."""
+    cam, lens, gb, p = small["cam"], small["lens"], small["gb"], small["params"]
+    W, H = cam.width, cam.height
+    f0 = orc.render_frame(small["sc"], cam, lens, dataclasses.replace(p, taa=synth.TAA_ALL), gb)
+    cam1 = synth.pan_camera(cam, 0.02)
+    gb1 = orc.gbuffer(small["sc"], cam1, lens)
+    t = orc.render_frame(small["sc"], cam1, lens, dataclasses.replace(p, taa=synth.TAA_RASTER), gb1,
+                         hist_in=f0["hist_out"], prev_cam=cam, prev_lens=lens)
+    r = _raster_plane(t["hist_out"], W, H)
+    assert not np.array_equal(r[..., :3], gb1.colour[..., :3])
+    box = ((r[0::2, 0::2, :3] + r[0::2, 1::2, :3]) + (r[1::2, 0::2, :3] + r[1::2, 1::2, :3])) * np.float32(0.25)
+    assert np.array_equal(t["colr"][..., :3], box)
+    hist = f0["hist_out"].copy()
+    _post_plane(hist, W, H)[..., :3] = 0.0
+    base = orc.render_frame(small["sc"], cam1, lens, dataclasses.replace(p, taa=synth.TAA_POST), gb1,
+                            hist_in=f0["hist_out"], prev_cam=cam, prev_lens=lens)
+    dark = orc.render_frame(small["sc"], cam1, lens, dataclasses.replace(p, taa=synth.TAA_POST), gb1,
+                            hist_in=hist, prev_cam=cam, prev_lens=lens)
+    assert np.array_equal(dark["ppmed"], base["ppmed"])
+    darker = dark["colour"][..., :3].sum(-1) < base["colour"][..., :3].sum(-1) - 1e-3
+    assert darker.mean() > 0.002 and (dark["colour"][..., :3] <= base["colour"][..., :3] + 1e-6).all()
+
+
+def test_jitter_moves_the_samples_by_the_stated_offset(orc, small):
+    """A jitter of a quarter pixel right and down at W x H puts each sample
+    where pixel (2x + 1, 2y + 1) of the unjittered 2W x 2H grid has its
+    centre, so the G-buffers agree there (up to rounding at silhouettes)."""
+    cam, lens, sc = small["cam"], small["lens"], small["sc"]
+    j = orc.gbuffer(sc, dataclasses.replace(cam, jitter=(0.25, 0.25)), lens)
+    fine = orc.gbuffer(sc, dataclasses.replace(cam, width=2 * cam.width, height=2 * cam.height), lens)
+    ref = fine.depth[1::2, 1::2]
+    hit = np.isfinite(ref) & np.isfinite(j.depth)
+    sky = ~np.isfinite(ref) & ~np.isfinite(j.depth)
+    close = (hit & np.isclose(j.depth, ref, rtol=1e-4)) | sky
+    assert close.mean() > 0.995 and hit.mean() > 0.3
+    plain = orc.gbuffer(sc, cam, lens)
+    assert (~np.isclose(plain.depth, ref, rtol=1e-6) & hit).mean() > 0.05   # the jitter did move the samples
