@@ -1044,6 +1044,10 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
     const int w0 = fc.mw[L0], h0 = fc.mh[L0], w1 = fc.mw[L1], h1 = fc.mh[L1];
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, sh = 0.0f;
     int na = 0;
+    // Every tap's fetches are issued (their indices are clamped, so always in
+    // bounds) and only valid taps are summed, in tap order: the loads of
+    // several taps can then be in flight at once.
+#pragma unroll 3
     for (int k = 0; k < kRingTaps; ++k) {
         float dist = Rr * rings.frac[k];
         float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
@@ -1052,15 +1056,15 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
         // a tap counts when its pixel is ray traced and its CoC radius
         // reaches the tap (invalid pixels carry -inf)
         const float2 tj = P.tap[j];
-        if (!(tj.x * 0.25f >= dist)) continue;
+        const bool ok = tj.x * 0.25f >= dist;
         float4 s0 = bilinear4(mip0, w0, h0, (sx + 0.5f) * sc0 - 0.5f, (sy + 0.5f) * sc0 - 0.5f);
         float4 s1 = bilinear4(mip1, w1, h1, (sx + 0.5f) * sc1 - 0.5f, (sy + 0.5f) * sc1 - 0.5f);
-        a0 = a0 + lerp1(s0.x, s1.x, fl);
-        a1 = a1 + lerp1(s0.y, s1.y, fl);
-        a2 = a2 + lerp1(s0.z, s1.z, fl);
-        a3 = a3 + lerp1(s0.w, s1.w, fl);
-        sh = sh + tj.y;
-        ++na;
+        a0 = ok ? a0 + lerp1(s0.x, s1.x, fl) : a0;
+        a1 = ok ? a1 + lerp1(s0.y, s1.y, fl) : a1;
+        a2 = ok ? a2 + lerp1(s0.z, s1.z, fl) : a2;
+        a3 = ok ? a3 + lerp1(s0.w, s1.w, fl) : a3;
+        sh = ok ? sh + tj.y : sh;
+        na += ok ? 1 : 0;
     }
     const float4 med = P.rtmed[i];
     float nb0 = a3 > 0.0f ? a0 / a3 : med.x, nb1 = a3 > 0.0f ? a1 / a3 : med.y, nb2 = a3 > 0.0f ? a2 / a3 : med.z;
