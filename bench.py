@@ -87,8 +87,10 @@ def stage_bytes(stage, W, H, P, R):
         "median": h * 16 + h * 16,
         # depth+normal in, history validity + variance (8 B) at the reprojected texel; prev index + count out
         "mask": h * 16 + h * 8 + h * 4 + h * 1,
-        "compact": 2 * h + P * 8 + R * 4,
-        "trace": R * (12 + 40),                     # queue/base/pixel of each ray in; hit, t, colour, position out
+        # counts in, queue and ray offsets per masked px and the ray -> pixel map out; then the ray
+        # generation: pixel, queue entry and offset of each ray in, its 48-byte record out
+        "compact": 2 * h + P * 8 + R * 4 + R * (12 + 48),
+        "trace": R * (48 + 40),                     # ray record in; hit, t, colour, position out
         # hit, colour, position of each ray; queue entry, ray offset, count in and 4 planes out per masked px
         "resolve": R * 36 + P * (4 + 4 + 1 + 64),
         # count, prev index, resolve planes, history A B C in; T0 T1 and history A B C out

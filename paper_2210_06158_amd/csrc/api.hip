@@ -113,6 +113,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
     L.queue = take(4 * np);
     L.ray_base = take(4 * np);
     L.ray_pix = take(4 * nr);
+    L.ray_rec = take(48 * nr);   // three float4 planes of nr
     L.ray_hit = take(4 * nr);
     L.ray_t = take(4 * nr);
     L.ray_col = take(16 * nr);
@@ -413,6 +414,7 @@ struct dof_batch {
     uint32_t *spill;                   // traversal spill (first frame's scratch)
     int32_t trace_blocks;
     bool dilate;                       // params.mask_mode == DOF_MASK_DILATE
+    int64_t max_rays;                  // sum over the items of half-res pixels x m
     int taa;                           // params.taa (DOF_TAA_* bits)
     std::vector<char> host;            // staging copy of the table
 };
@@ -656,6 +658,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
     dof::Job *jobs = reinterpret_cast<dof::Job *>(b->host.data() + jobs_at);
     head->njobs = n;
     uint32_t tot[dof::kNumGrids] = {};
+    int64_t max_rays = 0;
     for (int i = 0; i < n; ++i) {
         const dof_batch_item &it = items[i];
         dof::ScratchLayout L;
@@ -684,6 +687,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         J.grings = gather_rings(it.lens, *p);
         const dof::FrameConst &fc = J.fc;
         const int64_t np = (int64_t)fc.hw * fc.hh;
+        max_rays += np * fc.m;
         auto cdiv = [](int64_t a, int64_t c) { return (uint32_t)((a + c - 1) / c); };
         const uint32_t bxs[dof::kNumGrids] = {(uint32_t)fc.tw, cdiv(fc.tw, 16), cdiv(fc.hw, 64), (uint32_t)L.nchunks,
                                               cdiv(np, 64), cdiv(fc.hw, 8), cdiv(fc.W, 64)};
@@ -704,6 +708,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
     b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
     b->dilate = p->mask_mode == DOF_MASK_DILATE;
     b->taa = p->taa;
+    b->max_rays = max_rays;
     b->n = n;
     return DOF_OK;
 }
@@ -717,7 +722,7 @@ dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
     const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
     const dof::Rings &rings = ring_table();
     DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, s));
-    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, s));
+    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, b->max_rays, s));
     DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
     return DOF_OK;

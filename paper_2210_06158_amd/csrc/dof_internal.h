@@ -104,7 +104,7 @@ struct FrameConst {
 struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
-    size_t queue, ray_base, ray_pix, ray_hit, ray_t, ray_col, ray_pos;
+    size_t queue, ray_base, ray_pix, ray_rec, ray_hit, ray_t, ray_col, ray_pos;
     size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
     size_t spill;
     size_t total;
@@ -123,6 +123,7 @@ struct Planes {
     int32_t *ray_hit;
     float *ray_t;
     float4 *ray_col, *ray_pos;
+    float4 *rec0, *rec1, *rec2;   // ray records: (o, d.x), (d.y, d.z, sx, sy), (sz, 1/d) per ray
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
@@ -222,6 +223,8 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 int trace_blocks_per_cu(bool batch);   // resident blocks of the lens-ray traversal per CU
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
+// the ray records of every thin-lens ray of the frame (after the compaction)
+hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
                           void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,
@@ -240,7 +243,8 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // total blocks of grid g over the jobs
 hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
                             const Rings &rings, bool dilate, int taa, hipStream_t st);
-hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
+// max_rays: the sum over the jobs of half-res pixels x m (sizes the ray generation grid)
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks, int64_t max_rays,
                               hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
                              const Rings &rings, int taa, hipStream_t st);

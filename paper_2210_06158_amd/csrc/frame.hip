@@ -145,6 +145,10 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.ray_t = reinterpret_cast<float *>(s + L.ray_t);
     p.ray_col = reinterpret_cast<float4 *>(s + L.ray_col);
     p.ray_pos = reinterpret_cast<float4 *>(s + L.ray_pos);
+    const size_t nr = np * (size_t)fc.m;
+    p.rec0 = reinterpret_cast<float4 *>(s + L.ray_rec);
+    p.rec1 = p.rec0 + nr;
+    p.rec2 = p.rec1 + nr;
     float4 *res = reinterpret_cast<float4 *>(s + L.resolve);
     p.R0 = res; p.R1 = res + np; p.R2 = res + 2 * np; p.R3 = res + 3 * np;
     float4 *tmp = reinterpret_cast<float4 *>(s + L.temporal);
@@ -1377,6 +1381,8 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     k_compact_count<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
     k_compact_scan<<<1, 1024, 0, st>>>(L.nchunks, P, nullptr);
     k_compact_scatter<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
+    const hipError_t e = launch_raygen(fc, L, scratch, st);
+    if (e != hipSuccess) return e;
     DOF_REC(7);
     return hipGetLastError();
 }

@@ -45,16 +45,24 @@ struct WRay {
     float ix, iy, iz;   // slab reciprocals (zero components replaced by 1e-20)
 };
 
+// The watertight test's axes: kz the largest direction component, kx and ky
+// the next two in cyclic order, swapped when d[kz] < 0 (keeps the winding).
+__device__ inline void wray_axes(const float d[3], int &kx, int &ky, int &kz)
+{
+    float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    kx = kz + 1 == 3 ? 0 : kz + 1;
+    ky = kx + 1 == 3 ? 0 : kx + 1;
+    if (pick3(d[0], d[1], d[2], kz) < 0.0f) { int t = kx; kx = ky; ky = t; }
+}
+
 __device__ inline WRay make_wray(const float o[3], const float d[3])
 {
     WRay r;
     r.o0 = o[0]; r.o1 = o[1]; r.o2 = o[2];
-    float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
-    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-    int kx = kz + 1 == 3 ? 0 : kz + 1;
-    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    int kx, ky, kz;
+    wray_axes(d, kx, ky, kz);
     float dz = pick3(d[0], d[1], d[2], kz);
-    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
     r.kx = kx; r.ky = ky; r.kz = kz;
     r.sx = pick3(d[0], d[1], d[2], kx) / dz;
     r.sy = pick3(d[0], d[1], d[2], ky) / dz;
@@ -256,15 +264,39 @@ __device__ inline void lens_finish(const SceneArgs &S, const FrameConst &fc, int
     }
 }
 
+// Ray records (three float4 planes): (o, d.x), (d.y, d.z, sx, sy),
+// (sz, 1/d.x, 1/d.y, 1/d.z), written by the ray generation kernel so that a
+// traversal lane takes a new ray with three independent loads.
+__device__ inline void put_ray(float4 *rec0, float4 *rec1, float4 *rec2, uint32_t r, const float o[3],
+                               const float d[3])
+{
+    const WRay w = make_wray(o, d);
+    rec0[r] = make_float4(o[0], o[1], o[2], d[0]);
+    rec1[r] = make_float4(d[1], d[2], w.sx, w.sy);
+    rec2[r] = make_float4(w.sz, w.ix, w.iy, w.iz);
+}
+
+__device__ inline void get_ray(const float4 *rec0, const float4 *rec1, const float4 *rec2, uint32_t r, float o[3],
+                               float d[3], WRay &w)
+{
+    const float4 a = rec0[r], b = rec1[r], c = rec2[r];
+    o[0] = a.x; o[1] = a.y; o[2] = a.z;
+    d[0] = a.w; d[1] = b.x; d[2] = b.y;
+    w.o0 = a.x; w.o1 = a.y; w.o2 = a.z;
+    wray_axes(d, w.kx, w.ky, w.kz);
+    w.sx = b.z; w.sy = b.w; w.sz = c.x;
+    w.ix = c.y; w.iy = c.z; w.iz = c.w;
+}
+
 struct LensRays {
     static constexpr bool kPerLaneScene = false;
     FrameConst fc;
-    const uint32_t *queue, *ray_base, *ray_pix;
+    const float4 *rec0, *rec1, *rec2;
     int32_t *ray_hit;
     float *ray_t;
     float4 *ray_col, *ray_pos;
 
-    __device__ void setup(uint32_t r, float o[3], float d[3]) const { lens_ray(fc, queue, ray_base, ray_pix, r, o, d); }
+    __device__ void start(uint32_t r, float o[3], float d[3], WRay &w) const { get_ray(rec0, rec1, rec2, r, o, d, w); }
 
     __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
     {
@@ -308,10 +340,10 @@ struct BatchRays {
 
     __device__ SceneArgs scene(int j) const { return jobs[j].scene; }
 
-    __device__ void setup(uint32_t r, int j, float o[3], float d[3]) const
+    __device__ void start(uint32_t r, int j, float o[3], float d[3], WRay &w) const
     {
         const Job &J = jobs[j];
-        lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, r - offsets()[j], o, d);
+        get_ray(J.P.rec0, J.P.rec1, J.P.rec2, r - offsets()[j], o, d, w);
     }
 
     __device__ void finish(const SceneArgs &S, uint32_t r, int j, const float o[3], const float d[3],
@@ -331,6 +363,12 @@ struct PinholeRays {
     float *depth;
     void *normal;
     int nfmt;
+
+    __device__ void start(uint32_t p, float o[3], float d[3], WRay &w) const
+    {
+        setup(p, o, d);
+        w = make_wray(o, d);
+    }
 
     __device__ void setup(uint32_t p, float o[3], float d[3]) const
     {
@@ -368,13 +406,14 @@ struct RawRays {
     int32_t *hit;
     float *t;
 
-    __device__ void setup(uint32_t i, float o[3], float d[3]) const
+    __device__ void start(uint32_t i, float o[3], float d[3], WRay &w) const
     {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             o[a] = org[3 * (size_t)i + a];
             d[a] = dir[3 * (size_t)i + a];
         }
+        w = make_wray(o, d);
     }
 
     __device__ void finish(const SceneArgs &, uint32_t i, const float *, const float *, const Hit &h) const
@@ -384,11 +423,59 @@ struct RawRays {
     }
 };
 
+// ---------------------------------------------------------------- ray generation
+
+constexpr int kGenTB = 256;
+constexpr int kGenMaxBlocks = 2048;
+
+// Every thin-lens ray of a frame (the count is the compaction's ray total).
+__global__ __launch_bounds__(kGenTB) void k_raygen(FrameConst fc, const uint32_t *queue, const uint32_t *ray_base,
+                                                   const uint32_t *ray_pix, const uint32_t *count, float4 *rec0,
+                                                   float4 *rec1, float4 *rec2)
+{
+    const uint32_t N = *count;
+    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) {
+        float o[3], d[3];
+        lens_ray(fc, queue, ray_base, ray_pix, r, o, d);
+        put_ray(rec0, rec1, rec2, r, o, d);
+    }
+}
+
+// Every thin-lens ray of a batch: ray r belongs to the last job whose first
+// ray is at or before r (LDS copy of the jobs' first rays).
+__global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs, const BatchHead *head, int njobs)
+{
+    __shared__ uint32_t off[kMaxBatch + 1];
+    for (int j = threadIdx.x; j <= njobs; j += kGenTB) off[j] = head->ray_off[j];
+    __syncthreads();
+    const uint32_t N = head->rays;
+    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const Job &J = jobs[lo];
+        const uint32_t k = r - off[lo];
+        float o[3], d[3];
+        lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, k, o, d);
+        put_ray(J.P.rec0, J.P.rec1, J.P.rec2, k, o, d);
+    }
+}
+
+int gen_blocks(int64_t max_rays)
+{
+    const int64_t b = (max_rays + kGenTB - 1) / kGenTB;
+    return b < 1 ? 1 : (b > kGenMaxBlocks ? kGenMaxBlocks : (int)b);
+}
+
 // ---------------------------------------------------------------- persistent traversal
 
 constexpr int kSpillChunk = 8;    // stack entries moved per spill or refill (divides kStackLds and kStackMax)
 static_assert(kStackLds % kSpillChunk == 0 && kStackMax % kSpillChunk == 0, "spill chunks must tile the stack");
 constexpr int kRefill = 16;   // refill when at least this many lanes are idle
+constexpr uint32_t kGrab = 64;   // rays a wave takes from the shared work counter at a time
 constexpr int kLeafBatch = 32;   // run triangle tests when at least this many lanes have one pending
 
 template <class Src>
@@ -404,6 +491,11 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     uint32_t *stk = lds_stack + tid;
 
     bool active = false, exhausted = false;
+    // rays [pool, pool_end) taken by this wave and not yet handed to a lane
+    // (wave-uniform); a new batch of kGrab comes from the shared counter only
+    // when the pool is empty, so refills rarely touch the atomic
+    uint32_t pool = 0, pool_end = 0;
+    bool drained = false;   // the shared counter has passed N (wave-uniform)
     uint32_t item = 0, node = 0;
     int sp = 0, ns = 0;   // entries in LDS, entries spilled to global memory
     float o[3], d[3];
@@ -422,20 +514,29 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
         const uint64_t idle = __ballot(!active && !exhausted);
         const uint64_t live = __ballot(active);
         if (idle != 0ull && (__popcll(idle) >= kRefill || live == 0ull)) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(work, (uint32_t)__popcll(idle));
-            base = __shfl(base, 0);
+            if (pool == pool_end && !drained) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(work, kGrab);
+                base = __shfl(base, 0);
+                if (base >= N) {
+                    drained = true;
+                } else {
+                    pool = base;
+                    pool_end = N - base < kGrab ? N : base + kGrab;
+                }
+            }
+            const uint32_t avail = pool_end - pool;
+            const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!active && !exhausted) {
-                item = base + (uint32_t)__popcll(idle & lt);
-                if (item < N) {
+                item = pool + rank;
+                if (rank < avail) {
                     if constexpr (Src::kPerLaneScene) {
                         job = src.job_of(item);
                         Sl = src.scene(job);
-                        src.setup(item, job, o, d);
+                        src.start(item, job, o, d, wr);
                     } else {
-                        src.setup(item, o, d);
+                        src.start(item, o, d, wr);
                     }
-                    wr = make_wray(o, d);
                     h = Hit{INFINITY, ~0u, 0u};
                     node = 0;
                     sp = 0;
@@ -449,10 +550,12 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     } else {
                         trav = true;
                     }
-                } else {
+                } else if (drained) {
                     exhausted = true;
                 }
             }
+            const uint32_t nidle = (uint32_t)__popcll(idle);
+            pool += nidle < avail ? nidle : avail;
         }
         if (__ballot(active) == 0ull) {
             if (__ballot(!exhausted) == 0ull) break;
@@ -575,9 +678,10 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
 {
     LensRays src;
     src.fc = fc;
-    src.queue = reinterpret_cast<const uint32_t *>(scratch + L.queue);
-    src.ray_base = reinterpret_cast<const uint32_t *>(scratch + L.ray_base);
-    src.ray_pix = reinterpret_cast<const uint32_t *>(scratch + L.ray_pix);
+    const Planes P = planes(fc, L, scratch);
+    src.rec0 = P.rec0;
+    src.rec1 = P.rec1;
+    src.rec2 = P.rec2;
     src.ray_hit = reinterpret_cast<int32_t *>(scratch + L.ray_hit);
     src.ray_t = reinterpret_cast<float *>(scratch + L.ray_t);
     src.ray_col = reinterpret_cast<float4 *>(scratch + L.ray_col);
@@ -586,6 +690,15 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(
         scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork, reinterpret_cast<uint32_t *>(scratch + L.spill),
         reinterpret_cast<unsigned long long *>(cnt + kCntVisits));
+    return hipGetLastError();
+}
+
+hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st)
+{
+    const Planes P = planes(fc, L, scratch);
+    const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
+    k_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix, P.counters + kCntRays, P.rec0,
+                                                       P.rec1, P.rec2);
     return hipGetLastError();
 }
 
@@ -618,9 +731,10 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
 }
 
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
-                              hipStream_t st)
+                              int64_t max_rays, hipStream_t st)
 {
     kb_ray_offsets<<<1, 64, 0, st>>>(head, jobs, njobs);
+    kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
     k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
                                                                 &head->visits);
