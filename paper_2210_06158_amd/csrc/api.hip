@@ -114,6 +114,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
     L.ray_base = take(4 * np);
     L.ray_pix = take(4 * nr);
     L.ray_rec = take(48 * nr);   // three float4 planes of nr
+    L.ray_lt = take(8 * nr);
     L.ray_hit = take(4 * nr);
     L.ray_t = take(4 * nr);
     L.ray_col = take(16 * nr);
@@ -619,7 +620,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
     DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, s));
     const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
-    DOF_HIP(dof::launch_frame_post(fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
+    DOF_HIP(dof::launch_frame_post(scene->dev, fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
     scene->timed_frame = ev != nullptr;
     return DOF_OK;
 }

@@ -104,7 +104,7 @@ struct FrameConst {
 struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
-    size_t queue, ray_base, ray_pix, ray_rec, ray_hit, ray_t, ray_col, ray_pos;
+    size_t queue, ray_base, ray_pix, ray_rec, ray_lt, ray_hit, ray_t, ray_col, ray_pos;
     size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
     size_t spill;
     size_t total;
@@ -124,6 +124,7 @@ struct Planes {
     float *ray_t;
     float4 *ray_col, *ray_pos;
     float4 *rec0, *rec1, *rec2;   // ray records: (o, d.x), (d.y, d.z, sx, sy), (sz, 1/d) per ray
+    uint2 *ray_lt;                // traversal result per ray: (leaf of the hit or ~0, t bits)
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
@@ -225,6 +226,8 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
                         int blocks, hipStream_t st);
 // the ray records of every thin-lens ray of the frame (after the compaction)
 hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
+// hit record, distance, shaded colour and position of every ray (after the traversal)
+hipError_t launch_shade(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
                           void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,
@@ -235,7 +238,7 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
 hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                             const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask, hipEvent_t *ev,
                             hipStream_t st);
-hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+hipError_t launch_frame_post(const SceneDev &s, const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
                              const dof_frame_out &out, hipEvent_t *ev, hipStream_t st);
 hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);

@@ -149,6 +149,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.rec0 = reinterpret_cast<float4 *>(s + L.ray_rec);
     p.rec1 = p.rec0 + nr;
     p.rec2 = p.rec1 + nr;
+    p.ray_lt = reinterpret_cast<uint2 *>(s + L.ray_lt);
     float4 *res = reinterpret_cast<float4 *>(s + L.resolve);
     p.R0 = res; p.R1 = res + np; p.R2 = res + 2 * np; p.R3 = res + 3 * np;
     float4 *tmp = reinterpret_cast<float4 *>(s + L.temporal);
@@ -1387,13 +1388,17 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     return hipGetLastError();
 }
 
-hipError_t launch_frame_post(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
+hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
                              const dof_frame_out &out, hipEvent_t *ev, hipStream_t st)
 {
     Planes P = planes(fc, L, scratch);
     const int64_t np = (int64_t)fc.hw * fc.hh;
     DOF_REC(8);
+    {
+        const hipError_t e = launch_shade(sd, fc, L, scratch, st);
+        if (e != hipSuccess) return e;
+    }
     k_resolve<<<(unsigned)((np + 63) / 64), 64, 0, st>>>(fc, P, mask);
     DOF_REC(9);
     k_temporal<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, mask, hist_in, hist_out);

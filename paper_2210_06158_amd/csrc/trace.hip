@@ -288,19 +288,38 @@ __device__ inline void get_ray(const float4 *rec0, const float4 *rec1, const flo
     w.ix = c.y; w.iy = c.z; w.iz = c.w;
 }
 
+// The traversal's result of a lens ray: leaf of the closest hit (~0u: none)
+// and distance, one 8-byte store; the shading kernel expands it.
+__device__ inline void put_lt(uint2 *lt, uint32_t r, const Hit &h)
+{
+    lt[r] = make_uint2(h.id == ~0u ? ~0u : h.leaf, __float_as_uint(h.t));
+}
+
+// Hit record, distance, shaded colour and position of lens ray r from its
+// traversal result and ray record.
+__device__ inline void shade_ray(const SceneArgs &S, const FrameConst &fc, const Planes &P, uint32_t r)
+{
+    const uint2 lt = P.ray_lt[r];
+    const float4 a = P.rec0[r], b = P.rec1[r];
+    const float o[3] = {a.x, a.y, a.z}, d[3] = {a.w, b.x, b.y};
+    Hit h;
+    h.t = __uint_as_float(lt.y);
+    h.leaf = lt.x;
+    h.id = lt.x == ~0u ? ~0u : __float_as_uint(S.tris[3 * (size_t)lt.x].w);
+    lens_finish(S, fc, P.ray_hit, P.ray_t, P.ray_col, P.ray_pos, r, o, d, h);
+}
+
 struct LensRays {
     static constexpr bool kPerLaneScene = false;
     FrameConst fc;
     const float4 *rec0, *rec1, *rec2;
-    int32_t *ray_hit;
-    float *ray_t;
-    float4 *ray_col, *ray_pos;
+    uint2 *ray_lt;
 
     __device__ void start(uint32_t r, float o[3], float d[3], WRay &w) const { get_ray(rec0, rec1, rec2, r, o, d, w); }
 
-    __device__ void finish(const SceneArgs &S, uint32_t r, const float o[3], const float d[3], const Hit &h) const
+    __device__ void finish(const SceneArgs &, uint32_t r, const float *, const float *, const Hit &h) const
     {
-        lens_finish(S, fc, ray_hit, ray_t, ray_col, ray_pos, r, o, d, h);
+        put_lt(ray_lt, r, h);
     }
 };
 
@@ -346,11 +365,9 @@ struct BatchRays {
         get_ray(J.P.rec0, J.P.rec1, J.P.rec2, r - offsets()[j], o, d, w);
     }
 
-    __device__ void finish(const SceneArgs &S, uint32_t r, int j, const float o[3], const float d[3],
-                           const Hit &h) const
+    __device__ void finish(const SceneArgs &, uint32_t r, int j, const float *, const float *, const Hit &h) const
     {
-        const Job &J = jobs[j];
-        lens_finish(S, J.fc, J.P.ray_hit, J.P.ray_t, J.P.ray_col, J.P.ray_pos, r - offsets()[j], o, d, h);
+        put_lt(jobs[j].P.ray_lt, r - offsets()[j], h);
     }
 };
 
@@ -461,6 +478,31 @@ __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs
         float o[3], d[3];
         lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, k, o, d);
         put_ray(J.P.rec0, J.P.rec1, J.P.rec2, k, o, d);
+    }
+}
+
+// Shading of every lens ray of a frame / of a batch, after the traversal.
+__global__ __launch_bounds__(kGenTB) void k_shade(SceneArgs S, FrameConst fc, Planes P, const uint32_t *count)
+{
+    const uint32_t N = *count;
+    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) shade_ray(S, fc, P, r);
+}
+
+__global__ __launch_bounds__(kGenTB) void kb_shade(const Job *__restrict__ jobs, const BatchHead *head, int njobs)
+{
+    __shared__ uint32_t off[kMaxBatch + 1];
+    for (int j = threadIdx.x; j <= njobs; j += kGenTB) off[j] = head->ray_off[j];
+    __syncthreads();
+    const uint32_t N = head->rays;
+    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const Job &J = jobs[lo];
+        shade_ray(J.scene, J.fc, J.P, r - off[lo]);
     }
 }
 
@@ -682,10 +724,7 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     src.rec0 = P.rec0;
     src.rec1 = P.rec1;
     src.rec2 = P.rec2;
-    src.ray_hit = reinterpret_cast<int32_t *>(scratch + L.ray_hit);
-    src.ray_t = reinterpret_cast<float *>(scratch + L.ray_t);
-    src.ray_col = reinterpret_cast<float4 *>(scratch + L.ray_col);
-    src.ray_pos = reinterpret_cast<float4 *>(scratch + L.ray_pos);
+    src.ray_lt = P.ray_lt;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
     k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(
         scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork, reinterpret_cast<uint32_t *>(scratch + L.spill),
@@ -699,6 +738,14 @@ hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scr
     const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
     k_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix, P.counters + kCntRays, P.rec0,
                                                        P.rec1, P.rec2);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st)
+{
+    const Planes P = planes(fc, L, scratch);
+    const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
+    k_shade<<<gen_blocks(max_rays), kGenTB, 0, st>>>(scene_args(s), fc, P, P.counters + kCntRays);
     return hipGetLastError();
 }
 
@@ -738,6 +785,7 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint3
     BatchRays src{jobs, head, njobs};
     k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
                                                                 &head->visits);
+    kb_shade<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     return hipGetLastError();
 }
 
