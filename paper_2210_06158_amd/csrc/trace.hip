@@ -9,9 +9,14 @@
 //
 // Scheduling: each lane owns one ray at a time and advances it one BVH node
 // per loop iteration; when 16 or more lanes of a wave are idle (or all are),
-// the wave takes that many new ray indices from a device counter with one
-// atomic and hands them to its idle lanes, so long rays do not hold a whole
-// wave hostage (persistent threads with dynamic fetch).
+// the wave hands them the next rays of its pool, a run of 64 ray indices
+// taken from a device counter with one atomic whenever the pool is empty, so
+// long rays do not hold a whole wave hostage (persistent threads with dynamic
+// fetch) and the shared counter sees one atomic per 64 rays.  Thin-lens rays
+// come precomputed (a generation kernel writes a 48-byte record per ray) and
+// leave as an 8-byte (leaf, t) record that a shading kernel expands, so a
+// refill is three loads and a finishing ray one store: no arithmetic or
+// scene loads that the whole wave would wait on.
 //
 // Closest hit: binary radix tree whose nodes carry both children's boxes
 // (one 64-byte fetch tests two boxes), near child first, far child pushed on
