@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--stage-frames", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--trace-blocks", type=int, default=0, help="persistent traversal blocks (0 = library default)")
+    ap.add_argument("--trace-blocks", type=int, default=-1,
+                    help="persistent traversal blocks (0 = library default, -1 = autotuned per workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
@@ -125,6 +126,33 @@ def measured_traffic():
     fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
     write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
     return int(fetch + write)
+
+
+def autotune_grid(gs, cams, lenses, params, gbs, log, label, frames=6):
+    """The persistent traversal grid for a workload (setup, outside every
+    timed region): each candidate renders the same first `frames` frames of
+    the path, history chained from a reset; the fastest by HIP events wins
+    (returns (blocks, {candidate: ms}); 0 is the library default)."""
+    from paper_2210_06158_amd import dof, tune
+
+    W, H = cams[0].width, cams[0].height
+    hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
+    by_grid = {}
+
+    def trial(tb):
+        fr = by_grid.get(tb)
+        if fr is None:
+            fr = by_grid[tb] = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=tb)
+        for k in range(frames):
+            prev = cams[k - 1] if k > 0 else None
+            fr.render(gs, cams[k], lenses[k], gbs[k], hist[(k + 1) % 2] if prev is not None else None, hist[k % 2],
+                      prev_cam=prev, prev_lens=lenses[k - 1] if k > 0 else None)
+
+    best, ms = tune.tune(trial, tune.candidate_blocks(), reps=2)
+    del by_grid
+    log(f"{label}: traversal grid {best if best else 'library default'} ({ms})")
+    return best, {"trace_blocks": best if best else "library default",
+                  "candidates_ms": {str(k if k else "default"): round(v, 3) for k, v in ms.items()}}
 
 
 def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_blocks, log):
@@ -257,8 +285,10 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     gbuffer_ms = e0.elapsed_time(e1) / nfr
-    r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, args.trace_blocks,
-                 log)
+    tb, grid = args.trace_blocks, None
+    if tb < 0:
+        tb, grid = autotune_grid(gs, cams, [lens] * nfr, params, gbs, log, "1080p")
+    r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, tb, log)
     K, total_ms, frame_ms = r["K"], r["total_ms"], r["frame_ms"]
     rays, masked, visits, tests = r["rays"], r["masked"], r["visits"], r["tests"]
     fps = K / (total_ms / 1e3)
@@ -294,7 +324,7 @@ def main():
         m_sweep = {}
         for mm in (1, 8, 30, 50):
             pm = dataclasses.replace(params, m=mm)
-            rm = run_path(gs, cams, [lens] * nfr, pm, gbs, 20, 5, 20, args.trace_blocks, log)
+            rm = run_path(gs, cams, [lens] * nfr, pm, gbs, 20, 5, 20, tb, log)
             m_sweep[str(mm)] = {"frame_ms": round(rm["total_ms"] / rm["K"], 4),
                                 "trace_ms": round(rm["stage_ms"]["trace"], 4),
                                 "rays_per_frame": round(rm["rays"] / rm["K"], 1)}
@@ -302,14 +332,14 @@ def main():
         m_sweep["trace_ms_per_unit_m"] = round((t50 - t1) / 49.0, 5)
         # the mask grown by the neighbourhood max CoC (remedy proposed in 5.3)
         pd = dataclasses.replace(params, mask_mode=synth.MASK_DILATE)
-        rd = run_path(gs, cams, [lens] * nfr, pd, gbs, 20, 5, 20, args.trace_blocks, log)
+        rd = run_path(gs, cams, [lens] * nfr, pd, gbs, 20, 5, 20, tb, log)
         m_sweep["mask_dilated_m8"] = {"frame_ms": round(rd["total_ms"] / rd["K"], 4),
                                       "trace_ms": round(rd["stage_ms"]["trace"], 4),
                                       "rays_per_frame": round(rd["rays"] / rd["K"], 1)}
         # with the final TAA (3.4) after the composite; its kernel is timed
         # inside the composite stage
         pt = dataclasses.replace(params, taa=1)
-        rt = run_path(gs, cams, [lens] * nfr, pt, gbs, 20, 5, 20, args.trace_blocks, log)
+        rt = run_path(gs, cams, [lens] * nfr, pt, gbs, 20, 5, 20, tb, log)
         m_sweep["final_taa_m8"] = {"frame_ms": round(rt["total_ms"] / rt["K"], 4),
                                    "composite_and_taa_ms": round(rt["stage_ms"]["composite"], 4),
                                    "composite_ms_without": round(stage_ms["composite"], 4)}
@@ -318,7 +348,7 @@ def main():
         jc = synth.jittered(cams, seed=synth.BASE_SEED + 77)
         jg = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in jc]
         pa = dataclasses.replace(params, taa=synth.TAA_ALL)
-        ra = run_path(gs, jc, [lens] * nfr, pa, jg, 20, 5, 20, args.trace_blocks, log)
+        ra = run_path(gs, jc, [lens] * nfr, pa, jg, 20, 5, 20, tb, log)
         m_sweep["all_taa_jittered_m8"] = {"frame_ms": round(ra["total_ms"] / ra["K"], 4),
                                           "reduce_ms": round(ra["stage_ms"]["reduce"], 4),
                                           "median_ms": round(ra["stage_ms"]["median"], 4),
@@ -370,6 +400,7 @@ def main():
         "gbuffer_ms_per_frame": round(gbuffer_ms, 4),
         "frames_per_s_with_gbuffer": round(K / ((total_ms + K * gbuffer_ms) / 1e3), 2),
         "m_sweep": m_sweep,
+        "traversal_grid": grid,
         "bvh_build_ms": round(bvh_ms, 3),
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
@@ -396,7 +427,10 @@ def uhd_leg(args, log):
     gs.build_bvh()
     gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams, lenses)]
     torch.cuda.synchronize()
-    r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), args.trace_blocks, log)
+    tb, grid = args.trace_blocks, None
+    if tb < 0:
+        tb, grid = autotune_grid(gs, cams, lenses, params, gbs, log, "4k")
+    r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), tb, log)
     out = {
         "workload": "3840x2160, box city (130k boxes) behind a chain-link fence of 200k wire quads at depth 1-2, "
                     "1,960,002 triangles, 6-blade aperture N=2, focus pulled 3 -> 40 over 60 frames, m=16",
@@ -414,7 +448,8 @@ def uhd_leg(args, log):
     # the same path with the post-process gather shaped like the hexagonal
     # aperture (the polygonal-bokeh extension named in section 2)
     import dataclasses
-    rp = run_path(gs, cams, lenses, dataclasses.replace(params, pp_polygon=1), gbs, 20, 5, 20, args.trace_blocks, log)
+    rp = run_path(gs, cams, lenses, dataclasses.replace(params, pp_polygon=1), gbs, 20, 5, 20, tb, log)
+    out["traversal_grid"] = grid
     out["hexagonal_pp_gather"] = {"frames_per_s": round(rp["K"] / (rp["total_ms"] / 1e3), 2),
                                   "gather_ms": round(rp["stage_ms"]["gather"], 4)}
     log(f"4k: {out['frames_per_s']} frames/s")
