@@ -208,7 +208,12 @@ __host__ __device__ inline float fmin_cs(float a, float b) { return b < a ? b : 
 __host__ __device__ inline float fmax_cs(float a, float b) { return b > a ? b : a; }
 __host__ __device__ inline float sat(float x) { return x > 0.0f ? (x < 1.0f ? x : 1.0f) : 0.0f; }
 __host__ __device__ inline float lerp1(float a, float b, float t) { return a + (b - a) * t; }
-__host__ __device__ inline int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+// x clamped to [lo, hi] (lo <= hi); as max(lo, min(x, hi)) it is one med3 on the GPU
+__host__ __device__ inline int clampi(int x, int lo, int hi)
+{
+    const int m = x < hi ? x : hi;
+    return m > lo ? m : lo;
+}
 __host__ __device__ inline float clampf(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
 __device__ inline float luma709(float r, float g, float b) { return (0.2126f * r + 0.7152f * g) + 0.0722f * b; }
 

@@ -47,8 +47,10 @@ __device__ inline float4 bilinear4(const float4 *img, int w, int h, float x, flo
     int x1 = clampi(x0 + 1, 0, w - 1), y1 = clampi(y0 + 1, 0, h - 1);
     x0 = clampi(x0, 0, w - 1);
     y0 = clampi(y0, 0, h - 1);
-    float4 a = img[(size_t)y0 * w + x0], b = img[(size_t)y0 * w + x1];
-    float4 c = img[(size_t)y1 * w + x0], d = img[(size_t)y1 * w + x1];
+    // 32-bit texel indices: a frame has at most 2^30 pixels
+    const float4 *r0 = img + (uint32_t)(y0 * w), *r1 = img + (uint32_t)(y1 * w);
+    float4 a = r0[x0], b = r0[x1];
+    float4 c = r1[x0], d = r1[x1];
     float4 top, bot, o;
     top.x = a.x + (b.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
     top.y = a.y + (b.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
