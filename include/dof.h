@@ -240,10 +240,11 @@ dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes);
 dof_status dof_history_reset(void *hist, int32_t width, int32_t height, void *stream);
 dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_params *p, size_t *bytes);
 
-/* The pass (sections 3.1-3.3) for one frame: CoC and half-res reduce, tile
- * max, prefilter, 81-tap gather, median, ray mask, compaction, thin-lens
- * traversal, resolve, temporal accumulation, variance blur, median + mips,
- * reconstruction, composite.  Enqueued on `stream`, no host sync. */
+/* The pass (sections 3.1-3.4) for one frame: CoC and half-res reduce, tile
+ * max, prefilter, 81-tap gather, median, ray mask, compaction and thin-lens
+ * ray generation, traversal, shading of the hits and resolve, temporal
+ * accumulation, variance blur, median + mips, reconstruction, composite, and
+ * the TAA stages params.taa selects.  Enqueued on `stream`, no host sync. */
 dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
                             const dof_gbuffer *gb, const dof_history_io *hist, const dof_params *p,
                             const dof_frame_out *out, void *scratch, size_t scratch_bytes,
@@ -252,9 +253,10 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
 /* Stages timed when params.timing is set, in launch order. */
 #define DOF_NUM_STAGES 13
 /* Per-stage device time (ms) of the scene's most recent frame rendered with
- * params.timing != 0: reduce, dilate, prefilter, gather, median, mask,
- * compaction, trace, resolve, temporal, blur+median+mips, reconstruction,
- * composite.  Waits for that frame's last event (host sync on it only).
+ * params.timing != 0: reduce (with the raster TAA), dilate, prefilter,
+ * gather, median (with the post-filter TAA), mask, compaction (with the ray
+ * generation), trace (the traversal alone), resolve (with the shading),
+ * temporal, blur+median+mips, reconstruction, composite (with the final TAA).  Waits for that frame's last event (host sync on it only).
  * Writes min(cap, DOF_NUM_STAGES) values to ms (host) and the count to *n. */
 dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n);
 
