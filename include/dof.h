@@ -238,6 +238,9 @@ dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, con
 
 dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes);
 dof_status dof_history_reset(void *hist, int32_t width, int32_t height, void *stream);
+/* Scratch of one frame.  A frame may ask for at most 2^31 rays (half-res
+ * pixels x params.m): ray indices and counters are 32-bit; beyond it this
+ * query, dof_render_frame and dof_batch_set return DOF_E_UNSUPPORTED. */
 dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_params *p, size_t *bytes);
 
 /* The pass (sections 3.1-3.4) for one frame: CoC and half-res reduce, tile

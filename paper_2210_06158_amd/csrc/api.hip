@@ -269,6 +269,11 @@ bool camera_ok(const dof_camera *c)
     return true;
 }
 
+// Ray indices, counts and the traversal's work counter are 32-bit: a frame
+// may ask for at most 2^31 rays (half-res pixels x m).
+constexpr int64_t kMaxFrameRays = (int64_t)1 << 31;
+bool rays_fit(int width, int height, int m) { return (int64_t)(width / 2) * (height / 2) * m <= kMaxFrameRays; }
+
 dof_status params_check(const dof_params *p)
 {
     if (!p) return fail(DOF_E_INVALID, "params is NULL");
@@ -383,6 +388,8 @@ dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *
         return fail(DOF_E_INVALID, "bad output format");
     if (!scratch) return fail(DOF_E_INVALID, "scratch is NULL");
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    if (!rays_fit(cam->width, cam->height, p->m))
+        return fail(DOF_E_UNSUPPORTED, "half-res pixels x m exceeds 2^31 rays per frame");
     L = frame_layout(cam->width, cam->height, p->m, p->taa);
     if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
     have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
@@ -592,6 +599,7 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
         return fail(DOF_E_INVALID, "width/height must be even and positive");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
+    if (!rays_fit(width, height, p->m)) return fail(DOF_E_UNSUPPORTED, "half-res pixels x m exceeds 2^31 rays per frame");
     *bytes = frame_layout(width, height, p->m, p->taa).total;
     return DOF_OK;
 }
@@ -689,6 +697,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         const dof::FrameConst &fc = J.fc;
         const int64_t np = (int64_t)fc.hw * fc.hh;
         max_rays += np * fc.m;
+        if (max_rays > kMaxFrameRays) return fail(DOF_E_UNSUPPORTED, "batch exceeds 2^31 rays");
         auto cdiv = [](int64_t a, int64_t c) { return (uint32_t)((a + c - 1) / c); };
         const uint32_t bxs[dof::kNumGrids] = {(uint32_t)fc.tw, cdiv(fc.tw, 16), cdiv(fc.hw, 64), (uint32_t)L.nchunks,
                                               cdiv(np, 64), cdiv(fc.hw, 8), cdiv(fc.W, 64)};

@@ -168,3 +168,18 @@ def test_taa_bits_and_their_scratch(dof):
     assert L.dof_frame_scratch_bytes(640, 360, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID
     p.taa = -1
     assert L.dof_frame_scratch_bytes(640, 360, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID
+
+
+def test_frame_ray_count_limit(dof):
+    """Ray indices and counters are 32-bit: half-res pixels x m above 2^31
+    rays per frame is refused by the size query (and by the frame call)."""
+    L = dof.lib()
+    b = C.c_size_t()
+    p = dof.DofParams()
+    L.dof_default_params(C.byref(p))
+    p.m = 255
+    # 16384 x 8192: 2^25 half-res pixels x 255 > 2^31
+    assert L.dof_frame_scratch_bytes(16384, 8192, C.byref(p), C.byref(b)) == dof.DOF_E_UNSUPPORTED
+    assert b"2^31" in L.dof_last_error()
+    p.m = 64   # exactly 2^31
+    assert L.dof_frame_scratch_bytes(16384, 8192, C.byref(p), C.byref(b)) == 0
