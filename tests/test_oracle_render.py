@@ -659,3 +659,129 @@ def test_jitter_moves_the_samples_by_the_stated_offset(orc, small):
     assert close.mean() > 0.995 and hit.mean() > 0.3
     plain = orc.gbuffer(sc, cam, lens)
     assert (~np.isclose(plain.depth, ref, rtol=1e-6) & hit).mean() > 0.05   # the jitter did move the samples
+
+
+def _flat_gbuffer(orc, W, H, z, colour):
+    nrm = np.zeros((H, W, 4), np.float32)
+    nrm[..., 2] = -1.0
+    return orc.GBuffer(np.ascontiguousarray(colour, np.float32), np.full((H, W), z, np.float32), nrm)
+
+
+@pytest.mark.parametrize("focal", [0.1, 0.3])
+def test_prefilter_taps_on_a_quadratic_field(orc, focal):
+    """A3 with one CoC everywhere (so every tap weighs the same) on a colour
+    field (X/16)^2 of the half-res column X: the 3 x 3 taps at spacing s
+    (half the kernel diameter, which is a quarter of the neighbourhood's
+    maximum radius but never below sqrt(2)) average to the mean of the
+    piecewise-linear interpolation of the field at X - s, X, X + s
+    (numpy.interp).  focal 0.1 puts the diameter on its sqrt(2) floor,
+    0.3 above it."""
+    W, H, z = 64, 48, 40.0
+    lens = synth.Lens(focal=focal, fnum=1.0, focus=5.0)
+    hw, hh = W // 2, H // 2
+    X = np.arange(hw, dtype=np.float64)
+    col = np.ones((H, W, 4), np.float32)
+    col[..., :3] = np.repeat(((X / 16.0) ** 2).astype(np.float32), 2)[None, :, None]
+    gb = _flat_gbuffer(orc, W, H, z, col)
+    sc = orc.OracleScene(plane_scene(z))
+    sc.build_bvh()
+    cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    o = orc.render_frame(sc, cam, lens, synth.Params(), gb)
+    r = o["colr"][..., 3]
+    assert np.all(r == r[0, 0]) and r[0, 0] > 0                       # one far-field radius
+    Rn = float(o["tile_dil"].max())
+    assert np.all(o["tile_dil"] == Rn)
+    s = max(Rn * 0.25, math.sqrt(2.0)) * 0.5
+    assert (Rn * 0.25 < math.sqrt(2.0)) == (focal == 0.1)
+    f = lambda t: np.interp(t, X, (X / 16.0) ** 2)
+    inner = slice(3, hw - 4)
+    exp = (f(X - s) + f(X) + f(X + s)) / 3.0
+    got = o["pre"][4:hh - 4, inner, 0]
+    np.testing.assert_allclose(got, np.broadcast_to(exp[inner], got.shape), rtol=0, atol=1e-5)
+
+
+def _upsample(plane, W, H):
+    """Bilinear upsample of a half-res plane to full-res pixel centres (x/2 -
+    1/4, y/2 - 1/4), clamp to edge: scipy.ndimage.map_coordinates."""
+    from scipy.ndimage import map_coordinates
+    yy, xx = np.meshgrid(np.arange(H) * 0.5 - 0.25, np.arange(W) * 0.5 - 0.25, indexing="ij")
+    return np.stack([map_coordinates(plane[..., c].astype(np.float64), [yy, xx], order=1, mode="nearest")
+                     for c in range(3)], -1)
+
+
+@pytest.mark.parametrize("case", ["far_near_hits", "far_far_hits", "far_all_miss", "near_bright", "near_dim"])
+def test_composite_blend_ends(orc, case):
+    """A14's blends at their ends, every half-res pixel ray traced (mask mode
+    all) and outside the zone of focus.  Far field (eq. 7): when every ray
+    hits in front of the focus plane (ratio 1) the output is the upsampled
+    reconstruction; when none does (far hits, or misses: ratio 0) it is the
+    upsampled post-process image.  Near field: taps all brighter than
+    l_spec (bokeh proportion 1) give the post-process image, all dimmer (0)
+    the reconstruction.  The G-buffer is a random texture at one depth, so
+    the two images differ; the scene decides what the rays see."""
+    W, H = 64, 48
+    far = case.startswith("far")
+    z = 40.0 if far else 2.0
+    plane_z = {"far_near_hits": 2.0, "far_far_hits": 40.0, "far_all_miss": -50.0}.get(case, 2.0)
+    lens = synth.Lens(focal=0.1, fnum=1.0, focus=5.0)
+    rng = np.random.default_rng(21)
+    lo, hi = (1.5, 3.0) if case == "near_bright" else (0.0, 0.5)
+    tex = rng.uniform(lo, hi, (H // 4, W // 4, 3)).astype(np.float32)
+    col = np.ones((H, W, 4), np.float32)
+    col[..., :3] = np.repeat(np.repeat(tex, 4, 0), 4, 1)
+    gb = _flat_gbuffer(orc, W, H, z, col)
+    sc = orc.OracleScene(plane_scene(plane_z))
+    sc.build_bvh()
+    cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    o = orc.render_frame(sc, cam, lens, synth.Params(mask_mode=synth.MASK_ALL, m=4), gb)
+    assert np.all(o["mask"] == 4)
+    if far:
+        assert np.all(o["recon"][..., 3] == (1.0 if case == "far_near_hits" else 0.0))
+    rt, pp = _upsample(o["recon"], W, H), _upsample(o["ppmed"], W, H)
+    assert np.abs(rt - pp).max() > 0.05                                    # the two images differ
+    want = rt if case in ("far_near_hits", "near_dim") else pp
+    np.testing.assert_allclose(o["colour"][..., :3], want, rtol=0, atol=2e-5)
+
+
+def test_gather_includes_taps_inside_the_radius_and_counts_bright_ones(orc):
+    """A4 with one CoC radius R and one depth everywhere: sampleAlpha is the
+    same for every tap and every tap is foreground, so the gather is the plain
+    mean of the prefiltered image at the nearest texel of each tap whose
+    distance R * frac is below R (the outer ring, at distance exactly R, is
+    left out: D(0, i) is a strict comparison), and the bokeh proportion is
+    the share of those taps brighter than l_spec (Rec. 709 luma).  Tap
+    offsets from the ring table (pinned on its own); positions and rounding
+    in binary32 as the pass computes them."""
+    W, H, z = 64, 48, 40.0
+    lens = synth.Lens(focal=0.3, fnum=1.0, focus=5.0)
+    params = synth.Params()
+    hw, hh = W // 2, H // 2
+    X = np.arange(hw, dtype=np.float64)
+    col = np.ones((H, W, 4), np.float32)
+    col[..., :3] = np.repeat(((X / 16.0) ** 2).astype(np.float32), 2)[None, :, None]
+    gb = _flat_gbuffer(orc, W, H, z, col)
+    sc = orc.OracleScene(plane_scene(z))
+    sc.build_bvh()
+    cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    o = orc.render_frame(sc, cam, lens, params, gb)
+    pre = o["pre"]
+    R = np.float32(o["tile_dil"].max())
+    assert np.all(o["tile_dil"] == R) and np.all(np.abs(pre[..., 3]) == R) and R > 2
+    ox, oy, frac = (np.asarray(a, np.float32) for a in orc.gather_rings(lens, params))
+    inc = (R * frac) < R
+    assert inc.sum() == 49                                    # centre + rings of 8, 16, 24 taps
+    luma = (0.2126 * pre[..., 0] + 0.7152 * pre[..., 1]) + 0.0722 * pre[..., 2]
+    exp = np.zeros((hh, hw, 3))
+    bok = np.zeros((hh, hw))
+    for k in np.nonzero(inc)[0]:
+        ys = np.arange(hh, dtype=np.float32)[:, None] + oy[k] * R
+        xs = np.arange(hw, dtype=np.float32)[None, :] + ox[k] * R
+        iy = np.clip(np.floor(ys + np.float32(0.5)).astype(int), 0, hh - 1)
+        ix = np.clip(np.floor(xs + np.float32(0.5)).astype(int), 0, hw - 1)
+        iy, ix = np.broadcast_arrays(iy, ix)
+        exp += pre[iy, ix, :3]
+        bok += luma[iy, ix] > params.l_spec
+    n = float(inc.sum())
+    np.testing.assert_allclose(o["gather"][..., :3], exp / n, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(o["gather"][..., 3], bok / n, rtol=0, atol=1e-6)
+    assert 0.0 < o["gather"][..., 3].mean() < 1.0             # both kinds of tap occur
