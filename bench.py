@@ -63,6 +63,7 @@ def parse():
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
     ap.add_argument("--no-m-sweep", dest="m_sweep", action="store_false")
+    ap.add_argument("--no-shots", dest="shots", action="store_false", help="skip the BG / FG shot measurement")
     ap.add_argument("--uhd-steps", type=int, default=60, help="frames of the 3840x2160 measurement (0 = skip)")
     ap.add_argument("--batched-sessions", type=int, default=32, help="sessions of the batched measurement (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -153,6 +154,41 @@ def autotune_grid(gs, cams, lenses, params, gbs, log, label, frames=6):
     log(f"{label}: traversal grid {best if best else 'library default'} ({ms})")
     return best, {"trace_blocks": best if best else "library default",
                   "candidates_ms": {str(k if k else "default"): round(v, 3) for k, v in ms.items()}}
+
+
+def shots_leg(gs, scene, cams, lens, params, tb, main, log):
+    """Frame time by foreground coverage (Table 1 reports its BG / M / FG
+    shots): the 60-frame path (middle class) and two 20-frame shots of the
+    same scene, background ("BG") and inside the grass ("FG").  Coverage =
+    share of pixels whose pinhole ray hits grass (a grass-only copy of the
+    scene, G-buffers untimed)."""
+    import numpy as np
+    import torch
+
+    from paper_2210_06158_amd import dof, synth
+
+    gg = dof.Scene(synth.grass_only(scene))
+    gg.build_bvh()
+
+    def coverage(cs):
+        return round(float(np.mean([torch.isfinite(gg.render_gbuffer(c, lens)[1]).float().mean().item()
+                                    for c in cs])), 4)
+
+    W, H = cams[0].width, cams[0].height
+    out = {"M": {"grass_coverage": coverage(cams), "frames": len(cams), "frames_per_s": main["frames_per_s"],
+                 "p50_frame_ms": main["p50_frame_ms"], "rays_per_frame": main["rays_per_frame"],
+                 "trace_ms": main["trace_ms"]}}
+    for kind in ("BG", "FG"):
+        sc = synth.shot_cameras(kind, 20, W, H)
+        gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in sc]
+        r = run_path(gs, sc, [lens] * len(sc), params, gbs, 20, 5, 10, tb, log)
+        out[kind] = {"grass_coverage": coverage(sc), "frames": len(sc),
+                     "frames_per_s": round(r["K"] / (r["total_ms"] / 1e3), 2),
+                     "p50_frame_ms": round(float(np.percentile(r["frame_ms"], 50)), 4),
+                     "rays_per_frame": round(r["rays"] / r["K"], 1), "trace_ms": round(r["stage_ms"]["trace"], 4)}
+    del gg
+    log(f"shots: {out}")
+    return out
 
 
 def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_blocks, log):
@@ -316,6 +352,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy} MiB")
+    shots = None
+    if args.shots:
+        shots = shots_leg(gs, scene, cams, lens, params, tb, log=log,
+                          main={"frames_per_s": round(fps, 2), "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),
+                                "rays_per_frame": round(rays / K, 1), "trace_ms": round(stage_ms["trace"], 4)})
     # ray budget sweep (Table 2 reports m = 1, 30, 50): traversal and frame
     # time per m on the same path, and the traversal's cost per unit of m
     m_sweep = None
@@ -400,6 +441,7 @@ def main():
         "gbuffer_ms_per_frame": round(gbuffer_ms, 4),
         "frames_per_s_with_gbuffer": round(K / ((total_ms + K * gbuffer_ms) / 1e3), 2),
         "m_sweep": m_sweep,
+        "shots": shots,
         "traversal_grid": grid,
         "bvh_build_ms": round(bvh_ms, 3),
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),

@@ -434,6 +434,27 @@ def camera_spline(rng: SplitMix64, nframes: int, width: int, height: int,
     return cams
 
 
+def shot_cameras(kind: str, nframes: int = 20, width: int = 1920, height: int = 1080, seed: int = 1) -> list:
+    """Camera shots of the 1080p scene by foreground coverage, as Table 1
+    classes its shots: "BG" at eye height 1.1 pitched 2 degrees down (the
+    grass covers about 3 % of the frame), "FG" at 0.12 pitched 8 degrees down
+    inside the grass (about 70 %); the 60-frame path is the middle class
+    (20-40 %).  A slow dolly along x from -0.2 to 0.2."""
+    y, pitch = {"BG": (1.1, -2.0), "FG": (0.12, -8.0)}[kind]
+    out = []
+    for fi in range(nframes):
+        x = -0.2 + 0.4 * fi / max(1, nframes - 1)
+        out.append(look_camera((x, y, 0.0), 0.0, math.radians(pitch), width, height, frame=fi, seed=seed))
+    return out
+
+
+def grass_only(scene: Scene, n_blades: int = 50000) -> Scene:
+    """The grass of a 1080p-recipe scene (its last 4 n_blades triangles), to
+    measure how much of a frame the foreground covers."""
+    n = 4 * n_blades
+    return Scene(scene.verts[-n:], scene.albedo[-n:])
+
+
 def pan_camera(cam: Camera, dx: float) -> Camera:
     """The same camera translated by dx along its right axis."""
     p = np.asarray(cam.pos, np.float64) + dx * np.asarray(cam.right, np.float64)
