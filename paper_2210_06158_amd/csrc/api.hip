@@ -19,6 +19,8 @@ struct dof_scene {
     bool events_ready;   // ev[] created (host-side timing objects)
     bool timed_frame;    // ev[] hold the last timed frame
     hipEvent_t ev[DOF_NUM_STAGES + 1];
+    bool side_ready;     // side holds a stream and two events
+    dof::SideStream side;   // the post-process chain's stream (untimed frames)
 };
 
 namespace {
@@ -511,6 +513,18 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
         delete s;
         return fail(DOF_E_DEVICE, "scene upload: %s", hipGetErrorString(e));
     }
+    // the post-process chain's stream (default priority) and its fork / join
+    // events; without them frames run on the caller's stream alone
+    s->side_ready = hipStreamCreateWithFlags(&s->side.stream, hipStreamNonBlocking) == hipSuccess;
+    if (s->side_ready && hipEventCreateWithFlags(&s->side.fork, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(s->side.stream);
+        s->side_ready = false;
+    }
+    if (s->side_ready && hipEventCreateWithFlags(&s->side.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(s->side.fork);
+        (void)hipStreamDestroy(s->side.stream);
+        s->side_ready = false;
+    }
     *out = s;
     return DOF_OK;
 }
@@ -541,6 +555,11 @@ void dof_destroy_scene(dof_scene *scene)
     if (!scene) return;
     if (scene->events_ready)
         for (int i = 0; i <= DOF_NUM_STAGES; ++i) (void)hipEventDestroy(scene->ev[i]);
+    if (scene->side_ready) {
+        (void)hipEventDestroy(scene->side.fork);
+        (void)hipEventDestroy(scene->side.join);
+        (void)hipStreamDestroy(scene->side.stream);
+    }
     delete scene;
 }
 
@@ -625,10 +644,11 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
         }
         ev = scene->ev;
     }
-    DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, s));
+    const dof::SideStream *side = (ev == nullptr && scene->side_ready) ? &scene->side : nullptr;
+    DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, side, s));
     const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
-    DOF_HIP(dof::launch_frame_post(scene->dev, fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, s));
+    DOF_HIP(dof::launch_frame_post(scene->dev, fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, side, s));
     scene->timed_frame = ev != nullptr;
     return DOF_OK;
 }

@@ -239,13 +239,23 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
                              float *t, int blocks, hipStream_t st);
 
 // frame.hip
+// The post-process chain (prefilter, gather, median, post-filter TAA) reads
+// only what the reduce and the tile dilation wrote, and only the composite
+// reads its result: with a side stream it runs there, forked after the
+// dilation and joined before the composite, beside the mask, compaction,
+// traversal and ray-trace stages.
+struct SideStream {
+    hipStream_t stream;
+    hipEvent_t fork, join;   // recorded on the frame's stream / on the side stream
+};
 // ev (nullable): DOF_NUM_STAGES + 1 events; pre records ev[0..7], post ev[8..13]
+// side (nullable, and only without ev): the post-process chain's stream
 hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                             const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask, hipEvent_t *ev,
-                            hipStream_t st);
+                            const SideStream *side, hipStream_t st);
 hipError_t launch_frame_post(const SceneDev &s, const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
-                             const dof_frame_out &out, hipEvent_t *ev, hipStream_t st);
+                             const dof_frame_out &out, hipEvent_t *ev, const SideStream *side, hipStream_t st);
 hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
 // total blocks of grid g over the jobs

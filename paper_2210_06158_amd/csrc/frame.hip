@@ -1355,7 +1355,7 @@ inline dim3 grid2(int w, int h, int bx, int by) { return dim3((w + bx - 1) / bx,
 
 hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                             const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask, hipEvent_t *ev,
-                            hipStream_t st)
+                            const SideStream *side, hipStream_t st)
 {
     Planes P = planes(fc, L, scratch);
     const int64_t np = (int64_t)fc.hw * fc.hh;
@@ -1366,13 +1366,24 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     DOF_REC(1);
     k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
     DOF_REC(2);
-    k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
+    hipStream_t pst = st;   // the post-process chain's stream
+    if (side) {
+        hipError_t e = hipEventRecord(side->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+        if (e != hipSuccess) return e;
+        pst = side->stream;
+    }
+    k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
     DOF_REC(3);
-    k_gather<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
+    k_gather<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, rings, P);
     DOF_REC(4);
-    k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P);
+    k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
     if (fc.taa & DOF_TAA_POST)
-        k_taa_post<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, hist_in, hist_out);
+        k_taa_post<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P, hist_in, hist_out);
+    if (side) {
+        const hipError_t e = hipEventRecord(side->join, pst);
+        if (e != hipSuccess) return e;
+    }
     DOF_REC(5);
     if (fc.mask_mode == DOF_MASK_DILATE) {
         k_mask<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, P, hist_in, P.mask_raw);
@@ -1392,7 +1403,7 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
 
 hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rings &rings, const ScratchLayout &L, char *scratch,
                              const dof_gbuffer &gb, const void *hist_in, void *hist_out, uint8_t *mask,
-                             const dof_frame_out &out, hipEvent_t *ev, hipStream_t st)
+                             const dof_frame_out &out, hipEvent_t *ev, const SideStream *side, hipStream_t st)
 {
     Planes P = planes(fc, L, scratch);
     const int64_t np = (int64_t)fc.hw * fc.hh;
@@ -1409,6 +1420,10 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
     DOF_REC(11);
     k_recon<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
     DOF_REC(12);
+    if (side) {
+        const hipError_t e = hipStreamWaitEvent(st, side->join, 0);   // the post-process chain is done
+        if (e != hipSuccess) return e;
+    }
     k_composite<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, resolved_gbuffer(fc, P, gb), out);
     if (fc.taa & DOF_TAA_FINAL)
         k_taa_final<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);

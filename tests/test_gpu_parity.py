@@ -356,3 +356,38 @@ def test_taa_all_stages_on_jittered_frames_parity(env, orc):
     plain = orc.render_frame(env["osc"], cams[1], lens, env["params"], gb1, hist_in=o0["hist_out"],
                              prev_cam=cams[0], prev_lens=lens)
     assert not np.array_equal(plain["colr"], o1["colr"])                  # the raster TAA took part
+
+
+def test_single_frame_graph_replays(env, orc):
+    """dof_render_frame captured in a HIP graph -- its post-process chain
+    forks to the scene's side stream and joins back before the composite,
+    both inside the graph -- and replayed three times with new G-buffer
+    contents and eager work in between: every replay equals the eager frame
+    of the same inputs (colour, mask, history)."""
+    torch, dof = env["torch"], env["dof"]
+    cam, lens, params = env["cam"], env["lens"], env["params"]
+    W, H = cam.width, cam.height
+    gbs = [orc.gbuffer(env["osc"], synth.pan_camera(cam, 0.01 * k) if k else cam, lens) for k in range(3)]
+    g_in = to_gpu(torch, gbs[0])
+    fr = dof.Frame(W, H, params)
+    hout = dof.history_alloc(W, H)
+    fr.render(env["gs"], cam, lens, g_in, None, hout)            # warm-up outside the capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            fr.render(env["gs"], cam, lens, g_in, None, hout)
+    torch.cuda.synchronize()
+    for rep, gb in enumerate(reversed(gbs)):
+        src = to_gpu(torch, gb)
+        ref, ref_h = dof.Frame(W, H, params), dof.history_alloc(W, H)
+        ref.render(env["gs"], cam, lens, src, None, ref_h)
+        for dst, s in zip(g_in, src):
+            dst.copy_(s)
+        junk = torch.randn(1 << 20, device="cuda").sum()           # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(fr.colour, ref.colour), rep
+        assert torch.equal(fr.mask, ref.mask) and torch.equal(hout, ref_h), rep
