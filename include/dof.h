@@ -187,7 +187,8 @@ typedef struct dof_scene dof_scene;
  * quarter of the centre bounds' diagonal; ids: triangle ids in that order;
  * nodes: ntri-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
  * float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z, R.lo.z,
- * R.hi.z), uint4 (left, right, 0, 0)}, child bit 31 = leaf (sorted index);
+ * R.hi.z), uint4 (left, right, first leaf, last leaf)}, child bit 31 = leaf
+ * (sorted index), the node covering the sorted leaves first..last;
  * parent: 2 ntri - 1 entries (internal nodes, then leaves), root = ~0u;
  * tris: 3 float4 per leaf in sorted order (w of the first = id bits). */
 typedef struct {

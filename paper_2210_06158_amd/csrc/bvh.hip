@@ -296,9 +296,10 @@ __device__ inline int delta96(const uint64_t *keys, const uint32_t *ids, int n, 
 __global__ __launch_bounds__(kThreads) void k_karras(const uint64_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ ids, int n,
                                                      BvhNode *__restrict__ nodes, uint32_t *__restrict__ parent,
-                                                     uint32_t *__restrict__ flags)
+                                                     uint32_t *__restrict__ flags, uint32_t *__restrict__ exit_count)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i == 0) *exit_count = 0u;
     if (i >= n - 1) return;
     int dn = delta96(keys, ids, n, i, i + 1), dp = delta96(keys, ids, n, i, i - 1);
     int d = dn > dp ? 1 : -1;
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_karras(const uint64_t *__restrict_
     int lo = i < j ? i : j, hi = i < j ? j : i;
     uint32_t left = (lo == gamma) ? ((uint32_t)gamma | kLeaf) : (uint32_t)gamma;
     uint32_t right = (hi == gamma + 1) ? ((uint32_t)(gamma + 1) | kLeaf) : (uint32_t)(gamma + 1);
-    nodes[i].d = make_uint4(left, right, 0u, 0u);
+    nodes[i].d = make_uint4(left, right, (uint32_t)lo, (uint32_t)hi);   // children, leaf range
     parent[(left & kLeaf) ? (size_t)(n - 1) + (left & ~kLeaf) : left] = (uint32_t)i;
     parent[(right & kLeaf) ? (size_t)(n - 1) + (right & ~kLeaf) : right] = (uint32_t)i;
     flags[i] = 0u;
@@ -339,12 +340,46 @@ __device__ inline void store_child_box(BvhNode *nd, bool left, const float lo[3]
     }
 }
 
-// One thread per leaf climbs towards the root; the second thread to reach a
-// node (counted by an acq_rel atomic) merges both child boxes and continues.
-__global__ __launch_bounds__(kThreads) void k_refit(const float4 *__restrict__ tris, int n, BvhNode *nodes,
-                                                    const uint32_t *__restrict__ parent, uint32_t *flags)
+// Refit: one thread per leaf climbs towards the root; the second thread to
+// reach a node merges both child boxes and continues (compare-selects, left
+// first), so every box is exact whatever the schedule.  Shared data must not
+// need device-wide ordering per node: on a multi-die GPU an agent-scope
+// acquire / release writes back and invalidates the die's L2.  So:
+//  k_refit_local: a block owns kRefitThreads consecutive leaves; an internal
+//    node whose leaf range lies inside them (its index is an end of its range,
+//    so it is one of the block's indices) is finished within the block with
+//    LDS arrival counters and the children's boxes in LDS.  A thread whose
+//    next node's range leaves the block appends (child, node, box) to a list.
+//  k_refit_top: one workgroup climbs from every list entry through the nodes
+//    that span blocks (the kernel boundary publishes the first kernel's
+//    writes; inside one workgroup, workgroup-scope ordering suffices).
+// A full list (it holds exits_cap entries) makes a thread climb on with
+// device-wide counters instead, which composes with the second kernel: that
+// kernel only starts once every such climb has ended.
+constexpr int kRefitThreads = 1024;
+
+__device__ inline void union_lr(const float4 a, const float4 b, const float4 c, float lo[3], float hi[3])
 {
-    int i = blockIdx.x * kThreads + threadIdx.x;
+    // union(left, right) as compare-selects, left first
+    lo[0] = b.x < a.x ? b.x : a.x;
+    hi[0] = b.y > a.y ? b.y : a.y;
+    lo[1] = b.z < a.z ? b.z : a.z;
+    hi[1] = b.w > a.w ? b.w : a.w;
+    lo[2] = c.z < c.x ? c.z : c.x;
+    hi[2] = c.w > c.y ? c.w : c.y;
+}
+
+__global__ __launch_bounds__(kRefitThreads) void k_refit_local(const float4 *__restrict__ tris, int n, BvhNode *nodes,
+                                                               const uint32_t *__restrict__ parent, uint32_t *flags,
+                                                               uint4 *exits, uint32_t exits_cap, uint32_t *exit_count)
+{
+    __shared__ uint32_t lcnt[kRefitThreads];
+    __shared__ float lbox[kRefitThreads][12];   // per in-block node: left lo xyz, hi xyz, then right
+    const int tid = threadIdx.x;
+    const uint32_t b0 = blockIdx.x * kRefitThreads, b1 = b0 + kRefitThreads;
+    lcnt[tid] = 0u;
+    __syncthreads();
+    const int i = (int)b0 + tid;
     if (i >= n) return;
     float v[9];
     float4 t0 = tris[3 * (size_t)i], t1 = tris[3 * (size_t)i + 1], t2 = tris[3 * (size_t)i + 2];
@@ -357,20 +392,61 @@ __global__ __launch_bounds__(kThreads) void k_refit(const float4 *__restrict__ t
     uint32_t p = parent[(size_t)(n - 1) + i];
     while (p != ~0u) {
         BvhNode *nd = nodes + p;
-        bool is_left = nd->d.x == child;
+        const uint4 dd = nd->d;
+        if (!(dd.z >= b0 && dd.w < b1)) break;   // the node's range leaves the block
+        const bool is_left = dd.x == child;
         store_child_box(nd, is_left, lo, hi);
-        uint32_t old = __hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        float *slot = lbox[p - b0] + (is_left ? 0 : 6);
+        slot[0] = lo[0]; slot[1] = lo[1]; slot[2] = lo[2];
+        slot[3] = hi[0]; slot[4] = hi[1]; slot[5] = hi[2];
+        const uint32_t old = __hip_atomic_fetch_add(&lcnt[p - b0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0u) return;
-        float4 a = nd->a, b = nd->b, c = nd->c;
-        // union(left, right) as compare-selects, left first
-        lo[0] = b.x < a.x ? b.x : a.x;
-        hi[0] = b.y > a.y ? b.y : a.y;
-        lo[1] = b.z < a.z ? b.z : a.z;
-        hi[1] = b.w > a.w ? b.w : a.w;
-        lo[2] = c.z < c.x ? c.z : c.x;
-        hi[2] = c.w > c.y ? c.w : c.y;
+        const float *L = lbox[p - b0], *R = lbox[p - b0] + 6;
+        lo[0] = R[0] < L[0] ? R[0] : L[0];
+        hi[0] = R[3] > L[3] ? R[3] : L[3];
+        lo[1] = R[1] < L[1] ? R[1] : L[1];
+        hi[1] = R[4] > L[4] ? R[4] : L[4];
+        lo[2] = R[2] < L[2] ? R[2] : L[2];
+        hi[2] = R[5] > L[5] ? R[5] : L[5];
         child = p;
         p = parent[p];
+    }
+    if (p == ~0u) return;   // the whole tree lies in this block
+    const uint32_t e = __hip_atomic_fetch_add(exit_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e < exits_cap) {
+        exits[2 * (size_t)e] = make_uint4(child, p, __float_as_uint(lo[0]), __float_as_uint(lo[1]));
+        exits[2 * (size_t)e + 1] = make_uint4(__float_as_uint(lo[2]), __float_as_uint(hi[0]), __float_as_uint(hi[1]),
+                                              __float_as_uint(hi[2]));
+        return;
+    }
+    while (p != ~0u) {   // list full: device-wide counters
+        BvhNode *nd = nodes + p;
+        store_child_box(nd, nd->d.x == child, lo, hi);
+        if (__hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
+        union_lr(nd->a, nd->b, nd->c, lo, hi);
+        child = p;
+        p = parent[p];
+    }
+}
+
+__global__ __launch_bounds__(kRefitThreads) void k_refit_top(BvhNode *nodes, const uint32_t *__restrict__ parent,
+                                                             uint32_t *flags, const uint4 *__restrict__ exits,
+                                                             uint32_t exits_cap, const uint32_t *__restrict__ exit_count)
+{
+    const uint32_t m = min(*exit_count, exits_cap);
+    for (uint32_t e = threadIdx.x; e < m; e += kRefitThreads) {
+        const uint4 e0 = exits[2 * (size_t)e], e1 = exits[2 * (size_t)e + 1];
+        uint32_t child = e0.x, p = e0.y;
+        float lo[3] = {__uint_as_float(e0.z), __uint_as_float(e0.w), __uint_as_float(e1.x)};
+        float hi[3] = {__uint_as_float(e1.y), __uint_as_float(e1.z), __uint_as_float(e1.w)};
+        while (p != ~0u) {
+            BvhNode *nd = nodes + p;
+            store_child_box(nd, nd->d.x == child, lo, hi);
+            if (__hip_atomic_fetch_add(flags + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u) break;
+            union_lr(nd->a, nd->b, nd->c, lo, hi);
+            child = p;
+            p = parent[p];
+        }
     }
 }
 
@@ -400,8 +476,15 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
     }
     k_reorder<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, s.albedo_in, s.ids, n, s.tris, s.albedo);
     if (n >= 2) {
-        k_karras<<<ceil_div(n - 1, kThreads), kThreads, 0, st>>>(s.keys, s.ids, n, s.nodes, s.parent, s.flags);
-        k_refit<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.tris, n, s.nodes, s.parent, s.flags);
+        // the refit's list of block exits lives in the sort's spare key buffer (free after the sort)
+        uint4 *exits = reinterpret_cast<uint4 *>(s.keys_tmp);
+        const uint32_t cap = (uint32_t)((sizeof(uint64_t) * (size_t)n) / (2 * sizeof(uint4)));
+        uint32_t *exit_count = s.aux + 8;
+        k_karras<<<ceil_div(n - 1, kThreads), kThreads, 0, st>>>(s.keys, s.ids, n, s.nodes, s.parent, s.flags,
+                                                                   exit_count);
+        k_refit_local<<<ceil_div(n, kRefitThreads), kRefitThreads, 0, st>>>(s.tris, n, s.nodes, s.parent, s.flags,
+                                                                              exits, cap, exit_count);
+        k_refit_top<<<1, kRefitThreads, 0, st>>>(s.nodes, s.parent, s.flags, exits, cap, exit_count);
     }
     return hipGetLastError();
 }

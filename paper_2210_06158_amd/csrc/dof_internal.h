@@ -32,7 +32,7 @@ struct BvhNode {      // 64 B, both children's boxes with the parent
     float4 a;         // L.lo.x, L.hi.x, L.lo.y, L.hi.y
     float4 b;         // R.lo.x, R.hi.x, R.lo.y, R.hi.y
     float4 c;         // L.lo.z, L.hi.z, R.lo.z, R.hi.z
-    uint4 d;          // left, right, 0, 0
+    uint4 d;          // left, right, first and last leaf of the range (bit 31 of a child: leaf)
 };
 
 struct SceneShade {

@@ -98,6 +98,26 @@ def test_bvh_bit_exact(env, orc):
     nodes = v["nodes"].cpu().numpy().reshape(n - 1, 16)
     nu = nodes.view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
+    # leaf ranges: the leaves below each node, from the oracle's child arrays (children's ranges, leftmost
+    # and rightmost), and the Karras property that a node's index is an end of its range
+    first, last = np.zeros(n - 1, np.int64), np.zeros(n - 1, np.int64)
+    def span(c):
+        return (c & ~LEAF, c & ~LEAF) if c & LEAF else (first[c], last[c])
+    done = np.zeros(n - 1, bool)
+    stack = [0]
+    while stack:                       # post-order over the oracle's tree
+        i = stack[-1]
+        kids = [int(ob["left"][i]), int(ob["right"][i])]
+        todo = [k for k in kids if not (k & LEAF) and not done[k]]
+        if todo:
+            stack.extend(todo)
+            continue
+        stack.pop()
+        first[i], last[i] = span(kids[0])[0], span(kids[1])[1]
+        done[i] = True
+    assert np.array_equal(nu[:, 14], first) and np.array_equal(nu[:, 15], last)
+    idx = np.arange(n - 1)
+    assert np.all((idx == first) | (idx == last))
     assert np.array_equal(v["parent"].cpu().numpy().view(np.uint32), ob["parent"])
 
     def child_box(c):
