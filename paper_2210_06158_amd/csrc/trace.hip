@@ -316,7 +316,6 @@ __device__ inline void shade_ray(const SceneArgs &S, const FrameConst &fc, const
 
 struct LensRays {
     static constexpr bool kPerLaneScene = false;
-    FrameConst fc;
     const float4 *rec0, *rec1, *rec2;
     uint2 *ray_lt;
 
@@ -724,7 +723,6 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
                         hipStream_t st)
 {
     LensRays src;
-    src.fc = fc;
     const Planes P = planes(fc, L, scratch);
     src.rec0 = P.rec0;
     src.rec1 = P.rec1;
