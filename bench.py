@@ -252,7 +252,8 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_b
         t_tests += int(sv.view(np.int64)[2])
     return dict(W=W, H=H, K=K, total_ms=total_ms, frame_ms=frame_ms, rays=int(st[:, 1].astype(np.int64).sum()),
                 masked=int(st[:, 0].astype(np.int64).sum()), visits=int(st64[:, 1].sum()),
-                tests=int(st64[:, 2].sum()), stage_ms={s: v / nst for s, v in sums.items()},
+                tests=int(st64[:, 2].sum()), spills=int(st[:, 6].astype(np.int64).sum()),
+                stage_ms={s: v / nst for s, v in sums.items()},
                 stage_frames=nst, t_rays=t_rays, t_masked=t_masked, t_visits=t_visits, t_tests=t_tests)
 
 
@@ -434,6 +435,7 @@ def main():
         "trace_kernel_grays_per_s": round(trace_grays, 4) if trace_grays else None,
         "rays_per_frame": round(rays / K, 1),
         "node_visits_per_ray": round(visits / max(rays, 1), 2),
+        "stack_spills_per_frame": round(r["spills"] / K, 2),
         "tri_tests_per_ray": round(tests / max(rays, 1), 2),
         "masked_px_per_frame": round(masked / K, 1),
         "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),

@@ -159,7 +159,8 @@ typedef struct {
     uint32_t rays;          /* thin-lens rays traced */
     uint64_t node_visits;   /* BVH nodes fetched by the traversal */
     uint64_t tri_tests;     /* ray/triangle tests */
-    uint32_t reserved[2];
+    uint32_t stack_spills;  /* traversal stack chunks moved from LDS to the spill area */
+    uint32_t reserved[1];
 } dof_stats;
 
 typedef struct {

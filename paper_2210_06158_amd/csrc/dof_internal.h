@@ -200,7 +200,7 @@ inline size_t batch_table_bytes(int n)
 
 // counters[] slots (u32) in scratch: [0] masked px, [1] rays, [2..3] u64 node
 // visits, [4..5] u64 triangle tests, [8] traversal work counter
-enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntWork = 8 };
+enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntSpills = 6, kCntWork = 8 };
 
 // ---------------------------------------------------------------- helpers
 

@@ -657,7 +657,7 @@ __device__ inline void b_compact_scan(int64_t nchunks, const Planes &P, dof_stat
     if (threadIdx.x == 1023) {
         P.counters[kCntMasked] = pp[1023];
         P.counters[kCntRays] = pr[1023];
-        for (int k = kCntVisits; k < kCntVisits + 4; ++k) P.counters[k] = 0u;
+        for (int k = kCntVisits; k <= kCntSpills; ++k) P.counters[k] = 0u;
         P.counters[kCntWork] = 0u;
         if (stats) {
             stats->masked_px = pp[1023];
@@ -1431,7 +1431,8 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
     if (out.stats) {
         // copy the frame counters to the caller's stats record
         // masked px, rays, node visits, triangle tests
-        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 24, hipMemcpyDeviceToDevice, st);
+        // masked px, rays, node visits, triangle tests, stack spills
+        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 28, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();

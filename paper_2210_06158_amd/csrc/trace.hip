@@ -526,7 +526,8 @@ constexpr int kLeafBatch = 32;   // run triangle tests when at least this many l
 
 template <class Src>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
-                                                  uint32_t *work, uint32_t *spill, unsigned long long *stats)
+                                                  uint32_t *work, uint32_t *spill, unsigned long long *stats,
+                                                  uint32_t *spills_out)
 {
     __shared__ uint32_t lds_stack[kStackLds * kTB];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     float o[3], d[3];
     WRay wr;
     Hit h;
-    uint32_t visits = 0, tests = 0;
+    uint32_t visits = 0, tests = 0, spills = 0;
     // pending leaf hits of this lane (tested when enough lanes have some)
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
     int nq = 0;
@@ -643,6 +644,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     for (int i = 0; i < kStackLds - kSpillChunk; ++i) stk[i * kTB] = stk[(i + kSpillChunk) * kTB];
                     ns += kSpillChunk;
                     sp -= kSpillChunk;
+                    ++spills;
                 }
                 stk[sp * kTB] = farc;
                 ++sp;
@@ -682,6 +684,11 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             atomicAdd(stats, v);
             atomicAdd(stats + 1, t);
         }
+    }
+    if (spills_out) {
+        uint32_t sv = spills;
+        for (int off = 32; off >= 1; off >>= 1) sv += __shfl_xor(sv, off);
+        if (lane == 0 && sv) atomicAdd(spills_out, sv);
     }
 }
 
@@ -731,7 +738,7 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
     k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(
         scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork, reinterpret_cast<uint32_t *>(scratch + L.spill),
-        reinterpret_cast<unsigned long long *>(cnt + kCntVisits));
+        reinterpret_cast<unsigned long long *>(cnt + kCntVisits), cnt + kCntSpills);
     return hipGetLastError();
 }
 
@@ -765,7 +772,7 @@ hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour,
     src.nfmt = nfmt;
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
     k_traverse<PinholeRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H),
-                                                                  nullptr, s.aux, s.spill, nullptr);
+                                                                  nullptr, s.aux, s.spill, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -776,7 +783,7 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
     RawRays src{org, dir, hit, t};
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
     k_traverse<RawRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux, s.spill,
-                                                              nullptr);
+                                                              nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -787,7 +794,7 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint3
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
     k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
-                                                                &head->visits);
+                                                                &head->visits, nullptr);
     kb_shade<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     return hipGetLastError();
 }
