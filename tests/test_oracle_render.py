@@ -785,3 +785,69 @@ def test_gather_includes_taps_inside_the_radius_and_counts_bright_ones(orc):
     np.testing.assert_allclose(o["gather"][..., :3], exp / n, rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(o["gather"][..., 3], bok / n, rtol=0, atol=1e-6)
     assert 0.0 < o["gather"][..., 3].mean() < 1.0             # both kinds of tap occur
+
+
+def test_reconstruction_keeps_a_linear_field_whatever_b(orc):
+    """A13 beyond b = 0.  On a colour field linear in x, a box-averaged mip
+    level holds the field at each texel's footprint centre, so the bilinear
+    sample at a tap's mip coordinates ((x + 1/2) 2^-L - 1/2) is the field at
+    the tap itself, on either level; over the symmetric rings the taps then
+    average to the centre value, and with every tap valid the reconstruction
+    returns its median input unchanged for any blend factor b.  The field is
+    put into the ray-traced image through the history: a near plane of one
+    colour c hit by every ray, static camera (the near field reprojects each
+    pixel onto itself), so the temporal stage gives c + 0.95 (H - c) with H
+    the history's near colour, here linear in x; the history's luma moments
+    force a large variance, so b sits at its 0.9 cap.  The temporal CoC is
+    uniform only to rounding, and an outer-ring tap lies exactly at the
+    radius, so a neighbour whose CoC is a few ulps smaller rejects it; the
+    expected value therefore takes the mean over the taps that pass the
+    rejection rule: centre + b * slope * R * mean(ox over valid taps), which
+    is the centre itself when every tap passes."""
+    W, H, z = 128, 96, 2.0
+    hw, hh = W // 2, H // 2
+    np_ = hw * hh
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    col = np.full((H, W, 4), 0.5, np.float32)
+    gb = _flat_gbuffer(orc, W, H, z, col)
+    sc = orc.OracleScene(plane_scene(z))
+    sc.build_bvh()
+    cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    p = synth.Params(mask_mode=synth.MASK_ALL, m=4)
+    f0 = orc.render_frame(sc, cam, lens, p, gb)
+    hist = f0["hist_out"].copy()
+    X = np.arange(hw, dtype=np.float32)
+    A = hist[:4 * np_].reshape(hh, hw, 4)
+    A[..., :3] = (np.float32(0.2) + np.float32(0.01) * X)[None, :, None]
+    A[..., 3] = 1.0                                    # hit ratio: near field only
+    Cp = hist[8 * np_:12 * np_].reshape(hh, hw, 4)
+    Cp[..., 2] = 0.0                                   # luma mean
+    Cp[..., 3] = 1.0                                   # luma second moment
+    f1 = orc.render_frame(sc, dataclasses.replace(cam, frame=1), lens, p, gb, hist_in=hist, prev_cam=cam,
+                          prev_lens=lens)
+    assert np.all(f1["prev_idx"] == np.arange(np_).reshape(hh, hw))   # each pixel onto itself
+    assert np.all(f1["temporal"][0][..., 3] > 0)                      # every pixel ray traced
+    med, rec = f1["rtmed"], f1["recon"]
+    step = np.diff(med[..., 0], axis=1)                # the median input is linear in x
+    assert np.abs(step - step.mean()).max() < 1e-5 and abs(step.mean()) > 1e-3
+    bb = np.clip(f1["var_blur"] * p.var_recon_w, 0.0, p.b_max)
+    assert bb.min() > 0.5                              # b far from 0
+    ct = f1["temporal"][1][..., 0]                     # temporal CoC (full-res diameter)
+    lod = np.clip(ct * p.lod_scale, 0.0, p.lod_max)
+    assert lod.min() > 1.0 and np.any(lod % 1.0 > 0.1)  # two mip levels above the finest, blended
+    R = float(ct.max()) * 0.25                         # tap radius
+    m = int(math.ceil(R)) + 9                          # taps and coarsest texels stay inside
+    assert hh - 2 * m > 2 and hw - 2 * m > 2
+    inner = (slice(m, hh - m), slice(m, hw - m))
+    ox, oy, frac = orc.gather_rings(synth.Lens(), synth.Params())
+    ys, xs = np.mgrid[m:hh - m, m:hw - m]
+    Rr = ct[ys, xs].astype(np.float32) * np.float32(0.25)          # per-pixel tap radius
+    sx = xs[..., None].astype(np.float32) + ox[None, None, :] * Rr[..., None]
+    sy = ys[..., None].astype(np.float32) + oy[None, None, :] * Rr[..., None]
+    ix = np.clip(np.floor(sx + np.float32(0.5)).astype(int), 0, hw - 1)
+    iy = np.clip(np.floor(sy + np.float32(0.5)).astype(int), 0, hh - 1)
+    valid = ~(ct[iy, ix] * np.float32(0.25) < Rr[..., None] * frac[None, None, :])
+    assert valid.sum(axis=-1).min() >= 81 - 32                      # at most the outer ring drops
+    shift = (ox[None, None, :].astype(np.float64) * valid).sum(-1) / valid.sum(-1) * Rr
+    exp = med[inner][..., :3] + (bb[inner] * step.mean() * shift)[..., None]
+    np.testing.assert_allclose(rec[inner][..., :3], exp, rtol=0, atol=2e-5)
