@@ -59,6 +59,25 @@ __device__ inline float4 bilinear4(const float4 *img, int w, int h, float x, flo
     return o;
 }
 
+// bilinear4 where the caller has shown 0 <= x < w - 1 and 0 <= y < h - 1 and
+// w < 2^24: no clamp changes an index, floor is the integer conversion, and
+// x - floor(x) is exact for x >= 0 (so fract gives the same bits), hence the
+// same result with fewer instructions.
+__device__ inline float4 bilinear4_in(const float4 *img, int w, float x, float y)
+{
+    const int x0 = (int)x, y0 = (int)y;
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y);
+    const float4 *r0 = img + (uint32_t)(__umul24(y0, w) + x0), *r1 = r0 + w;
+    float4 a = r0[0], b = r0[1];
+    float4 c = r1[0], d = r1[1];
+    float4 top, bot, o;
+    top.x = a.x + (b.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
+    top.y = a.y + (b.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
+    top.z = a.z + (b.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
+    top.w = a.w + (b.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
+    return o;
+}
+
 __device__ inline int nearest_idx(float s, int n) { return clampi((int)floorf(s + 0.5f), 0, n - 1); }
 
 // Median of 9 by a max-min exchange network (19 compare-exchanges).
@@ -1025,6 +1044,61 @@ __global__ __launch_bounds__(64) void kb_blur_median_mips(const Job *__restrict_
 
 // ---------------------------------------------------------------- A13
 
+// Tap positions are c + o * R with |o| <= 1 (ring radii k/4, k <= 4), and
+// rounding is monotone, so they lie in [c - R, c + R] as computed in binary32;
+// every later coordinate map is monotone too, so testing the two ends bounds
+// every tap.  taps_inside: the nearest-pixel lookup of the tap plane needs no
+// clamp.  mip_taps_inside: the bilinear mip lookup at scale sc needs none and
+// reads only non-negative coordinates.
+__device__ inline bool taps_inside(int c, float R, int n)
+{
+    const float lo = (float)c + (-R), hi = (float)c + R;
+    return lo + 0.5f >= 0.0f && hi + 0.5f < (float)n;
+}
+
+__device__ inline bool mip_taps_inside(int c, float R, float sc, int n)
+{
+    const float lo = (float)c + (-R), hi = (float)c + R;
+    return (lo + 0.5f) * sc - 0.5f >= 0.0f && (hi + 0.5f) * sc - 0.5f < (float)(n - 1);
+}
+
+// The 81 taps of one pixel, summed in tap order.  Every tap's fetches are
+// issued (indices in bounds: clamped, or shown inside) and only valid taps are
+// summed, so the loads of several taps can be in flight at once.
+template <bool Inside>
+__device__ inline void recon_taps(int x, int y, float Rr, float fl, float sc0, float sc1, int hw, int hh,
+                                  const float4 *mip0, int w0, int h0, const float4 *mip1, int w1, int h1,
+                                  const Rings &rings, const float2 *tap, float &a0, float &a1, float &a2, float &a3,
+                                  float &sh, int &na)
+{
+#pragma unroll 3
+    for (int k = 0; k < kRingTaps; ++k) {
+        float dist = Rr * rings.frac[k];
+        float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
+        size_t j;
+        if (Inside)
+            j = (uint32_t)(__umul24((int)(sy + 0.5f), hw) + (int)(sx + 0.5f));
+        else
+            j = (size_t)nearest_idx(sy, hh) * hw + nearest_idx(sx, hw);
+        // a tap counts when its pixel is ray traced and its CoC radius
+        // reaches the tap (invalid pixels carry -inf)
+        const float2 tj = tap[j];
+        const bool ok = tj.x * 0.25f >= dist;
+        const float u0 = (sx + 0.5f) * sc0 - 0.5f, v0 = (sy + 0.5f) * sc0 - 0.5f;
+        const float u1 = (sx + 0.5f) * sc1 - 0.5f, v1 = (sy + 0.5f) * sc1 - 0.5f;
+        float4 s0 = Inside ? bilinear4_in(mip0, w0, u0, v0) : bilinear4(mip0, w0, h0, u0, v0);
+        float4 s1 = Inside ? bilinear4_in(mip1, w1, u1, v1) : bilinear4(mip1, w1, h1, u1, v1);
+        // a + (ok ? v : 0) is a + v or a itself: the sums start at +0 and
+        // so are never -0
+        a0 = a0 + (ok ? lerp1(s0.x, s1.x, fl) : 0.0f);
+        a1 = a1 + (ok ? lerp1(s0.y, s1.y, fl) : 0.0f);
+        a2 = a2 + (ok ? lerp1(s0.z, s1.z, fl) : 0.0f);
+        a3 = a3 + (ok ? lerp1(s0.w, s1.w, fl) : 0.0f);
+        sh = sh + (ok ? tj.y : 0.0f);
+        na += ok ? 1 : 0;
+    }
+}
+
 __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
 {
     const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
@@ -1051,28 +1125,15 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
     const int w0 = fc.mw[L0], h0 = fc.mh[L0], w1 = fc.mw[L1], h1 = fc.mh[L1];
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, sh = 0.0f;
     int na = 0;
-    // Every tap's fetches are issued (their indices are clamped, so always in
-    // bounds) and only valid taps are summed, in tap order: the loads of
-    // several taps can then be in flight at once.
-#pragma unroll 3
-    for (int k = 0; k < kRingTaps; ++k) {
-        float dist = Rr * rings.frac[k];
-        float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
-        int ix = nearest_idx(sx, hw), iy = nearest_idx(sy, hh);
-        size_t j = (size_t)iy * hw + ix;
-        // a tap counts when its pixel is ray traced and its CoC radius
-        // reaches the tap (invalid pixels carry -inf)
-        const float2 tj = P.tap[j];
-        const bool ok = tj.x * 0.25f >= dist;
-        float4 s0 = bilinear4(mip0, w0, h0, (sx + 0.5f) * sc0 - 0.5f, (sy + 0.5f) * sc0 - 0.5f);
-        float4 s1 = bilinear4(mip1, w1, h1, (sx + 0.5f) * sc1 - 0.5f, (sy + 0.5f) * sc1 - 0.5f);
-        a0 = ok ? a0 + lerp1(s0.x, s1.x, fl) : a0;
-        a1 = ok ? a1 + lerp1(s0.y, s1.y, fl) : a1;
-        a2 = ok ? a2 + lerp1(s0.z, s1.z, fl) : a2;
-        a3 = ok ? a3 + lerp1(s0.w, s1.w, fl) : a3;
-        sh = ok ? sh + tj.y : sh;
-        na += ok ? 1 : 0;
-    }
+    // The interior path is taken by a whole wave when every lane's taps stay
+    // inside all planes it reads (same arithmetic, no clamps).
+    const bool inside = hw < (1 << 24) && hh < (1 << 24) && taps_inside(x, Rr, hw) && taps_inside(y, Rr, hh) &&
+                        mip_taps_inside(x, Rr, sc0, w0) && mip_taps_inside(y, Rr, sc0, h0) &&
+                        mip_taps_inside(x, Rr, sc1, w1) && mip_taps_inside(y, Rr, sc1, h1);
+    if (__ballot(!inside) == 0ull)
+        recon_taps<true>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh, na);
+    else
+        recon_taps<false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh, na);
     const float4 med = P.rtmed[i];
     float nb0 = a3 > 0.0f ? a0 / a3 : med.x, nb1 = a3 > 0.0f ? a1 / a3 : med.y, nb2 = a3 > 0.0f ? a2 / a3 : med.z;
     float hnb = na > 0 ? sh / (float)na : hu;
