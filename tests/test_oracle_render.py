@@ -851,3 +851,132 @@ def test_reconstruction_keeps_a_linear_field_whatever_b(orc):
     shift = (ox[None, None, :].astype(np.float64) * valid).sum(-1) / valid.sum(-1) * Rr
     exp = med[inner][..., :3] + (bb[inner] * step.mean() * shift)[..., None]
     np.testing.assert_allclose(rec[inner][..., :3], exp, rtol=0, atol=2e-5)
+
+
+@pytest.mark.parametrize("field", ["near", "far"])
+def test_temporal_reprojection_under_a_pan(orc, field):
+    """A12 under camera motion.  The camera pans right by exactly s half-res
+    pitches at the depth of a plane facing it, so the point seen at half-res
+    pixel x was seen at x + s: each pixel centre reprojects to the middle of
+    that pixel, and a reprojection off screen has no history.  The history is
+    built by hand (seeded random near and far colours, age 1), and every
+    pixel shoots m rays.  A plane nearer than the focus ramp makes every hit near field: the
+    G-buffer reprojection (prev_idx) is x + s and the temporal colour is the
+    exponential average c + alpha_m (A[x + s] - c) of this frame's near mean
+    with the history's near colour, alpha_m the weight during motion.  A
+    plane beyond the ramp makes every hit far field: the far field is
+    reprojected through the mean far hit position, which lies on the plane
+    but off the pixel's centre line by the mean of its lens samples; the
+    texel it lands on comes from a pinhole projection into the previous
+    camera computed here in binary64 (coordinates within 1e-4 of a texel
+    edge skipped), mostly x + s, and the temporal colour averages the far
+    mean with the history's far colour there.  Without a history texel the
+    temporal colour is this frame's mean.  Age counts up from the history's."""
+    W, H, s = 128, 96, 3
+    hw, hh = W // 2, H // 2
+    np_ = hw * hh
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    z = 2.0 if field == "near" else 6.0
+    tanx = (lens.sensor * (lens.focus - lens.focal)) / (2.0 * lens.focal * lens.focus)
+    cam0 = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    cam1 = synth.pan_camera(cam0, s * z * 2.0 * tanx / hw)
+    gb = _flat_gbuffer(orc, W, H, z, np.full((H, W, 4), 0.5, np.float32))
+    sc = orc.OracleScene(plane_scene(z))
+    sc.build_bvh()
+    p = synth.Params(mask_mode=synth.MASK_ALL, m=4)
+    hist = orc.history_zeros(W, H)
+    rng = np.random.default_rng(5)
+    A = hist[:4 * np_].reshape(hh, hw, 4)
+    B = hist[4 * np_:8 * np_].reshape(hh, hw, 4)
+    A[..., :3] = rng.uniform(0.0, 1.0, (hh, hw, 3))
+    A[..., 3] = 1.0 if field == "near" else 0.0
+    B[..., :3] = rng.uniform(0.0, 1.0, (hh, hw, 3))
+    B[..., 3] = 1.0
+    f1 = orc.render_frame(sc, cam1, lens, p, gb, hist_in=hist, prev_cam=cam0, prev_lens=lens)
+    X = np.arange(hw)[None, :].repeat(hh, 0)
+    Y = np.arange(hh)[:, None].repeat(hw, 1)
+    on = X + s < hw
+    assert np.array_equal(f1["prev_idx"], np.where(on, Y * hw + X + s, -1))
+    T0 = f1["temporal"][0]
+    assert np.all(T0[..., 3] == 1.0)                                    # every pixel traced
+    a = np.float32(p.alpha_motion)
+    if field == "near":
+        cur = f1["resolve"][0][..., :3]
+        py, px, got = Y, X + s, on
+        Hc = A[..., :3]
+    else:
+        cur = f1["resolve"][1][..., :3]
+        fp = f1["resolve"][3]                                            # mean far hit position, validity
+        assert np.all(fp[on][:, 3] == 1.0) and np.allclose(fp[on][:, 2], z, rtol=0, atol=1e-5)
+        e = fp[..., :3].astype(np.float64) - np.asarray(cam0.pos, np.float64)
+        ex, ey, ez = (e @ np.asarray(v, np.float64) for v in (cam0.right, cam0.up, cam0.fwd))
+        u = ((ex / ez) / tanx + 1.0) * 0.5 * hw
+        w = (1.0 - (ey / ez) / (tanx * H / W)) * 0.5 * hh
+        px, py = np.floor(u).astype(int), np.floor(w).astype(int)
+        clear = (np.abs(u - np.round(u)) > 1e-4) & (np.abs(w - np.round(w)) > 1e-4)
+        got = on & clear & (px >= 0) & (px < hw) & (py >= 0) & (py < hh)
+        assert got.sum() > 0.95 * on.sum() and np.mean((px == X + s) & (py == Y)) > 0.8
+        Hc = B[..., :3]
+        off = clear & ((px >= hw) | (py < 0) | (py >= hh))
+        assert off.sum() >= s * hh - hh // 4
+        np.testing.assert_allclose(T0[off][:, :3], cur[off], rtol=0, atol=1e-6)   # no history: this frame
+    prev = Hc[np.clip(py, 0, hh - 1), np.clip(px, 0, hw - 1)]
+    exp = (cur + (prev - cur) * a).astype(np.float32)
+    np.testing.assert_allclose(T0[got][:, :3], exp[got], rtol=0, atol=1e-6)
+    assert np.ptp(T0[got][:, :3]) > 0.3                                  # the history field shows through
+    if field == "near":
+        np.testing.assert_allclose(T0[~on][:, :3], cur[~on], rtol=0, atol=1e-6)   # no history: this frame
+    hb = f1["hist_out"][4 * np_:8 * np_].reshape(hh, hw, 4)
+    assert np.all(hb[on][:, 3] == 2.0)
+
+
+def test_temporal_merge_of_mixed_fields_static(orc):
+    """A12's hit-ratio merge with both fields present.  A plane exactly at the
+    focus distance puts every ray at the middle of the near/far ramp (near
+    weight 1/2), and all rays of a pixel meet at its focus point, so with a
+    static camera both fields reproject onto the pixel itself and this
+    frame's hit ratio is 1/2.  Hand-set history: near colour 1, far colour 0,
+    accumulated hit ratio 1, near CoC 8, far CoC 2, luma moments 1/2 and 1/2.
+    With history weight 0.95 and this frame's colour c (the same in both
+    fields: one plane), CoC ~0 and luma l:
+        near 0.05 c + 0.95, far 0.05 c, hit ratio 0.5 + 0.5 * 0.95 = 0.975,
+        colour = far + 0.975 (near - far) = 0.05 c + 0.92625,
+        CoC = 1.9 + 0.975 (7.6 - 1.9) = 7.4575,
+        mu1 = 0.05 l + 0.475, mu2 = 0.05 l^2 + 0.475, variance mu2 - mu1^2.
+    A swapped merge would give 0.05 c + 0.02375, and merging by this frame's
+    hit ratio (the rule during motion) 0.05 c + 0.475."""
+    W, H = 128, 96
+    hw, hh = W // 2, H // 2
+    np_ = hw * hh
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    z = lens.focus
+    cam0 = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    cam1 = dataclasses.replace(cam0, frame=1)
+    gb = _flat_gbuffer(orc, W, H, z, np.full((H, W, 4), 0.5, np.float32))
+    sc = orc.OracleScene(plane_scene(z))
+    sc.build_bvh()
+    p = synth.Params(mask_mode=synth.MASK_ALL, m=4)
+    assert p.alpha == pytest.approx(0.95)
+    hist = orc.history_zeros(W, H)
+    A = hist[:4 * np_].reshape(hh, hw, 4)
+    B = hist[4 * np_:8 * np_].reshape(hh, hw, 4)
+    C = hist[8 * np_:12 * np_].reshape(hh, hw, 4)
+    A[...] = 1.0
+    B[..., :3] = 0.0
+    B[..., 3] = 1.0
+    C[...] = (8.0, 2.0, 0.5, 0.5)
+    f1 = orc.render_frame(sc, cam1, lens, p, gb, hist_in=hist, prev_cam=cam0, prev_lens=lens)
+    assert np.array_equal(f1["prev_idx"], np.arange(np_).reshape(hh, hw))
+    res = f1["resolve"]
+    np.testing.assert_allclose(res[1][..., 3], 0.5, rtol=0, atol=1e-5)        # this frame's hit ratio
+    c = res[0][..., :3].astype(np.float64)
+    np.testing.assert_allclose(res[1][..., :3], c, rtol=0, atol=1e-6)          # one plane: same colour
+    T0, T1 = f1["temporal"]
+    col = 0.05 * c + 0.92625
+    np.testing.assert_allclose(T0[..., :3], col, rtol=0, atol=2e-5)
+    np.testing.assert_allclose(T1[..., 0], 7.4575, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(T1[..., 1], 0.975, rtol=0, atol=1e-5)
+    l = col @ np.array([0.2126, 0.7152, 0.0722])
+    mu1, mu2 = 0.05 * l + 0.475, 0.05 * l * l + 0.475
+    np.testing.assert_allclose(T1[..., 2], np.maximum(mu2 - mu1 * mu1, 0.0), rtol=0, atol=2e-5)
+    assert T1[..., 2].min() > 0.1
