@@ -922,8 +922,8 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     /* A3 -- 9-tap bilateral prefilter (3.1.1).  Kernel diameter 1/8 of the
      * neighbourhood maximum CoC diameter, never below sqrt(2); taps on a 3x3
      * grid; weight 1 / (1 + |r_i - r_c|).  Pinned at one CoC on a quadratic
-     * field (tap spacing, sampling, normalisation); the weight at differing
-     * CoCs only by invariants (parity unpinned there). */
+     * field (tap spacing, sampling, normalisation) and across a step of the
+     * CoC (the weight). */
     for (int y = 0; y < hh; y++)
         for (int x = 0; x < hw; x++) {
             size_t i = (size_t)y * hw + x;
@@ -953,9 +953,9 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
      * background tap also needs the centre's radius to reach it.  The
      * proportion of weight on taps brighter than l_spec is the bokeh
      * intensity used by the composite.  Pinned at one CoC and one depth
-     * (inclusion, nearest-texel sampling, normalisation, bokeh share); the
-     * foreground/background depth weights and sampleAlpha at differing CoCs
-     * only by invariants (parity unpinned there). */
+     * (inclusion, nearest-texel sampling, normalisation, bokeh share) and
+     * across steps of depth and CoC (sampleAlpha, the foreground/background
+     * split, the centre-radius rule for background taps). */
 #pragma omp parallel for schedule(dynamic, 4) num_threads(g_threads)
     for (int y = 0; y < hh; y++)
         for (int x = 0; x < hw; x++) {

@@ -980,3 +980,156 @@ def test_temporal_merge_of_mixed_fields_static(orc):
     mu1, mu2 = 0.05 * l + 0.475, 0.05 * l * l + 0.475
     np.testing.assert_allclose(T1[..., 2], np.maximum(mu2 - mu1 * mu1, 0.0), rtol=0, atol=2e-5)
     assert T1[..., 2].min() > 0.1
+
+
+def _z_for_radius(orc, lens, W, r):
+    """Near-field depth whose half-res CoC radius (diameter / 4) is r, by
+    bisection on the oracle's CoC (decreasing in depth before the focus)."""
+    lo, hi = 1e-3, lens.focus
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if orc.coc(lens, W, mid) / 4.0 > r:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _two_region_gbuffer(orc, W, H, b, z1, z2, c1, c2):
+    """Full-res G-buffer: depth z1 and colour c1 left of full-res column 2b,
+    z2 and c2 from there on; normals face the camera."""
+    depth = np.full((H, W), z1, np.float32)
+    depth[:, 2 * b:] = z2
+    col = np.ones((H, W, 4), np.float32)
+    col[:, :2 * b, :3] = c1
+    col[:, 2 * b:, :3] = c2
+    nrm = np.zeros((H, W, 4), np.float32)
+    nrm[..., 2] = -1.0
+    return orc.GBuffer(col, depth, nrm)
+
+
+def test_prefilter_weights_across_a_coc_step(orc):
+    """A3 at differing CoCs.  Two near-field regions meet at half-res column b:
+    CoC radius 8 on the left, 6 on the right.  The dilated maximum radius 8
+    sets the kernel diameter to 8/4 = 2 and the tap spacing to 1, so the 3 x 3
+    taps sit on texel centres.  Next to the step, 6 taps share the centre's
+    radius (weight 1) and 3 differ by 2 (weight 1/(1 + 2) = 1/3):
+    (6 c1 + c2) / 7 left of it, (c1 + 6 c2) / 7 right of it, and the plain
+    region colour one texel further away."""
+    W, H, b = 128, 64, 32
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    z1, z2 = _z_for_radius(orc, lens, W, 8.0), _z_for_radius(orc, lens, W, 6.0)
+    c1, c2 = np.array([0.9, 0.2, 0.4], np.float32), np.array([0.1, 0.7, 0.3], np.float32)
+    gb = _two_region_gbuffer(orc, W, H, b, z1, z2, c1, c2)
+    sc = orc.OracleScene(plane_scene(z1))
+    out = orc.render_frame(sc, synth.look_camera((0, 0, 0), 0, 0, W, H), lens, synth.Params(), gb)
+    r = out["colr"][..., 3]
+    np.testing.assert_allclose(r[:, :b], -8.0, rtol=0, atol=1e-4)           # near field: negative radius
+    np.testing.assert_allclose(r[:, b:], -6.0, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(out["colr"][:, :b, :3], np.broadcast_to(c1, (H // 2, b, 3)), rtol=0, atol=1e-6)
+    pre = out["pre"][..., :3].astype(np.float64)
+    want = {b - 2: c1, b - 1: (6.0 * c1 + c2) / 7.0, b: (c1 + 6.0 * c2) / 7.0, b + 1: c2}
+    for x, v in want.items():
+        np.testing.assert_allclose(pre[:, x], np.broadcast_to(v, (H // 2, 3)), rtol=0, atol=2e-5)
+
+
+def _z_far_for_radius(orc, lens, W, r):
+    """Far-field depth whose half-res CoC radius is r (CoC rising with depth
+    beyond the focus)."""
+    lo, hi = lens.focus, 1e6
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if orc.coc(lens, W, mid) / 4.0 < r:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _gather_taps(orc, lens, params, x, y, Rn, hw, hh):
+    """Columns, rows and ring numbers (0 = centre .. 4 = rim) of the 81 taps
+    of half-res pixel (x, y) at radius Rn, nearest texel."""
+    ox, oy, frac = orc.gather_rings(lens, params)
+    sx = np.float32(x) + ox * np.float32(Rn)
+    sy = np.float32(y) + oy * np.float32(Rn)
+    col = np.clip(np.floor(sx + np.float32(0.5)).astype(int), 0, hw - 1)
+    row = np.clip(np.floor(sy + np.float32(0.5)).astype(int), 0, hh - 1)
+    return col, row, np.round(frac * 4).astype(int)
+
+
+def _luma(c):
+    return c @ np.array([0.2126, 0.7152, 0.0722])
+
+
+def test_gather_foreground_bleeds_over_a_sharp_background(orc):
+    """A4 at differing CoCs and depths: eq. (1) as scatter-as-gather.  Left of
+    half-res column b a near, strongly blurred foreground (radius 8, bright:
+    luma above l_spec), right of it a sharp background (radius 0.4) more than
+    the depth range behind it.  For a background centre next to the step
+    (dilated radius 8: rings at distances 0, 2, 4, 6, 8), a foreground tap
+    counts when its own radius 8 exceeds its distance (rings 1-3), with
+    sampleAlpha 1 / 8^2; a background tap at the centre's depth counts only
+    at distance 0 (radius 0.4), with sampleAlpha 1 / max(0.4, 1/2)^2 = 4.
+    Colour = (4 c + sum over the foreground taps of f / 64) / (4 + n_f / 64)
+    on the prefiltered colours; the bokeh share is the foreground's weight
+    fraction.  Every pixel of the row agrees."""
+    W, H, b = 128, 64, 32
+    hw, hh = W // 2, H // 2
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    p = synth.Params()
+    z1, z2 = _z_for_radius(orc, lens, W, 8.0), _z_for_radius(orc, lens, W, 0.4)
+    assert z2 - z1 > p.depth_range
+    c1, c2 = np.array([3.0, 2.5, 2.0], np.float32), np.array([0.2, 0.4, 0.3], np.float32)
+    gb = _two_region_gbuffer(orc, W, H, b, z1, z2, c1, c2)
+    out = orc.render_frame(orc.OracleScene(plane_scene(z1)), synth.look_camera((0, 0, 0), 0, 0, W, H), lens, p, gb)
+    r, pre, gat = out["colr"][..., 3], out["pre"][..., :3].astype(np.float64), out["gather"]
+    np.testing.assert_allclose(r[:, :b], -8.0, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(r[:, b:], -0.4, rtol=0, atol=1e-4)
+    assert np.all(out["tile_dil"] == out["tile_dil"].max())
+    Rn = float(out["tile_dil"].max())
+    assert abs(Rn - 8.0) < 1e-4
+    for x in (b, b + 1, b + 3, b + 5):
+        for y in (3, hh // 2, hh - 2):
+            col, row, ring = _gather_taps(orc, lens, p, x, y, Rn, hw, hh)
+            fg = (col < b) & (ring >= 1) & (ring <= 3)
+            w = np.where(fg, 1.0 / 64.0, 0.0)
+            w[ring == 0] = 4.0
+            assert fg.sum() > 0
+            taps = pre[row, col]
+            exp = (w[:, None] * taps).sum(0) / w.sum()
+            np.testing.assert_allclose(gat[y, x, :3], exp, rtol=0, atol=2e-5)
+            share = w[_luma(taps) > p.l_spec].sum() / w.sum()
+            assert abs(gat[y, x, 3] - share) < 2e-5 and 0.0 < share < 1.0
+
+
+def test_gather_background_needs_the_centre_radius(orc):
+    """A4: a background tap counts only where the smaller of its radius and
+    the centre's exceeds its distance.  Left of half-res column b a mildly
+    blurred near foreground (radius 2), right of it a strongly blurred far
+    background (radius 6).  For a foreground centre three or four texels from
+    the step (dilated radius 6: rings at 0, 1.5, 3, 4.5, 6), the background
+    taps on rings 2-3 have radius 6 beyond their distance but the centre's
+    2 is not, so none counts; foreground taps count on rings 0-1 (radius 2 >
+    1.5), which stay left of the step.  Colour = mean of the prefiltered
+    colour over those 9 taps (one sampleAlpha 1/4 for all)."""
+    W, H, b = 256, 64, 64
+    hw, hh = W // 2, H // 2
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    p = synth.Params()
+    z1, z2 = _z_for_radius(orc, lens, W, 2.0), _z_far_for_radius(orc, lens, W, 6.0)
+    c1, c2 = np.array([0.8, 0.3, 0.1], np.float32), np.array([0.1, 0.5, 0.9], np.float32)
+    gb = _two_region_gbuffer(orc, W, H, b, z1, z2, c1, c2)
+    out = orc.render_frame(orc.OracleScene(plane_scene(z1)), synth.look_camera((0, 0, 0), 0, 0, W, H), lens, p, gb)
+    r, pre, gat = out["colr"][..., 3], out["pre"][..., :3].astype(np.float64), out["gather"]
+    np.testing.assert_allclose(r[:, :b], -2.0, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(r[:, b:], 6.0, rtol=0, atol=1e-4)
+    Rn = float(out["tile_dil"].max())
+    assert abs(Rn - 6.0) < 1e-4
+    for x in (b - 3, b - 4):
+        for y in (3, hh // 2):
+            assert out["tile_dil"][y // p.tile, x // p.tile] == Rn             # dilated radius at the centre
+            col, row, ring = _gather_taps(orc, lens, p, x, y, Rn, hw, hh)
+            use = ring <= 1
+            assert np.all(col[use] < b) and np.any((col >= b) & (ring >= 2) & (ring <= 3))
+            exp = pre[row[use], col[use]].mean(0)
+            np.testing.assert_allclose(gat[y, x, :3], exp, rtol=0, atol=2e-5)
