@@ -21,6 +21,24 @@ namespace {
 
 constexpr int kBX = 64, kBY = 4;   // pixel-kernel block: one wave per row
 
+// The dispatcher deals workgroups round-robin to the 8 XCDs (workgroup i to
+// XCD i mod 8), each with its own L2.  xcd_tile renumbers the tiles of a 2-D
+// grid so that XCD x takes one contiguous run of them in row-major order:
+// neighbouring tiles, whose tap footprints overlap, then share one L2 instead
+// of fetching the same halo into several.  A bijection for any grid size, so
+// only the order of the work changes.  Worth it for the wide, uniform-cost
+// gather; kernels whose cost follows the ray mask keep the interleaved order,
+// which spreads expensive regions over all XCDs.
+__device__ inline void xcd_tile(uint32_t &bx, uint32_t &by)
+{
+    const uint32_t gx = gridDim.x, n = gridDim.x * gridDim.y;
+    const uint32_t id = blockIdx.x + blockIdx.y * gx;
+    const uint32_t x = id % 8u, s = id / 8u, per = n / 8u, rem = n % 8u;
+    const uint32_t t = x * per + (x < rem ? x : rem) + s;
+    bx = t % gx;
+    by = t / gx;
+}
+
 __device__ inline float4 ld_rgba(const void *p, int fmt, size_t i)
 {
     if (fmt == DOF_RGBA32F) return reinterpret_cast<const float4 *>(p)[i];
@@ -383,7 +401,10 @@ __device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const 
 
 __global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings, Planes P)
 {
-    b_gather(fc, rings, P, blockIdx.x, blockIdx.y);
+    // every pixel costs the same 81 taps, so bands per XCD stay balanced
+    uint32_t bx, by;
+    xcd_tile(bx, by);
+    b_gather(fc, rings, P, bx, by);
 }
 
 __global__ __launch_bounds__(kBX *kBY) void kb_gather(const Job *__restrict__ jobs, int njobs)
