@@ -48,6 +48,7 @@ struct WRay {
     int kx, ky, kz;
     float sx, sy, sz;
     float ix, iy, iz;   // slab reciprocals (zero components replaced by 1e-20)
+    float clx, cly, clz, chx, chy, chz;   // slab offsets of the low and high planes (box_hit)
 };
 
 // The watertight test's axes: kz the largest direction component, kx and ky
@@ -59,6 +60,32 @@ __device__ inline void wray_axes(const float d[3], int &kx, int &ky, int &kz)
     kx = kz + 1 == 3 ? 0 : kz + 1;
     ky = kx + 1 == 3 ? 0 : kx + 1;
     if (pick3(d[0], d[1], d[2], kz) < 0.0f) { int t = kx; kx = ky; ky = t; }
+}
+
+// A plane p meets the ray at fma(p, 1/d, c) with c = -o/d.  c carries an
+// absolute rounding error of at most 2^-24 |c|; it is moved outward by
+// max(2^-21 |c|, 2^-30 |1/d|) (down for the entry plane, up for the exit
+// plane, which one is which following the sign of 1/d), so the remaining
+// errors are relative to the distance and covered by box_hit's exit margin.
+// The second term widens each slab by 2^-30 in position: an axis the ray is
+// parallel to (d = 0, reciprocal 1e20) then never culls a box whose slab holds
+// the origin, faces included.  Needs the origin and the reciprocals; every
+// construction of a WRay ends with it.
+__device__ inline float slab_offset(float o, float inv, bool entry_if_positive)
+{
+    const float c = -(o * inv);
+    const float e = fmaxf(fabsf(c) * 4.76837158203125e-07f, fabsf(inv) * 9.31322574615478515625e-10f);   // 2^-21, 2^-30
+    return (inv > 0.0f) == entry_if_positive ? c - e : c + e;
+}
+
+__device__ inline void slab_offsets(WRay &r)
+{
+    r.clx = slab_offset(r.o0, r.ix, true);
+    r.cly = slab_offset(r.o1, r.iy, true);
+    r.clz = slab_offset(r.o2, r.iz, true);
+    r.chx = slab_offset(r.o0, r.ix, false);
+    r.chy = slab_offset(r.o1, r.iy, false);
+    r.chz = slab_offset(r.o2, r.iz, false);
 }
 
 __device__ inline WRay make_wray(const float o[3], const float d[3])
@@ -75,6 +102,7 @@ __device__ inline WRay make_wray(const float o[3], const float d[3])
     r.ix = 1.0f / (d[0] != 0.0f ? d[0] : 1e-20f);
     r.iy = 1.0f / (d[1] != 0.0f ? d[1] : 1e-20f);
     r.iz = 1.0f / (d[2] != 0.0f ? d[2] : 1e-20f);
+    slab_offsets(r);
     return r;
 }
 
@@ -116,9 +144,9 @@ __device__ inline bool tri_hit(const WRay &r, float4 v0, float4 v1, float4 v2, f
 __device__ inline bool box_hit(const WRay &r, float lx, float hx, float ly, float hy, float lz, float hz, float limit,
                                float &tenter)
 {
-    float t0x = (lx - r.o0) * r.ix, t1x = (hx - r.o0) * r.ix;
-    float t0y = (ly - r.o1) * r.iy, t1y = (hy - r.o1) * r.iy;
-    float t0z = (lz - r.o2) * r.iz, t1z = (hz - r.o2) * r.iz;
+    float t0x = fmaf(lx, r.ix, r.clx), t1x = fmaf(hx, r.ix, r.chx);
+    float t0y = fmaf(ly, r.iy, r.cly), t1y = fmaf(hy, r.iy, r.chy);
+    float t0z = fmaf(lz, r.iz, r.clz), t1z = fmaf(hz, r.iz, r.chz);
     float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
     float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.00000095367431640625f;
     tenter = tn;
@@ -291,6 +319,7 @@ __device__ inline void get_ray(const float4 *rec0, const float4 *rec1, const flo
     wray_axes(d, w.kx, w.ky, w.kz);
     w.sx = b.z; w.sy = b.w; w.sz = c.x;
     w.ix = c.y; w.iy = c.z; w.iz = c.w;
+    slab_offsets(w);
 }
 
 // The traversal's result of a lens ray: leaf of the closest hit (~0u: none)
