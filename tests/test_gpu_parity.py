@@ -162,6 +162,38 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
     assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
 
 
+
+def test_rays_lying_on_a_box_face(env, orc):
+    """Rays parallel to an axis (a direction component of exactly 0) that lie
+    in a face of a leaf's box and cross the triangle's edge in that face: the
+    watertight test counts the edge hit, so the box test must not cull the
+    leaf.  Faces at the high and the low end of z and x.  GPU, oracle BVH and
+    oracle brute force agree on every id and distance."""
+    torch, dof = env["torch"], env["dof"]
+    tri = np.array([
+        [0, 0, 2, 2, 0, 2, 1, 0, 1],        # edge in z = 2, the top face of its box
+        [5, 5, 5, 6, 5, 5, 5, 6, 6],        # elsewhere, so the root box is larger than the leaves
+        [4, 0, 1, 6, 0, 1, 5, 0, 2],        # edge in z = 1, the bottom face
+        [8, 0, 0, 8, 0, 1, 7, 0, 0.5],      # edge in x = 8, the high x face
+        [10, 0, 0, 10, 0, 1, 11, 0, 0.5],   # edge in x = 10, the low x face
+    ], np.float32)
+    sc = synth.Scene(tri, np.full((len(tri), 3), 0.5, np.float32))
+    osc = orc.OracleScene(sc)
+    osc.build_bvh()
+    gs = dof.Scene(sc)
+    gs.build_bvh()
+    o = np.array([[1, -1, 2], [1, 1, 2], [0.5, -3, 2], [5, -1, 1], [8, -1, 0.5], [8, 2, 0.5], [10, -1, 0.5]],
+                 np.float32)
+    d = np.array([[0, 1, 0], [0, -1, 0], [0, 1, 0], [0, 1, 0], [0, 1, 0], [0, -1, 0], [0, 1, 0]], np.float32)
+    hb, tb = orc.closest_hit(osc, o, d, use_bvh=True)
+    ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
+    assert np.array_equal(ho, [0, 0, 0, 2, 3, 3, 4]) and np.array_equal(to, [1, 1, 3, 1, 1, 2, 1])
+    assert np.array_equal(hb, ho) and np.array_equal(tb, to)
+    hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    assert np.array_equal(hg.cpu().numpy(), ho)
+    assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
+
+
 def caterpillar_scene():
     """Triangles whose Morton codes are 0, 2^k (k = 0..62) and 2^63 - 1: the
     radix tree is a chain about 63 deep.  Every triangle is huge and they all
