@@ -1349,8 +1349,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
      * from eq. (8), taps whose CoC radius is below their distance rejected,
      * neighbourhood mean blended in by b of eq. (5).  Invalid neighbours are
      * replaced by the centre in the median and carry zero weight in the
-     * validity-weighted mip chain.  Where ray-traced and empty pixels mix,
-     * that weighting is checked only by invariants (parity unpinned there). */
+     * validity-weighted mip chain. */
     for (int y = 0; y < hh; y++)
         for (int x = 0; x < hw; x++) {
             size_t i = (size_t)y * hw + x;

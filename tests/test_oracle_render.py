@@ -1133,3 +1133,73 @@ def test_gather_background_needs_the_centre_radius(orc):
             assert np.all(col[use] < b) and np.any((col >= b) & (ring >= 2) & (ring <= 3))
             exp = pre[row[use], col[use]].mean(0)
             np.testing.assert_allclose(gat[y, x, :3], exp, rtol=0, atol=2e-5)
+
+
+def test_reconstruction_mips_weight_by_validity(orc):
+    """A13 where ray-traced and empty pixels mix.  Only even half-res columns
+    are ray traced (their G-buffer depth is a near plane, out of focus; odd
+    columns sit at the focus distance, and with eq. (2)'s scale s = 0 only
+    out-of-focus near pixels get a ray), and the ray-traced colour is linear
+    in x, f(x), put in through the history as in the b > 0 pin above.  A mip
+    texel of level L >= 1 then averages valid children at columns
+    2^L X, 2^L X + 2, ...: its validity is 1/2 and its validity-normalised
+    colour f(2^L X + 2^(L-1) - 1), so every bilinear sample at a tap's mip
+    coordinates reads f(x_tap - 1/2) with weight 1/2 on both levels: the
+    validity weighting moves the field by half a pixel.  With b at its cap,
+    the median equal to the centre (its empty neighbours are replaced by the
+    centre) and only taps on ray-traced texels that pass the CoC rejection
+    counted: reconstruction = f(x) + b * slope * (R * mean(ox over valid
+    taps) - 1/2) at every even column away from the borders."""
+    W, H = 128, 96
+    hw, hh = W // 2, H // 2
+    np_ = hw * hh
+    lens = synth.Lens(focal=0.15, fnum=1.0, focus=5.0)
+    depth = np.full((H, W), lens.focus, np.float32)
+    for X in range(0, hw, 2):
+        depth[:, 2 * X:2 * X + 2] = 2.0
+    nrm = np.zeros((H, W, 4), np.float32)
+    nrm[..., 2] = -1.0
+    gb = orc.GBuffer(np.full((H, W, 4), 0.5, np.float32), depth, nrm)
+    sc = orc.OracleScene(plane_scene(2.0))
+    sc.build_bvh()
+    cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
+    p = synth.Params(s=0.0)
+    f0 = orc.render_frame(sc, cam, lens, p, gb)
+    hist = f0["hist_out"].copy()
+    X = np.arange(hw, dtype=np.float32)
+    A = hist[:4 * np_].reshape(hh, hw, 4)
+    A[..., :3] = (np.float32(0.2) + np.float32(0.01) * X)[None, :, None]
+    A[..., 3] = 1.0
+    hist[4 * np_ + 3:8 * np_:4] = 1.0                     # age: the history is valid everywhere
+    C = hist[8 * np_:12 * np_].reshape(hh, hw, 4)
+    C[..., 2] = 0.0
+    C[..., 3] = 1.0
+    f1 = orc.render_frame(sc, dataclasses.replace(cam, frame=1), lens, p, gb, hist_in=hist, prev_cam=cam,
+                          prev_lens=lens)
+    traced = f1["temporal"][0][..., 3] > 0
+    assert np.array_equal(traced, np.broadcast_to(X % 2 == 0, (hh, hw)))
+    med, rec = f1["rtmed"], f1["recon"]
+    even = med[:, 0::2, 0]
+    step = np.diff(even, axis=1).mean() / 2.0                          # slope per half-res pixel
+    assert abs(step) > 1e-3 and np.abs(np.diff(even, axis=1) - 2 * step).max() < 1e-5
+    bb = np.clip(f1["var_blur"] * p.var_recon_w, 0.0, p.b_max)
+    ct = f1["temporal"][1][..., 0]
+    lod = np.clip(ct * p.lod_scale, 0.0, p.lod_max)
+    assert bb[traced].min() == np.float32(p.b_max) and lod[traced].min() > 1.0   # b capped; mip levels >= 1
+    R = float(ct[traced].max()) * 0.25
+    m = int(math.ceil(R)) + 9
+    ox, oy, frac = orc.gather_rings(synth.Lens(), synth.Params())
+    checked = 0
+    for y in range(m, hh - m):
+        for x in range(m + (m % 2), hw - m, 2):
+            Rr = np.float32(ct[y, x]) * np.float32(0.25)
+            sx = np.float32(x) + ox * Rr
+            sy = np.float32(y) + oy * Rr
+            ix = np.floor(sx + np.float32(0.5)).astype(int)
+            iy = np.floor(sy + np.float32(0.5)).astype(int)
+            valid = traced[iy, ix] & ~(ct[iy, ix] * np.float32(0.25) < Rr * frac)
+            shift = float(Rr) * (ox.astype(np.float64) * valid).sum() / valid.sum() - 0.5
+            exp = med[y, x, :3] + bb[y, x] * step * shift
+            np.testing.assert_allclose(rec[y, x, :3], exp, rtol=0, atol=2e-5)
+            checked += 1
+    assert checked > 100
