@@ -1246,9 +1246,7 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
      * the mean far hit position (else the mean of valid 3x3 neighbours),
      * colour and CoC merged by the hit ratio (the latest one during motion),
      * luminance moments give the variance (after SVGF).  Planes: T0 c_rt rgb
-     * + validity, T1 c_t, h_use, variance, 0.  The 3x3 neighbour fill of a
-     * missing far position is checked only by invariants (parity unpinned
-     * there). */
+     * + validity, T1 c_t, h_use, variance, 0. */
     float *T0 = tmp, *T1 = tmp + 4 * np;
     const float ah = motion ? p->alpha_motion : p->alpha;
     for (int y = 0; y < hh; y++)

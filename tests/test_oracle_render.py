@@ -1203,3 +1203,57 @@ def test_reconstruction_mips_weight_by_validity(orc):
             np.testing.assert_allclose(rec[y, x, :3], exp, rtol=0, atol=2e-5)
             checked += 1
     assert checked > 100
+
+
+def test_temporal_far_position_filled_from_neighbours(orc):
+    """A12's fill of a missing far hit position.  Far-field strips (z = 7,
+    beyond the focus ramp) each exactly one half-res pixel wide cover the
+    even columns, with sky between them; a small aperture (f/4) keeps every
+    pixel's rays inside its own footprint, so even columns hit only strip
+    and odd columns only sky.  A miss adds no far position, so an odd pixel
+    has none and takes the mean of its valid 3 x 3 neighbours' (the six on
+    the even columns beside it), which lies on the strip plane over its own
+    centre and so, with a static camera, reprojects onto the pixel itself.
+    With the history's hit ratio 0 (the merge then keeps the far field) its
+    temporal colour is sky + 0.95 (B[y, x] - sky) for a seeded random far
+    history B; without the fill it would be the sky colour.  The camera sits
+    away from the world origin, so a position pulled towards the origin (a
+    fill that counted empty neighbours as zeros) lands on another texel."""
+    W, H = 128, 96
+    hw, hh = W // 2, H // 2
+    np_ = hw * hh
+    lens = synth.Lens(focal=0.15, fnum=4.0, focus=5.0)
+    tanx = (lens.sensor * (lens.focus - lens.focal)) / (2.0 * lens.focal * lens.focus)
+    z = 7.0
+    c0 = (0.4, 0.3, -2.0)                                              # camera position
+    quads = []
+    for X in range(0, hw, 2):
+        x0 = c0[0] + (X * 2.0 / hw - 1.0) * tanx * z
+        x1 = c0[0] + ((X + 1) * 2.0 / hw - 1.0) * tanx * z
+        zw = c0[2] + z
+        quads.append(synth.quad((x0, -50.0, zw), (x0, 50.0, zw), (x1, 50.0, zw), (x1, -50.0, zw)))
+    v = np.concatenate(quads).astype(np.float32)
+    sky = (0.55, 0.70, 0.95)
+    sc = orc.OracleScene(synth.Scene(v, np.full((len(v), 3), 0.5, np.float32), sky=sky))
+    sc.build_bvh()
+    cam = synth.look_camera(c0, 0, 0, W, H)
+    gb = _flat_gbuffer(orc, W, H, z, np.full((H, W, 4), 0.5, np.float32))
+    p = synth.Params(mask_mode=synth.MASK_ALL, m=4)
+    hist = orc.history_zeros(W, H)
+    B = hist[4 * np_:8 * np_].reshape(hh, hw, 4)
+    B[..., :3] = np.random.default_rng(11).uniform(0.0, 1.0, (hh, hw, 3))
+    B[..., 3] = 1.0                                                     # age
+    f1 = orc.render_frame(sc, dataclasses.replace(cam, frame=1), lens, p, gb, hist_in=hist, prev_cam=cam,
+                          prev_lens=lens)
+    res = f1["resolve"]
+    odd = np.broadcast_to(np.arange(hw) % 2 == 1, (hh, hw))
+    assert np.all(res[3][..., 3][~odd] == 1.0) and np.all(res[3][..., 3][odd] == 0.0)   # own far position or none
+    assert np.all(res[1][..., 3] == 0.0)                                # hit ratio 0: no near hits
+    np.testing.assert_allclose(res[1][odd][:, :3], np.broadcast_to(sky, (odd.sum(), 3)), rtol=0, atol=1e-6)
+    T0 = f1["temporal"][0]
+    inner = np.zeros((hh, hw), bool)
+    inner[1:-1, 1:-1] = True
+    sel = odd & inner
+    exp = np.asarray(sky, np.float32) + (B[..., :3] - np.asarray(sky, np.float32)) * np.float32(0.95)
+    np.testing.assert_allclose(T0[sel][:, :3], exp[sel], rtol=0, atol=2e-6)
+    assert sel.sum() > 1000
