@@ -1120,41 +1120,191 @@ __device__ inline void recon_taps(int x, int y, float Rr, float fl, float sc0, f
     }
 }
 
+constexpr int kReconLds = 2496;   // mip texels a block can stage in LDS (39 KB: 4 blocks per CU)
+
+// bilinear4 on texels staged in LDS: t holds the rows b[2]..b[3] and columns
+// b[0]..b[1] of one mip level, bw = b[1] - b[0] + 1 wide.  The box holds every
+// index the block's taps reach after the clamp to the image (see b_recon), so
+// clamping into the box gives the same texels as clamping into the image; it
+// also keeps every LDS access inside the staged box.
+__device__ inline float4 bilinear4_lds(const float4 *t, const int *b, int bw, float x, float y)
+{
+    float x0f = floorf(x), y0f = floorf(y);
+    float fx = x - x0f, fy = y - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    int x1 = clampi(x0 + 1, b[0], b[1]), y1 = clampi(y0 + 1, b[2], b[3]);
+    x0 = clampi(x0, b[0], b[1]);
+    y0 = clampi(y0, b[2], b[3]);
+    const float4 *r0 = t + (y0 - b[2]) * bw - b[0], *r1 = t + (y1 - b[2]) * bw - b[0];
+    float4 a = r0[x0], bq = r0[x1];
+    float4 c = r1[x0], d = r1[x1];
+    float4 top, bot, o;
+    top.x = a.x + (bq.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
+    top.y = a.y + (bq.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
+    top.z = a.z + (bq.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
+    top.w = a.w + (bq.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
+    return o;
+}
+
+// bilinear4_lds where the caller has shown the lookup inside the image (as
+// for bilinear4_in): no clamp changes an index, so none is applied.
+__device__ inline float4 bilinear4_lds_in(const float4 *t, const int *b, int bw, float x, float y)
+{
+    const int x0 = (int)x, y0 = (int)y;
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y);
+    const float4 *r0 = t + (__mul24(y0 - b[2], bw) + (x0 - b[0])), *r1 = r0 + bw;
+    float4 a = r0[0], bq = r0[1];
+    float4 c = r1[0], d = r1[1];
+    float4 top, bot, o;
+    top.x = a.x + (bq.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
+    top.y = a.y + (bq.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
+    top.z = a.z + (bq.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
+    top.w = a.w + (bq.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
+    return o;
+}
+
+// The taps of one pixel on mip levels staged in LDS (same order and
+// arithmetic as recon_taps; Inside as there).
+template <bool Inside>
+__device__ inline void recon_taps_lds(int x, int y, float Rr, float fl, float sc0, float sc1, int hw, int hh,
+                                      const float4 *t0, const int *b0, int bw0, const float4 *t1, const int *b1,
+                                      int bw1, const Rings &rings, const float2 *tap, float &a0, float &a1,
+                                      float &a2, float &a3, float &sh, int &na)
+{
+#pragma unroll 3
+    for (int k = 0; k < kRingTaps; ++k) {
+        float dist = Rr * rings.frac[k];
+        float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
+        size_t j;
+        if (Inside)
+            j = (uint32_t)(__umul24((int)(sy + 0.5f), hw) + (int)(sx + 0.5f));
+        else
+            j = (size_t)nearest_idx(sy, hh) * hw + nearest_idx(sx, hw);
+        const float2 tj = tap[j];
+        const bool ok = tj.x * 0.25f >= dist;
+        const float u0 = (sx + 0.5f) * sc0 - 0.5f, v0 = (sy + 0.5f) * sc0 - 0.5f;
+        const float u1 = (sx + 0.5f) * sc1 - 0.5f, v1 = (sy + 0.5f) * sc1 - 0.5f;
+        float4 s0 = Inside ? bilinear4_lds_in(t0, b0, bw0, u0, v0) : bilinear4_lds(t0, b0, bw0, u0, v0);
+        float4 s1 = Inside ? bilinear4_lds_in(t1, b1, bw1, u1, v1) : bilinear4_lds(t1, b1, bw1, u1, v1);
+        a0 = a0 + (ok ? lerp1(s0.x, s1.x, fl) : 0.0f);
+        a1 = a1 + (ok ? lerp1(s0.y, s1.y, fl) : 0.0f);
+        a2 = a2 + (ok ? lerp1(s0.z, s1.z, fl) : 0.0f);
+        a3 = a3 + (ok ? lerp1(s0.w, s1.w, fl) : 0.0f);
+        sh = sh + (ok ? tj.y : 0.0f);
+        na += ok ? 1 : 0;
+    }
+}
+
+// Index range that the bilinear lookups of taps between coordinates lo and hi
+// (one axis, already at the level's scale sc) reach after the clamp to
+// [0, n - 1]: the coordinate map and floor are monotone, so the two ends bound
+// every tap.
+__device__ inline void mip_span(float lo, float hi, float sc, int n, int &a, int &b)
+{
+    a = clampi((int)floorf((lo + 0.5f) * sc - 0.5f), 0, n - 1);
+    b = clampi((int)floorf((hi + 0.5f) * sc - 0.5f) + 1, 0, n - 1);
+}
+
 __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
 {
+    // The block's mip footprint: per level, the index box of every bilinear
+    // lookup its pixels' taps make (taps lie within R of the pixel on both
+    // axes), staged in LDS when the boxes fit; else the taps read the mips
+    // in global memory.
+    __shared__ float4 tex[kReconLds];
+    __shared__ int box[4][4];   // per level: first and last column, first and last row
+    __shared__ int base[5];     // per level: first LDS texel; [4]: texels in all
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    if (tid < 4) {
+        box[tid][0] = 0x7fffffff; box[tid][1] = -1;
+        box[tid][2] = 0x7fffffff; box[tid][3] = -1;
+    }
+    __syncthreads();
     const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
     const int hw = fc.hw, hh = fc.hh;
-    if (x >= hw || y >= hh) return;
-    const size_t i = (size_t)y * hw + x;
-    if (!(P.T0[i].w > 0.0f)) {
+    const bool in = x < hw && y < hh;
+    const size_t i = in ? (size_t)y * hw + x : 0;
+    const bool traced = in && P.T0[i].w > 0.0f;
+    float ct = 0.0f, hu = 0.0f, Rr = 0.0f, fl = 0.0f, sc0 = 1.0f, sc1 = 1.0f;
+    int L0 = 0, L1 = 0;
+    if (traced) {
+        const float4 t1 = P.T1[i];
+        ct = t1.x;
+        hu = t1.y;
+        Rr = fmin_cs(ct * 0.25f, fc.r_max);
+        const float lod = clampf(ct * fc.lod_scale, 0.0f, fc.lod_max);
+        L0 = (int)floorf(lod);
+        const int Lmax = fc.lod_levels;
+        if (L0 > Lmax) L0 = Lmax;
+        L1 = L0 < Lmax ? L0 + 1 : Lmax;
+        fl = lod - (float)L0;
+        for (int L = 0; L < L0; ++L) sc0 = sc0 * 0.5f;
+        for (int L = 0; L < L1; ++L) sc1 = sc1 * 0.5f;
+        const float lx = (float)x + (-Rr), hx = (float)x + Rr, ly = (float)y + (-Rr), hy = (float)y + Rr;
+        int c0, c1, r0, r1;
+        mip_span(lx, hx, sc0, fc.mw[L0], c0, c1);
+        mip_span(ly, hy, sc0, fc.mh[L0], r0, r1);
+        atomicMin(&box[L0][0], c0); atomicMax(&box[L0][1], c1);
+        atomicMin(&box[L0][2], r0); atomicMax(&box[L0][3], r1);
+        mip_span(lx, hx, sc1, fc.mw[L1], c0, c1);
+        mip_span(ly, hy, sc1, fc.mh[L1], r0, r1);
+        atomicMin(&box[L1][0], c0); atomicMax(&box[L1][1], c1);
+        atomicMin(&box[L1][2], r0); atomicMax(&box[L1][3], r1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        for (int L = 0; L < 4; ++L) {
+            base[L] = n;
+            if (box[L][1] >= box[L][0]) n += (box[L][1] - box[L][0] + 1) * (box[L][3] - box[L][2] + 1);
+        }
+        base[4] = n;
+    }
+    __syncthreads();
+    const bool staged = base[4] <= kReconLds;
+    if (staged) {
+        for (int L = 0; L < 4; ++L) {
+            if (box[L][1] < box[L][0]) continue;
+            const int bw = box[L][1] - box[L][0] + 1, cnt = bw * (box[L][3] - box[L][2] + 1);
+            const float4 *src = P.mips + fc.moff[L];
+            for (int e = tid; e < cnt; e += kBX * kBY) {
+                const int r = e / bw, c = e - r * bw;
+                tex[base[L] + e] = src[(size_t)(box[L][2] + r) * fc.mw[L] + box[L][0] + c];
+            }
+        }
+    }
+    __syncthreads();
+    if (!in) return;
+    if (!traced) {
         P.recon[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
-    const float4 t1 = P.T1[i];
-    const float ct = t1.x, hu = t1.y;
-    const float Rr = fmin_cs(ct * 0.25f, fc.r_max);
-    const float lod = clampf(ct * fc.lod_scale, 0.0f, fc.lod_max);
-    int L0 = (int)floorf(lod);
-    const int Lmax = fc.lod_levels;
-    if (L0 > Lmax) L0 = Lmax;
-    const int L1 = L0 < Lmax ? L0 + 1 : Lmax;
-    const float fl = lod - (float)L0;
-    float sc0 = 1.0f, sc1 = 1.0f;
-    for (int L = 0; L < L0; ++L) sc0 = sc0 * 0.5f;
-    for (int L = 0; L < L1; ++L) sc1 = sc1 * 0.5f;
-    const float4 *mip0 = P.mips + fc.moff[L0], *mip1 = P.mips + fc.moff[L1];
-    const int w0 = fc.mw[L0], h0 = fc.mh[L0], w1 = fc.mw[L1], h1 = fc.mh[L1];
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, sh = 0.0f;
     int na = 0;
-    // The interior path is taken by a whole wave when every lane's taps stay
-    // inside all planes it reads (same arithmetic, no clamps).
+    const float4 *mip0 = P.mips + fc.moff[L0], *mip1 = P.mips + fc.moff[L1];
+    const int w0 = fc.mw[L0], h0 = fc.mh[L0], w1 = fc.mw[L1], h1 = fc.mh[L1];
+    // The interior paths are taken by a whole wave when every lane's taps
+    // stay inside all planes it reads (same arithmetic, no clamps).
     const bool inside = hw < (1 << 24) && hh < (1 << 24) && taps_inside(x, Rr, hw) && taps_inside(y, Rr, hh) &&
                         mip_taps_inside(x, Rr, sc0, w0) && mip_taps_inside(y, Rr, sc0, h0) &&
                         mip_taps_inside(x, Rr, sc1, w1) && mip_taps_inside(y, Rr, sc1, h1);
-    if (__ballot(!inside) == 0ull)
-        recon_taps<true>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh, na);
-    else
-        recon_taps<false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh, na);
+    const bool all_inside = __ballot(!inside) == 0ull;
+    if (staged) {
+        const int bw0 = box[L0][1] - box[L0][0] + 1, bw1 = box[L1][1] - box[L1][0] + 1;
+        if (all_inside)
+            recon_taps_lds<true>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], box[L0], bw0, tex + base[L1], box[L1],
+                                 bw1, rings, P.tap, a0, a1, a2, a3, sh, na);
+        else
+            recon_taps_lds<false>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], box[L0], bw0, tex + base[L1], box[L1],
+                                  bw1, rings, P.tap, a0, a1, a2, a3, sh, na);
+    } else {
+        if (all_inside)
+            recon_taps<true>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh,
+                             na);
+        else
+            recon_taps<false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh,
+                              na);
+    }
     const float4 med = P.rtmed[i];
     float nb0 = a3 > 0.0f ? a0 / a3 : med.x, nb1 = a3 > 0.0f ? a1 / a3 : med.y, nb2 = a3 > 0.0f ? a2 / a3 : med.z;
     float hnb = na > 0 ? sh / (float)na : hu;
