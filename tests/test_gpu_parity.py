@@ -326,6 +326,29 @@ def test_mask_modes_parity(env, orc, frame0, mode, m):
     compare_frame(o, d, f"mask mode {mode}")
 
 
+def test_reconstruction_global_fallback_parity(env, orc):
+    """Blocks whose mip footprint does not fit the reconstruction's LDS
+    staging buffer read the mips in global memory.  A wide aperture (bar
+    CoCs near 70 px) with lod_scale 0.01 keeps tap radii of 12+ half-res px on
+    mip level 0, so such blocks need more than 2,700 texels, beyond the 2,496
+    staged; other blocks of the same frames stay staged.  Two frames, the
+    second on the first's history, with a variance weight that puts the
+    blend factor b at its cap, so the taps decide the result."""
+    lens = dataclasses.replace(env["lens"], focal=0.15, fnum=1.0)
+    p = dataclasses.replace(env["params"], lod_scale=0.01, mask_mode=synth.MASK_ALL, var_recon_w=1e6)
+    gb = orc.gbuffer(env["osc"], env["cam"], lens)
+    o0, d0 = run_pair(env, orc, env["cam"], lens, p, gb)
+    compare_frame(o0, d0, "recon fallback, frame 0")
+    cam1 = dataclasses.replace(env["cam"], frame=1)
+    o1, d1 = run_pair(env, orc, cam1, lens, p, gb, hist_in=o0["hist_out"], prev_cam=env["cam"], prev_lens=lens)
+    ct = o1["temporal"][1][..., 0]
+    traced = o1["temporal"][0][..., 3] > 0
+    big = traced & (ct * p.lod_scale < 1.0) & (ct * 0.25 >= 12.0)
+    assert big.sum() > 50                                               # level-0 radii that overflow a block
+    bb = np.clip(o1["var_blur"] * p.var_recon_w, 0.0, p.b_max)
+    assert (bb[big] > 0.5).mean() > 0.9                                 # the taps decide the result there
+    compare_frame(o1, d1, "recon fallback, frame 1")
+
 @pytest.mark.parametrize("polygon", [0, 1])
 def test_hexagon_aperture_and_ragged_size(env, orc, polygon):
     """6-blade aperture at a size that is not a multiple of any tile
