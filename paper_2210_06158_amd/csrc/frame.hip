@@ -785,7 +785,7 @@ __global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict_
 // range (a pixel's rays follow each other in queue order), which the wave
 // stages into LDS in chunks with coalesced loads; each lane then sums its
 // pixel's rays from LDS in ray order, as the single-thread loop would.
-constexpr int kResolveChunk = 512;
+constexpr int kResolveChunk = 256;
 
 __device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
                                  const uint32_t bx, const uint32_t by)
