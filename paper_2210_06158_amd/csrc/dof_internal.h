@@ -232,7 +232,76 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
 // the ray records of every thin-lens ray of the frame (after the compaction)
 hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
 // hit record, distance, shaded colour and position of every ray (after the traversal)
-hipError_t launch_shade(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
+// ---------------------------------------------------------------- A11 resolve, shared
+
+// One wave per 64 consecutive queue entries.  Their rays are one contiguous
+// range (a pixel's rays follow each other in queue order), which the wave
+// stages into LDS in chunks: fill(c0, c1, col, pos, hit) writes rays
+// [c0, c1) (colour with view depth, hit position, hit id) with the 64 lanes
+// sharing the work; each lane then sums its pixel's rays from LDS in ray
+// order, as the single-thread loop would.
+constexpr int kResolveChunk = 256;
+
+template <class Fill>
+__device__ inline void resolve_block(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
+                                     const uint32_t bx, Fill fill)
+{
+    __shared__ float4 s_col[kResolveChunk], s_pos[kResolveChunk];
+    __shared__ int32_t s_hit[kResolveChunk];
+    const uint32_t masked = P.counters[kCntMasked];
+    const uint32_t j0 = bx * 64;
+    if (j0 >= masked) return;
+    const uint32_t j = j0 + threadIdx.x;
+    const bool have = j < masked;
+    uint32_t q = 0, base = 0;
+    int n = 0;
+    if (have) {
+        q = P.queue[j];
+        n = mask[q];
+        base = P.ray_base[j];
+    }
+    const uint32_t jl = min(j0 + 63u, masked - 1u);
+    const uint32_t r0 = P.ray_base[j0], r1 = P.ray_base[jl] + mask[P.queue[jl]];
+    float N = 0.0f, sn0 = 0.0f, sn1 = 0.0f, sn2 = 0.0f, sf0 = 0.0f, sf1 = 0.0f, sf2 = 0.0f;
+    float scn = 0.0f, scf = 0.0f, fp0 = 0.0f, fp1 = 0.0f, fp2 = 0.0f, fw = 0.0f;
+    for (uint32_t c0 = r0; c0 < r1; c0 += kResolveChunk) {
+        const uint32_t c1 = min(c0 + (uint32_t)kResolveChunk, r1);
+        fill(c0, c1, s_col, s_pos, s_hit);
+        __syncthreads();
+        const uint32_t kb = max(base, c0), ke = min(base + (uint32_t)n, c1);
+        for (uint32_t r = kb; r < ke; ++r) {
+            const float4 c = s_col[r - c0];
+            const bool hit = s_hit[r - c0] >= 0;
+            float w = hit ? sat(0.5f + (fc.d - c.w) / fc.ramp) : 0.0f;
+            float om = 1.0f - w;
+            float cz = coc_px(fc.cock, fc.d, c.w);
+            N = N + w;
+            sn0 = sn0 + w * c.x; sf0 = sf0 + om * c.x;
+            sn1 = sn1 + w * c.y; sf1 = sf1 + om * c.y;
+            sn2 = sn2 + w * c.z; sf2 = sf2 + om * c.z;
+            scn = scn + w * cz;
+            scf = scf + om * cz;
+            if (hit) {
+                const float4 p = s_pos[r - c0];
+                fp0 = fp0 + om * p.x;
+                fp1 = fp1 + om * p.y;
+                fp2 = fp2 + om * p.z;
+                fw = fw + om;
+            }
+        }
+        __syncthreads();
+    }
+    if (!have) return;
+    const float nf = (float)n - N;
+    const bool hn = N > 0.0f, hf = nf > 0.0f, hp = fw > 0.0f;
+    P.R0[q] = make_float4(hn ? sn0 / N : 0.0f, hn ? sn1 / N : 0.0f, hn ? sn2 / N : 0.0f, N);
+    P.R1[q] = make_float4(hf ? sf0 / nf : 0.0f, hf ? sf1 / nf : 0.0f, hf ? sf2 / nf : 0.0f, N / (float)n);
+    P.R2[q] = make_float4(hn ? scn / N : 0.0f, hf ? scf / nf : 0.0f, (float)n, 0.0f);
+    P.R3[q] = make_float4(hp ? fp0 / fw : 0.0f, hp ? fp1 / fw : 0.0f, hp ? fp2 / fw : 0.0f, hp ? 1.0f : 0.0f);
+}
+
+hipError_t launch_shade_resolve(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
+                                const uint8_t *mask, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
                           void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,

@@ -781,76 +781,17 @@ __global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict_
 
 // ---------------------------------------------------------------- A11
 
-// One wave per 64 consecutive queue entries.  Their rays are one contiguous
-// range (a pixel's rays follow each other in queue order), which the wave
-// stages into LDS in chunks with coalesced loads; each lane then sums its
-// pixel's rays from LDS in ray order, as the single-thread loop would.
-constexpr int kResolveChunk = 256;
-
+// Resolve of the records that the batch shading kernel wrote.
 __device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
                                  const uint32_t bx, const uint32_t by)
 {
-    __shared__ float4 s_col[kResolveChunk], s_pos[kResolveChunk];
-    __shared__ int32_t s_hit[kResolveChunk];
-    const uint32_t masked = P.counters[kCntMasked];
-    const uint32_t j0 = bx * 64;
-    if (j0 >= masked) return;
-    const uint32_t j = j0 + threadIdx.x;
-    const bool have = j < masked;
-    uint32_t q = 0, base = 0;
-    int n = 0;
-    if (have) {
-        q = P.queue[j];
-        n = mask[q];
-        base = P.ray_base[j];
-    }
-    const uint32_t jl = min(j0 + 63u, masked - 1u);
-    const uint32_t r0 = P.ray_base[j0], r1 = P.ray_base[jl] + mask[P.queue[jl]];
-    float N = 0.0f, sn0 = 0.0f, sn1 = 0.0f, sn2 = 0.0f, sf0 = 0.0f, sf1 = 0.0f, sf2 = 0.0f;
-    float scn = 0.0f, scf = 0.0f, fp0 = 0.0f, fp1 = 0.0f, fp2 = 0.0f, fw = 0.0f;
-    for (uint32_t c0 = r0; c0 < r1; c0 += kResolveChunk) {
-        const uint32_t c1 = min(c0 + (uint32_t)kResolveChunk, r1);
+    resolve_block(fc, P, mask, bx, [&](uint32_t c0, uint32_t c1, float4 *col, float4 *pos, int32_t *hit) {
         for (uint32_t r = c0 + threadIdx.x; r < c1; r += 64) {
-            s_col[r - c0] = P.ray_col[r];
-            s_pos[r - c0] = P.ray_pos[r];
-            s_hit[r - c0] = P.ray_hit[r];
+            col[r - c0] = P.ray_col[r];
+            pos[r - c0] = P.ray_pos[r];
+            hit[r - c0] = P.ray_hit[r];
         }
-        __syncthreads();
-        const uint32_t kb = max(base, c0), ke = min(base + (uint32_t)n, c1);
-        for (uint32_t r = kb; r < ke; ++r) {
-            const float4 c = s_col[r - c0];
-            const bool hit = s_hit[r - c0] >= 0;
-            float w = hit ? sat(0.5f + (fc.d - c.w) / fc.ramp) : 0.0f;
-            float om = 1.0f - w;
-            float cz = coc_px(fc.cock, fc.d, c.w);
-            N = N + w;
-            sn0 = sn0 + w * c.x; sf0 = sf0 + om * c.x;
-            sn1 = sn1 + w * c.y; sf1 = sf1 + om * c.y;
-            sn2 = sn2 + w * c.z; sf2 = sf2 + om * c.z;
-            scn = scn + w * cz;
-            scf = scf + om * cz;
-            if (hit) {
-                const float4 p = s_pos[r - c0];
-                fp0 = fp0 + om * p.x;
-                fp1 = fp1 + om * p.y;
-                fp2 = fp2 + om * p.z;
-                fw = fw + om;
-            }
-        }
-        __syncthreads();
-    }
-    if (!have) return;
-    const float nf = (float)n - N;
-    const bool hn = N > 0.0f, hf = nf > 0.0f, hp = fw > 0.0f;
-    P.R0[q] = make_float4(hn ? sn0 / N : 0.0f, hn ? sn1 / N : 0.0f, hn ? sn2 / N : 0.0f, N);
-    P.R1[q] = make_float4(hf ? sf0 / nf : 0.0f, hf ? sf1 / nf : 0.0f, hf ? sf2 / nf : 0.0f, N / (float)n);
-    P.R2[q] = make_float4(hn ? scn / N : 0.0f, hf ? scf / nf : 0.0f, (float)n, 0.0f);
-    P.R3[q] = make_float4(hp ? fp0 / fw : 0.0f, hp ? fp1 / fw : 0.0f, hp ? fp2 / fw : 0.0f, hp ? 1.0f : 0.0f);
-}
-
-__global__ __launch_bounds__(64) void k_resolve(FrameConst fc, Planes P, const uint8_t *__restrict__ mask)
-{
-    b_resolve(fc, P, mask, blockIdx.x, blockIdx.y);
+    });
 }
 
 __global__ __launch_bounds__(64) void kb_resolve(const Job *__restrict__ jobs, int njobs)
@@ -1641,10 +1582,9 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
     const int64_t np = (int64_t)fc.hw * fc.hh;
     DOF_REC(8);
     {
-        const hipError_t e = launch_shade(sd, fc, L, scratch, st);
+        const hipError_t e = launch_shade_resolve(sd, fc, L, scratch, mask, st);
         if (e != hipSuccess) return e;
     }
-    k_resolve<<<(unsigned)((np + 63) / 64), 64, 0, st>>>(fc, P, mask);
     DOF_REC(9);
     k_temporal<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, mask, hist_in, hist_out);
     DOF_REC(10);

@@ -276,25 +276,42 @@ __device__ inline void lens_ray(const FrameConst &fc, const uint32_t *queue, con
 
 // Per-ray record of a lens ray: hit id, distance, shaded colour with view
 // depth, hit position (sky colour and +inf depth on a miss).
-__device__ inline void lens_finish(const SceneArgs &S, const FrameConst &fc, int32_t *ray_hit, float *ray_t,
-                                   float4 *ray_col, float4 *ray_pos, uint32_t r, const float o[3], const float d[3],
-                                   const Hit &h)
+// Hit id, distance, shaded colour with view depth and hit position of a lens
+// ray (sky colour and +inf depth on a miss).
+__device__ inline void lens_shade(const SceneArgs &S, const FrameConst &fc, const float o[3], const float d[3],
+                                  const Hit &h, int32_t &hit, float &t, float4 &col, float4 &pos)
 {
     if (h.id != ~0u) {
         float P0 = o[0] + h.t * d[0], P1 = o[1] + h.t * d[1], P2 = o[2] + h.t * d[2];
         float z = ((P0 - fc.cur.pos[0]) * fc.cur.fwd[0] + (P1 - fc.cur.pos[1]) * fc.cur.fwd[1]) +
                   (P2 - fc.cur.pos[2]) * fc.cur.fwd[2];
         Shaded s = dof::shade(S, fc.shade, h.leaf, d);
-        ray_hit[r] = (int32_t)h.id;
-        ray_t[r] = h.t;
-        ray_col[r] = make_float4(s.r, s.g, s.b, z);
-        ray_pos[r] = make_float4(P0, P1, P2, 0.0f);
+        hit = (int32_t)h.id;
+        t = h.t;
+        col = make_float4(s.r, s.g, s.b, z);
+        pos = make_float4(P0, P1, P2, 0.0f);
     } else {
-        ray_hit[r] = -1;
-        ray_t[r] = INFINITY;
-        ray_col[r] = make_float4(fc.shade.sky[0], fc.shade.sky[1], fc.shade.sky[2], INFINITY);
-        ray_pos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        hit = -1;
+        t = INFINITY;
+        col = make_float4(fc.shade.sky[0], fc.shade.sky[1], fc.shade.sky[2], INFINITY);
+        pos = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+}
+
+// Per-ray record of a lens ray: hit id, distance, colour with view depth, hit
+// position.
+__device__ inline void lens_finish(const SceneArgs &S, const FrameConst &fc, int32_t *ray_hit, float *ray_t,
+                                   float4 *ray_col, float4 *ray_pos, uint32_t r, const float o[3], const float d[3],
+                                   const Hit &h)
+{
+    int32_t hit;
+    float t;
+    float4 col, pos;
+    lens_shade(S, fc, o, d, h, hit, t, col, pos);
+    ray_hit[r] = hit;
+    ray_t[r] = t;
+    ray_col[r] = col;
+    ray_pos[r] = pos;
 }
 
 // Ray records (three float4 planes): (o, d.x), (d.y, d.z, sx, sy),
@@ -331,15 +348,22 @@ __device__ inline void put_lt(uint2 *lt, uint32_t r, const Hit &h)
 
 // Hit record, distance, shaded colour and position of lens ray r from its
 // traversal result and ray record.
-__device__ inline void shade_ray(const SceneArgs &S, const FrameConst &fc, const Planes &P, uint32_t r)
+__device__ inline void ray_of(const SceneArgs &S, const Planes &P, uint32_t r, float o[3], float d[3], Hit &h)
 {
     const uint2 lt = P.ray_lt[r];
     const float4 a = P.rec0[r], b = P.rec1[r];
-    const float o[3] = {a.x, a.y, a.z}, d[3] = {a.w, b.x, b.y};
-    Hit h;
+    o[0] = a.x; o[1] = a.y; o[2] = a.z;
+    d[0] = a.w; d[1] = b.x; d[2] = b.y;
     h.t = __uint_as_float(lt.y);
     h.leaf = lt.x;
     h.id = lt.x == ~0u ? ~0u : __float_as_uint(S.tris[3 * (size_t)lt.x].w);
+}
+
+__device__ inline void shade_ray(const SceneArgs &S, const FrameConst &fc, const Planes &P, uint32_t r)
+{
+    float o[3], d[3];
+    Hit h;
+    ray_of(S, P, r, o, d, h);
     lens_finish(S, fc, P.ray_hit, P.ray_t, P.ray_col, P.ray_pos, r, o, d, h);
 }
 
@@ -514,13 +538,33 @@ __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs
     }
 }
 
-// Shading of every lens ray of a frame / of a batch, after the traversal.
-__global__ __launch_bounds__(kGenTB) void k_shade(SceneArgs S, FrameConst fc, Planes P, const uint32_t *count)
+// Shading and resolve of a frame's lens rays in one pass: each block shades
+// the rays of its 64 pixels straight into the resolve's LDS chunks (and into
+// the per-ray records), so the records are not read back.
+__global__ __launch_bounds__(64) void k_shade_resolve(SceneArgs S, FrameConst fc, Planes P,
+                                                      const uint8_t *__restrict__ mask)
 {
-    const uint32_t N = *count;
-    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) shade_ray(S, fc, P, r);
+    resolve_block(fc, P, mask, blockIdx.x, [&](uint32_t c0, uint32_t c1, float4 *col, float4 *pos, int32_t *hit) {
+        for (uint32_t r = c0 + threadIdx.x; r < c1; r += 64) {
+            float o[3], d[3];
+            Hit h;
+            ray_of(S, P, r, o, d, h);
+            int32_t hi;
+            float t;
+            float4 c, p;
+            lens_shade(S, fc, o, d, h, hi, t, c, p);
+            P.ray_hit[r] = hi;
+            P.ray_t[r] = t;
+            P.ray_col[r] = c;
+            P.ray_pos[r] = p;
+            col[r - c0] = c;
+            pos[r - c0] = p;
+            hit[r - c0] = hi;
+        }
+    });
 }
 
+// Shading of every lens ray of a batch, after the traversal.
 __global__ __launch_bounds__(kGenTB) void kb_shade(const Job *__restrict__ jobs, const BatchHead *head, int njobs)
 {
     __shared__ uint32_t off[kMaxBatch + 1];
@@ -780,11 +824,12 @@ hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scr
     return hipGetLastError();
 }
 
-hipError_t launch_shade(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st)
+hipError_t launch_shade_resolve(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
+                                const uint8_t *mask, hipStream_t st)
 {
     const Planes P = planes(fc, L, scratch);
-    const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
-    k_shade<<<gen_blocks(max_rays), kGenTB, 0, st>>>(scene_args(s), fc, P, P.counters + kCntRays);
+    const int64_t np = (int64_t)fc.hw * fc.hh;
+    k_shade_resolve<<<(unsigned)((np + 63) / 64), 64, 0, st>>>(scene_args(s), fc, P, mask);
     return hipGetLastError();
 }
 
