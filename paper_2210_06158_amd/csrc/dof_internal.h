@@ -232,6 +232,23 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
 // the ray records of every thin-lens ray of the frame (after the compaction)
 hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scratch, hipStream_t st);
 // hit record, distance, shaded colour and position of every ray (after the traversal)
+// Job of a block of a batched launch: the last job whose first block in grid
+// g is at or before b; (bx, by) is the block within that job's own grid.
+__device__ inline int job_of_block(const Job *__restrict__ jobs, int njobs, int g, uint32_t b, uint32_t &bx,
+                                   uint32_t &by)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].bstart[g] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t lb = b - jobs[lo].bstart[g], w = jobs[lo].bx[g];
+    bx = lb % w;
+    by = lb / w;
+    return lo;
+}
+
 // ---------------------------------------------------------------- A11 resolve, shared
 
 // One wave per 64 consecutive queue entries.  Their rays are one contiguous
@@ -302,6 +319,7 @@ __device__ inline void resolve_block(const FrameConst &fc, const Planes &P, cons
 
 hipError_t launch_shade_resolve(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                                 const uint8_t *mask, hipStream_t st);
+hipError_t launch_batch_shade_resolve(const Job *jobs, int njobs, const uint32_t *nblk, hipStream_t st);
 hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour, int cfmt, float *depth,
                           void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,

@@ -219,22 +219,6 @@ dof_gbuffer resolved_gbuffer(const FrameConst &fc, const Planes &P, const dof_gb
 
 namespace {
 
-// Job of a block of a batched launch: the last job whose first block in grid
-// g is at or before b; (bx, by) is the block within that job's own grid.
-__device__ inline int job_of_block(const Job *__restrict__ jobs, int njobs, int g, uint32_t b, uint32_t &bx,
-                                   uint32_t &by)
-{
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].bstart[g] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const uint32_t lb = b - jobs[lo].bstart[g], w = jobs[lo].bx[g];
-    bx = lb % w;
-    by = lb / w;
-    return lo;
-}
 
 // ---------------------------------------------------------------- A1
 
@@ -780,26 +764,6 @@ __global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict_
 }
 
 // ---------------------------------------------------------------- A11
-
-// Resolve of the records that the batch shading kernel wrote.
-__device__ inline void b_resolve(const FrameConst &fc, const Planes &P, const uint8_t *__restrict__ mask,
-                                 const uint32_t bx, const uint32_t by)
-{
-    resolve_block(fc, P, mask, bx, [&](uint32_t c0, uint32_t c1, float4 *col, float4 *pos, int32_t *hit) {
-        for (uint32_t r = c0 + threadIdx.x; r < c1; r += 64) {
-            col[r - c0] = P.ray_col[r];
-            pos[r - c0] = P.ray_pos[r];
-            hit[r - c0] = P.ray_hit[r];
-        }
-    });
-}
-
-__global__ __launch_bounds__(64) void kb_resolve(const Job *__restrict__ jobs, int njobs)
-{
-    uint32_t bx, by;
-    const Job &J = jobs[job_of_block(jobs, njobs, kGridResolve, blockIdx.x, bx, by)];
-    b_resolve(J.fc, J.P, J.mask, bx, by);
-}
 
 // ---------------------------------------------------------------- A12
 
@@ -1637,7 +1601,10 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
 hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
                              int taa, hipStream_t st)
 {
-    kb_resolve<<<nblk[kGridResolve], 64, 0, st>>>(jobs, njobs);
+    {
+        const hipError_t e = launch_batch_shade_resolve(jobs, njobs, nblk, st);
+        if (e != hipSuccess) return e;
+    }
     kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);

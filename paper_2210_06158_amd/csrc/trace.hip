@@ -14,7 +14,7 @@
 // long rays do not hold a whole wave hostage (persistent threads with dynamic
 // fetch) and the shared counter sees one atomic per 64 rays.  Thin-lens rays
 // come precomputed (a generation kernel writes a 48-byte record per ray) and
-// leave as an 8-byte (leaf, t) record that a shading kernel expands, so a
+// leave as an 8-byte (leaf, t) record that the resolve expands when it shades, so a
 // refill is three loads and a finishing ray one store: no arithmetic or
 // scene loads that the whole wave would wait on.
 //
@@ -298,22 +298,6 @@ __device__ inline void lens_shade(const SceneArgs &S, const FrameConst &fc, cons
     }
 }
 
-// Per-ray record of a lens ray: hit id, distance, colour with view depth, hit
-// position.
-__device__ inline void lens_finish(const SceneArgs &S, const FrameConst &fc, int32_t *ray_hit, float *ray_t,
-                                   float4 *ray_col, float4 *ray_pos, uint32_t r, const float o[3], const float d[3],
-                                   const Hit &h)
-{
-    int32_t hit;
-    float t;
-    float4 col, pos;
-    lens_shade(S, fc, o, d, h, hit, t, col, pos);
-    ray_hit[r] = hit;
-    ray_t[r] = t;
-    ray_col[r] = col;
-    ray_pos[r] = pos;
-}
-
 // Ray records (three float4 planes): (o, d.x), (d.y, d.z, sx, sy),
 // (sz, 1/d.x, 1/d.y, 1/d.z), written by the ray generation kernel so that a
 // traversal lane takes a new ray with three independent loads.
@@ -340,14 +324,14 @@ __device__ inline void get_ray(const float4 *rec0, const float4 *rec1, const flo
 }
 
 // The traversal's result of a lens ray: leaf of the closest hit (~0u: none)
-// and distance, one 8-byte store; the shading kernel expands it.
+// and distance, one 8-byte store; the resolve expands it when it shades.
 __device__ inline void put_lt(uint2 *lt, uint32_t r, const Hit &h)
 {
     lt[r] = make_uint2(h.id == ~0u ? ~0u : h.leaf, __float_as_uint(h.t));
 }
 
-// Hit record, distance, shaded colour and position of lens ray r from its
-// traversal result and ray record.
+// Origin, direction and closest hit of lens ray r, from its ray record and
+// its traversal result.
 __device__ inline void ray_of(const SceneArgs &S, const Planes &P, uint32_t r, float o[3], float d[3], Hit &h)
 {
     const uint2 lt = P.ray_lt[r];
@@ -357,14 +341,6 @@ __device__ inline void ray_of(const SceneArgs &S, const Planes &P, uint32_t r, f
     h.t = __uint_as_float(lt.y);
     h.leaf = lt.x;
     h.id = lt.x == ~0u ? ~0u : __float_as_uint(S.tris[3 * (size_t)lt.x].w);
-}
-
-__device__ inline void shade_ray(const SceneArgs &S, const FrameConst &fc, const Planes &P, uint32_t r)
-{
-    float o[3], d[3];
-    Hit h;
-    ray_of(S, P, r, o, d, h);
-    lens_finish(S, fc, P.ray_hit, P.ray_t, P.ray_col, P.ray_pos, r, o, d, h);
 }
 
 struct LensRays {
@@ -541,10 +517,10 @@ __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs
 // Shading and resolve of a frame's lens rays in one pass: each block shades
 // the rays of its 64 pixels straight into the resolve's LDS chunks (and into
 // the per-ray records), so the records are not read back.
-__global__ __launch_bounds__(64) void k_shade_resolve(SceneArgs S, FrameConst fc, Planes P,
-                                                      const uint8_t *__restrict__ mask)
+__device__ inline void shade_resolve_block(const SceneArgs &S, const FrameConst &fc, const Planes &P,
+                                           const uint8_t *__restrict__ mask, uint32_t bx)
 {
-    resolve_block(fc, P, mask, blockIdx.x, [&](uint32_t c0, uint32_t c1, float4 *col, float4 *pos, int32_t *hit) {
+    resolve_block(fc, P, mask, bx, [&](uint32_t c0, uint32_t c1, float4 *col, float4 *pos, int32_t *hit) {
         for (uint32_t r = c0 + threadIdx.x; r < c1; r += 64) {
             float o[3], d[3];
             Hit h;
@@ -564,23 +540,17 @@ __global__ __launch_bounds__(64) void k_shade_resolve(SceneArgs S, FrameConst fc
     });
 }
 
-// Shading of every lens ray of a batch, after the traversal.
-__global__ __launch_bounds__(kGenTB) void kb_shade(const Job *__restrict__ jobs, const BatchHead *head, int njobs)
+__global__ __launch_bounds__(64) void k_shade_resolve(SceneArgs S, FrameConst fc, Planes P,
+                                                      const uint8_t *__restrict__ mask)
 {
-    __shared__ uint32_t off[kMaxBatch + 1];
-    for (int j = threadIdx.x; j <= njobs; j += kGenTB) off[j] = head->ray_off[j];
-    __syncthreads();
-    const uint32_t N = head->rays;
-    for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) {
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= r) lo = mid;
-            else hi = mid - 1;
-        }
-        const Job &J = jobs[lo];
-        shade_ray(J.scene, J.fc, J.P, r - off[lo]);
-    }
+    shade_resolve_block(S, fc, P, mask, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void kb_shade_resolve(const Job *__restrict__ jobs, int njobs)
+{
+    uint32_t bx, by;
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridResolve, blockIdx.x, bx, by)];
+    shade_resolve_block(J.scene, J.fc, J.P, J.mask, bx);
 }
 
 int gen_blocks(int64_t max_rays)
@@ -824,6 +794,12 @@ hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scr
     return hipGetLastError();
 }
 
+hipError_t launch_batch_shade_resolve(const Job *jobs, int njobs, const uint32_t *nblk, hipStream_t st)
+{
+    kb_shade_resolve<<<nblk[kGridResolve], 64, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_shade_resolve(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                                 const uint8_t *mask, hipStream_t st)
 {
@@ -869,7 +845,6 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint3
     BatchRays src{jobs, head, njobs};
     k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
                                                                 &head->visits, nullptr);
-    kb_shade<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     return hipGetLastError();
 }
 
