@@ -349,6 +349,27 @@ def test_reconstruction_global_fallback_parity(env, orc):
     assert (bb[big] > 0.5).mean() > 0.9                                 # the taps decide the result there
     compare_frame(o1, d1, "recon fallback, frame 1")
 
+
+@pytest.mark.parametrize("lod_scale,lod_max", [(0.2, 1.0), (0.05, 0.0)])
+def test_reconstruction_mip_level_limits_parity(env, orc, lod_scale, lod_max):
+    """Eq. (8) with a lower top level: lod_max 1 puts most pixels on levels 1
+    and 1 (both samples from one level, whose staged box then serves both),
+    lod_max 0 leaves only the finest level.  Second frame on the first's
+    history, blend factor b at its cap, so the taps decide the result."""
+    lens = dataclasses.replace(env["lens"], focal=0.15, fnum=1.0)
+    p = dataclasses.replace(env["params"], lod_scale=lod_scale, lod_max=lod_max, mask_mode=synth.MASK_ALL,
+                            var_recon_w=1e6)
+    gb = orc.gbuffer(env["osc"], env["cam"], lens)
+    o0, d0 = run_pair(env, orc, env["cam"], lens, p, gb)
+    compare_frame(o0, d0, f"lod_max {lod_max}, frame 0")
+    cam1 = dataclasses.replace(env["cam"], frame=1)
+    o1, d1 = run_pair(env, orc, cam1, lens, p, gb, hist_in=o0["hist_out"], prev_cam=env["cam"], prev_lens=lens)
+    ct = o1["temporal"][1][..., 0]
+    traced = o1["temporal"][0][..., 3] > 0
+    lod = np.clip(ct * lod_scale, 0.0, lod_max)
+    assert (lod[traced] >= lod_max).mean() > 0.2                       # many pixels at the top level
+    compare_frame(o1, d1, f"lod_max {lod_max}, frame 1")
+
 @pytest.mark.parametrize("polygon", [0, 1])
 def test_hexagon_aperture_and_ragged_size(env, orc, polygon):
     """6-blade aperture at a size that is not a multiple of any tile
