@@ -15,7 +15,7 @@ from __future__ import annotations
 def candidate_blocks(extra=()):
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    return sorted({0, *(cus * k for k in (4, 6, 8, 10, 12)), *extra})
+    return sorted({0, *(cus * k for k in (4, 6, 7, 8, 9, 10, 12)), *extra})
 
 
 def tune(run, candidates, reps: int = 3):
