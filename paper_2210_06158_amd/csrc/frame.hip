@@ -1040,9 +1040,9 @@ __device__ inline float4 bilinear4_lds(const float4 *t, const int *b, int bw, fl
     int x1 = clampi(x0 + 1, b[0], b[1]), y1 = clampi(y0 + 1, b[2], b[3]);
     x0 = clampi(x0, b[0], b[1]);
     y0 = clampi(y0, b[2], b[3]);
-    const float4 *r0 = t + (y0 - b[2]) * bw - b[0], *r1 = t + (y1 - b[2]) * bw - b[0];
-    float4 a = r0[x0], bq = r0[x1];
-    float4 c = r1[x0], d = r1[x1];
+    const int r0 = (y0 - b[2]) * bw, r1 = (y1 - b[2]) * bw, c0 = x0 - b[0], c1 = x1 - b[0];
+    float4 a = t[r0 + c0], bq = t[r0 + c1];
+    float4 c = t[r1 + c0], d = t[r1 + c1];
     float4 top, bot, o;
     top.x = a.x + (bq.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
     top.y = a.y + (bq.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
