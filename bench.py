@@ -286,8 +286,8 @@ def trace_roofline(r):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a "
-                                   "design note, not implemented)"}))
+        print(json.dumps({"error": "the hybrid DoF pass runs on one GPU; --gpus must be 1 (sharding across GPUs "
+                                   "is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
