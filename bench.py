@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
 # Floating-point operations of the traversal, counted from the kernel source:
-# one node visit = two slab tests (6 sub, 6 mul, 12 min/max/compare-class ops
-# and 2 for the 2^-20 exit margin each) plus the prune limit; one
+# one node visit = two slab tests (6 fma = 12 flops, 12 min/max/compare-class
+# ops and 2 for the 2^-20 exit margin each) plus the prune limit; one
 # triangle test = the watertight test (edge functions, determinant, distance).
 FLOP_PER_VISIT = 53
 FLOP_PER_TRI_TEST = 55
@@ -696,7 +696,7 @@ def cpu_baseline(scene, cams, lens, params, budget_s, log):
         done += 1
         hist, prev = out["hist_out"], cams[f]
         log(f"cpu oracle frame {f}: {spent:.2f} s total")
-        if spent >= budget_s or done >= 3:
+        if spent >= budget_s or done >= 10:
             break
     return {"value": round(done / spent, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} consecutive 1080p frames of the same camera path (G-buffer rendered untimed), "
