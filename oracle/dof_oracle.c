@@ -312,8 +312,7 @@ int orc_build_bvh(const orc_scene *s, orc_bvh *b)
     int n = s->ntri;
     uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     keyed *kv = (keyed *)malloc(sizeof(keyed) * (size_t)n);
-    if (!codes || !kv) { free(codes); free(kv); return -2; }
-    orc_morton(s, codes);
+    if (!codes || !kv || orc_morton(s, codes) != 0) { free(codes); free(kv); return -2; }
     for (int i = 0; i < n; i++) { kv[i].code = codes[i]; kv[i].id = (uint32_t)i; }
     free(codes);
     qsort(kv, (size_t)n, sizeof(keyed), cmp_keyed);
@@ -851,13 +850,15 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     float *rast = taa_rast ? (float *)calloc((size_t)W * H * 4, sizeof(float)) : NULL;
     float *ppt = taa_post ? (float *)calloc(np * 4, sizeof(float)) : NULL;
     float *comp = taa_final ? (float *)calloc((size_t)W * H * 4, sizeof(float)) : NULL;
+    /* allocated later; every exit frees each buffer once (free(NULL) is a no-op) */
+    int32_t *rhit = NULL;
+    float *rt = NULL, *rcol = NULL, *rpos = NULL;
+    int status = 0;
     if (!colr || !zn || !tmax || !tdil || !pre || !gat || !ppm || !prev || !queue || !rbase || !res || !tmp ||
         !var || !vblur || !rtmed || !rec || !hblur || !gblur || !mips || (taa_rast && !rast) || (taa_post && !ppt) ||
         (taa_final && !comp)) {
-        free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
-        free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-        free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp);
-        return -2;
+        status = -2;
+        goto done;
     }
 
     /* History layout: the half-res record (13 floats per half-res pixel),
@@ -1111,10 +1112,8 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     if (p->mask_mode == 3) {
         uint8_t *raw = (uint8_t *)malloc(np ? np : 1);
         if (!raw) {
-            free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
-            free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-            free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp); free(rast); free(ppt); free(comp);
-            return -2;
+            status = -2;
+            goto done;
         }
         memcpy(raw, out_mask, np);
         for (int y = 0; y < hh; y++)
@@ -1148,16 +1147,13 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
     /* A9/A10 -- thin-lens rays (3.2.2, after Cook 1984): from a random point
      * of the aperture towards the pixel's point on the focus plane at view
      * depth d, closest hit, Lambert shading.  Half resolution. */
-    int32_t *rhit = (int32_t *)malloc(sizeof(int32_t) * (R ? R : 1));
-    float *rt = (float *)malloc(sizeof(float) * (R ? R : 1));
-    float *rcol = (float *)malloc(sizeof(float) * 4 * (R ? R : 1));
-    float *rpos = (float *)malloc(sizeof(float) * 4 * (R ? R : 1));
+    rhit = (int32_t *)malloc(sizeof(int32_t) * (R ? R : 1));
+    rt = (float *)malloc(sizeof(float) * (R ? R : 1));
+    rcol = (float *)malloc(sizeof(float) * 4 * (R ? R : 1));
+    rpos = (float *)malloc(sizeof(float) * 4 * (R ? R : 1));
     if (!rhit || !rt || !rcol || !rpos) {
-        free(rhit); free(rt); free(rcol); free(rpos);
-        free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
-        free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
-        free(hblur); free(gblur); free(mips);
-        return -2;
+        status = -2;
+        goto done;
     }
 #pragma omp parallel for schedule(dynamic, 16) num_threads(g_threads)
     for (size_t j = 0; j < P; j++) {
@@ -1510,11 +1506,12 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
         dbg->n_masked = (int64_t)P;
         dbg->n_rays = (int64_t)R;
     }
+done:
     free(rhit); free(rt); free(rcol); free(rpos);
     free(colr); free(zn); free(tmax); free(tdil); free(pre); free(gat); free(ppm); free(prev);
     free(queue); free(rbase); free(res); free(tmp); free(var); free(vblur); free(rtmed); free(rec);
     free(hblur); free(gblur); free(mips); free(rast); free(ppt); free(comp);
-    return 0;
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -183,3 +183,29 @@ def test_frame_ray_count_limit(dof):
     assert b"2^31" in L.dof_last_error()
     p.m = 64   # exactly 2^31
     assert L.dof_frame_scratch_bytes(16384, 8192, C.byref(p), C.byref(b)) == 0
+
+
+def test_scene_creation_fails_cleanly_without_a_device(dof):
+    """With no GPU visible the scene upload fails: DOF_E_DEVICE, no handle,
+    and the host object is released (checked for leaks and double frees by the
+    sanitizer run of this file).  Skipped where a GPU is visible: the bogus
+    arena pointer would then reach the device."""
+    import numpy as np
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    L = dof.lib()
+    verts = np.zeros((2, 9), np.float32)
+    verts[0, 3], verts[0, 7], verts[1, 4] = 1.0, 1.0, 1.0
+    albedo = np.ones((2, 3), np.float32)
+    desc = dof.DofSceneDesc()
+    desc.ntri = 2
+    desc.verts = verts.ctypes.data
+    desc.albedo = albedo.ctypes.data
+    b = C.c_size_t()
+    assert L.dof_scene_bytes(2, C.byref(b)) == 0
+    h = C.c_void_p()
+    st = L.dof_create_scene(C.byref(desc), C.c_void_p(1 << 40), b.value, None, C.byref(h))
+    assert st == dof.DOF_E_DEVICE and not h.value
+    assert b"scene upload" in L.dof_last_error()
+    assert L.dof_create_scene(C.byref(desc), C.c_void_p(1 << 40), b.value - 1, None, C.byref(h)) == dof.DOF_E_NOMEM
