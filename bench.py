@@ -35,12 +35,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
-# Floating-point operations of the traversal, counted from the kernel source:
-# one node visit = two slab tests (6 fma = 12 flops, 12 min/max/compare-class
-# ops and 2 for the 2^-20 exit margin each) plus the prune limit; one
-# triangle test = the watertight test (edge functions, determinant, distance).
-FLOP_PER_VISIT = 53
-FLOP_PER_TRI_TEST = 55
+# Algorithmic floating-point work of the traversal: a node visit tests a pair
+# of boxes, 6 plane distances each as one fma (2 FLOP) = 24 FLOP per pair; a
+# watertight triangle test is about 40 FLOP (vertex translation 9, shear 12,
+# edge functions 9, determinant 2, scaled distance 8).  The roofline fraction
+# uses these.  Counting every arithmetic instruction the kernel issues for
+# them (min/max/compare-class operations, the exit margin and the prune
+# limit) gives 53 and 55, reported beside as the issued count.
+FLOP_PER_VISIT = 24
+FLOP_PER_TRI_TEST = 40
+ISSUED_FLOP_PER_VISIT = 53
+ISSUED_FLOP_PER_TRI_TEST = 55
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_1080p.txt")
 # what the traversal's memory traffic depends on: its kernel, the tree the
 # build produces, and the scene generator
@@ -55,8 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--m", type=int, default=8)
     ap.add_argument("--stage-frames", type=int, default=60)
+    ap.add_argument("--latency-passes", type=int, default=10,
+                    help="full passes over the 60-frame path timed frame by frame for p50/p99 (at least 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--trace-blocks", type=int, default=-1,
                     help="persistent traversal blocks (0 = library default, -1 = autotuned per workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -64,6 +70,8 @@ def parse():
                          "known traffic for hardware byte counters)")
     ap.add_argument("--no-m-sweep", dest="m_sweep", action="store_false")
     ap.add_argument("--no-shots", dest="shots", action="store_false", help="skip the BG / FG shot measurement")
+    ap.add_argument("--no-judge", dest="judge", action="store_false",
+                    help="skip the accuracy judge (hybrid vs 64-spp fully ray-traced frames)")
     ap.add_argument("--uhd-steps", type=int, default=60, help="frames of the 3840x2160 measurement (0 = skip)")
     ap.add_argument("--batched-sessions", type=int, default=32, help="sessions of the batched measurement (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -109,9 +117,10 @@ def stage_bytes(stage, W, H, P, R):
 
 
 def measured_traffic():
-    """HBM bytes per traversal launch from the committed rocprofv3 counter
-    summary, scaled by its copy-kernel calibration; None when the traversal,
-    the BVH build or the scene generator has changed since the counters were
+    """Per traversal launch, from the committed rocprofv3 counter summary:
+    HBM-side bytes (FETCH_SIZE and WRITE_SIZE scaled by their copy-kernel
+    calibration) and the L2's hits and misses; None when the traversal, the
+    BVH build or the scene generator has changed since the counters were
     taken."""
     import hashlib
     try:
@@ -126,37 +135,66 @@ def measured_traffic():
         return None
     fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
     write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
-    return int(fetch + write)
+    out = {"hbm_bytes": int(fetch + write)}
+    if "tcc_hit_per_launch" in kv and "tcc_miss_per_launch" in kv:
+        out["tcc_hit"] = float(kv["tcc_hit_per_launch"])
+        out["tcc_miss"] = float(kv["tcc_miss_per_launch"])
+    return out
 
 
-def autotune_grid(gs, cams, lenses, params, gbs, log, label, frames=6):
-    """The persistent traversal grid for a workload (setup, outside every
-    timed region): each candidate renders the same first `frames` frames of
-    the path, history chained from a reset; the fastest by HIP events wins
-    (returns (blocks, {candidate: ms}); 0 is the library default)."""
+def l2_figure(mt, ms):
+    """The traversal's L2 side: requests the L2 served per launch (hits and
+    misses from the counter summary), the hit rate, and the request rate over
+    this run's traversal time; bytes at the 128-byte L2 line as an upper
+    figure (a request moves at most one line)."""
+    if "tcc_hit" not in mt:
+        return None
+    req = mt["tcc_hit"] + mt["tcc_miss"]
+    return {"requests_per_launch": round(req), "hit_rate": round(mt["tcc_hit"] / req, 4),
+            "grequests_per_s": round(req / (ms * 1e-3) / 1e9, 2),
+            "GB_per_s_at_128B_per_request": round(req * 128 / (ms * 1e-3) / 1e9, 1)}
+
+
+def frame_for(W, H, params, cfg, **kw):
+    """A dof.Frame of the pass with the launch shapes of cfg (tune.search's
+    configuration; {} = library defaults), FP16 output."""
+    from paper_2210_06158_amd import dof, tune
+    tb, knobs = tune.split(cfg)
+    return dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=tb, knobs=knobs, **kw)
+
+
+def autotune(gs, cams, lenses, params, gbs, log, label, frames=6):
+    """The launch shapes for a workload (setup, outside every timed region):
+    coordinate descent over the traversal grid, stack depth, queue width,
+    refill and leaf-batch thresholds and the gather's LDS window, each trial
+    rendering the same first `frames` frames of the path, history chained
+    from a reset; HIP-event time.  Returns (configuration, report)."""
     from paper_2210_06158_amd import dof, tune
 
     W, H = cams[0].width, cams[0].height
     hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
-    by_grid = {}
+    cache = {}
 
-    def trial(tb):
-        fr = by_grid.get(tb)
+    def trial(cfg):
+        key = tuple(sorted(cfg.items()))
+        fr = cache.get(key)
         if fr is None:
-            fr = by_grid[tb] = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=tb)
+            fr = cache[key] = frame_for(W, H, params, cfg)
         for k in range(frames):
             prev = cams[k - 1] if k > 0 else None
             fr.render(gs, cams[k], lenses[k], gbs[k], hist[(k + 1) % 2] if prev is not None else None, hist[k % 2],
                       prev_cam=prev, prev_lens=lenses[k - 1] if k > 0 else None)
 
-    best, ms = tune.tune(trial, tune.candidate_blocks(), reps=2)
-    del by_grid
-    log(f"{label}: traversal grid {best if best else 'library default'} ({ms})")
-    return best, {"trace_blocks": best if best else "library default",
-                  "candidates_ms": {str(k if k else "default"): round(v, 3) for k, v in ms.items()}}
+    cfg, table = tune.search(trial)
+    cache.clear()
+    log(f"{label}: launch shapes {cfg} ({table})")
+    return cfg, {"chosen": {k: (v if v else "library default") if k == "trace_blocks" else v for k, v in cfg.items()},
+                 "ms_per_sample": {k: {str(c if c else "default") if k == "trace_blocks" else str(c): round(t, 3)
+                                       for c, t in v.items()} for k, v in table.items()},
+                 "sample_frames": frames}
 
 
-def shots_leg(gs, scene, cams, lens, params, tb, main, log):
+def shots_leg(gs, scene, cams, lens, params, cfg, main, log):
     """Frame time by foreground coverage (Table 1 reports its BG / M / FG
     shots): the 60-frame path (middle class) and two 20-frame shots of the
     same scene, background ("BG") and inside the grass ("FG").  Coverage =
@@ -181,7 +219,7 @@ def shots_leg(gs, scene, cams, lens, params, tb, main, log):
     for kind in ("BG", "FG"):
         sc = synth.shot_cameras(kind, 20, W, H)
         gbs = [gs.render_gbuffer(c, lens, fmt=dof.RGBA16F) for c in sc]
-        r = run_path(gs, sc, [lens] * len(sc), params, gbs, 20, 5, 10, tb, log)
+        r = run_path(gs, sc, [lens] * len(sc), params, gbs, 20, 5, 10, cfg, log)
         out[kind] = {"grass_coverage": coverage(sc), "frames": len(sc),
                      "frames_per_s": round(r["K"] / (r["total_ms"] / 1e3), 2),
                      "p50_frame_ms": round(float(np.percentile(r["frame_ms"], 50)), 4),
@@ -191,10 +229,15 @@ def shots_leg(gs, scene, cams, lens, params, tb, main, log):
     return out
 
 
-def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_blocks, log):
+def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, cfg, log, latency_passes=0):
     """Render steps frames of a camera path (after warmup frames) with one
-    dof_render_frame each, history ping-pong, then stage_frames more with
-    per-stage HIP events.  Returns timing and counter totals."""
+    dof_render_frame each, history ping-pong.  Then the same frames again
+    (the histories restored to their state before the timed frames) with
+    per-stage HIP events, so the per-stage figures describe the timed
+    workload; their ray counts must equal the timed frames' one by one.
+    Then latency_passes full passes over the path, continuing the history
+    chain, each frame bracketed by its own events (frame-time percentiles).
+    Returns timing and counter totals."""
     import numpy as np
     import torch
 
@@ -203,7 +246,7 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_b
     W, H = cams[0].width, cams[0].height
     nfr = len(cams)
     hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
-    fr = dof.Frame(W, H, params, out_format=dof.RGBA16F, trace_blocks=trace_blocks)
+    fr = frame_for(W, H, params, cfg)
 
     def step(i, frame):
         f = i % nfr
@@ -214,6 +257,7 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_b
     for i in range(warmup):
         step(i, fr)
     torch.cuda.synchronize()
+    snap = [h.clone() for h in hist]
     K = steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
@@ -236,8 +280,24 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_b
     st64 = st.view(np.int64)
     log(f"timed {K} frames of {W}x{H}: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
 
-    # live per-stage timing (same workload, HIP events around every stage)
-    frt = dof.Frame(W, H, params, out_format=dof.RGBA16F, timing=True, trace_blocks=trace_blocks)
+    # frame-time distribution over whole passes of the path
+    lat = None
+    if latency_passes > 0:
+        n = latency_passes * nfr
+        ls = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        le = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        for k in range(n):
+            ls[k].record()
+            step(warmup + K + k, fr)
+            le[k].record()
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_time(b) for a, b in zip(ls, le)])
+
+    # per-stage timing of the same frames: histories as before the timed loop
+    for h, sh in zip(hist, snap):
+        h.copy_(sh)
+    del snap
+    frt = frame_for(W, H, params, cfg, timing=True)
     sums = {s: 0.0 for s in dof.STAGES}
     t_rays = t_masked = t_visits = t_tests = 0
     nst = min(stage_frames, K)
@@ -246,11 +306,14 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, trace_b
         for s, v in gs.stage_times().items():
             sums[s] += v
         sv = frt.stats.cpu().numpy()
+        assert int(sv[1]) == int(st[k, 1]) and int(sv[0]) == int(st[k, 0]), \
+            f"stage-timed frame {k} traced {int(sv[1])} rays, the timed one {int(st[k, 1])}"
         t_masked += int(sv[0])
         t_rays += int(sv[1])
         t_visits += int(sv.view(np.int64)[1])
         t_tests += int(sv.view(np.int64)[2])
-    return dict(W=W, H=H, K=K, total_ms=total_ms, frame_ms=frame_ms, rays=int(st[:, 1].astype(np.int64).sum()),
+    return dict(W=W, H=H, K=K, total_ms=total_ms, frame_ms=frame_ms, latency_ms=lat,
+                rays=int(st[:, 1].astype(np.int64).sum()),
                 masked=int(st[:, 0].astype(np.int64).sum()), visits=int(st64[:, 1].sum()),
                 tests=int(st64[:, 2].sum()), spills=int(st[:, 6].astype(np.int64).sum()),
                 stage_ms={s: v / nst for s, v in sums.items()},
@@ -270,15 +333,23 @@ def stage_roofline(r):
 
 
 def trace_roofline(r):
-    """Roofline of the traversal: FP32 vector ALU peak, FLOPs from the
-    measured visit and test counts."""
+    """Roofline of the traversal: FP32 vector ALU peak, algorithmic FLOPs
+    (24 per box pair, 40 per triangle test) from the measured visit and test
+    counts of the stage-timed frames, over the traversal's own HIP-event
+    time."""
     nst = r["stage_frames"]
     flops = (FLOP_PER_VISIT * r["t_visits"] + FLOP_PER_TRI_TEST * r["t_tests"]) / nst
+    issued = (ISSUED_FLOP_PER_VISIT * r["t_visits"] + ISSUED_FLOP_PER_TRI_TEST * r["t_tests"]) / nst
     ms = r["stage_ms"]["trace"]
     achieved = flops / (ms * 1e-3) / 1e12
     return {"kernel": "trace (k_traverse<LensRays>)", "bound": "alu", "achieved": round(achieved, 3),
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5),
-            "flop_per_launch": int(flops), "ms_per_launch": round(ms, 5),
+            "flop_per_launch": int(flops), "flop_per_box_pair": FLOP_PER_VISIT,
+            "flop_per_tri_test": FLOP_PER_TRI_TEST, "rays_per_launch": round(r["t_rays"] / nst, 1),
+            "node_visits_per_ray": round(r["t_visits"] / max(r["t_rays"], 1), 3),
+            "tri_tests_per_ray": round(r["t_tests"] / max(r["t_rays"], 1), 3),
+            "issued_flop_frac": round(issued / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 5),
+            "ms_per_launch": round(ms, 5),
             "compulsory_bytes_per_launch": int(stage_bytes("trace", r["W"], r["H"], r["t_masked"] / nst,
                                                            r["t_rays"] / nst))}
 
@@ -322,11 +393,13 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     gbuffer_ms = e0.elapsed_time(e1) / nfr
-    tb, grid = args.trace_blocks, None
-    if tb < 0:
-        tb, grid = autotune_grid(gs, cams, [lens] * nfr, params, gbs, log, "1080p")
-    r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, tb, log)
+    tb, grid = {"trace_blocks": args.trace_blocks}, None
+    if args.trace_blocks < 0:
+        tb, grid = autotune(gs, cams, [lens] * nfr, params, gbs, log, "1080p")
+    r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, tb, log,
+                 latency_passes=max(1, args.latency_passes))
     K, total_ms, frame_ms = r["K"], r["total_ms"], r["frame_ms"]
+    lat_ms = r["latency_ms"]
     rays, masked, visits, tests = r["rays"], r["masked"], r["visits"], r["tests"]
     fps = K / (total_ms / 1e3)
     stage_ms = r["stage_ms"]
@@ -336,7 +409,9 @@ def main():
         # pointer chasing that executes on the vector ALUs: its roofline is
         # the FP32 vector peak, with FLOPs from the measured visit/test counts
         roofline = trace_roofline(r)
-        roofline["traffic"] = measured_traffic()
+        mt = measured_traffic()
+        roofline["traffic"] = mt["hbm_bytes"] if mt else None
+        roofline["l2"] = l2_figure(mt, roofline["ms_per_launch"]) if mt else None
     else:
         dom_bytes = stage_bytes(dom, W, H, P_avg, R_avg)
         achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
@@ -398,6 +473,7 @@ def main():
                                           "rays_per_frame": round(ra["rays"] / ra["K"], 1)}
         del jg
     del gbs
+    judge = judge_leg(gs, cams, lens, params, tb, log) if args.judge else None
 
     w4k = None
     if args.uhd_steps > 0:
@@ -413,7 +489,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, cams, lens, params, args.cpu_seconds, log)
+        cpu = cpu_baseline(scene, cams, lens, params, log)
 
     out = {
         "metric": "hybrid DoF frames/s at 1080p (1 MI355X)",
@@ -438,24 +514,102 @@ def main():
         "stack_spills_per_frame": round(r["spills"] / K, 2),
         "tri_tests_per_ray": round(tests / max(rays, 1), 2),
         "masked_px_per_frame": round(masked / K, 1),
-        "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 4),
-        "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 4),
+        "p50_frame_ms": round(float(np.percentile(lat_ms, 50)), 4),
+        "p99_frame_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "frame_ms_samples": {"frames": int(lat_ms.size), "passes_over_path": int(lat_ms.size // nfr),
+                             "mean": round(float(lat_ms.mean()), 4), "max": round(float(lat_ms.max()), 4),
+                             "timed_frames_p50": round(float(np.percentile(frame_ms, 50)), 4)},
         "gbuffer_ms_per_frame": round(gbuffer_ms, 4),
         "frames_per_s_with_gbuffer": round(K / ((total_ms + K * gbuffer_ms) / 1e3), 2),
         "m_sweep": m_sweep,
         "shots": shots,
-        "traversal_grid": grid,
+        "launch_shapes": grid,
         "bvh_build_ms": round(bvh_ms, 3),
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_roofline": stage_roofline(r),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy_judge": judge,
         "workload_4k": w4k,
         "batched": batched,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def ssim_luma(a, b):
+    """Mean SSIM (Wang et al. 2004: 11 x 11 Gaussian window, sigma 1.5,
+    C1 = 0.01^2, C2 = 0.03^2 for a unit range) of the Rec. 709 luma of two
+    H x W x 3 linear-RGB images, over the windows inside the image."""
+    import torch
+    import torch.nn.functional as F
+
+    w709 = torch.tensor([0.2126, 0.7152, 0.0722], dtype=torch.float64, device=a.device)
+    la, lb = a.double() @ w709, b.double() @ w709
+    x = torch.arange(11, dtype=torch.float64, device=a.device) - 5.0
+    g = torch.exp(-x * x / (2 * 1.5 ** 2))
+    g = g / g.sum()
+    win = (g[:, None] * g[None, :])[None, None]
+
+    def conv(t):
+        return F.conv2d(t[None, None], win)[0, 0]
+    ma, mb = conv(la), conv(lb)
+    saa, sbb, sab = conv(la * la) - ma * ma, conv(lb * lb) - mb * mb, conv(la * lb) - ma * mb
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    s = ((2 * ma * mb + c1) * (2 * sab + c2)) / ((ma * ma + mb * mb + c1) * (saa + sbb + c2))
+    return float(s.mean())
+
+
+def judge_leg(gs, cams, lens, params, tb, log, frames=(19, 39, 59), spp=64, budgets=(1, 8, 30)):
+    """Accuracy judge (section 5.1 and Fig. 7 compare the hybrid with full ray
+    tracing): the 1080p path rendered frame after frame with history at each
+    ray budget m; at the listed frames the output is compared with the same
+    view fully ray-traced at spp thin-lens rays per full-res pixel
+    (dof_render_reference).  RMSE and PSNR (peak 1) over linear RGB, SSIM on
+    luma.  Outputs are FP16 as in the timed run; everything else untimed."""
+    import dataclasses
+
+    import torch
+
+    from paper_2210_06158_amd import dof
+
+    W, H = cams[0].width, cams[0].height
+    refs, ref_ms = {}, []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for f in frames:
+        e0.record()
+        refs[f] = gs.render_reference(cams[f], lens, spp)[..., :3]
+        e1.record()
+        torch.cuda.synchronize()
+        ref_ms.append(e0.elapsed_time(e1))
+    gbs = {}
+    out = {"frames": list(frames), "spp": spp, "reference_ms_per_frame": round(sum(ref_ms) / len(ref_ms), 2),
+           "reference_grays_per_s": round(W * H * spp / (sum(ref_ms) / len(ref_ms) * 1e-3) / 1e9, 3)}
+    for m in budgets:
+        pm = dataclasses.replace(params, m=m)
+        fr = frame_for(W, H, pm, tb)
+        hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
+        res = []
+        for f in range(max(frames) + 1):
+            if f not in gbs:
+                gbs[f] = gs.render_gbuffer(cams[f], lens, fmt=dof.RGBA16F)
+            fr.render(gs, cams[f], lens, gbs[f], hist[(f + 1) % 2] if f else None, hist[f % 2],
+                      prev_cam=cams[f - 1] if f else None, prev_lens=lens)
+            if f in refs:
+                img = fr.colour[..., :3].float()
+                mse = float(((img.double() - refs[f].double()) ** 2).mean())
+                res.append((mse, ssim_luma(img, refs[f])))
+            if len(gbs) > 8 and f - 4 in gbs:
+                del gbs[f - 4]
+        mse = sum(r[0] for r in res) / len(res)
+        out[f"m{m}"] = {"rmse": round(mse ** 0.5, 5), "psnr_db": round(-10.0 * math.log10(mse), 3),
+                        "ssim_luma": round(sum(r[1] for r in res) / len(res), 5)}
+        del fr, hist
+    gbs.clear()
+    log(f"judge: {out}")
+    torch.cuda.synchronize()
+    return out
 
 
 def uhd_leg(args, log):
@@ -471,9 +625,9 @@ def uhd_leg(args, log):
     gs.build_bvh()
     gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams, lenses)]
     torch.cuda.synchronize()
-    tb, grid = args.trace_blocks, None
-    if tb < 0:
-        tb, grid = autotune_grid(gs, cams, lenses, params, gbs, log, "4k")
+    tb, grid = {"trace_blocks": args.trace_blocks}, None
+    if args.trace_blocks < 0:
+        tb, grid = autotune(gs, cams, lenses, params, gbs, log, "4k")
     r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), tb, log)
     out = {
         "workload": "3840x2160, box city (130k boxes) behind a chain-link fence of 200k wire quads at depth 1-2, "
@@ -493,7 +647,7 @@ def uhd_leg(args, log):
     # aperture (the polygonal-bokeh extension named in section 2)
     import dataclasses
     rp = run_path(gs, cams, lenses, dataclasses.replace(params, pp_polygon=1), gbs, 20, 5, 20, tb, log)
-    out["traversal_grid"] = grid
+    out["launch_shapes"] = grid
     out["hexagonal_pp_gather"] = {"frames_per_s": round(rp["K"] / (rp["total_ms"] / 1e3), 2),
                                   "gather_ms": round(rp["stage_ms"]["gather"], 4)}
     log(f"4k: {out['frames_per_s']} frames/s")
@@ -532,15 +686,18 @@ def batched_leg(n_sessions, steps, warmup, log):
         s.prepare(2)
     tuners = {}
 
-    def trial(tb):
-        if tb not in tuners:
-            tuners[tb] = dof.Batch(n_sessions, ss[0].params, trace_blocks=tb)
-        tuners[tb].set([s.item() for s in ss])
-        tuners[tb].run()
-    best_tb, tune_ms = tune.tune(trial, tune.candidate_blocks(), reps=2)
+    def trial(cfg):
+        key = tuple(sorted(cfg.items()))
+        if key not in tuners:
+            btb, bkn = tune.split(cfg)
+            tuners[key] = dof.Batch(n_sessions, ss[0].params, trace_blocks=btb, knobs=bkn)
+        tuners[key].set([s.item() for s in ss])
+        tuners[key].run()
+    best_cfg, tune_ms = tune.search(trial)
     del tuners
-    log(f"batched: traversal grid {best_tb} ({tune_ms})")
-    batch = dof.Batch(n_sessions, ss[0].params, trace_blocks=best_tb)
+    log(f"batched: launch shapes {best_cfg} ({tune_ms})")
+    best_tb, best_knobs = tune.split(best_cfg)
+    batch = dof.Batch(n_sessions, ss[0].params, trace_blocks=best_tb, knobs=best_knobs)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def run(mode, graph=None):
@@ -613,8 +770,8 @@ def batched_leg(n_sessions, steps, warmup, log):
                     for m, t in (("per_session", t_single), ("batched", t_batch), ("graph", t_graph))},
         "masked_grays_per_s_batched": round(r_batch / (t_batch.sum() * 1e-3) / 1e9, 4),
         "outputs_identical_across_modes": bool(same),
-        "autotuned_trace_blocks": best_tb if best_tb else "library default",
-        "autotune_ms": {str(k if k else "default"): round(v, 3) for k, v in tune_ms.items()},
+        "autotuned": {k: (v if v else "library default") if k == "trace_blocks" else v for k, v in best_cfg.items()},
+        "autotune_ms": {k: {str(c): round(t, 3) for c, t in v.items()} for k, v in tune_ms.items()},
         "rays_identical_across_modes": r_single == r_batch == r_graph,
     }
     log(f"batched: {out}")
@@ -646,6 +803,21 @@ def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
     single = run("single", 1, 1)
     single2 = run("single", 1, 2)
     batched = {mb: run("batched", mb, 2) for mb in (8, 16, 32)}
+    # the same sessions at an offered load the GPU can carry: 0.7 of the
+    # frames/s that batching sustained under overload, spread evenly over the
+    # sessions as Poisson streams
+    capacity = max(v["frames_per_s"] for v in batched.values())
+    rate70 = 0.7 * capacity / max(admitted, 1)
+    arr70 = serve.poisson_arrivals(n_sessions, rate70, seconds, seed=synth.BASE_SEED + 6300)
+    warm70 = serve.poisson_arrivals(n_sessions, rate70, 0.3, seed=synth.BASE_SEED + 6400)
+
+    def run70(mode, mb, mi):
+        srv.run(warm70, 0.3, mode=mode, max_batch=mb, max_inflight=mi)
+        return srv.run(arr70, seconds, mode=mode, max_batch=mb, max_inflight=mi)
+
+    at70 = {"rate_hz_per_session": round(rate70, 3), "offered_frames_per_s": round(len(arr70) / seconds, 1),
+            "one_frame_at_a_time": run70("single", 1, 1), "batched_max_batch_8": run70("batched", 8, 2),
+            "batched_max_batch_32": run70("batched", 32, 2)}
     res = {}
     for s in srv.sessions:
         key = f"{s.W}x{s.H}"
@@ -664,6 +836,8 @@ def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
         "batched": {f"max_batch_{k}": v for k, v in batched.items()},
         "speedup_frames_per_s_batched32_vs_one_at_a_time": round(batched[32]["frames_per_s"] /
                                                                  max(single["frames_per_s"], 1e-9), 3),
+        "capacity_frames_per_s": round(capacity, 1),
+        "at_70pct_of_capacity": at70,
     }
     log(f"serving: {out}")
     del srv
@@ -671,36 +845,85 @@ def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
     return out
 
 
-def cpu_baseline(scene, cams, lens, params, budget_s, log):
-    """The CPU oracle timed on this host on a bounded sample of the same
-    workload (whole frames of the 1080p path; G-buffer rendered untimed)."""
+def cpu_baseline(scene, cams, lens, params, log):
+    """The CPU oracle (as it stands) timed on this host, on bounded samples of
+    the same workloads, with all the threads this process may use (at most
+    16, the CPU share of a one-GPU machine) and with one thread.
+
+    * 1080p path: the oracle's LBVH build of 1,183,042 triangles (sequential
+      code), then frames 0-2 of the path with history (G-buffers rendered
+      untimed) on all threads -- the reported value -- and frame 0 on one.
+    * 256 x 256 workload: frame 0 and frame 1 (with history), all threads and
+      one.
+    * Accuracy judge: 64 thin-lens rays through each of 16,384 full-res pixels
+      of frame 0 (a strided sample of the 1080p frame), all threads."""
+    import dataclasses
+
+    import numpy as np
+
     import oracle
+    from paper_2210_06158_amd import synth
+
     try:
-        cores = len(os.sched_getaffinity(0))
+        avail = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    oracle.set_threads(cores)
-    osc = oracle.OracleScene(scene)
-    t = time.perf_counter()
-    osc.build_bvh()
-    bvh_s = time.perf_counter() - t
-    done, spent = 0, 0.0
-    hist, prev = None, None
-    for f in range(len(cams)):
-        gb = oracle.gbuffer(osc, cams[f], lens)
+        avail = os.cpu_count() or 1
+    threads = max(1, min(avail, 16))
+
+    def timed(fn):
         t = time.perf_counter()
-        out = oracle.render_frame(osc, cams[f], lens, params, gb, hist_in=hist, prev_cam=prev, prev_lens=lens,
-                                  debug=False)
-        spent += time.perf_counter() - t
-        done += 1
-        hist, prev = out["hist_out"], cams[f]
-        log(f"cpu oracle frame {f}: {spent:.2f} s total")
-        if spent >= budget_s or done >= 10:
-            break
-    return {"value": round(done / spent, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} consecutive 1080p frames of the same camera path (G-buffer rendered untimed), "
-                      f"oracle BVH build {bvh_s:.2f} s untimed"}
+        r = fn()
+        return r, time.perf_counter() - t
+
+    oracle.set_threads(threads)
+    osc = oracle.OracleScene(scene)
+    _, bvh_s = timed(osc.build_bvh)
+    log(f"cpu oracle: 1080p BVH {bvh_s:.2f} s")
+    gbs = [oracle.gbuffer(osc, cams[f], lens) for f in range(3)]
+
+    def path(nf):
+        hist, prev = None, None
+        for f in range(nf):
+            out = oracle.render_frame(osc, cams[f], lens, params, gbs[f], hist_in=hist, prev_cam=prev,
+                                      prev_lens=lens, debug=False)
+            hist, prev = out["hist_out"], cams[f]
+        return out
+
+    _, all3 = timed(lambda: path(3))
+    log(f"cpu oracle: 3 frames on {threads} threads {all3:.2f} s")
+    oracle.set_threads(1)
+    _, one1 = timed(lambda: path(1))
+    log(f"cpu oracle: frame 0 on one thread {one1:.2f} s")
+
+    s_scene, s_cam, s_lens, s_params = synth.scene_small()
+    sosc = oracle.OracleScene(s_scene)
+    sosc.build_bvh()
+    s_cam1 = synth.pan_camera(s_cam, 0.02)
+    s_gbs = [oracle.gbuffer(sosc, c, s_lens) for c in (s_cam, s_cam1)]
+
+    def small():
+        o0 = oracle.render_frame(sosc, s_cam, s_lens, s_params, s_gbs[0], debug=False)
+        oracle.render_frame(sosc, s_cam1, s_lens, s_params, s_gbs[1], hist_in=o0["hist_out"], prev_cam=s_cam,
+                            prev_lens=s_lens, debug=False)
+    _, small1 = timed(small)
+    oracle.set_threads(threads)
+    _, small_all = timed(small)
+
+    W, H = cams[0].width, cams[0].height
+    npx = 16384
+    sample = np.arange(npx, dtype=np.int64) * (W * H // npx)
+    full = dataclasses.replace(cams[0], width=2 * W, height=2 * H)   # its half-res grid is the W x H grid
+    _, judge_s = timed(lambda: oracle.pixel_estimate(osc, full, lens, sample.astype(np.uint32), 64))
+    log(f"cpu oracle: judge sample {judge_s:.2f} s")
+    return {"value": round(3 / all3, 5), "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": "frames 0-2 of the 1080p camera path with history (G-buffers untimed), all threads",
+            "host_cpus": os.cpu_count(), "cpus_available": avail,
+            "single_thread_frames_per_s": round(1 / one1, 5),
+            "lbvh_build_1080p_s": round(bvh_s, 3),
+            "small_256": {"frames": 2, "all_threads_frames_per_s": round(2 / small_all, 3),
+                          "single_thread_frames_per_s": round(2 / small1, 3)},
+            "judge_sample": {"pixels": npx, "spp": 64, "all_threads_mrays_per_s": round(npx * 64 / judge_s / 1e6, 3),
+                             "full_frame_estimate_s": round(judge_s * W * H / npx, 1)}}
 
 
 if __name__ == "__main__":

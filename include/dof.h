@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define DOF_ABI_VERSION 2
+#define DOF_ABI_VERSION 3
 
 typedef int32_t dof_status;
 #define DOF_OK 0
@@ -123,7 +123,31 @@ typedef struct {
      * in the history buffer; turning a stage on mid-sequence needs
      * history.reset. */
     int32_t taa;
-    int32_t reserved[1];
+    /* 1: keep each traced ray's hit id, distance, shaded colour and hit
+     * position in the scratch (40 more bytes per ray of half-res pixels x m)
+     * for dof_debug_view_get; 0 (default): the shading writes none of them */
+    int32_t ray_records;
+    /* Section 3.3 says both that a high hit ratio favours the post-process
+     * colour and that the blend happens only below a hit ratio of 0.3 because
+     * leaning to post-processing above it loses the ray-traced
+     * semi-transparencies.  0 (default): far-field output = lerp(post-process,
+     * ray traced, smoothstep(0, h_edge, h)); 1: the first sentence read
+     * literally, lerp(ray traced, post-process, smoothstep(0, h_edge, h)). */
+    int32_t composite_literal;
+    /* Launch-shape knobs, searched by the autotuner (0 = library default);
+     * no result depends on them.  gather_window: side of the LDS window in
+     * which the post-process gather stages a tile's texels, 32, 40 or 48
+     * (default 48), or -1 to read every tap from global memory.  trace_stack:
+     * LDS traversal stack entries per lane, 16, 24 (default) or 32.
+     * trace_grab: rays a wave takes from the shared work counter at a time,
+     * 1..256 (default 64).  trace_refill: idle lanes at which a wave takes
+     * new rays, 1..64 (default 16).  trace_leaf_batch: lanes with a pending
+     * leaf at which a wave runs its triangle tests, 1..64 (default 32). */
+    int32_t gather_window;
+    int32_t trace_stack;
+    int32_t trace_grab;
+    int32_t trace_refill;
+    int32_t trace_leaf_batch;
 } dof_params;
 
 /* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view
@@ -159,7 +183,8 @@ typedef struct {
     uint32_t rays;          /* thin-lens rays traced */
     uint64_t node_visits;   /* BVH nodes fetched by the traversal */
     uint64_t tri_tests;     /* ray/triangle tests */
-    uint32_t stack_spills;  /* traversal stack chunks moved from LDS to the spill area */
+    uint32_t stack_spills;  /* times a lane's LDS traversal stack was full and dropped its 8 oldest
+                             * entries (found again through parent links; the result is unchanged) */
     uint32_t reserved[1];
 } dof_stats;
 
@@ -199,7 +224,8 @@ typedef struct {
     const void *nodes, *tris;
 } dof_bvh_view;
 
-/* Device pointers into a frame's scratch (valid after dof_render_frame). */
+/* Device pointers into a frame's scratch (valid after dof_render_frame);
+ * ray_hit, ray_t, ray_col and ray_pos are NULL unless params.ray_records. */
 typedef struct {
     void *colr, *zn, *tile_max, *tile_dil, *pre, *gather, *ppmed, *prev_idx;
     void *queue, *ray_base, *ray_hit, *ray_t, *ray_col, *ray_pos;
@@ -210,8 +236,9 @@ int32_t dof_abi_version(void);
 const char *dof_last_error(void);
 void dof_default_params(dof_params *p);
 
-/* Scene arena size for ntri triangles (triangles, BVH, build scratch and a
- * traversal stack spill area of 84 MB). */
+/* Scene arena size for ntri triangles: input and leaf-ordered triangles,
+ * BVH nodes and parent links, and the build's keys, sort buffers and
+ * counters (about 200 bytes per triangle). */
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);
 
 /* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes) on
@@ -237,6 +264,23 @@ dof_status dof_trace_rays(const dof_scene *scene, int64_t n, const float *org, c
 dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
                               void *colour, int32_t colour_format, float *depth, void *normal,
                               int32_t normal_format, void *stream);
+
+/* Ground truth of the accuracy judge (section 5.1 measures the hybrid
+ * against full ray tracing): the thin-lens estimate of every full-res pixel,
+ * the mean shaded colour of spp rays from lens points towards the pixel's
+ * point on the focus plane (section 3.2.2's ray model at full resolution).
+ * Ray k of pixel y * W + x uses the lens sample the pass would give
+ * half-res pixel q = y * W + x of a 2W x 2H frame, so an oracle estimate over
+ * the same counters reproduces it.  Sums each pixel's colours in binary64 in
+ * sample order.  colour: device, W x H in colour_format (alpha 1).
+ * scratch: device, >= dof_reference_scratch_bytes (the (leaf, t) records of
+ * one chunk of at most 2^22 rays, whole pixels).  spp: 1..1024.  Uses the
+ * scene's work counter, like dof_render_gbuffer: not concurrently with
+ * another call on the same scene. */
+dof_status dof_reference_scratch_bytes(int32_t width, int32_t height, int32_t spp, size_t *bytes);
+dof_status dof_render_reference(dof_scene *scene, const dof_camera *cam, const dof_lens *lens, int32_t spp,
+                                void *colour, int32_t colour_format, void *scratch, size_t scratch_bytes,
+                                void *stream);
 
 dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes);
 dof_status dof_history_reset(void *hist, int32_t width, int32_t height, void *stream);
@@ -319,8 +363,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
 /* Renders the items of the last dof_batch_set on `stream`: launches only
  * (no host sync, no allocation), so it may be captured in a HIP graph.  A
  * captured run may be replayed after later dof_batch_set calls whose items
- * have the same count, sizes and order and the same first-item scratch
- * buffer (grid sizes and the traversal's spill area are captured).
+ * have the same count, sizes and order (grid sizes are captured).
  * stats (device pointer, nullable) receives the batch totals. */
 dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream);
 void dof_batch_destroy(dof_batch *b);

@@ -36,7 +36,8 @@ class OrcParams(C.Structure):
                 ("var_recon_w", C.c_float), ("b_max", C.c_float), ("h_edge", C.c_float),
                 ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32),
-                ("l_spec", C.c_float), ("mask_mode", C.c_int32), ("pp_polygon", C.c_int32), ("taa", C.c_int32)]
+                ("l_spec", C.c_float), ("mask_mode", C.c_int32), ("pp_polygon", C.c_int32), ("taa", C.c_int32),
+                ("composite_literal", C.c_int32)]
 
 
 class OrcScene(C.Structure):
@@ -125,7 +126,8 @@ def gather_rings(lens, params):
 def params_struct(p) -> OrcParams:
     return OrcParams(p.m, p.s, p.var_mask_w, p.alpha, p.alpha_motion, p.var_recon_w, p.b_max,
                      p.h_edge, p.lod_scale, p.lod_max, p.depth_range, p.r_max, p.tile,
-                     p.l_spec, p.mask_mode, getattr(p, "pp_polygon", 0), getattr(p, "taa", 0))
+                     p.l_spec, p.mask_mode, getattr(p, "pp_polygon", 0), getattr(p, "taa", 0),
+                     getattr(p, "composite_literal", 0))
 
 
 class OracleScene:

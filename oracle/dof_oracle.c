@@ -1469,7 +1469,10 @@ int orc_render_frame(const orc_scene *s, const orc_bvh *b,
             } else {
                 float t = sat(rh / p->h_edge);
                 float w = (t * t) * (3.0f - 2.0f * t);
-                for (int cc = 0; cc < 3; cc++) o[cc] = lerpf(pp[cc], rc[cc], w);
+                if (p->composite_literal) /* the literal reading of 3.3: high hit ratio -> post-process */
+                    for (int cc = 0; cc < 3; cc++) o[cc] = lerpf(rc[cc], pp[cc], w);
+                else
+                    for (int cc = 0; cc < 3; cc++) o[cc] = lerpf(pp[cc], rc[cc], w);
             }
             o[3] = 1.0f;
         }

@@ -54,6 +54,7 @@ typedef struct {
     int32_t mask_mode;                      /* 0 adaptive, 1 fixed, 2 all, 3 adaptive dilated by the neighbourhood max CoC */
     int32_t pp_polygon;                     /* 1: post-process gather taps on the aperture polygon (bladed lenses) */
     int32_t taa;                            /* TAA stages (3.4), bits ORC_TAA_*; history planes after the record */
+    int32_t composite_literal;              /* 1: far-field blend read literally (high hit ratio -> post-process) */
 } orc_params;
 
 typedef struct {

@@ -8,6 +8,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dof_internal.h"
 
 struct dof_scene {
@@ -27,11 +29,17 @@ namespace {
 
 thread_local char g_err[512] = "";
 
+dof_status vfail(dof_status code, const char *fmt, va_list ap)
+{
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    return code;
+}
+
 dof_status fail(dof_status code, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    vfail(code, fmt, ap);
     va_end(ap);
     return code;
 }
@@ -42,16 +50,24 @@ dof_status fail(dof_status code, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(DOF_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// A roctx range over the host side of an entry point (its argument checks
+// and launches); rocprofv3 --marker-trace records it, otherwise it costs a
+// call into an inert library.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct SceneLayout {
     size_t verts_in, albedo_in, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp, flags, hist, bounds;
-    size_t aux, spill, total;
+    size_t aux, total;
     int sort_blocks, bound_blocks;
 };
-
-constexpr size_t kSpillBytes = sizeof(uint32_t) * (size_t)dof::kSpillPerThread * dof::kTB * (size_t)dof::kMaxTraceBlocks;
 
 SceneLayout scene_layout(int64_t n)
 {
@@ -79,12 +95,11 @@ SceneLayout scene_layout(int64_t n)
     L.hist = take(sizeof(uint32_t) * 256 * ((size_t)L.sort_blocks + 1));
     L.bounds = take(sizeof(float) * (6 * (size_t)L.bound_blocks + 8));
     L.aux = take(64);
-    L.spill = take(kSpillBytes);
     L.total = off;
     return L;
 }
 
-dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
+dof::ScratchLayout frame_layout(int W, int H, int m, int taa, int ray_records)
 {
     dof::ScratchLayout L{};
     const size_t np = (size_t)(W / 2) * (H / 2);
@@ -117,10 +132,12 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
     L.ray_pix = take(4 * nr);
     L.ray_rec = take(48 * nr);   // three float4 planes of nr
     L.ray_lt = take(8 * nr);
-    L.ray_hit = take(4 * nr);
-    L.ray_t = take(4 * nr);
-    L.ray_col = take(16 * nr);
-    L.ray_pos = take(16 * nr);
+    if (ray_records) {   // per-ray hit id, distance, colour and position, for inspection only
+        L.ray_hit = take(4 * nr);
+        L.ray_t = take(4 * nr);
+        L.ray_col = take(16 * nr);
+        L.ray_pos = take(16 * nr);
+    }
     L.resolve = take(64 * np);
     L.temporal = take(32 * np);
     L.var_blur = take(4 * np);
@@ -138,7 +155,6 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa)
     L.comp = (taa & DOF_TAA_FINAL) ? take(16 * (size_t)W * H) : 0;   // composite colour before the final TAA
     L.rast = (taa & DOF_TAA_RASTER) ? take(16 * (size_t)W * H) : 0;  // raster colour after its TAA
     L.pptaa = (taa & DOF_TAA_POST) ? take(16 * np) : 0;              // post-filter output after its TAA
-    L.spill = take(kSpillBytes);
     L.total = off;
     return L;
 }
@@ -285,12 +301,32 @@ dof_status params_check(const dof_params *p)
     if (p->mask_mode < 0 || p->mask_mode > 3) return fail(DOF_E_INVALID, "bad mask_mode");
     if (p->pp_polygon != 0 && p->pp_polygon != 1) return fail(DOF_E_INVALID, "bad pp_polygon");
     if (p->taa < 0 || p->taa > (DOF_TAA_FINAL | DOF_TAA_RASTER | DOF_TAA_POST)) return fail(DOF_E_INVALID, "bad taa");
+    if (p->ray_records != 0 && p->ray_records != 1) return fail(DOF_E_INVALID, "bad ray_records");
+    if (p->composite_literal != 0 && p->composite_literal != 1) return fail(DOF_E_INVALID, "bad composite_literal");
+    if (p->gather_window != 0 && p->gather_window != -1 && p->gather_window != 32 && p->gather_window != 40 &&
+        p->gather_window != 48)
+        return fail(DOF_E_INVALID, "gather_window must be 0, -1, 32, 40 or 48");
+    if (p->trace_stack != 0 && p->trace_stack != 16 && p->trace_stack != 24 && p->trace_stack != 32)
+        return fail(DOF_E_INVALID, "trace_stack must be 0, 16, 24 or 32");
+    if (p->trace_grab < 0 || p->trace_grab > 256 || p->trace_refill < 0 || p->trace_refill > 64 ||
+        p->trace_leaf_batch < 0 || p->trace_leaf_batch > 64)
+        return fail(DOF_E_INVALID, "trace_grab must be in 0..256, trace_refill and trace_leaf_batch in 0..64");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
     if (!(p->lod_max >= 0.0f)) return fail(DOF_E_INVALID, "bad lod_max");
     if (p->trace_blocks < 0 || p->trace_blocks > dof::kMaxTraceBlocks) return fail(DOF_E_INVALID, "bad trace_blocks");
     return DOF_OK;
+}
+
+dof::TraceKnobs trace_knobs(const dof_params &p)
+{
+    dof::TraceKnobs k;
+    k.stack = p.trace_stack ? p.trace_stack : dof::kStackLds;
+    k.grab = p.trace_grab ? (uint32_t)p.trace_grab : 64u;
+    k.refill = p.trace_refill ? p.trace_refill : 16;
+    k.leaf_batch = p.trace_leaf_batch ? p.trace_leaf_batch : 32;
+    return k;
 }
 
 void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens &lens, const dof_params &p,
@@ -310,6 +346,10 @@ void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens 
     fc.m = p.m;
     fc.mask_mode = p.mask_mode;
     fc.taa = p.taa;
+    fc.ray_records = p.ray_records;
+    fc.composite_literal = p.composite_literal;
+    fc.gather_win = p.gather_window == 0 ? 48 : (p.gather_window < 0 ? 0 : p.gather_window);
+    fc.tk = trace_knobs(p);
     fc.have_hist = have_hist;
     fc.motion = motion;
     fc.seed = cam.seed;
@@ -355,14 +395,14 @@ bool same_view(const dof_camera &a, const dof_camera &b, const dof_lens &la, con
            memcmp(&la, &lb, sizeof(la)) == 0;
 }
 
-int default_trace_blocks(bool batch = false)
+int default_trace_blocks(bool batch = false, int stack = dof::kStackLds)
 {
     // as many 128-thread blocks as fit on the device at once (registers and
-    // the LDS stack decide), capped by the spill-buffer size
+    // the LDS stack decide), capped at the grid limit
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
-    per_cu = dof::trace_blocks_per_cu(batch);
+    per_cu = dof::trace_blocks_per_cu(batch, stack);
     if (per_cu <= 0) per_cu = 5;
     const int b = cus * per_cu;
     return b > dof::kMaxTraceBlocks ? dof::kMaxTraceBlocks : b;
@@ -392,13 +432,25 @@ dof_status check_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
     if (!rays_fit(cam->width, cam->height, p->m))
         return fail(DOF_E_UNSUPPORTED, "half-res pixels x m exceeds 2^31 rays per frame");
-    L = frame_layout(cam->width, cam->height, p->m, p->taa);
+    L = frame_layout(cam->width, cam->height, p->m, p->taa, p->ray_records);
     if (scratch_bytes < L.total) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", L.total, scratch_bytes);
     have_hist = !hist->reset && hist->in && hist->prev_camera.width == cam->width &&
                 hist->prev_camera.height == cam->height && lens_ok(&hist->prev_lens);
     const bool motion = have_hist && !same_view(*cam, hist->prev_camera, *lens, hist->prev_lens);
     fill_frame_const(scene, *cam, *lens, *p, have_hist, motion, hist->prev_camera, hist->prev_lens, fc);
     return DOF_OK;
+}
+
+// The ground-truth renderer traces at most this many rays per traversal
+// launch (whole pixels); its scratch holds their 8-byte (leaf, t) records.
+constexpr int64_t kRefChunkRays = (int64_t)1 << 22;
+constexpr int kRefMaxSpp = 1024;
+
+int64_t reference_chunk_px(int width, int height, int spp)
+{
+    const int64_t px = (int64_t)width * height;
+    const int64_t c = kRefChunkRays / spp;
+    return c < px ? (c < 1 ? 1 : c) : px;
 }
 
 const dof::Rings &ring_table()
@@ -421,11 +473,12 @@ struct dof_batch {
     int32_t max_items;
     int32_t n;                         // jobs of the current set (0 = none)
     uint32_t nblk[dof::kNumGrids];     // total blocks of each grid shape
-    uint32_t *spill;                   // traversal spill (first frame's scratch)
     int32_t trace_blocks;
     bool dilate;                       // params.mask_mode == DOF_MASK_DILATE
     int64_t max_rays;                  // sum over the items of half-res pixels x m
     int taa;                           // params.taa (DOF_TAA_* bits)
+    int gather_win;                    // the gather's LDS window (params.gather_window)
+    dof::TraceKnobs tk;                // traversal launch knobs (params.trace_*)
     std::vector<char> host;            // staging copy of the table
 };
 
@@ -495,7 +548,6 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
     d.hist = reinterpret_cast<uint32_t *>(a + L.hist);
     d.bounds = reinterpret_cast<float *>(a + L.bounds);
     d.aux = reinterpret_cast<uint32_t *>(a + L.aux);
-    d.spill = reinterpret_cast<uint32_t *>(a + L.spill);
     d.sort_blocks = L.sort_blocks;
     d.bound_blocks = L.bound_blocks;
     memcpy(s->shade.light_dir, desc->light_dir, sizeof(desc->light_dir));
@@ -531,6 +583,7 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
 
 dof_status dof_build_bvh(dof_scene *scene, void *stream)
 {
+    const Range range("dof_build_bvh");
     if (!scene) return fail(DOF_E_INVALID, "scene is NULL");
     DOF_HIP(dof::launch_build_bvh(scene->dev, static_cast<hipStream_t>(stream)));
     scene->built = true;
@@ -592,6 +645,38 @@ dof_status dof_render_gbuffer(const dof_scene *scene, const dof_camera *cam, con
     return DOF_OK;
 }
 
+dof_status dof_reference_scratch_bytes(int32_t width, int32_t height, int32_t spp, size_t *bytes)
+{
+    if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
+        return fail(DOF_E_INVALID, "width/height must be even and positive");
+    if ((int64_t)width * height > (int64_t)1 << 30) return fail(DOF_E_INVALID, "image too large");
+    if (spp < 1 || spp > kRefMaxSpp) return fail(DOF_E_INVALID, "spp must be in 1..%d", kRefMaxSpp);
+    *bytes = sizeof(uint2) * (size_t)(reference_chunk_px(width, height, spp) * spp);
+    return DOF_OK;
+}
+
+dof_status dof_render_reference(dof_scene *scene, const dof_camera *cam, const dof_lens *lens, int32_t spp,
+                                void *colour, int32_t colour_format, void *scratch, size_t scratch_bytes, void *stream)
+{
+    const Range range("dof_render_reference");
+    if (!scene || !camera_ok(cam) || !lens_ok(lens) || !colour || !scratch)
+        return fail(DOF_E_INVALID, "dof_render_reference: bad arguments");
+    if (colour_format != DOF_RGBA32F && colour_format != DOF_RGBA16F) return fail(DOF_E_INVALID, "bad format");
+    size_t need = 0;
+    dof_status st = dof_reference_scratch_bytes(cam->width, cam->height, spp, &need);
+    if (st != DOF_OK) return st;
+    if (scratch_bytes < need) return fail(DOF_E_NOMEM, "scratch needs %zu bytes, got %zu", need, scratch_bytes);
+    if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
+    dof_params p;
+    dof_default_params(&p);
+    dof::FrameConst fc;
+    fill_frame_const(scene, *cam, *lens, p, false, false, *cam, *lens, fc);
+    DOF_HIP(dof::launch_reference(scene->dev, fc, spp, static_cast<uint2 *>(scratch),
+                                  reference_chunk_px(cam->width, cam->height, spp), colour, colour_format,
+                                  default_trace_blocks(), static_cast<hipStream_t>(stream)));
+    return DOF_OK;
+}
+
 dof_status dof_history_bytes(int32_t width, int32_t height, size_t *bytes)
 {
     if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || !bytes)
@@ -619,7 +704,7 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
     if (!rays_fit(width, height, p->m)) return fail(DOF_E_UNSUPPORTED, "half-res pixels x m exceeds 2^31 rays per frame");
-    *bytes = frame_layout(width, height, p->m, p->taa).total;
+    *bytes = frame_layout(width, height, p->m, p->taa, p->ray_records).total;
     return DOF_OK;
 }
 
@@ -627,6 +712,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
                             const dof_history_io *hist, const dof_params *p, const dof_frame_out *out, void *scratch,
                             size_t scratch_bytes, void *stream)
 {
+    const Range range("dof_render_frame");
     dof::ScratchLayout L;
     dof::FrameConst fc;
     bool have_hist = false;
@@ -646,7 +732,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
     }
     const dof::SideStream *side = (ev == nullptr && scene->side_ready) ? &scene->side : nullptr;
     DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, side, s));
-    const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks();
+    const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(false, fc.tk.stack);
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
     DOF_HIP(dof::launch_frame_post(scene->dev, fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, side, s));
     scene->timed_frame = ev != nullptr;
@@ -712,7 +798,8 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         J.hist_out = it.history.out;
         J.mask = it.out.mask;
         J.out = it.out;
-        J.scene = dof::SceneArgs{it.scene->dev.ntri, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes};
+        J.scene = dof::SceneArgs{it.scene->dev.ntri, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes,
+                                 it.scene->dev.parent};
         J.grings = gather_rings(it.lens, *p);
         const dof::FrameConst &fc = J.fc;
         const int64_t np = (int64_t)fc.hw * fc.hh;
@@ -730,14 +817,15 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
             if (t > 0x7fffffffu) return fail(DOF_E_INVALID, "batch too large for one launch");
             tot[g] = (uint32_t)t;
         }
-        if (i == 0) b->spill = reinterpret_cast<uint32_t *>(scr + L.spill);
     }
     DOF_HIP(hipMemcpyAsync(b->table, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
                            static_cast<hipStream_t>(stream)));
     for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
-    b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true);
+    b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true, jobs[0].fc.tk.stack);
     b->dilate = p->mask_mode == DOF_MASK_DILATE;
     b->taa = p->taa;
+    b->gather_win = jobs[0].fc.gather_win;
+    b->tk = jobs[0].fc.tk;
     b->max_rays = max_rays;
     b->n = n;
     return DOF_OK;
@@ -745,14 +833,15 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
 
 dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
 {
+    const Range range("dof_batch_run");
     if (!b) return fail(DOF_E_INVALID, "batch is NULL");
     if (b->n < 1) return fail(DOF_E_STATE, "no items set");
     hipStream_t s = static_cast<hipStream_t>(stream);
     dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->table);
     const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
     const dof::Rings &rings = ring_table();
-    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, s));
-    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->spill, b->trace_blocks, b->max_rays, s));
+    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, b->gather_win, s));
+    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->trace_blocks, b->max_rays, b->tk, s));
     DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
     return DOF_OK;
@@ -777,7 +866,7 @@ dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, cons
         return fail(DOF_E_INVALID, "bad arguments");
     dof_status st = params_check(p);
     if (st != DOF_OK) return st;
-    const dof::ScratchLayout L = frame_layout(width, height, p->m, p->taa);
+    const dof::ScratchLayout L = frame_layout(width, height, p->m, p->taa, p->ray_records);
     char *s = static_cast<char *>(scratch);
     out->colr = s + L.colr;
     out->zn = s + L.zn;
@@ -789,10 +878,11 @@ dof_status dof_debug_view_get(void *scratch, int32_t width, int32_t height, cons
     out->prev_idx = s + L.prev_idx;
     out->queue = s + L.queue;
     out->ray_base = s + L.ray_base;
-    out->ray_hit = s + L.ray_hit;
-    out->ray_t = s + L.ray_t;
-    out->ray_col = s + L.ray_col;
-    out->ray_pos = s + L.ray_pos;
+    const bool rec = p->ray_records != 0;
+    out->ray_hit = rec ? s + L.ray_hit : nullptr;
+    out->ray_t = rec ? s + L.ray_t : nullptr;
+    out->ray_col = rec ? s + L.ray_col : nullptr;
+    out->ray_pos = rec ? s + L.ray_pos : nullptr;
     out->resolve = s + L.resolve;
     out->temporal = s + L.temporal;
     out->var_blur = s + L.var_blur;

@@ -18,13 +18,10 @@ constexpr float kSqrt2 = 1.41421356237f;  // one pixel diagonal (3.1.1, 3.3)
 constexpr int kTile = 16;                 // neighbourhood-max tile side
 constexpr int kRingTaps = 81;             // 1 + 8 + 16 + 24 + 32 (3.1.1)
 constexpr int kMaxBlades = 16;
-// The binary tree over 95 significant key bits is at most 95 deep, and the
-// traversal pushes at most one entry (node, entry distance) per level.
-constexpr int kStackLds = 24;             // traversal stack entries kept in LDS
-constexpr int kStackMax = 96;
-constexpr int kSpillPerThread = kStackMax - kStackLds;   // entries beyond LDS live in global memory
+constexpr int kStackLds = 24;             // default traversal stack entries per lane (LDS only; deeper
+                                          // work is found again through parent links); 16 and 32 also built
 constexpr int kTB = 128;                  // threads per traversal block
-constexpr int kMaxTraceBlocks = 4096;     // persistent traversal grid limit (spill buffers sized for it)
+constexpr int kMaxTraceBlocks = 4096;     // persistent traversal grid limit
 
 // ---------------------------------------------------------------- scene
 
@@ -53,7 +50,6 @@ struct SceneDev {
     uint32_t *hist;          // radix histograms (digit-major) + 256 digit offsets
     float *bounds;           // 6 partial-bound slots per reduce block + 8 final
     uint32_t *aux;           // 64 B: work counter of the scene-level traversal kernels
-    uint32_t *spill;         // traversal stack spill of the scene-level kernels
     int32_t sort_blocks;
     int32_t bound_blocks;
 };
@@ -85,9 +81,20 @@ __device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h,
     for (int a = 0; a < 3; ++a) fv[a] = (v.fwd[a] + u * v.right[a]) + vv * v.up[a];
 }
 
+// Launch-shape knobs of the traversal (dof_params.trace_*; results do not
+// depend on them).
+struct TraceKnobs {
+    int32_t stack;        // LDS stack entries per lane: 16, 24 or 32
+    uint32_t grab;        // rays per take from the shared work counter
+    int32_t refill;       // idle lanes that trigger a refill
+    int32_t leaf_batch;   // lanes with a pending leaf that trigger the triangle tests
+};
+
 struct FrameConst {
     int32_t W, H, hw, hh, tw, th, T, D;
-    int32_t m, mask_mode, have_hist, motion, taa;
+    int32_t gather_win;       // LDS window side of the gather (0: none)
+    TraceKnobs tk;
+    int32_t m, mask_mode, have_hist, motion, taa, ray_records, composite_literal;
     uint32_t seed, frame;
     float d, half_a, cock, znb, ramp;
     float s, var_mask_w, alpha_h, var_recon_w, b_max, h_edge, lod_scale, lod_max, depth_range;
@@ -106,7 +113,6 @@ struct ScratchLayout {
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_rec, ray_lt, ray_hit, ray_t, ray_col, ray_pos;
     size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
-    size_t spill;
     size_t total;
     int64_t nchunks;
 };
@@ -120,7 +126,7 @@ struct Planes {
     int32_t *prev_idx;
     uint2 *chunk_cnt, *chunk_off;
     uint32_t *counters, *queue, *ray_base, *ray_pix;
-    int32_t *ray_hit;
+    int32_t *ray_hit;        // per-ray planes: nullptr unless params.ray_records
     float *ray_t;
     float4 *ray_col, *ray_pos;
     float4 *rec0, *rec1, *rec2;   // ray records: (o, d.x), (d.y, d.z, sx, sy), (sz, 1/d) per ray
@@ -146,6 +152,7 @@ struct SceneArgs {
     const float4 *__restrict__ tris;
     const float4 *__restrict__ albedo;
     const BvhNode *__restrict__ nodes;
+    const uint32_t *__restrict__ parent;   // parent of each internal node (root: ~0u)
 };
 
 // ---------------------------------------------------------------- batches
@@ -226,7 +233,7 @@ __device__ inline float coc_px(float cock, float d, float z) { return cock * fab
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 
 // trace.hip
-int trace_blocks_per_cu(bool batch);   // resident blocks of the lens-ray traversal per CU
+int trace_blocks_per_cu(bool batch, int stack);   // resident blocks of the lens-ray traversal per CU
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
 // the ray records of every thin-lens ray of the frame (after the compaction)
@@ -324,6 +331,10 @@ hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour,
                           void *normal, int nfmt, int blocks, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, const float *dir, int32_t *hit,
                              float *t, int blocks, hipStream_t st);
+// spp thin-lens rays through every full-res pixel of fc's view, chunk_px
+// pixels per traversal launch; lt holds chunk_px * spp (leaf, t) records
+hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, uint2 *lt, int64_t chunk_px, void *colour,
+                            int cfmt, int blocks, hipStream_t st);
 
 // frame.hip
 // The post-process chain (prefilter, gather, median, post-filter TAA) reads
@@ -347,10 +358,10 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
 // total blocks of grid g over the jobs
 hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                            const Rings &rings, bool dilate, int taa, hipStream_t st);
+                            const Rings &rings, bool dilate, int taa, int gather_win, hipStream_t st);
 // max_rays: the sum over the jobs of half-res pixels x m (sizes the ray generation grid)
-hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks, int64_t max_rays,
-                              hipStream_t st);
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, int64_t max_rays,
+                              const TraceKnobs &tk, hipStream_t st);
 hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
                              const Rings &rings, int taa, hipStream_t st);
 

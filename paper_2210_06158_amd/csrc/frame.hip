@@ -180,10 +180,11 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.queue = reinterpret_cast<uint32_t *>(s + L.queue);
     p.ray_base = reinterpret_cast<uint32_t *>(s + L.ray_base);
     p.ray_pix = reinterpret_cast<uint32_t *>(s + L.ray_pix);
-    p.ray_hit = reinterpret_cast<int32_t *>(s + L.ray_hit);
-    p.ray_t = reinterpret_cast<float *>(s + L.ray_t);
-    p.ray_col = reinterpret_cast<float4 *>(s + L.ray_col);
-    p.ray_pos = reinterpret_cast<float4 *>(s + L.ray_pos);
+    const bool rec = fc.ray_records != 0;
+    p.ray_hit = rec ? reinterpret_cast<int32_t *>(s + L.ray_hit) : nullptr;
+    p.ray_t = rec ? reinterpret_cast<float *>(s + L.ray_t) : nullptr;
+    p.ray_col = rec ? reinterpret_cast<float4 *>(s + L.ray_col) : nullptr;
+    p.ray_pos = rec ? reinterpret_cast<float4 *>(s + L.ray_pos) : nullptr;
     const size_t nr = np * (size_t)fc.m;
     p.rec0 = reinterpret_cast<float4 *>(s + L.ray_rec);
     p.rec1 = p.rec0 + nr;
@@ -325,12 +326,15 @@ __device__ inline void b_prefilter(const FrameConst &fc, const Planes &P, const 
             az = az + w * v.z;
             sw = sw + w;
         }
-    P.pre[i] = make_float4(ax / sw, ay / sw, az / sw, rc);
+    const float4 pre = make_float4(ax / sw, ay / sw, az / sw, rc);
+    P.pre[i] = pre;
     // depth and the gather's per-tap weight of this pixel (sampleAlpha of
     // eq. 1 read as 1 / max(|r|, 1/2)^2), computed once here instead of at
-    // each of the 81 taps that read this pixel
+    // each of the 81 taps that read this pixel; its sign carries whether the
+    // pixel counts as a bright (specular) sample of the bokeh share
     const float mr = fmax_cs(fabsf(rc), 0.5f);
-    P.za[i] = make_float2(P.zh[i], 1.0f / (mr * mr));
+    const float alpha = 1.0f / (mr * mr);
+    P.za[i] = make_float2(P.zh[i], luma709(pre.x, pre.y, pre.z) > fc.l_spec ? -alpha : alpha);
 }
 
 __global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
@@ -347,55 +351,160 @@ __global__ __launch_bounds__(kBX *kBY) void kb_prefilter(const Job *__restrict__
 
 // ---------------------------------------------------------------- A4
 
-__device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
+// One block of 256 threads per 16 x 16 tile of half-res pixels, the tile of
+// the neighbourhood-maximum CoC, so the kernel radius R_n and with it every
+// tap offset is the same for the whole block.  Each tap's texel column
+// (per pixel column of the tile) and row (per pixel row) are computed once
+// per block into LDS tables, with the same binary32 operations as the
+// per-pixel definition, so the nearest-texel decisions are identical.  A
+// tile whose taps stay within kGatherWin x kGatherWin texels (R_n <= 15)
+// first stages that window of the prefiltered colour and the (depth, weight)
+// plane in LDS and reads its taps there; a wider tile reads them from global
+// memory (L1/L2), in a second kernel that needs little LDS and so keeps
+// many waves resident.  The window side (32, 40 or 48, or no staging) is a
+// launch knob of the autotuner.
+//
+// Per tap, with D_fg = [|r_i| > dist] and D_bg = D_fg and [|r_c| > dist]:
+// the two weights of eq. (1) add up to alpha when D_bg holds (foreground and
+// background shares of one tap), to alpha (1 - w_bg) when only D_fg holds,
+// and to 0 otherwise, so one weighted sum replaces the two and w_bg (with its
+// division) is evaluated only where it matters.  Sums are reassociated
+// relative to the per-pixel definition (tolerance parity); the weights'
+// zero/non-zero pattern, and so the empty-kernel fallback, is unchanged.
+// Whether a tile's taps fit a win x win texel window (win 0: no staging).
+__device__ inline bool gather_fits(float Rn, int win) { return win > 0 && kTile + 2 * ((int)ceilf(Rn) + 1) <= win; }
+
+// The taps of one ring (one distance): kBg when some lane of the wave has a
+// centre radius at or below the ring's distance, so that its background taps
+// need w_bg (a wave-uniform choice; the division runs only then).
+template <bool kLds, bool kBg>
+__device__ inline void gather_ring(const Rings &rings, const Planes &P, const float4 *s_pre, const float2 *s_za,
+                                   const short *ixt, const short *iyt, int hw, int k0, int k1, float dist,
+                                   bool centre_far, float zc, float range, float &v0, float &v1, float &v2,
+                                   float &sw, float &ss)
 {
-    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+        const int ix = ixt[k * kTile], iy = iyt[k * kTile];
+        float4 ci;
+        float2 za;
+        if constexpr (kLds) {
+            ci = s_pre[iy + ix];
+            za = s_za[iy + ix];
+        } else {
+            const uint32_t j = __umul24((uint32_t)iy, (uint32_t)hw) + (uint32_t)ix;
+            ci = P.pre[j];
+            za = P.za[j];
+        }
+        const float alpha = fabsf(za.y);
+        float wb = alpha;
+        if constexpr (kBg) wb = centre_far ? alpha : alpha * (1.0f - sat((za.x - zc) / range));
+        const float w = fabsf(ci.w) > dist ? wb : 0.0f;
+        v0 = v0 + w * ci.x;
+        v1 = v1 + w * ci.y;
+        v2 = v2 + w * ci.z;
+        sw = sw + w;
+        ss = ss + (za.y < 0.0f ? w : 0.0f);
+    }
+}
+
+// kWin > 0: the LDS variant for the tiles that fit a kWin window; kWin = 0:
+// the global variant for the tiles that do not fit fc.gather_win.
+template <int kWin>
+__device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t tx,
+                                const uint32_t ty)
+{
+    constexpr bool kLds = kWin > 0;
+    // per tap: the texel column of each pixel column of the tile and the
+    // texel row (LDS variant: window row times window width) of each pixel row
+    __shared__ short s_ix[kRingTaps * kTile], s_iy[kRingTaps * kTile];
+    __shared__ float4 s_pre[kLds ? kWin * kWin : 1];
+    __shared__ float2 s_za[kLds ? kWin * kWin : 1];
+    const int tid = threadIdx.x;
+    const int x0 = (int)tx * kTile, y0 = (int)ty * kTile;
+    const float Rn = P.tile_dil[(size_t)ty * fc.tw + tx];
+    if (gather_fits(Rn, kLds ? kWin : fc.gather_win) != kLds) return;   // the other variant takes this tile
+    // every tap lies within ceil(R_n) + 1 texels of its pixel (ring offsets <= 1 kernel radius)
+    const int C = (int)ceilf(Rn) + 1;
+    const int wx0 = max(x0 - C, 0), wx1 = min(x0 + kTile - 1 + C, fc.hw - 1);
+    const int wy0 = max(y0 - C, 0), wy1 = min(y0 + kTile - 1 + C, fc.hh - 1);
+    const int ww = wx1 - wx0 + 1;
+    for (int e = tid; e < kRingTaps * 2 * kTile; e += 256) {
+        const int k = e / (2 * kTile), c = e % (2 * kTile);
+        if (c < kTile) {
+            const int ix = nearest_idx((float)(x0 + c) + rings.ox[k] * Rn, fc.hw);
+            s_ix[k * kTile + c] = (short)(kLds ? clampi(ix, wx0, wx1) - wx0 : ix);
+        } else {
+            const int iy = nearest_idx((float)(y0 + c - kTile) + rings.oy[k] * Rn, fc.hh);
+            s_iy[k * kTile + c - kTile] = (short)(kLds ? (clampi(iy, wy0, wy1) - wy0) * ww : iy);
+        }
+    }
+    if constexpr (kLds) {
+        const int n = ww * (wy1 - wy0 + 1);
+        for (int t = tid; t < n; t += 256) {
+            const size_t j = (size_t)(wy0 + t / ww) * fc.hw + (wx0 + t % ww);
+            s_pre[t] = P.pre[j];
+            s_za[t] = P.za[j];
+        }
+    }
+    __syncthreads();
+    const int lx = tid & (kTile - 1), ly = tid / kTile;
+    const int x = x0 + lx, y = y0 + ly;
     if (x >= fc.hw || y >= fc.hh) return;
     const size_t i = (size_t)y * fc.hw + x;
-    const float Rn = P.tile_dil[(size_t)(y / fc.T) * fc.tw + x / fc.T];
     const float4 c0 = P.pre[i];
-    const float rc = c0.w, zc = P.zh[i], arc = fabsf(rc);
-    float vf0 = 0.0f, vf1 = 0.0f, vf2 = 0.0f, vb0 = 0.0f, vb1 = 0.0f, vb2 = 0.0f, sw = 0.0f, ss = 0.0f;
-    for (int k = 0; k < kRingTaps; ++k) {
-        float dist = Rn * rings.frac[k];
-        float sx = (float)x + rings.ox[k] * Rn, sy = (float)y + rings.oy[k] * Rn;
-        int ix = nearest_idx(sx, fc.hw), iy = nearest_idx(sy, fc.hh);
-        size_t j = (size_t)iy * fc.hw + ix;
-        float4 ci = P.pre[j];
-        float ari = fabsf(ci.w);
-        const float2 za = P.za[j];
-        float alpha = za.y;
-        float dfg = ari > dist ? 1.0f : 0.0f;
-        float dbg = fmin_cs(ari, arc) > dist ? 1.0f : 0.0f;
-        float wbg = sat((za.x - zc) / fc.depth_range);
-        float wf = alpha * ((1.0f - wbg) * dfg);
-        float wb = alpha * (wbg * dbg);
-        vf0 = vf0 + wf * ci.x; vb0 = vb0 + wb * ci.x;
-        vf1 = vf1 + wf * ci.y; vb1 = vb1 + wb * ci.y;
-        vf2 = vf2 + wf * ci.z; vb2 = vb2 + wb * ci.z;
-        float wi = wf + wb;
-        sw = sw + wi;
-        if (luma709(ci.x, ci.y, ci.z) > fc.l_spec) ss = ss + wi;
+    const float zc = P.zh[i], arc = fabsf(c0.w);
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, sw = 0.0f, ss = 0.0f;
+    // rings of 1, 8, 16, 24, 32 taps, each at one distance
+    constexpr int kRingStart[6] = {0, 1, 9, 25, 49, 81};
+#pragma unroll
+    for (int ring = 0; ring < 5; ++ring) {
+        const int k0 = kRingStart[ring], k1 = kRingStart[ring + 1];
+        const float dist = Rn * rings.frac[k0];
+        const bool centre_far = arc > dist;   // background taps need the centre's radius too
+        if (__all(centre_far))
+            gather_ring<kLds, false>(rings, P, s_pre, s_za, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, true, zc,
+                                     fc.depth_range, v0, v1, v2, sw, ss);
+        else
+            gather_ring<kLds, true>(rings, P, s_pre, s_za, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, centre_far, zc,
+                                    fc.depth_range, v0, v1, v2, sw, ss);
     }
     float4 o;
-    if (sw > 0.0f) o = make_float4((vf0 + vb0) / sw, (vf1 + vb1) / sw, (vf2 + vb2) / sw, ss / sw);
+    if (sw > 0.0f) o = make_float4(v0 / sw, v1 / sw, v2 / sw, ss / sw);
     else o = make_float4(c0.x, c0.y, c0.z, 0.0f);
     P.gather[i] = o;
 }
 
-__global__ __launch_bounds__(kBX *kBY) void k_gather(FrameConst fc, Rings rings, Planes P)
+template <int kWin>
+__global__ __launch_bounds__(256) void k_gather(FrameConst fc, Rings rings, Planes P)
 {
-    // every pixel costs the same 81 taps, so bands per XCD stay balanced
+    // every tile costs about the same, so contiguous bands per XCD stay
+    // balanced and neighbouring tiles share their halo in one L2
     uint32_t bx, by;
     xcd_tile(bx, by);
-    b_gather(fc, rings, P, bx, by);
+    b_gather<kWin>(fc, rings, P, bx, by);
 }
 
-__global__ __launch_bounds__(kBX *kBY) void kb_gather(const Job *__restrict__ jobs, int njobs)
+template <int kWin>
+__global__ __launch_bounds__(256) void kb_gather(const Job *__restrict__ jobs, int njobs)
 {
     uint32_t bx, by;
-    const Job &J = jobs[job_of_block(jobs, njobs, kGridHalf, blockIdx.x, bx, by)];
-    b_gather(J.fc, J.grings, J.P, bx, by);
+    const Job &J = jobs[job_of_block(jobs, njobs, kGridTiles, blockIdx.x, bx, by)];
+    b_gather<kWin>(J.fc, J.grings, J.P, bx, by);
+}
+
+// Both variants of the gather: the LDS one for tiles that fit the window,
+// the global one for the rest (grid: the tiles, or the batch's tile blocks).
+template <class Launch>
+void launch_gather_pair(int win, Launch launch)
+{
+    switch (win) {
+    case 32: launch(std::integral_constant<int, 32>{}); break;
+    case 40: launch(std::integral_constant<int, 40>{}); break;
+    case 48: launch(std::integral_constant<int, 48>{}); break;
+    default: break;
+    }
+    launch(std::integral_constant<int, 0>{});
 }
 
 // ---------------------------------------------------------------- A5
@@ -988,15 +1097,94 @@ __device__ inline bool mip_taps_inside(int c, float R, float sc, int n)
     return (lo + 0.5f) * sc - 0.5f >= 0.0f && (hi + 0.5f) * sc - 0.5f < (float)(n - 1);
 }
 
-// The 81 taps of one pixel, summed in tap order.  Every tap's fetches are
-// issued (indices in bounds: clamped, or shown inside) and only valid taps are
-// summed, so the loads of several taps can be in flight at once.
-template <bool Inside>
-__device__ inline void recon_taps(int x, int y, float Rr, float fl, float sc0, float sc1, int hw, int hh,
-                                  const float4 *mip0, int w0, int h0, const float4 *mip1, int w1, int h1,
-                                  const Rings &rings, const float2 *tap, float &a0, float &a1, float &a2, float &a3,
-                                  float &sh, int &na)
+// Trilinear accumulation of one tap: the two mip levels' bilinear samples
+// blended by the lod fraction, folded into eight texel weights (level 0
+// scaled by f0 = 1 - fl, level 1 by f1 = fl, both 0 for a rejected tap) and
+// summed with fused multiply-adds into the four channels.  Equal to the
+// per-tap lerp of two bilinear lerps in exact arithmetic (the
+// reconstruction's tolerance parity covers the rounding); which texels a tap
+// reads, and whether it counts, are decided exactly as in the per-pixel
+// definition.
+struct Tex4 {
+    float4 a, b, c, d;   // (x0, y0), (x1, y0), (x0, y1), (x1, y1)
+};
+
+__device__ inline void acc_bilinear(const Tex4 &t, float fx, float fy, float f, float &a0, float &a1, float &a2,
+                                    float &a3)
 {
+    const float wy1 = fy * f, wy0 = f - wy1;
+    const float wx0 = 1.0f - fx;
+    const float w00 = wx0 * wy0, w10 = fx * wy0, w01 = wx0 * wy1, w11 = fx * wy1;
+    a0 = fmaf(t.d.x, w11, fmaf(t.c.x, w01, fmaf(t.b.x, w10, fmaf(t.a.x, w00, a0))));
+    a1 = fmaf(t.d.y, w11, fmaf(t.c.y, w01, fmaf(t.b.y, w10, fmaf(t.a.y, w00, a1))));
+    a2 = fmaf(t.d.z, w11, fmaf(t.c.z, w01, fmaf(t.b.z, w10, fmaf(t.a.z, w00, a2))));
+    a3 = fmaf(t.d.w, w11, fmaf(t.c.w, w01, fmaf(t.b.w, w10, fmaf(t.a.w, w00, a3))));
+}
+
+// The four texels of a bilinear lookup at (x, y) of a w x h level: clamped to
+// the image, or (Inside) shown inside it by the caller.
+template <bool Inside>
+__device__ inline Tex4 fetch4(const float4 *img, int w, int h, float x, float y, float &fx, float &fy)
+{
+    Tex4 t;
+    if (Inside) {
+        const int x0 = (int)x, y0 = (int)y;
+        fx = __builtin_amdgcn_fractf(x);
+        fy = __builtin_amdgcn_fractf(y);
+        const float4 *r0 = img + (__mul24(y0, w) + x0), *r1 = r0 + w;
+        t.a = r0[0]; t.b = r0[1]; t.c = r1[0]; t.d = r1[1];
+    } else {
+        const float x0f = floorf(x), y0f = floorf(y);
+        fx = x - x0f;
+        fy = y - y0f;
+        const int xi = (int)x0f, yi = (int)y0f;
+        const int xa = clampi(xi, 0, w - 1), xb = clampi(xi + 1, 0, w - 1);
+        const size_t ra = (size_t)clampi(yi, 0, h - 1) * w, rb = (size_t)clampi(yi + 1, 0, h - 1) * w;
+        t.a = img[ra + xa]; t.b = img[ra + xb]; t.c = img[rb + xa]; t.d = img[rb + xb];
+    }
+    return t;
+}
+
+// The same from a level staged in LDS: t holds its rows b[2]..b[3] and
+// columns b[0]..b[1], bw = b[1] - b[0] + 1 wide.  The box holds every index
+// the block's taps reach after the clamp to the image (see b_recon), so
+// clamping into the box gives the same texels as clamping into the image,
+// and every LDS access stays inside the staged box.
+template <bool Inside>
+__device__ inline Tex4 fetch4_lds(const float4 *tex, const int *b, int bw, float x, float y, float &fx, float &fy)
+{
+    Tex4 t;
+    if (Inside) {
+        const int x0 = (int)x, y0 = (int)y;
+        fx = __builtin_amdgcn_fractf(x);
+        fy = __builtin_amdgcn_fractf(y);
+        const float4 *r0 = tex + (__mul24(y0 - b[2], bw) + (x0 - b[0])), *r1 = r0 + bw;
+        t.a = r0[0]; t.b = r0[1]; t.c = r1[0]; t.d = r1[1];
+    } else {
+        const float x0f = floorf(x), y0f = floorf(y);
+        fx = x - x0f;
+        fy = y - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        const int x1 = clampi(x0 + 1, b[0], b[1]) - b[0], y1 = clampi(y0 + 1, b[2], b[3]) - b[2];
+        x0 = clampi(x0, b[0], b[1]) - b[0];
+        y0 = clampi(y0, b[2], b[3]) - b[2];
+        const int r0 = y0 * bw, r1 = y1 * bw;
+        t.a = tex[r0 + x0]; t.b = tex[r0 + x1]; t.c = tex[r1 + x0]; t.d = tex[r1 + x1];
+    }
+    return t;
+}
+
+// The 81 taps of one pixel in tap order, from global memory (Lds = false) or
+// from the staged levels.  Every tap's fetches are issued (indices in
+// bounds: clamped, or shown inside) and rejected taps weigh 0, so the loads
+// of several taps can be in flight at once.
+template <bool Inside, bool Lds>
+__device__ inline void recon_taps(int x, int y, float Rr, float fl, float sc0, float sc1, int hw, int hh,
+                                  const float4 *m0, int w0, int h0, const int *b0, const float4 *m1, int w1, int h1,
+                                  const int *b1, const Rings &rings, const float2 *tap, float &a0, float &a1,
+                                  float &a2, float &a3, float &sh, int &na)
+{
+    const float omf = 1.0f - fl;
 #pragma unroll 3
     for (int k = 0; k < kRingTaps; ++k) {
         float dist = Rr * rings.frac[k];
@@ -1012,93 +1200,17 @@ __device__ inline void recon_taps(int x, int y, float Rr, float fl, float sc0, f
         const bool ok = tj.x * 0.25f >= dist;
         const float u0 = (sx + 0.5f) * sc0 - 0.5f, v0 = (sy + 0.5f) * sc0 - 0.5f;
         const float u1 = (sx + 0.5f) * sc1 - 0.5f, v1 = (sy + 0.5f) * sc1 - 0.5f;
-        float4 s0 = Inside ? bilinear4_in(mip0, w0, u0, v0) : bilinear4(mip0, w0, h0, u0, v0);
-        float4 s1 = Inside ? bilinear4_in(mip1, w1, u1, v1) : bilinear4(mip1, w1, h1, u1, v1);
-        // a + (ok ? v : 0) is a + v or a itself: the sums start at +0 and
-        // so are never -0
-        a0 = a0 + (ok ? lerp1(s0.x, s1.x, fl) : 0.0f);
-        a1 = a1 + (ok ? lerp1(s0.y, s1.y, fl) : 0.0f);
-        a2 = a2 + (ok ? lerp1(s0.z, s1.z, fl) : 0.0f);
-        a3 = a3 + (ok ? lerp1(s0.w, s1.w, fl) : 0.0f);
+        float fx0, fy0, fx1, fy1;
+        const Tex4 t0 = Lds ? fetch4_lds<Inside>(m0, b0, w0, u0, v0, fx0, fy0) : fetch4<Inside>(m0, w0, h0, u0, v0, fx0, fy0);
+        const Tex4 t1 = Lds ? fetch4_lds<Inside>(m1, b1, w1, u1, v1, fx1, fy1) : fetch4<Inside>(m1, w1, h1, u1, v1, fx1, fy1);
+        acc_bilinear(t0, fx0, fy0, ok ? omf : 0.0f, a0, a1, a2, a3);
+        acc_bilinear(t1, fx1, fy1, ok ? fl : 0.0f, a0, a1, a2, a3);
         sh = sh + (ok ? tj.y : 0.0f);
         na += ok ? 1 : 0;
     }
 }
 
 constexpr int kReconLds = 2496;   // mip texels a block can stage in LDS (39 KB: 4 blocks per CU)
-
-// bilinear4 on texels staged in LDS: t holds the rows b[2]..b[3] and columns
-// b[0]..b[1] of one mip level, bw = b[1] - b[0] + 1 wide.  The box holds every
-// index the block's taps reach after the clamp to the image (see b_recon), so
-// clamping into the box gives the same texels as clamping into the image; it
-// also keeps every LDS access inside the staged box.
-__device__ inline float4 bilinear4_lds(const float4 *t, const int *b, int bw, float x, float y)
-{
-    float x0f = floorf(x), y0f = floorf(y);
-    float fx = x - x0f, fy = y - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int x1 = clampi(x0 + 1, b[0], b[1]), y1 = clampi(y0 + 1, b[2], b[3]);
-    x0 = clampi(x0, b[0], b[1]);
-    y0 = clampi(y0, b[2], b[3]);
-    const int r0 = (y0 - b[2]) * bw, r1 = (y1 - b[2]) * bw, c0 = x0 - b[0], c1 = x1 - b[0];
-    float4 a = t[r0 + c0], bq = t[r0 + c1];
-    float4 c = t[r1 + c0], d = t[r1 + c1];
-    float4 top, bot, o;
-    top.x = a.x + (bq.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
-    top.y = a.y + (bq.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
-    top.z = a.z + (bq.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
-    top.w = a.w + (bq.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
-    return o;
-}
-
-// bilinear4_lds where the caller has shown the lookup inside the image (as
-// for bilinear4_in): no clamp changes an index, so none is applied.
-__device__ inline float4 bilinear4_lds_in(const float4 *t, const int *b, int bw, float x, float y)
-{
-    const int x0 = (int)x, y0 = (int)y;
-    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y);
-    const float4 *r0 = t + (__mul24(y0 - b[2], bw) + (x0 - b[0])), *r1 = r0 + bw;
-    float4 a = r0[0], bq = r0[1];
-    float4 c = r1[0], d = r1[1];
-    float4 top, bot, o;
-    top.x = a.x + (bq.x - a.x) * fx; bot.x = c.x + (d.x - c.x) * fx; o.x = top.x + (bot.x - top.x) * fy;
-    top.y = a.y + (bq.y - a.y) * fx; bot.y = c.y + (d.y - c.y) * fx; o.y = top.y + (bot.y - top.y) * fy;
-    top.z = a.z + (bq.z - a.z) * fx; bot.z = c.z + (d.z - c.z) * fx; o.z = top.z + (bot.z - top.z) * fy;
-    top.w = a.w + (bq.w - a.w) * fx; bot.w = c.w + (d.w - c.w) * fx; o.w = top.w + (bot.w - top.w) * fy;
-    return o;
-}
-
-// The taps of one pixel on mip levels staged in LDS (same order and
-// arithmetic as recon_taps; Inside as there).
-template <bool Inside>
-__device__ inline void recon_taps_lds(int x, int y, float Rr, float fl, float sc0, float sc1, int hw, int hh,
-                                      const float4 *t0, const int *b0, int bw0, const float4 *t1, const int *b1,
-                                      int bw1, const Rings &rings, const float2 *tap, float &a0, float &a1,
-                                      float &a2, float &a3, float &sh, int &na)
-{
-#pragma unroll 3
-    for (int k = 0; k < kRingTaps; ++k) {
-        float dist = Rr * rings.frac[k];
-        float sx = (float)x + rings.ox[k] * Rr, sy = (float)y + rings.oy[k] * Rr;
-        size_t j;
-        if (Inside)
-            j = (uint32_t)(__umul24((int)(sy + 0.5f), hw) + (int)(sx + 0.5f));
-        else
-            j = (size_t)nearest_idx(sy, hh) * hw + nearest_idx(sx, hw);
-        const float2 tj = tap[j];
-        const bool ok = tj.x * 0.25f >= dist;
-        const float u0 = (sx + 0.5f) * sc0 - 0.5f, v0 = (sy + 0.5f) * sc0 - 0.5f;
-        const float u1 = (sx + 0.5f) * sc1 - 0.5f, v1 = (sy + 0.5f) * sc1 - 0.5f;
-        float4 s0 = Inside ? bilinear4_lds_in(t0, b0, bw0, u0, v0) : bilinear4_lds(t0, b0, bw0, u0, v0);
-        float4 s1 = Inside ? bilinear4_lds_in(t1, b1, bw1, u1, v1) : bilinear4_lds(t1, b1, bw1, u1, v1);
-        a0 = a0 + (ok ? lerp1(s0.x, s1.x, fl) : 0.0f);
-        a1 = a1 + (ok ? lerp1(s0.y, s1.y, fl) : 0.0f);
-        a2 = a2 + (ok ? lerp1(s0.z, s1.z, fl) : 0.0f);
-        a3 = a3 + (ok ? lerp1(s0.w, s1.w, fl) : 0.0f);
-        sh = sh + (ok ? tj.y : 0.0f);
-        na += ok ? 1 : 0;
-    }
-}
 
 // Index range that the bilinear lookups of taps between coordinates lo and hi
 // (one axis, already at the level's scale sc) reach after the clamp to
@@ -1197,18 +1309,18 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
     if (staged) {
         const int bw0 = box[L0][1] - box[L0][0] + 1, bw1 = box[L1][1] - box[L1][0] + 1;
         if (all_inside)
-            recon_taps_lds<true>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], box[L0], bw0, tex + base[L1], box[L1],
-                                 bw1, rings, P.tap, a0, a1, a2, a3, sh, na);
+            recon_taps<true, true>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], bw0, 0, box[L0], tex + base[L1], bw1,
+                                   0, box[L1], rings, P.tap, a0, a1, a2, a3, sh, na);
         else
-            recon_taps_lds<false>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], box[L0], bw0, tex + base[L1], box[L1],
-                                  bw1, rings, P.tap, a0, a1, a2, a3, sh, na);
+            recon_taps<false, true>(x, y, Rr, fl, sc0, sc1, hw, hh, tex + base[L0], bw0, 0, box[L0], tex + base[L1],
+                                    bw1, 0, box[L1], rings, P.tap, a0, a1, a2, a3, sh, na);
     } else {
         if (all_inside)
-            recon_taps<true>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh,
-                             na);
+            recon_taps<true, false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, nullptr, mip1, w1, h1, nullptr, rings,
+                                    P.tap, a0, a1, a2, a3, sh, na);
         else
-            recon_taps<false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, mip1, w1, h1, rings, P.tap, a0, a1, a2, a3, sh,
-                              na);
+            recon_taps<false, false>(x, y, Rr, fl, sc0, sc1, hw, hh, mip0, w0, h0, nullptr, mip1, w1, h1, nullptr, rings,
+                                     P.tap, a0, a1, a2, a3, sh, na);
     }
     const float4 med = P.rtmed[i];
     float nb0 = a3 > 0.0f ? a0 / a3 : med.x, nb1 = a3 > 0.0f ? a1 / a3 : med.y, nb2 = a3 > 0.0f ? a2 / a3 : med.z;
@@ -1280,7 +1392,10 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
     } else {
         float t = sat(rh / fc.h_edge);
         float w = (t * t) * (3.0f - 2.0f * t);
-        o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
+        if (fc.composite_literal)   // the literal reading: a high hit ratio favours the post-process colour
+            o = make_float4(lerp1(rc0, pp.x, w), lerp1(rc1, pp.y, w), lerp1(rc2, pp.z, w), 1.0f);
+        else
+            o = make_float4(lerp1(pp.x, rc0, w), lerp1(pp.y, rc1, w), lerp1(pp.z, rc2, w), 1.0f);
     }
     if (fc.taa & DOF_TAA_FINAL) P.comp[p] = o;
     else st_rgba(out.colour, out.colour_format, p, o);
@@ -1512,7 +1627,9 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     }
     k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
     DOF_REC(3);
-    k_gather<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, rings, P);
+    launch_gather_pair(fc.gather_win, [&](auto w) {
+        k_gather<decltype(w)::value><<<dim3(fc.tw, fc.th), 256, 0, pst>>>(fc, rings, P);
+    });
     DOF_REC(4);
     k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
     if (fc.taa & DOF_TAA_POST)
@@ -1543,7 +1660,6 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
                              const dof_frame_out &out, hipEvent_t *ev, const SideStream *side, hipStream_t st)
 {
     Planes P = planes(fc, L, scratch);
-    const int64_t np = (int64_t)fc.hw * fc.hh;
     DOF_REC(8);
     {
         const hipError_t e = launch_shade_resolve(sd, fc, L, scratch, mask, st);
@@ -1565,9 +1681,8 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
         k_taa_final<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);
     DOF_REC(13);
     if (out.stats) {
-        // copy the frame counters to the caller's stats record
-        // masked px, rays, node visits, triangle tests
-        // masked px, rays, node visits, triangle tests, stack spills
+        // the frame counters into the caller's stats record: masked px, rays,
+        // node visits, triangle tests, stack overflows
         hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 28, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
@@ -1581,13 +1696,15 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
 }
 
 hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                            bool dilate, int taa, hipStream_t st)
+                            bool dilate, int taa, int gather_win, hipStream_t st)
 {
     if (taa & DOF_TAA_RASTER) kb_taa_raster<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
     kb_prefilter<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
-    kb_gather<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    launch_gather_pair(gather_win, [&](auto w) {
+        kb_gather<decltype(w)::value><<<nblk[kGridTiles], 256, 0, st>>>(jobs, njobs);
+    });
     kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     if (taa & DOF_TAA_POST) kb_taa_post<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);

@@ -20,10 +20,15 @@
 //
 // Closest hit: binary radix tree whose nodes carry both children's boxes
 // (one 64-byte fetch tests two boxes), near child first, far child pushed on
-// a per-lane stack: 24 entries in LDS; when they are full the oldest 8 move
-// to a global spill area and come back when the LDS part runs empty, so any
-// depth the 96-bit keys allow is exact (at most 96 - 24 entries are ever
-// spilled, the size of the spill area) and a pop is always an LDS read.
+// a per-lane stack of 24 entries in LDS, so a pop is always an LDS read.  When
+// the stack is full its oldest 8 entries are dropped; when it later runs empty
+// the lane finds the dropped work again by walking parent links upwards: at
+// each ancestor reached from its near child (entry distances compared as when
+// it was first visited) whose far child still passes the box test, that far
+// child is the next subtree.  Every dropped entry is such a far child, and the
+// box test only loses children as the best hit shrinks, so the walk visits
+// exactly the pending subtrees that can still hold the closest hit: any depth
+// the 96-bit keys allow is exact with no memory beyond LDS.
 // Each outer iteration advances a lane by up to two nodes, which halves the
 // per-iteration cost of the wave-wide refill and batching decisions.  Leaf
 // hits wait in a 4-entry per-lane queue and the triangle test runs when at
@@ -39,7 +44,7 @@
 namespace dof {
 namespace {
 
-SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.ntri, s.tris, s.albedo, s.nodes}; }
+SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.ntri, s.tris, s.albedo, s.nodes, s.parent}; }
 
 __device__ inline float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
@@ -250,17 +255,15 @@ __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
 
 // ---------------------------------------------------------------- ray sources
 
-// Thin-lens ray r of a frame: its pixel from the ray -> pixel map, the
-// pixel's point on the focus plane, a lens point, normalised direction.
-__device__ inline void lens_ray(const FrameConst &fc, const uint32_t *queue, const uint32_t *ray_base,
-                                const uint32_t *ray_pix, uint32_t r, float o[3], float d[3])
+// Thin-lens ray k of pixel q = y w + x of a w x h grid: the pixel's point on
+// the focus plane (view depth d), a lens point from the counter hash of
+// (seed, frame, q, k), the normalised direction between them.
+__device__ inline void thin_lens_ray(const FrameConst &fc, uint32_t q, uint32_t w, uint32_t h, uint32_t k, float o[3],
+                                     float d[3])
 {
-    const uint32_t j = ray_pix[r];
-    const uint32_t q = queue[j];
-    const uint32_t k = r - ray_base[j];
-    const int x = (int)(q % (uint32_t)fc.hw), y = (int)(q / (uint32_t)fc.hw);
+    const int x = (int)(q % w), y = (int)(q / w);
     float fv[3], pf[3];
-    pixel_dir(fc.cur, x, y, fc.hw, fc.hh, fv);
+    pixel_dir(fc.cur, x, y, (int)w, (int)h, fv);
 #pragma unroll
     for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
     float lx, ly;
@@ -272,6 +275,15 @@ __device__ inline void lens_ray(const FrameConst &fc, const uint32_t *queue, con
     float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] = d[a] / len;
+}
+
+// Thin-lens ray r of a frame: its pixel from the ray -> pixel map, traced at
+// half resolution.
+__device__ inline void lens_ray(const FrameConst &fc, const uint32_t *queue, const uint32_t *ray_base,
+                                const uint32_t *ray_pix, uint32_t r, float o[3], float d[3])
+{
+    const uint32_t j = ray_pix[r];
+    thin_lens_ray(fc, queue[j], (uint32_t)fc.hw, (uint32_t)fc.hh, r - ray_base[j], o, d);
 }
 
 // Per-ray record of a lens ray: hit id, distance, shaded colour with view
@@ -473,6 +485,60 @@ struct RawRays {
     }
 };
 
+// The fully ray-traced image (ground truth of the accuracy judge): ray r of
+// a chunk is sample k = r mod spp of full-res pixel p0 + r / spp, traced at
+// full resolution with the frame's lens; its (leaf, t) result goes to lt[r].
+struct RefRays {
+    static constexpr bool kPerLaneScene = false;
+    FrameConst fc;
+    uint32_t p0, spp;
+    uint2 *lt;
+
+    __device__ void ray(uint32_t r, float o[3], float d[3]) const
+    {
+        thin_lens_ray(fc, p0 + r / spp, (uint32_t)fc.W, (uint32_t)fc.H, r % spp, o, d);
+    }
+
+    __device__ void start(uint32_t r, float o[3], float d[3], WRay &w) const
+    {
+        ray(r, o, d);
+        w = make_wray(o, d);
+    }
+
+    __device__ void finish(const SceneArgs &, uint32_t r, const float *, const float *, const Hit &h) const
+    {
+        put_lt(lt, r, h);
+    }
+};
+
+// Mean shaded colour of each pixel's spp rays of a chunk (binary64 sum in
+// sample order, one rounding to binary32).
+__global__ __launch_bounds__(256) void k_ref_average(SceneArgs S, RefRays src, uint32_t npx, void *colour, int cfmt)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= npx) return;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    for (uint32_t k = 0; k < src.spp; ++k) {
+        const uint32_t r = i * src.spp + k;
+        float o[3], d[3];
+        src.ray(r, o, d);
+        const uint2 lt = src.lt[r];
+        Hit h;
+        h.t = __uint_as_float(lt.y);
+        h.leaf = lt.x;
+        h.id = lt.x == ~0u ? ~0u : __float_as_uint(S.tris[3 * (size_t)lt.x].w);
+        int32_t hi;
+        float t;
+        float4 c, p;
+        lens_shade(S, src.fc, o, d, h, hi, t, c, p);
+        acc0 += (double)c.x;
+        acc1 += (double)c.y;
+        acc2 += (double)c.z;
+    }
+    const double n = (double)src.spp;
+    st_rgba(colour, cfmt, (size_t)src.p0 + i, make_float4((float)(acc0 / n), (float)(acc1 / n), (float)(acc2 / n), 1.0f));
+}
+
 // ---------------------------------------------------------------- ray generation
 
 constexpr int kGenTB = 256;
@@ -515,8 +581,8 @@ __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs
 }
 
 // Shading and resolve of a frame's lens rays in one pass: each block shades
-// the rays of its 64 pixels straight into the resolve's LDS chunks (and into
-// the per-ray records), so the records are not read back.
+// the rays of its 64 pixels straight into the resolve's LDS chunks (and, when
+// the frame keeps them, into the per-ray planes), so nothing is read back.
 __device__ inline void shade_resolve_block(const SceneArgs &S, const FrameConst &fc, const Planes &P,
                                            const uint8_t *__restrict__ mask, uint32_t bx)
 {
@@ -529,10 +595,12 @@ __device__ inline void shade_resolve_block(const SceneArgs &S, const FrameConst 
             float t;
             float4 c, p;
             lens_shade(S, fc, o, d, h, hi, t, c, p);
-            P.ray_hit[r] = hi;
-            P.ray_t[r] = t;
-            P.ray_col[r] = c;
-            P.ray_pos[r] = p;
+            if (P.ray_hit) {   // per-ray planes kept for inspection (params.ray_records)
+                P.ray_hit[r] = hi;
+                P.ray_t[r] = t;
+                P.ray_col[r] = c;
+                P.ray_pos[r] = p;
+            }
             col[r - c0] = c;
             pos[r - c0] = p;
             hit[r - c0] = hi;
@@ -561,37 +629,39 @@ int gen_blocks(int64_t max_rays)
 
 // ---------------------------------------------------------------- persistent traversal
 
-constexpr int kSpillChunk = 8;    // stack entries moved per spill or refill (divides kStackLds and kStackMax)
-static_assert(kStackLds % kSpillChunk == 0 && kStackMax % kSpillChunk == 0, "spill chunks must tile the stack");
-constexpr int kRefill = 16;   // refill when at least this many lanes are idle
-constexpr uint32_t kGrab = 64;   // rays a wave takes from the shared work counter at a time
-constexpr int kLeafBatch = 32;   // run triangle tests when at least this many lanes have one pending
+constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS stack is full
+// Launch knobs (TraceKnobs, defaults in brackets): a wave refills when at
+// least tk.refill lanes are idle [16], takes tk.grab rays from the shared
+// work counter at a time [64], and runs its triangle tests when at least
+// tk.leaf_batch lanes have one pending [32]; kStack LDS stack entries per
+// lane [24].
 
-template <class Src>
+template <class Src, int kStack>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
-                                                  uint32_t *work, uint32_t *spill, unsigned long long *stats,
-                                                  uint32_t *spills_out)
+                                                  uint32_t *work, unsigned long long *stats, uint32_t *drops_out,
+                                                  TraceKnobs tk)
 {
-    __shared__ uint32_t lds_stack[kStackLds * kTB];
+    static_assert(kDropChunk < kStack, "a drop must leave room for the push");
+    __shared__ uint32_t lds_stack[kStack * kTB];
+    const uint32_t grab = tk.grab;
     const int tid = threadIdx.x, lane = tid & 63;
-    const uint32_t nthreads = gridDim.x * kTB;
-    const uint32_t gtid = blockIdx.x * kTB + tid;
     const uint32_t N = count_ptr ? *count_ptr : count;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t *stk = lds_stack + tid;
 
     bool active = false, exhausted = false;
     // rays [pool, pool_end) taken by this wave and not yet handed to a lane
-    // (wave-uniform); a new batch of kGrab comes from the shared counter only
+    // (wave-uniform); a new batch of `grab` comes from the shared counter only
     // when the pool is empty, so refills rarely touch the atomic
     uint32_t pool = 0, pool_end = 0;
     bool drained = false;   // the shared counter has passed N (wave-uniform)
     uint32_t item = 0, node = 0;
-    int sp = 0, ns = 0;   // entries in LDS, entries spilled to global memory
+    int sp = 0;             // entries on the LDS stack
+    bool dropped = false;   // entries of this ray were dropped (found again through parent links)
     float o[3], d[3];
     WRay wr;
     Hit h;
-    uint32_t visits = 0, tests = 0, spills = 0;
+    uint32_t visits = 0, tests = 0, drops = 0;
     // pending leaf hits of this lane (tested when enough lanes have some)
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
     int nq = 0;
@@ -603,16 +673,16 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     while (true) {
         const uint64_t idle = __ballot(!active && !exhausted);
         const uint64_t live = __ballot(active);
-        if (idle != 0ull && (__popcll(idle) >= kRefill || live == 0ull)) {
+        if (idle != 0ull && (__popcll(idle) >= tk.refill || live == 0ull)) {
             if (pool == pool_end && !drained) {
                 uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(work, kGrab);
+                if (lane == 0) base = atomicAdd(work, grab);
                 base = __shfl(base, 0);
                 if (base >= N) {
                     drained = true;
                 } else {
                     pool = base;
-                    pool_end = N - base < kGrab ? N : base + kGrab;
+                    pool_end = N - base < grab ? N : base + grab;
                 }
             }
             const uint32_t avail = pool_end - pool;
@@ -630,7 +700,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     h = Hit{INFINITY, ~0u, 0u};
                     node = 0;
                     sp = 0;
-                    ns = 0;
+                    dropped = false;
                     nq = 0;
                     active = true;
                     if (Sl.ntri == 1) {
@@ -654,7 +724,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
         // triangle tests, batched across the wave
         const bool want = active && nq > 0;
         const bool must = want && (nq >= 3 || !trav);
-        if (__ballot(must) != 0ull || __popcll(__ballot(want)) >= kLeafBatch) {
+        if (__ballot(must) != 0ull || __popcll(__ballot(want)) >= tk.leaf_batch) {
             if (want) {
                 ++tests;
                 consider_leaf(Sl, wr, q0, h);
@@ -681,13 +751,12 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             hr = hr && !pr;
             if (hl && hr) {
                 const uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
-                if (sp == kStackLds) {
-                    // LDS part full: its older half moves to the global spill area
-                    for (int i = 0; i < kSpillChunk; ++i) spill[(size_t)(ns + i) * nthreads + gtid] = stk[i * kTB];
-                    for (int i = 0; i < kStackLds - kSpillChunk; ++i) stk[i * kTB] = stk[(i + kSpillChunk) * kTB];
-                    ns += kSpillChunk;
-                    sp -= kSpillChunk;
-                    ++spills;
+                if (sp == kStack) {
+                    // stack full: the oldest entries go (the parent walk finds them again)
+                    for (int i = 0; i < kStack - kDropChunk; ++i) stk[i * kTB] = stk[(i + kDropChunk) * kTB];
+                    sp -= kDropChunk;
+                    dropped = true;
+                    ++drops;
                 }
                 stk[sp * kTB] = farc;
                 ++sp;
@@ -696,19 +765,32 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                 node = L;
             } else if (hr) {
                 node = R;
+            } else if (sp > 0) {
+                --sp;
+                node = stk[sp * kTB];
+            } else if (dropped) {
+                // stack empty after a drop: walk up from this finished subtree
+                // to the nearest ancestor whose far child is still pending
+                trav = false;
+                uint32_t c = node;
+                for (uint32_t a = Sl.parent[c]; a != ~0u; c = a, a = Sl.parent[a]) {
+                    const BvhNode pn = Sl.nodes[a];
+                    ++visits;
+                    const float lim = h.t * 1.0009765625f;
+                    float ta, tb;
+                    const bool ha = box_hit(wr, pn.a.x, pn.a.y, pn.a.z, pn.a.w, pn.c.x, pn.c.y, lim, ta);
+                    const bool hb = box_hit(wr, pn.b.x, pn.b.y, pn.b.z, pn.b.w, pn.c.z, pn.c.w, lim, tb);
+                    const bool from_left = pn.d.x == c;
+                    const uint32_t other = from_left ? pn.d.y : pn.d.x;
+                    const bool came_near = from_left ? ta <= tb : !(ta <= tb);
+                    if (came_near && (other & kLeaf) == 0u && (from_left ? hb : ha)) {
+                        node = other;
+                        trav = true;
+                        break;
+                    }
+                }
             } else {
-                if (sp == 0 && ns > 0) {
-                    // LDS part empty: the most recently spilled chunk comes back
-                    ns -= kSpillChunk;
-                    for (int i = 0; i < kSpillChunk; ++i) stk[i * kTB] = spill[(size_t)(ns + i) * nthreads + gtid];
-                    sp = kSpillChunk;
-                }
-                if (sp > 0) {
-                    --sp;
-                    node = stk[sp * kTB];
-                } else {
-                    trav = false;
-                }
+                trav = false;
             }
         }
         if (active && !trav && nq == 0) {
@@ -728,10 +810,10 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             atomicAdd(stats + 1, t);
         }
     }
-    if (spills_out) {
-        uint32_t sv = spills;
+    if (drops_out) {
+        uint32_t sv = drops;
         for (int off = 32; off >= 1; off >>= 1) sv += __shfl_xor(sv, off);
-        if (lane == 0 && sv) atomicAdd(spills_out, sv);
+        if (lane == 0 && sv) atomicAdd(drops_out, sv);
     }
 }
 
@@ -761,11 +843,22 @@ int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks
 
 }  // namespace
 
-int trace_blocks_per_cu(bool batch)
+// The traversal kernel of a ray source for a stack depth: f(kernel_tag).
+template <class Src, class F>
+void with_stack(int stack, F f)
+{
+    if (stack == 16) f(k_traverse<Src, 16>);
+    else if (stack == 32) f(k_traverse<Src, 32>);
+    else f(k_traverse<Src, kStackLds>);
+}
+
+int trace_blocks_per_cu(bool batch, int stack)
 {
     int n = 0;
-    const hipError_t e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<BatchRays>, kTB, 0)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_traverse<LensRays>, kTB, 0);
+    hipError_t e = hipSuccess;
+    auto occ = [&](auto kern) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kTB, 0); };
+    if (batch) with_stack<BatchRays>(stack, occ);
+    else with_stack<LensRays>(stack, occ);
     return e == hipSuccess ? n : 0;
 }
 
@@ -779,9 +872,11 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     src.rec2 = P.rec2;
     src.ray_lt = P.ray_lt;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
-    k_traverse<LensRays><<<clamp_blocks(blocks), kTB, 0, st>>>(
-        scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork, reinterpret_cast<uint32_t *>(scratch + L.spill),
-        reinterpret_cast<unsigned long long *>(cnt + kCntVisits), cnt + kCntSpills);
+    with_stack<LensRays>(fc.tk.stack, [&](auto kern) {
+        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork,
+                                                  reinterpret_cast<unsigned long long *>(cnt + kCntVisits),
+                                                  cnt + kCntSpills, fc.tk);
+    });
     return hipGetLastError();
 }
 
@@ -821,8 +916,8 @@ hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour,
     src.normal = normal;
     src.nfmt = nfmt;
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
-    k_traverse<PinholeRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H),
-                                                                  nullptr, s.aux, s.spill, nullptr, nullptr);
+    k_traverse<PinholeRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(
+        scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H), nullptr, s.aux, nullptr, nullptr, fc.tk);
     return hipGetLastError();
 }
 
@@ -832,19 +927,39 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
     if (n == 0) return hipSuccess;
     RawRays src{org, dir, hit, t};
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
-    k_traverse<RawRays><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux, s.spill,
-                                                              nullptr, nullptr);
+    TraceKnobs tk{kStackLds, 64u, 16, 32};
+    k_traverse<RawRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux,
+                                                                         nullptr, nullptr, tk);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, uint32_t *spill, int blocks,
-                              int64_t max_rays, hipStream_t st)
+hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, uint2 *lt, int64_t chunk_px, void *colour,
+                            int cfmt, int blocks, hipStream_t st)
+{
+    const int64_t npx = (int64_t)fc.W * fc.H;
+    for (int64_t p0 = 0; p0 < npx; p0 += chunk_px) {
+        const uint32_t n = (uint32_t)(npx - p0 < chunk_px ? npx - p0 : chunk_px);
+        RefRays src{fc, (uint32_t)p0, (uint32_t)spp, lt};
+        k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+        k_traverse<RefRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, n * (uint32_t)spp,
+                                                                            nullptr, s.aux, nullptr, nullptr, fc.tk);
+        k_ref_average<<<(n + 255) / 256, 256, 0, st>>>(scene_args(s), src, n, colour, cfmt);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, int64_t max_rays,
+                              const TraceKnobs &tk, hipStream_t st)
 {
     kb_ray_offsets<<<1, 64, 0, st>>>(head, jobs, njobs);
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
-    k_traverse<BatchRays><<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, spill,
-                                                                &head->visits, nullptr);
+    with_stack<BatchRays>(tk.stack, [&](auto kern) {
+        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, &head->visits,
+                                                  nullptr, tk);
+    });
     return hipGetLastError();
 }
 

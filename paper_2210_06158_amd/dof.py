@@ -40,7 +40,12 @@ class DofParams(C.Structure):
                 ("b_max", C.c_float), ("h_edge", C.c_float), ("lod_scale", C.c_float), ("lod_max", C.c_float),
                 ("depth_range", C.c_float), ("r_max", C.c_float), ("tile", C.c_int32), ("l_spec", C.c_float),
                 ("mask_mode", C.c_int32), ("trace_blocks", C.c_int32), ("timing", C.c_int32),
-                ("pp_polygon", C.c_int32), ("taa", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("pp_polygon", C.c_int32), ("taa", C.c_int32), ("ray_records", C.c_int32), ("composite_literal", C.c_int32),
+                ("gather_window", C.c_int32), ("trace_stack", C.c_int32), ("trace_grab", C.c_int32),
+                ("trace_refill", C.c_int32), ("trace_leaf_batch", C.c_int32)]
+
+# launch-shape knobs of dof_params (0 = library default), set from a dict
+KNOBS = ("gather_window", "trace_stack", "trace_grab", "trace_refill", "trace_leaf_batch")
 
 
 class DofGBuffer(C.Structure):
@@ -90,7 +95,7 @@ EXPORTS = ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_scene
            "dof_build_bvh", "dof_bvh_view_get", "dof_destroy_scene", "dof_trace_rays", "dof_render_gbuffer",
            "dof_history_bytes", "dof_history_reset", "dof_frame_scratch_bytes", "dof_render_frame",
            "dof_debug_view_get", "dof_stage_times", "dof_batch_bytes", "dof_batch_create", "dof_batch_set",
-           "dof_batch_run", "dof_batch_destroy")
+           "dof_batch_run", "dof_batch_destroy", "dof_reference_scratch_bytes", "dof_render_reference")
 
 STAGES = ("reduce", "dilate", "prefilter", "gather", "median", "mask", "compact", "trace", "resolve", "temporal",
           "blur_median_mips", "recon", "composite")
@@ -135,13 +140,15 @@ def lib():
         L.dof_batch_create.argtypes = [vp, C.c_size_t, C.c_int32, P(vp)]
         L.dof_batch_set.argtypes = [vp, P(DofBatchItem), C.c_int32, P(DofParams), vp]
         L.dof_batch_run.argtypes = [vp, vp, vp]
+        L.dof_reference_scratch_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_size_t)]
+        L.dof_render_reference.argtypes = [vp, P(DofCamera), P(DofLens), C.c_int32, vp, C.c_int32, vp, C.c_size_t, vp]
         L.dof_batch_destroy.argtypes = [vp]
         L.dof_batch_destroy.restype = None
         for name in EXPORTS:
             if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
                             "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
-        if L.dof_abi_version() != 2:
+        if L.dof_abi_version() != 3:
             raise ImportError("libdof ABI version mismatch")
         _lib = L
     return _lib
@@ -165,7 +172,8 @@ def lens_struct(lens) -> DofLens:
     return DofLens(lens.focal, lens.fnum, lens.focus, lens.sensor, lens.blades, lens.blade_rot)
 
 
-def params_struct(p, trace_blocks: int = 0, timing: bool = False) -> DofParams:
+def params_struct(p, trace_blocks: int = 0, timing: bool = False, ray_records: bool = False,
+                  knobs: dict | None = None) -> DofParams:
     s = DofParams()
     lib().dof_default_params(C.byref(s))
     for k in ("m", "s", "var_mask_w", "alpha", "alpha_motion", "var_recon_w", "b_max", "h_edge", "lod_scale",
@@ -173,8 +181,13 @@ def params_struct(p, trace_blocks: int = 0, timing: bool = False) -> DofParams:
         setattr(s, k, getattr(p, k))
     s.pp_polygon = int(getattr(p, "pp_polygon", 0))
     s.taa = int(getattr(p, "taa", 0))
+    s.composite_literal = int(getattr(p, "composite_literal", 0))
     s.trace_blocks = trace_blocks
     s.timing = 1 if timing else 0
+    s.ray_records = 1 if ray_records else 0
+    for k, v in (knobs or {}).items():
+        assert k in KNOBS, k
+        setattr(s, k, int(v))
     return s
 
 
@@ -242,6 +255,18 @@ class Scene:
                                        _ptr(normal), nf, _stream()))
         return colour, depth, normal
 
+    def render_reference(self, cam, lens, spp, fmt=RGBA32F, device="cuda"):
+        """The fully ray-traced image (spp thin-lens rays per full-res pixel)."""
+        nb = C.c_size_t()
+        check(lib().dof_reference_scratch_bytes(cam.width, cam.height, spp, C.byref(nb)))
+        scratch = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        dt = torch.float32 if fmt == RGBA32F else torch.float16
+        colour = torch.empty((cam.height, cam.width, 4), dtype=dt, device=device)
+        c, l = camera_struct(cam), lens_struct(lens)
+        check(lib().dof_render_reference(self.handle, C.byref(c), C.byref(l), spp, _ptr(colour), fmt,
+                                         _ptr(scratch), nb.value, _stream()))
+        return colour
+
     def stage_times(self):
         """Per-stage ms of the last frame rendered with timing on."""
         buf = (C.c_float * len(STAGES))()
@@ -273,9 +298,9 @@ def history_alloc(W, H, device="cuda"):
     return torch.zeros(history_bytes(W, H) // 4, dtype=torch.float32, device=device)
 
 
-def scratch_bytes(W, H, params) -> int:
+def scratch_bytes(W, H, params, ray_records: bool = False) -> int:
     b = C.c_size_t()
-    ps = params_struct(params)
+    ps = params_struct(params, ray_records=ray_records)
     check(lib().dof_frame_scratch_bytes(W, H, C.byref(ps), C.byref(b)))
     return b.value
 
@@ -283,11 +308,13 @@ def scratch_bytes(W, H, params) -> int:
 class Frame:
     """Per-resolution buffers of the pass: scratch, outputs, stats."""
 
-    def __init__(self, W, H, params, out_format=RGBA32F, device="cuda", trace_blocks=0, timing=False):
+    def __init__(self, W, H, params, out_format=RGBA32F, device="cuda", trace_blocks=0, timing=False,
+                 ray_records=False, knobs=None):
         self.W, self.H = W, H
         self.params = params
-        self.ps = params_struct(params, trace_blocks, timing)
-        self.nbytes = scratch_bytes(W, H, params)
+        self.ray_records = ray_records
+        self.ps = params_struct(params, trace_blocks, timing, ray_records, knobs)
+        self.nbytes = scratch_bytes(W, H, params, ray_records)
         self.scratch = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         dt = torch.float32 if out_format == RGBA32F else torch.float16
         self.out_format = out_format
@@ -328,7 +355,10 @@ class Frame:
         P, R = int(cnt[0]), int(cnt[1])
 
         def get(name, nbytes, dtype, shape):
-            return self._view(getattr(v, name) - base, nbytes, dtype).cpu().numpy().reshape(shape)
+            ptr = getattr(v, name)
+            if ptr is None:    # a per-ray plane the frame does not keep
+                return None
+            return self._view(ptr - base, nbytes, dtype).cpu().numpy().reshape(shape)
 
         dims = [(hw, hh)]
         for _ in range(3):
@@ -368,7 +398,7 @@ class Batch:
     the last run (frames, rays, node visits, triangle tests) are in stats.
     """
 
-    def __init__(self, max_items, params, device="cuda", trace_blocks=0):
+    def __init__(self, max_items, params, device="cuda", trace_blocks=0, ray_records=False, knobs=None):
         nb = C.c_size_t()
         check(lib().dof_batch_bytes(max_items, C.byref(nb)))
         self.table = torch.empty(nb.value, dtype=torch.uint8, device=device)
@@ -376,7 +406,8 @@ class Batch:
         check(lib().dof_batch_create(_ptr(self.table), nb.value, max_items, C.byref(h)))
         self.handle = h
         self.max_items = max_items
-        self.ps = params_struct(params, trace_blocks, False)
+        # every item's scratch must be laid out with the same ray_records
+        self.ps = params_struct(params, trace_blocks, False, ray_records, knobs)
         self.stats = torch.zeros(6, dtype=torch.int32, device=device)
         self._lib = lib()
 

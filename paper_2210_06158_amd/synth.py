@@ -117,6 +117,7 @@ class Params:
     mask_mode: int = MASK_ADAPTIVE
     pp_polygon: int = 0         # 1: post-process gather kernel shaped like a bladed aperture
     taa: int = 0                # TAA stages (3.4), bits TAA_FINAL / TAA_RASTER / TAA_POST
+    composite_literal: int = 0  # 1: eq. (7)'s far-field blend read literally (high hit ratio -> post-process)
 
 
 @dataclass

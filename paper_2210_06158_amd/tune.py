@@ -1,15 +1,38 @@
-"""Autotuning of the launch parameters that are runtime choices.
+"""Autotuning of the pass's launch shapes (none of them changes a result).
 
-The persistent traversal's grid (dof_params.trace_blocks) is the one launch
-parameter the library leaves to its caller: too few blocks leave compute
-units idle while long rays drain, too many only add waves that find no work.
-The tuner renders the same frames with each candidate grid (multiples of the
-compute-unit count, plus the library default of as many blocks as fit at
-once) and keeps the fastest by HIP-event time.  Tile size (16) and stack
-depth are compile-time constants of the kernels.
+Searched per workload, by HIP-event time of the same sample of frames:
+
+* trace_blocks -- the persistent traversal's grid: too few blocks leave
+  compute units idle while long rays drain, too many only add waves that
+  find no work (multiples of the compute-unit count, and the library default
+  of as many blocks as fit at once);
+* trace_stack -- LDS stack entries per traversal lane (16, 24, 32): fewer
+  entries leave room for more resident blocks, more make stack overflows
+  (recovered through parent links) rarer;
+* trace_grab -- rays a wave takes from the shared work counter at a time
+  (the traversal's queue width);
+* trace_refill -- idle lanes at which a wave takes new rays;
+* trace_leaf_batch -- lanes with a pending leaf at which a wave runs its
+  triangle tests;
+* gather_window -- the LDS window of the post-process gather's staged tiles
+  (32, 40, 48 texels, or -1: every tap from global memory).
+
+The search is coordinate descent from the library defaults: one knob at a
+time over its candidates with the others held, keeping the fastest.
 """
 
 from __future__ import annotations
+
+KNOB_SPACE = {
+    "trace_blocks": None,                      # filled from the device (candidate_blocks)
+    "trace_stack": (16, 24, 32),
+    "trace_grab": (32, 64, 128),
+    "trace_refill": (8, 16, 24),
+    "trace_leaf_batch": (16, 24, 32, 40),
+    "gather_window": (-1, 32, 40, 48),
+}
+DEFAULTS = {"trace_blocks": 0, "trace_stack": 24, "trace_grab": 64, "trace_refill": 16, "trace_leaf_batch": 32,
+            "gather_window": 48}
 
 
 def candidate_blocks(extra=()):
@@ -19,7 +42,7 @@ def candidate_blocks(extra=()):
 
 
 def tune(run, candidates, reps: int = 3):
-    """run(trace_blocks) renders a fixed sample of work (same every call);
+    """run(candidate) renders a fixed sample of work (same every call);
     returns (best candidate, {candidate: median ms})."""
     import statistics
 
@@ -27,7 +50,7 @@ def tune(run, candidates, reps: int = 3):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     times = {}
     for c in candidates:
-        run(c)                     # warm-up for this grid
+        run(c)                     # warm-up for this candidate
         ms = []
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -39,3 +62,25 @@ def tune(run, candidates, reps: int = 3):
         times[c] = statistics.median(ms)
     best = min(times, key=times.get)
     return best, times
+
+
+def search(run, space=None, reps: int = 2, order=None):
+    """Coordinate descent over the knobs: run(config) renders the sample with
+    config (a dict with every knob of `space`).  Returns (best config,
+    {knob: {value: ms}})."""
+    space = dict(KNOB_SPACE if space is None else space)
+    if space.get("trace_blocks", ()) is None:
+        space["trace_blocks"] = candidate_blocks()
+    cfg = {k: DEFAULTS[k] for k in space}
+    table = {}
+    for knob in order or list(space):
+        best, times = tune(lambda v: run({**cfg, knob: v}), space[knob], reps=reps)
+        cfg[knob] = best
+        table[knob] = times
+    return cfg, table
+
+
+def split(cfg):
+    """(trace_blocks, the dof_params knobs) of a configuration."""
+    cfg = dict(cfg)
+    return cfg.pop("trace_blocks", 0), cfg

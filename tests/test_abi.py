@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(dof):
 
 def test_abi_version_and_defaults(dof):
     L = dof.lib()
-    assert L.dof_abi_version() == 2
+    assert L.dof_abi_version() == 3
     assert C.sizeof(dof.DofCamera) == 16 * 4 + 2 * 4   # basis, size, counters, jitter
     p = dof.DofParams()
     L.dof_default_params(C.byref(p))
@@ -96,6 +96,14 @@ def test_render_rejects_bad_arguments_before_device_work(dof):
     assert L.dof_create_scene(None, None, 0, None, None) == dof.DOF_E_INVALID
     assert L.dof_build_bvh(None, None) == dof.DOF_E_INVALID
     assert L.dof_trace_rays(None, 1, None, None, None, None, None) == dof.DOF_E_INVALID
+    assert L.dof_render_reference(None, C.byref(cam), C.byref(lens), 4, None, 0, None, 0, None) == dof.DOF_E_INVALID
+    b = C.c_size_t()
+    assert L.dof_reference_scratch_bytes(256, 256, 0, C.byref(b)) == dof.DOF_E_INVALID
+    assert L.dof_reference_scratch_bytes(256, 256, 1025, C.byref(b)) == dof.DOF_E_INVALID
+    assert L.dof_reference_scratch_bytes(256, 256, 16, C.byref(b)) == 0 and b.value == 8 * 256 * 256 * 16
+    # whole pixels of at most 2^22 rays per chunk
+    assert L.dof_reference_scratch_bytes(1920, 1080, 64, C.byref(b)) == 0 and b.value == 8 * (1 << 22)
+    assert L.dof_reference_scratch_bytes(1920, 1080, 48, C.byref(b)) == 0 and b.value == 8 * ((1 << 22) // 48) * 48
     v = dof.DofDebugView()
     assert L.dof_debug_view_get(None, 256, 256, C.byref(p), C.byref(v)) == dof.DOF_E_INVALID
     # offsets of the debug view follow the scratch layout and stay inside it
@@ -103,9 +111,18 @@ def test_render_rejects_bad_arguments_before_device_work(dof):
     assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == 0
     base = 1 << 40
     assert L.dof_debug_view_get(C.c_void_p(base), 256, 256, C.byref(p), C.byref(v)) == 0
+    per_ray = ("ray_hit", "ray_t", "ray_col", "ray_pos")
+    assert all(getattr(v, f) is None for f in per_ray)      # not kept unless params.ray_records
+    p.ray_records = 1
+    small = b.value
+    assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == 0
+    assert b.value >= small + 40 * 128 * 128 * p.m              # 40 B per ray of the frame's budget
+    assert L.dof_debug_view_get(C.c_void_p(base), 256, 256, C.byref(p), C.byref(v)) == 0
     offs = [getattr(v, f) - base for f in dof.DEBUG_FIELDS]
     assert all(0 <= o < b.value for o in offs) and len(set(offs)) == len(offs)
     assert all(o % 256 == 0 for o in offs)
+    p.ray_records = 2
+    assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID
 
 
 def test_batch_entry_points_check_arguments_on_the_host(dof):
@@ -209,3 +226,24 @@ def test_scene_creation_fails_cleanly_without_a_device(dof):
     assert st == dof.DOF_E_DEVICE and not h.value
     assert b"scene upload" in L.dof_last_error()
     assert L.dof_create_scene(C.byref(desc), C.c_void_p(1 << 40), b.value - 1, None, C.byref(h)) == dof.DOF_E_NOMEM
+
+
+def test_launch_knob_ranges(dof):
+    L = dof.lib()
+    b = C.c_size_t()
+    ok = {"gather_window": (0, -1, 32, 40, 48), "trace_stack": (0, 16, 24, 32), "trace_grab": (0, 1, 256),
+          "trace_refill": (0, 1, 64), "trace_leaf_batch": (0, 1, 64)}
+    bad = {"gather_window": (16, 64, -2), "trace_stack": (8, 48), "trace_grab": (-1, 257), "trace_refill": (65,),
+           "trace_leaf_batch": (-3, 65)}
+    for k, vals in ok.items():
+        for v in vals:
+            p = dof.DofParams()
+            L.dof_default_params(C.byref(p))
+            setattr(p, k, v)
+            assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == 0, (k, v)
+    for k, vals in bad.items():
+        for v in vals:
+            p = dof.DofParams()
+            L.dof_default_params(C.byref(p))
+            setattr(p, k, v)
+            assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID, (k, v)

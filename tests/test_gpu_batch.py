@@ -70,7 +70,7 @@ def render_alone(sess, hist_in=None, prev=None):
     res = []
     for k, it in enumerate(sess["items"]):
         cam = it["cam"]
-        fr = dof.Frame(cam.width, cam.height, sess["params"])
+        fr = dof.Frame(cam.width, cam.height, sess["params"], ray_records=True)
         hout = dof.history_alloc(cam.width, cam.height)
         hin = hist_in[k] if hist_in is not None else None
         pc = prev[k] if prev is not None else None
@@ -84,7 +84,7 @@ def make_frames(sess):
     frs, houts = [], []
     for it in sess["items"]:
         cam = it["cam"]
-        frs.append(dof.Frame(cam.width, cam.height, sess["params"]))
+        frs.append(dof.Frame(cam.width, cam.height, sess["params"], ray_records=True))
         houts.append(dof.history_alloc(cam.width, cam.height))
     return frs, houts
 
@@ -114,7 +114,7 @@ def test_batch_equals_single_frames(sess):
     torch, dof = sess["torch"], sess["dof"]
     alone = render_alone(sess)
     frs, houts = make_frames(sess)
-    b = dof.Batch(8, sess["params"])
+    b = dof.Batch(8, sess["params"], ray_records=True)
     b.set(batch_items(sess, frs, houts))
     b.run()
     got = [grab(torch, frs[k], houts[k]) for k in range(len(frs))]
@@ -134,7 +134,7 @@ def test_batch_with_dilated_mask_equals_single_frames(sess):
         sess["params"] = dataclasses.replace(params, mask_mode=synth.MASK_DILATE)
         alone = render_alone(sess)
         frs, houts = make_frames(sess)
-        b = dof.Batch(4, sess["params"])
+        b = dof.Batch(4, sess["params"], ray_records=True)
         b.set(batch_items(sess, frs, houts))
         b.run()
         for k in range(len(frs)):
@@ -154,7 +154,7 @@ def test_batch_with_polygonal_gather_equals_single_frames(sess):
         sess["params"] = dataclasses.replace(params, pp_polygon=1)
         alone = render_alone(sess)
         frs, houts = make_frames(sess)
-        b = dof.Batch(4, sess["params"])
+        b = dof.Batch(4, sess["params"], ray_records=True)
         b.set(batch_items(sess, frs, houts))
         b.run()
         for k in range(len(frs)):
@@ -183,7 +183,7 @@ def test_batch_second_frame_with_history(sess):
             it["cam"] = c1
         alone = render_alone(sess, hist_in=hist, prev=prev)
         frs, houts = make_frames(sess)
-        b = dof.Batch(4, sess["params"])
+        b = dof.Batch(4, sess["params"], ray_records=True)
         b.set(batch_items(sess, frs, houts, hist_in=hist, prev=prev))
         b.run()
         for k in range(len(frs)):
@@ -203,7 +203,7 @@ def test_batch_with_taa_equals_single_frames(sess):
         sess["params"] = dataclasses.replace(params, taa=1)
         alone0 = render_alone(sess)
         frs, houts = make_frames(sess)
-        b = dof.Batch(4, sess["params"])
+        b = dof.Batch(4, sess["params"], ray_records=True)
         b.set(batch_items(sess, frs, houts))
         b.run()
         for k in range(len(frs)):
@@ -237,7 +237,7 @@ def test_batch_with_all_taa_stages_and_jitter_equals_single_frames(sess):
             it["cam"] = synth.jittered([it["cam"]], seed=synth.BASE_SEED + 40 + k)[0]
         alone0 = render_alone(sess)
         frs, houts = make_frames(sess)
-        b = dof.Batch(4, sess["params"])
+        b = dof.Batch(4, sess["params"], ray_records=True)
         b.set(batch_items(sess, frs, houts))
         b.run()
         for k in range(len(frs)):
@@ -263,7 +263,7 @@ def test_batch_item_matches_oracle(sess, orc):
     """The hexagonal-aperture item of a batch against the CPU oracle."""
     torch, dof = sess["torch"], sess["dof"]
     frs, houts = make_frames(sess)
-    b = dof.Batch(4, sess["params"])
+    b = dof.Batch(4, sess["params"], ray_records=True)
     b.set(batch_items(sess, frs, houts))
     b.run()
     k = 1
@@ -285,7 +285,7 @@ def test_batch_graph_replays(sess):
     eager batch of the same table."""
     torch, dof = sess["torch"], sess["dof"]
     frs, houts = make_frames(sess)
-    b = dof.Batch(4, sess["params"])
+    b = dof.Batch(4, sess["params"], ray_records=True)
     b.set(batch_items(sess, frs, houts))
     b.run()                       # warm-up outside the capture
     torch.cuda.synchronize()
@@ -301,7 +301,7 @@ def test_batch_graph_replays(sess):
             for it, c0 in zip(sess["items"], saved):
                 it["cam"] = dataclasses.replace(synth.pan_camera(c0, 0.01 * rep), frame=rep)
             ref_frs, ref_houts = make_frames(sess)
-            ref = dof.Batch(4, sess["params"])
+            ref = dof.Batch(4, sess["params"], ray_records=True)
             ref.set(batch_items(sess, ref_frs, ref_houts))
             ref.run()
             want = [grab(torch, ref_frs[k], ref_houts[k]) for k in range(len(ref_frs))]
@@ -321,7 +321,7 @@ def test_batch_rejects_bad_items(sess):
     torch, dof = sess["torch"], sess["dof"]
     frs, houts = make_frames(sess)
     items = batch_items(sess, frs, houts)
-    b = dof.Batch(2, sess["params"])
+    b = dof.Batch(2, sess["params"], ray_records=True)
     with pytest.raises(dof.DofError) as e:
         b.set(items[:3])
     assert e.value.code == dof.DOF_E_NOMEM

@@ -37,10 +37,10 @@ def to_gpu(torch, gb):
     return (torch.from_numpy(gb.colour).cuda(), torch.from_numpy(gb.depth).cuda(), torch.from_numpy(gb.normal).cuda())
 
 
-def run_pair(env, orc, cam, lens, params, gb, hist_in=None, prev_cam=None, prev_lens=None, fmt16=False):
+def run_pair(env, orc, cam, lens, params, gb, hist_in=None, prev_cam=None, prev_lens=None, fmt16=False, knobs=None):
     torch, dof = env["torch"], env["dof"]
     o = orc.render_frame(env["osc"], cam, lens, params, gb, hist_in=hist_in, prev_cam=prev_cam, prev_lens=prev_lens)
-    fr = dof.Frame(cam.width, cam.height, params)
+    fr = dof.Frame(cam.width, cam.height, params, ray_records=True, knobs=knobs)
     g = to_gpu(torch, gb)
     if fmt16:
         g = (g[0].half(), g[1], g[2].half())
@@ -198,7 +198,8 @@ def caterpillar_scene():
     """Triangles whose Morton codes are 0, 2^k (k = 0..62) and 2^63 - 1: the
     radix tree is a chain about 63 deep.  Every triangle is huge and they all
     overlap, so a ray enters both children at every level and the traversal
-    stack grows past its 32 LDS entries into the global spill area."""
+    stack outgrows its 24 LDS entries: the oldest entries are dropped and
+    found again by walking parent links, which must not change any hit."""
     S = float(2 ** 23)
     cents = [(0.0, 0.0, 0.0), (2.0 ** 21, 2.0 ** 21, 2.0 ** 21)]
     for k in range(63):
@@ -324,6 +325,28 @@ def test_mask_modes_parity(env, orc, frame0, mode, m):
     p = dataclasses.replace(env["params"], mask_mode=mode, m=m)
     o, d = run_pair(env, orc, env["cam"], env["lens"], p, gb)
     compare_frame(o, d, f"mask mode {mode}")
+
+
+def test_literal_composite_reading_parity(env, orc, frame0):
+    """The far-field blend read literally (composite_literal = 1): the whole
+    frame against the oracle, and the output differs from the default
+    reading's where far-field pixels blend."""
+    gb, _, d0 = frame0
+    p = dataclasses.replace(env["params"], composite_literal=1)
+    o, d = run_pair(env, orc, env["cam"], env["lens"], p, gb)
+    compare_frame(o, d, "literal composite")
+    assert np.abs(d["colour"] - d0["colour"]).max() > 1e-3
+
+
+def test_gather_windows_parity(env, orc, frame0):
+    """The gather with every LDS window the tuner may pick (and none): the
+    prefiltered/gathered planes against the oracle, and identical to each
+    other bit for bit (one tap arithmetic in both variants)."""
+    gb, _, d0 = frame0
+    for win in (-1, 32, 40):
+        o, d = run_pair(env, orc, env["cam"], env["lens"], env["params"], gb, knobs={"gather_window": win})
+        compare_frame(o, d, f"gather window {win}")
+        assert np.array_equal(d["gather"], d0["gather"]), win
 
 
 def test_reconstruction_global_fallback_parity(env, orc):

@@ -51,7 +51,7 @@ def gpu_frame(big, cam, gb, hist_in=None, prev_cam=None, fmt=None, lens=None, pa
     lens = big["lens"] if lens is None else lens
     params = big["params"] if params is None else params
     gs = big["gs"] if gs is None else gs
-    fr = dof.Frame(cam.width, cam.height, params, out_format=fmt)
+    fr = dof.Frame(cam.width, cam.height, params, out_format=fmt, ray_records=True)
     g = (torch.from_numpy(gb.colour).cuda().half(), torch.from_numpy(gb.depth).cuda(),
          torch.from_numpy(gb.normal).cuda().half())
     hin = torch.from_numpy(hist_in).cuda() if hist_in is not None else None
@@ -160,7 +160,7 @@ def test_full_frame_4k_hexagon(big, orc):
     assert lens1.focus != lens.focus
     gb1 = half_gb(orc, orc.gbuffer(osc, cam1, lens1))
     o1 = orc.render_frame(osc, cam1, lens1, params, gb1, hist_in=o["hist_out"], prev_cam=cam, prev_lens=lens)
-    fr = big["dof"].Frame(cam1.width, cam1.height, params, out_format=big["dof"].RGBA16F)
+    fr = big["dof"].Frame(cam1.width, cam1.height, params, out_format=big["dof"].RGBA16F, ray_records=True)
     g = (torch.from_numpy(gb1.colour).cuda().half(), torch.from_numpy(gb1.depth).cuda(),
          torch.from_numpy(gb1.normal).cuda().half())
     hin = torch.from_numpy(o["hist_out"]).cuda()
@@ -189,7 +189,7 @@ def small_env(orc):
 
 def run_small(torch, dof, gs, osc, orc, cam, lens, params, gb):
     o = orc.render_frame(osc, cam, lens, params, gb)
-    fr = dof.Frame(cam.width, cam.height, params)
+    fr = dof.Frame(cam.width, cam.height, params, ray_records=True)
     g = (torch.from_numpy(gb.colour).cuda(), torch.from_numpy(gb.depth).cuda(), torch.from_numpy(gb.normal).cuda())
     fr.render(gs, cam, lens, g, None, dof.history_alloc(cam.width, cam.height))
     torch.cuda.synchronize()
@@ -243,7 +243,7 @@ def test_rejected_arguments(orc):
     with pytest.raises(dof.DofError) as e:
         dof.Frame(255, 256, params)
     assert e.value.code == dof.DOF_E_INVALID
-    fr = dof.Frame(cam.width, cam.height, params)
+    fr = dof.Frame(cam.width, cam.height, params, ray_records=True)
     gb = orc.gbuffer(osc, cam, lens)
     g = (torch.from_numpy(gb.colour).cuda(), torch.from_numpy(gb.depth).cuda(), torch.from_numpy(gb.normal).cuda())
     hist = dof.history_alloc(cam.width, cam.height)

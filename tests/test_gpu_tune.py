@@ -65,3 +65,72 @@ def test_extreme_grids_agree():
     for tb in (1, 3, 4096):
         for a, r in zip(out[tb], out[0]):
             assert np.array_equal(a, r), tb
+
+
+def test_launch_knobs_never_change_a_result():
+    """Every value of every launch knob the autotuner searches (traversal
+    stack depth, queue width, refill and leaf-batch thresholds, the gather's
+    LDS window, including no staging) renders the same frame bit for bit --
+    colour, mask, history -- on the 256 x 256 workload and a second frame
+    with history, alone and in a batch of two."""
+    import dataclasses
+    import torch
+    from paper_2210_06158_amd import dof, tune
+    torch.cuda.set_device(0)
+    scene, cam, lens, params = synth.scene_small()
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    cam1 = synth.pan_camera(dataclasses.replace(cam, frame=1), 0.02)
+    gbs = [gs.render_gbuffer(c, lens) for c in (cam, cam1)]
+
+    def render(knobs, tb=0):
+        fr = dof.Frame(cam.width, cam.height, params, trace_blocks=tb, knobs=knobs)
+        h0, h1 = dof.history_alloc(cam.width, cam.height), dof.history_alloc(cam.width, cam.height)
+        fr.render(gs, cam, lens, gbs[0], None, h0)
+        fr.render(gs, cam1, lens, gbs[1], h0, h1, prev_cam=cam, prev_lens=lens)
+        frs = [dof.Frame(cam.width, cam.height, params, knobs=knobs) for _ in range(2)]
+        hs = [dof.history_alloc(cam.width, cam.height) for _ in range(2)]
+        b = dof.Batch(2, params, trace_blocks=tb, knobs=knobs)
+        b.set([frs[0].item(gs, cam, lens, gbs[0], None, hs[0]),
+               frs[1].item(gs, cam1, lens, gbs[1], h0, hs[1], prev_cam=cam, prev_lens=lens)])
+        b.run()
+        torch.cuda.synchronize()
+        return [fr.colour.cpu().numpy(), fr.mask.cpu().numpy(), h1.cpu().numpy(), fr.stats.cpu().numpy()[:2],
+                frs[0].colour.cpu().numpy(), frs[1].colour.cpu().numpy(), hs[1].cpu().numpy()]
+
+    ref = render({})
+    assert ref[3][1] > 1000
+    cases = [{k: v} for k, vals in tune.KNOB_SPACE.items() if k != "trace_blocks" for v in vals]
+    cases.append({"trace_stack": 16, "trace_grab": 1, "trace_refill": 1, "trace_leaf_batch": 1, "gather_window": 32})
+    cases.append({"trace_stack": 32, "trace_grab": 256, "trace_refill": 64, "trace_leaf_batch": 64,
+                  "gather_window": -1})
+    for knobs in cases:
+        got = render(knobs)
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r), knobs
+
+
+def test_search_picks_the_fastest_per_knob():
+    """Coordinate descent: each knob's candidates are all timed with the
+    others held at the running best, and the fastest is kept."""
+    import torch
+    from paper_2210_06158_amd import dof, tune
+    torch.cuda.set_device(0)
+    scene, cam, lens, params = synth.scene_small()
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    gb = gs.render_gbuffer(cam, lens)
+    h = dof.history_alloc(cam.width, cam.height)
+    seen = []
+
+    def run(cfg):
+        seen.append(dict(cfg))
+        tb, knobs = tune.split(cfg)
+        dof.Frame(cam.width, cam.height, params, trace_blocks=tb, knobs=knobs).render(gs, cam, lens, gb, None, h)
+
+    space = {"trace_blocks": (0, 256), "trace_stack": (16, 24), "gather_window": (-1, 48)}
+    cfg, table = tune.search(run, space=space, reps=1)
+    assert set(table) == set(space)
+    for k, times in table.items():
+        assert set(times) == set(space[k]) and cfg[k] == min(times, key=times.get)
+    assert all(set(c) == set(space) for c in seen)

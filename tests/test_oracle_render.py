@@ -709,8 +709,9 @@ def _upsample(plane, W, H):
                      for c in range(3)], -1)
 
 
+@pytest.mark.parametrize("literal", [0, 1])
 @pytest.mark.parametrize("case", ["far_near_hits", "far_far_hits", "far_all_miss", "near_bright", "near_dim"])
-def test_composite_blend_ends(orc, case):
+def test_composite_blend_ends(orc, case, literal):
     """A14's blends at their ends, every half-res pixel ray traced (mask mode
     all) and outside the zone of focus.  Far field (eq. 7): when every ray
     hits in front of the focus plane (ratio 1) the output is the upsampled
@@ -718,7 +719,10 @@ def test_composite_blend_ends(orc, case):
     upsampled post-process image.  Near field: taps all brighter than
     l_spec (bokeh proportion 1) give the post-process image, all dimmer (0)
     the reconstruction.  The G-buffer is a random texture at one depth, so
-    the two images differ; the scene decides what the rays see."""
+    the two images differ; the scene decides what the rays see.  With the
+    literal reading of the far-field rule (composite_literal) the far-field
+    ends swap: ratio 1 gives the post-process image, ratio 0 the
+    reconstruction; the near field does not change."""
     W, H = 64, 48
     far = case.startswith("far")
     z = 40.0 if far else 2.0
@@ -733,13 +737,16 @@ def test_composite_blend_ends(orc, case):
     sc = orc.OracleScene(plane_scene(plane_z))
     sc.build_bvh()
     cam = synth.look_camera((0, 0, 0), 0, 0, W, H)
-    o = orc.render_frame(sc, cam, lens, synth.Params(mask_mode=synth.MASK_ALL, m=4), gb)
+    o = orc.render_frame(sc, cam, lens, synth.Params(mask_mode=synth.MASK_ALL, m=4, composite_literal=literal), gb)
     assert np.all(o["mask"] == 4)
     if far:
         assert np.all(o["recon"][..., 3] == (1.0 if case == "far_near_hits" else 0.0))
     rt, pp = _upsample(o["recon"], W, H), _upsample(o["ppmed"], W, H)
     assert np.abs(rt - pp).max() > 0.05                                    # the two images differ
-    want = rt if case in ("far_near_hits", "near_dim") else pp
+    to_rt = case in ("far_near_hits", "near_dim")
+    if far and literal:
+        to_rt = not to_rt
+    want = rt if to_rt else pp
     np.testing.assert_allclose(o["colour"][..., :3], want, rtol=0, atol=2e-5)
 
 

@@ -59,7 +59,8 @@ def test_host_library_under_address_and_ub_sanitizers(tmp_path):
              "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     objs = []
     procs = []
-    for src in ("api.hip", "bvh.hip", "frame.hip", "trace.hip"):
+    from paper_2210_06158_amd import build as pkg_build
+    for src in pkg_build.SOURCES:
         o = str(tmp_path / src.replace(".hip", ".o"))
         objs.append(o)
         procs.append(subprocess.Popen(["hipcc", *flags, *host_san, "-c", os.path.join(CSRC, src), "-o", o],
@@ -68,7 +69,8 @@ def test_host_library_under_address_and_ub_sanitizers(tmp_path):
         out, _ = p.communicate(timeout=900)
         assert p.returncode == 0, out
     lib = str(tmp_path / "libdof_san.so")
-    rc, out = _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libsan", *host_san, *objs, "-o", lib])
+    rc, out = _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libsan", *host_san, *objs,
+                    *pkg_build.LINK_FLAGS, "-o", lib])
     assert rc == 0, out
     code = (
         "import sys\n"
