@@ -305,6 +305,23 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
                             const dof_frame_out *out, void *scratch, size_t scratch_bytes,
                             void *stream);
 
+/* dof_render_frame without a caller scratch buffer, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The scratch is a buffer of
+ * DOF_NOALLOC_SCRATCH_MB MiB that the library keeps on each GPU it runs on
+ * until the process ends; this call allocates nothing.  Frames whose
+ * dof_frame_scratch_bytes exceeds it (e.g. 640 x 360 at m = 8 fits, 1920 x
+ * 1080 does not) and params.timing != 0 return DOF_E_UNSUPPORTED; everything
+ * else behaves as dof_render_frame.  Every call on a GPU shares that GPU's
+ * buffer: calls that overlap on one GPU (two streams or two threads) race,
+ * and the per-frame planes of dof_debug_view_get are only those of the last
+ * call.  The buffer's device address is looked up on the first call on each
+ * device (outside a stream capture, preferably). */
+#define DOF_NOALLOC_SCRATCH_MB 64
+dof_status dof_render_frame_noalloc(dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
+                                    const dof_gbuffer *gb, const dof_history_io *hist, const dof_params *p,
+                                    const dof_frame_out *out, void *stream);
+
 /* Stages timed when params.timing is set, in launch order. */
 #define DOF_NUM_STAGES 13
 /* Per-stage device time (ms) of the scene's most recent frame rendered with

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdof.so")
-SOURCES = ["api.hip", "bvh.hip", "frame.hip", "trace.hip"]
+SOURCES = ["api.hip", "bvh.hip", "frame.hip", "trace.hip", "noalloc.hip"]
 
 ARCH = os.environ.get("DOF_OFFLOAD_ARCH", "gfx950")
 # roctx ranges around the entry points (rocprofv3 --marker-trace)

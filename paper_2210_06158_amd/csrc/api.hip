@@ -482,6 +482,16 @@ struct dof_batch {
     std::vector<char> host;            // staging copy of the table
 };
 
+// the error message of a failing call made in another translation unit
+dof_status dof::set_error(dof_status code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(code, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
 extern "C" {
 
 int32_t dof_abi_version(void) { return DOF_ABI_VERSION; }

@@ -229,6 +229,9 @@ __device__ inline float coc_px(float cock, float d, float z) { return cock * fab
 
 // ---------------------------------------------------------------- launchers
 
+// api.hip: sets the calling thread's dof_last_error message and returns code
+dof_status set_error(dof_status code, const char *fmt, ...);
+
 // bvh.hip
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 

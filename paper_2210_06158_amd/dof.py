@@ -95,7 +95,9 @@ EXPORTS = ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_scene
            "dof_build_bvh", "dof_bvh_view_get", "dof_destroy_scene", "dof_trace_rays", "dof_render_gbuffer",
            "dof_history_bytes", "dof_history_reset", "dof_frame_scratch_bytes", "dof_render_frame",
            "dof_debug_view_get", "dof_stage_times", "dof_batch_bytes", "dof_batch_create", "dof_batch_set",
-           "dof_batch_run", "dof_batch_destroy", "dof_reference_scratch_bytes", "dof_render_reference")
+           "dof_batch_run", "dof_batch_destroy", "dof_reference_scratch_bytes", "dof_render_reference",
+           "dof_render_frame_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 STAGES = ("reduce", "dilate", "prefilter", "gather", "median", "mask", "compact", "trace", "resolve", "temporal",
           "blur_median_mips", "recon", "composite")
@@ -142,6 +144,8 @@ def lib():
         L.dof_batch_run.argtypes = [vp, vp, vp]
         L.dof_reference_scratch_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_size_t)]
         L.dof_render_reference.argtypes = [vp, P(DofCamera), P(DofLens), C.c_int32, vp, C.c_int32, vp, C.c_size_t, vp]
+        L.dof_render_frame_noalloc.argtypes = [vp, P(DofCamera), P(DofLens), P(DofGBuffer), P(DofHistoryIO),
+                                               P(DofParams), P(DofFrameOut), vp]
         L.dof_batch_destroy.argtypes = [vp]
         L.dof_batch_destroy.restype = None
         for name in EXPORTS:
@@ -341,6 +345,15 @@ class Frame:
         check(lib().dof_render_frame(it.scene, C.byref(it.camera), C.byref(it.lens), C.byref(it.gbuffer),
                                      C.byref(it.history), C.byref(self.ps), C.byref(it.out), it.scratch,
                                      it.scratch_bytes, _stream()))
+
+    def render_noalloc(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None,
+                       reset=False):
+        """The same frame through dof_render_frame_noalloc: the library's own
+        scratch buffer instead of this frame's (outputs land in this frame's
+        colour, mask and stats; debug() does not see that scratch)."""
+        it = self.item(scene, cam, lens, gb, hist_in, hist_out, prev_cam, prev_lens, reset)
+        check(lib().dof_render_frame_noalloc(it.scene, C.byref(it.camera), C.byref(it.lens), C.byref(it.gbuffer),
+                                             C.byref(it.history), C.byref(self.ps), C.byref(it.out), _stream()))
 
     def debug(self):
         """Host copies of every intermediate plane (synchronises)."""

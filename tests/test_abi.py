@@ -228,6 +228,25 @@ def test_scene_creation_fails_cleanly_without_a_device(dof):
     assert L.dof_create_scene(C.byref(desc), C.c_void_p(1 << 40), b.value - 1, None, C.byref(h)) == dof.DOF_E_NOMEM
 
 
+def test_noalloc_rejects_frames_beyond_its_buffer(dof):
+    import ctypes as C
+    from paper_2210_06158_amd import synth
+    L = dof.lib()
+    p = dof.params_struct(synth.Params(m=8))
+    b = C.c_size_t()
+    assert L.dof_frame_scratch_bytes(1920, 1080, C.byref(p), C.byref(b)) == 0 and b.value > dof.NOALLOC_SCRATCH_BYTES
+    cam = dof.DofCamera()
+    cam.width, cam.height = 1920, 1080
+    cam.right[0], cam.up[1], cam.fwd[2] = 1.0, 1.0, 1.0
+    lens = dof.DofLens(0.05, 1.4, 15.0, 0.036, 0, 0.0)
+    st = L.dof_render_frame_noalloc(C.c_void_p(1), C.byref(cam), C.byref(lens), None, None, C.byref(p), None, None)
+    assert st == dof.DOF_E_UNSUPPORTED and b"needs" in L.dof_last_error()
+    p.timing = 1
+    cam.width, cam.height = 64, 64
+    st = L.dof_render_frame_noalloc(C.c_void_p(1), C.byref(cam), C.byref(lens), None, None, C.byref(p), None, None)
+    assert st == dof.DOF_E_UNSUPPORTED and b"timing" in L.dof_last_error()
+
+
 def test_launch_knob_ranges(dof):
     L = dof.lib()
     b = C.c_size_t()
