@@ -136,8 +136,9 @@ typedef struct {
     int32_t composite_literal;
     /* Launch-shape knobs, searched by the autotuner (0 = library default);
      * no result depends on them.  gather_window: side of the LDS window in
-     * which the post-process gather stages a tile's texels, 32, 40 or 48
-     * (default 48), or -1 to read every tap from global memory.  trace_stack:
+     * which the post-process gather stages the texels of each tile whose taps
+     * fit it, 32, 40 or 48, or -1 (and the default 0): every tap read from
+     * global memory.  trace_stack:
      * LDS traversal stack entries per lane, 16, 24 (default) or 32.
      * trace_grab: rays a wave takes from the shared work counter at a time,
      * 1..256 (default 64).  trace_refill: idle lanes at which a wave takes

@@ -121,7 +121,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa, int ray_records)
     L.pre = take(16 * np);
     L.gather = take(16 * np);
     L.ppmed = take(16 * np);
-    L.za = take(8 * np);
+    L.gtex = take(16 * np);
     L.prev_idx = take(4 * np);
     L.mask_raw = take(np);
     L.chunk_cnt = take(8 * (size_t)L.nchunks);
@@ -348,7 +348,7 @@ void fill_frame_const(const dof_scene *s, const dof_camera &cam, const dof_lens 
     fc.taa = p.taa;
     fc.ray_records = p.ray_records;
     fc.composite_literal = p.composite_literal;
-    fc.gather_win = p.gather_window == 0 ? 48 : (p.gather_window < 0 ? 0 : p.gather_window);
+    fc.gather_win = p.gather_window <= 0 ? 0 : p.gather_window;
     fc.tk = trace_knobs(p);
     fc.have_hist = have_hist;
     fc.motion = motion;

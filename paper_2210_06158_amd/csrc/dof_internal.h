@@ -112,7 +112,7 @@ struct ScratchLayout {
     size_t colr, zn, zh, tile_max, tile_dil, pre, gather, ppmed, prev_idx, mask_raw;
     size_t chunk_cnt, chunk_off, counters;
     size_t queue, ray_base, ray_pix, ray_rec, ray_lt, ray_hit, ray_t, ray_col, ray_pos;
-    size_t za, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
+    size_t gtex, resolve, temporal, var_blur, rtmed, mips, tap, recon, comp, rast, pptaa;
     size_t total;
     int64_t nchunks;
 };
@@ -134,7 +134,8 @@ struct Planes {
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;
     float2 *tap;             // per half-res pixel: (CoC if ray traced else -inf, hit ratio)
-    float2 *za;              // per half-res pixel: (depth, gather weight 1 / max(|r|, 1/2)^2)
+    float4 *gtex;            // per half-res pixel, as the gather reads it: prefiltered rgb and |CoC radius|,
+                             // the radius's sign bit set for a bright (specular) pixel
     uint8_t *mask_raw;       // adaptive ray counts before dilation (mask mode DOF_MASK_DILATE)
     float4 *comp;            // full-res composite colour before the final TAA (DOF_TAA_FINAL)
     float4 *rast;            // full-res raster colour after its TAA (DOF_TAA_RASTER)

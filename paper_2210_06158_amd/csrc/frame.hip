@@ -198,7 +198,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.rtmed = reinterpret_cast<float4 *>(s + L.rtmed);
     p.mips = reinterpret_cast<float4 *>(s + L.mips);
     p.tap = reinterpret_cast<float2 *>(s + L.tap);
-    p.za = reinterpret_cast<float2 *>(s + L.za);
+    p.gtex = reinterpret_cast<float4 *>(s + L.gtex);
     p.mask_raw = reinterpret_cast<uint8_t *>(s + L.mask_raw);
     p.comp = (fc.taa & DOF_TAA_FINAL) ? reinterpret_cast<float4 *>(s + L.comp) : nullptr;
     p.rast = (fc.taa & DOF_TAA_RASTER) ? reinterpret_cast<float4 *>(s + L.rast) : nullptr;
@@ -328,13 +328,12 @@ __device__ inline void b_prefilter(const FrameConst &fc, const Planes &P, const 
         }
     const float4 pre = make_float4(ax / sw, ay / sw, az / sw, rc);
     P.pre[i] = pre;
-    // depth and the gather's per-tap weight of this pixel (sampleAlpha of
-    // eq. 1 read as 1 / max(|r|, 1/2)^2), computed once here instead of at
-    // each of the 81 taps that read this pixel; its sign carries whether the
-    // pixel counts as a bright (specular) sample of the bokeh share
-    const float mr = fmax_cs(fabsf(rc), 0.5f);
-    const float alpha = 1.0f / (mr * mr);
-    P.za[i] = make_float2(P.zh[i], luma709(pre.x, pre.y, pre.z) > fc.l_spec ? -alpha : alpha);
+    // the texel as the gather's taps read it, one 16-byte load: colour, the
+    // radius's magnitude (the only part the gather uses) and, in its sign
+    // bit, whether the pixel counts as a bright (specular) sample of the
+    // bokeh share
+    const bool bright = luma709(pre.x, pre.y, pre.z) > fc.l_spec;
+    P.gtex[i] = make_float4(pre.x, pre.y, pre.z, __uint_as_float(__float_as_uint(fabsf(rc)) | (bright ? 0x80000000u : 0u)));
 }
 
 __global__ __launch_bounds__(kBX *kBY) void k_prefilter(FrameConst fc, Planes P)
@@ -356,13 +355,16 @@ __global__ __launch_bounds__(kBX *kBY) void kb_prefilter(const Job *__restrict__
 // tap offset is the same for the whole block.  Each tap's texel column
 // (per pixel column of the tile) and row (per pixel row) are computed once
 // per block into LDS tables, with the same binary32 operations as the
-// per-pixel definition, so the nearest-texel decisions are identical.  A
-// tile whose taps stay within kGatherWin x kGatherWin texels (R_n <= 15)
-// first stages that window of the prefiltered colour and the (depth, weight)
-// plane in LDS and reads its taps there; a wider tile reads them from global
-// memory (L1/L2), in a second kernel that needs little LDS and so keeps
-// many waves resident.  The window side (32, 40 or 48, or no staging) is a
-// launch knob of the autotuner.
+// per-pixel definition, so the nearest-texel decisions are identical.  Each
+// tap is one 16-byte load of the prefilter's gather texel (colour, radius
+// magnitude, bright flag).  Optionally (launch knob gather_window) a tile
+// whose taps stay within a win x win texel window first stages that window
+// (texels and depths) in LDS and reads its taps there, in a kernel of its
+// own; the other tiles read their taps from global memory (L1/L2) in a
+// kernel that needs little LDS and so keeps many waves resident.  On the
+// 1080p and 4K workloads the global reads are faster (the tiles that fit a
+// window are the ones whose centres need the depth term, and the staging
+// kernel holds fewer waves), so no staging is the default.
 //
 // Per tap, with D_fg = [|r_i| > dist] and D_bg = D_fg and [|r_c| > dist]:
 // the two weights of eq. (1) add up to alpha when D_bg holds (foreground and
@@ -376,35 +378,40 @@ __device__ inline bool gather_fits(float Rn, int win) { return win > 0 && kTile 
 
 // The taps of one ring (one distance): kBg when some lane of the wave has a
 // centre radius at or below the ring's distance, so that its background taps
-// need w_bg (a wave-uniform choice; the division runs only then).
+// need w_bg (a wave-uniform choice; the depth load and the division run only
+// then).  sampleAlpha = 1 / max(|r|, 1/2)^2 with a hardware reciprocal
+// (weights are normalised by their sum; tolerance parity).
 template <bool kLds, bool kBg>
-__device__ inline void gather_ring(const Rings &rings, const Planes &P, const float4 *s_pre, const float2 *s_za,
-                                   const short *ixt, const short *iyt, int hw, int k0, int k1, float dist,
-                                   bool centre_far, float zc, float range, float &v0, float &v1, float &v2,
-                                   float &sw, float &ss)
+__device__ inline void gather_ring(const Planes &P, const float4 *s_tex, const float *s_z, const short *ixt,
+                                   const short *iyt, int hw, int k0, int k1, float dist, bool centre_far, float zc,
+                                   float range, float &v0, float &v1, float &v2, float &sw, float &ss)
 {
 #pragma unroll 4
     for (int k = k0; k < k1; ++k) {
         const int ix = ixt[k * kTile], iy = iyt[k * kTile];
         float4 ci;
-        float2 za;
+        uint32_t j = 0;
         if constexpr (kLds) {
-            ci = s_pre[iy + ix];
-            za = s_za[iy + ix];
+            j = (uint32_t)(iy + ix);
+            ci = s_tex[j];
         } else {
-            const uint32_t j = __umul24((uint32_t)iy, (uint32_t)hw) + (uint32_t)ix;
-            ci = P.pre[j];
-            za = P.za[j];
+            j = __umul24((uint32_t)iy, (uint32_t)hw) + (uint32_t)ix;
+            ci = P.gtex[j];
         }
-        const float alpha = fabsf(za.y);
+        const float ari = fabsf(ci.w);
+        const float mr = fmax_cs(ari, 0.5f);
+        const float alpha = __builtin_amdgcn_rcpf(mr * mr);
         float wb = alpha;
-        if constexpr (kBg) wb = centre_far ? alpha : alpha * (1.0f - sat((za.x - zc) / range));
-        const float w = fabsf(ci.w) > dist ? wb : 0.0f;
-        v0 = v0 + w * ci.x;
-        v1 = v1 + w * ci.y;
-        v2 = v2 + w * ci.z;
+        if constexpr (kBg) {
+            const float zi = kLds ? s_z[j] : P.zh[j];
+            wb = centre_far ? alpha : alpha * (1.0f - sat((zi - zc) / range));
+        }
+        const float w = ari > dist ? wb : 0.0f;
+        v0 = fmaf(w, ci.x, v0);
+        v1 = fmaf(w, ci.y, v1);
+        v2 = fmaf(w, ci.z, v2);
         sw = sw + w;
-        ss = ss + (za.y < 0.0f ? w : 0.0f);
+        ss = ss + ((__float_as_uint(ci.w) >> 31) ? w : 0.0f);
     }
 }
 
@@ -418,8 +425,8 @@ __device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const 
     // per tap: the texel column of each pixel column of the tile and the
     // texel row (LDS variant: window row times window width) of each pixel row
     __shared__ short s_ix[kRingTaps * kTile], s_iy[kRingTaps * kTile];
-    __shared__ float4 s_pre[kLds ? kWin * kWin : 1];
-    __shared__ float2 s_za[kLds ? kWin * kWin : 1];
+    __shared__ float4 s_tex[kLds ? kWin * kWin : 1];
+    __shared__ float s_z[kLds ? kWin * kWin : 1];
     const int tid = threadIdx.x;
     const int x0 = (int)tx * kTile, y0 = (int)ty * kTile;
     const float Rn = P.tile_dil[(size_t)ty * fc.tw + tx];
@@ -440,12 +447,15 @@ __device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const 
         }
     }
     if constexpr (kLds) {
-        const int n = ww * (wy1 - wy0 + 1);
-        for (int t = tid; t < n; t += 256) {
-            const size_t j = (size_t)(wy0 + t / ww) * fc.hw + (wx0 + t % ww);
-            s_pre[t] = P.pre[j];
-            s_za[t] = P.za[j];
-        }
+        // rows of the window, 64 texels wide at a time (kWin <= 64)
+        static_assert(kWin <= 64, "one pass of 64 columns per window row");
+        const int c = tid & 63;
+        if (c < ww)
+            for (int r = tid >> 6; r <= wy1 - wy0; r += 4) {
+                const size_t j = (size_t)(wy0 + r) * fc.hw + (wx0 + c);
+                s_tex[r * ww + c] = P.gtex[j];
+                s_z[r * ww + c] = P.zh[j];
+            }
     }
     __syncthreads();
     const int lx = tid & (kTile - 1), ly = tid / kTile;
@@ -463,10 +473,10 @@ __device__ inline void b_gather(const FrameConst &fc, const Rings &rings, const 
         const float dist = Rn * rings.frac[k0];
         const bool centre_far = arc > dist;   // background taps need the centre's radius too
         if (__all(centre_far))
-            gather_ring<kLds, false>(rings, P, s_pre, s_za, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, true, zc,
+            gather_ring<kLds, false>(P, s_tex, s_z, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, true, zc,
                                      fc.depth_range, v0, v1, v2, sw, ss);
         else
-            gather_ring<kLds, true>(rings, P, s_pre, s_za, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, centre_far, zc,
+            gather_ring<kLds, true>(P, s_tex, s_z, s_ix + lx, s_iy + ly, fc.hw, k0, k1, dist, centre_far, zc,
                                     fc.depth_range, v0, v1, v2, sw, ss);
     }
     float4 o;

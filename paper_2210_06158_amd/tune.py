@@ -32,7 +32,7 @@ KNOB_SPACE = {
     "gather_window": (-1, 32, 40, 48),
 }
 DEFAULTS = {"trace_blocks": 0, "trace_stack": 24, "trace_grab": 64, "trace_refill": 16, "trace_leaf_batch": 32,
-            "gather_window": 48}
+            "gather_window": -1}
 
 
 def candidate_blocks(extra=()):
