@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-blocks", type=int, default=-1,
                     help="persistent traversal blocks (0 = library default, -1 = autotuned per workload)")
+    ap.add_argument("--config", type=str, default=None,
+                    help="launch shapes as JSON (trace_blocks and dof_params knobs, e.g. the autotuner's pick) "
+                         "for every workload, instead of autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device (a reference kernel of "
                          "known traffic for hardware byte counters)")
@@ -153,6 +156,13 @@ def l2_figure(mt, ms):
     return {"requests_per_launch": round(req), "hit_rate": round(mt["tcc_hit"] / req, 4),
             "grequests_per_s": round(req / (ms * 1e-3) / 1e9, 2),
             "GB_per_s_at_128B_per_request": round(req * 128 / (ms * 1e-3) / 1e9, 1)}
+
+
+def fixed_config(args):
+    """The launch shapes given on the command line (None: autotune)."""
+    if args.config:
+        return json.loads(args.config)
+    return {"trace_blocks": args.trace_blocks} if args.trace_blocks >= 0 else None
 
 
 def frame_for(W, H, params, cfg, **kw):
@@ -393,8 +403,8 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     gbuffer_ms = e0.elapsed_time(e1) / nfr
-    tb, grid = {"trace_blocks": args.trace_blocks}, None
-    if args.trace_blocks < 0:
+    tb, grid = fixed_config(args), None
+    if tb is None:
         tb, grid = autotune(gs, cams, [lens] * nfr, params, gbs, log, "1080p")
     r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, tb, log,
                  latency_passes=max(1, args.latency_passes))
@@ -625,8 +635,8 @@ def uhd_leg(args, log):
     gs.build_bvh()
     gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams, lenses)]
     torch.cuda.synchronize()
-    tb, grid = {"trace_blocks": args.trace_blocks}, None
-    if args.trace_blocks < 0:
+    tb, grid = fixed_config(args), None
+    if tb is None:
         tb, grid = autotune(gs, cams, lenses, params, gbs, log, "4k")
     r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), tb, log)
     out = {

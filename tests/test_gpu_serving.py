@@ -55,3 +55,36 @@ def test_admission_by_memory_budget(server):
     assert small.admit(server["specs"][0])
     assert not small.admit(server["specs"][1])
     assert small.rejected == 1 and len(small.sessions) == 1 and small.used <= small.budget
+
+
+def test_served_frames_match_the_oracle(server, orc):
+    """The first two frames served for two sessions (continuous batching,
+    FP16 G-buffer and output) against the CPU oracle rendering the same views
+    in sequence, the second on the first's history, from the same G-buffers
+    (the oracle's, rounded to FP16 as the sessions store them): colour within
+    1e-3 and the history record after the second frame within 1e-5."""
+    import numpy as np
+    torch, serve, srv = server["torch"], server["serve"], server["srv"]
+    arrivals = [(0.0, 0), (0.0, 1), (0.05, 0), (0.05, 1)]
+    kept = {}
+    m = srv.run(arrivals, 0.1, mode="batched", keep=kept)
+    assert m["served"] == 4 and m["superseded"] == 0
+    for sid in (0, 1):
+        sess = srv.sessions[sid]
+        scene, cams, lens, _ = synth.scene_session(server["specs"][sid])
+        osc = orc.OracleScene(scene)
+        osc.build_bvh()
+        hist, prev = None, None
+        for k in range(2):
+            cam = sess.cam(k)
+            g = orc.gbuffer(osc, sess.cams[k % len(sess.ring)], lens)
+            gb = orc.GBuffer(g.colour.astype(np.float16).astype(np.float32), g.depth,
+                             g.normal.astype(np.float16).astype(np.float32))
+            o = orc.render_frame(osc, cam, lens, server["params"], gb, hist_in=hist, prev_cam=prev,
+                                 prev_lens=lens if prev is not None else None, debug=False)
+            got = kept[sid][k].float().cpu().numpy()
+            err = float(np.abs(got[..., :3] - o["colour"][..., :3]).max())
+            assert err <= 1e-3, (sid, k, err)
+            hist, prev = o["hist_out"], cam
+        # the session's history after its second frame equals the oracle's
+        np.testing.assert_allclose(sess.history_out().cpu().numpy(), hist, rtol=1e-5, atol=1e-5)
