@@ -104,9 +104,10 @@ def stage_bytes(stage, W, H, P, R):
         # generation: pixel, queue entry and offset of each ray in, its 48-byte record out
         "compact": 2 * h + P * 8 + R * 4 + R * (12 + 48),
         "trace": R * (48 + 8),                      # ray record in; (leaf, t) out
-        # one pass: (leaf, t), origin and direction of each ray in, its hit, t, colour, position record
-        # out; queue entry, ray offset, count in and 4 planes out per masked px
-        "resolve": R * (8 + 32 + 40) + P * (4 + 4 + 1 + 64),
+        # one pass: (leaf, t), origin and direction of each ray in (the per-ray hit, t, colour and
+        # position planes are off in measured runs); queue entry, ray offset, count in and 4 planes
+        # out per masked px
+        "resolve": R * (8 + 32) + P * (4 + 4 + 1 + 64),
         # count, prev index, resolve planes, history A B C in; T0 T1 and history A B C out
         "temporal": h * (1 + 4 + 64 + 48) + h * (32 + 48),
         # T0 T1 in; variance, history variance, tap record, median, mip level 0 (+ levels 1-3) out

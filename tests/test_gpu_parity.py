@@ -194,57 +194,101 @@ def test_rays_lying_on_a_box_face(env, orc):
     assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
 
 
-def caterpillar_scene():
-    """Triangles whose Morton codes are 0, 2^k (k = 0..62) and 2^63 - 1: the
-    radix tree is a chain about 63 deep.  Every triangle is huge and they all
-    overlap, so a ray enters both children at every level and the traversal
-    stack outgrows its 24 LDS entries: the oldest entries are dropped and
-    found again by walking parent links, which must not change any hit."""
+def morton_cell(code):
+    """Integer cell (x, y, z) of a 63-bit Morton code (bit 3i+2 is x, 3i+1 y,
+    3i z)."""
+    x = y = z = 0
+    for i in range(21):
+        z |= ((code >> (3 * i)) & 1) << i
+        y |= ((code >> (3 * i + 1)) & 1) << i
+        x |= ((code >> (3 * i + 2)) & 1) << i
+    return float(x), float(y), float(z)
+
+
+def ladder_scene():
+    """A tree about 62 levels deep in which every level has two internal
+    children: triangle centroids on the Morton codes 0, 1 and 2^k, 2^k + 1
+    (k = 1..62), plus one at (2^21, 2^21, 2^21) that fixes the grid to unit
+    cells.  The top split at level k separates the pair {2^k, 2^k + 1} (an
+    internal node with two leaves) from the rest.  Every triangle is huge
+    and they all overlap, so a ray enters both children everywhere; the
+    remaining chain's box contains the pair's, so the chain is the near child
+    and the pair is pushed, about 62 entries: the LDS stack (16, 24 or 32
+    entries) overflows, its oldest entries are dropped and must be found
+    again by walking parent links.  The three vertex depths are permuted per
+    triangle (bounds and centroid unchanged), so the planes tilt differently
+    and the closest hit varies across rays; a traversal that lost the dropped
+    entries returns a different hit for many of them."""
+    import itertools
     S = float(2 ** 23)
-    cents = [(0.0, 0.0, 0.0), (2.0 ** 21, 2.0 ** 21, 2.0 ** 21)]
-    for k in range(63):
-        axis = 2 - (k % 3)                      # bit 3i+2 is x, 3i+1 y, 3i z
-        c = [0.0, 0.0, 0.0]
-        c[axis] = float(2 ** (k // 3))
-        cents.append(tuple(c))
+    codes = [0, 1]
+    for k in range(1, 63):
+        codes += [1 << k, (1 << k) + 1]
+    cents = [morton_cell(c) for c in codes] + [(2.0 ** 21, 2.0 ** 21, 2.0 ** 21)]
+    perms = list(itertools.permutations((-1.0, 1.0, 0.0)))
     tris = []
-    for cx, cy, cz in cents:
-        tris.append([cx - S, cy - S, cz - S, cx + S, cy - S, cz + S, cx, cy + S, cz])
+    for i, (cx, cy, cz) in enumerate(cents):
+        p = perms[(i * 7 + i // 5) % 6]
+        tris.append([cx - S, cy - S, cz + p[0] * S, cx + S, cy - S, cz + p[1] * S, cx, cy + S, cz + p[2] * S])
     v = np.array(tris, np.float32)
     return synth.Scene(v, np.ones((v.shape[0], 3), np.float32))
 
 
-def test_deep_tree_stack_spill(env, orc):
-    torch, dof = env["torch"], env["dof"]
-    sc = caterpillar_scene()
+def ladder_rungs(ob, n):
+    """Internal nodes of the oracle's tree whose two children are internal."""
+    left, right = ob["left"][:n - 1], ob["right"][:n - 1]
+    return int(np.sum(((left & LEAF) == 0) & ((right & LEAF) == 0)))
+
+
+@pytest.fixture(scope="module")
+def ladder(env, orc):
+    dof = env["dof"]
+    sc = ladder_scene()
     osc = orc.OracleScene(sc)
     ob = osc.build_bvh()
     gs = dof.Scene(sc)
     gs.build_bvh()
-    torch.cuda.synchronize()
+    env["torch"].cuda.synchronize()
+    assert ladder_rungs(ob, sc.ntri) >= 60
+    return sc, osc, ob, gs
+
+
+def test_deep_tree_stack_drops(env, orc, ladder):
+    torch = env["torch"]
+    sc, osc, ob, gs = ladder
     view = gs.bvh_view()
     assert np.array_equal(view["keys"].cpu().numpy().view(np.uint64), ob["keys"])
     n = sc.ntri
     nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
-    # depth of the tree (> 32 LDS stack entries are needed)
-    depth, stack = 0, [(0, 0)]
-    while stack:
-        node, dd = stack.pop()
-        depth = max(depth, dd)
-        for c in (int(ob["left"][node]), int(ob["right"][node])):
-            if not c & LEAF:
-                stack.append((c, dd + 1))
-    assert depth > 40
     rng = synth.SplitMix64(99)
     nr = 4096
-    o = np.stack([rng.uniform(nr, -1e5, 1e5), rng.uniform(nr, -1e5, 1e5), np.full(nr, -3e7)], 1).astype(np.float32)
-    d = np.stack([rng.uniform(nr, -0.01, 0.01), rng.uniform(nr, -0.01, 0.01), np.ones(nr)], 1).astype(np.float32)
+    o = np.stack([rng.uniform(nr, -2e6, 2e6), rng.uniform(nr, -2e6, 2e6), np.full(nr, -3e7)], 1).astype(np.float32)
+    d = np.stack([rng.uniform(nr, -0.1, 0.1), rng.uniform(nr, -0.1, 0.05), np.ones(nr)], 1).astype(np.float32)
     hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
     ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
-    assert (ho >= 0).mean() > 0.9
+    assert (ho >= 0).mean() > 0.9 and np.unique(ho).size >= 8
     assert np.array_equal(hg.cpu().numpy(), ho)
     assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))
+
+
+@pytest.mark.parametrize("stack", [16, 24, 32])
+def test_deep_tree_frame_with_each_stack_depth(env, orc, ladder, stack):
+    """The frame pass's lens rays on the ladder tree with each LDS stack
+    depth: the frame counts its drops, and every ray's hit and distance equal
+    the oracle's (whose traversal recurses without a depth limit)."""
+    sc, osc, _, gs = ladder
+    cam = synth.Camera(pos=(0.0, 0.0, -3.0e7), right=(1.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), fwd=(0.0, 0.0, 1.0),
+                       width=64, height=48)
+    lens = synth.Lens(focal=0.1, fnum=1.4, focus=3.0e7)
+    params = synth.Params(m=4, mask_mode=synth.MASK_ALL)
+    gb = orc.gbuffer(osc, cam, lens)
+    o, d = run_pair(dict(env, osc=osc, gs=gs), orc, cam, lens, params, gb, knobs={"trace_stack": stack})
+    assert o["n_rays"] == 32 * 24 * 4 and int(d["stats"][1]) == o["n_rays"]
+    assert int(d["stats"][6]) > 0, "no stack drops: the test does not reach the parent walk"
+    assert np.unique(o["ray_hit"]).size >= 8
+    assert np.array_equal(d["ray_hit"], o["ray_hit"])
+    assert np.array_equal(d["ray_t"].view(np.uint32), o["ray_t"].view(np.uint32))
 
 
 def test_watertight_on_gpu(env, orc):
