@@ -735,6 +735,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
 #pragma unroll
         for (int step = 0; step < 2; ++step) {
             if (!(active && trav && nq <= 2)) continue;
+            const uint32_t nd_self = node;
             const BvhNode nd = Sl.nodes[node];
             ++visits;
             const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
@@ -749,48 +750,48 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             nq += (int)pl + (int)pr;
             hl = hl && !pl;
             hr = hr && !pr;
-            if (hl && hr) {
-                const uint32_t nearc = tl <= tr ? L : R, farc = tl <= tr ? R : L;
-                if (sp == kStack) {
-                    // stack full: the oldest entries go (the parent walk finds them again)
-                    for (int i = 0; i < kStack - kDropChunk; ++i) stk[i * kTB] = stk[(i + kDropChunk) * kTB];
-                    sp -= kDropChunk;
-                    dropped = true;
-                    ++drops;
-                }
-                stk[sp * kTB] = farc;
-                ++sp;
-                node = nearc;
-            } else if (hl) {
-                node = L;
-            } else if (hr) {
-                node = R;
-            } else if (sp > 0) {
-                --sp;
-                node = stk[sp * kTB];
-            } else if (dropped) {
-                // stack empty after a drop: walk up from this finished subtree
-                // to the nearest ancestor whose far child is still pending
+            const bool both = hl && hr;
+            const bool none = !hl && !hr;
+            if (both && sp == kStack) {
+                // stack full: the oldest entries go (the parent walk finds them again)
+                for (int i = 0; i < kStack - kDropChunk; ++i) stk[i * kTB] = stk[(i + kDropChunk) * kTB];
+                sp -= kDropChunk;
+                dropped = true;
+                ++drops;
+            }
+            // next node by selects (no divergent branches): the near child when both are
+            // hit (the far one pushed), else the one hit child, else the stack top
+            const bool nearl = tl <= tr;
+            if (both) stk[sp * kTB] = nearl ? R : L;
+            const bool pop = none && sp > 0;
+            uint32_t top = 0u;
+            if (pop) top = stk[(sp - 1) * kTB];
+            const uint32_t one = hl ? L : R;
+            node = both ? (nearl ? L : R) : (none ? top : one);
+            sp += both ? 1 : (pop ? -1 : 0);
+            if (none && !pop) {
                 trav = false;
-                uint32_t c = node;
-                for (uint32_t a = Sl.parent[c]; a != ~0u; c = a, a = Sl.parent[a]) {
-                    const BvhNode pn = Sl.nodes[a];
-                    ++visits;
-                    const float lim = h.t * 1.0009765625f;
-                    float ta, tb;
-                    const bool ha = box_hit(wr, pn.a.x, pn.a.y, pn.a.z, pn.a.w, pn.c.x, pn.c.y, lim, ta);
-                    const bool hb = box_hit(wr, pn.b.x, pn.b.y, pn.b.z, pn.b.w, pn.c.z, pn.c.w, lim, tb);
-                    const bool from_left = pn.d.x == c;
-                    const uint32_t other = from_left ? pn.d.y : pn.d.x;
-                    const bool came_near = from_left ? ta <= tb : !(ta <= tb);
-                    if (came_near && (other & kLeaf) == 0u && (from_left ? hb : ha)) {
-                        node = other;
-                        trav = true;
-                        break;
+                if (dropped) {
+                    // stack empty after a drop: walk up from this finished subtree
+                    // to the nearest ancestor whose far child is still pending
+                    uint32_t c = nd_self;
+                    for (uint32_t a = Sl.parent[c]; a != ~0u; c = a, a = Sl.parent[a]) {
+                        const BvhNode pn = Sl.nodes[a];
+                        ++visits;
+                        const float lim = h.t * 1.0009765625f;
+                        float ta, tb;
+                        const bool ha = box_hit(wr, pn.a.x, pn.a.y, pn.a.z, pn.a.w, pn.c.x, pn.c.y, lim, ta);
+                        const bool hb = box_hit(wr, pn.b.x, pn.b.y, pn.b.z, pn.b.w, pn.c.z, pn.c.w, lim, tb);
+                        const bool from_left = pn.d.x == c;
+                        const uint32_t other = from_left ? pn.d.y : pn.d.x;
+                        const bool came_near = from_left ? ta <= tb : !(ta <= tb);
+                        if (came_near && (other & kLeaf) == 0u && (from_left ? hb : ha)) {
+                            node = other;
+                            trav = true;
+                            break;
+                        }
                     }
                 }
-            } else {
-                trav = false;
             }
         }
         if (active && !trav && nq == 0) {
