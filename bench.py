@@ -166,6 +166,59 @@ def fixed_config(args):
     return {"trace_blocks": args.trace_blocks} if args.trace_blocks >= 0 else None
 
 
+def scene_for(scene, cams, lenses, params, log, label, fixed, frames=6, reps=2):
+    """The scene's BVH for a workload (setup, outside every timed region):
+    with leaf_split (long thin triangles as four clipped leaf references)
+    and without, each rendering the first `frames` frames of the path with
+    the library's default launch shapes; the faster is kept.  Splitting cuts
+    triangle tests where thin triangles fill little of their boxes, at the
+    price of more leaves (a larger tree); which wins depends on the scene.
+    fixed["leaf_split"] (from --config) skips the trial.  Returns
+    (dof.Scene with its BVH built, report)."""
+    import dataclasses
+    import torch
+
+    from paper_2210_06158_amd import dof
+    if fixed is not None and "leaf_split" in fixed:
+        gs = dof.Scene(dataclasses.replace(scene, leaf_split=int(fixed["leaf_split"])))
+        gs.build_bvh()
+        return gs, {"chosen": int(fixed["leaf_split"])}
+    W, H = cams[0].width, cams[0].height
+    hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
+    fr = frame_for(W, H, params, {})
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times, scenes, gbs = {}, {}, None
+    for ls in (1, 0):
+        gs = dof.Scene(dataclasses.replace(scene, leaf_split=ls))
+        gs.build_bvh()
+        if gbs is None:
+            gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams[:frames], lenses[:frames])]
+        ms = []
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            e0.record()
+            for k in range(frames):
+                prev = cams[k - 1] if k > 0 else None
+                fr.render(gs, cams[k], lenses[k], gbs[k], hist[(k + 1) % 2] if prev is not None else None,
+                          hist[k % 2], prev_cam=prev, prev_lens=lenses[k - 1] if k > 0 else None)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                ms.append(e0.elapsed_time(e1))
+        times[ls], scenes[ls] = min(ms), gs
+    best = min(times, key=times.get)
+    log(f"{label}: leaf_split {best} ({times})")
+    gs = scenes.pop(best)
+    scenes.clear()
+    return gs, {"chosen": best, "ms_per_sample": {str(k): round(v, 3) for k, v in times.items()},
+                "leaves": gs.bvh_view()["nleaf"], "sample_frames": frames}
+
+
+def launch_cfg(cfg):
+    """cfg without the scene-build choice."""
+    return None if cfg is None else {k: v for k, v in cfg.items() if k != "leaf_split"}
+
+
 def frame_for(W, H, params, cfg, **kw):
     """A dof.Frame of the pass with the launch shapes of cfg (tune.search's
     configuration; {} = library defaults), FP16 output."""
@@ -387,8 +440,7 @@ def main():
     nfr = len(cams)
     log(f"scene: {scene.ntri} triangles, {W}x{H}, m={params.m}")
 
-    gs = dof.Scene(scene)
-    gs.build_bvh()
+    gs, split = scene_for(scene, cams, [lens] * nfr, params, log, "1080p", fixed_config(args))
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -404,9 +456,10 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     gbuffer_ms = e0.elapsed_time(e1) / nfr
-    tb, grid = fixed_config(args), None
+    tb, grid = launch_cfg(fixed_config(args)), None
     if tb is None:
         tb, grid = autotune(gs, cams, [lens] * nfr, params, gbs, log, "1080p")
+        grid["leaf_split"] = split
     r = run_path(gs, cams, [lens] * nfr, params, gbs, args.steps, args.warmup, args.stage_frames, tb, log,
                  latency_passes=max(1, args.latency_passes))
     K, total_ms, frame_ms = r["K"], r["total_ms"], r["frame_ms"]
@@ -536,6 +589,7 @@ def main():
         "shots": shots,
         "launch_shapes": grid,
         "bvh_build_ms": round(bvh_ms, 3),
+        "bvh_leaves": gs.bvh_view()["nleaf"],
         "bvh_mtris_per_s": round(scene.ntri / (bvh_ms * 1e-3) / 1e6, 1),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_roofline": stage_roofline(r),
@@ -632,13 +686,13 @@ def uhd_leg(args, log):
     from paper_2210_06158_amd import dof, synth
 
     scene, cams, lenses, params = synth.scene_4k()
-    gs = dof.Scene(scene)
-    gs.build_bvh()
+    gs, split = scene_for(scene, cams, lenses, params, log, "4k", fixed_config(args))
     gbs = [gs.render_gbuffer(c, l, fmt=dof.RGBA16F) for c, l in zip(cams, lenses)]
     torch.cuda.synchronize()
-    tb, grid = fixed_config(args), None
+    tb, grid = launch_cfg(fixed_config(args)), None
     if tb is None:
         tb, grid = autotune(gs, cams, lenses, params, gbs, log, "4k")
+        grid["leaf_split"] = split
     r = run_path(gs, cams, lenses, params, gbs, args.uhd_steps, 5, min(args.uhd_steps, 30), tb, log)
     out = {
         "workload": "3840x2160, box city (130k boxes) behind a chain-link fence of 200k wire quads at depth 1-2, "

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define DOF_ABI_VERSION 3
+#define DOF_ABI_VERSION 4
 
 typedef int32_t dof_status;
 #define DOF_OK 0
@@ -202,24 +202,37 @@ typedef struct {
     const float *albedo;    /* host, 3 floats per triangle */
     float light_dir[3];     /* direction the light travels (unit) */
     float light_rad[3], ambient[3], sky[3];
+    int32_t leaf_split;     /* 1: a long thin triangle (its box's three face areas sum to more than 8
+                             * times its area) becomes 4 leaf references, the triangle clipped to
+                             * quarters of its box along the longest axis (early split clipping,
+                             * Ernst & Greiner 2007), so rays that enter the box beside the triangle
+                             * mostly skip its test; 0: one leaf per triangle.  Hits are the same. */
 } dof_scene_desc;
 
 typedef struct dof_scene dof_scene;
 
 /* Device views of the acceleration structure (for inspection and tests).
- * keys: sorted 64-bit keys, ties in id order: bits 0-62 are the Morton code
- * of the triangle box centre on cubic cells (one scale, 2^21 over the
- * largest extent of the centre bounds; 21 bits per axis, x at bit 3i+2,
- * y 3i+1, z 3i), bit 63 is set for a triangle whose box diagonal exceeds a
- * quarter of the centre bounds' diagonal; ids: triangle ids in that order;
- * nodes: ntri-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
- * float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z, R.lo.z,
- * R.hi.z), uint4 (left, right, first leaf, last leaf)}, child bit 31 = leaf
- * (sorted index), the node covering the sorted leaves first..last;
- * parent: 2 ntri - 1 entries (internal nodes, then leaves), root = ~0u;
- * tris: 3 float4 per leaf in sorted order (w of the first = id bits). */
+ * Its nleaf leaves are references: a triangle, or with leaf_split one of the
+ * four pieces of a split triangle; reference r of triangle i is
+ * ref_off[i] + j (pieces j = 0..3 in slab order), and its box is the
+ * triangle's box, or for a piece: on the split axis the slab, on the others
+ * the range of the piece's vertices and edge crossings (each crossing
+ * widened by 2^-20 (|edge extent| + |x|)), clipped to the triangle's box.
+ * keys: sorted 64-bit keys, ties in reference order: bits 0-62 are the
+ * Morton code of the reference box centre on cubic cells (one scale, 2^21
+ * over the largest extent of the centre bounds; 21 bits per axis, x at bit
+ * 3i+2, y 3i+1, z 3i), bit 63 is set for a box whose diagonal exceeds a
+ * quarter of the centre bounds' diagonal; ids: reference indices in that
+ * order; nodes: nleaf-1 records of 64 B {float4 (L.lo.x, L.hi.x, L.lo.y,
+ * L.hi.y), float4 (R.lo.x, R.hi.x, R.lo.y, R.hi.y), float4 (L.lo.z, L.hi.z,
+ * R.lo.z, R.hi.z), uint4 (left, right, first leaf, last leaf)}, child bit
+ * 31 = leaf (sorted index), the node covering the sorted leaves
+ * first..last; parent: 2 nleaf - 1 entries (internal nodes, then leaves),
+ * root = ~0u; tris: 3 float4 per leaf in sorted order, the vertices of the
+ * leaf's triangle (w of the first = triangle id bits). */
 typedef struct {
     int32_t ntri;
+    int32_t nleaf;
     const uint64_t *keys;
     const uint32_t *ids, *parent;
     const void *nodes, *tris;
@@ -237,12 +250,17 @@ int32_t dof_abi_version(void);
 const char *dof_last_error(void);
 void dof_default_params(dof_params *p);
 
-/* Scene arena size for ntri triangles: input and leaf-ordered triangles,
- * BVH nodes and parent links, and the build's keys, sort buffers and
- * counters (about 200 bytes per triangle). */
+/* Scene arena size bound for ntri triangles of any shape: input triangles,
+ * then per leaf reference (at most 4 per triangle) its box, the leaf-ordered
+ * triangle, BVH node and parent links, and the build's keys, sort buffers and
+ * counters (about 200 bytes per reference). */
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);
 
-/* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes) on
+/* The exact arena size for desc's triangles (counts the split triangles
+ * when desc->leaf_split); errors as dof_create_scene's argument checks. */
+dof_status dof_scene_bytes_desc(const dof_scene_desc *desc, size_t *bytes);
+
+/* Copies desc's host arrays into `arena` (device, >= dof_scene_bytes_desc) on
  * `stream` and returns a host handle; the arena must outlive the scene.
  * Synchronises `stream` once (the host arrays may be freed on return). */
 dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t arena_bytes,

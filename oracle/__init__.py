@@ -42,12 +42,13 @@ class OrcParams(C.Structure):
 
 class OrcScene(C.Structure):
     _fields_ = [("ntri", C.c_int32), ("verts", C.c_void_p), ("albedo", C.c_void_p),
-                ("light_dir", _f3), ("light_rad", _f3), ("ambient", _f3), ("sky", _f3)]
+                ("light_dir", _f3), ("light_rad", _f3), ("ambient", _f3), ("sky", _f3),
+                ("leaf_split", C.c_int32)]
 
 
 class OrcBvh(C.Structure):
-    _fields_ = [("ntri", C.c_int32), ("keys", C.c_void_p), ("ids", C.c_void_p), ("left", C.c_void_p),
-                ("right", C.c_void_p), ("parent", C.c_void_p), ("bounds", C.c_void_p),
+    _fields_ = [("nleaf", C.c_int32), ("keys", C.c_void_p), ("refs", C.c_void_p), ("ids", C.c_void_p),
+                ("left", C.c_void_p), ("right", C.c_void_p), ("parent", C.c_void_p), ("bounds", C.c_void_p),
                 ("leaf_bounds", C.c_void_p)]
 
 
@@ -77,6 +78,10 @@ def lib():
         L.orc_zone.argtypes = [C.POINTER(OrcLens), C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.orc_morton.argtypes = [C.POINTER(OrcScene), vp]
         L.orc_build_bvh.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcBvh)]
+        L.orc_leaf_refs.argtypes = [C.POINTER(OrcScene), vp]
+        L.orc_leaf_refs.restype = C.c_int64
+        L.orc_ref_boxes.argtypes = [C.POINTER(OrcScene), vp, vp, vp]
+        L.orc_morton_boxes.argtypes = [vp, C.c_int64, vp]
         L.orc_closest_hit.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcBvh), C.c_int64, vp, vp, vp, vp]
         L.orc_lens_sample.argtypes = [C.c_uint32] * 4 + [C.c_int32, C.c_float,
                                                          C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -133,22 +138,42 @@ def params_struct(p) -> OrcParams:
 class OracleScene:
     """Holds the scene arrays alive next to their C view."""
 
-    def __init__(self, scene):
+    def __init__(self, scene, leaf_split=None):
         self.verts = np.ascontiguousarray(scene.verts, dtype=np.float32)
         self.albedo = np.ascontiguousarray(scene.albedo, dtype=np.float32)
+        if leaf_split is None:
+            leaf_split = getattr(scene, "leaf_split", 1)
         self.s = OrcScene(self.verts.shape[0], _ptr(self.verts), _ptr(self.albedo),
                           _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient),
-                          _f3(*scene.sky))
+                          _f3(*scene.sky), 1 if leaf_split else 0)
         self.ntri = self.verts.shape[0]
         self.bvh = None
 
+    def leaf_refs(self):
+        """(ref_off[ntri+1], boxes[nleaf, 6], ref_tri[nleaf]) of the leaf references."""
+        off = np.zeros(self.ntri + 1, np.uint32)
+        n = lib().orc_leaf_refs(C.byref(self.s), _ptr(off))
+        if n <= 0:
+            raise RuntimeError(f"orc_leaf_refs failed: {n}")
+        boxes = np.zeros((n, 6), np.float32)
+        tri = np.zeros(n, np.uint32)
+        if lib().orc_ref_boxes(C.byref(self.s), _ptr(off), _ptr(boxes), _ptr(tri)) != 0:
+            raise RuntimeError("orc_ref_boxes failed")
+        return off, boxes, tri
+
     def build_bvh(self):
-        n = self.ntri
-        b = dict(keys=np.zeros(n, np.uint64), ids=np.zeros(n, np.uint32), left=np.zeros(max(n - 1, 1), np.uint32),
+        off = np.zeros(self.ntri + 1, np.uint32)
+        n = lib().orc_leaf_refs(C.byref(self.s), _ptr(off))
+        if n <= 0:
+            raise RuntimeError(f"orc_leaf_refs failed: {n}")
+        self.nleaf = n
+        b = dict(keys=np.zeros(n, np.uint64), refs=np.zeros(n, np.uint32), ids=np.zeros(n, np.uint32),
+                 left=np.zeros(max(n - 1, 1), np.uint32),
                  right=np.zeros(max(n - 1, 1), np.uint32), parent=np.zeros(2 * n - 1, np.uint32),
                  bounds=np.zeros((max(n - 1, 1), 6), np.float32),
                  leaf_bounds=np.zeros((n, 6), np.float32))
-        st = OrcBvh(n, *(_ptr(b[k]) for k in ("keys", "ids", "left", "right", "parent", "bounds", "leaf_bounds")))
+        st = OrcBvh(n, *(_ptr(b[k]) for k in ("keys", "refs", "ids", "left", "right", "parent", "bounds",
+                                                "leaf_bounds")))
         rc = lib().orc_build_bvh(C.byref(self.s), C.byref(st))
         if rc != 0:
             raise RuntimeError(f"orc_build_bvh failed: {rc}")
@@ -169,6 +194,14 @@ def morton(scene: OracleScene) -> np.ndarray:
     rc = lib().orc_morton(C.byref(scene.s), _ptr(out))
     if rc != 0:
         raise RuntimeError("orc_morton failed")
+    return out
+
+
+def morton_boxes(boxes: np.ndarray) -> np.ndarray:
+    boxes = np.ascontiguousarray(boxes, np.float32)
+    out = np.zeros(boxes.shape[0], np.uint64)
+    if lib().orc_morton_boxes(_ptr(boxes), C.c_int64(boxes.shape[0]), _ptr(out)) != 0:
+        raise RuntimeError("orc_morton_boxes failed")
     return out
 
 

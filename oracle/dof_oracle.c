@@ -192,17 +192,16 @@ static uint64_t spread21(uint32_t x)
     return r;
 }
 
-/* LBVH key of each triangle: a 63-bit Morton code (21 bits per axis, x at
- * bit 3i+2, y at 3i+1, z at 3i) of its box centre, quantised on cubic cells
- * (one scale 2^21 / largest extent of the centre bounds, for all axes), and
- * bit 63 set for a large triangle: one whose box diagonal exceeds a quarter
- * of the diagonal of the centre bounds (compared squared).  The flag puts
- * the few scene-sized triangles (ground planes) under one child of the root
- * instead of inflating every box on their path. */
-int orc_morton(const orc_scene *s, uint64_t *codes)
+/* LBVH key of a box: a 63-bit Morton code (21 bits per axis, x at bit 3i+2,
+ * y at 3i+1, z at 3i) of its centre, quantised on cubic cells (one scale
+ * 2^21 / largest extent of the centre bounds, for all axes), and bit 63 set
+ * for a large box: one whose diagonal exceeds a quarter of the diagonal of
+ * the centre bounds (compared squared).  The flag puts the few scene-sized
+ * triangles (ground planes) under one child of the root instead of inflating
+ * every box on their path. */
+int orc_morton_boxes(const float *boxes, int64_t n, uint64_t *codes)
 {
-    if (!s || s->ntri <= 0 || !codes) return -1;
-    int n = s->ntri;
+    if (!boxes || n <= 0 || !codes) return -1;
     float *cen = (float *)malloc(sizeof(float) * 3 * (size_t)n);
     float *diag2 = (float *)malloc(sizeof(float) * (size_t)n);
     if (!cen || !diag2) {
@@ -211,9 +210,8 @@ int orc_morton(const orc_scene *s, uint64_t *codes)
         return -2;
     }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = 0; i < n; i++) {
-        float bl[3], bh[3];
-        tri_box(s->verts + 9 * (size_t)i, bl, bh);
+    for (int64_t i = 0; i < n; i++) {
+        const float *bl = boxes + 6 * (size_t)i, *bh = bl + 3;
         for (int a = 0; a < 3; a++) {
             float c = (bl[a] + bh[a]) * 0.5f;
             cen[3 * (size_t)i + a] = c;
@@ -229,7 +227,7 @@ int orc_morton(const orc_scene *s, uint64_t *codes)
     e = ext[2] > e ? ext[2] : e;
     float inv = e > 0.0f ? 2097152.0f / e : 0.0f;
     float large = ((ext[0] * ext[0] + ext[1] * ext[1]) + ext[2] * ext[2]) * 0.0625f;
-    for (int i = 0; i < n; i++) {
+    for (int64_t i = 0; i < n; i++) {
         uint32_t qv[3];
         for (int a = 0; a < 3; a++) {
             float t = floorf((cen[3 * (size_t)i + a] - lo[a]) * inv);
@@ -241,6 +239,143 @@ int orc_morton(const orc_scene *s, uint64_t *codes)
     }
     free(cen);
     free(diag2);
+    return 0;
+}
+
+/* Keys of the triangles' own boxes (no leaf splitting). */
+int orc_morton(const orc_scene *s, uint64_t *codes)
+{
+    if (!s || s->ntri <= 0 || !codes) return -1;
+    float *boxes = (float *)malloc(sizeof(float) * 6 * (size_t)s->ntri);
+    if (!boxes) return -2;
+    for (int i = 0; i < s->ntri; i++) tri_box(s->verts + 9 * (size_t)i, boxes + 6 * (size_t)i, boxes + 6 * (size_t)i + 3);
+    int rc = orc_morton_boxes(boxes, s->ntri, codes);
+    free(boxes);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Leaf references: early split clipping (Ernst & Greiner, "Early Split     */
+/* Clipping for Bounding Volume Hierarchies", IEEE RT 2007).  A long thin    */
+/* slanted triangle (a grass blade, a fence wire) fills little of its box,   */
+/* so most rays that enter the box miss it.  Such a triangle becomes four    */
+/* leaf references, the triangle clipped to four equal slabs of its box      */
+/* along the box's longest axis; each reference's box bounds its piece.      */
+/* ------------------------------------------------------------------------ */
+
+/* Split iff the sum of the box's three face areas exceeds 8 times the
+ * triangle's area: (sum)^2 > 16 |e1 x e2|^2, in binary64 (deterministic;
+ * the library decides with the same formula). */
+static int ref_count(const float *v)
+{
+    float lo[3], hi[3];
+    tri_box(v, lo, hi);
+    double e[3], u[3], w[3];
+    for (int a = 0; a < 3; a++) {
+        e[a] = (double)hi[a] - (double)lo[a];
+        u[a] = (double)v[3 + a] - (double)v[a];
+        w[a] = (double)v[6 + a] - (double)v[a];
+    }
+    double faces = (e[0] * e[1] + e[1] * e[2]) + e[2] * e[0];
+    double cx = u[1] * w[2] - u[2] * w[1];
+    double cy = u[2] * w[0] - u[0] * w[2];
+    double cz = u[0] * w[1] - u[1] * w[0];
+    double c2 = (cx * cx + cy * cy) + cz * cz;
+    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? 4 : 1;
+}
+
+int64_t orc_leaf_refs(const orc_scene *s, uint32_t *ref_off)
+{
+    if (!s || s->ntri <= 0 || !ref_off) return -1;
+    uint64_t acc = 0;
+    for (int i = 0; i < s->ntri; i++) {
+        ref_off[i] = (uint32_t)acc;
+        acc += s->leaf_split ? (uint64_t)ref_count(s->verts + 9 * (size_t)i) : 1u;
+        if (acc > 0x7fffffffu) return -1;
+    }
+    ref_off[s->ntri] = (uint32_t)acc;
+    return (int64_t)acc;
+}
+
+/* Box of the piece of triangle v inside the slab s0 <= x_k <= s1: on axis k
+ * the slab; on each other axis the range of the vertices inside the slab and
+ * of the points where edges cross its planes.  A crossing point is computed
+ * in binary32 and widened by 2^-20 (|edge extent| + |x|), more than its
+ * rounding error, then the range is clipped to the triangle's box: every
+ * point of the piece lies in the box. */
+static void piece_box(const float *v, int k, float s0, float s1, const float lo[3], const float hi[3], float *out)
+{
+    out[k] = s0;
+    out[3 + k] = s1;
+    for (int m = 0; m < 3; m++) {
+        if (m == k) continue;
+        float pl = INFINITY, ph = -INFINITY;
+        for (int i = 0; i < 3; i++) {
+            float vk = v[3 * i + k];
+            if (vk >= s0 && vk <= s1) {
+                float x = v[3 * i + m];
+                pl = x < pl ? x : pl;
+                ph = x > ph ? x : ph;
+            }
+        }
+        for (int e = 0; e < 3; e++) {
+            const float *p = v + 3 * e, *q = v + 3 * ((e + 1) % 3);
+            for (int c = 0; c < 2; c++) {
+                float pc = c ? s1 : s0;
+                if ((p[k] < pc && pc < q[k]) || (q[k] < pc && pc < p[k])) {
+                    float t = (pc - p[k]) / (q[k] - p[k]);
+                    float d = q[m] - p[m];
+                    float x = p[m] + d * t;
+                    float g = (fabsf(d) + fabsf(x)) * 9.5367431640625e-07f;
+                    float xl = x - g, xh = x + g;
+                    pl = xl < pl ? xl : pl;
+                    ph = xh > ph ? xh : ph;
+                }
+            }
+        }
+        pl = lo[m] > pl ? lo[m] : pl;
+        ph = hi[m] < ph ? hi[m] : ph;
+        if (pl > ph) {
+            pl = lo[m];
+            ph = hi[m];
+        }
+        out[m] = pl;
+        out[3 + m] = ph;
+    }
+}
+
+int orc_ref_boxes(const orc_scene *s, const uint32_t *ref_off, float *boxes, uint32_t *ref_tri)
+{
+    if (!s || s->ntri <= 0 || !ref_off || !boxes || !ref_tri) return -1;
+    for (int i = 0; i < s->ntri; i++) {
+        const float *v = s->verts + 9 * (size_t)i;
+        const uint32_t r0 = ref_off[i], nr = ref_off[i + 1] - r0;
+        float lo[3], hi[3];
+        tri_box(v, lo, hi);
+        if (nr == 1) {
+            float *o = boxes + 6 * (size_t)r0;
+            for (int a = 0; a < 3; a++) { o[a] = lo[a]; o[3 + a] = hi[a]; }
+            ref_tri[r0] = (uint32_t)i;
+            continue;
+        }
+        if (nr != 4) return -1;
+        /* slabs along the longest box axis (first one on ties) */
+        float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        int k = 0;
+        if (ext[1] > ext[k]) k = 1;
+        if (ext[2] > ext[k]) k = 2;
+        float q = ext[k] * 0.25f, sl[5];
+        sl[0] = lo[k];
+        sl[4] = hi[k];
+        for (int j = 1; j < 4; j++) {
+            float x = lo[k] + q * (float)j;
+            sl[j] = x < hi[k] ? x : hi[k];
+        }
+        for (int j = 0; j < 4; j++) {
+            piece_box(v, k, sl[j], sl[j + 1], lo, hi, boxes + 6 * (size_t)(r0 + j));
+            ref_tri[r0 + j] = (uint32_t)i;
+        }
+    }
     return 0;
 }
 
@@ -264,12 +399,12 @@ static void box_union(const float *a, const float *b, float *o)
     }
 }
 
-/* Bit b (0 = most significant) of the 96-bit key (code << 32 | id) of leaf i:
- * the code occupies key bits 0..63, the id bits 64..95. */
+/* Bit b (0 = most significant) of the 96-bit key (code << 32 | reference) of
+ * leaf i: the code occupies key bits 0..63, the reference index bits 64..95. */
 static int key_bit(const orc_bvh *b, uint32_t i, int bit)
 {
     if (bit < 64) return (int)((b->keys[i] >> (63 - bit)) & 1u);
-    return (int)((b->ids[i] >> (95 - bit)) & 1u);
+    return (int)((b->refs[i] >> (95 - bit)) & 1u);
 }
 
 /* Top-down: the node covering sorted leaves [first, last] splits where the
@@ -285,7 +420,7 @@ static void build_rec(orc_bvh *b, uint32_t first, uint32_t last, uint32_t index)
     uint32_t l, r;
     if (split == first) {
         l = split | LEAF_BIT;
-        b->parent[(b->ntri - 1) + split] = index;
+        b->parent[(b->nleaf - 1) + split] = index;
     } else {
         l = split;
         b->parent[split] = index;
@@ -293,7 +428,7 @@ static void build_rec(orc_bvh *b, uint32_t first, uint32_t last, uint32_t index)
     }
     if (split + 1 == last) {
         r = (split + 1) | LEAF_BIT;
-        b->parent[(b->ntri - 1) + split + 1] = index;
+        b->parent[(b->nleaf - 1) + split + 1] = index;
     } else {
         r = split + 1;
         b->parent[split + 1] = index;
@@ -308,29 +443,41 @@ static void build_rec(orc_bvh *b, uint32_t first, uint32_t last, uint32_t index)
 
 int orc_build_bvh(const orc_scene *s, orc_bvh *b)
 {
-    if (!s || !b || s->ntri <= 0 || b->ntri != s->ntri) return -1;
-    int n = s->ntri;
-    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
-    keyed *kv = (keyed *)malloc(sizeof(keyed) * (size_t)n);
-    if (!codes || !kv || orc_morton(s, codes) != 0) { free(codes); free(kv); return -2; }
-    for (int i = 0; i < n; i++) { kv[i].code = codes[i]; kv[i].id = (uint32_t)i; }
-    free(codes);
+    if (!s || !b || s->ntri <= 0) return -1;
+    int status = 0;
+    uint32_t *ref_off = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)s->ntri + 1));
+    float *boxes = NULL;
+    uint32_t *ref_tri = NULL;
+    uint64_t *codes = NULL;
+    keyed *kv = NULL;
+    if (!ref_off) return -2;
+    const int64_t n = orc_leaf_refs(s, ref_off);
+    if (n <= 0 || n != b->nleaf) { status = -1; goto done; }
+    boxes = (float *)malloc(sizeof(float) * 6 * (size_t)n);
+    ref_tri = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    kv = (keyed *)malloc(sizeof(keyed) * (size_t)n);
+    if (!boxes || !ref_tri || !codes || !kv) { status = -2; goto done; }
+    if (orc_ref_boxes(s, ref_off, boxes, ref_tri) != 0) { status = -1; goto done; }
+    if (orc_morton_boxes(boxes, n, codes) != 0) { status = -2; goto done; }
+    for (int64_t i = 0; i < n; i++) { kv[i].code = codes[i]; kv[i].id = (uint32_t)i; }
     qsort(kv, (size_t)n, sizeof(keyed), cmp_keyed);
-    for (int i = 0; i < n; i++) { b->keys[i] = kv[i].code; b->ids[i] = kv[i].id; }
-    free(kv);
-    for (int i = 0; i < n; i++) {
-        uint32_t id = b->ids[i];
-        float lo[3], hi[3];
-        tri_box(s->verts + 9 * (size_t)id, lo, hi);
-        for (int a = 0; a < 3; a++) {
-            b->leaf_bounds[6 * (size_t)i + a] = lo[a];
-            b->leaf_bounds[6 * (size_t)i + 3 + a] = hi[a];
-        }
+    for (int64_t i = 0; i < n; i++) {
+        const uint32_t r = kv[i].id;
+        b->keys[i] = kv[i].code;
+        b->refs[i] = r;
+        b->ids[i] = ref_tri[r];
+        memcpy(b->leaf_bounds + 6 * (size_t)i, boxes + 6 * (size_t)r, sizeof(float) * 6);
     }
     b->parent[0] = ~0u;
-    if (n == 1) return 0;
-    build_rec(b, 0, (uint32_t)n - 1, 0);
-    return 0;
+    if (n > 1) build_rec(b, 0, (uint32_t)n - 1, 0);
+done:
+    free(ref_off);
+    free(boxes);
+    free(ref_tri);
+    free(codes);
+    free(kv);
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -62,17 +62,21 @@ typedef struct {
     const float *verts;                     /* 9 per triangle */
     const float *albedo;                    /* 3 per triangle */
     float light_dir[3], light_rad[3], ambient[3], sky[3];
+    int32_t leaf_split;                     /* 1: long thin triangles become 4 clipped leaf references */
 } orc_scene;
 
-/* Binary radix tree over 96-bit keys (the 64-bit key of orc_morton -- a
- * large-triangle flag over a 63-bit Morton code -- then the triangle id),
- * Karras numbering.  All arrays are caller-allocated. */
+/* Binary radix tree over the leaf references (a triangle, or with
+ * leaf_split one of its clipped pieces): 96-bit keys (the 64-bit key of the
+ * reference's box -- a large-box flag over a 63-bit Morton code -- then the
+ * reference index), Karras numbering.  All arrays are caller-allocated;
+ * nleaf comes from orc_leaf_refs. */
 typedef struct {
-    int32_t ntri;
-    uint64_t *keys;         /* ntri 64-bit keys, ascending with ids */
-    uint32_t *ids;          /* ntri triangle ids in leaf order */
-    uint32_t *left, *right; /* ntri-1 each; bit 31 set = leaf (sorted index) */
-    uint32_t *parent;       /* 2*ntri-1: internal nodes then leaves; root = ~0u */
+    int32_t nleaf;
+    uint64_t *keys;         /* nleaf 64-bit keys, ascending with refs */
+    uint32_t *refs;         /* nleaf reference indices in leaf order */
+    uint32_t *ids;          /* nleaf triangle ids in leaf order */
+    uint32_t *left, *right; /* nleaf-1 each; bit 31 set = leaf (sorted index) */
+    uint32_t *parent;       /* 2*nleaf-1: internal nodes then leaves; root = ~0u */
     float *bounds;          /* 6 per internal node: lo xyz, hi xyz */
     float *leaf_bounds;     /* 6 per leaf, sorted order */
 } orc_bvh;
@@ -108,6 +112,17 @@ float orc_coc(const orc_lens *lens, int32_t width, float z);
 int orc_zone(const orc_lens *lens, int32_t width, float *z_near, float *z_far);
 
 int orc_morton(const orc_scene *s, uint64_t *codes);
+
+/* Leaf references (early split clipping, Ernst & Greiner 2007): ref_off gets
+ * ntri+1 offsets (triangle i owns references ref_off[i] .. ref_off[i+1]-1);
+ * returns their number, or < 0 on bad arguments. */
+int64_t orc_leaf_refs(const orc_scene *s, uint32_t *ref_off);
+
+/* The references' boxes (6 floats: lo xyz, hi xyz) and triangles. */
+int orc_ref_boxes(const orc_scene *s, const uint32_t *ref_off, float *boxes, uint32_t *ref_tri);
+
+/* orc_morton's keys for n boxes given as lo xyz, hi xyz. */
+int orc_morton_boxes(const float *boxes, int64_t n, uint64_t *codes);
 int orc_build_bvh(const orc_scene *s, orc_bvh *b);
 
 /* Closest hit per ray; bvh == NULL means brute force over all triangles. */

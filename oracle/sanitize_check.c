@@ -81,11 +81,18 @@ static orc_scene make_scene(void)
     box(3, 0, 10, 4, 1, 11, 0.9f, 0.9f, 0.1f);
     box(-0.4f, 0, 1.8f, -0.38f, 3, 1.82f, 0.3f, 0.3f, 0.3f);
     box(0.5f, 0, 2.2f, 0.52f, 3, 2.22f, 0.6f, 0.4f, 0.2f);
+    /* leaning grass blades: long thin triangles that the BVH splits into clipped pieces */
+    for (int i = 0; i < 6; i++) {
+        const float x = -1.5f + 0.5f * (float)i, z = 3.0f + 0.3f * (float)i;
+        const float a[3] = {x, 0, z}, b[3] = {x + 0.02f, 0, z}, c[3] = {x + 0.3f, 1.2f, z + 0.2f};
+        tri(a, b, c, 0.2f, 0.6f, 0.1f);
+    }
     orc_scene s;
     memset(&s, 0, sizeof(s));
     s.ntri = g_ntri;
     s.verts = g_verts;
     s.albedo = g_albedo;
+    s.leaf_split = 1;
     const float L[3] = {-0.4f, -1.0f, 0.6f};
     const float n = sqrtf(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
     for (int a = 0; a < 3; a++) {
@@ -102,20 +109,21 @@ static orc_scene make_scene(void)
 static int alloc_bvh(orc_bvh *b, int n)
 {
     memset(b, 0, sizeof(*b));
-    b->ntri = n;
+    b->nleaf = n;
     b->keys = malloc(sizeof(uint64_t) * n);
+    b->refs = malloc(sizeof(uint32_t) * n);
     b->ids = malloc(sizeof(uint32_t) * n);
     b->left = malloc(sizeof(uint32_t) * (n - 1));
     b->right = malloc(sizeof(uint32_t) * (n - 1));
     b->parent = malloc(sizeof(uint32_t) * (2 * n - 1));
     b->bounds = malloc(sizeof(float) * 6 * (n - 1));
     b->leaf_bounds = malloc(sizeof(float) * 6 * n);
-    return b->keys && b->ids && b->left && b->right && b->parent && b->bounds && b->leaf_bounds;
+    return b->keys && b->refs && b->ids && b->left && b->right && b->parent && b->bounds && b->leaf_bounds;
 }
 
 static void free_bvh(orc_bvh *b)
 {
-    free(b->keys); free(b->ids); free(b->left); free(b->right);
+    free(b->keys); free(b->refs); free(b->ids); free(b->left); free(b->right);
     free(b->parent); free(b->bounds); free(b->leaf_bounds);
 }
 
@@ -237,9 +245,27 @@ int main(void)
     orc_set_threads(2);
     const orc_scene s = make_scene();
     const int n = s.ntri;
+    uint32_t ref_off[257];
+    const int64_t nleaf = orc_leaf_refs(&s, ref_off);
+    CHECK(nleaf > n);
     orc_bvh b;
-    CHECK(alloc_bvh(&b, n));
+    CHECK(alloc_bvh(&b, (int)nleaf));
     CHECK(orc_build_bvh(&s, &b) == 0);
+    {
+        float *boxes = malloc(sizeof(float) * 6 * (size_t)nleaf);
+        uint32_t *rt = malloc(sizeof(uint32_t) * (size_t)nleaf);
+        uint64_t *kc = malloc(sizeof(uint64_t) * (size_t)nleaf);
+        CHECK(boxes && rt && kc);
+        CHECK(orc_ref_boxes(&s, ref_off, boxes, rt) == 0);
+        CHECK(orc_morton_boxes(boxes, nleaf, kc) == 0);
+        EACH_ALLOCATION_FAILS(orc_morton_boxes(boxes, nleaf, kc));
+        CHECK(orc_ref_boxes(&s, NULL, boxes, rt) == -1);
+        CHECK(orc_morton_boxes(NULL, nleaf, kc) == -1);
+        free(boxes);
+        free(rt);
+        free(kc);
+    }
+    CHECK(orc_leaf_refs(NULL, ref_off) == -1);
 
     /* closest hits: brute force and BVH agree */
     enum { NR = 512 };

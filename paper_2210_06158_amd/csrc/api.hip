@@ -64,12 +64,13 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct SceneLayout {
-    size_t verts_in, albedo_in, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp, flags, hist, bounds;
-    size_t aux, total;
+    size_t verts_in, albedo_in, ref_off, ref_box, ref_tri, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp;
+    size_t flags, hist, bounds, aux, total;
     int sort_blocks, bound_blocks;
 };
 
-SceneLayout scene_layout(int64_t n)
+// nt triangles, n leaf references
+SceneLayout scene_layout(int64_t nt, int64_t n)
 {
     SceneLayout L{};
     size_t off = 0;
@@ -81,8 +82,11 @@ SceneLayout scene_layout(int64_t n)
     const int64_t ni = n > 1 ? n - 1 : 1;
     L.sort_blocks = (int)((n + 4095) / 4096);
     L.bound_blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    L.verts_in = take(sizeof(float) * 9 * n);
-    L.albedo_in = take(sizeof(float) * 3 * n);
+    L.verts_in = take(sizeof(float) * 9 * nt);
+    L.albedo_in = take(sizeof(float) * 3 * nt);
+    L.ref_off = take(sizeof(uint32_t) * (nt + 1));
+    L.ref_box = take(sizeof(float) * 6 * n);
+    L.ref_tri = take(sizeof(uint32_t) * n);
     L.tris = take(sizeof(float4) * 3 * n);
     L.albedo = take(sizeof(float4) * n);
     L.nodes = take(sizeof(dof::BvhNode) * ni);
@@ -97,6 +101,56 @@ SceneLayout scene_layout(int64_t n)
     L.aux = take(64);
     L.total = off;
     return L;
+}
+
+// Leaf references (early split clipping, Ernst & Greiner 2007): with
+// desc->leaf_split a triangle whose box's three face areas sum to more than 8
+// times its area -- a long thin slanted triangle, which most rays entering its
+// box miss -- becomes 4 references, its pieces in quarters of the box along
+// the longest axis (clipped on the device when the BVH is built).  Decided
+// here in binary64, so the size query and the upload agree.
+constexpr int kMaxRefsPerTri = 4;
+
+uint32_t refs_of(const float *v)
+{
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        float x = v[a], y = v[3 + a], z = v[6 + a];
+        float m = x;
+        m = y < m ? y : m;
+        m = z < m ? z : m;
+        lo[a] = m;
+        float M = x;
+        M = y > M ? y : M;
+        M = z > M ? z : M;
+        hi[a] = M;
+    }
+    double e[3], u[3], w[3];
+    for (int a = 0; a < 3; ++a) {
+        e[a] = (double)hi[a] - (double)lo[a];
+        u[a] = (double)v[3 + a] - (double)v[a];
+        w[a] = (double)v[6 + a] - (double)v[a];
+    }
+    const double faces = (e[0] * e[1] + e[1] * e[2]) + e[2] * e[0];
+    const double cx = u[1] * w[2] - u[2] * w[1];
+    const double cy = u[2] * w[0] - u[0] * w[2];
+    const double cz = u[0] * w[1] - u[1] * w[0];
+    const double c2 = (cx * cx + cy * cy) + cz * cz;
+    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? (uint32_t)kMaxRefsPerTri : 1u;
+}
+
+// Reference offsets of the triangles (off may be NULL: count only); -1 when
+// the references would not fit 31-bit leaf indices.
+int64_t leaf_refs(const dof_scene_desc *desc, uint32_t *off)
+{
+    uint64_t acc = 0;
+    for (int32_t i = 0; i < desc->ntri; ++i) {
+        if (off) off[i] = (uint32_t)acc;
+        acc += desc->leaf_split ? refs_of(desc->verts + 9 * (size_t)i) : 1u;
+        if (acc > (uint64_t)INT32_MAX) return -1;
+    }
+    if (off) off[desc->ntri] = (uint32_t)acc;
+    return (int64_t)acc;
 }
 
 dof::ScratchLayout frame_layout(int W, int H, int m, int taa, int ray_records)
@@ -524,17 +578,45 @@ void dof_default_params(dof_params *p)
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes)
 {
     if (ntri <= 0 || !bytes) return fail(DOF_E_INVALID, "ntri must be > 0 and bytes non-NULL");
-    *bytes = scene_layout(ntri).total;
+    *bytes = scene_layout(ntri, (int64_t)kMaxRefsPerTri * ntri).total;
+    return DOF_OK;
+}
+
+static dof_status check_desc(const dof_scene_desc *desc)
+{
+    if (!desc || !desc->verts || !desc->albedo || desc->ntri <= 0)
+        return fail(DOF_E_INVALID, "scene description: NULL argument or ntri <= 0");
+    if (desc->leaf_split != 0 && desc->leaf_split != 1) return fail(DOF_E_INVALID, "leaf_split must be 0 or 1");
+    return DOF_OK;
+}
+
+dof_status dof_scene_bytes_desc(const dof_scene_desc *desc, size_t *bytes)
+{
+    if (!bytes) return fail(DOF_E_INVALID, "bytes is NULL");
+    const dof_status st = check_desc(desc);
+    if (st != DOF_OK) return st;
+    const int64_t n = leaf_refs(desc, nullptr);
+    if (n < 0) return fail(DOF_E_UNSUPPORTED, "more than 2^31 - 1 leaf references");
+    *bytes = scene_layout(desc->ntri, n).total;
     return DOF_OK;
 }
 
 dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t arena_bytes, void *stream,
                             dof_scene **out)
 {
-    if (!desc || !out || !arena || !desc->verts || !desc->albedo || desc->ntri <= 0)
-        return fail(DOF_E_INVALID, "dof_create_scene: NULL argument or ntri <= 0");
+    if (!out || !arena) return fail(DOF_E_INVALID, "dof_create_scene: NULL argument");
+    const dof_status st0 = check_desc(desc);
+    if (st0 != DOF_OK) return st0;
     *out = nullptr;
-    const SceneLayout L = scene_layout(desc->ntri);
+    std::vector<uint32_t> ref_off;
+    try {
+        ref_off.resize((size_t)desc->ntri + 1);
+    } catch (...) {
+        return fail(DOF_E_NOMEM, "host allocation failed");
+    }
+    const int64_t nleaf = leaf_refs(desc, ref_off.data());
+    if (nleaf < 0) return fail(DOF_E_UNSUPPORTED, "more than 2^31 - 1 leaf references");
+    const SceneLayout L = scene_layout(desc->ntri, nleaf);
     if (arena_bytes < L.total) return fail(DOF_E_NOMEM, "scene arena needs %zu bytes, got %zu", L.total, arena_bytes);
     dof_scene *s = new (std::nothrow) dof_scene;
     if (!s) return fail(DOF_E_NOMEM, "host allocation failed");
@@ -544,8 +626,12 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
     s->arena_bytes = arena_bytes;
     dof::SceneDev &d = s->dev;
     d.ntri = desc->ntri;
+    d.nleaf = (int32_t)nleaf;
     d.verts_in = reinterpret_cast<float *>(a + L.verts_in);
     d.albedo_in = reinterpret_cast<float *>(a + L.albedo_in);
+    d.ref_off = reinterpret_cast<uint32_t *>(a + L.ref_off);
+    d.ref_box = reinterpret_cast<float *>(a + L.ref_box);
+    d.ref_tri = reinterpret_cast<uint32_t *>(a + L.ref_tri);
     d.tris = reinterpret_cast<float4 *>(a + L.tris);
     d.albedo = reinterpret_cast<float4 *>(a + L.albedo);
     d.nodes = reinterpret_cast<dof::BvhNode *>(a + L.nodes);
@@ -570,6 +656,9 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
     if (e == hipSuccess)
         e = hipMemcpyAsync(a + L.albedo_in, desc->albedo, sizeof(float) * 3 * (size_t)desc->ntri,
                            hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a + L.ref_off, ref_off.data(), sizeof(uint32_t) * ref_off.size(), hipMemcpyHostToDevice,
+                           st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         delete s;
@@ -605,6 +694,7 @@ dof_status dof_bvh_view_get(const dof_scene *scene, dof_bvh_view *out)
     if (!scene || !out) return fail(DOF_E_INVALID, "NULL argument");
     if (!scene->built) return fail(DOF_E_STATE, "BVH not built");
     out->ntri = scene->dev.ntri;
+    out->nleaf = scene->dev.nleaf;
     out->keys = scene->dev.keys;
     out->ids = scene->dev.ids;
     out->parent = scene->dev.parent;
@@ -808,7 +898,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         J.hist_out = it.history.out;
         J.mask = it.out.mask;
         J.out = it.out;
-        J.scene = dof::SceneArgs{it.scene->dev.ntri, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes,
+        J.scene = dof::SceneArgs{it.scene->dev.nleaf, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes,
                                  it.scene->dev.parent};
         J.grings = gather_rings(it.lens, *p);
         const dof::FrameConst &fc = J.fc;

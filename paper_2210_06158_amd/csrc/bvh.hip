@@ -1,11 +1,14 @@
 // LBVH build on the device: the acceleration structure that replaces the
 // DXR build the paper times inside its Ray Trace pass (section 5.2).
 //
-//   centroid bounds -> 64-bit keys (a large-triangle flag in bit 63 over a
+//   leaf references (a triangle, or four clipped pieces of a long thin one:
+//   early split clipping, Ernst & Greiner 2007) with their boxes ->
+//   centroid bounds -> 64-bit keys (a large-box flag in bit 63 over a
 //   63-bit Morton code, 21 bits per axis, of cubic cells) -> stable LSD
-//   radix sort of (key, id) -> binary radix tree over the 96-bit keys
-//   key << 32 | id (Karras 2012) -> triangles reordered to leaf order ->
-//   bottom-up refit of the child boxes stored in each node.
+//   radix sort of (key, reference) -> binary radix tree over the 96-bit keys
+//   key << 32 | reference (Karras 2012) -> the references' triangles
+//   written in leaf order -> bottom-up refit of the child boxes stored in
+//   each node.
 //
 // All results are bit-reproducible: min/max are compare-selects and the
 // sort is stable, so the tree depends only on the input triangles.
@@ -46,17 +49,106 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
-// Per-block min/max of triangle-box centroids (grid-stride).
-__global__ __launch_bounds__(kThreads) void k_centroid_bounds(const float *__restrict__ verts, int n,
+// Box of the piece of triangle v inside the slab s0 <= x_k <= s1: on axis k
+// the slab; on each other axis the range of the vertices inside the slab and
+// of the points where edges cross its planes.  A crossing point is computed
+// in binary32 and widened by 2^-20 (|edge extent| + |x|), more than its
+// rounding error; the range is then clipped to the triangle's box.  So the
+// box holds every point of the piece, and the pieces' boxes together hold
+// the triangle: a ray that meets the triangle enters one of them.
+__device__ inline void piece_box(const float *v, int k, float s0, float s1, const float lo[3], const float hi[3],
+                                 float *out)
+{
+    out[k] = s0;
+    out[3 + k] = s1;
+    for (int m = 0; m < 3; ++m) {
+        if (m == k) continue;
+        float pl = INFINITY, ph = -INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            const float vk = v[3 * i + k];
+            if (vk >= s0 && vk <= s1) {
+                const float x = v[3 * i + m];
+                pl = x < pl ? x : pl;
+                ph = x > ph ? x : ph;
+            }
+        }
+        for (int e = 0; e < 3; ++e) {
+            const float *p = v + 3 * e, *q = v + 3 * (e == 2 ? 0 : e + 1);
+            for (int c = 0; c < 2; ++c) {
+                const float pc = c ? s1 : s0;
+                if ((p[k] < pc && pc < q[k]) || (q[k] < pc && pc < p[k])) {
+                    const float t = (pc - p[k]) / (q[k] - p[k]);
+                    const float d = q[m] - p[m];
+                    const float x = p[m] + d * t;
+                    const float g = (fabsf(d) + fabsf(x)) * 9.5367431640625e-07f;   // 2^-20
+                    const float xl = x - g, xh = x + g;
+                    pl = xl < pl ? xl : pl;
+                    ph = xh > ph ? xh : ph;
+                }
+            }
+        }
+        pl = lo[m] > pl ? lo[m] : pl;
+        ph = hi[m] < ph ? hi[m] : ph;
+        if (pl > ph) {
+            pl = lo[m];
+            ph = hi[m];
+        }
+        out[m] = pl;
+        out[3 + m] = ph;
+    }
+}
+
+// One thread per triangle: its references' boxes and triangle index.  A
+// triangle with one reference keeps its own box; one with four is cut into
+// quarters of its box along the longest axis (the first one on ties).
+__global__ __launch_bounds__(kThreads) void k_ref_emit(const float *__restrict__ verts, int nt,
+                                                       const uint32_t *__restrict__ ref_off, float *__restrict__ boxes,
+                                                       uint32_t *__restrict__ ref_tri)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= nt) return;
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = verts[9 * (size_t)i + k];
+    float lo[3], hi[3];
+    tri_box3(v, lo, hi);
+    const uint32_t r0 = ref_off[i], nr = ref_off[i + 1] - r0;
+    if (nr == 1) {
+        float *o = boxes + 6 * (size_t)r0;
+        o[0] = lo[0]; o[1] = lo[1]; o[2] = lo[2];
+        o[3] = hi[0]; o[4] = hi[1]; o[5] = hi[2];
+        ref_tri[r0] = (uint32_t)i;
+        return;
+    }
+    const float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+    int k = 0;
+    if (ext[1] > ext[k]) k = 1;
+    if (ext[2] > ext[k]) k = 2;
+    const float q = ext[k] * 0.25f;
+    float sl[5];
+    sl[0] = lo[k];
+    sl[4] = hi[k];
+    for (int j = 1; j < 4; ++j) {
+        const float x = lo[k] + q * (float)j;
+        sl[j] = x < hi[k] ? x : hi[k];
+    }
+    for (int j = 0; j < 4; ++j) {
+        float o[6];
+        piece_box(v, k, sl[j], sl[j + 1], lo, hi, o);
+        float *dst = boxes + 6 * (size_t)(r0 + j);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) dst[a] = o[a];
+        ref_tri[r0 + j] = (uint32_t)i;
+    }
+}
+
+// Per-block min/max of reference-box centroids (grid-stride).
+__global__ __launch_bounds__(kThreads) void k_centroid_bounds(const float *__restrict__ boxes, int n,
                                                               float *__restrict__ partial)
 {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
-        float v[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = verts[9 * (size_t)i + k];
-        float bl[3], bh[3];
-        tri_box3(v, bl, bh);
+        const float *bl = boxes + 6 * (size_t)i, *bh = bl + 3;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             float c = (bl[a] + bh[a]) * 0.5f;
@@ -130,17 +222,18 @@ __device__ inline uint64_t spread_bits21(uint32_t v)
     return x;
 }
 
-__global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ verts, int n,
+__global__ __launch_bounds__(kThreads) void k_morton(const float *__restrict__ boxes, int n,
                                                      const float *__restrict__ fin, uint64_t *__restrict__ keys,
                                                      uint32_t *__restrict__ ids)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    float v[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) v[k] = verts[9 * (size_t)i + k];
     float bl[3], bh[3];
-    tri_box3(v, bl, bh);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = boxes[6 * (size_t)i + a];
+        bh[a] = boxes[6 * (size_t)i + 3 + a];
+    }
     uint32_t q[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -269,12 +362,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t *__re
 // ---------------------------------------------------------------- hierarchy
 
 __global__ __launch_bounds__(kThreads) void k_reorder(const float *__restrict__ verts, const float *__restrict__ alb,
-                                                      const uint32_t *__restrict__ ids, int n,
+                                                      const uint32_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ ref_tri, int n,
                                                       float4 *__restrict__ tris, float4 *__restrict__ albedo)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    uint32_t id = ids[i];
+    uint32_t id = ref_tri[ids[i]];
     const float *v = verts + 9 * (size_t)id;
     tris[3 * (size_t)i + 0] = make_float4(v[0], v[1], v[2], __uint_as_float(id));
     tris[3 * (size_t)i + 1] = make_float4(v[3], v[4], v[5], 0.0f);
@@ -283,8 +377,8 @@ __global__ __launch_bounds__(kThreads) void k_reorder(const float *__restrict__ 
     albedo[i] = make_float4(a[0], a[1], a[2], 0.0f);
 }
 
-// Length of the common prefix of the 96-bit keys (code << 32 | id) of leaves
-// i and j; -1 outside the array.
+// Length of the common prefix of the 96-bit keys (code << 32 | reference) of
+// leaves i and j; -1 outside the array.
 __device__ inline int delta96(const uint64_t *keys, const uint32_t *ids, int n, int i, int j)
 {
     if (j < 0 || j >= n) return -1;
@@ -369,7 +463,8 @@ __device__ inline void union_lr(const float4 a, const float4 b, const float4 c, 
     hi[2] = c.w > c.y ? c.w : c.y;
 }
 
-__global__ __launch_bounds__(kRefitThreads) void k_refit_local(const float4 *__restrict__ tris, int n, BvhNode *nodes,
+__global__ __launch_bounds__(kRefitThreads) void k_refit_local(const float *__restrict__ ref_box,
+                                                               const uint32_t *__restrict__ ids, int n, BvhNode *nodes,
                                                                const uint32_t *__restrict__ parent, uint32_t *flags,
                                                                uint4 *exits, uint32_t exits_cap, uint32_t *exit_count)
 {
@@ -381,13 +476,9 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_local(const float4 *__r
     __syncthreads();
     const int i = (int)b0 + tid;
     if (i >= n) return;
-    float v[9];
-    float4 t0 = tris[3 * (size_t)i], t1 = tris[3 * (size_t)i + 1], t2 = tris[3 * (size_t)i + 2];
-    v[0] = t0.x; v[1] = t0.y; v[2] = t0.z;
-    v[3] = t1.x; v[4] = t1.y; v[5] = t1.z;
-    v[6] = t2.x; v[7] = t2.y; v[8] = t2.z;
-    float lo[3], hi[3];
-    tri_box3(v, lo, hi);
+    // the leaf's box: its reference's
+    const float *rb = ref_box + 6 * (size_t)ids[i];
+    float lo[3] = {rb[0], rb[1], rb[2]}, hi[3] = {rb[3], rb[4], rb[5]};
     uint32_t child = (uint32_t)i | kLeaf;
     uint32_t p = parent[(size_t)(n - 1) + i];
     while (p != ~0u) {
@@ -456,12 +547,13 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
 {
-    const int n = s.ntri;
+    const int nt = s.ntri, n = s.nleaf;
     const int nb = s.bound_blocks;
-    k_centroid_bounds<<<nb, kThreads, 0, st>>>(s.verts_in, n, s.bounds);
+    k_ref_emit<<<ceil_div(nt, kThreads), kThreads, 0, st>>>(s.verts_in, nt, s.ref_off, s.ref_box, s.ref_tri);
+    k_centroid_bounds<<<nb, kThreads, 0, st>>>(s.ref_box, n, s.bounds);
     k_bounds_final<<<1, 256, 0, st>>>(s.bounds, nb);
     const float *fin = s.bounds + 6 * (size_t)nb;
-    k_morton<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, n, fin, s.keys, s.ids);
+    k_morton<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.ref_box, n, fin, s.keys, s.ids);
     const int sb = s.sort_blocks;
     uint32_t *doff = s.hist + 256 * (size_t)sb;
     uint64_t *ka = s.keys, *kb = s.keys_tmp;
@@ -474,7 +566,8 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
         uint64_t *t = ka; ka = kb; kb = t;
         uint32_t *u = va; va = vb; vb = u;
     }
-    k_reorder<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, s.albedo_in, s.ids, n, s.tris, s.albedo);
+    k_reorder<<<ceil_div(n, kThreads), kThreads, 0, st>>>(s.verts_in, s.albedo_in, s.ids, s.ref_tri, n, s.tris,
+                                                          s.albedo);
     if (n >= 2) {
         // the refit's list of block exits lives in the sort's spare key buffer (free after the sort)
         uint4 *exits = reinterpret_cast<uint4 *>(s.keys_tmp);
@@ -482,8 +575,8 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
         uint32_t *exit_count = s.aux + 8;
         k_karras<<<ceil_div(n - 1, kThreads), kThreads, 0, st>>>(s.keys, s.ids, n, s.nodes, s.parent, s.flags,
                                                                    exit_count);
-        k_refit_local<<<ceil_div(n, kRefitThreads), kRefitThreads, 0, st>>>(s.tris, n, s.nodes, s.parent, s.flags,
-                                                                              exits, cap, exit_count);
+        k_refit_local<<<ceil_div(n, kRefitThreads), kRefitThreads, 0, st>>>(s.ref_box, s.ids, n, s.nodes, s.parent,
+                                                                              s.flags, exits, cap, exit_count);
         k_refit_top<<<1, kRefitThreads, 0, st>>>(s.nodes, s.parent, s.flags, exits, cap, exit_count);
     }
     return hipGetLastError();

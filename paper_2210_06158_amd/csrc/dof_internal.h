@@ -36,17 +36,23 @@ struct SceneShade {
     float light_dir[3], light_rad[3], ambient[3], sky[3];
 };
 
+// The tree's leaves are references: a triangle, or (early split clipping)
+// one of four pieces of a long thin triangle clipped to quarters of its box.
 struct SceneDev {
     int32_t ntri;
+    int32_t nleaf;           // references
     const float *verts_in;   // 9 per triangle, original order
     const float *albedo_in;  // 3 per triangle, original order
-    float4 *tris;            // 3 per leaf, sorted order; tris[3i].w = id bits
+    const uint32_t *ref_off; // ntri + 1: triangle i owns references ref_off[i] .. ref_off[i+1]-1
+    float *ref_box;          // 6 per reference: lo xyz, hi xyz
+    uint32_t *ref_tri;       // triangle of each reference
+    float4 *tris;            // 3 per leaf, sorted order; tris[3i].w = triangle id bits
     float4 *albedo;          // 1 per leaf, sorted order
-    BvhNode *nodes;          // ntri - 1
-    uint32_t *parent;        // 2 ntri - 1
+    BvhNode *nodes;          // nleaf - 1
+    uint32_t *parent;        // 2 nleaf - 1
     uint64_t *keys, *keys_tmp;   // 63-bit Morton codes
-    uint32_t *ids, *ids_tmp;
-    uint32_t *flags;         // ntri - 1 refit visit counters
+    uint32_t *ids, *ids_tmp;     // reference indices (sorted: in leaf order)
+    uint32_t *flags;         // nleaf - 1 refit visit counters
     uint32_t *hist;          // radix histograms (digit-major) + 256 digit offsets
     float *bounds;           // 6 partial-bound slots per reduce block + 8 final
     uint32_t *aux;           // 64 B: work counter of the scene-level traversal kernels
@@ -149,7 +155,7 @@ dof_gbuffer resolved_gbuffer(const FrameConst &fc, const Planes &P, const dof_gb
 
 // What the traversal reads of a scene.
 struct SceneArgs {
-    int32_t ntri;
+    int32_t nleaf;
     const float4 *__restrict__ tris;
     const float4 *__restrict__ albedo;
     const BvhNode *__restrict__ nodes;

@@ -44,7 +44,7 @@
 namespace dof {
 namespace {
 
-SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.ntri, s.tris, s.albedo, s.nodes, s.parent}; }
+SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.nleaf, s.tris, s.albedo, s.nodes, s.parent}; }
 
 __device__ inline float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     dropped = false;
                     nq = 0;
                     active = true;
-                    if (Sl.ntri == 1) {
+                    if (Sl.nleaf == 1) {
                         trav = false;
                         q0 = 0u;
                         nq = 1;

@@ -74,12 +74,12 @@ class DofBatchItem(C.Structure):
 
 class DofSceneDesc(C.Structure):
     _fields_ = [("ntri", C.c_int32), ("verts", C.c_void_p), ("albedo", C.c_void_p), ("light_dir", _f3),
-                ("light_rad", _f3), ("ambient", _f3), ("sky", _f3)]
+                ("light_rad", _f3), ("ambient", _f3), ("sky", _f3), ("leaf_split", C.c_int32)]
 
 
 class DofBvhView(C.Structure):
-    _fields_ = [("ntri", C.c_int32), ("keys", C.c_void_p), ("ids", C.c_void_p), ("parent", C.c_void_p),
-                ("nodes", C.c_void_p), ("tris", C.c_void_p)]
+    _fields_ = [("ntri", C.c_int32), ("nleaf", C.c_int32), ("keys", C.c_void_p), ("ids", C.c_void_p),
+                ("parent", C.c_void_p), ("nodes", C.c_void_p), ("tris", C.c_void_p)]
 
 
 DEBUG_FIELDS = ("colr", "zn", "tile_max", "tile_dil", "pre", "gather", "ppmed", "prev_idx", "queue", "ray_base",
@@ -91,7 +91,8 @@ class DofDebugView(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in DEBUG_FIELDS]
 
 
-EXPORTS = ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_scene_bytes", "dof_create_scene",
+EXPORTS = ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_scene_bytes", "dof_scene_bytes_desc",
+           "dof_create_scene",
            "dof_build_bvh", "dof_bvh_view_get", "dof_destroy_scene", "dof_trace_rays", "dof_render_gbuffer",
            "dof_history_bytes", "dof_history_reset", "dof_frame_scratch_bytes", "dof_render_frame",
            "dof_debug_view_get", "dof_stage_times", "dof_batch_bytes", "dof_batch_create", "dof_batch_set",
@@ -124,6 +125,7 @@ def lib():
         L.dof_default_params.argtypes = [P(DofParams)]
         L.dof_default_params.restype = None
         L.dof_scene_bytes.argtypes = [C.c_int32, P(C.c_size_t)]
+        L.dof_scene_bytes_desc.argtypes = [P(DofSceneDesc), P(C.c_size_t)]
         L.dof_create_scene.argtypes = [P(DofSceneDesc), vp, C.c_size_t, vp, P(vp)]
         L.dof_build_bvh.argtypes = [vp, vp]
         L.dof_bvh_view_get.argtypes = [vp, P(DofBvhView)]
@@ -152,7 +154,7 @@ def lib():
             if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
                             "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
-        if L.dof_abi_version() != 3:
+        if L.dof_abi_version() != 4:
             raise ImportError("libdof ABI version mismatch")
         _lib = L
     return _lib
@@ -202,15 +204,18 @@ def _ptr(t):
 class Scene:
     """A scene resident in a caller-owned (torch) device arena."""
 
-    def __init__(self, scene, device="cuda"):
+    def __init__(self, scene, device="cuda", leaf_split=None):
         verts = np.ascontiguousarray(scene.verts, np.float32)
         alb = np.ascontiguousarray(scene.albedo, np.float32)
         n = verts.shape[0]
-        nbytes = C.c_size_t()
-        check(lib().dof_scene_bytes(n, C.byref(nbytes)))
-        self.arena = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        if leaf_split is None:
+            leaf_split = getattr(scene, "leaf_split", 1)
         desc = DofSceneDesc(n, verts.ctypes.data_as(C.c_void_p), alb.ctypes.data_as(C.c_void_p),
-                            _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient), _f3(*scene.sky))
+                            _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient), _f3(*scene.sky),
+                            1 if leaf_split else 0)
+        nbytes = C.c_size_t()
+        check(lib().dof_scene_bytes_desc(C.byref(desc), C.byref(nbytes)))
+        self.arena = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
         h = C.c_void_p()
         check(lib().dof_create_scene(C.byref(desc), _ptr(self.arena), nbytes.value, _stream(), C.byref(h)))
         self.handle = h
@@ -222,8 +227,8 @@ class Scene:
     def bvh_view(self):
         v = DofBvhView()
         check(lib().dof_bvh_view_get(self.handle, C.byref(v)))
-        n = self.ntri
-        return dict(keys=self._slice(v.keys, 8 * n, torch.int64), ids=self._slice(v.ids, 4 * n, torch.int32),
+        n = v.nleaf
+        return dict(nleaf=n, keys=self._slice(v.keys, 8 * n, torch.int64), ids=self._slice(v.ids, 4 * n, torch.int32),
                     parent=self._slice(v.parent, 4 * (2 * n - 1), torch.int32),
                     nodes=self._slice(v.nodes, 64 * max(n - 1, 1), torch.float32),
                     tris=self._slice(v.tris, 48 * n, torch.float32))
@@ -287,8 +292,23 @@ class Scene:
 
 
 def scene_bytes(ntri) -> int:
+    """Arena bound for ntri triangles of any shape."""
     b = C.c_size_t()
     check(lib().dof_scene_bytes(ntri, C.byref(b)))
+    return b.value
+
+
+def scene_bytes_for(scene, leaf_split=None) -> int:
+    """The exact arena size of this scene (its split triangles counted)."""
+    verts = np.ascontiguousarray(scene.verts, np.float32)
+    alb = np.ascontiguousarray(scene.albedo, np.float32)
+    if leaf_split is None:
+        leaf_split = getattr(scene, "leaf_split", 1)
+    desc = DofSceneDesc(verts.shape[0], verts.ctypes.data_as(C.c_void_p), alb.ctypes.data_as(C.c_void_p),
+                        _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient), _f3(*scene.sky),
+                        1 if leaf_split else 0)
+    b = C.c_size_t()
+    check(lib().dof_scene_bytes_desc(C.byref(desc), C.byref(b)))
     return b.value
 
 

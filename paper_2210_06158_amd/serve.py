@@ -103,11 +103,11 @@ class Server:
     def admit(self, spec) -> bool:
         """Create a resident session if its bytes fit the budget."""
         _, w, h, ns, nb = spec
-        need = sessions.resident_bytes(2 + 240 * ns + 4 * nb, w, h, self.params) + (self.ring - 1) * w * h * 20
+        scene, cams, lens, _ = synth.scene_session(spec)
+        need = sessions.resident_bytes(dof.scene_bytes_for(scene), w, h, self.params) + (self.ring - 1) * w * h * 20
         if self.used + need > self.budget:
             self.rejected += 1
             return False
-        scene, cams, lens, _ = synth.scene_session(spec)
         s = RingSession(scene, cams, lens, self.params, ring=self.ring, device=self.device)
         self.sessions.append(s)
         self.used += s.bytes

@@ -16,11 +16,11 @@ import dataclasses
 from . import dof, synth
 
 
-def resident_bytes(ntri: int, width: int, height: int, params) -> int:
+def resident_bytes(scene_arena_bytes: int, width: int, height: int, params) -> int:
     """HBM a session holds: scene arena, one FP16 G-buffer, two history
     records, frame scratch, FP16 colour, mask and stats."""
     px = width * height
-    return (dof.scene_bytes(ntri) + px * 20 + 2 * dof.history_bytes(width, height)
+    return (scene_arena_bytes + px * 20 + 2 * dof.history_bytes(width, height)
             + dof.scratch_bytes(width, height, params) + px * 8 + px // 4 + 32)
 
 
@@ -40,7 +40,7 @@ class Session:
         self.frame = dof.Frame(self.W, self.H, params, out_format=dof.RGBA16F, device=device)
         self.done = 0              # frames rendered so far (history chain position)
         self.gb_frame = -1
-        self.bytes = resident_bytes(self.ntri, self.W, self.H, params)
+        self.bytes = resident_bytes(self.gs.arena.numel(), self.W, self.H, params)
         assert px > 0
 
     @classmethod

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(dof):
 
 def test_abi_version_and_defaults(dof):
     L = dof.lib()
-    assert L.dof_abi_version() == 3
+    assert L.dof_abi_version() == 4
     assert C.sizeof(dof.DofCamera) == 16 * 4 + 2 * 4   # basis, size, counters, jitter
     p = dof.DofParams()
     L.dof_default_params(C.byref(p))
@@ -220,7 +220,7 @@ def test_scene_creation_fails_cleanly_without_a_device(dof):
     desc.verts = verts.ctypes.data
     desc.albedo = albedo.ctypes.data
     b = C.c_size_t()
-    assert L.dof_scene_bytes(2, C.byref(b)) == 0
+    assert L.dof_scene_bytes_desc(C.byref(desc), C.byref(b)) == 0
     h = C.c_void_p()
     st = L.dof_create_scene(C.byref(desc), C.c_void_p(1 << 40), b.value, None, C.byref(h))
     assert st == dof.DOF_E_DEVICE and not h.value
@@ -266,3 +266,34 @@ def test_launch_knob_ranges(dof):
             L.dof_default_params(C.byref(p))
             setattr(p, k, v)
             assert L.dof_frame_scratch_bytes(256, 256, C.byref(p), C.byref(b)) == dof.DOF_E_INVALID, (k, v)
+
+
+def test_scene_bytes_count_the_leaf_references(dof):
+    """dof_scene_bytes_desc sizes the arena for the scene's leaf references:
+    more with leaf_split on a soup of thin triangles, never above the
+    any-shape bound of dof_scene_bytes; bad arguments are rejected."""
+    import ctypes as C
+    import oracle
+    from paper_2210_06158_amd import synth
+    L = dof.lib()
+    v, a = synth.random_triangles(500, seed=31, size=1.5)
+    nref = oracle.OracleScene(synth.Scene(v, a)).leaf_refs()[2].size
+    assert nref > 600
+    sizes = {}
+    for split in (0, 1):
+        desc = dof.DofSceneDesc(500, v.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p))
+        desc.leaf_split = split
+        b = C.c_size_t()
+        assert L.dof_scene_bytes_desc(C.byref(desc), C.byref(b)) == 0
+        sizes[split] = b.value
+    bound = C.c_size_t()
+    assert L.dof_scene_bytes(500, C.byref(bound)) == 0
+    # per extra reference: box 24, triangle 4, leaf triangle 48, albedo 16, node 64, 2 parents, 2 keys, 2 ids, flag
+    per_ref = 24 + 4 + 48 + 16 + 64 + 8 + 16 + 8 + 4
+    assert sizes[1] - sizes[0] >= per_ref * (nref - 500) - 16 * 256   # alignment of each array to 256 B
+    assert sizes[0] < sizes[1] <= bound.value
+    desc.leaf_split = 2
+    assert L.dof_scene_bytes_desc(C.byref(desc), C.byref(b)) == dof.DOF_E_INVALID
+    assert L.dof_scene_bytes_desc(None, C.byref(b)) == dof.DOF_E_INVALID
+    desc.leaf_split = 1
+    assert L.dof_scene_bytes_desc(C.byref(desc), None) == dof.DOF_E_INVALID

@@ -90,11 +90,12 @@ def test_bvh_bit_exact(env, orc):
     torch = env["torch"]
     v = env["gs"].bvh_view()
     ob = env["osc"].bvh
-    n = env["osc"].ntri
+    n = v["nleaf"]
+    assert n == ob["refs"].size
     keys = v["keys"].cpu().numpy().view(np.uint64)
-    ids = v["ids"].cpu().numpy().view(np.uint32)
+    refs = v["ids"].cpu().numpy().view(np.uint32)
     assert np.array_equal(keys, ob["keys"])
-    assert np.array_equal(ids, ob["ids"])
+    assert np.array_equal(refs, ob["refs"])
     nodes = v["nodes"].cpu().numpy().reshape(n - 1, 16)
     nu = nodes.view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
@@ -129,9 +130,9 @@ def test_bvh_bit_exact(env, orc):
         assert np.array_equal(lb.view(np.uint32), child_box(int(ob["left"][i])).view(np.uint32))
         assert np.array_equal(rb.view(np.uint32), child_box(int(ob["right"][i])).view(np.uint32))
     tris = v["tris"].cpu().numpy().reshape(n, 12)
-    want = env["scene"].verts[ids]
+    want = env["scene"].verts[ob["ids"]]
     assert np.array_equal(tris[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]], want)
-    assert np.array_equal(tris[:, 3].view(np.uint32), ids)
+    assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
 
 
 @pytest.mark.parametrize("n,seed", [(1, 3), (2, 4), (3, 5), (257, 6), (5000, 7)])
@@ -145,12 +146,29 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
     gs.build_bvh()
     torch.cuda.synchronize()
     view = gs.bvh_view()
+    nl = view["nleaf"]
+    assert nl == ob["refs"].size and (n < 100 or nl > n)     # the larger soups have split triangles
     keys = view["keys"].cpu().numpy().view(np.uint64)
-    ids = view["ids"].cpu().numpy().view(np.uint32)
-    assert np.array_equal(keys, ob["keys"]) and np.array_equal(ids, ob["ids"])
-    if n > 1:
-        nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
-        assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
+    refs = view["ids"].cpu().numpy().view(np.uint32)
+    assert np.array_equal(keys, ob["keys"]) and np.array_equal(refs, ob["refs"])
+    if nl > 1:
+        nodes = view["nodes"].cpu().numpy().reshape(nl - 1, 16)
+        nu = nodes.view(np.uint32)
+        assert np.array_equal(nu[:, 12], ob["left"][:nl - 1]) and np.array_equal(nu[:, 13], ob["right"][:nl - 1])
+        # child boxes bit for bit: split references carry clipped boxes
+        lb = np.stack([nodes[:, 0], nodes[:, 2], nodes[:, 8], nodes[:, 1], nodes[:, 3], nodes[:, 9]], 1)
+        rb = np.stack([nodes[:, 4], nodes[:, 6], nodes[:, 10], nodes[:, 5], nodes[:, 7], nodes[:, 11]], 1)
+        def boxes_of(ch):
+            ch = ch[:nl - 1].astype(np.int64)
+            leaf = (ch & 0x80000000) != 0
+            out = np.where(leaf[:, None], ob["leaf_bounds"][np.where(leaf, ch & 0x7FFFFFFF, 0)],
+                           ob["bounds"][np.where(leaf, 0, ch)])
+            return out.astype(np.float32)
+        assert np.array_equal(lb.view(np.uint32), boxes_of(ob["left"]).view(np.uint32))
+        assert np.array_equal(rb.view(np.uint32), boxes_of(ob["right"]).view(np.uint32))
+    tris = view["tris"].cpu().numpy().reshape(nl, 12)
+    assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
+    assert np.array_equal(tris[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]], v[ob["ids"]])
     rng = synth.SplitMix64(seed * 31)
     nr = 20000
     o = rng.uniform(3 * nr, -5, 5).reshape(nr, 3).astype(np.float32)
@@ -258,7 +276,7 @@ def test_deep_tree_stack_drops(env, orc, ladder):
     sc, osc, ob, gs = ladder
     view = gs.bvh_view()
     assert np.array_equal(view["keys"].cpu().numpy().view(np.uint64), ob["keys"])
-    n = sc.ntri
+    n = view["nleaf"]
     nu = view["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
     rng = synth.SplitMix64(99)

@@ -82,9 +82,12 @@ def check(o, d, label, colour_tol=COLOUR_TOL):
 def test_bvh_full_size_bit_exact(big):
     v = big["gs"].bvh_view()
     ob = big["osc"].bvh
-    n = big["scene"].ntri
+    n = v["nleaf"]
+    assert n == ob["refs"].size and n > big["scene"].ntri     # the grass blades are split
     assert np.array_equal(v["keys"].cpu().numpy().view(np.uint64), ob["keys"])
-    assert np.array_equal(v["ids"].cpu().numpy().view(np.uint32), ob["ids"])
+    assert np.array_equal(v["ids"].cpu().numpy().view(np.uint32), ob["refs"])
+    tris = v["tris"].cpu().numpy().reshape(n, 12)
+    assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
     nodes = v["nodes"].cpu().numpy().reshape(n - 1, 16)
     nu = nodes.view(np.uint32)
     assert np.array_equal(nu[:, 12], ob["left"][:n - 1]) and np.array_equal(nu[:, 13], ob["right"][:n - 1])
@@ -145,7 +148,8 @@ def test_full_frame_4k_hexagon(big, orc):
     torch.cuda.synchronize()
     v = gs.bvh_view()
     assert np.array_equal(v["keys"].cpu().numpy().view(np.uint64), osc.bvh["keys"])
-    n = scene.ntri
+    n = v["nleaf"]
+    assert np.array_equal(v["ids"].cpu().numpy().view(np.uint32), osc.bvh["refs"])
     nu = v["nodes"].cpu().numpy().reshape(n - 1, 16).view(np.uint32)
     assert np.array_equal(nu[:, 12], osc.bvh["left"][:n - 1]) and np.array_equal(nu[:, 13], osc.bvh["right"][:n - 1])
     cam, lens = cams[0], lenses[0]

@@ -30,13 +30,15 @@ def test_morton_golden(orc):
     assert orc.morton(sc).tolist() == g["triangle_codes"]
 
 
-def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
-    """Checks of a binary radix tree over the 96-bit keys code << 32 | id."""
+def _tree_checks(codes, refs, left, right, parent, bounds, leaf_bounds, ref_boxes):
+    """Checks of a binary radix tree over the 96-bit keys code << 32 | ref
+    whose leaves are the references with boxes ref_boxes[ref]."""
     n = codes.size
-    keys = [(int(c) << 32) | int(i) for c, i in zip(codes, ids)]
-    ids = ids.astype(np.int64)
+    keys = [(int(c) << 32) | int(i) for c, i in zip(codes, refs)]
+    refs = refs.astype(np.int64)
     assert all(a < b for a, b in zip(keys, keys[1:]))
-    assert sorted(ids.tolist()) == list(range(n))
+    assert sorted(refs.tolist()) == list(range(n))
+    assert np.array_equal(leaf_bounds, ref_boxes[refs])
     if n == 1:
         return
     seen_leaf = np.zeros(n, int)
@@ -48,7 +50,6 @@ def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
             seen_node[ch] += 1
     assert (seen_leaf == 1).all()
     assert seen_node[0] == 0 and (seen_node[1:] == 1).all()
-    tri = verts.reshape(-1, 3, 3)
     # ranges by explicit DFS, then the defining properties of each split
     stack = [(0, 0, n - 1)]
     while stack:
@@ -66,10 +67,8 @@ def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
             assert (rc & 0x7FFFFFFF) == split + 1 == l
         else:
             assert rc == split + 1
-        sub = tri[ids[f:l + 1]]
-        lo = sub.min(axis=(0, 1))
-        hi = sub.max(axis=(0, 1))
-        assert np.array_equal(bounds[node], np.concatenate([lo, hi]))
+        sub = ref_boxes[refs[f:l + 1]]
+        assert np.array_equal(bounds[node], np.concatenate([sub[:, :3].min(0), sub[:, 3:].max(0)]))
         if lc & 0x80000000:
             assert split == f
             assert parent[n - 1 + split] == node
@@ -81,32 +80,135 @@ def _tree_checks(codes, ids, left, right, parent, bounds, leaf_bounds, verts):
             stack.append((rc, split + 1, l))
         else:
             assert parent[n - 1 + l] == node
-    for i in range(n):
-        t = tri[ids[i]]
-        assert np.array_equal(leaf_bounds[i], np.concatenate([t.min(0), t.max(0)]))
+
+
+def _check_built_tree(orc, sc, v):
+    b = sc.build_bvh()
+    off, boxes, tri = sc.leaf_refs()
+    n = boxes.shape[0]
+    codes = orc.morton_boxes(boxes)
+    assert np.array_equal(b["keys"], codes[b["refs"]])
+    assert np.array_equal(b["ids"], tri[b["refs"]])
+    # the references of each triangle, in order; an unsplit one is the triangle's box
+    tv = v.reshape(-1, 3, 3)
+    for i in range(tv.shape[0]):
+        r = np.arange(off[i], off[i + 1])
+        assert (tri[r] == i).all() and len(r) in (1, 4)
+        if len(r) == 1:
+            assert np.array_equal(boxes[r[0]], np.concatenate([tv[i].min(0), tv[i].max(0)]))
+    _tree_checks(b["keys"], b["refs"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
+                 b["leaf_bounds"], boxes)
+    return b, off, boxes, tri
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 513, 2000])
 def test_radix_tree_properties(orc, n):
     v, a = synth.random_triangles(n, seed=100 + n)
-    sc = orc.OracleScene(synth.Scene(v, a))
-    b = sc.build_bvh()
-    codes = orc.morton(sc)
-    assert np.array_equal(b["keys"], codes[b["ids"]])
-    _tree_checks(b["keys"], b["ids"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
-                 b["leaf_bounds"], v)
+    _check_built_tree(orc, orc.OracleScene(synth.Scene(v, a)), v)
+
+
+def test_radix_tree_without_leaf_split_is_over_triangles(orc):
+    v, a = synth.random_triangles(300, seed=9)
+    sc = orc.OracleScene(synth.Scene(v, a), leaf_split=0)
+    b, off, boxes, tri = _check_built_tree(orc, sc, v)
+    assert np.array_equal(off, np.arange(301)) and np.array_equal(b["refs"], b["ids"])
+    assert np.array_equal(b["keys"], orc.morton(sc)[b["ids"]])
 
 
 def test_radix_tree_duplicate_codes(orc):
-    # many coincident triangles share one Morton code; the id breaks ties
+    # many coincident triangles share one Morton code; the reference index breaks ties
     v, a = synth.random_triangles(40, seed=5)
     v = np.concatenate([v, np.repeat(v[:3], 50, axis=0)])
     a = np.concatenate([a, np.repeat(a[:3], 50, axis=0)])
+    _check_built_tree(orc, orc.OracleScene(synth.Scene(v, a)), v)
+
+
+# ---------------------------------------------------------------- leaf references
+
+def _exact_piece_box(tri, k, s0, s1):
+    """Bounds of triangle tri (3x3, binary64) clipped to s0 <= x_k <= s1:
+    Sutherland-Hodgman against both planes, then min / max."""
+    def clip(poly, val, keep_ge):
+        out = []
+        for i in range(len(poly)):
+            a, b = poly[i], poly[(i + 1) % len(poly)]
+            ina = a[k] >= val if keep_ge else a[k] <= val
+            inb = b[k] >= val if keep_ge else b[k] <= val
+            if ina:
+                out.append(a)
+            if ina != inb:
+                out.append(a + (b - a) * ((val - a[k]) / (b[k] - a[k])))
+        return out
+    poly = clip(clip([p for p in tri], s0, True), s1, False)
+    pts = np.array(poly)
+    return pts.min(0), pts.max(0)
+
+
+def test_leaf_split_rule(orc):
+    """Four references iff the box's three face areas sum to more than 8 times
+    the triangle's area; the slabs cut the longest box axis in quarters."""
+    g = json.load(open(os.path.join(GOLD, "leaf_split_cases.json")))
+    for case in g["cases"]:
+        v = np.array([case["verts"]], np.float32)
+        sc = orc.OracleScene(synth.Scene(v, np.ones((1, 3), np.float32)))
+        off, boxes, tri = sc.leaf_refs()
+        assert int(off[1]) == case["refs"], case["name"]
+        for box, want in zip(boxes, case.get("pieces", [])):
+            lo, hi = np.array(want[:3]), np.array(want[3:])
+            # the exact piece bounds lie inside, and the box exceeds them by at most 2^-18 of the scale
+            assert (box[:3] <= lo).all() and (box[3:] >= hi).all(), case["name"]
+            assert (lo - box[:3] <= 2.0 ** -18 * case["scale"]).all(), case["name"]
+            assert (box[3:] - hi <= 2.0 ** -18 * case["scale"]).all(), case["name"]
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_leaf_split_pieces_cover_and_fit_the_triangle(orc, seed):
+    """Each split triangle: the pieces' slabs tile its box along the longest
+    axis, every piece box contains the exactly clipped piece (binary64) and
+    exceeds it by at most 2^-18 of the triangle's size, and sample points of
+    the triangle (including vertices and edge points on the slab planes) lie
+    in some piece box."""
+    v, a = synth.random_triangles(400, seed=seed, size=1.5)
     sc = orc.OracleScene(synth.Scene(v, a))
-    b = sc.build_bvh()
-    n = v.shape[0]
-    _tree_checks(b["keys"], b["ids"], b["left"][:n - 1], b["right"][:n - 1], b["parent"], b["bounds"][:n - 1],
-                 b["leaf_bounds"], v)
+    off, boxes, tri = sc.leaf_refs()
+    tv = v.reshape(-1, 3, 3).astype(np.float64)
+    nsplit = 0
+    rng = np.random.default_rng(seed)
+    for i in range(tv.shape[0]):
+        r = np.arange(off[i], off[i + 1])
+        if len(r) == 1:
+            continue
+        nsplit += 1
+        lo, hi = tv[i].min(0), tv[i].max(0)
+        ext = (hi - lo).astype(np.float32)
+        k = int(np.argmax(ext))
+        pb = boxes[r].astype(np.float64)
+        assert pb[0, k] == lo[k] and pb[-1, 3 + k] == hi[k]
+        assert (pb[1:, k] == pb[:-1, 3 + k]).all() and (pb[:, k] <= pb[:, 3 + k]).all()
+        scale = float(np.abs(tv[i]).max() + (hi - lo).max())
+        for j in range(4):
+            elo, ehi = _exact_piece_box(tv[i], k, pb[j, k], pb[j, 3 + k])
+            assert (pb[j, :3] <= elo + 1e-12 * scale).all() and (pb[j, 3:] >= ehi - 1e-12 * scale).all()
+            assert (elo - pb[j, :3] <= 2.0 ** -18 * scale).all() and (pb[j, 3:] - ehi <= 2.0 ** -18 * scale).all()
+        w = rng.dirichlet([1, 1, 1], 200)
+        pts = np.concatenate([w @ tv[i], tv[i]])
+        for p in pts:
+            inside = ((pb[:, :3] <= p) & (p <= pb[:, 3:])).all(1)
+            assert inside.any()
+    assert nsplit > 40
+
+
+def test_leaf_split_keeps_every_closest_hit(orc):
+    """Random soups with many thin triangles: the tree over split references
+    finds the same closest hits as the tree over whole triangles, bit for bit."""
+    v, a = synth.random_triangles(600, seed=21, size=1.2)
+    o, d = _random_rays(3000, seed=22)
+    s1 = orc.OracleScene(synth.Scene(v, a), leaf_split=1)
+    s0 = orc.OracleScene(synth.Scene(v, a), leaf_split=0)
+    h1, t1 = orc.closest_hit(s1, o, d)
+    h0, t0 = orc.closest_hit(s0, o, d)
+    assert s1.leaf_refs()[0][-1] > s0.leaf_refs()[0][-1]
+    assert np.array_equal(h1, h0) and np.array_equal(t1.view(np.uint32), t0.view(np.uint32))
 
 
 def _random_rays(n, seed, spread=5.0):
