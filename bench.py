@@ -168,9 +168,9 @@ def fixed_config(args):
 
 def scene_for(scene, cams, lenses, params, log, label, fixed, frames=6, reps=2):
     """The scene's BVH for a workload (setup, outside every timed region):
-    with leaf_split (long thin triangles as four clipped leaf references)
-    and without, each rendering the first `frames` frames of the path with
-    the library's default launch shapes; the faster is kept.  Splitting cuts
+    each leaf_split (a long thin triangle as 2^s clipped leaf references,
+    s = 2, 3, 1, 0) renders the first `frames` frames of the path with the
+    library's default launch shapes; the fastest is kept.  Splitting cuts
     triangle tests where thin triangles fill little of their boxes, at the
     price of more leaves (a larger tree); which wins depends on the scene.
     fixed["leaf_split"] (from --config) skips the trial.  Returns
@@ -188,7 +188,7 @@ def scene_for(scene, cams, lenses, params, log, label, fixed, frames=6, reps=2):
     fr = frame_for(W, H, params, {})
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     times, scenes, gbs = {}, {}, None
-    for ls in (1, 0):
+    for ls in (2, 3, 1, 0):
         gs = dof.Scene(dataclasses.replace(scene, leaf_split=ls))
         gs.build_bvh()
         if gbs is None:

@@ -202,19 +202,20 @@ typedef struct {
     const float *albedo;    /* host, 3 floats per triangle */
     float light_dir[3];     /* direction the light travels (unit) */
     float light_rad[3], ambient[3], sky[3];
-    int32_t leaf_split;     /* 1: a long thin triangle (its box's three face areas sum to more than 8
-                             * times its area) becomes 4 leaf references, the triangle clipped to
-                             * quarters of its box along the longest axis (early split clipping,
+    int32_t leaf_split;     /* s = 1..3: a long thin triangle (its box's three face areas sum to more
+                             * than 8 times its area) becomes 2^s leaf references, the triangle clipped
+                             * to equal slabs of its box along the longest axis (early split clipping,
                              * Ernst & Greiner 2007), so rays that enter the box beside the triangle
-                             * mostly skip its test; 0: one leaf per triangle.  Hits are the same. */
+                             * mostly skip its test; 0: one leaf per triangle.  Hits are the same;
+                             * which s is fastest depends on the scene. */
 } dof_scene_desc;
 
 typedef struct dof_scene dof_scene;
 
 /* Device views of the acceleration structure (for inspection and tests).
  * Its nleaf leaves are references: a triangle, or with leaf_split one of the
- * four pieces of a split triangle; reference r of triangle i is
- * ref_off[i] + j (pieces j = 0..3 in slab order), and its box is the
+ * 2^leaf_split pieces of a split triangle; reference r of triangle i is
+ * ref_off[i] + j (pieces j in slab order), and its box is the
  * triangle's box, or for a piece: on the split axis the slab, on the others
  * the range of the piece's vertices and edge crossings (each crossing
  * widened by 2^-20 (|edge extent| + |x|)), clipped to the triangle's box.
@@ -251,7 +252,7 @@ const char *dof_last_error(void);
 void dof_default_params(dof_params *p);
 
 /* Scene arena size bound for ntri triangles of any shape: input triangles,
- * then per leaf reference (at most 4 per triangle) its box, the leaf-ordered
+ * then per leaf reference (at most 8 per triangle) its box, the leaf-ordered
  * triangle, BVH node and parent links, and the build's keys, sort buffers and
  * counters (about 200 bytes per reference). */
 dof_status dof_scene_bytes(int32_t ntri, size_t *bytes);

@@ -142,10 +142,10 @@ class OracleScene:
         self.verts = np.ascontiguousarray(scene.verts, dtype=np.float32)
         self.albedo = np.ascontiguousarray(scene.albedo, dtype=np.float32)
         if leaf_split is None:
-            leaf_split = getattr(scene, "leaf_split", 1)
+            leaf_split = getattr(scene, "leaf_split", 2)
         self.s = OrcScene(self.verts.shape[0], _ptr(self.verts), _ptr(self.albedo),
                           _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient),
-                          _f3(*scene.sky), 1 if leaf_split else 0)
+                          _f3(*scene.sky), int(leaf_split))
         self.ntri = self.verts.shape[0]
         self.bvh = None
 

@@ -258,15 +258,16 @@ int orc_morton(const orc_scene *s, uint64_t *codes)
 /* Leaf references: early split clipping (Ernst & Greiner, "Early Split     */
 /* Clipping for Bounding Volume Hierarchies", IEEE RT 2007).  A long thin    */
 /* slanted triangle (a grass blade, a fence wire) fills little of its box,   */
-/* so most rays that enter the box miss it.  Such a triangle becomes four    */
-/* leaf references, the triangle clipped to four equal slabs of its box      */
-/* along the box's longest axis; each reference's box bounds its piece.      */
+/* so most rays that enter the box miss it.  Such a triangle becomes 2, 4 or */
+/* 8 leaf references, the triangle clipped to equal slabs of its box along   */
+/* the box's longest axis; each reference's box bounds its piece.            */
 /* ------------------------------------------------------------------------ */
 
-/* Split iff the sum of the box's three face areas exceeds 8 times the
- * triangle's area: (sum)^2 > 16 |e1 x e2|^2, in binary64 (deterministic;
- * the library decides with the same formula). */
-static int ref_count(const float *v)
+/* A triangle is thin iff the sum of its box's three face areas exceeds 8
+ * times its area: (sum)^2 > 16 |e1 x e2|^2, in binary64 (deterministic; the
+ * library decides with the same formula).  A thin triangle gets 2^split
+ * references, any other one. */
+static int ref_count(const float *v, int split)
 {
     float lo[3], hi[3];
     tri_box(v, lo, hi);
@@ -281,16 +282,16 @@ static int ref_count(const float *v)
     double cy = u[2] * w[0] - u[0] * w[2];
     double cz = u[0] * w[1] - u[1] * w[0];
     double c2 = (cx * cx + cy * cy) + cz * cz;
-    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? 4 : 1;
+    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? 1 << split : 1;
 }
 
 int64_t orc_leaf_refs(const orc_scene *s, uint32_t *ref_off)
 {
-    if (!s || s->ntri <= 0 || !ref_off) return -1;
+    if (!s || s->ntri <= 0 || !ref_off || s->leaf_split < 0 || s->leaf_split > 3) return -1;
     uint64_t acc = 0;
     for (int i = 0; i < s->ntri; i++) {
         ref_off[i] = (uint32_t)acc;
-        acc += s->leaf_split ? (uint64_t)ref_count(s->verts + 9 * (size_t)i) : 1u;
+        acc += s->leaf_split ? (uint64_t)ref_count(s->verts + 9 * (size_t)i, s->leaf_split) : 1u;
         if (acc > 0x7fffffffu) return -1;
     }
     ref_off[s->ntri] = (uint32_t)acc;
@@ -358,20 +359,20 @@ int orc_ref_boxes(const orc_scene *s, const uint32_t *ref_off, float *boxes, uin
             ref_tri[r0] = (uint32_t)i;
             continue;
         }
-        if (nr != 4) return -1;
-        /* slabs along the longest box axis (first one on ties) */
+        if (nr != 2 && nr != 4 && nr != 8) return -1;
+        /* nr equal slabs along the longest box axis (first one on ties) */
         float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
         int k = 0;
         if (ext[1] > ext[k]) k = 1;
         if (ext[2] > ext[k]) k = 2;
-        float q = ext[k] * 0.25f, sl[5];
+        float q = ext[k] * (1.0f / (float)nr), sl[9];
         sl[0] = lo[k];
-        sl[4] = hi[k];
-        for (int j = 1; j < 4; j++) {
+        sl[nr] = hi[k];
+        for (uint32_t j = 1; j < nr; j++) {
             float x = lo[k] + q * (float)j;
             sl[j] = x < hi[k] ? x : hi[k];
         }
-        for (int j = 0; j < 4; j++) {
+        for (uint32_t j = 0; j < nr; j++) {
             piece_box(v, k, sl[j], sl[j + 1], lo, hi, boxes + 6 * (size_t)(r0 + j));
             ref_tri[r0 + j] = (uint32_t)i;
         }

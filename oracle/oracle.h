@@ -62,7 +62,7 @@ typedef struct {
     const float *verts;                     /* 9 per triangle */
     const float *albedo;                    /* 3 per triangle */
     float light_dir[3], light_rad[3], ambient[3], sky[3];
-    int32_t leaf_split;                     /* 1: long thin triangles become 4 clipped leaf references */
+    int32_t leaf_split;                     /* s = 1..3: a long thin triangle becomes 2^s clipped leaf references; 0: none */
 } orc_scene;
 
 /* Binary radix tree over the leaf references (a triangle, or with

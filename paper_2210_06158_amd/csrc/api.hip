@@ -104,14 +104,15 @@ SceneLayout scene_layout(int64_t nt, int64_t n)
 }
 
 // Leaf references (early split clipping, Ernst & Greiner 2007): with
-// desc->leaf_split a triangle whose box's three face areas sum to more than 8
-// times its area -- a long thin slanted triangle, which most rays entering its
-// box miss -- becomes 4 references, its pieces in quarters of the box along
-// the longest axis (clipped on the device when the BVH is built).  Decided
-// here in binary64, so the size query and the upload agree.
-constexpr int kMaxRefsPerTri = 4;
+// desc->leaf_split = s > 0 a triangle whose box's three face areas sum to more
+// than 8 times its area -- a long thin slanted triangle, which most rays
+// entering its box miss -- becomes 2^s references, its pieces in equal slabs
+// of the box along the longest axis (clipped on the device when the BVH is
+// built).  Decided here in binary64, so the size query and the upload agree.
+constexpr int kMaxLeafSplit = 3;
+constexpr int kMaxRefsPerTri = 1 << kMaxLeafSplit;
 
-uint32_t refs_of(const float *v)
+uint32_t refs_of(const float *v, int split)
 {
     float lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
@@ -136,7 +137,7 @@ uint32_t refs_of(const float *v)
     const double cy = u[2] * w[0] - u[0] * w[2];
     const double cz = u[0] * w[1] - u[1] * w[0];
     const double c2 = (cx * cx + cy * cy) + cz * cz;
-    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? (uint32_t)kMaxRefsPerTri : 1u;
+    return (c2 > 0.0 && faces * faces > 16.0 * c2) ? 1u << split : 1u;
 }
 
 // Reference offsets of the triangles (off may be NULL: count only); -1 when
@@ -146,7 +147,7 @@ int64_t leaf_refs(const dof_scene_desc *desc, uint32_t *off)
     uint64_t acc = 0;
     for (int32_t i = 0; i < desc->ntri; ++i) {
         if (off) off[i] = (uint32_t)acc;
-        acc += desc->leaf_split ? refs_of(desc->verts + 9 * (size_t)i) : 1u;
+        acc += desc->leaf_split ? refs_of(desc->verts + 9 * (size_t)i, desc->leaf_split) : 1u;
         if (acc > (uint64_t)INT32_MAX) return -1;
     }
     if (off) off[desc->ntri] = (uint32_t)acc;
@@ -586,7 +587,8 @@ static dof_status check_desc(const dof_scene_desc *desc)
 {
     if (!desc || !desc->verts || !desc->albedo || desc->ntri <= 0)
         return fail(DOF_E_INVALID, "scene description: NULL argument or ntri <= 0");
-    if (desc->leaf_split != 0 && desc->leaf_split != 1) return fail(DOF_E_INVALID, "leaf_split must be 0 or 1");
+    if (desc->leaf_split < 0 || desc->leaf_split > kMaxLeafSplit)
+        return fail(DOF_E_INVALID, "leaf_split must be 0..%d", kMaxLeafSplit);
     return DOF_OK;
 }
 

@@ -99,8 +99,9 @@ __device__ inline void piece_box(const float *v, int k, float s0, float s1, cons
 }
 
 // One thread per triangle: its references' boxes and triangle index.  A
-// triangle with one reference keeps its own box; one with four is cut into
-// quarters of its box along the longest axis (the first one on ties).
+// triangle with one reference keeps its own box; one with 2, 4 or 8 is cut
+// into that many equal slabs of its box along the longest axis (the first
+// one on ties).
 __global__ __launch_bounds__(kThreads) void k_ref_emit(const float *__restrict__ verts, int nt,
                                                        const uint32_t *__restrict__ ref_off, float *__restrict__ boxes,
                                                        uint32_t *__restrict__ ref_tri)
@@ -124,15 +125,16 @@ __global__ __launch_bounds__(kThreads) void k_ref_emit(const float *__restrict__
     int k = 0;
     if (ext[1] > ext[k]) k = 1;
     if (ext[2] > ext[k]) k = 2;
-    const float q = ext[k] * 0.25f;
-    float sl[5];
+    const int np = nr <= 2 ? 2 : (nr <= 4 ? 4 : 8);   // 2, 4 or 8 (the host never writes another count)
+    const float q = ext[k] * (1.0f / (float)np);
+    float sl[9];
     sl[0] = lo[k];
-    sl[4] = hi[k];
-    for (int j = 1; j < 4; ++j) {
+    sl[np] = hi[k];
+    for (int j = 1; j < np; ++j) {
         const float x = lo[k] + q * (float)j;
         sl[j] = x < hi[k] ? x : hi[k];
     }
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < np; ++j) {
         float o[6];
         piece_box(v, k, sl[j], sl[j + 1], lo, hi, o);
         float *dst = boxes + 6 * (size_t)(r0 + j);

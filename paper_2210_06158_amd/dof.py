@@ -209,10 +209,10 @@ class Scene:
         alb = np.ascontiguousarray(scene.albedo, np.float32)
         n = verts.shape[0]
         if leaf_split is None:
-            leaf_split = getattr(scene, "leaf_split", 1)
+            leaf_split = getattr(scene, "leaf_split", 2)
         desc = DofSceneDesc(n, verts.ctypes.data_as(C.c_void_p), alb.ctypes.data_as(C.c_void_p),
                             _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient), _f3(*scene.sky),
-                            1 if leaf_split else 0)
+                            int(leaf_split))
         nbytes = C.c_size_t()
         check(lib().dof_scene_bytes_desc(C.byref(desc), C.byref(nbytes)))
         self.arena = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
@@ -303,10 +303,10 @@ def scene_bytes_for(scene, leaf_split=None) -> int:
     verts = np.ascontiguousarray(scene.verts, np.float32)
     alb = np.ascontiguousarray(scene.albedo, np.float32)
     if leaf_split is None:
-        leaf_split = getattr(scene, "leaf_split", 1)
+        leaf_split = getattr(scene, "leaf_split", 2)
     desc = DofSceneDesc(verts.shape[0], verts.ctypes.data_as(C.c_void_p), alb.ctypes.data_as(C.c_void_p),
                         _f3(*scene.light_dir), _f3(*scene.light_rad), _f3(*scene.ambient), _f3(*scene.sky),
-                        1 if leaf_split else 0)
+                        int(leaf_split))
     b = C.c_size_t()
     check(lib().dof_scene_bytes_desc(C.byref(desc), C.byref(b)))
     return b.value

@@ -128,7 +128,7 @@ class Scene:
     light_rad: tuple = (1.0, 1.0, 1.0)
     ambient: tuple = (0.15, 0.15, 0.15)
     sky: tuple = (0.55, 0.70, 0.95)
-    leaf_split: int = 1         # BVH leaves: long thin triangles split into 4 clipped references
+    leaf_split: int = 2         # BVH leaves: a long thin triangle becomes 2^leaf_split clipped references
 
     @property
     def ntri(self) -> int:

@@ -280,7 +280,7 @@ def test_scene_bytes_count_the_leaf_references(dof):
     nref = oracle.OracleScene(synth.Scene(v, a)).leaf_refs()[2].size
     assert nref > 600
     sizes = {}
-    for split in (0, 1):
+    for split in (0, 1, 2, 3):
         desc = dof.DofSceneDesc(500, v.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p))
         desc.leaf_split = split
         b = C.c_size_t()
@@ -290,10 +290,11 @@ def test_scene_bytes_count_the_leaf_references(dof):
     assert L.dof_scene_bytes(500, C.byref(bound)) == 0
     # per extra reference: box 24, triangle 4, leaf triangle 48, albedo 16, node 64, 2 parents, 2 keys, 2 ids, flag
     per_ref = 24 + 4 + 48 + 16 + 64 + 8 + 16 + 8 + 4
-    assert sizes[1] - sizes[0] >= per_ref * (nref - 500) - 16 * 256   # alignment of each array to 256 B
-    assert sizes[0] < sizes[1] <= bound.value
-    desc.leaf_split = 2
-    assert L.dof_scene_bytes_desc(C.byref(desc), C.byref(b)) == dof.DOF_E_INVALID
+    assert sizes[2] - sizes[0] >= per_ref * (nref - 500) - 16 * 256   # alignment of each array to 256 B
+    assert sizes[0] < sizes[1] < sizes[2] < sizes[3] <= bound.value
+    for bad in (-1, 4):
+        desc.leaf_split = bad
+        assert L.dof_scene_bytes_desc(C.byref(desc), C.byref(b)) == dof.DOF_E_INVALID
     assert L.dof_scene_bytes_desc(None, C.byref(b)) == dof.DOF_E_INVALID
     desc.leaf_split = 1
     assert L.dof_scene_bytes_desc(C.byref(desc), None) == dof.DOF_E_INVALID

@@ -135,11 +135,15 @@ def test_bvh_bit_exact(env, orc):
     assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
 
 
-@pytest.mark.parametrize("n,seed", [(1, 3), (2, 4), (3, 5), (257, 6), (5000, 7)])
-def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
+@pytest.mark.parametrize("n,seed,split", [(1, 3, 2), (2, 4, 2), (3, 5, 2), (257, 6, 2), (5000, 7, 2), (5000, 8, 1),
+                                          (5000, 9, 3), (2000, 10, 0)])
+def test_bvh_random_soups_and_closest_hit(env, orc, n, seed, split):
+    """Random soups (many thin triangles) with each leaf split: keys, leaf
+    references, children, child boxes and leaf triangles bit for bit, and
+    every ray's closest hit equal to brute force over the triangles."""
     torch, dof = env["torch"], env["dof"]
     v, a = synth.random_triangles(n, seed=seed, spread=4.0, size=0.8)
-    sc = synth.Scene(v, a)
+    sc = synth.Scene(v, a, leaf_split=split)
     osc = orc.OracleScene(sc)
     ob = osc.build_bvh()
     gs = dof.Scene(sc)
@@ -147,7 +151,7 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed):
     torch.cuda.synchronize()
     view = gs.bvh_view()
     nl = view["nleaf"]
-    assert nl == ob["refs"].size and (n < 100 or nl > n)     # the larger soups have split triangles
+    assert nl == ob["refs"].size and (n < 100 or (nl > n) == (split > 0))   # the larger soups have thin triangles
     keys = view["keys"].cpu().numpy().view(np.uint64)
     refs = view["ids"].cpu().numpy().view(np.uint32)
     assert np.array_equal(keys, ob["keys"]) and np.array_equal(refs, ob["refs"])

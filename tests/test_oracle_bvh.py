@@ -161,15 +161,15 @@ def test_leaf_split_rule(orc):
             assert (box[3:] - hi <= 2.0 ** -18 * case["scale"]).all(), case["name"]
 
 
-@pytest.mark.parametrize("seed", [11, 12])
-def test_leaf_split_pieces_cover_and_fit_the_triangle(orc, seed):
-    """Each split triangle: the pieces' slabs tile its box along the longest
-    axis, every piece box contains the exactly clipped piece (binary64) and
-    exceeds it by at most 2^-18 of the triangle's size, and sample points of
-    the triangle (including vertices and edge points on the slab planes) lie
-    in some piece box."""
+@pytest.mark.parametrize("split,seed", [(1, 11), (2, 12), (3, 13)])
+def test_leaf_split_pieces_cover_and_fit_the_triangle(orc, split, seed):
+    """Each split triangle: its 2^split pieces' slabs tile its box along the
+    longest axis, every piece box contains the exactly clipped piece
+    (binary64) and exceeds it by at most 2^-18 of the triangle's size, and
+    sample points of the triangle (including its vertices) lie in some piece
+    box."""
     v, a = synth.random_triangles(400, seed=seed, size=1.5)
-    sc = orc.OracleScene(synth.Scene(v, a))
+    sc = orc.OracleScene(synth.Scene(v, a), leaf_split=split)
     off, boxes, tri = sc.leaf_refs()
     tv = v.reshape(-1, 3, 3).astype(np.float64)
     nsplit = 0
@@ -178,6 +178,7 @@ def test_leaf_split_pieces_cover_and_fit_the_triangle(orc, seed):
         r = np.arange(off[i], off[i + 1])
         if len(r) == 1:
             continue
+        assert len(r) == 1 << split
         nsplit += 1
         lo, hi = tv[i].min(0), tv[i].max(0)
         ext = (hi - lo).astype(np.float32)
@@ -186,7 +187,7 @@ def test_leaf_split_pieces_cover_and_fit_the_triangle(orc, seed):
         assert pb[0, k] == lo[k] and pb[-1, 3 + k] == hi[k]
         assert (pb[1:, k] == pb[:-1, 3 + k]).all() and (pb[:, k] <= pb[:, 3 + k]).all()
         scale = float(np.abs(tv[i]).max() + (hi - lo).max())
-        for j in range(4):
+        for j in range(len(r)):
             elo, ehi = _exact_piece_box(tv[i], k, pb[j, k], pb[j, 3 + k])
             assert (pb[j, :3] <= elo + 1e-12 * scale).all() and (pb[j, 3:] >= ehi - 1e-12 * scale).all()
             assert (elo - pb[j, :3] <= 2.0 ** -18 * scale).all() and (pb[j, 3:] - ehi <= 2.0 ** -18 * scale).all()
@@ -203,12 +204,15 @@ def test_leaf_split_keeps_every_closest_hit(orc):
     finds the same closest hits as the tree over whole triangles, bit for bit."""
     v, a = synth.random_triangles(600, seed=21, size=1.2)
     o, d = _random_rays(3000, seed=22)
-    s1 = orc.OracleScene(synth.Scene(v, a), leaf_split=1)
     s0 = orc.OracleScene(synth.Scene(v, a), leaf_split=0)
-    h1, t1 = orc.closest_hit(s1, o, d)
     h0, t0 = orc.closest_hit(s0, o, d)
-    assert s1.leaf_refs()[0][-1] > s0.leaf_refs()[0][-1]
-    assert np.array_equal(h1, h0) and np.array_equal(t1.view(np.uint32), t0.view(np.uint32))
+    counts = [s0.leaf_refs()[0][-1]]
+    for split in (1, 2, 3):
+        s1 = orc.OracleScene(synth.Scene(v, a), leaf_split=split)
+        h1, t1 = orc.closest_hit(s1, o, d)
+        counts.append(s1.leaf_refs()[0][-1])
+        assert np.array_equal(h1, h0) and np.array_equal(t1.view(np.uint32), t0.view(np.uint32))
+    assert counts == sorted(counts) and counts[0] < counts[1]
 
 
 def _random_rays(n, seed, spread=5.0):
