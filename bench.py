@@ -545,11 +545,11 @@ def main():
 
     batched = None
     if args.batched_sessions > 0:
-        batched = batched_leg(args.batched_sessions, args.batched_steps, 2, log)
+        batched = batched_leg(args.batched_sessions, args.batched_steps, 2, log, leaf_split=split["chosen"])
 
     serving = None
     if args.serving_sessions > 0:
-        serving = serving_leg(args.serving_sessions, args.serving_seconds, log)
+        serving = serving_leg(args.serving_sessions, args.serving_seconds, log, leaf_split=split["chosen"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -721,17 +721,19 @@ def uhd_leg(args, log):
     return out
 
 
-def batched_leg(n_sessions, steps, warmup, log):
+def batched_leg(n_sessions, steps, warmup, log, leaf_split=None):
     """Frames/s of n sessions rendered per step as per-session launches, as
     one batched launch per stage, and as a graph replay of the batched run.
-    G-buffers are rendered before each step, outside the timed region."""
+    G-buffers are rendered before each step, outside the timed region.  The
+    sessions' scenes (the 1080p scene's family) use the BVH leaf split level
+    chosen on the 1080p workload."""
     import numpy as np
     import torch
 
     from paper_2210_06158_amd import dof, sessions, synth
 
     specs = synth.session_specs(n_sessions)
-    ss = [sessions.Session.from_spec(sp, m=8) for sp in specs]
+    ss = [sessions.Session.from_spec(sp, m=8, leaf_split=leaf_split) for sp in specs]
     torch.cuda.synchronize()
     px = sum(s.W * s.H for s in ss)
     tris = sum(s.ntri for s in ss)
@@ -825,6 +827,7 @@ def batched_leg(n_sessions, steps, warmup, log):
         "resolutions": res,
         "megapixels_per_step": round(px / 1e6, 2),
         "triangles": tris,
+        "leaf_split": leaf_split,
         "steps": steps,
         "rays_per_step": round(r_batch / steps, 1),
         "per_session_launches_frames_per_s": round(fps["single"], 2),
@@ -845,15 +848,16 @@ def batched_leg(n_sessions, steps, warmup, log):
     return out
 
 
-def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
+def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200, leaf_split=None):
     """Continuous batching vs one frame at a time on the same Poisson request
-    stream (sessions admitted under an HBM budget)."""
+    stream (sessions admitted under an HBM budget; their scenes use the BVH
+    leaf split level chosen on the 1080p workload)."""
     import torch
 
     from paper_2210_06158_amd import serve, synth
 
     params = synth.Params(m=8)
-    srv = serve.Server(budget_gib << 30, params, max_batch=32, max_inflight=2, ring=4)
+    srv = serve.Server(budget_gib << 30, params, max_batch=32, max_inflight=2, ring=4, leaf_split=leaf_split)
     specs = serve.serving_specs(n_sessions)
     admitted = sum(srv.admit(sp) for sp in specs)
     torch.cuda.synchronize()
@@ -892,6 +896,7 @@ def serving_leg(n_sessions, seconds, log, rate_hz=60.0, budget_gib=200):
                     f"Poisson requests at {rate_hz:g} Hz per session for {seconds:g} s, m=8, newest request of a "
                     "session supersedes a waiting one",
         "sessions_admitted": admitted,
+        "leaf_split": leaf_split,
         "resident_gib": round(srv.used / 2**30, 2),
         "budget_gib": budget_gib,
         "resolutions": res,

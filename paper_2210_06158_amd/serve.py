@@ -22,6 +22,7 @@ clock at the start of the run.
 
 from __future__ import annotations
 
+import dataclasses
 import math
 import time
 
@@ -85,10 +86,11 @@ class RingSession(sessions.Session):
 
 class Server:
     def __init__(self, budget_bytes: int, params, max_batch: int = 32, max_inflight: int = 2, ring: int = 4,
-                 device="cuda"):
+                 device="cuda", leaf_split=None):
         import torch
         self.torch = torch
         self.budget = budget_bytes
+        self.leaf_split = leaf_split      # BVH leaf split level of the sessions' scenes (None: the scene's own)
         self.params = params
         self.max_batch = max_batch
         self.max_inflight = max_inflight
@@ -104,6 +106,8 @@ class Server:
         """Create a resident session if its bytes fit the budget."""
         _, w, h, ns, nb = spec
         scene, cams, lens, _ = synth.scene_session(spec)
+        if self.leaf_split is not None:
+            scene = dataclasses.replace(scene, leaf_split=self.leaf_split)
         need = sessions.resident_bytes(dof.scene_bytes_for(scene), w, h, self.params) + (self.ring - 1) * w * h * 20
         if self.used + need > self.budget:
             self.rejected += 1

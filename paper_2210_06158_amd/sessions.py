@@ -44,9 +44,11 @@ class Session:
         assert px > 0
 
     @classmethod
-    def from_spec(cls, spec, m=8, device="cuda"):
+    def from_spec(cls, spec, m=8, device="cuda", leaf_split=None):
         scene, cams, lens, params = synth.scene_session(spec)
         params.m = m
+        if leaf_split is not None:
+            scene = dataclasses.replace(scene, leaf_split=leaf_split)
         return cls(scene, cams, lens, params, device=device)
 
     def cam(self, k):
