@@ -101,9 +101,9 @@ def stage_bytes(stage, W, H, P, R):
         # depth+normal in, history validity + variance (8 B) at the reprojected texel; prev index + count out
         "mask": h * 16 + h * 8 + h * 4 + h * 1,
         # counts in, queue and ray offsets per masked px and the ray -> pixel map out; then the ray
-        # generation: pixel, queue entry and offset of each ray in, its 48-byte record out
-        "compact": 2 * h + P * 8 + R * 4 + R * (12 + 48),
-        "trace": R * (48 + 8),                      # ray record in; (leaf, t) out
+        # generation: pixel, queue entry and offset of each ray in, its 24-byte record out
+        "compact": 2 * h + P * 8 + R * 4 + R * (12 + 24),
+        "trace": R * (24 + 8),                      # ray record in; (leaf, t) out
         # one pass: (leaf, t), origin and direction of each ray in (the per-ray hit, t, colour and
         # position planes are off in measured runs); queue entry, ray offset, count in and 4 planes
         # out per masked px

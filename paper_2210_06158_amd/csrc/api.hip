@@ -185,7 +185,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa, int ray_records)
     L.queue = take(4 * np);
     L.ray_base = take(4 * np);
     L.ray_pix = take(4 * nr);
-    L.ray_rec = take(48 * nr);   // three float4 planes of nr
+    L.ray_rec = take(24 * nr);   // a float4 and a float2 plane of nr
     L.ray_lt = take(8 * nr);
     if (ray_records) {   // per-ray hit id, distance, colour and position, for inspection only
         L.ray_hit = take(4 * nr);

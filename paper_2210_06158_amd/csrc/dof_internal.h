@@ -135,7 +135,8 @@ struct Planes {
     int32_t *ray_hit;        // per-ray planes: nullptr unless params.ray_records
     float *ray_t;
     float4 *ray_col, *ray_pos;
-    float4 *rec0, *rec1, *rec2;   // ray records: (o, d.x), (d.y, d.z, sx, sy), (sz, 1/d) per ray
+    float4 *rec0;                 // ray records: (o, d.x) per ray
+    float2 *rec1;                 //              (d.y, d.z) per ray
     uint2 *ray_lt;                // traversal result per ray: (leaf of the hit or ~0, t bits)
     float4 *R0, *R1, *R2, *R3, *T0, *T1, *rtmed, *mips, *recon;
     float *var_blur;

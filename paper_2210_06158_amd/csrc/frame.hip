@@ -187,8 +187,7 @@ Planes planes(const FrameConst &fc, const ScratchLayout &L, char *s)
     p.ray_pos = rec ? reinterpret_cast<float4 *>(s + L.ray_pos) : nullptr;
     const size_t nr = np * (size_t)fc.m;
     p.rec0 = reinterpret_cast<float4 *>(s + L.ray_rec);
-    p.rec1 = p.rec0 + nr;
-    p.rec2 = p.rec1 + nr;
+    p.rec1 = reinterpret_cast<float2 *>(p.rec0 + nr);
     p.ray_lt = reinterpret_cast<uint2 *>(s + L.ray_lt);
     float4 *res = reinterpret_cast<float4 *>(s + L.resolve);
     p.R0 = res; p.R1 = res + np; p.R2 = res + 2 * np; p.R3 = res + 3 * np;

@@ -313,26 +313,23 @@ __device__ inline void lens_shade(const SceneArgs &S, const FrameConst &fc, cons
 // Ray records (three float4 planes): (o, d.x), (d.y, d.z, sx, sy),
 // (sz, 1/d.x, 1/d.y, 1/d.z), written by the ray generation kernel so that a
 // traversal lane takes a new ray with three independent loads.
-__device__ inline void put_ray(float4 *rec0, float4 *rec1, float4 *rec2, uint32_t r, const float o[3],
-                               const float d[3])
+// A ray record is its origin and direction (24 B: a float4 and a float2
+// plane); the traversal derives the watertight shear and the reciprocals when
+// a lane takes the ray (six correctly rounded divides, shared by the lanes a
+// refill starts), which costs less than moving them through memory.
+__device__ inline void put_ray(float4 *rec0, float2 *rec1, uint32_t r, const float o[3], const float d[3])
 {
-    const WRay w = make_wray(o, d);
     rec0[r] = make_float4(o[0], o[1], o[2], d[0]);
-    rec1[r] = make_float4(d[1], d[2], w.sx, w.sy);
-    rec2[r] = make_float4(w.sz, w.ix, w.iy, w.iz);
+    rec1[r] = make_float2(d[1], d[2]);
 }
 
-__device__ inline void get_ray(const float4 *rec0, const float4 *rec1, const float4 *rec2, uint32_t r, float o[3],
-                               float d[3], WRay &w)
+__device__ inline void get_ray(const float4 *rec0, const float2 *rec1, uint32_t r, float o[3], float d[3], WRay &w)
 {
-    const float4 a = rec0[r], b = rec1[r], c = rec2[r];
+    const float4 a = rec0[r];
+    const float2 b = rec1[r];
     o[0] = a.x; o[1] = a.y; o[2] = a.z;
     d[0] = a.w; d[1] = b.x; d[2] = b.y;
-    w.o0 = a.x; w.o1 = a.y; w.o2 = a.z;
-    wray_axes(d, w.kx, w.ky, w.kz);
-    w.sx = b.z; w.sy = b.w; w.sz = c.x;
-    w.ix = c.y; w.iy = c.z; w.iz = c.w;
-    slab_offsets(w);
+    w = make_wray(o, d);
 }
 
 // The traversal's result of a lens ray: leaf of the closest hit (~0u: none)
@@ -347,7 +344,8 @@ __device__ inline void put_lt(uint2 *lt, uint32_t r, const Hit &h)
 __device__ inline void ray_of(const SceneArgs &S, const Planes &P, uint32_t r, float o[3], float d[3], Hit &h)
 {
     const uint2 lt = P.ray_lt[r];
-    const float4 a = P.rec0[r], b = P.rec1[r];
+    const float4 a = P.rec0[r];
+    const float2 b = P.rec1[r];
     o[0] = a.x; o[1] = a.y; o[2] = a.z;
     d[0] = a.w; d[1] = b.x; d[2] = b.y;
     h.t = __uint_as_float(lt.y);
@@ -357,10 +355,11 @@ __device__ inline void ray_of(const SceneArgs &S, const Planes &P, uint32_t r, f
 
 struct LensRays {
     static constexpr bool kPerLaneScene = false;
-    const float4 *rec0, *rec1, *rec2;
+    const float4 *rec0;
+    const float2 *rec1;
     uint2 *ray_lt;
 
-    __device__ void start(uint32_t r, float o[3], float d[3], WRay &w) const { get_ray(rec0, rec1, rec2, r, o, d, w); }
+    __device__ void start(uint32_t r, float o[3], float d[3], WRay &w) const { get_ray(rec0, rec1, r, o, d, w); }
 
     __device__ void finish(const SceneArgs &, uint32_t r, const float *, const float *, const Hit &h) const
     {
@@ -407,7 +406,7 @@ struct BatchRays {
     __device__ void start(uint32_t r, int j, float o[3], float d[3], WRay &w) const
     {
         const Job &J = jobs[j];
-        get_ray(J.P.rec0, J.P.rec1, J.P.rec2, r - offsets()[j], o, d, w);
+        get_ray(J.P.rec0, J.P.rec1, r - offsets()[j], o, d, w);
     }
 
     __device__ void finish(const SceneArgs &, uint32_t r, int j, const float *, const float *, const Hit &h) const
@@ -547,13 +546,13 @@ constexpr int kGenMaxBlocks = 2048;
 // Every thin-lens ray of a frame (the count is the compaction's ray total).
 __global__ __launch_bounds__(kGenTB) void k_raygen(FrameConst fc, const uint32_t *queue, const uint32_t *ray_base,
                                                    const uint32_t *ray_pix, const uint32_t *count, float4 *rec0,
-                                                   float4 *rec1, float4 *rec2)
+                                                   float2 *rec1)
 {
     const uint32_t N = *count;
     for (uint32_t r = blockIdx.x * kGenTB + threadIdx.x; r < N; r += gridDim.x * kGenTB) {
         float o[3], d[3];
         lens_ray(fc, queue, ray_base, ray_pix, r, o, d);
-        put_ray(rec0, rec1, rec2, r, o, d);
+        put_ray(rec0, rec1, r, o, d);
     }
 }
 
@@ -576,7 +575,7 @@ __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs
         const uint32_t k = r - off[lo];
         float o[3], d[3];
         lens_ray(J.fc, J.P.queue, J.P.ray_base, J.P.ray_pix, k, o, d);
-        put_ray(J.P.rec0, J.P.rec1, J.P.rec2, k, o, d);
+        put_ray(J.P.rec0, J.P.rec1, k, o, d);
     }
 }
 
@@ -870,7 +869,6 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     const Planes P = planes(fc, L, scratch);
     src.rec0 = P.rec0;
     src.rec1 = P.rec1;
-    src.rec2 = P.rec2;
     src.ray_lt = P.ray_lt;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
     with_stack<LensRays>(fc.tk.stack, [&](auto kern) {
@@ -886,7 +884,7 @@ hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scr
     const Planes P = planes(fc, L, scratch);
     const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
     k_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix, P.counters + kCntRays, P.rec0,
-                                                       P.rec1, P.rec2);
+                                                       P.rec1);
     return hipGetLastError();
 }
 
