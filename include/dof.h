@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define DOF_ABI_VERSION 4
+#define DOF_ABI_VERSION 5
 
 typedef int32_t dof_status;
 #define DOF_OK 0
@@ -143,12 +143,18 @@ typedef struct {
      * trace_grab: rays a wave takes from the shared work counter at a time,
      * 1..256 (default 64).  trace_refill: idle lanes at which a wave takes
      * new rays, 1..64 (default 16).  trace_leaf_batch: lanes with a pending
-     * leaf at which a wave runs its triangle tests, 1..64 (default 32). */
+     * leaf at which a wave runs its triangle tests, 1..64 (default 32).
+     * trace_order: the order in which the persistent traversal hands out the
+     * rays of the queue (row-major pixels): 1 from the first ray, 2 (and the
+     * default 0) from the last -- the bottom image rows first, which in
+     * ground-level views holds the near foreground whose rays cost most, so
+     * cheap sky and background rays fill the kernel's tail. */
     int32_t gather_window;
     int32_t trace_stack;
     int32_t trace_grab;
     int32_t trace_refill;
     int32_t trace_leaf_batch;
+    int32_t trace_order;
 } dof_params;
 
 /* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view

@@ -366,6 +366,7 @@ dof_status params_check(const dof_params *p)
     if (p->trace_grab < 0 || p->trace_grab > 256 || p->trace_refill < 0 || p->trace_refill > 64 ||
         p->trace_leaf_batch < 0 || p->trace_leaf_batch > 64)
         return fail(DOF_E_INVALID, "trace_grab must be in 0..256, trace_refill and trace_leaf_batch in 0..64");
+    if (p->trace_order < 0 || p->trace_order > 2) return fail(DOF_E_INVALID, "trace_order must be 0, 1 or 2");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
@@ -381,6 +382,7 @@ dof::TraceKnobs trace_knobs(const dof_params &p)
     k.grab = p.trace_grab ? (uint32_t)p.trace_grab : 64u;
     k.refill = p.trace_refill ? p.trace_refill : 16;
     k.leaf_batch = p.trace_leaf_batch ? p.trace_leaf_batch : 32;
+    k.reverse = p.trace_order == 1 ? 0 : 1;
     return k;
 }
 

@@ -94,6 +94,7 @@ struct TraceKnobs {
     uint32_t grab;        // rays per take from the shared work counter
     int32_t refill;       // idle lanes that trigger a refill
     int32_t leaf_batch;   // lanes with a pending leaf that trigger the triangle tests
+    int32_t reverse;      // 1: rays handed out from the end of the queue
 };
 
 struct FrameConst {

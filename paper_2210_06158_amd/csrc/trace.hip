@@ -633,7 +633,10 @@ constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS st
 // least tk.refill lanes are idle [16], takes tk.grab rays from the shared
 // work counter at a time [64], and runs its triangle tests when at least
 // tk.leaf_batch lanes have one pending [32]; kStack LDS stack entries per
-// lane [24].
+// lane [24]; tk.reverse hands the rays out from the end of the queue [for
+// frames; the scene-level sources keep the queue order].  The last rays a
+// persistent grid hands out set its tail: when they are cheap, every wave
+// finishes at nearly the same time.
 
 template <class Src, int kStack>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
@@ -689,6 +692,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             if (!active && !exhausted) {
                 item = pool + rank;
                 if (rank < avail) {
+                    if (tk.reverse) item = N - 1u - item;   // pool + rank < N
                     if constexpr (Src::kPerLaneScene) {
                         job = src.job_of(item);
                         Sl = src.scene(job);

@@ -42,10 +42,10 @@ class DofParams(C.Structure):
                 ("mask_mode", C.c_int32), ("trace_blocks", C.c_int32), ("timing", C.c_int32),
                 ("pp_polygon", C.c_int32), ("taa", C.c_int32), ("ray_records", C.c_int32), ("composite_literal", C.c_int32),
                 ("gather_window", C.c_int32), ("trace_stack", C.c_int32), ("trace_grab", C.c_int32),
-                ("trace_refill", C.c_int32), ("trace_leaf_batch", C.c_int32)]
+                ("trace_refill", C.c_int32), ("trace_leaf_batch", C.c_int32), ("trace_order", C.c_int32)]
 
 # launch-shape knobs of dof_params (0 = library default), set from a dict
-KNOBS = ("gather_window", "trace_stack", "trace_grab", "trace_refill", "trace_leaf_batch")
+KNOBS = ("gather_window", "trace_stack", "trace_grab", "trace_refill", "trace_leaf_batch", "trace_order")
 
 
 class DofGBuffer(C.Structure):
@@ -154,7 +154,7 @@ def lib():
             if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
                             "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
-        if L.dof_abi_version() != 4:
+        if L.dof_abi_version() != 5:
             raise ImportError("libdof ABI version mismatch")
         _lib = L
     return _lib

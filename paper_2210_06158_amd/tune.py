@@ -15,7 +15,10 @@ Searched per workload, by HIP-event time of the same sample of frames:
 * trace_leaf_batch -- lanes with a pending leaf at which a wave runs its
   triangle tests;
 * gather_window -- the LDS window of the post-process gather's staged tiles
-  (32, 40, 48 texels, or -1: every tap from global memory).
+  (32, 40, 48 texels, or -1: every tap from global memory);
+* trace_order -- rays handed out from the end of the queue (2: bottom image
+  rows first) or from its start (1); the last rays handed out set the
+  persistent grid's tail.
 
 The search is coordinate descent from the library defaults: one knob at a
 time over its candidates with the others held, keeping the fastest.
@@ -30,9 +33,10 @@ KNOB_SPACE = {
     "trace_refill": (8, 16, 24),
     "trace_leaf_batch": (16, 24, 32, 40),
     "gather_window": (-1, 32, 40, 48),
+    "trace_order": (2, 1),
 }
 DEFAULTS = {"trace_blocks": 0, "trace_stack": 24, "trace_grab": 64, "trace_refill": 16, "trace_leaf_batch": 32,
-            "gather_window": -1}
+            "gather_window": -1, "trace_order": 2}
 
 
 def candidate_blocks(extra=()):

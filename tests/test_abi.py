@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(dof):
 
 def test_abi_version_and_defaults(dof):
     L = dof.lib()
-    assert L.dof_abi_version() == 4
+    assert L.dof_abi_version() == 5
     assert C.sizeof(dof.DofCamera) == 16 * 4 + 2 * 4   # basis, size, counters, jitter
     p = dof.DofParams()
     L.dof_default_params(C.byref(p))
@@ -251,9 +251,9 @@ def test_launch_knob_ranges(dof):
     L = dof.lib()
     b = C.c_size_t()
     ok = {"gather_window": (0, -1, 32, 40, 48), "trace_stack": (0, 16, 24, 32), "trace_grab": (0, 1, 256),
-          "trace_refill": (0, 1, 64), "trace_leaf_batch": (0, 1, 64)}
+          "trace_refill": (0, 1, 64), "trace_leaf_batch": (0, 1, 64), "trace_order": (0, 1, 2)}
     bad = {"gather_window": (16, 64, -2), "trace_stack": (8, 48), "trace_grab": (-1, 257), "trace_refill": (65,),
-           "trace_leaf_batch": (-3, 65)}
+           "trace_leaf_batch": (-3, 65), "trace_order": (-1, 3)}
     for k, vals in ok.items():
         for v in vals:
             p = dof.DofParams()
