@@ -471,3 +471,35 @@ def random_triangles(n: int, seed: int, spread: float = 4.0, size: float = 0.6):
     v = (c + off).reshape(n, 9).astype(np.float32)
     alb = rng.uniform(n * 3).reshape(n, 3).astype(np.float32)
     return v, alb
+
+
+def awkward_triangles(seed: int):
+    """Thin triangles at awkward places for the leaf split and the traversal:
+    three coordinate scales (1, 1e3, 3e6), a vertex exactly on a quarter plane
+    of its box, equal x and y extents (a tie for the longest axis), and
+    degenerate triangles (collinear, repeated vertices).  Returns (v, albedo,
+    rays' origins, rays' directions): 20000 rays aimed near the centroids."""
+    rng = SplitMix64(seed)
+    tris = []
+    for s in (1.0, 1e3, 3e6):
+        for _ in range(40):
+            c = rng.uniform(3, -2 * s, 2 * s)
+            d = rng.uniform(3, -s, s)
+            w = rng.uniform(3, -0.01 * s, 0.01 * s)
+            tris.append([*c, *(c + d), *(c + d + w)])
+    tris.append([0, 0, 0, 2, 0.01, 0, 8, 0.02, 0.01])
+    tris.append([0, 0, 0, 4, 4, 0.01, 4.02, 4, 0])
+    tris.append([0, 0, 5, 1, 1, 6, 2, 2, 7])
+    tris.append([1, 1, 1, 1, 1, 1, 3, 0, 0])
+    v = np.array(tris, np.float32)
+    n = v.shape[0]
+    nr = 20000
+    tv = v.reshape(n, 3, 3).astype(np.float64)
+    pick = (rng.next_u64(nr) % np.uint64(n)).astype(np.int64)
+    bary = rng.uniform(3 * nr, 0.05, 1.0).reshape(nr, 3)
+    bary /= bary.sum(1, keepdims=True)
+    tgt = np.einsum("rk,rkc->rc", bary, tv[pick])
+    scale = np.abs(tv[pick]).max((1, 2)).clip(1.0, None)[:, None]
+    o = tgt + rng.uniform(3 * nr, -1, 1).reshape(nr, 3) * scale
+    d = tgt - o
+    return v, np.ones((n, 3), np.float32), o.astype(np.float32), d.astype(np.float32)

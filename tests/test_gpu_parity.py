@@ -576,3 +576,38 @@ def test_single_frame_graph_replays(env, orc):
         assert torch.isfinite(junk)
         assert torch.equal(fr.colour, ref.colour), rep
         assert torch.equal(fr.mask, ref.mask) and torch.equal(hout, ref_h), rep
+
+
+@pytest.mark.parametrize("split", [1, 2, 3])
+def test_leaf_split_edge_cases(env, orc, split):
+    """Reference boxes, keys and tree bit for bit and every closest hit equal
+    to brute force on the awkward soup, at each split level."""
+    torch, dof = env["torch"], env["dof"]
+    v, a, o, d = synth.awkward_triangles(4242)
+    sc = synth.Scene(v, a, leaf_split=split)
+    osc = orc.OracleScene(sc)
+    ob = osc.build_bvh()
+    gs = dof.Scene(sc)
+    gs.build_bvh()
+    torch.cuda.synchronize()
+    view = gs.bvh_view()
+    nl = view["nleaf"]
+    assert nl == ob["refs"].size and nl > v.shape[0]
+    assert np.array_equal(view["keys"].cpu().numpy().view(np.uint64), ob["keys"])
+    assert np.array_equal(view["ids"].cpu().numpy().view(np.uint32), ob["refs"])
+    nodes = view["nodes"].cpu().numpy().reshape(nl - 1, 16)
+    nu = nodes.view(np.uint32)
+    assert np.array_equal(nu[:, 12], ob["left"][:nl - 1]) and np.array_equal(nu[:, 13], ob["right"][:nl - 1])
+    lb = np.stack([nodes[:, 0], nodes[:, 2], nodes[:, 8], nodes[:, 1], nodes[:, 3], nodes[:, 9]], 1)
+    rb = np.stack([nodes[:, 4], nodes[:, 6], nodes[:, 10], nodes[:, 5], nodes[:, 7], nodes[:, 11]], 1)
+    for ch, got in ((ob["left"], lb), (ob["right"], rb)):
+        ch = ch[:nl - 1].astype(np.int64)
+        leaf = (ch & 0x80000000) != 0
+        want = np.where(leaf[:, None], ob["leaf_bounds"][np.where(leaf, ch & 0x7FFFFFFF, 0)],
+                        ob["bounds"][np.where(leaf, 0, ch)]).astype(np.float32)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
+    ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
+    assert (ho >= 0).mean() > 0.3
+    assert np.array_equal(hg.cpu().numpy(), ho)
+    assert np.array_equal(tg.cpu().numpy().view(np.uint32), to.view(np.uint32))

@@ -215,6 +215,25 @@ def test_leaf_split_keeps_every_closest_hit(orc):
     assert counts == sorted(counts) and counts[0] < counts[1]
 
 
+
+@pytest.mark.parametrize("split", [0, 1, 2, 3])
+def test_leaf_split_awkward_soup_equals_brute_force(orc, split):
+    """Thin triangles at three coordinate scales up to 3e6, a vertex on a
+    slab plane, a tie for the longest axis and degenerate triangles: every
+    reference box holds its piece of the triangle and the tree's closest hits
+    equal brute force over the triangles, bit for bit."""
+    v, a, o, d = synth.awkward_triangles(4242)
+    sc = orc.OracleScene(synth.Scene(v, a), leaf_split=split)
+    off, boxes, tri = sc.leaf_refs()
+    assert len(tri) == off[-1] and (split == 0) == (len(tri) == v.shape[0])
+    tv = v.reshape(-1, 3, 3).astype(np.float64)
+    lo, hi = tv.min(1), tv.max(1)
+    assert np.all(boxes[:, :3] >= lo[tri]) and np.all(boxes[:, 3:] <= hi[tri])
+    hb, tb = orc.closest_hit(sc, o, d, use_bvh=True)
+    hf, tf = orc.closest_hit(sc, o, d, use_bvh=False)
+    assert (hf >= 0).mean() > 0.3
+    assert np.array_equal(hb, hf) and np.array_equal(tb.view(np.uint32), tf.view(np.uint32))
+
 def _random_rays(n, seed, spread=5.0):
     rng = synth.SplitMix64(seed)
     o = rng.uniform(3 * n, -spread, spread).reshape(n, 3)
