@@ -295,12 +295,13 @@ def shots_leg(gs, scene, cams, lens, params, cfg, main, log):
 
 def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, cfg, log, latency_passes=0):
     """Render steps frames of a camera path (after warmup frames) with one
-    dof_render_frame each, history ping-pong.  Then the same frames again
-    (the histories restored to their state before the timed frames) with
+    dof_render_frame each, history ping-pong, timed as a whole.  Then
+    latency_passes full passes over the path, continuing the history chain,
+    each frame bracketed by its own events (frame-time percentiles).  Then
+    the timed frames twice more, the histories restored to their state before
+    them: each frame bracketed by its own events (per-frame spans), and with
     per-stage HIP events, so the per-stage figures describe the timed
-    workload; their ray counts must equal the timed frames' one by one.
-    Then latency_passes full passes over the path, continuing the history
-    chain, each frame bracketed by its own events (frame-time percentiles).
+    workload; both replays must trace the timed frames' rays one by one.
     Returns timing and counter totals."""
     import numpy as np
     import torch
@@ -312,34 +313,30 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, cfg, lo
     hist = [dof.history_alloc(W, H), dof.history_alloc(W, H)]
     fr = frame_for(W, H, params, cfg)
 
-    def step(i, frame):
+    def step(i, frame, stats=None):
         f = i % nfr
         prev = cams[f - 1] if f > 0 else None
         frame.render(gs, cams[f], lenses[f], gbs[f], hist[(i + 1) % 2] if prev is not None else None, hist[i % 2],
-                     prev_cam=prev, prev_lens=lenses[f - 1] if f > 0 else None)
+                     prev_cam=prev, prev_lens=lenses[f - 1] if f > 0 else None, stats=stats)
 
     for i in range(warmup):
         step(i, fr)
     torch.cuda.synchronize()
     snap = [h.clone() for h in hist]
     K = steps
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    # the timed frames back to back: each writes its counters straight into
+    # its own stats record, and no event or copy sits between frames
     stats = torch.zeros((K, 8), dtype=torch.int32, device="cuda")
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
     for k in range(K):
-        starts[k].record()
-        step(warmup + k, fr)
-        ends[k].record()
-        stats[k].copy_(fr.stats, non_blocking=True)
+        step(warmup + k, fr, stats[k])
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
-    frame_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     st = stats.cpu().numpy()
     st64 = st.view(np.int64)
     log(f"timed {K} frames of {W}x{H}: {total_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
@@ -356,6 +353,21 @@ def run_path(gs, cams, lenses, params, gbs, steps, warmup, stage_frames, cfg, lo
             le[k].record()
         torch.cuda.synchronize()
         lat = np.array([a.elapsed_time(b) for a, b in zip(ls, le)])
+
+    # per-frame spans of the timed frames: the same frames again, histories as
+    # before the timed loop, each bracketed by its own events
+    for h, sh in zip(hist, snap):
+        h.copy_(sh)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    rstats = torch.zeros((K, 8), dtype=torch.int32, device="cuda")
+    for k in range(K):
+        starts[k].record()
+        step(warmup + k, fr, rstats[k])
+        ends[k].record()
+    torch.cuda.synchronize()
+    frame_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    assert np.array_equal(rstats.cpu().numpy()[:, :2], st[:, :2]), "per-frame replay traced other rays"
 
     # per-stage timing of the same frames: histories as before the timed loop
     for h, sh in zip(hist, snap):

@@ -1412,6 +1412,11 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
 
 __global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
 {
+    // The frame's counters are final once the traversal has run: the first
+    // block copies them into the caller's stats record (masked px, rays, node
+    // visits, triangle tests, stack overflows: seven 32-bit words).
+    if (out.stats && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.y == 0 && threadIdx.x < 7)
+        reinterpret_cast<uint32_t *>(out.stats)[threadIdx.x] = P.counters[threadIdx.x];
     b_composite(fc, P, gb, out, blockIdx.x, blockIdx.y);
 }
 
@@ -1689,12 +1694,6 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
     if (fc.taa & DOF_TAA_FINAL)
         k_taa_final<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out, out);
     DOF_REC(13);
-    if (out.stats) {
-        // the frame counters into the caller's stats record: masked px, rays,
-        // node visits, triangle tests, stack overflows
-        hipError_t e = hipMemcpyAsync(out.stats, scratch + L.counters, 28, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
-    }
     return hipGetLastError();
 }
 

@@ -346,8 +346,10 @@ class Frame:
         self.mask = torch.empty((H // 2, W // 2), dtype=torch.uint8, device=device)
         self.stats = torch.zeros(8, dtype=torch.int32, device=device)
 
-    def item(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False):
-        """The frame's arguments as one batch item (see Batch)."""
+    def item(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False,
+             stats=None):
+        """The frame's arguments as one batch item (see Batch).  stats: a device
+        int32 tensor of 8 elements for the frame's counters (default: self.stats)."""
         colour, depth, normal = gb
         cf = RGBA32F if colour.dtype == torch.float32 else RGBA16F
         nf = RGBA32F if normal.dtype == torch.float32 else RGBA16F
@@ -356,12 +358,16 @@ class Frame:
                            camera_struct(prev_cam if prev_cam is not None else cam),
                            lens_struct(prev_lens if prev_lens is not None else lens),
                            1 if (reset or hist_in is None or prev_cam is None) else 0)
-        out = DofFrameOut(_ptr(self.colour), self.out_format, _ptr(self.mask), _ptr(self.stats))
+        if stats is None:
+            stats = self.stats
+        assert stats.dtype == torch.int32 and stats.numel() == 8 and stats.is_contiguous()
+        out = DofFrameOut(_ptr(self.colour), self.out_format, _ptr(self.mask), _ptr(stats))
         return DofBatchItem(scene.handle, camera_struct(cam), lens_struct(lens), g, hio, out, _ptr(self.scratch),
                             self.nbytes)
 
-    def render(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False):
-        it = self.item(scene, cam, lens, gb, hist_in, hist_out, prev_cam, prev_lens, reset)
+    def render(self, scene: Scene, cam, lens, gb, hist_in, hist_out, prev_cam=None, prev_lens=None, reset=False,
+               stats=None):
+        it = self.item(scene, cam, lens, gb, hist_in, hist_out, prev_cam, prev_lens, reset, stats)
         check(lib().dof_render_frame(it.scene, C.byref(it.camera), C.byref(it.lens), C.byref(it.gbuffer),
                                      C.byref(it.history), C.byref(self.ps), C.byref(it.out), it.scratch,
                                      it.scratch_bytes, _stream()))
