@@ -1632,25 +1632,25 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     DOF_REC(1);
     k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
     DOF_REC(2);
-    hipStream_t pst = st;   // the post-process chain's stream
-    if (side) {
-        hipError_t e = hipEventRecord(side->fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
-        if (e != hipSuccess) return e;
-        pst = side->stream;
-    }
-    k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
-    DOF_REC(3);
-    launch_gather_pair(fc.gather_win, [&](auto w) {
-        k_gather<decltype(w)::value><<<dim3(fc.tw, fc.th), 256, 0, pst>>>(fc, rings, P);
-    });
-    DOF_REC(4);
-    k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
-    if (fc.taa & DOF_TAA_POST)
-        k_taa_post<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P, hist_in, hist_out);
-    if (side) {
-        const hipError_t e = hipEventRecord(side->join, pst);
-        if (e != hipSuccess) return e;
+    // The post-process chain reads only the reduce's and the dilation's planes
+    // and only the composite reads its result: with a side stream it is forked
+    // after the ray generation, so it shares the GPU with the traversal and not
+    // with the mask, compaction and generation that lead up to it.
+    auto chain = [&](hipStream_t pst) -> hipError_t {
+        k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
+        DOF_REC(3);
+        launch_gather_pair(fc.gather_win, [&](auto w) {
+            k_gather<decltype(w)::value><<<dim3(fc.tw, fc.th), 256, 0, pst>>>(fc, rings, P);
+        });
+        DOF_REC(4);
+        k_median_pp<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
+        if (fc.taa & DOF_TAA_POST)
+            k_taa_post<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P, hist_in, hist_out);
+        return hipSuccess;
+    };
+    if (!side) {
+        const hipError_t ec = chain(st);
+        if (ec != hipSuccess) return ec;
     }
     DOF_REC(5);
     if (fc.mask_mode == DOF_MASK_DILATE) {
@@ -1666,6 +1666,14 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     const hipError_t e = launch_raygen(fc, L, scratch, st);
     if (e != hipSuccess) return e;
     DOF_REC(7);
+    if (side) {
+        hipError_t e2 = hipEventRecord(side->fork, st);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(side->stream, side->fork, 0);
+        if (e2 != hipSuccess) return e2;
+        e2 = chain(side->stream);
+        if (e2 == hipSuccess) e2 = hipEventRecord(side->join, side->stream);
+        if (e2 != hipSuccess) return e2;
+    }
     return hipGetLastError();
 }
 
