@@ -21,7 +21,9 @@ Searched per workload, by HIP-event time of the same sample of frames:
   persistent grid's tail.
 
 The search is coordinate descent from the library defaults: one knob at a
-time over its candidates with the others held, keeping the fastest.
+time over its candidates with the others held, keeping the fastest unless the
+value already held is within `margin` (1 %) of it -- differences that small
+are run-to-run noise, and chasing them only makes the pick flip between runs.
 """
 
 from __future__ import annotations
@@ -45,7 +47,16 @@ def candidate_blocks(extra=()):
     return sorted({0, *(cus * k for k in (4, 6, 7, 8, 9, 10, 12)), *extra})
 
 
-def tune(run, candidates, reps: int = 3):
+def pick(times, incumbent=None, margin: float = 0.0):
+    """The fastest candidate of {candidate: ms}, or the incumbent when it is
+    within a relative margin of the fastest."""
+    best = min(times, key=times.get)
+    if incumbent in times and times[incumbent] <= times[best] * (1.0 + margin):
+        return incumbent
+    return best
+
+
+def tune(run, candidates, reps: int = 3, incumbent=None, margin: float = 0.0):
     """run(candidate) renders a fixed sample of work (same every call);
     returns (best candidate, {candidate: median ms})."""
     import statistics
@@ -64,11 +75,10 @@ def tune(run, candidates, reps: int = 3):
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         times[c] = statistics.median(ms)
-    best = min(times, key=times.get)
-    return best, times
+    return pick(times, incumbent, margin), times
 
 
-def search(run, space=None, reps: int = 2, order=None):
+def search(run, space=None, reps: int = 2, order=None, margin: float = 0.01):
     """Coordinate descent over the knobs: run(config) renders the sample with
     config (a dict with every knob of `space`).  Returns (best config,
     {knob: {value: ms}})."""
@@ -78,7 +88,8 @@ def search(run, space=None, reps: int = 2, order=None):
     cfg = {k: DEFAULTS[k] for k in space}
     table = {}
     for knob in order or list(space):
-        best, times = tune(lambda v: run({**cfg, knob: v}), space[knob], reps=reps)
+        best, times = tune(lambda v: run({**cfg, knob: v}), space[knob], reps=reps, incumbent=cfg[knob],
+                           margin=margin)
         cfg[knob] = best
         table[knob] = times
     return cfg, table

@@ -118,3 +118,13 @@ def test_committed_traffic_summary_parses():
     for k in ("source_sha256", "fetch_kib_per_launch", "write_kib_per_launch", "fetch_scale", "write_scale"):
         assert k in kv
     assert all(math.isfinite(float(kv[k])) for k in ("fetch_kib_per_launch", "write_kib_per_launch"))
+
+
+def test_tuner_keeps_the_incumbent_within_its_margin():
+    from paper_2210_06158_amd import tune
+    times = {16: 10.0, 24: 9.95, 32: 10.4}
+    assert tune.pick(times) == 24                              # the fastest
+    assert tune.pick(times, incumbent=16, margin=0.01) == 16   # 0.5 % slower: kept
+    assert tune.pick(times, incumbent=32, margin=0.01) == 24   # 4.5 % slower: replaced
+    assert tune.pick(times, incumbent=40, margin=0.01) == 24   # not a candidate
+    assert tune.pick({1: 5.0}, incumbent=1, margin=0.0) == 1
