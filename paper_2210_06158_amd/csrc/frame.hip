@@ -1231,6 +1231,12 @@ __device__ inline void mip_span(float lo, float hi, float sc, int n, int &a, int
     b = clampi((int)floorf((hi + 0.5f) * sc - 0.5f) + 1, 0, n - 1);
 }
 
+// Block of a frame's reconstruction: 16 x 16 pixels, whose square footprint
+// stages fewer halo texels than a 64 x 4 row block (batches keep the common
+// 64 x 4 pixel-kernel grid); the output does not depend on the shape.
+constexpr int kReconBX = 16, kReconBY = 16;
+
+template <int BX = kBX, int BY = kBY>
 __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const Planes &P, const uint32_t bx, const uint32_t by)
 {
     // The block's mip footprint: per level, the index box of every bilinear
@@ -1240,13 +1246,13 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
     __shared__ float4 tex[kReconLds];
     __shared__ int box[4][4];   // per level: first and last column, first and last row
     __shared__ int base[5];     // per level: first LDS texel; [4]: texels in all
-    const int tid = threadIdx.y * kBX + threadIdx.x;
+    const int tid = threadIdx.y * BX + threadIdx.x;
     if (tid < 4) {
         box[tid][0] = 0x7fffffff; box[tid][1] = -1;
         box[tid][2] = 0x7fffffff; box[tid][3] = -1;
     }
     __syncthreads();
-    const int x = bx * kBX + threadIdx.x, y = by * kBY + threadIdx.y;
+    const int x = bx * BX + threadIdx.x, y = by * BY + threadIdx.y;
     const int hw = fc.hw, hh = fc.hh;
     const bool in = x < hw && y < hh;
     const size_t i = in ? (size_t)y * hw + x : 0;
@@ -1293,7 +1299,7 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
             if (box[L][1] < box[L][0]) continue;
             const int bw = box[L][1] - box[L][0] + 1, cnt = bw * (box[L][3] - box[L][2] + 1);
             const float4 *src = P.mips + fc.moff[L];
-            for (int e = tid; e < cnt; e += kBX * kBY) {
+            for (int e = tid; e < cnt; e += BX * BY) {
                 const int r = e / bw, c = e - r * bw;
                 tex[base[L] + e] = src[(size_t)(box[L][2] + r) * fc.mw[L] + box[L][0] + c];
             }
@@ -1338,9 +1344,9 @@ __device__ inline void b_recon(const FrameConst &fc, const Rings &rings, const P
     P.recon[i] = make_float4(lerp1(med.x, nb0, bb), lerp1(med.y, nb1, bb), lerp1(med.z, nb2, bb), lerp1(hu, hnb, bb));
 }
 
-__global__ __launch_bounds__(kBX *kBY) void k_recon(FrameConst fc, Rings rings, Planes P)
+__global__ __launch_bounds__(kReconBX *kReconBY) void k_recon(FrameConst fc, Rings rings, Planes P)
 {
-    b_recon(fc, rings, P, blockIdx.x, blockIdx.y);
+    b_recon<kReconBX, kReconBY>(fc, rings, P, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kBX *kBY) void kb_recon(const Job *__restrict__ jobs, int njobs, Rings rings)
@@ -1692,7 +1698,7 @@ hipError_t launch_frame_post(const SceneDev &sd, const FrameConst &fc, const Rin
     DOF_REC(10);
     k_blur_median_mips<<<grid2(fc.hw, fc.hh, 8, 8), 64, 0, st>>>(fc, P, hist_out);
     DOF_REC(11);
-    k_recon<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, rings, P);
+    k_recon<<<grid2(fc.hw, fc.hh, kReconBX, kReconBY), dim3(kReconBX, kReconBY), 0, st>>>(fc, rings, P);
     DOF_REC(12);
     if (side) {
         const hipError_t e = hipStreamWaitEvent(st, side->join, 0);   // the post-process chain is done
