@@ -320,11 +320,11 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
  * ray generation, traversal, shading of the hits and resolve, temporal
  * accumulation, variance blur, median + mips, reconstruction, composite, and
  * the TAA stages params.taa selects.  Enqueued on `stream`, no host sync.
- * Unless params.timing is set, the post-process chain (prefilter, gather,
- * median) runs on a stream the scene owns (created with it, default
- * priority), forked from `stream` after the ray generation (it reads only
- * what the reduce and the tile dilation wrote) and joined back before the
- * composite with events, so it runs beside the traversal: the work stays
+ * Unless params.timing is set, the post-process chain (tile dilation but in
+ * the dilated mask mode, prefilter, gather, median) runs on a stream the
+ * scene owns (created with it, default priority), forked from `stream` after
+ * the ray generation (it reads only what the reduce wrote) and joined back
+ * before the composite with events, so it runs beside the traversal: the work stays
  * ordered on `stream` and a HIP graph capture of the call takes both
  * branches.  Frames of one scene
  * share that stream, so their post-process chains run one after another. */

@@ -349,11 +349,11 @@ hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, ui
                             int cfmt, int blocks, hipStream_t st);
 
 // frame.hip
-// The post-process chain (prefilter, gather, median, post-filter TAA) reads
-// only what the reduce and the tile dilation wrote, and only the composite
-// reads its result: with a side stream it runs there, forked after the ray
-// generation and joined before the composite, beside the traversal and the
-// ray-trace stages.
+// The post-process chain (tile dilation but in the dilated mask mode,
+// prefilter, gather, median, post-filter TAA) reads only what the reduce
+// wrote, and only the composite reads its result: with a side stream it runs
+// there, forked after the ray generation and joined before the composite,
+// beside the traversal and the ray-trace stages.
 struct SideStream {
     hipStream_t stream;
     hipEvent_t fork, join;   // recorded on the frame's stream / on the side stream

@@ -1636,13 +1636,17 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
         k_taa_raster<<<grid2(fc.W, fc.H, kBX, kBY), dim3(kBX, kBY), 0, st>>>(fc, P, gb, hist_in, hist_out);
     k_reduce<<<dim3(fc.tw, fc.th), dim3(kTile, kTile), 0, st>>>(fc, resolved_gbuffer(fc, P, gb), P);
     DOF_REC(1);
-    k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
+    // the dilated tile radii feed the prefilter and the gather, and the ray
+    // mask only in its dilated mode: otherwise the dilation heads the side chain
+    const bool dil_side = side && fc.mask_mode != DOF_MASK_DILATE;
+    if (!dil_side) k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, st>>>(fc, P);
     DOF_REC(2);
     // The post-process chain reads only the reduce's and the dilation's planes
     // and only the composite reads its result: with a side stream it is forked
     // after the ray generation, so it shares the GPU with the traversal and not
     // with the mask, compaction and generation that lead up to it.
     auto chain = [&](hipStream_t pst) -> hipError_t {
+        if (dil_side) k_dilate<<<grid2(fc.tw, fc.th, 16, 16), dim3(16, 16), 0, pst>>>(fc, P);
         k_prefilter<<<grid2(fc.hw, fc.hh, kBX, kBY), dim3(kBX, kBY), 0, pst>>>(fc, P);
         DOF_REC(3);
         launch_gather_pair(fc.gather_win, [&](auto w) {
