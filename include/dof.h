@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define DOF_ABI_VERSION 5
+#define DOF_ABI_VERSION 6
 
 typedef int32_t dof_status;
 #define DOF_OK 0
@@ -236,13 +236,19 @@ typedef struct dof_scene dof_scene;
  * 31 = leaf (sorted index), the node covering the sorted leaves
  * first..last; parent: 2 nleaf - 1 entries (internal nodes, then leaves),
  * root = ~0u; tris: 3 float4 per leaf in sorted order, the vertices of the
- * leaf's triangle (w of the first = triangle id bits). */
+ * leaf's triangle (w of the first = triangle id bits); nodes16: the copy of
+ * the nodes the traversal reads, nleaf-1 records of 32 B {uint32 L.x, L.y,
+ * L.z, R.x, R.y, R.z, left, right}, each box axis a binary16 pair (low plane
+ * in bits 0-15 rounded down, high plane in bits 16-31 rounded up; a result
+ * in the subnormal range moved outward to 0 or to 2^-14), so each box holds
+ * the binary32 one. */
 typedef struct {
     int32_t ntri;
     int32_t nleaf;
     const uint64_t *keys;
     const uint32_t *ids, *parent;
     const void *nodes, *tris;
+    const void *nodes16;
 } dof_bvh_view;
 
 /* Device pointers into a frame's scratch (valid after dof_render_frame);

@@ -64,7 +64,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct SceneLayout {
-    size_t verts_in, albedo_in, ref_off, ref_box, ref_tri, tris, albedo, nodes, parent, keys, keys_tmp, ids, ids_tmp;
+    size_t verts_in, albedo_in, ref_off, ref_box, ref_tri, tris, albedo, nodes, nodes16, parent, keys, keys_tmp, ids,
+        ids_tmp;
     size_t flags, hist, bounds, aux, total;
     int sort_blocks, bound_blocks;
 };
@@ -90,6 +91,7 @@ SceneLayout scene_layout(int64_t nt, int64_t n)
     L.tris = take(sizeof(float4) * 3 * n);
     L.albedo = take(sizeof(float4) * n);
     L.nodes = take(sizeof(dof::BvhNode) * ni);
+    L.nodes16 = take(sizeof(dof::BvhNode16) * ni);
     L.parent = take(sizeof(uint32_t) * (2 * n - 1));
     L.keys = take(sizeof(uint64_t) * n);
     L.keys_tmp = take(sizeof(uint64_t) * n);
@@ -639,6 +641,7 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
     d.tris = reinterpret_cast<float4 *>(a + L.tris);
     d.albedo = reinterpret_cast<float4 *>(a + L.albedo);
     d.nodes = reinterpret_cast<dof::BvhNode *>(a + L.nodes);
+    d.nodes16 = reinterpret_cast<dof::BvhNode16 *>(a + L.nodes16);
     d.parent = reinterpret_cast<uint32_t *>(a + L.parent);
     d.keys = reinterpret_cast<uint64_t *>(a + L.keys);
     d.keys_tmp = reinterpret_cast<uint64_t *>(a + L.keys_tmp);
@@ -703,6 +706,7 @@ dof_status dof_bvh_view_get(const dof_scene *scene, dof_bvh_view *out)
     out->ids = scene->dev.ids;
     out->parent = scene->dev.parent;
     out->nodes = scene->dev.nodes;
+    out->nodes16 = scene->dev.nodes16;
     out->tris = scene->dev.tris;
     return DOF_OK;
 }
@@ -902,7 +906,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
         J.hist_out = it.history.out;
         J.mask = it.out.mask;
         J.out = it.out;
-        J.scene = dof::SceneArgs{it.scene->dev.nleaf, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes,
+        J.scene = dof::SceneArgs{it.scene->dev.nleaf, it.scene->dev.tris, it.scene->dev.albedo, it.scene->dev.nodes16,
                                  it.scene->dev.parent};
         J.grings = gather_rings(it.lens, *p);
         const dof::FrameConst &fc = J.fc;

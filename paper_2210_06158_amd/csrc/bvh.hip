@@ -547,6 +547,44 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
+// The traversal's binary16 copy of the nodes.  Each plane is converted with
+// directed rounding, low planes down and high planes up, and a result in the
+// subnormal range goes outward to 0 or to the smallest normal (2^-14), so the
+// copy holds every box whatever the device's binary16 denormal mode; a plane
+// beyond the binary16 range becomes an infinite one on its side.
+__device__ inline uint32_t half_bits(__half h) { return (uint32_t)__half_as_ushort(h); }
+
+__device__ inline uint32_t plane_down(float x)
+{
+    const float m = 6.103515625e-05f;   // 2^-14, the smallest normal binary16
+    float v = __half2float(__float2half_rd(x));
+    if (v > 0.0f && v < m) v = 0.0f;
+    else if (v < 0.0f && v > -m) v = -m;
+    return half_bits(__float2half_rn(v));   // v is a binary16 value: exact
+}
+
+__device__ inline uint32_t plane_up(float x)
+{
+    const float m = 6.103515625e-05f;
+    float v = __half2float(__float2half_ru(x));
+    if (v > 0.0f && v < m) v = m;
+    else if (v < 0.0f && v > -m) v = 0.0f;
+    return half_bits(__float2half_rn(v));
+}
+
+__device__ inline uint32_t axis16(float lo, float hi) { return plane_down(lo) | (plane_up(hi) << 16); }
+
+__global__ __launch_bounds__(kThreads) void k_nodes16(const BvhNode *__restrict__ nodes, int n, BvhNode16 *out)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const BvhNode nd = nodes[i];
+    BvhNode16 o;
+    o.a = make_uint4(axis16(nd.a.x, nd.a.y), axis16(nd.a.z, nd.a.w), axis16(nd.c.x, nd.c.y), axis16(nd.b.x, nd.b.y));
+    o.b = make_uint4(axis16(nd.b.z, nd.b.w), axis16(nd.c.z, nd.c.w), nd.d.x, nd.d.y);
+    out[i] = o;
+}
+
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
 {
     const int nt = s.ntri, n = s.nleaf;
@@ -580,6 +618,7 @@ hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
         k_refit_local<<<ceil_div(n, kRefitThreads), kRefitThreads, 0, st>>>(s.ref_box, s.ids, n, s.nodes, s.parent,
                                                                               s.flags, exits, cap, exit_count);
         k_refit_top<<<1, kRefitThreads, 0, st>>>(s.nodes, s.parent, s.flags, exits, cap, exit_count);
+        k_nodes16<<<ceil_div(n - 1, kThreads), kThreads, 0, st>>>(s.nodes, n - 1, s.nodes16);
     }
     return hipGetLastError();
 }

@@ -32,6 +32,17 @@ struct BvhNode {      // 64 B, both children's boxes with the parent
     uint4 d;          // left, right, first and last leaf of the range (bit 31 of a child: leaf)
 };
 
+// The traversal's copy of a node, 32 B: the children's boxes in binary16,
+// each low plane rounded down and each high plane rounded up (no subnormal
+// values: those go out to 0 or to the smallest normal), so every box holds the
+// binary32 box and the slab test stays conservative.  Each 32-bit word packs
+// one axis of one box: the low plane in its low half, the high plane in its
+// high half.
+struct BvhNode16 {
+    uint4 a;          // L.x, L.y, L.z, R.x
+    uint4 b;          // R.y, R.z, left, right
+};
+
 struct SceneShade {
     float light_dir[3], light_rad[3], ambient[3], sky[3];
 };
@@ -49,6 +60,7 @@ struct SceneDev {
     float4 *tris;            // 3 per leaf, sorted order; tris[3i].w = triangle id bits
     float4 *albedo;          // 1 per leaf, sorted order
     BvhNode *nodes;          // nleaf - 1
+    BvhNode16 *nodes16;      // nleaf - 1: the traversal's binary16 copy
     uint32_t *parent;        // 2 nleaf - 1
     uint64_t *keys, *keys_tmp;   // 63-bit Morton codes
     uint32_t *ids, *ids_tmp;     // reference indices (sorted: in leaf order)
@@ -160,7 +172,7 @@ struct SceneArgs {
     int32_t nleaf;
     const float4 *__restrict__ tris;
     const float4 *__restrict__ albedo;
-    const BvhNode *__restrict__ nodes;
+    const BvhNode16 *__restrict__ nodes;   // binary16 boxes (conservative)
     const uint32_t *__restrict__ parent;   // parent of each internal node (root: ~0u)
 };
 

@@ -44,7 +44,7 @@
 namespace dof {
 namespace {
 
-SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.nleaf, s.tris, s.albedo, s.nodes, s.parent}; }
+SceneArgs scene_args(const SceneDev &s) { return SceneArgs{s.nleaf, s.tris, s.albedo, s.nodes16, s.parent}; }
 
 __device__ inline float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
@@ -157,6 +157,20 @@ __device__ inline bool box_hit(const WRay &r, float lx, float hx, float ly, floa
     tenter = tn;
     // tn <= tf, tf >= 0 and tn <= limit (limit >= 0) in one comparison
     return fmaxf(tn, 0.0f) <= fminf(tf, limit);
+}
+
+// The planes of a binary16 node word: low plane in the low half, high plane
+// in the high half.  Converted exactly; the compiler folds the conversion into
+// the slab test's fused multiply-add (a mixed-precision fma).
+__device__ inline float lo16(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
+__device__ inline float hi16(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
+
+// Slab tests of both children of a binary16 node.
+__device__ inline void node_hits(const WRay &r, const BvhNode16 &nd, float limit, bool &hl, bool &hr, float &tl,
+                                 float &tr)
+{
+    hl = box_hit(r, lo16(nd.a.x), hi16(nd.a.x), lo16(nd.a.y), hi16(nd.a.y), lo16(nd.a.z), hi16(nd.a.z), limit, tl);
+    hr = box_hit(r, lo16(nd.a.w), hi16(nd.a.w), lo16(nd.b.x), hi16(nd.b.x), lo16(nd.b.y), hi16(nd.b.y), limit, tr);
 }
 
 struct Hit {
@@ -739,13 +753,13 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
         for (int step = 0; step < 2; ++step) {
             if (!(active && trav && nq <= 2)) continue;
             const uint32_t nd_self = node;
-            const BvhNode nd = Sl.nodes[node];
+            const BvhNode16 nd = Sl.nodes[node];
             ++visits;
             const float limit = h.t * 1.0009765625f;   // prune against the best hit, 2^-10 relative slack
             float tl, tr;
-            bool hl = box_hit(wr, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, limit, tl);
-            bool hr = box_hit(wr, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, limit, tr);
-            const uint32_t L = nd.d.x, R = nd.d.y;
+            bool hl, hr;
+            node_hits(wr, nd, limit, hl, hr, tl, tr);
+            const uint32_t L = nd.b.z, R = nd.b.w;
             // leaf children go to the front of the pending queue (shift in)
             const bool pl = hl && (L & kLeaf) != 0u, pr = hr && (R & kLeaf) != 0u;
             q3 = pl ? q2 : q3; q2 = pl ? q1 : q2; q1 = pl ? q0 : q1; q0 = pl ? (L & ~kLeaf) : q0;
@@ -779,14 +793,14 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
                     // to the nearest ancestor whose far child is still pending
                     uint32_t c = nd_self;
                     for (uint32_t a = Sl.parent[c]; a != ~0u; c = a, a = Sl.parent[a]) {
-                        const BvhNode pn = Sl.nodes[a];
+                        const BvhNode16 pn = Sl.nodes[a];
                         ++visits;
                         const float lim = h.t * 1.0009765625f;
                         float ta, tb;
-                        const bool ha = box_hit(wr, pn.a.x, pn.a.y, pn.a.z, pn.a.w, pn.c.x, pn.c.y, lim, ta);
-                        const bool hb = box_hit(wr, pn.b.x, pn.b.y, pn.b.z, pn.b.w, pn.c.z, pn.c.w, lim, tb);
-                        const bool from_left = pn.d.x == c;
-                        const uint32_t other = from_left ? pn.d.y : pn.d.x;
+                        bool ha, hb;
+                        node_hits(wr, pn, lim, ha, hb, ta, tb);
+                        const bool from_left = pn.b.z == c;
+                        const uint32_t other = from_left ? pn.b.w : pn.b.z;
                         const bool came_near = from_left ? ta <= tb : !(ta <= tb);
                         if (came_near && (other & kLeaf) == 0u && (from_left ? hb : ha)) {
                             node = other;

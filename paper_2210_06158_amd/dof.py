@@ -79,7 +79,8 @@ class DofSceneDesc(C.Structure):
 
 class DofBvhView(C.Structure):
     _fields_ = [("ntri", C.c_int32), ("nleaf", C.c_int32), ("keys", C.c_void_p), ("ids", C.c_void_p),
-                ("parent", C.c_void_p), ("nodes", C.c_void_p), ("tris", C.c_void_p)]
+                ("parent", C.c_void_p), ("nodes", C.c_void_p), ("tris", C.c_void_p),
+                ("nodes16", C.c_void_p)]
 
 
 DEBUG_FIELDS = ("colr", "zn", "tile_max", "tile_dil", "pre", "gather", "ppmed", "prev_idx", "queue", "ray_base",
@@ -154,7 +155,7 @@ def lib():
             if name not in ("dof_abi_version", "dof_last_error", "dof_default_params", "dof_destroy_scene",
                             "dof_batch_destroy"):
                 getattr(L, name).restype = C.c_int32
-        if L.dof_abi_version() != 5:
+        if L.dof_abi_version() != 6:
             raise ImportError("libdof ABI version mismatch")
         _lib = L
     return _lib
@@ -231,6 +232,7 @@ class Scene:
         return dict(nleaf=n, keys=self._slice(v.keys, 8 * n, torch.int64), ids=self._slice(v.ids, 4 * n, torch.int32),
                     parent=self._slice(v.parent, 4 * (2 * n - 1), torch.int32),
                     nodes=self._slice(v.nodes, 64 * max(n - 1, 1), torch.float32),
+                    nodes16=self._slice(v.nodes16, 32 * max(n - 1, 1), torch.int32),
                     tris=self._slice(v.tris, 48 * n, torch.float32))
 
     def _slice(self, ptr, nbytes, dtype):

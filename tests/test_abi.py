@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(dof):
 
 def test_abi_version_and_defaults(dof):
     L = dof.lib()
-    assert L.dof_abi_version() == 5
+    assert L.dof_abi_version() == 6
     assert C.sizeof(dof.DofCamera) == 16 * 4 + 2 * 4   # basis, size, counters, jitter
     p = dof.DofParams()
     L.dof_default_params(C.byref(p))

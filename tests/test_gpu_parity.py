@@ -135,6 +135,39 @@ def test_bvh_bit_exact(env, orc):
     assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
 
 
+def half_words(box):
+    """The traversal's binary16 words of child boxes (n, 6: lo xyz, hi xyz):
+    per axis the low plane rounded down in bits 0-15 and the high plane
+    rounded up in bits 16-31, a result in the subnormal range moved outward to
+    0 or 2^-14 (written from the definition with numpy's binary16)."""
+    m = np.float32(2.0 ** -14)
+
+    def conv(x, down):
+        x = np.asarray(x, np.float32)
+        with np.errstate(over="ignore"):
+            h = x.astype(np.float16)
+        if down:
+            h = np.where(h.astype(np.float32) > x, np.nextafter(h, np.float16(-np.inf)), h)
+        else:
+            h = np.where(h.astype(np.float32) < x, np.nextafter(h, np.float16(np.inf)), h)
+        v = h.astype(np.float32)
+        sub_pos, sub_neg = (v > 0) & (v < m), (v < 0) & (v > -m)
+        v = np.where(sub_pos, np.float32(0) if down else m, np.where(sub_neg, -m if down else np.float32(0), v))
+        return v.astype(np.float16).view(np.uint16).astype(np.uint32)
+
+    return np.stack([conv(box[:, a], True) | (conv(box[:, a + 3], False) << 16) for a in range(3)], 1)
+
+
+def check_nodes16(view, lbox, rbox, left, right):
+    """The binary16 node copy: both children's boxes rounded outward and the
+    child links, word for word."""
+    nl = view["nleaf"]
+    got = view["nodes16"].cpu().numpy().view(np.uint32).reshape(nl - 1, 8)
+    want = np.concatenate([half_words(lbox), half_words(rbox)], 1)
+    assert np.array_equal(got[:, :6], want)
+    assert np.array_equal(got[:, 6], left[:nl - 1]) and np.array_equal(got[:, 7], right[:nl - 1])
+
+
 @pytest.mark.parametrize("n,seed,split", [(1, 3, 2), (2, 4, 2), (3, 5, 2), (257, 6, 2), (5000, 7, 2), (5000, 8, 1),
                                           (5000, 9, 3), (2000, 10, 0)])
 def test_bvh_random_soups_and_closest_hit(env, orc, n, seed, split):
@@ -170,6 +203,7 @@ def test_bvh_random_soups_and_closest_hit(env, orc, n, seed, split):
             return out.astype(np.float32)
         assert np.array_equal(lb.view(np.uint32), boxes_of(ob["left"]).view(np.uint32))
         assert np.array_equal(rb.view(np.uint32), boxes_of(ob["right"]).view(np.uint32))
+        check_nodes16(view, boxes_of(ob["left"]), boxes_of(ob["right"]), ob["left"], ob["right"])
     tris = view["tris"].cpu().numpy().reshape(nl, 12)
     assert np.array_equal(tris[:, 3].view(np.uint32), ob["ids"])
     assert np.array_equal(tris[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]], v[ob["ids"]])
@@ -600,12 +634,15 @@ def test_leaf_split_edge_cases(env, orc, split):
     assert np.array_equal(nu[:, 12], ob["left"][:nl - 1]) and np.array_equal(nu[:, 13], ob["right"][:nl - 1])
     lb = np.stack([nodes[:, 0], nodes[:, 2], nodes[:, 8], nodes[:, 1], nodes[:, 3], nodes[:, 9]], 1)
     rb = np.stack([nodes[:, 4], nodes[:, 6], nodes[:, 10], nodes[:, 5], nodes[:, 7], nodes[:, 11]], 1)
+    want_boxes = []
     for ch, got in ((ob["left"], lb), (ob["right"], rb)):
         ch = ch[:nl - 1].astype(np.int64)
         leaf = (ch & 0x80000000) != 0
         want = np.where(leaf[:, None], ob["leaf_bounds"][np.where(leaf, ch & 0x7FFFFFFF, 0)],
                         ob["bounds"][np.where(leaf, 0, ch)]).astype(np.float32)
         assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+        want_boxes.append(want)
+    check_nodes16(view, want_boxes[0], want_boxes[1], ob["left"], ob["right"])
     hg, tg = gs.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
     ho, to = orc.closest_hit(osc, o, d, use_bvh=False)
     assert (ho >= 0).mean() > 0.3
