@@ -545,8 +545,6 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_top(BvhNode *nodes, con
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-}  // namespace
-
 // The traversal's binary16 copy of the nodes.  Each plane is converted with
 // directed rounding, low planes down and high planes up, and a result in the
 // subnormal range goes outward to 0 or to the smallest normal (2^-14), so the
@@ -584,6 +582,8 @@ __global__ __launch_bounds__(kThreads) void k_nodes16(const BvhNode *__restrict_
     o.b = make_uint4(axis16(nd.b.z, nd.b.w), axis16(nd.c.z, nd.c.w), nd.d.x, nd.d.y);
     out[i] = o;
 }
+
+}  // namespace
 
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st)
 {
