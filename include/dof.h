@@ -148,13 +148,16 @@ typedef struct {
      * rays of the queue (row-major pixels): 1 from the first ray, 2 (and the
      * default 0) from the last -- the bottom image rows first, which in
      * ground-level views holds the near foreground whose rays cost most, so
-     * cheap sky and background rays fill the kernel's tail. */
+     * cheap sky and background rays fill the kernel's tail.  trace_steps:
+     * node visits per lane in one iteration of the traversal loop (between
+     * its refill and triangle-test decisions), 3 (and the default 0) or 4. */
     int32_t gather_window;
     int32_t trace_stack;
     int32_t trace_grab;
     int32_t trace_refill;
     int32_t trace_leaf_batch;
     int32_t trace_order;
+    int32_t trace_steps;
 } dof_params;
 
 /* Full-resolution G-buffer (section 3): sharp colour (alpha ignored), view

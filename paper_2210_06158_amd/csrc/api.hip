@@ -369,6 +369,8 @@ dof_status params_check(const dof_params *p)
         p->trace_leaf_batch < 0 || p->trace_leaf_batch > 64)
         return fail(DOF_E_INVALID, "trace_grab must be in 0..256, trace_refill and trace_leaf_batch in 0..64");
     if (p->trace_order < 0 || p->trace_order > 2) return fail(DOF_E_INVALID, "trace_order must be 0, 1 or 2");
+    if (p->trace_steps != 0 && p->trace_steps != 3 && p->trace_steps != 4)
+        return fail(DOF_E_INVALID, "trace_steps must be 0, 3 or 4");
     if (p->mask_mode == DOF_MASK_DILATE && p->r_max > 32.0f)
         return fail(DOF_E_UNSUPPORTED, "mask dilation supports r_max <= 32");
     if (!(p->r_max > 0.0f) || !(p->depth_range > 0.0f) || !(p->h_edge > 0.0f)) return fail(DOF_E_INVALID, "bad params");
@@ -385,6 +387,7 @@ dof::TraceKnobs trace_knobs(const dof_params &p)
     k.refill = p.trace_refill ? p.trace_refill : 16;
     k.leaf_batch = p.trace_leaf_batch ? p.trace_leaf_batch : 32;
     k.reverse = p.trace_order == 1 ? 0 : 1;
+    k.steps = p.trace_steps ? p.trace_steps : dof::kTraceSteps;
     return k;
 }
 
@@ -454,14 +457,14 @@ bool same_view(const dof_camera &a, const dof_camera &b, const dof_lens &la, con
            memcmp(&la, &lb, sizeof(la)) == 0;
 }
 
-int default_trace_blocks(bool batch = false, int stack = dof::kStackLds)
+int default_trace_blocks(bool batch = false, int stack = dof::kStackLds, int steps = dof::kTraceSteps)
 {
     // as many 128-thread blocks as fit on the device at once (registers and
     // the LDS stack decide), capped at the grid limit
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 1024;
-    per_cu = dof::trace_blocks_per_cu(batch, stack);
+    per_cu = dof::trace_blocks_per_cu(batch, stack, steps);
     if (per_cu <= 0) per_cu = 5;
     const int b = cus * per_cu;
     return b > dof::kMaxTraceBlocks ? dof::kMaxTraceBlocks : b;
@@ -840,7 +843,7 @@ dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_l
     }
     const dof::SideStream *side = (ev == nullptr && scene->side_ready) ? &scene->side : nullptr;
     DOF_HIP(dof::launch_frame_pre(fc, gather_rings(*lens, *p), L, scr, *gb, hin, hist->out, out->mask, ev, side, s));
-    const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(false, fc.tk.stack);
+    const int blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(false, fc.tk.stack, fc.tk.steps);
     DOF_HIP(dof::launch_trace(scene->dev, fc, L, scr, blocks, s));
     DOF_HIP(dof::launch_frame_post(scene->dev, fc, rings, L, scr, *gb, hin, hist->out, out->mask, *out, ev, side, s));
     scene->timed_frame = ev != nullptr;
@@ -929,7 +932,7 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
     DOF_HIP(hipMemcpyAsync(b->table, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
                            static_cast<hipStream_t>(stream)));
     for (int g = 0; g < dof::kNumGrids; ++g) b->nblk[g] = tot[g];
-    b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true, jobs[0].fc.tk.stack);
+    b->trace_blocks = p->trace_blocks > 0 ? p->trace_blocks : default_trace_blocks(true, jobs[0].fc.tk.stack, jobs[0].fc.tk.steps);
     b->dilate = p->mask_mode == DOF_MASK_DILATE;
     b->taa = p->taa;
     b->gather_win = jobs[0].fc.gather_win;

@@ -21,6 +21,7 @@ constexpr int kMaxBlades = 16;
 constexpr int kStackLds = 24;             // default traversal stack entries per lane (LDS only; deeper
                                           // work is found again through parent links); 16 and 32 also built
 constexpr int kTB = 128;                  // threads per traversal block
+constexpr int kTraceSteps = 3;            // default node visits per lane in one traversal loop iteration
 constexpr int kMaxTraceBlocks = 4096;     // persistent traversal grid limit
 
 // ---------------------------------------------------------------- scene
@@ -107,6 +108,7 @@ struct TraceKnobs {
     int32_t refill;       // idle lanes that trigger a refill
     int32_t leaf_batch;   // lanes with a pending leaf that trigger the triangle tests
     int32_t reverse;      // 1: rays handed out from the end of the queue
+    int32_t steps;        // node visits per lane in one loop iteration: 3 or 4
 };
 
 struct FrameConst {
@@ -257,7 +259,7 @@ dof_status set_error(dof_status code, const char *fmt, ...);
 hipError_t launch_build_bvh(SceneDev &s, hipStream_t st);
 
 // trace.hip
-int trace_blocks_per_cu(bool batch, int stack);   // resident blocks of the lens-ray traversal per CU
+int trace_blocks_per_cu(bool batch, int stack, int steps);   // resident blocks of the lens-ray traversal per CU
 hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLayout &L, char *scratch,
                         int blocks, hipStream_t st);
 // the ray records of every thin-lens ray of the frame (after the compaction)

@@ -7,34 +7,37 @@
 //             image of section 3, produced by ray casting);
 //  RawRays    closest hit of caller-given rays.
 //
-// Scheduling: each lane owns one ray at a time and advances it one BVH node
-// per loop iteration; when 16 or more lanes of a wave are idle (or all are),
-// the wave hands them the next rays of its pool, a run of 64 ray indices
-// taken from a device counter with one atomic whenever the pool is empty, so
-// long rays do not hold a whole wave hostage (persistent threads with dynamic
-// fetch) and the shared counter sees one atomic per 64 rays.  Thin-lens rays
-// come precomputed (a generation kernel writes a 48-byte record per ray) and
-// leave as an 8-byte (leaf, t) record that the resolve expands when it shades, so a
-// refill is three loads and a finishing ray one store: no arithmetic or
-// scene loads that the whole wave would wait on.
+// Scheduling: each lane owns one ray at a time and advances it up to three
+// or four BVH nodes per loop iteration; when enough lanes of a wave are idle
+// (16 by default, or all of them) the wave hands them the next rays of its
+// pool, a run of 64 ray indices taken from a device counter with one atomic
+// whenever the pool is empty, so long rays do not hold a whole wave hostage
+// (persistent threads with dynamic fetch) and the shared counter sees one
+// atomic per 64 rays.  Thin-lens rays come from a generation kernel as
+// 24-byte records (origin and direction); a lane that takes one derives the
+// watertight test's shear and the slab reciprocals itself.  A finishing ray
+// leaves one 8-byte (leaf, t) record that the resolve expands when it shades,
+// so no lane waits on scene loads for shading.
 //
-// Closest hit: binary radix tree whose nodes carry both children's boxes
-// (one 64-byte fetch tests two boxes), near child first, far child pushed on
-// a per-lane stack of 24 entries in LDS, so a pop is always an LDS read.  When
-// the stack is full its oldest 8 entries are dropped; when it later runs empty
-// the lane finds the dropped work again by walking parent links upwards: at
-// each ancestor reached from its near child (entry distances compared as when
-// it was first visited) whose far child still passes the box test, that far
-// child is the next subtree.  Every dropped entry is such a far child, and the
-// box test only loses children as the best hit shrinks, so the walk visits
-// exactly the pending subtrees that can still hold the closest hit: any depth
-// the 96-bit keys allow is exact with no memory beyond LDS.
-// Each outer iteration advances a lane by up to two nodes, which halves the
-// per-iteration cost of the wave-wide refill and batching decisions.  Leaf
-// hits wait in a 4-entry per-lane queue and the triangle test runs when at
-// least 32 lanes of the wave have one (or a queue is nearly full, or a lane
-// has finished its traversal), so it executes with most lanes active
-// instead of once per node visit for a few lanes; watertight ray/triangle
+// Closest hit: binary radix tree; the traversal reads a 32-byte copy of each
+// node holding both children's boxes in binary16, rounded outward (one fetch
+// of two 16-byte words tests two boxes).  Near child first, far child pushed
+// on a per-lane stack of 16, 24 or 32 entries in LDS, so a pop is always an
+// LDS read.  When the stack is full its oldest 8 entries are dropped; when it
+// later runs empty the lane finds the dropped work again by walking parent
+// links upwards: at each ancestor reached from its near child (entry
+// distances compared as when it was first visited) whose far child still
+// passes the box test, that far child is the next subtree.  Every dropped
+// entry is such a far child, and the box test only loses children as the
+// best hit shrinks, so the walk visits exactly the pending subtrees that can
+// still hold the closest hit: any depth is exact with no memory beyond LDS.
+// Each outer iteration advances a lane by up to three or four nodes (a launch
+// knob), which spreads the wave-wide refill and batching decisions over
+// several visits.  Leaf hits wait in a 4-entry per-lane queue and the
+// triangle test runs when enough lanes of the wave have one (32 by default),
+// or a queue is nearly full, or a lane has finished its traversal, so it
+// executes with most lanes active instead of once per node visit for a few
+// lanes; watertight ray/triangle
 // test of Woop, Benthin & Wald (JCGT 2013), two-sided, t > 0, equal
 // distances resolved to the smaller triangle id -- the same answer as brute
 // force over all triangles.  Box tests are loosened by a relative margin so
@@ -647,12 +650,13 @@ constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS st
 // least tk.refill lanes are idle [16], takes tk.grab rays from the shared
 // work counter at a time [64], and runs its triangle tests when at least
 // tk.leaf_batch lanes have one pending [32]; kStack LDS stack entries per
-// lane [24]; tk.reverse hands the rays out from the end of the queue [for
+// lane [24]; kSteps node visits per lane per iteration [3]; tk.reverse
+// hands the rays out from the end of the queue [for
 // frames; the scene-level sources keep the queue order].  The last rays a
 // persistent grid hands out set its tail: when they are cheap, every wave
 // finishes at nearly the same time.
 
-template <class Src, int kStack>
+template <class Src, int kStack, int kSteps>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
                                                   uint32_t *work, unsigned long long *stats, uint32_t *drops_out,
                                                   TraceKnobs tk)
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             }
         }
 #pragma unroll
-        for (int step = 0; step < 2; ++step) {
+        for (int step = 0; step < kSteps; ++step) {
             if (!(active && trav && nq <= 2)) continue;
             const uint32_t nd_self = node;
             const BvhNode16 nd = Sl.nodes[node];
@@ -861,22 +865,30 @@ int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks
 
 }  // namespace
 
-// The traversal kernel of a ray source for a stack depth: f(kernel_tag).
-template <class Src, class F>
-void with_stack(int stack, F f)
+// The traversal kernel of a ray source for a stack depth and a number of
+// node visits per loop iteration: f(kernel).
+template <class Src, int kStack, class F>
+void with_steps(int steps, F f)
 {
-    if (stack == 16) f(k_traverse<Src, 16>);
-    else if (stack == 32) f(k_traverse<Src, 32>);
-    else f(k_traverse<Src, kStackLds>);
+    if (steps == 4) f(k_traverse<Src, kStack, 4>);
+    else f(k_traverse<Src, kStack, kTraceSteps>);
 }
 
-int trace_blocks_per_cu(bool batch, int stack)
+template <class Src, class F>
+void with_shape(int stack, int steps, F f)
+{
+    if (stack == 16) with_steps<Src, 16>(steps, f);
+    else if (stack == 32) with_steps<Src, 32>(steps, f);
+    else with_steps<Src, kStackLds>(steps, f);
+}
+
+int trace_blocks_per_cu(bool batch, int stack, int steps)
 {
     int n = 0;
     hipError_t e = hipSuccess;
     auto occ = [&](auto kern) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kTB, 0); };
-    if (batch) with_stack<BatchRays>(stack, occ);
-    else with_stack<LensRays>(stack, occ);
+    if (batch) with_shape<BatchRays>(stack, steps, occ);
+    else with_shape<LensRays>(stack, steps, occ);
     return e == hipSuccess ? n : 0;
 }
 
@@ -889,7 +901,7 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     src.rec1 = P.rec1;
     src.ray_lt = P.ray_lt;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
-    with_stack<LensRays>(fc.tk.stack, [&](auto kern) {
+    with_shape<LensRays>(fc.tk.stack, fc.tk.steps, [&](auto kern) {
         kern<<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork,
                                                   reinterpret_cast<unsigned long long *>(cnt + kCntVisits),
                                                   cnt + kCntSpills, fc.tk);
@@ -933,7 +945,7 @@ hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour,
     src.normal = normal;
     src.nfmt = nfmt;
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
-    k_traverse<PinholeRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(
+    k_traverse<PinholeRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(
         scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H), nullptr, s.aux, nullptr, nullptr, fc.tk);
     return hipGetLastError();
 }
@@ -945,7 +957,7 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
     RawRays src{org, dir, hit, t};
     k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
     TraceKnobs tk{kStackLds, 64u, 16, 32};
-    k_traverse<RawRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux,
+    k_traverse<RawRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux,
                                                                          nullptr, nullptr, tk);
     return hipGetLastError();
 }
@@ -958,7 +970,7 @@ hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, ui
         const uint32_t n = (uint32_t)(npx - p0 < chunk_px ? npx - p0 : chunk_px);
         RefRays src{fc, (uint32_t)p0, (uint32_t)spp, lt};
         k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
-        k_traverse<RefRays, kStackLds><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, n * (uint32_t)spp,
+        k_traverse<RefRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, n * (uint32_t)spp,
                                                                             nullptr, s.aux, nullptr, nullptr, fc.tk);
         k_ref_average<<<(n + 255) / 256, 256, 0, st>>>(scene_args(s), src, n, colour, cfmt);
         const hipError_t e = hipGetLastError();
@@ -973,7 +985,7 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int b
     kb_ray_offsets<<<1, 64, 0, st>>>(head, jobs, njobs);
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
-    with_stack<BatchRays>(tk.stack, [&](auto kern) {
+    with_shape<BatchRays>(tk.stack, tk.steps, [&](auto kern) {
         kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, &head->visits,
                                                   nullptr, tk);
     });

@@ -42,10 +42,12 @@ class DofParams(C.Structure):
                 ("mask_mode", C.c_int32), ("trace_blocks", C.c_int32), ("timing", C.c_int32),
                 ("pp_polygon", C.c_int32), ("taa", C.c_int32), ("ray_records", C.c_int32), ("composite_literal", C.c_int32),
                 ("gather_window", C.c_int32), ("trace_stack", C.c_int32), ("trace_grab", C.c_int32),
-                ("trace_refill", C.c_int32), ("trace_leaf_batch", C.c_int32), ("trace_order", C.c_int32)]
+                ("trace_refill", C.c_int32), ("trace_leaf_batch", C.c_int32), ("trace_order", C.c_int32),
+                ("trace_steps", C.c_int32)]
 
 # launch-shape knobs of dof_params (0 = library default), set from a dict
-KNOBS = ("gather_window", "trace_stack", "trace_grab", "trace_refill", "trace_leaf_batch", "trace_order")
+KNOBS = ("gather_window", "trace_stack", "trace_grab", "trace_refill", "trace_leaf_batch", "trace_order",
+         "trace_steps")
 
 
 class DofGBuffer(C.Structure):

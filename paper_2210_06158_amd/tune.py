@@ -18,7 +18,10 @@ Searched per workload, by HIP-event time of the same sample of frames:
   (32, 40, 48 texels, or -1: every tap from global memory);
 * trace_order -- rays handed out from the end of the queue (2: bottom image
   rows first) or from its start (1); the last rays handed out set the
-  persistent grid's tail.
+  persistent grid's tail;
+* trace_steps -- node visits per lane in one iteration of the traversal
+  loop (3, 4): more visits between the loop's refill and triangle-test
+  decisions save their ballots but hold finished lanes longer.
 
 The search is coordinate descent from the library defaults: one knob at a
 time over its candidates with the others held, keeping the fastest unless the
@@ -36,9 +39,10 @@ KNOB_SPACE = {
     "trace_leaf_batch": (16, 24, 32, 40),
     "gather_window": (-1, 32, 40, 48),
     "trace_order": (2, 1),
+    "trace_steps": (3, 4),
 }
 DEFAULTS = {"trace_blocks": 0, "trace_stack": 24, "trace_grab": 64, "trace_refill": 16, "trace_leaf_batch": 32,
-            "gather_window": -1, "trace_order": 2}
+            "gather_window": -1, "trace_order": 2, "trace_steps": 3}
 
 
 def candidate_blocks(extra=()):

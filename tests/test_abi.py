@@ -251,9 +251,11 @@ def test_launch_knob_ranges(dof):
     L = dof.lib()
     b = C.c_size_t()
     ok = {"gather_window": (0, -1, 32, 40, 48), "trace_stack": (0, 16, 24, 32), "trace_grab": (0, 1, 256),
-          "trace_refill": (0, 1, 64), "trace_leaf_batch": (0, 1, 64), "trace_order": (0, 1, 2)}
+          "trace_refill": (0, 1, 64), "trace_leaf_batch": (0, 1, 64), "trace_order": (0, 1, 2),
+          "trace_steps": (0, 3, 4)}
     bad = {"gather_window": (16, 64, -2), "trace_stack": (8, 48), "trace_grab": (-1, 257), "trace_refill": (65,),
-           "trace_leaf_batch": (-3, 65), "trace_order": (-1, 3)}
+           "trace_leaf_batch": (-3, 65), "trace_order": (-1, 3),
+           "trace_steps": (1, 2, 5)}
     for k, vals in ok.items():
         for v in vals:
             p = dof.DofParams()

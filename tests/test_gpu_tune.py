@@ -69,8 +69,9 @@ def test_extreme_grids_agree():
 
 def test_launch_knobs_never_change_a_result():
     """Every value of every launch knob the autotuner searches (traversal
-    stack depth, queue width, refill and leaf-batch thresholds, the gather's
-    LDS window, including no staging) renders the same frame bit for bit --
+    stack depth, queue width, refill and leaf-batch thresholds, hand-out
+    order, node visits per loop iteration, the gather's LDS window, including
+    no staging) renders the same frame bit for bit --
     colour, mask, history -- on the 256 x 256 workload and a second frame
     with history, alone and in a batch of two."""
     import dataclasses
@@ -101,9 +102,10 @@ def test_launch_knobs_never_change_a_result():
     ref = render({})
     assert ref[3][1] > 1000
     cases = [{k: v} for k, vals in tune.KNOB_SPACE.items() if k != "trace_blocks" for v in vals]
-    cases.append({"trace_stack": 16, "trace_grab": 1, "trace_refill": 1, "trace_leaf_batch": 1, "gather_window": 32})
+    cases.append({"trace_stack": 16, "trace_grab": 1, "trace_refill": 1, "trace_leaf_batch": 1, "gather_window": 32,
+                  "trace_steps": 4})
     cases.append({"trace_stack": 32, "trace_grab": 256, "trace_refill": 64, "trace_leaf_batch": 64,
-                  "gather_window": -1})
+                  "gather_window": -1, "trace_steps": 3})
     for knobs in cases:
         got = render(knobs)
         for a, r in zip(got, ref):
