@@ -333,10 +333,10 @@ dof_status dof_frame_scratch_bytes(int32_t width, int32_t height, const dof_para
  * the dilated mask mode, prefilter, gather, median) runs on a stream the
  * scene owns (created with it, default priority), forked from `stream` after
  * the ray generation (it reads only what the reduce wrote) and joined back
- * before the composite with events, so it runs beside the traversal: the work stays
- * ordered on `stream` and a HIP graph capture of the call takes both
- * branches.  Frames of one scene
- * share that stream, so their post-process chains run one after another. */
+ * before the composite with events, so it runs beside the traversal: the
+ * work stays ordered on `stream` and a HIP graph capture of the call takes
+ * both branches.  Frames of one scene share that stream, so their
+ * post-process chains run one after another. */
 dof_status dof_render_frame(dof_scene *scene, const dof_camera *cam, const dof_lens *lens,
                             const dof_gbuffer *gb, const dof_history_io *hist, const dof_params *p,
                             const dof_frame_out *out, void *scratch, size_t scratch_bytes,
