@@ -757,6 +757,9 @@ __device__ inline void b_compact_count(int64_t np, const uint8_t *__restrict__ m
 
 __global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t *__restrict__ mask, Planes P)
 {
+    // the traversal's counters start the frame at zero (the totals of the
+    // compaction are written by its last scatter block)
+    if (blockIdx.x == 0 && threadIdx.x >= kCntVisits && threadIdx.x <= kCntWork) P.counters[threadIdx.x] = 0u;
     b_compact_count(np, mask, P, blockIdx.x, blockIdx.y);
 }
 
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(256) void kb_compact_count(const Job *__restrict__ 
     b_compact_count((int64_t)J.fc.hw * J.fc.hh, J.mask, J.P, bx, by);
 }
 
-__device__ inline void b_compact_scan(int64_t nchunks, const Planes &P, dof_stats *stats)
+__device__ inline void b_compact_scan(int64_t nchunks, const Planes &P)
 {
     __shared__ uint32_t pp[1024], pr[1024];
     const int per = (int)((nchunks + 1023) / 1024);
@@ -801,35 +804,26 @@ __device__ inline void b_compact_scan(int64_t nchunks, const Planes &P, dof_stat
         P.counters[kCntRays] = pr[1023];
         for (int k = kCntVisits; k <= kCntSpills; ++k) P.counters[k] = 0u;
         P.counters[kCntWork] = 0u;
-        if (stats) {
-            stats->masked_px = pp[1023];
-            stats->rays = pr[1023];
-        }
     }
-}
-
-__global__ __launch_bounds__(1024) void k_compact_scan(int64_t nchunks, Planes P, dof_stats *stats)
-{
-    b_compact_scan(nchunks, P, stats);
 }
 
 __global__ __launch_bounds__(1024) void kb_compact_scan(const Job *__restrict__ jobs)
 {
     const Job &J = jobs[blockIdx.x];
     const int64_t np = (int64_t)J.fc.hw * J.fc.hh;
-    b_compact_scan((np + kChunk - 1) / kChunk, J.P, nullptr);
+    b_compact_scan((np + kChunk - 1) / kChunk, J.P);
 }
 
-__device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, const Planes &P, const uint32_t bx, const uint32_t by)
+__device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, const Planes &P, const uint32_t bx,
+                                         const uint32_t by, uint2 start)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     __shared__ uint32_t wp[4], wr[4];
     __shared__ uint32_t runp, runr;
     __shared__ uint32_t s_pix[kPixLds];   // ray -> queue position of one round's rays
     if (tid == 0) {
-        uint2 o = P.chunk_off[bx];
-        runp = o.x;
-        runr = o.y;
+        runp = start.x;
+        runr = start.y;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     size_t base = (size_t)bx * kChunk;
@@ -869,16 +863,41 @@ __device__ inline void b_compact_scatter(int64_t np, const uint8_t *__restrict__
     }
 }
 
+// A frame's scatter finds its chunk's offsets itself, summing the counts of
+// the chunks before it (integer sums: the same offsets as a scan), so a
+// frame needs no separate scan launch; the last chunk's block writes the
+// totals.
 __global__ __launch_bounds__(256) void k_compact_scatter(int64_t np, const uint8_t *__restrict__ mask, Planes P)
 {
-    b_compact_scatter(np, mask, P, blockIdx.x, blockIdx.y);
+    __shared__ uint32_t sp[4], sr[4];
+    const uint32_t bx = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t cp = 0, cr = 0;
+    for (uint32_t i = (uint32_t)tid; i < bx; i += 256) {
+        const uint2 c = P.chunk_cnt[i];
+        cp += c.x;
+        cr += c.y;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        cp += __shfl_xor(cp, o);
+        cr += __shfl_xor(cr, o);
+    }
+    if (lane == 0) { sp[w] = cp; sr[w] = cr; }
+    __syncthreads();
+    const uint2 start = make_uint2(sp[0] + sp[1] + sp[2] + sp[3], sr[0] + sr[1] + sr[2] + sr[3]);
+    if (bx == gridDim.x - 1 && tid == 0) {
+        const uint2 c = P.chunk_cnt[bx];
+        P.counters[kCntMasked] = start.x + c.x;
+        P.counters[kCntRays] = start.y + c.y;
+    }
+    b_compact_scatter(np, mask, P, bx, blockIdx.y, start);
 }
 
 __global__ __launch_bounds__(256) void kb_compact_scatter(const Job *__restrict__ jobs, int njobs)
 {
     uint32_t bx, by;
     const Job &J = jobs[job_of_block(jobs, njobs, kGridChunk, blockIdx.x, bx, by)];
-    b_compact_scatter((int64_t)J.fc.hw * J.fc.hh, J.mask, J.P, bx, by);
+    b_compact_scatter((int64_t)J.fc.hw * J.fc.hh, J.mask, J.P, bx, by, J.P.chunk_off[bx]);
 }
 
 // ---------------------------------------------------------------- A11
@@ -1671,7 +1690,6 @@ hipError_t launch_frame_pre(const FrameConst &fc, const Rings &rings, const Scra
     }
     DOF_REC(6);
     k_compact_count<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
-    k_compact_scan<<<1, 1024, 0, st>>>(L.nchunks, P, nullptr);
     k_compact_scatter<<<(unsigned)L.nchunks, 256, 0, st>>>(np, mask, P);
     const hipError_t e = launch_raygen(fc, L, scratch, st);
     if (e != hipSuccess) return e;
