@@ -249,7 +249,7 @@ def autotune(gs, cams, lenses, params, gbs, log, label, frames=6):
             fr.render(gs, cams[k], lenses[k], gbs[k], hist[(k + 1) % 2] if prev is not None else None, hist[k % 2],
                       prev_cam=prev, prev_lens=lenses[k - 1] if k > 0 else None)
 
-    cfg, table = tune.search(trial)
+    cfg, table = tune.search(trial, reps=3)
     cache.clear()
     log(f"{label}: launch shapes {cfg} ({table})")
     return cfg, {"chosen": {k: (v if v else "library default") if k == "trace_blocks" else v for k, v in cfg.items()},
@@ -772,7 +772,7 @@ def batched_leg(n_sessions, steps, warmup, log, leaf_split=None):
             tuners[key] = dof.Batch(n_sessions, ss[0].params, trace_blocks=btb, knobs=bkn)
         tuners[key].set([s.item() for s in ss])
         tuners[key].run()
-    best_cfg, tune_ms = tune.search(trial)
+    best_cfg, tune_ms = tune.search(trial, reps=3)
     del tuners
     log(f"batched: launch shapes {best_cfg} ({tune_ms})")
     best_tb, best_knobs = tune.split(best_cfg)

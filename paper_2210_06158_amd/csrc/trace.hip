@@ -239,17 +239,30 @@ __device__ inline bool in_aperture(const Aperture &ap, float x, float y)
     return true;
 }
 
-// Lens point by rejection from [-1, 1)^2 (24-bit lattice), at most 32 tries.
-__device__ inline void lens_point(const Aperture &ap, uint32_t seed, uint32_t frame, uint32_t q, uint32_t k,
-                                  float &lx, float &ly)
+// Lens point by rejection from [-1, 1)^2 (24-bit lattice), at most 32 tries:
+// try att of ray k of the pixel whose hashed seed is h.
+constexpr uint32_t kLensTries = 32;
+
+__device__ inline uint32_t lens_seed(uint32_t seed, uint32_t frame, uint32_t q)
 {
-    uint32_t h = pcg_hash(pcg_hash(pcg_hash(seed) ^ frame) ^ q);
-    for (uint32_t att = 0; att < 32u; ++att) {
-        uint32_t a = pcg_hash(h ^ ((k << 8) | att));
-        uint32_t b = pcg_hash(a);
-        float x = (float)(a >> 8) * (1.0f / 8388608.0f) - 1.0f;
-        float y = (float)(b >> 8) * (1.0f / 8388608.0f) - 1.0f;
-        if (in_aperture(ap, x, y)) {
+    return pcg_hash(pcg_hash(pcg_hash(seed) ^ frame) ^ q);
+}
+
+__device__ inline bool lens_try(const Aperture &ap, uint32_t h, uint32_t k, uint32_t att, float &x, float &y)
+{
+    uint32_t a = pcg_hash(h ^ ((k << 8) | att));
+    uint32_t b = pcg_hash(a);
+    x = (float)(a >> 8) * (1.0f / 8388608.0f) - 1.0f;
+    y = (float)(b >> 8) * (1.0f / 8388608.0f) - 1.0f;
+    return in_aperture(ap, x, y);
+}
+
+// The tries att0, att0 + 1, ... of a ray; (0, 0) when none of the 32 lands.
+__device__ inline void lens_point_from(const Aperture &ap, uint32_t h, uint32_t k, uint32_t att0, float &lx, float &ly)
+{
+    for (uint32_t att = att0; att < kLensTries; ++att) {
+        float x, y;
+        if (lens_try(ap, h, k, att, x, y)) {
             lx = x;
             ly = y;
             return;
@@ -257,6 +270,12 @@ __device__ inline void lens_point(const Aperture &ap, uint32_t seed, uint32_t fr
     }
     lx = 0.0f;
     ly = 0.0f;
+}
+
+__device__ inline void lens_point(const Aperture &ap, uint32_t seed, uint32_t frame, uint32_t q, uint32_t k,
+                                  float &lx, float &ly)
+{
+    lens_point_from(ap, lens_seed(seed, frame, q), k, 0, lx, ly);
 }
 
 __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
@@ -275,16 +294,19 @@ __device__ inline void st_rgba(void *p, int fmt, size_t i, float4 v)
 // Thin-lens ray k of pixel q = y w + x of a w x h grid: the pixel's point on
 // the focus plane (view depth d), a lens point from the counter hash of
 // (seed, frame, q, k), the normalised direction between them.
-__device__ inline void thin_lens_ray(const FrameConst &fc, uint32_t q, uint32_t w, uint32_t h, uint32_t k, float o[3],
-                                     float d[3])
+// The pixel's point on the focus plane.
+__device__ inline void focus_point(const FrameConst &fc, uint32_t q, uint32_t w, uint32_t h, float pf[3])
 {
     const int x = (int)(q % w), y = (int)(q / w);
-    float fv[3], pf[3];
+    float fv[3];
     pixel_dir(fc.cur, x, y, (int)w, (int)h, fv);
 #pragma unroll
     for (int a = 0; a < 3; ++a) pf[a] = fc.cur.pos[a] + fv[a] * fc.d;
-    float lx, ly;
-    lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
+}
+
+// The ray from lens point (lx, ly) through the focus-plane point pf.
+__device__ inline void lens_through(const FrameConst &fc, const float pf[3], float lx, float ly, float o[3], float d[3])
+{
 #pragma unroll
     for (int a = 0; a < 3; ++a) o[a] = fc.cur.pos[a] + fc.half_a * (lx * fc.cur.right[a] + ly * fc.cur.up[a]);
 #pragma unroll
@@ -292,6 +314,16 @@ __device__ inline void thin_lens_ray(const FrameConst &fc, uint32_t q, uint32_t 
     float len = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] = d[a] / len;
+}
+
+__device__ inline void thin_lens_ray(const FrameConst &fc, uint32_t q, uint32_t w, uint32_t h, uint32_t k, float o[3],
+                                     float d[3])
+{
+    float pf[3];
+    focus_point(fc, q, w, h, pf);
+    float lx, ly;
+    lens_point(fc.ap, fc.seed, fc.frame, q, k, lx, ly);
+    lens_through(fc, pf, lx, ly, o, d);
 }
 
 // Thin-lens ray r of a frame: its pixel from the ray -> pixel map, traced at
@@ -573,8 +605,70 @@ __global__ __launch_bounds__(kGenTB) void k_raygen(FrameConst fc, const uint32_t
     }
 }
 
-// Every thin-lens ray of a batch: ray r belongs to the last job whose first
-// ray is at or before r (LDS copy of the jobs' first rays).
+// The same for a bladed aperture, whose lens points take more tries
+// (rejection from the square keeps 65 % of them for a hexagon against 79 %
+// for a circle).  A wave walks runs of up to kGenSpan rays (shorter when the
+// frame has few rays, so every wave gets some); each ray first gets
+// kGenFirst tries, the rays still without a point wait in a per-wave LDS
+// list, and the wave then runs the remaining tries for them one per lane, so
+// it does not spin for its unluckiest lane while the others idle.  Every ray
+// gets the same tries in the same order as one lens_point call.
+constexpr int kGenSpan = 512;
+constexpr uint32_t kGenFirst = 2;
+
+__global__ __launch_bounds__(kGenTB) void k_raygen_bladed(FrameConst fc, const uint32_t *queue,
+                                                          const uint32_t *ray_base, const uint32_t *ray_pix,
+                                                          const uint32_t *count, float4 *rec0, float2 *rec1)
+{
+    __shared__ uint32_t left[kGenTB / 64][kGenSpan];
+    const uint32_t N = *count;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t nwaves = gridDim.x * (kGenTB / 64);
+    const uint32_t hw = (uint32_t)fc.hw, hh = (uint32_t)fc.hh;
+    uint32_t span = ((N / nwaves + 1u) + 63u) & ~63u;
+    span = span < (uint32_t)kGenSpan ? span : (uint32_t)kGenSpan;
+    for (uint32_t base = (blockIdx.x * (kGenTB / 64) + w) * span; base < N; base += nwaves * span) {
+        const uint32_t end = N - base < span ? N : base + span;
+        uint32_t nleft = 0;   // wave-uniform
+        for (uint32_t r0 = base; r0 < end; r0 += 64) {
+            const uint32_t r = r0 + (uint32_t)lane;
+            bool miss = false;
+            if (r < end) {
+                const uint32_t j = ray_pix[r], q = queue[j], k = r - ray_base[j];
+                const uint32_t hs = lens_seed(fc.seed, fc.frame, q);
+                float lx = 0.0f, ly = 0.0f;
+                bool ok = false;
+                for (uint32_t att = 0; att < kGenFirst && !ok; ++att) ok = lens_try(fc.ap, hs, k, att, lx, ly);
+                if (ok) {
+                    float pf[3], o[3], d[3];
+                    focus_point(fc, q, hw, hh, pf);
+                    lens_through(fc, pf, lx, ly, o, d);
+                    put_ray(rec0, rec1, r, o, d);
+                } else {
+                    miss = true;
+                }
+            }
+            const uint64_t m = __ballot(miss);
+            if (miss) left[w][nleft + (uint32_t)__popcll(m & lt)] = r;
+            nleft += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t t = (uint32_t)lane; t < nleft; t += 64) {
+            const uint32_t r = left[w][t];
+            const uint32_t j = ray_pix[r], q = queue[j], k = r - ray_base[j];
+            float lx, ly, pf[3], o[3], d[3];
+            lens_point_from(fc.ap, lens_seed(fc.seed, fc.frame, q), k, kGenFirst, lx, ly);
+            focus_point(fc, q, hw, hh, pf);
+            lens_through(fc, pf, lx, ly, o, d);
+            put_ray(rec0, rec1, r, o, d);
+        }
+        __builtin_amdgcn_wave_barrier();   // the list is rewritten by the next run
+    }
+}
+
 __global__ __launch_bounds__(kGenTB) void kb_raygen(const Job *__restrict__ jobs, const BatchHead *head, int njobs)
 {
     __shared__ uint32_t off[kMaxBatch + 1];
@@ -913,8 +1007,12 @@ hipError_t launch_raygen(const FrameConst &fc, const ScratchLayout &L, char *scr
 {
     const Planes P = planes(fc, L, scratch);
     const int64_t max_rays = (int64_t)fc.hw * fc.hh * fc.m;
-    k_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix, P.counters + kCntRays, P.rec0,
-                                                       P.rec1);
+    if (fc.ap.blades >= 3)
+        k_raygen_bladed<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix,
+                                                                 P.counters + kCntRays, P.rec0, P.rec1);
+    else
+        k_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(fc, P.queue, P.ray_base, P.ray_pix, P.counters + kCntRays,
+                                                           P.rec0, P.rec1);
     return hipGetLastError();
 }
 
