@@ -150,7 +150,7 @@ typedef struct {
      * ground-level views holds the near foreground whose rays cost most, so
      * cheap sky and background rays fill the kernel's tail.  trace_steps:
      * node visits per lane in one iteration of the traversal loop (between
-     * its refill and triangle-test decisions), 3 (and the default 0) or 4. */
+     * its refill and triangle-test decisions), 3 or 4 (and the default 0). */
     int32_t gather_window;
     int32_t trace_stack;
     int32_t trace_grab;

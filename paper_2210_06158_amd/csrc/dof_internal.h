@@ -21,7 +21,7 @@ constexpr int kMaxBlades = 16;
 constexpr int kStackLds = 24;             // default traversal stack entries per lane (LDS only; deeper
                                           // work is found again through parent links); 16 and 32 also built
 constexpr int kTB = 128;                  // threads per traversal block
-constexpr int kTraceSteps = 3;            // default node visits per lane in one traversal loop iteration
+constexpr int kTraceSteps = 4;            // default node visits per lane in one traversal loop iteration
 constexpr int kMaxTraceBlocks = 4096;     // persistent traversal grid limit
 
 // ---------------------------------------------------------------- scene

@@ -744,7 +744,7 @@ constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS st
 // least tk.refill lanes are idle [16], takes tk.grab rays from the shared
 // work counter at a time [64], and runs its triangle tests when at least
 // tk.leaf_batch lanes have one pending [32]; kStack LDS stack entries per
-// lane [24]; kSteps node visits per lane per iteration [3]; tk.reverse
+// lane [24]; kSteps node visits per lane per iteration [4]; tk.reverse
 // hands the rays out from the end of the queue [for
 // frames; the scene-level sources keep the queue order].  The last rays a
 // persistent grid hands out set its tail: when they are cheap, every wave
@@ -964,8 +964,8 @@ int clamp_blocks(int blocks) { return blocks < 1 ? 1 : (blocks > kMaxTraceBlocks
 template <class Src, int kStack, class F>
 void with_steps(int steps, F f)
 {
-    if (steps == 4) f(k_traverse<Src, kStack, 4>);
-    else f(k_traverse<Src, kStack, kTraceSteps>);
+    if (steps == 3) f(k_traverse<Src, kStack, 3>);
+    else f(k_traverse<Src, kStack, 4>);
 }
 
 template <class Src, class F>

@@ -39,10 +39,10 @@ KNOB_SPACE = {
     "trace_leaf_batch": (16, 24, 32, 40),
     "gather_window": (-1, 32, 40, 48),
     "trace_order": (2, 1),
-    "trace_steps": (3, 4),
+    "trace_steps": (4, 3),
 }
 DEFAULTS = {"trace_blocks": 0, "trace_stack": 24, "trace_grab": 64, "trace_refill": 16, "trace_leaf_batch": 32,
-            "gather_window": -1, "trace_order": 2, "trace_steps": 3}
+            "gather_window": -1, "trace_order": 2, "trace_steps": 4}
 
 
 def candidate_blocks(extra=()):
