@@ -140,8 +140,8 @@ typedef struct {
      * fit it, 32, 40 or 48, or -1 (and the default 0): every tap read from
      * global memory.  trace_stack:
      * LDS traversal stack entries per lane, 16, 24 (default) or 32.
-     * trace_grab: rays a wave takes from the shared work counter at a time,
-     * 1..256 (default 64).  trace_refill: idle lanes at which a wave takes
+     * trace_grab: rays a wave takes from the traversal's work counters at a
+     * time, 1..256 (default 64).  trace_refill: idle lanes at which a wave takes
      * new rays, 1..64 (default 16).  trace_leaf_batch: lanes with a pending
      * leaf at which a wave runs its triangle tests, 1..64 (default 32).
      * trace_order: the order in which the persistent traversal hands out the

@@ -100,7 +100,7 @@ SceneLayout scene_layout(int64_t nt, int64_t n)
     L.flags = take(sizeof(uint32_t) * ni);
     L.hist = take(sizeof(uint32_t) * 256 * ((size_t)L.sort_blocks + 1));
     L.bounds = take(sizeof(float) * (6 * (size_t)L.bound_blocks + 8));
-    L.aux = take(64);
+    L.aux = take(dof::kWorkBytes);
     L.total = off;
     return L;
 }
@@ -183,7 +183,7 @@ dof::ScratchLayout frame_layout(int W, int H, int m, int taa, int ray_records)
     L.mask_raw = take(np);
     L.chunk_cnt = take(8 * (size_t)L.nchunks);
     L.chunk_off = take(8 * (size_t)L.nchunks);
-    L.counters = take(64);
+    L.counters = take(dof::kCountersBytes);
     L.queue = take(4 * np);
     L.ray_base = take(4 * np);
     L.ray_pix = take(4 * nr);

@@ -68,7 +68,7 @@ struct SceneDev {
     uint32_t *flags;         // nleaf - 1 refit visit counters
     uint32_t *hist;          // radix histograms (digit-major) + 256 digit offsets
     float *bounds;           // 6 partial-bound slots per reduce block + 8 final
-    uint32_t *aux;           // 64 B: work counter of the scene-level traversal kernels
+    uint32_t *aux;           // work counters of the scene-level traversal kernels ([8]: the refit's exit count)
     int32_t sort_blocks;
     int32_t bound_blocks;
 };
@@ -104,7 +104,7 @@ __device__ inline void pixel_dir(const ViewConst &v, int x, int y, int w, int h,
 // depend on them).
 struct TraceKnobs {
     int32_t stack;        // LDS stack entries per lane: 16, 24 or 32
-    uint32_t grab;        // rays per take from the shared work counter
+    uint32_t grab;        // rays per take from the work counters
     int32_t refill;       // idle lanes that trigger a refill
     int32_t leaf_batch;   // lanes with a pending leaf that trigger the triangle tests
     int32_t reverse;      // 1: rays handed out from the end of the queue
@@ -213,13 +213,20 @@ struct Job {
     uint32_t bx[kNumGrids];       // blocks per row of this job in each grid
 };
 
+// The persistent traversal's work counters: kWorkParts u32 counters,
+// kWorkStride u32 (256 B) apart.  Chunk g of a launch's rays (`grab` rays
+// each) is handed out by counter g % kWorkParts, so the waves' takes spread
+// over eight addresses instead of queueing on one.
+constexpr int kWorkParts = 8, kWorkStride = 64;
+constexpr size_t kWorkBytes = sizeof(uint32_t) * kWorkParts * kWorkStride;
+
 struct BatchHead {      // the first 24 bytes are the batch's dof_batch_stats
     int32_t njobs;
     uint32_t rays;                       // total rays of the batch
     unsigned long long visits, tests;    // traversal statistics of the batch
-    uint32_t work;                       // traversal work counter
-    uint32_t pad;
+    uint32_t pad[2];
     uint32_t ray_off[kMaxBatch + 1];     // first ray of each job in the batch
+    uint32_t work[kWorkParts * kWorkStride];   // traversal work counters
 };
 static_assert(offsetof(BatchHead, visits) == 8 && offsetof(BatchHead, tests) == 16, "stats prefix");
 
@@ -229,8 +236,10 @@ inline size_t batch_table_bytes(int n)
 }
 
 // counters[] slots (u32) in scratch: [0] masked px, [1] rays, [2..3] u64 node
-// visits, [4..5] u64 triangle tests, [8] traversal work counter
-enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntSpills = 6, kCntWork = 8 };
+// visits, [4..5] u64 triangle tests, [6] stack drops; from [64] (256 B in)
+// the traversal's work counters
+enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntSpills = 6, kCntWork = 64 };
+constexpr size_t kCountersBytes = sizeof(uint32_t) * kCntWork + kWorkBytes;
 
 // ---------------------------------------------------------------- helpers
 

@@ -759,7 +759,8 @@ __global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t
 {
     // the traversal's counters start the frame at zero (the totals of the
     // compaction are written by its last scatter block)
-    if (blockIdx.x == 0 && threadIdx.x >= kCntVisits && threadIdx.x <= kCntWork) P.counters[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x >= kCntVisits && threadIdx.x <= kCntSpills) P.counters[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kWorkParts) P.counters[kCntWork + threadIdx.x * kWorkStride] = 0u;
     b_compact_count(np, mask, P, blockIdx.x, blockIdx.y);
 }
 
@@ -803,7 +804,6 @@ __device__ inline void b_compact_scan(int64_t nchunks, const Planes &P)
         P.counters[kCntMasked] = pp[1023];
         P.counters[kCntRays] = pr[1023];
         for (int k = kCntVisits; k <= kCntSpills; ++k) P.counters[k] = 0u;
-        P.counters[kCntWork] = 0u;
     }
 }
 

@@ -10,10 +10,12 @@
 // Scheduling: each lane owns one ray at a time and advances it up to three
 // or four BVH nodes per loop iteration; when enough lanes of a wave are idle
 // (16 by default, or all of them) the wave hands them the next rays of its
-// pool, a run of 64 ray indices taken from a device counter with one atomic
-// whenever the pool is empty, so long rays do not hold a whole wave hostage
-// (persistent threads with dynamic fetch) and the shared counter sees one
-// atomic per 64 rays.  Thin-lens rays come from a generation kernel as
+// pool, a run of 64 ray indices taken with one atomic whenever the pool is
+// empty, so long rays do not hold a whole wave hostage (persistent threads
+// with dynamic fetch).  The runs are dealt over eight device counters 256 B
+// apart (run g by counter g mod 8), so the takes of all waves do not queue
+// on one address: with a single counter they did, and a 1080p frame's
+// traversal ran 10 % longer.  Thin-lens rays come from a generation kernel as
 // 24-byte records (origin and direction); a lane that takes one derives the
 // watertight test's shear and the slab reciprocals itself.  A finishing ray
 // leaves one 8-byte (leaf, t) record that the resolve expands when it shades,
@@ -741,8 +743,8 @@ int gen_blocks(int64_t max_rays)
 
 constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS stack is full
 // Launch knobs (TraceKnobs, defaults in brackets): a wave refills when at
-// least tk.refill lanes are idle [16], takes tk.grab rays from the shared
-// work counter at a time [64], and runs its triangle tests when at least
+// least tk.refill lanes are idle [16], takes tk.grab rays from the work
+// counters at a time [64], and runs its triangle tests when at least
 // tk.leaf_batch lanes have one pending [32]; kStack LDS stack entries per
 // lane [24]; kSteps node visits per lane per iteration [4]; tk.reverse
 // hands the rays out from the end of the queue [for
@@ -765,10 +767,11 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
 
     bool active = false, exhausted = false;
     // rays [pool, pool_end) taken by this wave and not yet handed to a lane
-    // (wave-uniform); a new batch of `grab` comes from the shared counter only
-    // when the pool is empty, so refills rarely touch the atomic
+    // (wave-uniform); a new batch of `grab` comes from the work counters only
+    // when the pool is empty, so refills rarely touch an atomic
     uint32_t pool = 0, pool_end = 0;
-    bool drained = false;   // the shared counter has passed N (wave-uniform)
+    bool drained = false;   // every work counter has passed N (wave-uniform)
+    uint32_t part = blockIdx.x % kWorkParts;   // the work counter this wave takes from first
     uint32_t item = 0, node = 0;
     int sp = 0;             // entries on the LDS stack
     bool dropped = false;   // entries of this ray were dropped (found again through parent links)
@@ -789,9 +792,23 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
         const uint64_t live = __ballot(active);
         if (idle != 0ull && (__popcll(idle) >= tk.refill || live == 0ull)) {
             if (pool == pool_end && !drained) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(work, grab);
+                // chunk g = k * kWorkParts + part is the k-th take of counter
+                // part; a counter past the last chunk sends the wave on to
+                // the next, and a wave that finds all past it is drained
+                uint32_t base = N;
+                if (lane == 0) {
+                    for (int t = 0; t < kWorkParts; ++t) {
+                        const uint32_t k = atomicAdd(work + part * kWorkStride, 1u);
+                        const uint64_t b = ((uint64_t)k * kWorkParts + part) * grab;
+                        if (b < N) {
+                            base = (uint32_t)b;
+                            break;
+                        }
+                        part = part + 1 == kWorkParts ? 0u : part + 1;
+                    }
+                }
                 base = __shfl(base, 0);
+                part = __shfl(part, 0);
                 if (base >= N) {
                     drained = true;
                 } else {
@@ -933,9 +950,9 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
     }
 }
 
-__global__ void k_zero_u32(uint32_t *p, int n)
+__global__ void k_zero_work(uint32_t *work)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+    if ((int)threadIdx.x < kWorkParts) work[threadIdx.x * kWorkStride] = 0u;
 }
 
 // First ray of every job of a batch (exclusive prefix of the jobs' ray
@@ -950,7 +967,7 @@ __global__ void kb_ray_offsets(BatchHead *head, const Job *__restrict__ jobs, in
     }
     head->ray_off[njobs] = acc;
     head->rays = acc;
-    head->work = 0u;
+    for (int p = 0; p < kWorkParts; ++p) head->work[p * kWorkStride] = 0u;
     head->visits = 0ull;
     head->tests = 0ull;
 }
@@ -1042,7 +1059,7 @@ hipError_t launch_gbuffer(const SceneDev &s, const FrameConst &fc, void *colour,
     src.depth = depth;
     src.normal = normal;
     src.nfmt = nfmt;
-    k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+    k_zero_work<<<1, 64, 0, st>>>(s.aux);
     k_traverse<PinholeRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(
         scene_args(s), src, (uint32_t)((int64_t)fc.W * fc.H), nullptr, s.aux, nullptr, nullptr, fc.tk);
     return hipGetLastError();
@@ -1053,7 +1070,7 @@ hipError_t launch_trace_rays(const SceneDev &s, int64_t n, const float *org, con
 {
     if (n == 0) return hipSuccess;
     RawRays src{org, dir, hit, t};
-    k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+    k_zero_work<<<1, 64, 0, st>>>(s.aux);
     TraceKnobs tk{kStackLds, 64u, 16, 32};
     k_traverse<RawRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, (uint32_t)n, nullptr, s.aux,
                                                                          nullptr, nullptr, tk);
@@ -1067,7 +1084,7 @@ hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, ui
     for (int64_t p0 = 0; p0 < npx; p0 += chunk_px) {
         const uint32_t n = (uint32_t)(npx - p0 < chunk_px ? npx - p0 : chunk_px);
         RefRays src{fc, (uint32_t)p0, (uint32_t)spp, lt};
-        k_zero_u32<<<1, 64, 0, st>>>(s.aux, 16);
+        k_zero_work<<<1, 64, 0, st>>>(s.aux);
         k_traverse<RefRays, kStackLds, kTraceSteps><<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, n * (uint32_t)spp,
                                                                             nullptr, s.aux, nullptr, nullptr, fc.tk);
         k_ref_average<<<(n + 255) / 256, 256, 0, st>>>(scene_args(s), src, n, colour, cfmt);
@@ -1084,7 +1101,7 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int b
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
     with_shape<BatchRays>(tk.stack, tk.steps, [&](auto kern) {
-        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, &head->work, &head->visits,
+        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, head->work, &head->visits,
                                                   nullptr, tk);
     });
     return hipGetLastError();

@@ -9,8 +9,8 @@ Searched per workload, by HIP-event time of the same sample of frames:
 * trace_stack -- LDS stack entries per traversal lane (16, 24, 32): fewer
   entries leave room for more resident blocks, more make stack overflows
   (recovered through parent links) rarer;
-* trace_grab -- rays a wave takes from the shared work counter at a time
-  (the traversal's queue width);
+* trace_grab -- rays a wave takes from the traversal's work counters at a
+  time (its queue width; 32 to 256);
 * trace_refill -- idle lanes at which a wave takes new rays;
 * trace_leaf_batch -- lanes with a pending leaf at which a wave runs its
   triangle tests;
@@ -34,7 +34,7 @@ from __future__ import annotations
 KNOB_SPACE = {
     "trace_blocks": None,                      # filled from the device (candidate_blocks)
     "trace_stack": (16, 24, 32),
-    "trace_grab": (32, 64, 128),
+    "trace_grab": (32, 64, 128, 256),
     "trace_refill": (8, 16, 24),
     "trace_leaf_batch": (16, 24, 32, 40),
     "gather_window": (-1, 32, 40, 48),
