@@ -213,11 +213,15 @@ struct Job {
     uint32_t bx[kNumGrids];       // blocks per row of this job in each grid
 };
 
-// The persistent traversal's work counters: kWorkParts u32 counters,
-// kWorkStride u32 (256 B) apart.  Chunk g of a launch's rays (`grab` rays
-// each) is handed out by counter g % kWorkParts, so the waves' takes spread
-// over eight addresses instead of queueing on one.
-constexpr int kWorkParts = 8, kWorkStride = 64;
+// The persistent traversal's work counters: kWorkParts slots of kWorkStride
+// u32 (256 B).  Slot p holds work counter p at [0]: chunk g of a launch's rays
+// (`grab` rays each) is handed out by counter g % kWorkParts, so the waves'
+// takes spread over eight addresses instead of queueing on one.  From
+// [kStatAt] (another 128-B line) the slot holds the statistics that the waves
+// of blocks b = p mod kWorkParts add when they finish: node visits (u64),
+// triangle tests (u64), stack drops (u32); a launch's totals are the sums
+// over the slots.
+constexpr int kWorkParts = 8, kWorkStride = 64, kStatAt = 32, kStatWords = 5;
 constexpr size_t kWorkBytes = sizeof(uint32_t) * kWorkParts * kWorkStride;
 
 struct BatchHead {      // the first 24 bytes are the batch's dof_batch_stats
@@ -226,7 +230,7 @@ struct BatchHead {      // the first 24 bytes are the batch's dof_batch_stats
     unsigned long long visits, tests;    // traversal statistics of the batch
     uint32_t pad[2];
     uint32_t ray_off[kMaxBatch + 1];     // first ray of each job in the batch
-    uint32_t work[kWorkParts * kWorkStride];   // traversal work counters
+    alignas(8) uint32_t work[kWorkParts * kWorkStride];   // traversal work counters and statistics slots
 };
 static_assert(offsetof(BatchHead, visits) == 8 && offsetof(BatchHead, tests) == 16, "stats prefix");
 
@@ -235,10 +239,9 @@ inline size_t batch_table_bytes(int n)
     return (sizeof(BatchHead) + 255) / 256 * 256 + sizeof(Job) * (size_t)n;
 }
 
-// counters[] slots (u32) in scratch: [0] masked px, [1] rays, [2..3] u64 node
-// visits, [4..5] u64 triangle tests, [6] stack drops; from [64] (256 B in)
-// the traversal's work counters
-enum : int { kCntMasked = 0, kCntRays = 1, kCntVisits = 2, kCntTests = 4, kCntSpills = 6, kCntWork = 64 };
+// counters[] (u32) in scratch: [0] masked px, [1] rays; from [64] (256 B in)
+// the traversal's work-counter and statistics slots
+enum : int { kCntMasked = 0, kCntRays = 1, kCntWork = 64 };
 constexpr size_t kCountersBytes = sizeof(uint32_t) * kCntWork + kWorkBytes;
 
 // ---------------------------------------------------------------- helpers
@@ -397,7 +400,7 @@ hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, c
 // max_rays: the sum over the jobs of half-res pixels x m (sizes the ray generation grid)
 hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, int64_t max_rays,
                               const TraceKnobs &tk, hipStream_t st);
-hipError_t launch_batch_post(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
+hipError_t launch_batch_post(BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
                              const Rings &rings, int taa, hipStream_t st);
 
 }  // namespace dof

@@ -759,8 +759,11 @@ __global__ __launch_bounds__(256) void k_compact_count(int64_t np, const uint8_t
 {
     // the traversal's counters start the frame at zero (the totals of the
     // compaction are written by its last scatter block)
-    if (blockIdx.x == 0 && threadIdx.x >= kCntVisits && threadIdx.x <= kCntSpills) P.counters[threadIdx.x] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x < kWorkParts) P.counters[kCntWork + threadIdx.x * kWorkStride] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kWorkParts) {
+        uint32_t *w = P.counters + kCntWork + threadIdx.x * kWorkStride;
+        w[0] = 0u;
+        for (int k = 0; k < kStatWords; ++k) w[kStatAt + k] = 0u;
+    }
     b_compact_count(np, mask, P, blockIdx.x, blockIdx.y);
 }
 
@@ -803,7 +806,6 @@ __device__ inline void b_compact_scan(int64_t nchunks, const Planes &P)
     if (threadIdx.x == 1023) {
         P.counters[kCntMasked] = pp[1023];
         P.counters[kCntRays] = pr[1023];
-        for (int k = kCntVisits; k <= kCntSpills; ++k) P.counters[k] = 0u;
     }
 }
 
@@ -1438,10 +1440,24 @@ __device__ inline void b_composite(const FrameConst &fc, const Planes &P, const 
 __global__ __launch_bounds__(kBX *kBY) void k_composite(FrameConst fc, Planes P, dof_gbuffer gb, dof_frame_out out)
 {
     // The frame's counters are final once the traversal has run: the first
-    // block copies them into the caller's stats record (masked px, rays, node
-    // visits, triangle tests, stack overflows: seven 32-bit words).
-    if (out.stats && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.y == 0 && threadIdx.x < 7)
-        reinterpret_cast<uint32_t *>(out.stats)[threadIdx.x] = P.counters[threadIdx.x];
+    // thread writes the caller's stats record (masked px, rays, and the sums
+    // of the traversal's statistics slots).
+    if (out.stats && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.y == 0 && threadIdx.x == 0) {
+        unsigned long long v = 0ull, t = 0ull;
+        uint32_t drops = 0u;
+        for (int p = 0; p < kWorkParts; ++p) {
+            const uint32_t *w = P.counters + kCntWork + p * kWorkStride + kStatAt;
+            v += *reinterpret_cast<const unsigned long long *>(w);
+            t += *reinterpret_cast<const unsigned long long *>(w + 2);
+            drops += w[4];
+        }
+        dof_stats *o = out.stats;
+        o->masked_px = P.counters[kCntMasked];
+        o->rays = P.counters[kCntRays];
+        o->node_visits = v;
+        o->tri_tests = t;
+        o->stack_spills = drops;
+    }
     b_composite(fc, P, gb, out, blockIdx.x, blockIdx.y);
 }
 
@@ -1453,10 +1469,21 @@ __global__ __launch_bounds__(kBX *kBY) void kb_composite(const Job *__restrict__
 }
 
 // Per-job stats records of a batch: masked pixels and rays of the job; the
-// traversal statistics of a batch are kept once, in its head.
-__global__ void kb_stats(const Job *__restrict__ jobs, int njobs)
+// traversal statistics of a batch are kept once, in its head (the first
+// thread sums the traversal's statistics slots there).
+__global__ void kb_stats(BatchHead *head, const Job *__restrict__ jobs, int njobs)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {
+        unsigned long long v = 0ull, t = 0ull;
+        for (int p = 0; p < kWorkParts; ++p) {
+            const uint32_t *w = head->work + p * kWorkStride + kStatAt;
+            v += *reinterpret_cast<const unsigned long long *>(w);
+            t += *reinterpret_cast<const unsigned long long *>(w + 2);
+        }
+        head->visits = v;
+        head->tests = t;
+    }
     if (j >= njobs || !jobs[j].out.stats) return;
     const uint32_t *c = jobs[j].P.counters;
     dof_stats *o = jobs[j].out.stats;
@@ -1759,7 +1786,7 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
     return hipGetLastError();
 }
 
-hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
+hipError_t launch_batch_post(BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
                              int taa, hipStream_t st)
 {
     {
@@ -1771,7 +1798,7 @@ hipError_t launch_batch_post(const BatchHead *, const Job *jobs, int njobs, cons
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
     kb_composite<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     if (taa & DOF_TAA_FINAL) kb_taa_final<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
-    kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(jobs, njobs);
+    kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(head, jobs, njobs);
     return hipGetLastError();
 }
 

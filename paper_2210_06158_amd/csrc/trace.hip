@@ -752,6 +752,9 @@ constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS st
 // persistent grid hands out set its tail: when they are cheap, every wave
 // finishes at nearly the same time.
 
+// work: slot 0 of the work-counter slots; stats and drops_out (or null):
+// slot 0's node-visit and stack-drop statistics, a wave adding its totals to
+// the slot of its block (b mod kWorkParts) when it finishes.
 template <class Src, int kStack, int kSteps>
 __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
                                                   uint32_t *work, unsigned long long *stats, uint32_t *drops_out,
@@ -939,14 +942,15 @@ __global__ __launch_bounds__(kTB) void k_traverse(SceneArgs S, Src src, uint32_t
             t += __shfl_xor(t, off);
         }
         if (lane == 0) {
-            atomicAdd(stats, v);
-            atomicAdd(stats + 1, t);
+            unsigned long long *slot = stats + (blockIdx.x % kWorkParts) * (kWorkStride / 2);
+            atomicAdd(slot, v);
+            atomicAdd(slot + 1, t);
         }
     }
     if (drops_out) {
         uint32_t sv = drops;
         for (int off = 32; off >= 1; off >>= 1) sv += __shfl_xor(sv, off);
-        if (lane == 0 && sv) atomicAdd(drops_out, sv);
+        if (lane == 0 && sv) atomicAdd(drops_out + (blockIdx.x % kWorkParts) * kWorkStride, sv);
     }
 }
 
@@ -967,7 +971,11 @@ __global__ void kb_ray_offsets(BatchHead *head, const Job *__restrict__ jobs, in
     }
     head->ray_off[njobs] = acc;
     head->rays = acc;
-    for (int p = 0; p < kWorkParts; ++p) head->work[p * kWorkStride] = 0u;
+    for (int p = 0; p < kWorkParts; ++p) {
+        uint32_t *w = head->work + p * kWorkStride;
+        w[0] = 0u;
+        for (int k = 0; k < kStatWords; ++k) w[kStatAt + k] = 0u;
+    }
     head->visits = 0ull;
     head->tests = 0ull;
 }
@@ -1014,8 +1022,8 @@ hipError_t launch_trace(const SceneDev &s, const FrameConst &fc, const ScratchLa
     uint32_t *cnt = reinterpret_cast<uint32_t *>(scratch + L.counters);
     with_shape<LensRays>(fc.tk.stack, fc.tk.steps, [&](auto kern) {
         kern<<<clamp_blocks(blocks), kTB, 0, st>>>(scene_args(s), src, 0u, cnt + kCntRays, cnt + kCntWork,
-                                                  reinterpret_cast<unsigned long long *>(cnt + kCntVisits),
-                                                  cnt + kCntSpills, fc.tk);
+                                                  reinterpret_cast<unsigned long long *>(cnt + kCntWork + kStatAt),
+                                                  cnt + kCntWork + kStatAt + 4, fc.tk);
     });
     return hipGetLastError();
 }
@@ -1101,7 +1109,8 @@ hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int b
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
     BatchRays src{jobs, head, njobs};
     with_shape<BatchRays>(tk.stack, tk.steps, [&](auto kern) {
-        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, head->work, &head->visits,
+        kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, head->work,
+                                                  reinterpret_cast<unsigned long long *>(head->work + kStatAt),
                                                   nullptr, tk);
     });
     return hipGetLastError();
