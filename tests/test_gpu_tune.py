@@ -136,3 +136,43 @@ def test_search_picks_the_fastest_per_knob():
     for k, times in table.items():
         assert set(times) == set(space[k]) and cfg[k] == min(times, key=times.get)
     assert all(set(c) == set(space) for c in seen)
+
+
+def test_traversal_statistics_add_up_over_the_counter_slots():
+    """With triangle tests run whenever any lane has a pending leaf
+    (trace_leaf_batch 1), each ray's node visits, triangle tests and stack
+    drops follow from that ray alone, so a frame's totals do not depend on
+    the persistent grid.  One block (every wave adds into one statistics
+    slot), 16 blocks (two per slot) and the default grid give the same
+    totals, and a batch of the frame twice gives twice them: the slots are
+    summed completely, once."""
+    import torch
+    from paper_2210_06158_amd import dof
+    torch.cuda.set_device(0)
+    scene, cam, lens, params = synth.scene_small()
+    gs = dof.Scene(scene)
+    gs.build_bvh()
+    gb = gs.render_gbuffer(cam, lens)
+    knobs = {"trace_leaf_batch": 1, "trace_stack": 16}
+
+    def frame_totals(tb):
+        fr = dof.Frame(cam.width, cam.height, params, trace_blocks=tb, knobs=knobs)
+        fr.render(gs, cam, lens, gb, None, dof.history_alloc(cam.width, cam.height))
+        torch.cuda.synchronize()
+        s = fr.stats.cpu().numpy()
+        s64 = s.view(np.int64)
+        return int(s[1]), int(s64[1]), int(s64[2]), int(s[6])
+
+    one = frame_totals(1)
+    rays, visits, tests, drops = one
+    assert rays > 1000 and visits >= rays and 0 < tests <= 2 * visits
+    assert frame_totals(16) == one and frame_totals(0) == one
+
+    frs = [dof.Frame(cam.width, cam.height, params, knobs=knobs) for _ in range(2)]
+    b = dof.Batch(2, params, trace_blocks=16, knobs=knobs)
+    hs = [dof.history_alloc(cam.width, cam.height) for _ in range(2)]   # kept alive: the items hold pointers
+    b.set([f.item(gs, cam, lens, gb, None, h) for f, h in zip(frs, hs)])
+    b.run()
+    torch.cuda.synchronize()
+    nf, brays, bvisits, btests = b.totals()
+    assert nf == 2 and (brays, bvisits, btests) == (2 * rays, 2 * visits, 2 * tests)
