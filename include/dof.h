@@ -417,8 +417,11 @@ dof_status dof_batch_set(dof_batch *b, const dof_batch_item *items, int32_t n, c
 /* Renders the items of the last dof_batch_set on `stream`: launches only
  * (no host sync, no allocation), so it may be captured in a HIP graph.  A
  * captured run may be replayed after later dof_batch_set calls whose items
- * have the same count, sizes and order (grid sizes are captured).
- * stats (device pointer, nullable) receives the batch totals. */
+ * have the same count, sizes and order (grid sizes are captured).  As in
+ * dof_render_frame, the post-process chain runs on a stream the batch owns
+ * (created with it, default priority), forked from `stream` after the ray
+ * generation and joined back before the composite; runs of one batch share
+ * it.  stats (device pointer, nullable) receives the batch totals. */
 dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream);
 void dof_batch_destroy(dof_batch *b);
 

@@ -529,6 +529,31 @@ dof::Rings gather_rings(const dof_lens &lens, const dof_params &p)
 
 }  // namespace
 
+// A post-process chain's stream (non-blocking, default priority) with its
+// fork and join events, on the current device; false when any of them could
+// not be created (then nothing is left allocated).
+static bool side_create(dof::SideStream &sd)
+{
+    if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(sd.stream);
+        return false;
+    }
+    if (hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(sd.fork);
+        (void)hipStreamDestroy(sd.stream);
+        return false;
+    }
+    return true;
+}
+
+static void side_destroy(dof::SideStream &sd)
+{
+    (void)hipEventDestroy(sd.fork);
+    (void)hipEventDestroy(sd.join);
+    (void)hipStreamDestroy(sd.stream);
+}
+
 struct dof_batch {
     char *table;                       // device: BatchHead, then the jobs
     size_t table_bytes;
@@ -542,6 +567,8 @@ struct dof_batch {
     int gather_win;                    // the gather's LDS window (params.gather_window)
     dof::TraceKnobs tk;                // traversal launch knobs (params.trace_*)
     std::vector<char> host;            // staging copy of the table
+    bool side_ready;                   // side holds a stream and two events
+    dof::SideStream side;              // the post-process chain's stream
 };
 
 // the error message of a failing call made in another translation unit
@@ -674,18 +701,9 @@ dof_status dof_create_scene(const dof_scene_desc *desc, void *arena, size_t aren
         delete s;
         return fail(DOF_E_DEVICE, "scene upload: %s", hipGetErrorString(e));
     }
-    // the post-process chain's stream (default priority) and its fork / join
-    // events; without them frames run on the caller's stream alone
-    s->side_ready = hipStreamCreateWithFlags(&s->side.stream, hipStreamNonBlocking) == hipSuccess;
-    if (s->side_ready && hipEventCreateWithFlags(&s->side.fork, hipEventDisableTiming) != hipSuccess) {
-        (void)hipStreamDestroy(s->side.stream);
-        s->side_ready = false;
-    }
-    if (s->side_ready && hipEventCreateWithFlags(&s->side.join, hipEventDisableTiming) != hipSuccess) {
-        (void)hipEventDestroy(s->side.fork);
-        (void)hipStreamDestroy(s->side.stream);
-        s->side_ready = false;
-    }
+    // the post-process chain's stream and its fork / join events; without
+    // them frames run on the caller's stream alone
+    s->side_ready = side_create(s->side);
     *out = s;
     return DOF_OK;
 }
@@ -719,11 +737,7 @@ void dof_destroy_scene(dof_scene *scene)
     if (!scene) return;
     if (scene->events_ready)
         for (int i = 0; i <= DOF_NUM_STAGES; ++i) (void)hipEventDestroy(scene->ev[i]);
-    if (scene->side_ready) {
-        (void)hipEventDestroy(scene->side.fork);
-        (void)hipEventDestroy(scene->side.join);
-        (void)hipStreamDestroy(scene->side.stream);
-    }
+    if (scene->side_ready) side_destroy(scene->side);
     delete scene;
 }
 
@@ -869,6 +883,7 @@ dof_status dof_batch_create(void *table, size_t table_bytes, int32_t max_items, 
     b->table_bytes = table_bytes;
     b->max_items = max_items;
     b->n = 0;
+    b->side_ready = side_create(b->side);
     *out = b;
     return DOF_OK;
 }
@@ -951,14 +966,29 @@ dof_status dof_batch_run(dof_batch *b, dof_batch_stats *stats, void *stream)
     dof::BatchHead *head = reinterpret_cast<dof::BatchHead *>(b->table);
     const dof::Job *jobs = reinterpret_cast<const dof::Job *>(b->table + dof::batch_table_bytes(0));
     const dof::Rings &rings = ring_table();
-    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, b->gather_win, s));
-    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->trace_blocks, b->max_rays, b->tk, s));
-    DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, s));
+    // as for a frame, the post-process chain runs on the batch's side stream
+    // beside the traversal, forked after the ray generation
+    const dof::SideStream *side = b->side_ready ? &b->side : nullptr;
+    DOF_HIP(dof::launch_batch_pre(head, jobs, b->n, b->nblk, rings, b->dilate, b->taa, b->gather_win, side, s));
+    DOF_HIP(dof::launch_batch_raygen(head, jobs, b->n, b->max_rays, s));
+    if (side) {
+        DOF_HIP(hipEventRecord(side->fork, s));
+        DOF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+        DOF_HIP(dof::launch_batch_chain(jobs, b->n, b->nblk, rings, !b->dilate, b->taa, b->gather_win, side->stream));
+        DOF_HIP(hipEventRecord(side->join, side->stream));
+    }
+    DOF_HIP(dof::launch_batch_trace(head, jobs, b->n, b->trace_blocks, b->tk, s));
+    DOF_HIP(dof::launch_batch_post(head, jobs, b->n, b->nblk, rings, b->taa, side, s));
     if (stats) DOF_HIP(hipMemcpyAsync(stats, b->table, sizeof(dof_batch_stats), hipMemcpyDeviceToDevice, s));
     return DOF_OK;
 }
 
-void dof_batch_destroy(dof_batch *b) { delete b; }
+void dof_batch_destroy(dof_batch *b)
+{
+    if (!b) return;
+    if (b->side_ready) side_destroy(b->side);
+    delete b;
+}
 
 dof_status dof_stage_times(dof_scene *scene, float *ms, int32_t cap, int32_t *n)
 {

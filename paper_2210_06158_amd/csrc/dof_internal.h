@@ -395,12 +395,20 @@ hipError_t launch_frame_post(const SceneDev &s, const FrameConst &fc, const Ring
 hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st);
 // batch: head at the table start, jobs at batch_table_bytes(0); nblk[g] =
 // total blocks of grid g over the jobs
+// side (nullable): the post-process chain (launch_batch_chain) is left to the
+// caller, to run on side->stream after the ray generation; else pre runs it
 hipError_t launch_batch_pre(const BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                            const Rings &rings, bool dilate, int taa, int gather_win, hipStream_t st);
+                            const Rings &rings, bool dilate, int taa, int gather_win, const SideStream *side,
+                            hipStream_t st);
+// the post-process chain (with_dilate: the tile dilation first)
+hipError_t launch_batch_chain(const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings, bool with_dilate,
+                              int taa, int gather_win, hipStream_t st);
 // max_rays: the sum over the jobs of half-res pixels x m (sizes the ray generation grid)
-hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, int64_t max_rays,
-                              const TraceKnobs &tk, hipStream_t st);
+hipError_t launch_batch_raygen(BatchHead *head, const Job *jobs, int njobs, int64_t max_rays, hipStream_t st);
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, const TraceKnobs &tk,
+                              hipStream_t st);
+// side (nullable): the composite waits for side->join
 hipError_t launch_batch_post(BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk,
-                             const Rings &rings, int taa, hipStream_t st);
+                             const Rings &rings, int taa, const SideStream *side, hipStream_t st);
 
 }  // namespace dof

@@ -1766,18 +1766,31 @@ hipError_t launch_history_reset(float *hist, int64_t nfloats, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                            bool dilate, int taa, int gather_win, hipStream_t st)
+hipError_t launch_batch_chain(const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings, bool with_dilate,
+                              int taa, int gather_win, hipStream_t st)
 {
-    if (taa & DOF_TAA_RASTER) kb_taa_raster<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
-    kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
-    kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
+    if (with_dilate) kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
     kb_prefilter<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     launch_gather_pair(gather_win, [&](auto w) {
         kb_gather<decltype(w)::value><<<nblk[kGridTiles], 256, 0, st>>>(jobs, njobs);
     });
     kb_median_pp<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     if (taa & DOF_TAA_POST) kb_taa_post<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
+                            bool dilate, int taa, int gather_win, const SideStream *side, hipStream_t st)
+{
+    if (taa & DOF_TAA_RASTER) kb_taa_raster<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
+    kb_reduce<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
+    // as in a frame: the dilation heads the side chain unless the ray mask
+    // reads the dilated radii
+    if (!side || dilate) kb_dilate<<<nblk[kGridDilate], dim3(16, 16), 0, st>>>(jobs, njobs);
+    if (!side) {
+        const hipError_t e = launch_batch_chain(jobs, njobs, nblk, rings, false, taa, gather_win, st);
+        if (e != hipSuccess) return e;
+    }
     kb_mask<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     if (dilate) kb_mask_dilate<<<nblk[kGridTiles], dim3(kTile, kTile), 0, st>>>(jobs, njobs);
     kb_compact_count<<<nblk[kGridChunk], 256, 0, st>>>(jobs, njobs);
@@ -1787,7 +1800,7 @@ hipError_t launch_batch_pre(const BatchHead *, const Job *jobs, int njobs, const
 }
 
 hipError_t launch_batch_post(BatchHead *head, const Job *jobs, int njobs, const uint32_t *nblk, const Rings &rings,
-                             int taa, hipStream_t st)
+                             int taa, const SideStream *side, hipStream_t st)
 {
     {
         const hipError_t e = launch_batch_shade_resolve(jobs, njobs, nblk, st);
@@ -1796,6 +1809,10 @@ hipError_t launch_batch_post(BatchHead *head, const Job *jobs, int njobs, const 
     kb_temporal<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_blur_median_mips<<<nblk[kGridMip], 64, 0, st>>>(jobs, njobs);
     kb_recon<<<nblk[kGridHalf], dim3(kBX, kBY), 0, st>>>(jobs, njobs, rings);
+    if (side) {
+        const hipError_t e = hipStreamWaitEvent(st, side->join, 0);   // the post-process chain is done
+        if (e != hipSuccess) return e;
+    }
     kb_composite<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     if (taa & DOF_TAA_FINAL) kb_taa_final<<<nblk[kGridFull], dim3(kBX, kBY), 0, st>>>(jobs, njobs);
     kb_stats<<<(njobs + 127) / 128, 128, 0, st>>>(head, jobs, njobs);

@@ -1102,11 +1102,16 @@ hipError_t launch_reference(const SceneDev &s, const FrameConst &fc, int spp, ui
     return hipSuccess;
 }
 
-hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, int64_t max_rays,
-                              const TraceKnobs &tk, hipStream_t st)
+hipError_t launch_batch_raygen(BatchHead *head, const Job *jobs, int njobs, int64_t max_rays, hipStream_t st)
 {
     kb_ray_offsets<<<1, 64, 0, st>>>(head, jobs, njobs);
     kb_raygen<<<gen_blocks(max_rays), kGenTB, 0, st>>>(jobs, head, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_trace(BatchHead *head, const Job *jobs, int njobs, int blocks, const TraceKnobs &tk,
+                              hipStream_t st)
+{
     BatchRays src{jobs, head, njobs};
     with_shape<BatchRays>(tk.stack, tk.steps, [&](auto kern) {
         kern<<<clamp_blocks(blocks), kTB, 0, st>>>(SceneArgs{}, src, 0u, &head->rays, head->work,
