@@ -58,7 +58,8 @@ struct WRay {
     int kx, ky, kz;
     float sx, sy, sz;
     float ix, iy, iz;   // slab reciprocals (zero components replaced by 1e-20)
-    float clx, cly, clz, chx, chy, chz;   // slab offsets of the low and high planes (box_hit)
+    float cnx, cny, cnz, cfx, cfy, cfz;   // slab offsets of the entry and exit planes (box_hit)
+    uint32_t swx, swy, swz;               // 16 where the entry plane is a node word's high half, else 0
 };
 
 // The watertight test's axes: kz the largest direction component, kx and ky
@@ -90,12 +91,13 @@ __device__ inline float slab_offset(float o, float inv, bool entry_if_positive)
 
 __device__ inline void slab_offsets(WRay &r)
 {
-    r.clx = slab_offset(r.o0, r.ix, true);
-    r.cly = slab_offset(r.o1, r.iy, true);
-    r.clz = slab_offset(r.o2, r.iz, true);
-    r.chx = slab_offset(r.o0, r.ix, false);
-    r.chy = slab_offset(r.o1, r.iy, false);
-    r.chz = slab_offset(r.o2, r.iz, false);
+    const float clx = slab_offset(r.o0, r.ix, true), chx = slab_offset(r.o0, r.ix, false);
+    const float cly = slab_offset(r.o1, r.iy, true), chy = slab_offset(r.o1, r.iy, false);
+    const float clz = slab_offset(r.o2, r.iz, true), chz = slab_offset(r.o2, r.iz, false);
+    const bool px = r.ix > 0.0f, py = r.iy > 0.0f, pz = r.iz > 0.0f;
+    r.cnx = px ? clx : chx; r.cfx = px ? chx : clx; r.swx = px ? 0u : 16u;
+    r.cny = py ? cly : chy; r.cfy = py ? chy : cly; r.swy = py ? 0u : 16u;
+    r.cnz = pz ? clz : chz; r.cfz = pz ? chz : clz; r.swz = pz ? 0u : 16u;
 }
 
 __device__ inline WRay make_wray(const float o[3], const float d[3])
@@ -147,35 +149,42 @@ __device__ inline bool tri_hit(const WRay &r, float4 v0, float4 v1, float4 v2, f
     return true;
 }
 
-// Conservative slab test against [0, limit]; returns the entry distance.
-// It only culls, so it may use the hardware min/max (no NaN can arise: the
-// reciprocals are finite); the exit distance is enlarged by 2^-20 relative
-// to cover rounding.
-__device__ inline bool box_hit(const WRay &r, float lx, float hx, float ly, float hy, float lz, float hz, float limit,
-                               float &tenter)
-{
-    float t0x = fmaf(lx, r.ix, r.clx), t1x = fmaf(hx, r.ix, r.chx);
-    float t0y = fmaf(ly, r.iy, r.cly), t1y = fmaf(hy, r.iy, r.chy);
-    float t0z = fmaf(lz, r.iz, r.clz), t1z = fmaf(hz, r.iz, r.chz);
-    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.00000095367431640625f;
-    tenter = tn;
-    // tn <= tf, tf >= 0 and tn <= limit (limit >= 0) in one comparison
-    return fmaxf(tn, 0.0f) <= fminf(tf, limit);
-}
-
 // The planes of a binary16 node word: low plane in the low half, high plane
 // in the high half.  Converted exactly; the compiler folds the conversion into
 // the slab test's fused multiply-add (a mixed-precision fma).
 __device__ inline float lo16(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
 __device__ inline float hi16(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
 
+// Conservative slab test of a binary16 box (three node words) against
+// [0, limit]; returns the entry distance.  Each word's halves are swapped
+// (alignbit by 16) where that axis' reciprocal is negative, so its low half is
+// the entry plane and its high half the exit plane in every lane.  The slab
+// distance is monotone in the plane (and the entry offset lies below the exit
+// offset), so these are exactly the smaller and larger of the two distances:
+// one swap per axis instead of a min and a max.  The test only culls, so it
+// may use the hardware min/max (no NaN can arise: the reciprocals are
+// finite); the exit distance is enlarged by 2^-20 relative to cover rounding.
+__device__ inline bool box_hit(const WRay &r, uint32_t wx, uint32_t wy, uint32_t wz, float limit, float &tenter)
+{
+    wx = __builtin_amdgcn_alignbit(wx, wx, r.swx);
+    wy = __builtin_amdgcn_alignbit(wy, wy, r.swy);
+    wz = __builtin_amdgcn_alignbit(wz, wz, r.swz);
+    float nx = fmaf(lo16(wx), r.ix, r.cnx), fx = fmaf(hi16(wx), r.ix, r.cfx);
+    float ny = fmaf(lo16(wy), r.iy, r.cny), fy = fmaf(hi16(wy), r.iy, r.cfy);
+    float nz = fmaf(lo16(wz), r.iz, r.cnz), fz = fmaf(hi16(wz), r.iz, r.cfz);
+    float tn = fmaxf(fmaxf(nx, ny), nz);
+    float tf = fminf(fminf(fx, fy), fz) * 1.00000095367431640625f;
+    tenter = tn;
+    // tn <= tf, tf >= 0 and tn <= limit (limit >= 0) in one comparison
+    return fmaxf(tn, 0.0f) <= fminf(tf, limit);
+}
+
 // Slab tests of both children of a binary16 node.
 __device__ inline void node_hits(const WRay &r, const BvhNode16 &nd, float limit, bool &hl, bool &hr, float &tl,
                                  float &tr)
 {
-    hl = box_hit(r, lo16(nd.a.x), hi16(nd.a.x), lo16(nd.a.y), hi16(nd.a.y), lo16(nd.a.z), hi16(nd.a.z), limit, tl);
-    hr = box_hit(r, lo16(nd.a.w), hi16(nd.a.w), lo16(nd.b.x), hi16(nd.b.x), lo16(nd.b.y), hi16(nd.b.y), limit, tr);
+    hl = box_hit(r, nd.a.x, nd.a.y, nd.a.z, limit, tl);
+    hr = box_hit(r, nd.a.w, nd.b.x, nd.b.y, limit, tr);
 }
 
 struct Hit {
@@ -763,7 +772,7 @@ constexpr int kDropChunk = 8;    // oldest stack entries dropped when the LDS st
 // makes a 32-session batch 3.6 % faster.  The 32-entry stack is LDS-bound
 // below both.
 template <class Src, int kStack, int kSteps>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(Src::kPerLaneScene ? 6 : (kStack == 16 ? 7 : 1))))
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(Src::kPerLaneScene ? (kStack == 32 ? 1 : 6) : (kStack == 16 ? 7 : 1))))
 void k_traverse(SceneArgs S, Src src, uint32_t count, const uint32_t *count_ptr,
                                                   uint32_t *work, unsigned long long *stats, uint32_t *drops_out,
                                                   TraceKnobs tk)
